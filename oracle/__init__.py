@@ -1,0 +1,251 @@
+"""CPU FP64 oracle for the thin-lattice tracking path.
+
+TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the benchmark's
+CPU-baseline leg are the only callers.  Nothing in the product package
+imports it, and it imports nothing from the product package.
+
+``oracle.c`` holds the element maps and the turn loop (plain C, FP64,
+``-ffp-contract=off``).  This module adds ctypes marshalling and the
+host-side analysis built on the one-turn map: the central-difference
+Jacobian and the uncoupled linear normal form (paper section "Twiss
+module", steps 2 and 3).
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SOURCES = ["oracle.c"]
+LIB = os.path.join(HERE, "liboracle.so")
+
+CFLAGS = ["-O2", "-fno-fast-math", "-ffp-contract=off", "-march=x86-64-v3",
+          "-fopenmp", "-fPIC", "-shared", "-std=c11", "-D_GNU_SOURCE"]
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (it is the checker, never the product path)."""
+    srcs = [os.path.join(HERE, s) for s in SOURCES]
+    if not force and os.path.exists(LIB):
+        lib_t = os.path.getmtime(LIB)
+        if all(os.path.getmtime(s) <= lib_t for s in srcs):
+            return LIB
+    tmp = LIB + ".tmp%d" % os.getpid()
+    subprocess.run(["gcc", *CFLAGS, "-o", tmp, *srcs, "-lm"], check=True)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build(force=False)
+        L = ctypes.CDLL(LIB)
+        L.oracle_track.restype = ctypes.c_int64
+        L.oracle_track_backward.restype = ctypes.c_int64
+        L.oracle_init.restype = ctypes.c_int
+        L.oracle_track_canonical.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+class _Parts(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_void_p) for n in
+                ("x", "px", "y", "py", "zeta", "delta", "ptau", "rpp", "rvv",
+                 "state", "at_element", "at_turn", "pid")] + [("n", ctypes.c_int64)]
+
+
+FLOAT_FIELDS = ("x", "px", "y", "py", "zeta", "delta", "ptau", "rpp", "rvv")
+INT_FIELDS = ("state", "at_element", "at_turn")
+
+
+class Particles:
+    """Structure-of-arrays FP64 particle set held in numpy arrays."""
+
+    def __init__(self, n: int):
+        self.n = int(n)
+        for f in FLOAT_FIELDS:
+            setattr(self, f, np.zeros(self.n, dtype=np.float64))
+        for f in INT_FIELDS:
+            setattr(self, f, np.zeros(self.n, dtype=np.int32))
+        self.particle_id = np.zeros(self.n, dtype=np.int64)
+        self.turn = 0
+
+    def _struct(self) -> _Parts:
+        s = _Parts()
+        for f in FLOAT_FIELDS + INT_FIELDS:
+            setattr(s, f, getattr(self, f).ctypes.data)
+        s.pid = self.particle_id.ctypes.data
+        s.n = self.n
+        return s
+
+    def copy(self) -> "Particles":
+        p = Particles(self.n)
+        for f in FLOAT_FIELDS + INT_FIELDS + ("particle_id",):
+            getattr(p, f)[:] = getattr(self, f)
+        p.turn = self.turn
+        return p
+
+    def coords(self) -> np.ndarray:
+        return np.stack([self.x, self.px, self.y, self.py, self.zeta, self.delta], axis=1)
+
+    def subset(self, idx) -> "Particles":
+        idx = np.asarray(idx)
+        p = Particles(len(idx))
+        for f in FLOAT_FIELDS + INT_FIELDS + ("particle_id",):
+            getattr(p, f)[:] = getattr(self, f)[idx]
+        p.turn = self.turn
+        return p
+
+
+def _ref3(ref) -> np.ndarray:
+    if hasattr(ref, "as_array"):
+        return np.ascontiguousarray(ref.as_array(), dtype=np.float64)
+    return np.ascontiguousarray(np.asarray(ref, dtype=np.float64))
+
+
+def _els(elements) -> np.ndarray:
+    a = np.ascontiguousarray(elements)
+    assert a.dtype.itemsize == 248, "element records must use the 248-byte layout"
+    return a
+
+
+def init(coords6, ref, first_id: int = 0) -> Particles:
+    """Particles from (n, 6) coordinates (x, px, y, py, zeta, delta)."""
+    c = np.ascontiguousarray(coords6, dtype=np.float64).reshape(-1, 6)
+    p = Particles(c.shape[0])
+    s = p._struct()
+    r = _ref3(ref)
+    lib().oracle_init(c.ctypes.data_as(ctypes.c_void_p), ctypes.c_int64(p.n),
+                      ctypes.c_int64(first_id), r.ctypes.data_as(ctypes.c_void_p),
+                      ctypes.byref(s))
+    return p
+
+
+def track(elements, ref, parts: Particles, n_turns: int, nthreads: int = 0) -> int:
+    """Forward tracking in place from turn ``parts.turn``; returns passes."""
+    el = _els(elements)
+    r = _ref3(ref)
+    s = parts._struct()
+    passes = lib().oracle_track(el.ctypes.data_as(ctypes.c_void_p), ctypes.c_int32(len(el)),
+                                r.ctypes.data_as(ctypes.c_void_p), ctypes.byref(s),
+                                ctypes.c_int32(parts.turn), ctypes.c_int32(n_turns),
+                                ctypes.c_int32(nthreads))
+    if passes < 0:
+        raise ValueError("oracle_track rejected its input (code %d)" % passes)
+    parts.turn += n_turns
+    return int(passes)
+
+
+def track_backward(elements, ref, parts: Particles, n_turns: int, nthreads: int = 0) -> int:
+    el = _els(elements)
+    r = _ref3(ref)
+    s = parts._struct()
+    passes = lib().oracle_track_backward(el.ctypes.data_as(ctypes.c_void_p),
+                                         ctypes.c_int32(len(el)),
+                                         r.ctypes.data_as(ctypes.c_void_p), ctypes.byref(s),
+                                         ctypes.c_int32(parts.turn), ctypes.c_int32(n_turns),
+                                         ctypes.c_int32(nthreads))
+    if passes < 0:
+        raise ValueError("oracle_track_backward rejected its input (code %d)" % passes)
+    parts.turn -= n_turns
+    return int(passes)
+
+
+def reference(ref) -> tuple[float, float]:
+    """(beta0, gamma0) as the oracle computes them."""
+    out = np.zeros(2)
+    r = _ref3(ref)
+    lib().oracle_reference(r.ctypes.data_as(ctypes.c_void_p), out.ctypes.data_as(ctypes.c_void_p))
+    return float(out[0]), float(out[1])
+
+
+def one_turn(elements, ref, u6, n_turns: int = 1) -> np.ndarray:
+    """Canonical map u = (x, px, y, py, zeta, pzeta) -> T^n(u)."""
+    el = _els(elements)
+    r = _ref3(ref)
+    u = np.array(u6, dtype=np.float64)
+    st = lib().oracle_track_canonical(el.ctypes.data_as(ctypes.c_void_p), ctypes.c_int32(len(el)),
+                                      r.ctypes.data_as(ctypes.c_void_p),
+                                      u.ctypes.data_as(ctypes.c_void_p), ctypes.c_int32(n_turns))
+    if st != 1:
+        raise RuntimeError("reference trajectory lost (state %d)" % st)
+    return u
+
+
+DEFAULT_FD_STEPS = np.array([1e-7, 1e-9, 1e-7, 1e-9, 1e-6, 1e-8])
+
+
+def jacobian(elements, ref, u0=None, h=DEFAULT_FD_STEPS, n_turns: int = 1,
+             richardson: bool = True) -> np.ndarray:
+    """Central-difference Jacobian of the canonical one-turn map (Twiss step 2):
+    J[:, j] = (T(u0 + h_j e_j) - T(u0 - h_j e_j)) / (2 h_j), optionally
+    Richardson-extrapolated from steps h and h/2."""
+    u0 = np.zeros(6) if u0 is None else np.asarray(u0, dtype=np.float64)
+
+    def cd(hh):
+        J = np.zeros((6, 6))
+        for j in range(6):
+            e = np.zeros(6)
+            e[j] = hh[j]
+            J[:, j] = (one_turn(elements, ref, u0 + e, n_turns)
+                       - one_turn(elements, ref, u0 - e, n_turns)) / (2.0 * hh[j])
+        return J
+
+    h = np.asarray(h, dtype=np.float64)
+    J1 = cd(h)
+    if not richardson:
+        return J1
+    J2 = cd(h / 2.0)
+    return (4.0 * J2 - J1) / 3.0
+
+
+S6 = np.kron(np.eye(3), np.array([[0.0, 1.0], [-1.0, 0.0]]))
+
+
+def symplectic_error(J: np.ndarray) -> float:
+    return float(np.max(np.abs(J.T @ S6 @ J - S6)))
+
+
+def normal_form_2x2(M: np.ndarray) -> dict:
+    """Uncoupled linear normal form of a 2x2 block (Twiss step 3 for one plane):
+    cos mu = tr/2, sin mu = sign(M12) sqrt(1 - cos^2), beta = M12/sin mu,
+    alpha = (M11 - M22)/(2 sin mu)."""
+    cmu = 0.5 * (M[0, 0] + M[1, 1])
+    smu = math.copysign(math.sqrt(max(0.0, 1.0 - cmu * cmu)), M[0, 1])
+    beta = M[0, 1] / smu
+    alpha = (M[0, 0] - M[1, 1]) / (2.0 * smu)
+    mu = math.atan2(smu, cmu) % (2.0 * math.pi)
+    return {"cos_mu": cmu, "sin_mu": smu, "beta": beta, "alpha": alpha,
+            "q": mu / (2.0 * math.pi)}
+
+
+def regular_mask(elements, ref, coords6, n_turns: int = 100, rtol: float = 1e-13,
+                 floor_frac: float = 1e-3) -> np.ndarray:
+    """Regular-orbit classification decided by the oracle alone: particle i is
+    regular if its twin, started with x moved by one ulp, stays within
+    ``rtol * max(|o|, s_c)`` of it in every coordinate after ``n_turns`` turns,
+    where s_c = floor_frac x the ensemble RMS of that coordinate.  Lost
+    particles (either twin) are not regular."""
+    c = np.array(coords6, dtype=np.float64).reshape(-1, 6)
+    a = init(c, ref)
+    c2 = c.copy()
+    c2[:, 0] = np.nextafter(c2[:, 0], np.inf)
+    b = init(c2, ref)
+    track(elements, ref, a, n_turns)
+    track(elements, ref, b, n_turns)
+    ok = (a.state == 1) & (b.state == 1)
+    ca, cb = a.coords(), b.coords()
+    if ok.any():
+        sc = floor_frac * np.sqrt(np.mean(ca[ok] ** 2, axis=0))
+    else:
+        sc = np.zeros(6)
+    err = np.abs(ca - cb) / np.maximum(np.abs(ca), sc[None, :])
+    return ok & np.all(err <= rtol, axis=1)

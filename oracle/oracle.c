@@ -1,0 +1,414 @@
+/*
+ * oracle.c -- plain, slow, obviously-correct CPU FP64 reference of the thin
+ * lattice tracking path (element-by-element tracking of a particle ensemble
+ * through a ring, paper section "Lattice modelling and single particle
+ * tracking").
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+ * benchmark's CPU-baseline leg may load this library.  It shares no code,
+ * header, table or constant generator with the HIP library; the two agree
+ * only on the element-record layout and on the written formulas below.
+ *
+ * The paper names the elements (drifts, thin multipoles with multipolar
+ * errors, RF cavities, tilts and misalignments as reference-frame changes,
+ * aperture checks that stop lost particles) but prints no formula.  Each map
+ * below is the standard accelerator-physics reading, stated next to it.
+ * Build: gcc -O2 -fno-fast-math -ffp-contract=off (every fused multiply-add
+ * is an explicit fma() call; everything else is a correctly rounded IEEE op).
+ *
+ * Coordinates: x, y [m]; px = Px/P0, py = Py/P0; zeta = s - beta0 c t [m];
+ * delta = (P - P0)/P0; derived and stored: ptau = (E - E0)/(P0 c),
+ * rpp = 1/(1+delta), rvv = beta/beta0.  One species per run (chi = 1).
+ *
+ * Loss codes: state 1 alive, 0 outside an aperture, -1 imaginary or
+ * non-finite longitudinal momentum in a drift.  On loss at element e of turn
+ * t: at_element = e, at_turn = t, coordinates stay as they entered e.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+enum { O_DRIFT = 1, O_DRIFT_EXP = 2, O_MULT = 3, O_RF = 4, O_SHIFT = 5,
+       O_SROT = 6, O_AP_CIRC = 7, O_AP_ELL = 8, O_AP_RECT = 9, O_MARKER = 10 };
+
+#define O_MAXORD 10
+
+/* element record: same byte layout as the element-description interface */
+typedef struct {
+  int32_t type, order;
+  double length;
+  double knl[O_MAXORD + 1], ksl[O_MAXORD + 1];
+  double hxl;
+  double p[6];
+} orc_elem;
+
+typedef struct {
+  double *x, *px, *y, *py, *zeta, *delta, *ptau, *rpp, *rvv;
+  int32_t *state, *at_element, *at_turn;
+  int64_t *pid;
+  int64_t n;
+} orc_parts;
+
+typedef struct {
+  double beta0, gamma0, p0c, mass0, charge0;
+} orc_ref;
+
+/* reference quantities: E0 = sqrt(p0c^2 + m^2), gamma0 = E0/m, beta0 = p0c/E0 */
+static orc_ref make_ref(const double ref3[3]) {
+  orc_ref r;
+  r.mass0 = ref3[0];
+  r.charge0 = ref3[1];
+  r.p0c = ref3[2];
+  double e0 = sqrt(r.p0c * r.p0c + r.mass0 * r.mass0);
+  r.gamma0 = e0 / r.mass0;
+  r.beta0 = r.p0c / e0;
+  return r;
+}
+
+/* per-particle working copy */
+typedef struct {
+  double x, px, y, py, zeta, delta, ptau, rpp, rvv;
+} orc_pt;
+
+/* ptau from delta without cancellation: u = delta(2+delta),
+   ptau = beta0 u / (1 + sqrt(1 + beta0^2 u))  (= sqrt((1+d)^2 + 1/(b0 g0)^2) - 1/b0) */
+static void set_from_delta(orc_pt* q, double b0) {
+  double u = q->delta * (2.0 + q->delta);
+  q->ptau = b0 * u / (1.0 + sqrt(1.0 + b0 * b0 * u));
+  q->rpp = 1.0 / (1.0 + q->delta);
+  q->rvv = (1.0 + q->delta) / (1.0 + b0 * q->ptau);
+}
+
+/* delta from ptau: v = ptau (ptau + 2/beta0) = delta(2+delta),
+   delta = v / (1 + sqrt(1 + v)) */
+static void set_from_ptau(orc_pt* q, double b0) {
+  double v = q->ptau * (q->ptau + 2.0 / b0);
+  q->delta = v / (1.0 + sqrt(1.0 + v));
+  q->rpp = 1.0 / (1.0 + q->delta);
+  q->rvv = (1.0 + q->delta) / (1.0 + b0 * q->ptau);
+}
+
+/* Exact drift over L: straight flight, path L(1+delta)/pz, and
+   dzeta = L - L(1+beta0 ptau)/pz written without cancellation as
+   (L/pz) * ( (delta(2+delta) - px^2 - py^2)/(1+pz) - beta0 ptau ).
+   Returns 0 if pz^2 is not positive (or not a number). */
+static int drift_exact(orc_pt* q, double L, double b0) {
+  double opd = 1.0 + q->delta;
+  double px2 = q->px * q->px;
+  double py2 = q->py * q->py;
+  double pz2 = opd * opd - px2 - py2;
+  if (!(pz2 > 0.0)) return 0;
+  double pz = sqrt(pz2);
+  double lp = L / pz;
+  q->x = fma(q->px, lp, q->x);
+  q->y = fma(q->py, lp, q->y);
+  double u = q->delta * (2.0 + q->delta);
+  double dz = (u - px2 - py2) / (1.0 + pz) - b0 * q->ptau;
+  q->zeta = fma(lp, dz, q->zeta);
+  return 1;
+}
+
+/* Expanded drift, exact flow of H = pzeta - (1+delta) + (px^2+py^2)/(2(1+delta)):
+   x += L px rpp, y += L py rpp,
+   zeta += L [ (delta - beta0 ptau) rpp - (px^2+py^2) rpp^3 (1+beta0 ptau)/2 ]. */
+static void drift_expanded(orc_pt* q, double L, double b0) {
+  double lr = L * q->rpp;
+  q->x = fma(q->px, lr, q->x);
+  q->y = fma(q->py, lr, q->y);
+  double pp = q->px * q->px + q->py * q->py;
+  double r3 = q->rpp * q->rpp * q->rpp;
+  double dz = (q->delta - b0 * q->ptau) * q->rpp - 0.5 * pp * r3 * (1.0 + b0 * q->ptau);
+  q->zeta = fma(L, dz, q->zeta);
+}
+
+/* Thin multipole: dpx - i dpy = - sum_n (knl_n + i ksl_n) (x + i y)^n / n!,
+   by Horner from the highest order down, each complex step
+   b <- b z + c_n as re = fma(br, x, fma(-bi, y, cr)), im = fma(br, y, fma(bi, x, ci)).
+   Curvature hxl (frame bend over the radiation length Lr):
+   dpx += hxl (1+delta) - knl0 hxl x / Lr (Lr > 0), dzeta = -hxl x (1+beta0 ptau) rpp.
+   sgn = +1 forward, -1 applies the exact inverse (x, y, delta unchanged). */
+typedef struct { double cr[O_MAXORD + 1], ci[O_MAXORD + 1]; } orc_coef;
+
+static void multipole_kick(orc_pt* q, const orc_elem* e, const orc_coef* c, double b0, double sgn) {
+  int N = e->order;
+  double br = c->cr[N], bi = c->ci[N];
+  for (int n = N - 1; n >= 0; --n) {
+    double tr = fma(br, q->x, fma(-bi, q->y, c->cr[n]));
+    double ti = fma(br, q->y, fma(bi, q->x, c->ci[n]));
+    br = tr;
+    bi = ti;
+  }
+  if (sgn > 0) {
+    q->px = q->px - br;
+    q->py = q->py + bi;
+  } else {
+    q->px = q->px + br;
+    q->py = q->py - bi;
+  }
+  if (e->hxl != 0.0) {
+    double dpx = e->hxl * (1.0 + q->delta);
+    if (e->length > 0.0) dpx = dpx - e->knl[0] * e->hxl * q->x / e->length;
+    double dz = e->hxl * q->x * (1.0 + b0 * q->ptau) * q->rpp;
+    if (sgn > 0) {
+      q->px = q->px + dpx;
+      q->zeta = q->zeta - dz;
+    } else {
+      q->px = q->px - dpx;
+      q->zeta = q->zeta + dz;
+    }
+  }
+}
+
+/* RF cavity (thin): ptau += (q V / p0c) sin(lag pi/180 - k zeta), k = 2 pi f/(beta0 c);
+   then delta, rpp, rvv from ptau.  No transverse kick. */
+static void rf_kick(orc_pt* q, const orc_elem* e, const orc_ref* r, double sgn) {
+  const double clight = 299792458.0;
+  double amp = r->charge0 * e->p[0] / r->p0c;
+  double k = 2.0 * M_PI * e->p[1] / (r->beta0 * clight);
+  double phi = e->p[2] * M_PI / 180.0;
+  double s = sin(phi - k * q->zeta);
+  if (sgn > 0)
+    q->ptau = q->ptau + amp * s;
+  else
+    q->ptau = q->ptau - amp * s;
+  set_from_ptau(q, r->beta0);
+}
+
+/* Reference-frame rotation by angle t about s:
+   (x, y) <- (c x + s y, c y - s x), same for (px, py). */
+static void srot(orc_pt* q, double cth, double sth) {
+  double x = cth * q->x + sth * q->y;
+  double y = cth * q->y - sth * q->x;
+  double px = cth * q->px + sth * q->py;
+  double py = cth * q->py - sth * q->px;
+  q->x = x; q->y = y; q->px = px; q->py = py;
+}
+
+/* aperture predicates written as "not inside", so a NaN coordinate is lost;
+   a particle exactly on the boundary survives */
+static int inside(const orc_pt* q, const orc_elem* e) {
+  switch (e->type) {
+    case O_AP_CIRC: {
+      double r2 = e->p[0] * e->p[0];
+      return q->x * q->x + q->y * q->y <= r2;
+    }
+    case O_AP_ELL: {
+      double ia2 = 1.0 / (e->p[0] * e->p[0]);
+      double ib2 = 1.0 / (e->p[1] * e->p[1]);
+      return q->x * q->x * ia2 + q->y * q->y * ib2 <= 1.0;
+    }
+    case O_AP_RECT:
+      return e->p[0] <= q->x && q->x <= e->p[1] && e->p[2] <= q->y && q->y <= e->p[3];
+    default:
+      return 1;
+  }
+}
+
+/* c_n = (knl_n + i ksl_n) / n!  (n! as an exact double) */
+static orc_coef* build_coefs(const orc_elem* el, int n_el) {
+  orc_coef* c = (orc_coef*)calloc((size_t)(n_el > 0 ? n_el : 1), sizeof(orc_coef));
+  for (int i = 0; i < n_el; ++i) {
+    double fact = 1.0;
+    for (int n = 0; n <= O_MAXORD; ++n) {
+      if (n > 0) fact *= (double)n;
+      c[i].cr[n] = el[i].knl[n] / fact;
+      c[i].ci[n] = el[i].ksl[n] / fact;
+    }
+  }
+  return c;
+}
+
+static int validate(const orc_elem* el, int n_el) {
+  for (int i = 0; i < n_el; ++i) {
+    int t = el[i].type;
+    if (t < O_DRIFT || t > O_MARKER) return -2;
+    if (t == O_MULT && (el[i].order < 0 || el[i].order > O_MAXORD)) return -2;
+  }
+  return 0;
+}
+
+static void load_pt(const orc_parts* P, int64_t i, orc_pt* q) {
+  q->x = P->x[i]; q->px = P->px[i]; q->y = P->y[i]; q->py = P->py[i];
+  q->zeta = P->zeta[i]; q->delta = P->delta[i]; q->ptau = P->ptau[i];
+  q->rpp = P->rpp[i]; q->rvv = P->rvv[i];
+}
+
+static void store_pt(const orc_parts* P, int64_t i, const orc_pt* q) {
+  P->x[i] = q->x; P->px[i] = q->px; P->y[i] = q->y; P->py[i] = q->py;
+  P->zeta[i] = q->zeta; P->delta[i] = q->delta; P->ptau[i] = q->ptau;
+  P->rpp[i] = q->rpp; P->rvv[i] = q->rvv;
+}
+
+/* apply element e to q; returns new state (1 alive, 0 aperture loss, -1 pz loss) */
+static int apply(orc_pt* q, const orc_elem* e, const orc_coef* c, const orc_ref* r, double sgn) {
+  switch (e->type) {
+    case O_DRIFT:
+      return drift_exact(q, sgn * e->length, r->beta0) ? 1 : -1;
+    case O_DRIFT_EXP:
+      drift_expanded(q, sgn * e->length, r->beta0);
+      return 1;
+    case O_MULT:
+      multipole_kick(q, e, c, r->beta0, sgn);
+      return 1;
+    case O_RF:
+      rf_kick(q, e, r, sgn);
+      return 1;
+    case O_SHIFT:
+      q->x = q->x - sgn * e->p[0];
+      q->y = q->y - sgn * e->p[1];
+      return 1;
+    case O_SROT:
+      srot(q, cos(e->p[0]), sgn * sin(e->p[0]));
+      return 1;
+    case O_AP_CIRC:
+    case O_AP_ELL:
+    case O_AP_RECT:
+      return inside(q, e) ? 1 : 0;
+    default:
+      return 1;
+  }
+}
+
+/* ---------------------------------------------------------------- API */
+
+/* Particle set-up from (n,6) host coordinates: derived variables from delta,
+   state = 1, at_element = at_turn = 0, particle_id = first_id + i. */
+int oracle_init(const double* coords6, int64_t n, int64_t first_id, const double ref3[3],
+                orc_parts* P) {
+  orc_ref r = make_ref(ref3);
+  for (int64_t i = 0; i < n; ++i) {
+    orc_pt q;
+    memset(&q, 0, sizeof q);
+    q.x = coords6[6 * i + 0]; q.px = coords6[6 * i + 1];
+    q.y = coords6[6 * i + 2]; q.py = coords6[6 * i + 3];
+    q.zeta = coords6[6 * i + 4]; q.delta = coords6[6 * i + 5];
+    set_from_delta(&q, r.beta0);
+    store_pt(P, i, &q);
+    P->state[i] = 1;
+    P->at_element[i] = 0;
+    P->at_turn[i] = 0;
+    P->pid[i] = first_id + i;
+  }
+  return 0;
+}
+
+/* Forward tracking for n_turns turns starting at turn t0:
+   for t in [t0, t0+n): for e in 0..E-1: if alive apply(e); survivors get at_turn = t+1.
+   Returns the number of (particle, element) applications made while alive
+   (including the application at which a particle is lost), or < 0 on error. */
+int64_t oracle_track(const orc_elem* el, int32_t n_el, const double ref3[3], orc_parts* P,
+                     int32_t t0, int32_t n_turns, int32_t nthreads) {
+  if (n_turns < 0 || n_el < 0) return -1;
+  if (validate(el, n_el)) return -2;
+  orc_ref r = make_ref(ref3);
+  orc_coef* c = build_coefs(el, n_el);
+  int64_t passes = 0;
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 64) reduction(+ : passes)
+#endif
+  for (int64_t i = 0; i < P->n; ++i) {
+    if (P->state[i] != 1) continue;
+    orc_pt q;
+    load_pt(P, i, &q);
+    int st = 1, lost_e = 0, lost_t = 0;
+    for (int32_t t = t0; t < t0 + n_turns && st == 1; ++t) {
+      for (int32_t e = 0; e < n_el; ++e) {
+        ++passes;
+        st = apply(&q, &el[e], &c[e], &r, 1.0);
+        if (st != 1) { /* loss is decided before any coordinate is modified */
+          lost_e = e;
+          lost_t = t;
+          break;
+        }
+      }
+      if (st == 1) P->at_turn[i] = t + 1;
+    }
+    store_pt(P, i, &q);
+    if (st != 1) {
+      P->state[i] = st;
+      P->at_element[i] = lost_e;
+      P->at_turn[i] = lost_t;
+    } else {
+      P->at_element[i] = 0;
+    }
+  }
+  free(c);
+  return passes;
+}
+
+/* Backward tracking: turns in reverse, elements E-1..0, each applying its
+   inverse (drift -L, kicks subtracted, shift +d, rotation -angle); apertures
+   are still checked.  Survivors end with at_turn = t0 - n_turns.  Particles
+   lost while going backward record the turn index being undone. */
+int64_t oracle_track_backward(const orc_elem* el, int32_t n_el, const double ref3[3],
+                              orc_parts* P, int32_t t0, int32_t n_turns, int32_t nthreads) {
+  if (n_turns < 0 || n_el < 0) return -1;
+  if (validate(el, n_el)) return -2;
+  orc_ref r = make_ref(ref3);
+  orc_coef* c = build_coefs(el, n_el);
+  int64_t passes = 0;
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 64) reduction(+ : passes)
+#endif
+  for (int64_t i = 0; i < P->n; ++i) {
+    if (P->state[i] != 1) continue;
+    orc_pt q;
+    load_pt(P, i, &q);
+    int st = 1, lost_e = 0, lost_t = 0;
+    for (int32_t t = t0 - 1; t >= t0 - n_turns && st == 1; --t) {
+      for (int32_t e = n_el - 1; e >= 0; --e) {
+        ++passes;
+        st = apply(&q, &el[e], &c[e], &r, -1.0);
+        if (st != 1) {
+          lost_e = e;
+          lost_t = t;
+          break;
+        }
+      }
+      if (st == 1) P->at_turn[i] = t;
+    }
+    store_pt(P, i, &q);
+    if (st != 1) {
+      P->state[i] = st;
+      P->at_element[i] = lost_e;
+      P->at_turn[i] = lost_t;
+    }
+  }
+  free(c);
+  return passes;
+}
+
+/* Track a single canonical 6-vector u = (x, px, y, py, zeta, pzeta) through
+   n_turns turns (no apertures are skipped: a loss returns its state).  Used
+   for the central-difference one-turn Jacobian, where the canonical partner of
+   zeta is pzeta = ptau/beta0 (delta, rpp, rvv recomputed from ptau). */
+int oracle_track_canonical(const orc_elem* el, int32_t n_el, const double ref3[3],
+                           double* u6, int32_t n_turns) {
+  if (validate(el, n_el)) return -2;
+  orc_ref r = make_ref(ref3);
+  orc_coef* c = build_coefs(el, n_el);
+  orc_pt q;
+  q.x = u6[0]; q.px = u6[1]; q.y = u6[2]; q.py = u6[3]; q.zeta = u6[4];
+  q.ptau = u6[5] * r.beta0;
+  set_from_ptau(&q, r.beta0);
+  int st = 1;
+  for (int32_t t = 0; t < n_turns && st == 1; ++t)
+    for (int32_t e = 0; e < n_el && st == 1; ++e) st = apply(&q, &el[e], &c[e], &r, 1.0);
+  u6[0] = q.x; u6[1] = q.px; u6[2] = q.y; u6[3] = q.py; u6[4] = q.zeta;
+  u6[5] = q.ptau / r.beta0;
+  free(c);
+  return st;
+}
+
+/* reference quantities as the oracle computes them: beta0, gamma0 */
+void oracle_reference(const double ref3[3], double out2[2]) {
+  orc_ref r = make_ref(ref3);
+  out2[0] = r.beta0;
+  out2[1] = r.gamma0;
+}
