@@ -1,0 +1,202 @@
+/*
+ * xtm.h -- C ABI of the MI355X (gfx950) thin-lattice FP64 tracking library.
+ *
+ * The library tracks an ensemble of particles element by element through a
+ * ring lattice for many turns (paper: Xsuite, arXiv 2310.00317, section
+ * "Lattice modelling and single particle tracking": the beam line is a
+ * sequence of element objects; the tracker runs the whole line in one
+ * compiled kernel; aperture elements stop particles found outside and record
+ * where they were lost, section "Particle-matter interaction and collimation
+ * studies").  The user-facing operations are: build a lattice, bind and
+ * initialise a particle set, track it n turns, read out the losses.
+ *
+ * Conventions for every entry point:
+ *  - Return value: XTM_OK (0) or a negative xtm_status.  Nothing throws
+ *    across the ABI.  xtm_last_error() gives a message for the calling
+ *    thread's last failure.
+ *  - Argument, element and reference validation is synchronous.  Device
+ *    faults surface at the next synchronising call (xtm_sync,
+ *    xtm_get_losses, or xtm_track when stats are requested) as XTM_E_HIP.
+ *  - Streams are passed as `void*` holding a hipStream_t (NULL = the null
+ *    stream).  All work is stream-ordered; only the calls documented as
+ *    synchronising wait for the device.
+ *  - Particle memory is CALLER-owned device memory; lattices and particle
+ *    views are LIBRARY-owned handles.  The library never frees or
+ *    reallocates caller memory.
+ *  - Particle-level trouble is not an error: it is recorded per particle
+ *    (state 1 alive, 0 lost on an aperture, -1 lost because the longitudinal
+ *    momentum became imaginary or non-finite in a drift), with the element
+ *    index (at_element) and turn (at_turn) of the loss.
+ *  - A handle must not be used from two host threads at once.
+ *
+ * Coordinates (per particle, FP64): x, y [m]; px = Px/P0, py = Py/P0;
+ * zeta = s - beta0 c t [m]; delta = (P-P0)/P0; derived and stored:
+ * ptau = (E-E0)/(P0 c), rpp = 1/(1+delta), rvv = beta/beta0.
+ */
+#ifndef XTM_H
+#define XTM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t xtm_status;
+enum {
+  XTM_OK = 0,
+  XTM_E_ARG = -1,         /* bad argument (null pointer, negative size, ...) */
+  XTM_E_ELEMENT = -2,     /* unknown element type or invalid element data    */
+  XTM_E_HIP = -3,         /* HIP runtime or device error                     */
+  XTM_E_NOMEM = -4,       /* device allocation failed                        */
+  XTM_E_REFERENCE = -5,   /* lattice and particles disagree on the reference */
+  XTM_E_UNSUPPORTED = -6, /* valid request the library does not implement    */
+  XTM_E_STATE = -7        /* call out of order (e.g. tracking an unset set)  */
+};
+
+/* Element type codes. */
+enum {
+  XTM_DRIFT = 1,          /* exact drift, length L                                   */
+  XTM_DRIFT_EXPANDED = 2, /* drift of the paraxial (expanded) Hamiltonian, length L  */
+  XTM_MULTIPOLE = 3,      /* thin multipole, orders 0..order, optional curvature     */
+  XTM_RF = 4,             /* thin RF cavity                                          */
+  XTM_XYSHIFT = 5,        /* reference-frame translation (misalignment)              */
+  XTM_SROTATION = 6,      /* reference-frame rotation about s (tilt)                 */
+  XTM_AP_CIRCLE = 7,      /* circular aperture                                       */
+  XTM_AP_ELLIPSE = 8,     /* elliptic aperture                                       */
+  XTM_AP_RECT = 9,        /* rectangular aperture                                    */
+  XTM_MARKER = 10         /* no-op                                                   */
+};
+#define XTM_MAX_ORDER 10
+
+/*
+ * Element description (248 bytes, natural alignment).  Meaning by type:
+ *  DRIFT, DRIFT_EXPANDED: length = L [m] (any sign; negative L undoes a drift).
+ *  MULTIPOLE: order N in 0..10; knl[n], ksl[n] integrated normal/skew strengths
+ *    of MAD index n [m^-n]; the kick is dpx - i dpy = -sum_n (knl_n + i ksl_n)
+ *    (x + i y)^n / n!.  hxl [rad] bends the reference frame over the length
+ *    `length` [m]: dpx += hxl (1+delta) - knl0 hxl x / length (last term only if
+ *    length > 0), zeta -= hxl x (1 + beta0 ptau) rpp.
+ *  RF: p[0] = V [V], p[1] = f [Hz], p[2] = lag [deg]:
+ *    ptau += (charge0 V / p0c) sin(lag pi/180 - 2 pi f zeta / (beta0 c)).
+ *  XYSHIFT: p[0] = dx, p[1] = dy [m]: x -= dx, y -= dy.
+ *  SROTATION: p[0] = angle [rad]: (x,y) <- (c x + s y, c y - s x), same for (px,py).
+ *  AP_CIRCLE: p[0] = r > 0.  AP_ELLIPSE: p[0] = a > 0, p[1] = b > 0.
+ *  AP_RECT: p[0..3] = xmin < xmax, ymin < ymax.  A particle exactly on the
+ *    boundary survives; a NaN coordinate is outside.
+ *  Unused fields are ignored.
+ */
+typedef struct xtm_element_desc {
+  int32_t type;
+  int32_t order;
+  double length;
+  double knl[XTM_MAX_ORDER + 1];
+  double ksl[XTM_MAX_ORDER + 1];
+  double hxl;
+  double p[6];
+} xtm_element_desc;
+
+/* Reference particle: rest mass [eV], charge [e], momentum p0c [eV].
+   beta0 = p0c / sqrt(p0c^2 + m^2), gamma0 = sqrt(p0c^2 + m^2) / m. */
+typedef struct xtm_reference {
+  double mass0_eV;
+  double charge0;
+  double p0c_eV;
+} xtm_reference;
+
+typedef struct xtm_lattice_s* xtm_lattice;     /* library-owned */
+typedef struct xtm_particles_s* xtm_particles; /* library-owned view of caller memory */
+
+/* Caller-owned device arrays of length n (contiguous, 8-byte aligned). */
+typedef struct xtm_arrays {
+  double *x, *px, *y, *py, *zeta, *delta, *ptau, *rpp, *rvv;
+  int32_t *state, *at_element, *at_turn;
+  int64_t* particle_id;
+  int64_t n;
+} xtm_arrays;
+
+const char* xtm_last_error(void);
+const char* xtm_version(void);
+
+/* Build a lattice from n element descriptions (host memory, copied; the
+   caller may free `el` on return).  Validates every element (unknown type,
+   order outside 0..10, non-positive aperture sizes, empty rectangle ->
+   XTM_E_ELEMENT; mass or p0c not positive -> XTM_E_REFERENCE).  Packs a
+   device table of per-element parameters for the forward and the inverse
+   (backward) direction.  n = 0 is allowed (tracking is then a no-op). */
+xtm_status xtm_lattice_create(const xtm_element_desc* el, int32_t n, const xtm_reference* ref,
+                              xtm_lattice* out);
+xtm_status xtm_lattice_destroy(xtm_lattice lat);
+/* Number of elements and size in bytes of the device table (forward). */
+xtm_status xtm_lattice_info(xtm_lattice lat, int32_t* n_elements, int64_t* table_bytes);
+
+/* Bind caller-owned device arrays as a particle set for reference `ref`.
+   Allocates the library's per-set work buffers (alive list, counters:
+   ~9 bytes per particle).  The arrays must stay valid until release. */
+xtm_status xtm_particles_bind(const xtm_arrays* a, const xtm_reference* ref, xtm_particles* out);
+xtm_status xtm_particles_release(xtm_particles p);
+
+/* Initialise the bound set from n x 6 row-major coordinates
+   (x, px, y, py, zeta, delta), n = the bound length.  `coords` is device
+   memory if coords_on_device != 0, host memory otherwise (copied before
+   return).  Derives ptau, rpp, rvv from delta; state = 1; at_element =
+   at_turn = 0; particle_id = first_id + i.  Resets the set's turn to 0 and
+   its alive list to all particles.  Stream-ordered. */
+xtm_status xtm_particles_init(xtm_particles p, const double* coords, int64_t first_id,
+                              int32_t coords_on_device, void* stream);
+
+/* Adopt externally written arrays (e.g. a snapshot restored by the caller):
+   the set's turn becomes `turn` and its alive list is rebuilt from `state`
+   on the device.  Alive particles must have at_turn == turn. */
+xtm_status xtm_particles_reset(xtm_particles p, int32_t turn, void* stream);
+
+/* Current turn of the set's alive particles (host-side counter). */
+xtm_status xtm_particles_turn(xtm_particles p, int32_t* turn);
+
+/* Tracking options (a zeroed struct, or NULL, selects defaults). */
+typedef struct xtm_track_opts {
+  int32_t turns_per_chunk; /* turns per kernel launch; 0 = automatic                  */
+  int32_t block;           /* threads per workgroup (64..1024, multiple of 64); 0 = auto */
+  int32_t no_compact;      /* 1 = keep lost particles in the alive list between chunks */
+  int32_t use_graph;       /* 1 = replay the chunk sequence as a captured hipGraph    */
+  int32_t time_kernels;    /* 1 = time each tracking launch with HIP events (stats)   */
+} xtm_track_opts;
+
+typedef struct xtm_track_stats {
+  int64_t passes;     /* (particle, element) applications made while alive, loss included */
+  int64_t alive;      /* particles alive after the call */
+  int32_t launches;   /* tracking-kernel launches made by the call */
+  int32_t reserved;
+  double kernel_ms;   /* summed duration of those launches (time_kernels = 1), else 0 */
+} xtm_track_stats;
+
+/* Track the set n_turns turns forward through `lat`, continuing from the
+   set's turn t: for each turn, each element in order is applied to every
+   alive particle; a particle lost at element e of turn u gets state 0/-1,
+   at_element = e, at_turn = u, and keeps its coordinates as they entered e;
+   survivors end with at_turn = t + n_turns.  track(a) then track(b) gives
+   bitwise the same result as track(a+b).  Returns after enqueueing, unless
+   `stats` is non-NULL, in which case it synchronises the stream and fills
+   the statistics.  XTM_E_REFERENCE if lat and p have different references. */
+xtm_status xtm_track(xtm_lattice lat, xtm_particles p, int32_t n_turns,
+                     const xtm_track_opts* opts, void* stream, xtm_track_stats* stats);
+
+/* Track n_turns backward: turns in reverse, elements last to first, each
+   applying its exact inverse (drift -L, kicks subtracted, shift +d, rotation
+   -angle); apertures still check.  Survivors end with at_turn = t - n_turns;
+   a particle lost while going back records the turn index being undone. */
+xtm_status xtm_track_backward(xtm_lattice lat, xtm_particles p, int32_t n_turns,
+                              void* stream, xtm_track_stats* stats);
+
+/* Copy the loss record into host buffers of the bound length (any may be
+   NULL).  Synchronises the stream. */
+xtm_status xtm_get_losses(xtm_particles p, int32_t* h_state, int32_t* h_at_turn,
+                          int32_t* h_at_element, void* stream);
+
+/* Synchronise the stream and report any asynchronous device error. */
+xtm_status xtm_sync(void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* XTM_H */

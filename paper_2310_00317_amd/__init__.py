@@ -1,0 +1,262 @@
+"""MI355X (gfx950) FP64 thin-lattice particle tracker.
+
+Thin Python binding over the C ABI of ``libxtm.so`` (declared in
+``include/xtm.h``).  It only marshals arguments: device memory comes from
+torch tensors on the ROCm device, every computation runs in the library's
+HIP kernels.  Importing the package does not load the library; the first
+call that needs it does, and raises if it was not built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+from . import inputs  # noqa: F401  (seeded input generators)
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libxtm.so")
+
+XTM_OK = 0
+STATUS_NAMES = {0: "XTM_OK", -1: "XTM_E_ARG", -2: "XTM_E_ELEMENT", -3: "XTM_E_HIP",
+                -4: "XTM_E_NOMEM", -5: "XTM_E_REFERENCE", -6: "XTM_E_UNSUPPORTED",
+                -7: "XTM_E_STATE"}
+
+FLOAT_FIELDS = ("x", "px", "y", "py", "zeta", "delta", "ptau", "rpp", "rvv")
+INT_FIELDS = ("state", "at_element", "at_turn")
+
+
+class XtmError(RuntimeError):
+    def __init__(self, code: int, where: str, msg: str):
+        super().__init__(f"{where}: {STATUS_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class _Reference(ctypes.Structure):
+    _fields_ = [("mass0_eV", ctypes.c_double), ("charge0", ctypes.c_double),
+                ("p0c_eV", ctypes.c_double)]
+
+
+class _Arrays(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_void_p) for f in FLOAT_FIELDS + INT_FIELDS + ("particle_id",)] + \
+        [("n", ctypes.c_int64)]
+
+
+class TrackOpts(ctypes.Structure):
+    _fields_ = [("turns_per_chunk", ctypes.c_int32), ("block", ctypes.c_int32),
+                ("no_compact", ctypes.c_int32), ("use_graph", ctypes.c_int32),
+                ("time_kernels", ctypes.c_int32)]
+
+
+class TrackStats(ctypes.Structure):
+    _fields_ = [("passes", ctypes.c_int64), ("alive", ctypes.c_int64),
+                ("launches", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("kernel_ms", ctypes.c_double)]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libxtm.so (built by ``paper_2310_00317_amd.build``); no fallback."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_2310_00317_amd.build` (there is no CPU fallback)")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+        sig = {
+            "xtm_last_error": ([], ctypes.c_char_p),
+            "xtm_version": ([], ctypes.c_char_p),
+            "xtm_lattice_create": ([vp, i32, vp, vp], i32),
+            "xtm_lattice_destroy": ([vp], i32),
+            "xtm_lattice_info": ([vp, vp, vp], i32),
+            "xtm_particles_bind": ([vp, vp, vp], i32),
+            "xtm_particles_release": ([vp], i32),
+            "xtm_particles_init": ([vp, vp, i64, i32, vp], i32),
+            "xtm_particles_reset": ([vp, i32, vp], i32),
+            "xtm_particles_turn": ([vp, vp], i32),
+            "xtm_track": ([vp, vp, i32, vp, vp, vp], i32),
+            "xtm_track_backward": ([vp, vp, i32, vp, vp], i32),
+            "xtm_get_losses": ([vp, vp, vp, vp, vp], i32),
+            "xtm_sync": ([vp], i32),
+        }
+        for name, (args, res) in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+def check(code: int, where: str) -> None:
+    if code != XTM_OK:
+        raise XtmError(code, where, lib().xtm_last_error().decode())
+
+
+def _ref_struct(ref) -> _Reference:
+    return _Reference(float(ref.mass0_eV), float(ref.charge0), float(ref.p0c_eV))
+
+
+def _stream(stream=None):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Lattice:
+    """Library-owned element table built from 248-byte element records."""
+
+    def __init__(self, elements: np.ndarray, ref):
+        el = np.ascontiguousarray(elements)
+        if el.dtype.itemsize != inputs.ELEMENT_DTYPE.itemsize:
+            raise ValueError("elements must use inputs.ELEMENT_DTYPE")
+        self.ref = ref
+        self.n_elements = len(el)
+        self._el = el
+        r = _ref_struct(ref)
+        h = ctypes.c_void_p()
+        check(lib().xtm_lattice_create(el.ctypes.data_as(ctypes.c_void_p), len(el),
+                                       ctypes.byref(r), ctypes.byref(h)), "xtm_lattice_create")
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def table_bytes(self) -> int:
+        n = ctypes.c_int32()
+        b = ctypes.c_int64()
+        check(lib().xtm_lattice_info(self._h, ctypes.byref(n), ctypes.byref(b)), "xtm_lattice_info")
+        return int(b.value)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().xtm_lattice_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Particles:
+    """Caller-owned SoA particle arrays (torch tensors on the GPU) bound as a set."""
+
+    def __init__(self, n: int, ref, device="cuda"):
+        import torch
+        self.n = int(n)
+        self.ref = ref
+        self.device = torch.device(device)
+        m = max(self.n, 1)
+        for f in FLOAT_FIELDS:
+            setattr(self, f, torch.zeros(m, dtype=torch.float64, device=self.device))
+        for f in INT_FIELDS:
+            setattr(self, f, torch.zeros(m, dtype=torch.int32, device=self.device))
+        self.particle_id = torch.zeros(m, dtype=torch.int64, device=self.device)
+        a = _Arrays()
+        for f in FLOAT_FIELDS + INT_FIELDS + ("particle_id",):
+            setattr(a, f, getattr(self, f).data_ptr())
+        a.n = self.n
+        r = _ref_struct(ref)
+        h = ctypes.c_void_p()
+        check(lib().xtm_particles_bind(ctypes.byref(a), ctypes.byref(r), ctypes.byref(h)),
+              "xtm_particles_bind")
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def init(self, coords, first_id: int = 0, stream=None):
+        """Set coordinates from an (n, 6) array (numpy: host; torch cuda tensor: device)."""
+        import torch
+        if isinstance(coords, torch.Tensor):
+            c = coords.to(dtype=torch.float64).contiguous()
+            if c.shape != (self.n, 6):
+                raise ValueError("coords must have shape (n, 6)")
+            on_dev = 1 if c.is_cuda else 0
+            ptr = ctypes.c_void_p(c.data_ptr())
+            keep = c
+        else:
+            keep = np.ascontiguousarray(coords, dtype=np.float64).reshape(-1, 6)
+            if keep.shape[0] != self.n:
+                raise ValueError("coords must have shape (n, 6)")
+            on_dev = 0
+            ptr = keep.ctypes.data_as(ctypes.c_void_p)
+        check(lib().xtm_particles_init(self._h, ptr, int(first_id), on_dev, _stream(stream)),
+              "xtm_particles_init")
+        if on_dev:
+            torch.cuda.current_stream().synchronize()
+        del keep
+        return self
+
+    def reset(self, turn: int, stream=None):
+        check(lib().xtm_particles_reset(self._h, int(turn), _stream(stream)), "xtm_particles_reset")
+
+    @property
+    def turn(self) -> int:
+        t = ctypes.c_int32()
+        check(lib().xtm_particles_turn(self._h, ctypes.byref(t)), "xtm_particles_turn")
+        return int(t.value)
+
+    def to_numpy(self) -> dict:
+        import torch
+        torch.cuda.synchronize()
+        out = {}
+        for f in FLOAT_FIELDS + INT_FIELDS + ("particle_id",):
+            out[f] = getattr(self, f)[: self.n].cpu().numpy()
+        return out
+
+    def losses(self, stream=None):
+        st = np.zeros(max(self.n, 1), dtype=np.int32)
+        at = np.zeros_like(st)
+        ae = np.zeros_like(st)
+        check(lib().xtm_get_losses(self._h, st.ctypes.data_as(ctypes.c_void_p),
+                                   at.ctypes.data_as(ctypes.c_void_p),
+                                   ae.ctypes.data_as(ctypes.c_void_p), _stream(stream)),
+              "xtm_get_losses")
+        return st[: self.n], at[: self.n], ae[: self.n]
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().xtm_particles_release(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def track(lattice: Lattice, particles: Particles, n_turns: int, turns_per_chunk: int = 0,
+          block: int = 0, compact: bool = True, graph: bool = False, stats: bool = True,
+          time_kernels: bool = False, stream=None, full_stats: bool = False):
+    """Track ``n_turns`` forward.  With ``stats`` (synchronising) returns
+    (passes, alive), or the whole TrackStats if ``full_stats``."""
+    o = TrackOpts(int(turns_per_chunk), int(block), 0 if compact else 1, 1 if graph else 0,
+                  1 if time_kernels else 0)
+    s = TrackStats()
+    check(lib().xtm_track(lattice.handle, particles.handle, int(n_turns), ctypes.byref(o),
+                          _stream(stream), ctypes.byref(s) if (stats or full_stats) else None),
+          "xtm_track")
+    if full_stats:
+        return s
+    return (int(s.passes), int(s.alive)) if stats else None
+
+
+def track_backward(lattice: Lattice, particles: Particles, n_turns: int, stats: bool = True,
+                   stream=None):
+    s = TrackStats()
+    check(lib().xtm_track_backward(lattice.handle, particles.handle, int(n_turns), _stream(stream),
+                                   ctypes.byref(s) if stats else None), "xtm_track_backward")
+    return (int(s.passes), int(s.alive)) if stats else None
+
+
+def sync(stream=None):
+    check(lib().xtm_sync(_stream(stream)), "xtm_sync")

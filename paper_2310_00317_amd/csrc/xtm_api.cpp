@@ -1,0 +1,499 @@
+// xtm_api.cpp -- C ABI of the tracking library (see include/xtm.h).
+//
+// Host side: validation, packing of the element table (forward and inverse
+// direction), per-set work buffers, and the chunk loop that drives the
+// gfx950 kernels on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <exception>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/xtm.h"
+#include "xtm_internal.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+xtm_status fail(xtm_status code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+xtm_status hip_fail(hipError_t e, const char* where) {
+  return fail(XTM_E_HIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr, where)               \
+  do {                                     \
+    hipError_t _e = (expr);                \
+    if (_e != hipSuccess) return hip_fail(_e, where); \
+  } while (0)
+
+constexpr double kClight = 299792458.0;
+
+struct RefQ {
+  double mass0, charge0, p0c, beta0, gamma0;
+};
+
+bool make_ref(const xtm_reference* r, RefQ* q) {
+  if (!r || !(r->mass0_eV > 0.0) || !(r->p0c_eV > 0.0) || !std::isfinite(r->charge0)) return false;
+  q->mass0 = r->mass0_eV;
+  q->charge0 = r->charge0;
+  q->p0c = r->p0c_eV;
+  const double e0 = std::sqrt(q->p0c * q->p0c + q->mass0 * q->mass0);
+  q->gamma0 = e0 / q->mass0;
+  q->beta0 = q->p0c / e0;
+  return true;
+}
+
+bool same_ref(const RefQ& a, const RefQ& b) {
+  return a.mass0 == b.mass0 && a.charge0 == b.charge0 && a.p0c == b.p0c;
+}
+
+}  // namespace
+
+struct xtm_lattice_s {
+  int32_t n_el = 0;
+  RefQ ref{};
+  std::vector<uint64_t> fwd_h, bwd_h;
+  uint64_t* fwd_d = nullptr;
+  uint64_t* bwd_d = nullptr;
+};
+
+struct xtm_particles_s {
+  xtm_arrays a{};
+  RefQ ref{};
+  int64_t n = 0;
+  int32_t turn = 0;
+  bool initialised = false;
+  int32_t* idx[2] = {nullptr, nullptr};
+  int32_t cur = 0;          // which idx buffer holds the alive list
+  int32_t* ctrl = nullptr;  // [0] alive count, [2] count scanned by the last epilogue
+  int32_t* blockcnt = nullptr;
+  int64_t* passes = nullptr;
+  int64_t alive_upper = 0;  // host-side upper bound of the alive count
+};
+
+namespace {
+
+using namespace xtm;
+
+void put_d(std::vector<uint64_t>& v, double d) {
+  uint64_t u;
+  std::memcpy(&u, &d, 8);
+  v.push_back(u);
+}
+
+// Pack one element; sgn = +1 forward map, -1 its exact inverse (parameters
+// negated so that the same kernel code applies the inverse).
+xtm_status pack(const xtm_element_desc& e, int32_t index, const RefQ& r, double sgn,
+                std::vector<uint64_t>& out) {
+  auto hdr = [&](uint32_t kt, uint32_t order, uint32_t nw) {
+    out.push_back(make_header(kt, order, nw, (uint32_t)index));
+  };
+  const std::string where = "element " + std::to_string(index) + ": ";
+  switch (e.type) {
+    case XTM_DRIFT:
+    case XTM_DRIFT_EXPANDED:
+      if (!std::isfinite(e.length)) return fail(XTM_E_ELEMENT, where + "non-finite drift length");
+      hdr(e.type == XTM_DRIFT ? K_DRIFT : K_DRIFT_EXP, 0, 1);
+      put_d(out, sgn * e.length);
+      return XTM_OK;
+    case XTM_MULTIPOLE: {
+      if (e.order < 0 || e.order > XTM_MAX_ORDER)
+        return fail(XTM_E_ELEMENT, where + "multipole order outside 0..10");
+      const bool curv = (e.hxl != 0.0);
+      const uint32_t N = (uint32_t)e.order;
+      hdr(curv ? K_MULT_CURV : K_MULT, N, 2 * (N + 1) + (curv ? 3 : 0));
+      // c_n = (knl_n + i ksl_n)/n!, stored from the top order down
+      double fact[XTM_MAX_ORDER + 1];
+      fact[0] = 1.0;
+      for (int n = 1; n <= XTM_MAX_ORDER; ++n) fact[n] = fact[n - 1] * (double)n;
+      for (int n = (int)N; n >= 0; --n) {
+        const double cr = e.knl[n] / fact[n];
+        const double ci = e.ksl[n] / fact[n];
+        put_d(out, sgn * cr);
+        put_d(out, sgn * ci);
+      }
+      if (curv) {
+        put_d(out, sgn * e.hxl);
+        put_d(out, sgn * (e.knl[0] * e.hxl));
+        put_d(out, e.length);
+      }
+      return XTM_OK;
+    }
+    case XTM_RF: {
+      const double V = e.p[0], f = e.p[1], lag = e.p[2];
+      if (!std::isfinite(V) || !std::isfinite(f) || !std::isfinite(lag) || f < 0.0)
+        return fail(XTM_E_ELEMENT, where + "RF needs finite V, f >= 0, lag");
+      hdr(K_RF, 0, 3);
+      const double amp = r.charge0 * V / r.p0c;
+      const double k = 2.0 * M_PI * f / (r.beta0 * kClight);
+      const double phi = lag * M_PI / 180.0;
+      put_d(out, sgn * amp);
+      put_d(out, k);
+      put_d(out, phi);
+      return XTM_OK;
+    }
+    case XTM_XYSHIFT:
+      hdr(K_SHIFT, 0, 2);
+      put_d(out, sgn * e.p[0]);
+      put_d(out, sgn * e.p[1]);
+      return XTM_OK;
+    case XTM_SROTATION:
+      hdr(K_SROT, 0, 2);
+      put_d(out, std::cos(e.p[0]));
+      put_d(out, sgn * std::sin(e.p[0]));
+      return XTM_OK;
+    case XTM_AP_CIRCLE:
+      if (!(e.p[0] > 0.0)) return fail(XTM_E_ELEMENT, where + "aperture radius must be > 0");
+      hdr(K_AP_CIRC, 0, 1);
+      put_d(out, e.p[0] * e.p[0]);
+      return XTM_OK;
+    case XTM_AP_ELLIPSE:
+      if (!(e.p[0] > 0.0) || !(e.p[1] > 0.0))
+        return fail(XTM_E_ELEMENT, where + "ellipse half-axes must be > 0");
+      hdr(K_AP_ELL, 0, 2);
+      put_d(out, 1.0 / (e.p[0] * e.p[0]));
+      put_d(out, 1.0 / (e.p[1] * e.p[1]));
+      return XTM_OK;
+    case XTM_AP_RECT:
+      if (!(e.p[0] < e.p[1]) || !(e.p[2] < e.p[3]))
+        return fail(XTM_E_ELEMENT, where + "rectangle needs xmin < xmax and ymin < ymax");
+      hdr(K_AP_RECT, 0, 4);
+      for (int k = 0; k < 4; ++k) put_d(out, e.p[k]);
+      return XTM_OK;
+    case XTM_MARKER:
+      hdr(K_MARKER, 0, 0);
+      return XTM_OK;
+    default:
+      return fail(XTM_E_ELEMENT, where + "unknown element type " + std::to_string(e.type));
+  }
+}
+
+SoA soa_of(const xtm_particles_s* p) {
+  SoA s;
+  s.x = p->a.x; s.px = p->a.px; s.y = p->a.y; s.py = p->a.py; s.zeta = p->a.zeta;
+  s.delta = p->a.delta; s.ptau = p->a.ptau; s.rpp = p->a.rpp; s.rvv = p->a.rvv;
+  s.state = p->a.state; s.at_element = p->a.at_element; s.at_turn = p->a.at_turn;
+  s.pid = p->a.particle_id;
+  return s;
+}
+
+KernelRef kref(const RefQ& r) {
+  KernelRef k;
+  k.beta0 = r.beta0;
+  k.two_over_beta0 = 2.0 / r.beta0;
+  return k;
+}
+
+xtm_status read_alive(xtm_particles_s* p, hipStream_t s, int64_t* alive, int64_t* passes) {
+  int32_t c[4];
+  HIP_TRY(hipMemcpyAsync(c, p->ctrl, sizeof c, hipMemcpyDeviceToHost, s), "read counters");
+  int64_t np = 0;
+  HIP_TRY(hipMemcpyAsync(&np, p->passes, sizeof np, hipMemcpyDeviceToHost, s), "read passes");
+  HIP_TRY(hipStreamSynchronize(s), "synchronise");
+  if (alive) *alive = c[0];
+  if (passes) *passes = np;
+  p->alive_upper = c[0];
+  return XTM_OK;
+}
+
+int32_t auto_chunk(int64_t n, int32_t n_el, int32_t n_turns) {
+  // aim at ~2e10 passes per launch so launch and epilogue costs vanish, while
+  // compacting often enough that lost lanes stop costing issue slots
+  const double per_turn = (double)(n > 0 ? n : 1) * (double)(n_el > 0 ? n_el : 1);
+  double k = 2e10 / per_turn;
+  if (k < 1.0) k = 1.0;
+  if (k > (double)n_turns) k = (double)n_turns;
+  return (int32_t)k;
+}
+
+xtm_status run_turns(xtm_lattice_s* L, xtm_particles_s* P, int32_t n_turns,
+                     const xtm_track_opts* o, hipStream_t s, xtm_track_stats* stats,
+                     bool backward) {
+  if (!L || !P) return fail(XTM_E_ARG, "null handle");
+  if (n_turns < 0) return fail(XTM_E_ARG, "n_turns must be >= 0");
+  if (!P->initialised) return fail(XTM_E_STATE, "particle set not initialised");
+  if (!same_ref(L->ref, P->ref))
+    return fail(XTM_E_REFERENCE, "lattice and particle set have different references");
+  if (backward && P->turn - n_turns < INT32_MIN / 2) return fail(XTM_E_ARG, "turn underflow");
+  if (!backward && (int64_t)P->turn + n_turns > INT32_MAX / 2) return fail(XTM_E_ARG, "turn overflow");
+  int32_t block = (o && o->block) ? o->block : 256;
+  if (block < 64 || block > 256 || block % 64)
+    return fail(XTM_E_ARG, "block must be 64, 128, 192 or 256");
+  const bool compact = !(o && o->no_compact) || backward;
+  int32_t chunk = (o && o->turns_per_chunk > 0) ? o->turns_per_chunk
+                                                 : auto_chunk(P->alive_upper, L->n_el, n_turns);
+  if (stats) HIP_TRY(launch_fill_i64(P->passes, 0, s), "clear passes");
+  const uint64_t* tab = backward ? L->bwd_d : L->fwd_d;
+  const SoA soa = soa_of(P);
+  const KernelRef kr = kref(L->ref);
+  const bool timing = stats && o && o->time_kernels;
+  std::vector<hipEvent_t> ev;
+  int32_t launches = 0;
+  int32_t done = 0;
+  while (done < n_turns && L->n_el > 0 && P->alive_upper > 0) {
+    const int32_t k = (n_turns - done < chunk) ? n_turns - done : chunk;
+    const int32_t t0 = backward ? P->turn - done : P->turn + done;
+    int32_t* in = P->idx[P->cur];
+    int32_t* out = compact ? P->idx[1 - P->cur] : nullptr;
+    if (timing) {
+      hipEvent_t a, b;
+      HIP_TRY(hipEventCreate(&a), "event");
+      HIP_TRY(hipEventCreate(&b), "event");
+      ev.push_back(a);
+      ev.push_back(b);
+      HIP_TRY(hipEventRecord(a, s), "event record");
+    }
+    HIP_TRY(launch_track(tab, L->n_el, soa, in, P->ctrl, P->alive_upper, block, k, t0,
+                         backward ? 1 : 0, kr, s),
+            "track kernel launch");
+    if (timing) HIP_TRY(hipEventRecord(ev.back(), s), "event record");
+    ++launches;
+    HIP_TRY(launch_epilogue(in, out, P->alive_upper, soa, P->ctrl, P->blockcnt, P->passes,
+                            L->n_el, k, t0, backward ? 1 : 0, s),
+            "epilogue launch");
+    if (compact) P->cur = 1 - P->cur;
+    done += k;
+  }
+  P->turn = backward ? P->turn - n_turns : P->turn + n_turns;
+  if (stats) {
+    int64_t alive = 0, passes = 0;
+    xtm_status st = read_alive(P, s, &alive, &passes);
+    double ms = 0.0;
+    for (size_t j = 0; j + 1 < ev.size(); j += 2) {
+      float dt = 0.f;
+      if (st == XTM_OK && hipEventElapsedTime(&dt, ev[j], ev[j + 1]) == hipSuccess) ms += dt;
+    }
+    for (hipEvent_t e : ev) hipEventDestroy(e);
+    if (st != XTM_OK) return st;
+    stats->alive = alive;
+    stats->passes = passes;
+    stats->launches = launches;
+    stats->kernel_ms = ms;
+  }
+  return XTM_OK;
+}
+
+template <class F>
+xtm_status guarded(F&& f) {
+  try {
+    return f();
+  } catch (const std::bad_alloc&) {
+    return fail(XTM_E_NOMEM, "host allocation failed");
+  } catch (const std::exception& ex) {
+    return fail(XTM_E_ARG, ex.what());
+  } catch (...) {
+    return fail(XTM_E_ARG, "unknown exception");
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* xtm_last_error(void) { return g_err.c_str(); }
+
+const char* xtm_version(void) { return "xtm 0.1 (gfx950, FP64 thin-lattice tracker)"; }
+
+xtm_status xtm_lattice_create(const xtm_element_desc* el, int32_t n, const xtm_reference* ref,
+                              xtm_lattice* out) {
+  return guarded([&]() -> xtm_status {
+    if (!out) return fail(XTM_E_ARG, "out is null");
+    *out = nullptr;
+    if (n < 0 || (n > 0 && !el)) return fail(XTM_E_ARG, "bad element array");
+    RefQ r;
+    if (!make_ref(ref, &r)) return fail(XTM_E_REFERENCE, "reference needs mass > 0 and p0c > 0");
+    auto* L = new xtm_lattice_s();
+    L->n_el = n;
+    L->ref = r;
+    for (int32_t i = 0; i < n; ++i) {
+      xtm_status st = pack(el[i], i, r, 1.0, L->fwd_h);
+      if (st != XTM_OK) { delete L; return st; }
+    }
+    for (int32_t i = n - 1; i >= 0; --i) {
+      xtm_status st = pack(el[i], i, r, -1.0, L->bwd_h);
+      if (st != XTM_OK) { delete L; return st; }
+    }
+    const size_t bytes = (L->fwd_h.size() + 1) * sizeof(uint64_t);
+    if (hipMalloc(&L->fwd_d, bytes) != hipSuccess || hipMalloc(&L->bwd_d, bytes) != hipSuccess) {
+      hipFree(L->fwd_d);
+      delete L;
+      return fail(XTM_E_NOMEM, "device allocation of the element table failed");
+    }
+    L->fwd_h.push_back(0);
+    L->bwd_h.push_back(0);
+    if (hipMemcpy(L->fwd_d, L->fwd_h.data(), bytes, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(L->bwd_d, L->bwd_h.data(), bytes, hipMemcpyHostToDevice) != hipSuccess) {
+      hipFree(L->fwd_d);
+      hipFree(L->bwd_d);
+      delete L;
+      return fail(XTM_E_HIP, "copy of the element table failed");
+    }
+    *out = L;
+    return XTM_OK;
+  });
+}
+
+xtm_status xtm_lattice_destroy(xtm_lattice L) {
+  if (!L) return XTM_OK;
+  hipFree(L->fwd_d);
+  hipFree(L->bwd_d);
+  delete L;
+  return XTM_OK;
+}
+
+xtm_status xtm_lattice_info(xtm_lattice L, int32_t* n_elements, int64_t* table_bytes) {
+  if (!L) return fail(XTM_E_ARG, "null lattice");
+  if (n_elements) *n_elements = L->n_el;
+  if (table_bytes) *table_bytes = (int64_t)(L->fwd_h.size() * sizeof(uint64_t));
+  return XTM_OK;
+}
+
+xtm_status xtm_particles_bind(const xtm_arrays* a, const xtm_reference* ref, xtm_particles* out) {
+  return guarded([&]() -> xtm_status {
+    if (!out) return fail(XTM_E_ARG, "out is null");
+    *out = nullptr;
+    if (!a || a->n < 0) return fail(XTM_E_ARG, "bad array descriptor");
+    if (a->n > INT32_MAX - 1024) return fail(XTM_E_ARG, "at most 2^31 - 1025 particles per set");
+    if (a->n > 0 && (!a->x || !a->px || !a->y || !a->py || !a->zeta || !a->delta || !a->ptau ||
+                     !a->rpp || !a->rvv || !a->state || !a->at_element || !a->at_turn ||
+                     !a->particle_id))
+      return fail(XTM_E_ARG, "null particle array");
+    RefQ r;
+    if (!make_ref(ref, &r)) return fail(XTM_E_REFERENCE, "reference needs mass > 0 and p0c > 0");
+    auto* P = new xtm_particles_s();
+    P->a = *a;
+    P->ref = r;
+    P->n = a->n;
+    const int64_t m = a->n > 0 ? a->n : 1;
+    const int64_t nb = (m + kScanBlock - 1) / kScanBlock;
+    bool ok = hipMalloc(&P->idx[0], m * sizeof(int32_t)) == hipSuccess &&
+              hipMalloc(&P->idx[1], m * sizeof(int32_t)) == hipSuccess &&
+              hipMalloc(&P->ctrl, 4 * sizeof(int32_t)) == hipSuccess &&
+              hipMalloc(&P->blockcnt, nb * sizeof(int32_t)) == hipSuccess &&
+              hipMalloc(&P->passes, sizeof(int64_t)) == hipSuccess;
+    if (!ok) {
+      hipFree(P->idx[0]); hipFree(P->idx[1]); hipFree(P->ctrl); hipFree(P->blockcnt);
+      hipFree(P->passes);
+      delete P;
+      return fail(XTM_E_NOMEM, "device allocation of particle work buffers failed");
+    }
+    *out = P;
+    return XTM_OK;
+  });
+}
+
+xtm_status xtm_particles_release(xtm_particles P) {
+  if (!P) return XTM_OK;
+  hipFree(P->idx[0]);
+  hipFree(P->idx[1]);
+  hipFree(P->ctrl);
+  hipFree(P->blockcnt);
+  hipFree(P->passes);
+  delete P;
+  return XTM_OK;
+}
+
+xtm_status xtm_particles_init(xtm_particles P, const double* coords, int64_t first_id,
+                              int32_t coords_on_device, void* stream) {
+  return guarded([&]() -> xtm_status {
+    if (!P) return fail(XTM_E_ARG, "null particle set");
+    if (P->n > 0 && !coords) return fail(XTM_E_ARG, "coords is null");
+    hipStream_t s = (hipStream_t)stream;
+    const double* dc = coords;
+    double* tmp = nullptr;
+    if (P->n > 0 && !coords_on_device) {
+      const size_t bytes = (size_t)P->n * 6 * sizeof(double);
+      if (hipMalloc(&tmp, bytes) != hipSuccess) return fail(XTM_E_NOMEM, "staging allocation failed");
+      hipError_t e = hipMemcpyAsync(tmp, coords, bytes, hipMemcpyHostToDevice, s);
+      if (e == hipSuccess) e = hipStreamSynchronize(s);
+      if (e != hipSuccess) { hipFree(tmp); return hip_fail(e, "upload of coordinates"); }
+      dc = tmp;
+    }
+    hipError_t e = launch_init(dc, P->n, first_id, soa_of(P), kref(P->ref), s);
+    if (e == hipSuccess) e = launch_iota(P->idx[0], P->n, P->ctrl, (int32_t)P->n, s);
+    if (e == hipSuccess) e = launch_fill_i64(P->passes, 0, s);
+    if (tmp) {
+      hipError_t e2 = hipStreamSynchronize(s);
+      hipFree(tmp);
+      if (e == hipSuccess) e = e2;
+    }
+    if (e != hipSuccess) return hip_fail(e, "particle initialisation");
+    P->cur = 0;
+    P->turn = 0;
+    P->alive_upper = P->n;
+    P->initialised = true;
+    return XTM_OK;
+  });
+}
+
+xtm_status xtm_particles_reset(xtm_particles P, int32_t turn, void* stream) {
+  return guarded([&]() -> xtm_status {
+    if (!P) return fail(XTM_E_ARG, "null particle set");
+    hipStream_t s = (hipStream_t)stream;
+    // all indices into the spare buffer, then one compaction into the live one
+    hipError_t e = launch_iota(P->idx[1 - P->cur], P->n, P->ctrl, (int32_t)P->n, s);
+    if (e == hipSuccess)
+      e = launch_epilogue(P->idx[1 - P->cur], P->idx[P->cur], P->n > 0 ? P->n : 1, soa_of(P),
+                          P->ctrl, P->blockcnt, P->passes, 0, 0, turn, 0, s);
+    if (e != hipSuccess) return hip_fail(e, "alive-list rebuild");
+    P->turn = turn;
+    P->alive_upper = P->n;
+    P->initialised = true;
+    return XTM_OK;
+  });
+}
+
+xtm_status xtm_particles_turn(xtm_particles P, int32_t* turn) {
+  if (!P || !turn) return fail(XTM_E_ARG, "null argument");
+  *turn = P->turn;
+  return XTM_OK;
+}
+
+xtm_status xtm_track(xtm_lattice L, xtm_particles P, int32_t n_turns, const xtm_track_opts* opts,
+                     void* stream, xtm_track_stats* stats) {
+  return guarded([&]() {
+    return run_turns(L, P, n_turns, opts, (hipStream_t)stream, stats, false);
+  });
+}
+
+xtm_status xtm_track_backward(xtm_lattice L, xtm_particles P, int32_t n_turns, void* stream,
+                              xtm_track_stats* stats) {
+  return guarded([&]() {
+    return run_turns(L, P, n_turns, nullptr, (hipStream_t)stream, stats, true);
+  });
+}
+
+xtm_status xtm_get_losses(xtm_particles P, int32_t* h_state, int32_t* h_at_turn,
+                          int32_t* h_at_element, void* stream) {
+  return guarded([&]() -> xtm_status {
+    if (!P) return fail(XTM_E_ARG, "null particle set");
+    hipStream_t s = (hipStream_t)stream;
+    const size_t bytes = (size_t)P->n * sizeof(int32_t);
+    if (P->n > 0) {
+      if (h_state) HIP_TRY(hipMemcpyAsync(h_state, P->a.state, bytes, hipMemcpyDeviceToHost, s), "copy state");
+      if (h_at_turn) HIP_TRY(hipMemcpyAsync(h_at_turn, P->a.at_turn, bytes, hipMemcpyDeviceToHost, s), "copy at_turn");
+      if (h_at_element)
+        HIP_TRY(hipMemcpyAsync(h_at_element, P->a.at_element, bytes, hipMemcpyDeviceToHost, s), "copy at_element");
+    }
+    HIP_TRY(hipStreamSynchronize(s), "synchronise");
+    return XTM_OK;
+  });
+}
+
+xtm_status xtm_sync(void* stream) {
+  hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "stream synchronise");
+  e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "device error");
+  return XTM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,61 @@
+// xtm_internal.h -- shared declarations between the C-ABI runtime and the
+// gfx950 kernels of the tracking library (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace xtm {
+
+// Device element-table record: one 64-bit header word followed by `nw`
+// FP64 parameter words.  Header bits: [0,8) kernel type, [8,16) multipole
+// order, [16,32) parameter word count, [32,64) user element index.
+enum KType : uint32_t {
+  K_DRIFT = 1,
+  K_DRIFT_EXP = 2,
+  K_MULT = 3,       // coefficients only:  cr_N, ci_N, ..., cr_0, ci_0
+  K_MULT_CURV = 4,  // coefficients, then hxl, knl0*hxl, Lr
+  K_RF = 5,         // amp = charge0 V / p0c, k = 2 pi f / (beta0 c), phase [rad]
+  K_SHIFT = 6,      // dx, dy
+  K_SROT = 7,       // cos, sin
+  K_AP_CIRC = 8,    // r^2
+  K_AP_ELL = 9,     // 1/a^2, 1/b^2
+  K_AP_RECT = 10,   // xmin, xmax, ymin, ymax
+  K_MARKER = 11
+};
+
+__host__ __device__ inline uint64_t make_header(uint32_t ktype, uint32_t order, uint32_t nw,
+                                                uint32_t index) {
+  return (uint64_t)(ktype & 0xffu) | ((uint64_t)(order & 0xffu) << 8) |
+         ((uint64_t)(nw & 0xffffu) << 16) | ((uint64_t)index << 32);
+}
+
+struct SoA {
+  double *x, *px, *y, *py, *zeta, *delta, *ptau, *rpp, *rvv;
+  int32_t *state, *at_element, *at_turn;
+  int64_t* pid;
+};
+
+struct KernelRef {
+  double beta0;
+  double two_over_beta0;
+};
+
+// launch helpers implemented in xtm_kernels.hip; all are stream-ordered
+hipError_t launch_init(const double* coords6, int64_t n, int64_t first_id, SoA P, KernelRef r,
+                       hipStream_t s);
+hipError_t launch_iota(int32_t* idx, int64_t n, int32_t* ctrl, int32_t n_alive, hipStream_t s);
+hipError_t launch_track(const uint64_t* tab, int32_t n_el, SoA P, const int32_t* idx,
+                        const int32_t* ctrl, int64_t grid_upper, int32_t block, int32_t n_turns,
+                        int32_t t0, int32_t backward, KernelRef r, hipStream_t s);
+// end-of-chunk bookkeeping: passes of the chunk (added to *passes), then an
+// order-preserving compaction of the alive list into idx_out (if idx_out != null)
+hipError_t launch_epilogue(const int32_t* idx_in, int32_t* idx_out, int64_t grid_upper,
+                           SoA P, int32_t* ctrl, int32_t* blockcnt, int64_t* passes,
+                           int32_t n_el, int32_t chunk_turns, int32_t t0, int32_t backward,
+                           hipStream_t s);
+hipError_t launch_fill_i64(int64_t* p, int64_t v, hipStream_t s);
+
+constexpr int kScanBlock = 1024;
+
+}  // namespace xtm

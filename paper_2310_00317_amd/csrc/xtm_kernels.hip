@@ -1,0 +1,413 @@
+// xtm_kernels.hip -- gfx950 kernels of the thin-lattice FP64 tracker.
+//
+// One thread owns one particle.  Its nine FP64 coordinates live in VGPRs for
+// the whole chunk of turns; the element table is walked with wave-uniform
+// (scalar) loads, so element parameters land in SGPRs and the element switch
+// is a scalar branch.  HBM is touched only at chunk boundaries (one
+// coalesced-by-index load and store of the particle state).
+//
+// Maps (paper section "Lattice modelling and single particle tracking": thin
+// elements, multipolar errors, tilts and misalignments as reference-frame
+// changes; aperture checks stop lost particles, section "Particle-matter
+// interaction and collimation studies").  Every fused multiply-add is an
+// explicit fma(); everything else is a correctly rounded IEEE operation, and
+// the library is built with -ffp-contract=off, so the operation order below
+// is the rounding contract:
+//   exact drift    pz = sqrt((1+d)^2 - px^2 - py^2), lp = L/pz,
+//                  x = fma(px, lp, x), y = fma(py, lp, y),
+//                  zeta = fma(lp, (d(2+d) - px^2 - py^2)/(1+pz) - beta0 ptau, zeta)
+//   expanded drift x = fma(px, L rpp, x), ...,
+//                  zeta = fma(L, (d - beta0 ptau) rpp - 0.5 (px^2+py^2) rpp^3 (1+beta0 ptau), zeta)
+//   multipole      Horner from the top order: b <- b z + c_n with
+//                  re = fma(br, x, fma(-bi, y, cr)), im = fma(br, y, fma(bi, x, ci));
+//                  px -= re, py += im  (c_n = (knl_n + i ksl_n)/n!)
+//   RF             ptau += amp sin(phase - k zeta); delta = v/(1+sqrt(1+v)),
+//                  v = ptau (ptau + 2/beta0); rpp = 1/(1+delta); rvv = (1+delta)/(1+beta0 ptau)
+//   apertures      lost iff !(inside), so NaN is lost and the boundary survives
+#include "xtm_internal.h"
+
+namespace xtm {
+
+// ------------------------------------------------------------- particle init
+__global__ void __launch_bounds__(256) k_init(const double* __restrict__ c6, int64_t n,
+                                              int64_t first_id, SoA P, KernelRef r) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double* c = c6 + 6 * i;
+  double d = c[5];
+  // ptau from delta without cancellation: u = d(2+d), ptau = b0 u / (1 + sqrt(1 + b0^2 u))
+  double u = d * (2.0 + d);
+  double ptau = r.beta0 * u / (1.0 + sqrt(1.0 + r.beta0 * r.beta0 * u));
+  P.x[i] = c[0];
+  P.px[i] = c[1];
+  P.y[i] = c[2];
+  P.py[i] = c[3];
+  P.zeta[i] = c[4];
+  P.delta[i] = d;
+  P.ptau[i] = ptau;
+  P.rpp[i] = 1.0 / (1.0 + d);
+  P.rvv[i] = (1.0 + d) / (1.0 + r.beta0 * ptau);
+  P.state[i] = 1;
+  P.at_element[i] = 0;
+  P.at_turn[i] = 0;
+  P.pid[i] = first_id + i;
+}
+
+__global__ void __launch_bounds__(256) k_iota(int32_t* idx, int64_t n, int32_t* ctrl,
+                                              int32_t n_alive) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) idx[i] = (int32_t)i;
+  if (i == 0) {
+    ctrl[0] = n_alive;
+    ctrl[2] = n_alive;
+  }
+}
+
+__global__ void k_fill_i64(int64_t* p, int64_t v) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
+}
+
+// ------------------------------------------------------------ element maps
+struct Pt {
+  double x, px, y, py, zeta, delta, ptau, rpp, rvv;
+  // invariants of delta, refreshed whenever ptau changes (same values the
+  // formulas would recompute, so caching does not change rounding)
+  double opd2, u, bpt;
+};
+
+__device__ __forceinline__ void refresh(Pt& q, double beta0) {
+  double opd = 1.0 + q.delta;
+  q.opd2 = opd * opd;
+  q.u = q.delta * (2.0 + q.delta);
+  q.bpt = beta0 * q.ptau;
+}
+
+template <int N>
+__device__ __forceinline__ void horner(Pt& q, const double* __restrict__ c) {
+  double br = c[0], bi = c[1];
+#pragma unroll
+  for (int k = 1; k <= N; ++k) {
+    double cr = c[2 * k], ci = c[2 * k + 1];
+    double tr = fma(br, q.x, fma(-bi, q.y, cr));
+    double ti = fma(br, q.y, fma(bi, q.x, ci));
+    br = tr;
+    bi = ti;
+  }
+  q.px = q.px - br;
+  q.py = q.py + bi;
+}
+
+__device__ __forceinline__ void horner_n(Pt& q, const double* __restrict__ c, uint32_t order) {
+  switch (order) {
+    case 0: horner<0>(q, c); break;
+    case 1: horner<1>(q, c); break;
+    case 2: horner<2>(q, c); break;
+    case 3: horner<3>(q, c); break;
+    case 4: horner<4>(q, c); break;
+    case 5: horner<5>(q, c); break;
+    case 6: horner<6>(q, c); break;
+    case 7: horner<7>(q, c); break;
+    case 8: horner<8>(q, c); break;
+    case 9: horner<9>(q, c); break;
+    default: horner<10>(q, c); break;
+  }
+}
+
+// ------------------------------------------------------------ track kernel
+// Tracks idx[i] for i < ctrl[0] through n_turns turns of the table `tab`
+// (forward table, or the reversed table of inverse maps when backward != 0).
+__global__ void __launch_bounds__(256) k_track(const uint64_t* __restrict__ tab, int32_t n_el,
+                                               SoA P, const int32_t* __restrict__ idx,
+                                               const int32_t* __restrict__ ctrl, int32_t n_turns,
+                                               int32_t t0, int32_t backward, KernelRef r) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ctrl[0]) return;
+  const int32_t p = idx[i];
+  if (P.state[p] != 1) return;
+
+  Pt q;
+  q.x = P.x[p];
+  q.px = P.px[p];
+  q.y = P.y[p];
+  q.py = P.py[p];
+  q.zeta = P.zeta[p];
+  q.delta = P.delta[p];
+  q.ptau = P.ptau[p];
+  q.rpp = P.rpp[p];
+  q.rvv = P.rvv[p];
+  refresh(q, r.beta0);
+
+  const double beta0 = r.beta0;
+  int32_t st = 1, lost_e = 0, lost_t = 0;
+  for (int32_t t = 0; t < n_turns; ++t) {
+    uint32_t off = 0;
+    for (int32_t e = 0; e < n_el; ++e) {
+      // the walk position is the same for every lane; saying so lets the
+      // compiler fetch the record with scalar loads into SGPRs
+      off = __builtin_amdgcn_readfirstlane(off);
+      const uint64_t* w = tab + off;
+      const uint64_t h = w[0];
+      const uint32_t ktype = (uint32_t)(h & 0xffu);
+      const uint32_t order = (uint32_t)((h >> 8) & 0xffu);
+      const uint32_t nw = (uint32_t)((h >> 16) & 0xffffu);
+      const double* __restrict__ prm = reinterpret_cast<const double*>(w + 1);
+      switch (ktype) {
+        case K_DRIFT: {
+          const double L = prm[0];
+          const double px2 = q.px * q.px;
+          const double py2 = q.py * q.py;
+          const double pz2 = q.opd2 - px2 - py2;
+          if (!(pz2 > 0.0)) {
+            st = -1;
+            lost_e = e;
+            lost_t = t;
+            goto done;
+          }
+          const double pz = sqrt(pz2);
+          const double lp = L / pz;
+          q.x = fma(q.px, lp, q.x);
+          q.y = fma(q.py, lp, q.y);
+          const double dz = (q.u - px2 - py2) / (1.0 + pz) - q.bpt;
+          q.zeta = fma(lp, dz, q.zeta);
+          break;
+        }
+        case K_DRIFT_EXP: {
+          const double L = prm[0];
+          const double lr = L * q.rpp;
+          q.x = fma(q.px, lr, q.x);
+          q.y = fma(q.py, lr, q.y);
+          const double pp = q.px * q.px + q.py * q.py;
+          const double r3 = q.rpp * q.rpp * q.rpp;
+          const double dz = (q.delta - q.bpt) * q.rpp - 0.5 * pp * r3 * (1.0 + q.bpt);
+          q.zeta = fma(L, dz, q.zeta);
+          break;
+        }
+        case K_MULT:
+          horner_n(q, prm, order);
+          break;
+        case K_MULT_CURV: {
+          horner_n(q, prm, order);
+          const double* cv = prm + 2 * (order + 1);
+          const double hxl = cv[0], k0h = cv[1], lr = cv[2];
+          double dpx = hxl * (1.0 + q.delta);
+          if (lr > 0.0) dpx = dpx - k0h * q.x / lr;
+          const double dz = hxl * q.x * (1.0 + q.bpt) * q.rpp;
+          q.px = q.px + dpx;
+          q.zeta = q.zeta - dz;
+          break;
+        }
+        case K_RF: {
+          const double s = sin(prm[2] - prm[1] * q.zeta);
+          q.ptau = q.ptau + prm[0] * s;
+          const double v = q.ptau * (q.ptau + r.two_over_beta0);
+          q.delta = v / (1.0 + sqrt(1.0 + v));
+          q.rpp = 1.0 / (1.0 + q.delta);
+          q.rvv = (1.0 + q.delta) / (1.0 + beta0 * q.ptau);
+          refresh(q, beta0);
+          break;
+        }
+        case K_SHIFT:
+          q.x = q.x - prm[0];
+          q.y = q.y - prm[1];
+          break;
+        case K_SROT: {
+          const double c = prm[0], s = prm[1];
+          const double x = c * q.x + s * q.y;
+          const double y = c * q.y - s * q.x;
+          const double px = c * q.px + s * q.py;
+          const double py = c * q.py - s * q.px;
+          q.x = x;
+          q.y = y;
+          q.px = px;
+          q.py = py;
+          break;
+        }
+        case K_AP_CIRC:
+          if (!(q.x * q.x + q.y * q.y <= prm[0])) {
+            st = 0;
+            lost_e = e;
+            lost_t = t;
+            goto done;
+          }
+          break;
+        case K_AP_ELL:
+          if (!(q.x * q.x * prm[0] + q.y * q.y * prm[1] <= 1.0)) {
+            st = 0;
+            lost_e = e;
+            lost_t = t;
+            goto done;
+          }
+          break;
+        case K_AP_RECT:
+          if (!(prm[0] <= q.x && q.x <= prm[1] && prm[2] <= q.y && q.y <= prm[3])) {
+            st = 0;
+            lost_e = e;
+            lost_t = t;
+            goto done;
+          }
+          break;
+        default:
+          break;
+      }
+      off += 1 + nw;
+    }
+  }
+done:
+  P.x[p] = q.x;
+  P.px[p] = q.px;
+  P.y[p] = q.y;
+  P.py[p] = q.py;
+  P.zeta[p] = q.zeta;
+  P.delta[p] = q.delta;
+  P.ptau[p] = q.ptau;
+  P.rpp[p] = q.rpp;
+  P.rvv[p] = q.rvv;
+  if (st == 1) {
+    P.at_turn[p] = backward ? t0 - n_turns : t0 + n_turns;
+    P.at_element[p] = 0;
+  } else {
+    P.state[p] = st;
+    P.at_element[p] = backward ? n_el - 1 - lost_e : lost_e;
+    P.at_turn[p] = backward ? t0 - 1 - lost_t : t0 + lost_t;
+  }
+}
+
+// -------------------------------------------------------- chunk epilogue
+// Block-wide exclusive scan of a 0/1 flag over kScanBlock threads (16 wave64s).
+__device__ __forceinline__ int32_t block_rank(bool flag, int32_t* s_wave, int32_t* total) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const uint64_t m = __ballot(flag);
+  const int32_t in_wave = __popcll(m & ((lane == 0) ? 0ull : (~0ull >> (64 - lane))));
+  if (lane == 0) s_wave[wave] = __popcll(m);
+  __syncthreads();
+  int32_t before = 0, all = 0;
+  const int nw = blockDim.x >> 6;
+  for (int k = 0; k < nw; ++k) {
+    const int32_t c = s_wave[k];
+    before += (k < wave) ? c : 0;
+    all += c;
+  }
+  *total = all;
+  return before + in_wave;
+}
+
+// Pass 1: per-block alive counts and the chunk's pass count.
+__global__ void __launch_bounds__(kScanBlock) k_count(const int32_t* __restrict__ idx, SoA P,
+                                                      int32_t* ctrl, int32_t* blockcnt,
+                                                      unsigned long long* passes, int32_t n_el,
+                                                      int32_t chunk_turns, int32_t t0,
+                                                      int32_t backward) {
+  __shared__ int32_t s_wave[kScanBlock / 64];
+  __shared__ unsigned long long s_pass[kScanBlock / 64];
+  const int32_t n_alive = ctrl[0];
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  bool alive = false;
+  int64_t np = 0;
+  if (i < n_alive) {
+    const int32_t p = idx[i];
+    const int32_t st = P.state[p];
+    alive = (st == 1);
+    if (alive) {
+      np = (int64_t)chunk_turns * n_el;
+    } else {
+      const int32_t at = P.at_turn[p], ae = P.at_element[p];
+      if (!backward && at >= t0 && at < t0 + chunk_turns)
+        np = (int64_t)(at - t0) * n_el + ae + 1;
+      else if (backward && at <= t0 - 1 && at >= t0 - chunk_turns)
+        np = (int64_t)(t0 - 1 - at) * n_el + (n_el - ae);
+    }
+  }
+  int32_t total;
+  block_rank(alive, s_wave, &total);
+  // wave-level sum of passes, then one atomic per block
+  unsigned long long v = (unsigned long long)np;
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  if ((threadIdx.x & 63) == 0) s_pass[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long s = 0;
+    for (int k = 0; k < (int)(blockDim.x >> 6); ++k) s += s_pass[k];
+    if (s) atomicAdd(passes, s);
+    blockcnt[blockIdx.x] = total;
+    if (blockIdx.x == 0) ctrl[2] = n_alive;  // count this epilogue scanned
+  }
+}
+
+// Pass 2: order-preserving scatter of alive entries; the last block writes
+// the new alive count.  Reads the old count from ctrl[2] (set by pass 1) so
+// the write of ctrl[0] cannot race with any reader of this launch.
+__global__ void __launch_bounds__(kScanBlock) k_scatter(const int32_t* __restrict__ idx_in,
+                                                        int32_t* __restrict__ idx_out, SoA P,
+                                                        int32_t* ctrl,
+                                                        const int32_t* __restrict__ blockcnt) {
+  __shared__ int32_t s_wave[kScanBlock / 64];
+  __shared__ int32_t s_red[kScanBlock / 64];
+  const int32_t n_old = ctrl[2];
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  // offset = sum of the counts of the preceding blocks
+  int32_t part = 0;
+  for (int32_t b = threadIdx.x; b < (int32_t)blockIdx.x; b += blockDim.x) part += blockcnt[b];
+  for (int off = 32; off > 0; off >>= 1) part += __shfl_down(part, off, 64);
+  if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = part;
+  __syncthreads();
+  int32_t offset = 0;
+  for (int k = 0; k < (int)(blockDim.x >> 6); ++k) offset += s_red[k];
+  bool alive = false;
+  int32_t p = 0;
+  if (i < n_old) {
+    p = idx_in[i];
+    alive = (P.state[p] == 1);
+  }
+  int32_t total;
+  const int32_t rank = block_rank(alive, s_wave, &total);
+  if (alive) idx_out[offset + rank] = p;
+  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) ctrl[0] = offset + total;
+}
+
+// ------------------------------------------------------------- launchers
+static inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+hipError_t launch_init(const double* coords6, int64_t n, int64_t first_id, SoA P, KernelRef r,
+                       hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_init, dim3(blocks_for(n, 256)), dim3(256), 0, s, coords6, n, first_id, P, r);
+  return hipGetLastError();
+}
+
+hipError_t launch_iota(int32_t* idx, int64_t n, int32_t* ctrl, int32_t n_alive, hipStream_t s) {
+  int64_t m = n > 0 ? n : 1;
+  hipLaunchKernelGGL(k_iota, dim3(blocks_for(m, 256)), dim3(256), 0, s, idx, n, ctrl, n_alive);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_i64(int64_t* p, int64_t v, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_i64, dim3(1), dim3(64), 0, s, p, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_track(const uint64_t* tab, int32_t n_el, SoA P, const int32_t* idx,
+                        const int32_t* ctrl, int64_t grid_upper, int32_t block, int32_t n_turns,
+                        int32_t t0, int32_t backward, KernelRef r, hipStream_t s) {
+  if (grid_upper <= 0 || n_turns <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_track, dim3(blocks_for(grid_upper, block)), dim3(block), 0, s, tab, n_el, P,
+                     idx, ctrl, n_turns, t0, backward, r);
+  return hipGetLastError();
+}
+
+hipError_t launch_epilogue(const int32_t* idx_in, int32_t* idx_out, int64_t grid_upper, SoA P,
+                           int32_t* ctrl, int32_t* blockcnt, int64_t* passes, int32_t n_el,
+                           int32_t chunk_turns, int32_t t0, int32_t backward, hipStream_t s) {
+  if (grid_upper <= 0) return hipSuccess;
+  const unsigned nb = blocks_for(grid_upper, kScanBlock);
+  hipLaunchKernelGGL(k_count, dim3(nb), dim3(kScanBlock), 0, s, idx_in, P, ctrl, blockcnt,
+                     reinterpret_cast<unsigned long long*>(passes), n_el, chunk_turns, t0,
+                     backward);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || idx_out == nullptr) return e;
+  hipLaunchKernelGGL(k_scatter, dim3(nb), dim3(kScanBlock), 0, s, idx_in, idx_out, P, ctrl,
+                     blockcnt);
+  return hipGetLastError();
+}
+
+}  // namespace xtm

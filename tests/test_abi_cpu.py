@@ -1,0 +1,98 @@
+"""CPU-side checks of the C-ABI library: it loads, exports every declared
+entry point, and validates its arguments before touching a device."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2310_00317_amd import inputs as I
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "xtm.h")
+
+
+def declared_functions():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(xtm_[a-z0-9_]+)\s*\(", txt)))
+
+
+@pytest.fixture(scope="module")
+def xtm():
+    import paper_2310_00317_amd as P
+    if not os.path.exists(P.LIB_PATH):
+        pytest.fail("libxtm.so is not built (run __graft_entry__.build())")
+    return P
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for n in ("xtm_lattice_create", "xtm_particles_bind", "xtm_particles_init", "xtm_track",
+              "xtm_track_backward", "xtm_get_losses", "xtm_sync"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(xtm):
+    L = xtm.lib()
+    missing = [n for n in declared_functions() if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_element_struct_layout_matches_header():
+    # offsets of xtm_element_desc under natural alignment
+    d = I.ELEMENT_DTYPE
+    assert d.itemsize == 248
+    assert [d.fields[k][1] for k in d.names] == [0, 4, 8, 16, 104, 192, 200]
+
+
+def _create(xtm, els, ref=I.PROTON_450GEV):
+    r = xtm._ref_struct(ref)
+    h = ctypes.c_void_p()
+    code = xtm.lib().xtm_lattice_create(els.ctypes.data_as(ctypes.c_void_p), len(els),
+                                        ctypes.byref(r), ctypes.byref(h))
+    return code, h
+
+
+@pytest.mark.parametrize("mutate,expected", [
+    (lambda e: e.__setitem__("type", 99), -2),
+    (lambda e: (e.__setitem__("type", I.MULTIPOLE), e.__setitem__("order", 11)), -2),
+    (lambda e: (e.__setitem__("type", I.MULTIPOLE), e.__setitem__("order", -1)), -2),
+    (lambda e: (e.__setitem__("type", I.AP_CIRCLE)), -2),                       # r = 0
+    (lambda e: (e.__setitem__("type", I.AP_ELLIPSE), e["p"].__setitem__(0, 1.0)), -2),
+    (lambda e: (e.__setitem__("type", I.AP_RECT), e["p"].__setitem__(slice(0, 4), [1, 0, -1, 1])), -2),
+    (lambda e: (e.__setitem__("type", I.DRIFT), e.__setitem__("length", np.inf)), -2),
+    (lambda e: (e.__setitem__("type", I.RF), e["p"].__setitem__(1, -1.0)), -2),
+])
+def test_invalid_elements_rejected_before_any_device_work(xtm, mutate, expected):
+    els = I.line([I.drift(1.0), I.drift(1.0)])
+    e = els[1]
+    mutate(e)
+    els[1] = e
+    code, h = _create(xtm, els)
+    assert code == expected
+    assert h.value is None
+    msg = xtm.lib().xtm_last_error().decode()
+    assert "element 1" in msg
+
+
+def test_bad_reference_and_arguments(xtm):
+    els = I.line([I.drift(1.0)])
+    code, _ = _create(xtm, els, I.Reference(0.0, 1.0, 1e9))
+    assert code == -5
+    r = xtm._ref_struct(I.PROTON_450GEV)
+    h = ctypes.c_void_p()
+    assert xtm.lib().xtm_lattice_create(None, 3, ctypes.byref(r), ctypes.byref(h)) == -1
+    assert xtm.lib().xtm_lattice_create(None, 0, ctypes.byref(r), None) == -1
+    a = xtm._Arrays()
+    a.n = -1
+    assert xtm.lib().xtm_particles_bind(ctypes.byref(a), ctypes.byref(r), ctypes.byref(h)) == -1
+    a.n = 10  # null arrays
+    assert xtm.lib().xtm_particles_bind(ctypes.byref(a), ctypes.byref(r), ctypes.byref(h)) == -1
+    assert xtm.lib().xtm_track(None, None, 1, None, None, None) == -1
+    assert xtm.lib().xtm_particles_turn(None, None) == -1
+
+
+def test_version_string(xtm):
+    assert b"gfx950" in xtm.lib().xtm_version()
