@@ -81,13 +81,15 @@ def random_lattice(seed, n=200):
     for _ in range(n):
         k = rng.integers(0, 10)
         if k == 0:
-            els.append(I.drift(rng.uniform(0.1, 5.0)))
+            els.append(I.drift(rng.uniform(0.05, 0.5)))
         elif k == 1:
-            els.append(I.drift(rng.uniform(0.1, 5.0), expanded=True))
+            els.append(I.drift(rng.uniform(0.05, 0.5), expanded=True))
         elif k in (2, 3):
             N = int(rng.integers(0, 11))
-            knl = rng.normal(0, 1, N + 1) * 10.0 ** (-np.arange(N + 1) * 0.3) * 1e-2
-            ksl = rng.normal(0, 1, N + 1) * 10.0 ** (-np.arange(N + 1) * 0.3) * 1e-2
+            # each order kicks by ~1e-7 rad at r = 10 mm
+            scale = np.array([1e-7 * math.factorial(n) / 1e-2 ** n for n in range(N + 1)])
+            knl = rng.normal(0, 1, N + 1) * scale
+            ksl = rng.normal(0, 1, N + 1) * scale
             if k == 3:
                 th = rng.normal(0, 1e-3)
                 knl[0] = th
@@ -101,11 +103,11 @@ def random_lattice(seed, n=200):
         elif k == 6:
             els.append(I.srotation(rng.normal(0, 0.3)))
         elif k == 7:
-            els.append(I.ap_ellipse(0.03, 0.02))
+            els.append(I.ap_ellipse(0.008, 0.0065))
         elif k == 8:
-            els.append(I.ap_rect(-0.025, 0.03, -0.02, 0.015))
+            els.append(I.ap_rect(-0.0075, 0.008, -0.007, 0.0065))
         else:
-            els.append(I.ap_circle(0.028) if rng.random() < 0.5 else I.marker())
+            els.append(I.ap_circle(0.0085) if rng.random() < 0.5 else I.marker())
     return I.line(els)
 
 
@@ -114,10 +116,11 @@ def test_every_element_type_random_lattice(P, oracle_mod, seed):
     banner(f"random lattice seed {seed}")
     el = random_lattice(seed)
     rng = np.random.default_rng(seed + 100)
-    c = rng.normal(0, [4e-3, 2e-4, 4e-3, 2e-4, 0.05, 1e-3], (700, 6))
+    c = rng.normal(0, [3e-3, 2e-6, 3e-3, 2e-6, 0.05, 1e-3], (700, 6))
     g, gp, _, _, _ = gpu_run(P, el, REF, c, 20)
     o, op = oracle_run(oracle_mod, el, REF, c, 20)
-    assert (o.state != 1).any() and (o.state == 1).any()
+    # the inputs exercise both outcomes
+    assert 0.05 < np.mean(o.state == 1) < 0.98
     assert_parity(g, o, rtol=1e-12)
     assert gp == op
 
