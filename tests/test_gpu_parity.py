@@ -155,9 +155,14 @@ def test_launch_shape_invariance(P, opts):
         assert np.array_equal(a[f], b[f], equal_nan=True), f
 
 
-def test_backward_parity_and_reversibility(P, oracle_mod):
-    banner("backward tracking")
-    el = I.cfg1_lattice()
+@pytest.mark.parametrize("rf_on", [False, True])
+def test_backward_parity_and_reversibility(P, oracle_mod, rf_on):
+    """Forward 100 turns then backward 100 turns.  Without RF every map obeys
+    the rounding contract, so the GPU equals the oracle bitwise.  With RF the
+    device sin and the host libm sin may differ by an ulp; over the 200-turn
+    round trip the gate is 1e-11 on the oracle's regular orbits."""
+    banner(f"backward tracking, rf_on={rf_on}")
+    el = I.cfg1_lattice(rf_on=rf_on)
     c = I.cfg1_particles(500, seed=12)
     lat = P.Lattice(el, REF)
     parts = P.Particles(len(c), REF).init(c)
@@ -169,7 +174,11 @@ def test_backward_parity_and_reversibility(P, oracle_mod):
     o = oracle_mod.init(c, REF)
     oracle_mod.track(el, REF, o, 100)
     oracle_mod.track_backward(el, REF, o, 100)
-    assert_parity(g, o, rtol=1e-12)
+    if rf_on:
+        reg = oracle_mod.regular_mask(el, REF, c)
+        assert_parity(g, o, rtol=1e-11, mask=reg)
+    else:
+        assert_parity(g, o, rtol=0.0)
     rms = np.sqrt(np.mean(c[alive] ** 2, axis=0))
     for j, f in enumerate(("x", "px", "y", "py", "zeta", "delta")):
         err = np.abs(g[f][alive] - c[alive, j])
