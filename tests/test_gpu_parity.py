@@ -160,7 +160,7 @@ def test_backward_parity_and_reversibility(P, oracle_mod, rf_on):
     """Forward 100 turns then backward 100 turns.  Without RF every map obeys
     the rounding contract, so the GPU equals the oracle bitwise.  With RF the
     device sin and the host libm sin may differ by an ulp; over the 200-turn
-    round trip the gate is 1e-11 on the oracle's regular orbits."""
+    round trip the gate is 1e-12 of max(|value|, RMS of the coordinate)."""
     banner(f"backward tracking, rf_on={rf_on}")
     el = I.cfg1_lattice(rf_on=rf_on)
     c = I.cfg1_particles(500, seed=12)
@@ -175,8 +175,14 @@ def test_backward_parity_and_reversibility(P, oracle_mod, rf_on):
     oracle_mod.track(el, REF, o, 100)
     oracle_mod.track_backward(el, REF, o, 100)
     if rf_on:
-        reg = oracle_mod.regular_mask(el, REF, c)
-        assert_parity(g, o, rtol=1e-11, mask=reg)
+        # 200 turns of ulp-level sin differences: compare against the RMS scale
+        # (seen: 2e-11 with a 1e-3 x RMS floor, i.e. 2e-14 of the RMS)
+        from parity_util import rel_err
+        alive_both = (o.state == 1) & (g["state"] == 1)
+        errs = rel_err(g, o, alive_both, floor_frac=1.0)
+        for f, e in errs.items():
+            assert np.max(e[alive_both]) <= 1e-12, f
+        assert np.array_equal(g["state"], o.state) and np.array_equal(g["at_turn"], o.at_turn)
     else:
         assert_parity(g, o, rtol=0.0)
     rms = np.sqrt(np.mean(c[alive] ** 2, axis=0))
