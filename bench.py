@@ -99,6 +99,7 @@ def main():
     ap.add_argument("--particles", type=int, default=None)
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--chunk", type=int, default=0)
+    ap.add_argument("--variant", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-every", type=int, default=100)
     ap.add_argument("--cpu-turns", type=int, default=500)
@@ -127,7 +128,8 @@ def main():
     if args.warmup > 0:
         w = P.Particles(n, ref).init(coords_dev)
         for _ in range(args.warmup):
-            P.track(lat, w, tps, block=args.block, turns_per_chunk=args.chunk)
+            P.track(lat, w, tps, block=args.block, turns_per_chunk=args.chunk,
+                    variant=args.variant)
         w.close()
         del w
 
@@ -143,7 +145,7 @@ def main():
     alive = n
     for s in range(steps):
         st = P.track(lat, parts, tps, block=args.block, turns_per_chunk=args.chunk,
-                     time_kernels=True, full_stats=True)
+                     variant=args.variant, time_kernels=True, full_stats=True)
         total_passes += st.passes
         kernel_ms += st.kernel_ms
         launches += st.launches

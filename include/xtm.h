@@ -160,6 +160,8 @@ typedef struct xtm_track_opts {
   int32_t no_compact;      /* 1 = keep lost particles in the alive list between chunks */
   int32_t use_graph;       /* 1 = replay the chunk sequence as a captured hipGraph    */
   int32_t time_kernels;    /* 1 = time each tracking launch with HIP events (stats)   */
+  int32_t variant;         /* tracking kernel: 0 = default, 1 = exit-on-loss,
+                              2 = freeze-on-loss (same results, different control flow) */
 } xtm_track_opts;
 
 typedef struct xtm_track_stats {

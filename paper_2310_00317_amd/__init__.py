@@ -46,7 +46,7 @@ class _Arrays(ctypes.Structure):
 class TrackOpts(ctypes.Structure):
     _fields_ = [("turns_per_chunk", ctypes.c_int32), ("block", ctypes.c_int32),
                 ("no_compact", ctypes.c_int32), ("use_graph", ctypes.c_int32),
-                ("time_kernels", ctypes.c_int32)]
+                ("time_kernels", ctypes.c_int32), ("variant", ctypes.c_int32)]
 
 
 class TrackStats(ctypes.Structure):
@@ -236,11 +236,11 @@ class Particles:
 
 def track(lattice: Lattice, particles: Particles, n_turns: int, turns_per_chunk: int = 0,
           block: int = 0, compact: bool = True, graph: bool = False, stats: bool = True,
-          time_kernels: bool = False, stream=None, full_stats: bool = False):
+          time_kernels: bool = False, variant: int = 0, stream=None, full_stats: bool = False):
     """Track ``n_turns`` forward.  With ``stats`` (synchronising) returns
     (passes, alive), or the whole TrackStats if ``full_stats``."""
     o = TrackOpts(int(turns_per_chunk), int(block), 0 if compact else 1, 1 if graph else 0,
-                  1 if time_kernels else 0)
+                  1 if time_kernels else 0, int(variant))
     s = TrackStats()
     check(lib().xtm_track(lattice.handle, particles.handle, int(n_turns), ctypes.byref(o),
                           _stream(stream), ctypes.byref(s) if (stats or full_stats) else None),

@@ -228,6 +228,8 @@ xtm_status run_turns(xtm_lattice_s* L, xtm_particles_s* P, int32_t n_turns,
   if (block < 64 || block > 256 || block % 64)
     return fail(XTM_E_ARG, "block must be 64, 128, 192 or 256");
   const bool compact = !(o && o->no_compact) || backward;
+  const int32_t variant = (o && o->variant) ? o->variant : 2;
+  if (variant != 1 && variant != 2) return fail(XTM_E_ARG, "kernel variant must be 0, 1 or 2");
   int32_t chunk = (o && o->turns_per_chunk > 0) ? o->turns_per_chunk
                                                  : auto_chunk(P->alive_upper, L->n_el, n_turns);
   if (stats) HIP_TRY(launch_fill_i64(P->passes, 0, s), "clear passes");
@@ -252,7 +254,7 @@ xtm_status run_turns(xtm_lattice_s* L, xtm_particles_s* P, int32_t n_turns,
       HIP_TRY(hipEventRecord(a, s), "event record");
     }
     HIP_TRY(launch_track(tab, L->n_el, soa, in, P->ctrl, P->alive_upper, block, k, t0,
-                         backward ? 1 : 0, kr, s),
+                         backward ? 1 : 0, kr, variant, s),
             "track kernel launch");
     if (timing) HIP_TRY(hipEventRecord(ev.back(), s), "event record");
     ++launches;

@@ -141,6 +141,7 @@ def test_resume_bitwise(P):
 
 
 @pytest.mark.parametrize("opts", [dict(turns_per_chunk=1), dict(turns_per_chunk=7, block=64),
+                                  dict(variant=1), dict(variant=1, turns_per_chunk=13),
                                   dict(turns_per_chunk=100, block=128, compact=False),
                                   dict(turns_per_chunk=33, block=192)])
 def test_launch_shape_invariance(P, opts):
