@@ -161,7 +161,8 @@ typedef struct xtm_track_opts {
   int32_t use_graph;       /* 1 = replay the chunk sequence as a captured hipGraph    */
   int32_t time_kernels;    /* 1 = time each tracking launch with HIP events (stats)   */
   int32_t variant;         /* tracking kernel: 0 = default, 1 = exit-on-loss,
-                              2 = freeze-on-loss (same results, different control flow) */
+                              2 = freeze-on-loss, 3 = freeze-on-loss with the element
+                              table staged in LDS (same results, different schedule) */
 } xtm_track_opts;
 
 typedef struct xtm_track_stats {

@@ -37,6 +37,8 @@ enum { O_DRIFT = 1, O_DRIFT_EXP = 2, O_MULT = 3, O_RF = 4, O_SHIFT = 5,
 
 #define O_MAXORD 10
 
+double oracle_gauss_at(uint64_t seed, int64_t pid, int32_t turn, int32_t element, int32_t draw);
+
 /* element record: same byte layout as the element-description interface */
 typedef struct {
   int32_t type, order;
@@ -133,7 +135,8 @@ static void drift_expanded(orc_pt* q, double L, double b0) {
    sgn = +1 forward, -1 applies the exact inverse (x, y, delta unchanged). */
 typedef struct { double cr[O_MAXORD + 1], ci[O_MAXORD + 1]; } orc_coef;
 
-static void multipole_kick(orc_pt* q, const orc_elem* e, const orc_coef* c, double b0, double sgn) {
+static void multipole_kick(orc_pt* q, const orc_elem* e, const orc_coef* c, double b0, double sgn,
+                           double* fkx, double* fky) {
   int N = e->order;
   double br = c->cr[N], bi = c->ci[N];
   for (int n = N - 1; n >= 0; --n) {
@@ -142,6 +145,8 @@ static void multipole_kick(orc_pt* q, const orc_elem* e, const orc_coef* c, doub
     br = tr;
     bi = ti;
   }
+  *fkx = -br; /* field part of the kick, (dpx, dpy) */
+  *fky = bi;
   if (sgn > 0) {
     q->px = q->px - br;
     q->py = q->py + bi;
@@ -208,6 +213,40 @@ static int inside(const orc_pt* q, const orc_elem* e) {
   }
 }
 
+/* Synchrotron radiation in a thin multipole of radiation length Lr > 0
+   (paper section "Synchrotron radiation models and compensation": a "mean"
+   model of deterministic energy loss and a "quantum" model with
+   fluctuations; here the quantum part is the Gaussian diffusion limit).
+   Curvature from the field kick h = |(dpx, dpy)| rpp / Lr; gamma = gamma0 (1 + beta0 ptau);
+   mean loss dE = (2/3) r m gamma^4 h^2 Lr [eV];
+   quantum:  dE += sqrt((55/(24 sqrt 3)) r m hbar_c gamma^7 |h|^3 Lr) g,  g ~ N(0,1)
+   (r = classical radius of the species, m its rest energy [eV]);
+   ptau -= dE/p0c; delta, rpp, rvv from ptau; px, py scaled by (1+delta_new)/(1+delta_old). */
+#define O_R_ELECTRON 2.8179403262e-15
+#define O_M_ELECTRON_EV 0.51099895000e6
+#define O_HBAR_C_EVM 197.3269804e-9
+
+static void radiate(orc_pt* q, double fkx, double fky, double Lr, const orc_ref* r, int mode,
+                    double g) {
+  double rclass = O_R_ELECTRON * (O_M_ELECTRON_EV / r->mass0) * r->charge0 * r->charge0;
+  double h = sqrt(fkx * fkx + fky * fky) * q->rpp / Lr;
+  double gam = r->gamma0 * (1.0 + r->beta0 * q->ptau);
+  double g2 = gam * gam;
+  double g4 = g2 * g2;
+  double dE = (2.0 / 3.0) * rclass * r->mass0 * g4 * h * h * Lr;
+  if (mode == 2) {
+    double g7 = g4 * g2 * gam;
+    double var = 55.0 / (24.0 * sqrt(3.0)) * rclass * r->mass0 * O_HBAR_C_EVM * g7 * h * h * h * Lr;
+    dE = dE + sqrt(var) * g;
+  }
+  double opd_old = 1.0 + q->delta;
+  q->ptau = q->ptau - dE / r->p0c;
+  set_from_ptau(q, r->beta0);
+  double f = (1.0 + q->delta) / opd_old;
+  q->px = q->px * f;
+  q->py = q->py * f;
+}
+
 /* c_n = (knl_n + i ksl_n) / n!  (n! as an exact double) */
 static orc_coef* build_coefs(const orc_elem* el, int n_el) {
   orc_coef* c = (orc_coef*)calloc((size_t)(n_el > 0 ? n_el : 1), sizeof(orc_coef));
@@ -244,7 +283,10 @@ static void store_pt(const orc_parts* P, int64_t i, const orc_pt* q) {
 }
 
 /* apply element e to q; returns new state (1 alive, 0 aperture loss, -1 pz loss) */
-static int apply(orc_pt* q, const orc_elem* e, const orc_coef* c, const orc_ref* r, double sgn) {
+static int apply(orc_pt* q, const orc_elem* e, const orc_coef* c, const orc_ref* r, double sgn,
+                 double* fkx, double* fky) {
+  *fkx = 0.0;
+  *fky = 0.0;
   switch (e->type) {
     case O_DRIFT:
       return drift_exact(q, sgn * e->length, r->beta0) ? 1 : -1;
@@ -252,7 +294,7 @@ static int apply(orc_pt* q, const orc_elem* e, const orc_coef* c, const orc_ref*
       drift_expanded(q, sgn * e->length, r->beta0);
       return 1;
     case O_MULT:
-      multipole_kick(q, e, c, r->beta0, sgn);
+      multipole_kick(q, e, c, r->beta0, sgn, fkx, fky);
       return 1;
     case O_RF:
       rf_kick(q, e, r, sgn);
@@ -300,9 +342,21 @@ int oracle_init(const double* coords6, int64_t n, int64_t first_id, const double
    for t in [t0, t0+n): for e in 0..E-1: if alive apply(e); survivors get at_turn = t+1.
    Returns the number of (particle, element) applications made while alive
    (including the application at which a particle is lost), or < 0 on error. */
+int64_t oracle_track_rad(const orc_elem* el, int32_t n_el, const double ref3[3], orc_parts* P,
+                         int32_t t0, int32_t n_turns, int32_t nthreads, int32_t radiation,
+                         uint64_t seed);
+
 int64_t oracle_track(const orc_elem* el, int32_t n_el, const double ref3[3], orc_parts* P,
                      int32_t t0, int32_t n_turns, int32_t nthreads) {
-  if (n_turns < 0 || n_el < 0) return -1;
+  return oracle_track_rad(el, n_el, ref3, P, t0, n_turns, nthreads, 0, 0);
+}
+
+/* radiation: 0 off, 1 mean, 2 mean + quantum (Gaussian, Philox stream of
+   (seed, particle id, turn, element)) */
+int64_t oracle_track_rad(const orc_elem* el, int32_t n_el, const double ref3[3], orc_parts* P,
+                         int32_t t0, int32_t n_turns, int32_t nthreads, int32_t radiation,
+                         uint64_t seed) {
+  if (n_turns < 0 || n_el < 0 || radiation < 0 || radiation > 2) return -1;
   if (validate(el, n_el)) return -2;
   orc_ref r = make_ref(ref3);
   orc_coef* c = build_coefs(el, n_el);
@@ -319,7 +373,12 @@ int64_t oracle_track(const orc_elem* el, int32_t n_el, const double ref3[3], orc
     for (int32_t t = t0; t < t0 + n_turns && st == 1; ++t) {
       for (int32_t e = 0; e < n_el; ++e) {
         ++passes;
-        st = apply(&q, &el[e], &c[e], &r, 1.0);
+        double fkx, fky;
+        st = apply(&q, &el[e], &c[e], &r, 1.0, &fkx, &fky);
+        if (st == 1 && radiation && el[e].type == O_MULT && el[e].length > 0.0) {
+          double g = radiation == 2 ? oracle_gauss_at(seed, P->pid[i], t, e, 0) : 0.0;
+          radiate(&q, fkx, fky, el[e].length, &r, radiation, g);
+        }
         if (st != 1) { /* loss is decided before any coordinate is modified */
           lost_e = e;
           lost_t = t;
@@ -364,7 +423,8 @@ int64_t oracle_track_backward(const orc_elem* el, int32_t n_el, const double ref
     for (int32_t t = t0 - 1; t >= t0 - n_turns && st == 1; --t) {
       for (int32_t e = n_el - 1; e >= 0; --e) {
         ++passes;
-        st = apply(&q, &el[e], &c[e], &r, -1.0);
+        double fkx, fky;
+        st = apply(&q, &el[e], &c[e], &r, -1.0, &fkx, &fky);
         if (st != 1) {
           lost_e = e;
           lost_t = t;
@@ -399,7 +459,10 @@ int oracle_track_canonical(const orc_elem* el, int32_t n_el, const double ref3[3
   set_from_ptau(&q, r.beta0);
   int st = 1;
   for (int32_t t = 0; t < n_turns && st == 1; ++t)
-    for (int32_t e = 0; e < n_el && st == 1; ++e) st = apply(&q, &el[e], &c[e], &r, 1.0);
+    for (int32_t e = 0; e < n_el && st == 1; ++e) {
+      double fkx, fky;
+      st = apply(&q, &el[e], &c[e], &r, 1.0, &fkx, &fky);
+    }
   u6[0] = q.x; u6[1] = q.px; u6[2] = q.y; u6[3] = q.py; u6[4] = q.zeta;
   u6[5] = q.ptau / r.beta0;
   free(c);
@@ -411,4 +474,79 @@ void oracle_reference(const double ref3[3], double out2[2]) {
   orc_ref r = make_ref(ref3);
   out2[0] = r.beta0;
   out2[1] = r.gamma0;
+}
+
+/* ------------------------------------------------------------------ RNG
+ * Philox4x32-10 counter-based generator (Salmon, Moraes, Dror, Shaw, SC'11):
+ * a 128-bit counter (c0..c3) and a 64-bit key (k0, k1); each of 10 rounds
+ * multiplies c0 and c2 by two fixed odd 32-bit constants, keeps the high and
+ * low halves, and mixes them with c1, c3 and the key:
+ *   (h0,l0) = M0 * c0, (h1,l1) = M1 * c2,
+ *   c <- (h1 ^ c1 ^ k0, l1, h0 ^ c3 ^ k1, l0);
+ * between rounds the key advances by the Weyl increments
+ * floor(2^32 (golden ratio - 1)) and floor(2^32 (sqrt(3) - 1)).
+ */
+#define O_PHILOX_M0 0xD2511F53u
+#define O_PHILOX_M1 0xCD9E8D57u
+#define O_PHILOX_W0 0x9E3779B9u
+#define O_PHILOX_W1 0xBB67AE85u
+
+void oracle_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
+  uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+  uint32_t k0 = key[0], k1 = key[1];
+  for (int r = 0; r < 10; ++r) {
+    if (r > 0) {
+      k0 += O_PHILOX_W0;
+      k1 += O_PHILOX_W1;
+    }
+    uint64_t p0 = (uint64_t)O_PHILOX_M0 * (uint64_t)c0;
+    uint64_t p1 = (uint64_t)O_PHILOX_M1 * (uint64_t)c2;
+    uint32_t h0 = (uint32_t)(p0 >> 32), l0 = (uint32_t)p0;
+    uint32_t h1 = (uint32_t)(p1 >> 32), l1 = (uint32_t)p1;
+    uint32_t n0 = h1 ^ c1 ^ k0;
+    uint32_t n2 = h0 ^ c3 ^ k1;
+    c0 = n0; c1 = l1; c2 = n2; c3 = l0;
+  }
+  out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* n blocks from consecutive counters: block j uses (ctr0 + j) with carry
+   through the 128-bit counter, key = (seed_lo, seed_hi). */
+void oracle_philox_stream(uint64_t seed, const uint32_t ctr0[4], int64_t n_blocks, uint32_t* out) {
+  uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+  for (int64_t j = 0; j < n_blocks; ++j) {
+    uint32_t c[4];
+    uint64_t lo = ((uint64_t)ctr0[1] << 32 | ctr0[0]) + (uint64_t)j;
+    uint64_t carry = lo < (uint64_t)j ? 1u : 0u;
+    uint64_t hi = ((uint64_t)ctr0[3] << 32 | ctr0[2]) + carry;
+    c[0] = (uint32_t)lo; c[1] = (uint32_t)(lo >> 32);
+    c[2] = (uint32_t)hi; c[3] = (uint32_t)(hi >> 32);
+    oracle_philox4x32_10(c, key, out + 4 * j);
+  }
+}
+
+/* Uniform in (0,1) from two words: k = (w_a << 20) | (w_b >> 12) (52 bits),
+   u = (k + 1/2) 2^-52, exact in binary64. */
+double oracle_uniform(uint32_t wa, uint32_t wb) {
+  uint64_t k = ((uint64_t)wa << 20) | (uint64_t)(wb >> 12);
+  return ((double)k + 0.5) * 0x1p-52;
+}
+
+/* Standard normal by Box-Muller from one Philox block:
+   u1 from (w0, w1), u2 from (w2, w3); g = sqrt(-2 ln u1) cos(2 pi u2). */
+double oracle_gauss(const uint32_t w[4]) {
+  double u1 = oracle_uniform(w[0], w[1]);
+  double u2 = oracle_uniform(w[2], w[3]);
+  return sqrt(-2.0 * log(u1)) * cos(2.0 * M_PI * u2);
+}
+
+/* Gaussian deviate of (seed, particle id, turn, element): counter
+   (pid_lo, pid_hi, turn, element * 8 + draw). */
+double oracle_gauss_at(uint64_t seed, int64_t pid, int32_t turn, int32_t element, int32_t draw) {
+  uint32_t ctr[4] = {(uint32_t)(uint64_t)pid, (uint32_t)((uint64_t)pid >> 32), (uint32_t)turn,
+                     (uint32_t)element * 8u + (uint32_t)draw};
+  uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+  uint32_t w[4];
+  oracle_philox4x32_10(ctr, key, w);
+  return oracle_gauss(w);
 }

@@ -63,6 +63,10 @@ struct xtm_lattice_s {
   std::vector<uint64_t> fwd_h, bwd_h;
   uint64_t* fwd_d = nullptr;
   uint64_t* bwd_d = nullptr;
+  // LDS segments of each table: (first word, word count, element count)
+  std::vector<int32_t> fwd_seg_h, bwd_seg_h;
+  int32_t* fwd_seg_d = nullptr;
+  int32_t* bwd_seg_d = nullptr;
 };
 
 struct xtm_particles_s {
@@ -176,6 +180,31 @@ xtm_status pack(const xtm_element_desc& e, int32_t index, const RefQ& r, double 
   }
 }
 
+// Greedy split of a packed table into segments of at most kSegWords words.
+std::vector<int32_t> segment(const std::vector<uint64_t>& tab, int32_t n_el) {
+  std::vector<int32_t> seg;
+  size_t off = 0, start = 0;
+  int32_t count = 0;
+  for (int32_t e = 0; e < n_el; ++e) {
+    const size_t len = 1 + ((tab[off] >> 16) & 0xffffu);
+    if (off + len - start > (size_t)kSegWords) {
+      seg.push_back((int32_t)start);
+      seg.push_back((int32_t)(off - start));
+      seg.push_back(count);
+      start = off;
+      count = 0;
+    }
+    off += len;
+    ++count;
+  }
+  if (count > 0 || seg.empty()) {
+    seg.push_back((int32_t)start);
+    seg.push_back((int32_t)(off - start));
+    seg.push_back(count);
+  }
+  return seg;
+}
+
 SoA soa_of(const xtm_particles_s* p) {
   SoA s;
   s.x = p->a.x; s.px = p->a.px; s.y = p->a.y; s.py = p->a.py; s.zeta = p->a.zeta;
@@ -229,7 +258,7 @@ xtm_status run_turns(xtm_lattice_s* L, xtm_particles_s* P, int32_t n_turns,
     return fail(XTM_E_ARG, "block must be 64, 128, 192 or 256");
   const bool compact = !(o && o->no_compact) || backward;
   const int32_t variant = (o && o->variant) ? o->variant : 2;
-  if (variant != 1 && variant != 2) return fail(XTM_E_ARG, "kernel variant must be 0, 1 or 2");
+  if (variant < 1 || variant > 3) return fail(XTM_E_ARG, "kernel variant must be 0..3");
   int32_t chunk = (o && o->turns_per_chunk > 0) ? o->turns_per_chunk
                                                  : auto_chunk(P->alive_upper, L->n_el, n_turns);
   if (stats) HIP_TRY(launch_fill_i64(P->passes, 0, s), "clear passes");
@@ -253,7 +282,9 @@ xtm_status run_turns(xtm_lattice_s* L, xtm_particles_s* P, int32_t n_turns,
       ev.push_back(b);
       HIP_TRY(hipEventRecord(a, s), "event record");
     }
-    HIP_TRY(launch_track(tab, L->n_el, soa, in, P->ctrl, P->alive_upper, block, k, t0,
+    HIP_TRY(launch_track(tab, backward ? L->bwd_seg_d : L->fwd_seg_d,
+                         (int32_t)((backward ? L->bwd_seg_h.size() : L->fwd_seg_h.size()) / 3),
+                         L->n_el, soa, in, P->ctrl, P->alive_upper, block, k, t0,
                          backward ? 1 : 0, kr, variant, s),
             "track kernel launch");
     if (timing) HIP_TRY(hipEventRecord(ev.back(), s), "event record");
@@ -323,6 +354,19 @@ xtm_status xtm_lattice_create(const xtm_element_desc* el, int32_t n, const xtm_r
       xtm_status st = pack(el[i], i, r, -1.0, L->bwd_h);
       if (st != XTM_OK) { delete L; return st; }
     }
+    L->fwd_seg_h = segment(L->fwd_h, n);
+    L->bwd_seg_h = segment(L->bwd_h, n);
+    const size_t sbytes = L->fwd_seg_h.size() * sizeof(int32_t);
+    if (hipMalloc(&L->fwd_seg_d, sbytes) != hipSuccess ||
+        hipMalloc(&L->bwd_seg_d, L->bwd_seg_h.size() * sizeof(int32_t)) != hipSuccess ||
+        hipMemcpy(L->fwd_seg_d, L->fwd_seg_h.data(), sbytes, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(L->bwd_seg_d, L->bwd_seg_h.data(), L->bwd_seg_h.size() * sizeof(int32_t),
+                  hipMemcpyHostToDevice) != hipSuccess) {
+      hipFree(L->fwd_seg_d);
+      hipFree(L->bwd_seg_d);
+      delete L;
+      return fail(XTM_E_NOMEM, "device allocation of the segment table failed");
+    }
     const size_t bytes = (L->fwd_h.size() + 1) * sizeof(uint64_t);
     if (hipMalloc(&L->fwd_d, bytes) != hipSuccess || hipMalloc(&L->bwd_d, bytes) != hipSuccess) {
       hipFree(L->fwd_d);
@@ -347,6 +391,8 @@ xtm_status xtm_lattice_destroy(xtm_lattice L) {
   if (!L) return XTM_OK;
   hipFree(L->fwd_d);
   hipFree(L->bwd_d);
+  hipFree(L->fwd_seg_d);
+  hipFree(L->bwd_seg_d);
   delete L;
   return XTM_OK;
 }

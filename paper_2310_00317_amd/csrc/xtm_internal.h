@@ -45,10 +45,13 @@ struct KernelRef {
 hipError_t launch_init(const double* coords6, int64_t n, int64_t first_id, SoA P, KernelRef r,
                        hipStream_t s);
 hipError_t launch_iota(int32_t* idx, int64_t n, int32_t* ctrl, int32_t n_alive, hipStream_t s);
-hipError_t launch_track(const uint64_t* tab, int32_t n_el, SoA P, const int32_t* idx,
-                        const int32_t* ctrl, int64_t grid_upper, int32_t block, int32_t n_turns,
-                        int32_t t0, int32_t backward, KernelRef r, int32_t variant,
-                        hipStream_t s);
+// words per LDS segment of the element table (variant 3); a record never
+// straddles two segments
+constexpr int kSegWords = 4096;
+hipError_t launch_track(const uint64_t* tab, const int32_t* seg, int32_t n_seg, int32_t n_el,
+                        SoA P, const int32_t* idx, const int32_t* ctrl, int64_t grid_upper,
+                        int32_t block, int32_t n_turns, int32_t t0, int32_t backward, KernelRef r,
+                        int32_t variant, hipStream_t s);
 // end-of-chunk bookkeeping: passes of the chunk (added to *passes), then an
 // order-preserving compaction of the alive list into idx_out (if idx_out != null)
 hipError_t launch_epilogue(const int32_t* idx_in, int32_t* idx_out, int64_t grid_upper,

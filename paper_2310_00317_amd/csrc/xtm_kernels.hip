@@ -418,6 +418,160 @@ __global__ void __launch_bounds__(256) k_track2(const uint64_t* __restrict__ tab
   }
 }
 
+// ------------------------------------------------ track kernel, variant 3
+// Freeze-on-loss like variant 2, but the element table is staged in LDS in
+// segments of at most kSegWords words (a segment never splits a record).  The
+// workgroup copies a segment with coalesced vector loads, then every wave
+// reads headers and parameters from LDS with uniform addresses (broadcast
+// reads that pipeline, unlike scalar loads whose returns are unordered).  A
+// lattice that fits in one segment is copied once per launch.
+template <int kSegWords>
+__global__ void __launch_bounds__(256) k_track3(const uint64_t* __restrict__ tab,
+                                                const int32_t* __restrict__ seg, int32_t n_seg,
+                                                int32_t n_el, SoA P,
+                                                const int32_t* __restrict__ idx,
+                                                const int32_t* __restrict__ ctrl, int32_t n_turns,
+                                                int32_t t0, int32_t backward, KernelRef r) {
+  __shared__ uint64_t lds[kSegWords];
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int32_t n_alive = ctrl[0];
+  const bool in_range = i < n_alive;
+  const int32_t p = in_range ? idx[i] : 0;
+  bool lost = !in_range || P.state[p] != 1;
+  // block-uniform early exit (no barrier has been reached yet)
+  if (__syncthreads_and(lost)) return;
+
+  Pt q;
+  q.x = P.x[p]; q.px = P.px[p]; q.y = P.y[p]; q.py = P.py[p]; q.zeta = P.zeta[p];
+  q.delta = P.delta[p]; q.ptau = P.ptau[p]; q.rpp = P.rpp[p]; q.rvv = P.rvv[p];
+  refresh(q, r.beta0);
+  const double beta0 = r.beta0;
+
+  auto load_segment = [&](int32_t sgi) {
+    const int32_t w0 = seg[3 * sgi], nwords = seg[3 * sgi + 1];
+    for (int32_t k = threadIdx.x; k < nwords; k += blockDim.x) lds[k] = tab[w0 + k];
+  };
+  if (n_seg == 1) {
+    load_segment(0);
+    __syncthreads();
+  }
+  for (int32_t t = 0; t < n_turns; ++t) {
+    int32_t e_base = 0;
+    for (int32_t sgi = 0; sgi < n_seg; ++sgi) {
+      if (n_seg > 1) {
+        __syncthreads();
+        load_segment(sgi);
+        __syncthreads();
+      }
+      const int32_t n_here = seg[3 * sgi + 2];
+      uint32_t off = 0;
+      for (int32_t k = 0; k < n_here; ++k) {
+        const int32_t e = e_base + k;
+        const uint64_t h = lds[off];
+        const uint32_t ktype = (uint32_t)(h & 0xffu);
+        const uint32_t order = (uint32_t)((h >> 8) & 0xffu);
+        const uint32_t nw = (uint32_t)((h >> 16) & 0xffffu);
+        const double* prm = reinterpret_cast<const double*>(&lds[off + 1]);
+        if (ktype == K_MULT) {
+          horner_n(q, prm, order);
+        } else if (ktype == K_DRIFT) {
+          const double L = prm[0];
+          const double px2 = q.px * q.px;
+          const double py2 = q.py * q.py;
+          const double pz2 = q.opd2 - px2 - py2;
+          if (!(pz2 > 0.0) && !lost) {
+            freeze(P, p, q, -1, e, t, n_el, t0, backward);
+            lost = true;
+          }
+          const double pz = sqrt(pz2);
+          const double lp = L / pz;
+          q.x = fma(q.px, lp, q.x);
+          q.y = fma(q.py, lp, q.y);
+          const double dz = (q.u - px2 - py2) / (1.0 + pz) - q.bpt;
+          q.zeta = fma(lp, dz, q.zeta);
+        } else if (ktype == K_AP_CIRC) {
+          if (!(q.x * q.x + q.y * q.y <= prm[0]) && !lost) {
+            freeze(P, p, q, 0, e, t, n_el, t0, backward);
+            lost = true;
+          }
+        } else {
+          switch (ktype) {
+            case K_DRIFT_EXP: {
+              const double L = prm[0];
+              const double lr = L * q.rpp;
+              q.x = fma(q.px, lr, q.x);
+              q.y = fma(q.py, lr, q.y);
+              const double pp = q.px * q.px + q.py * q.py;
+              const double r3 = q.rpp * q.rpp * q.rpp;
+              const double dz = (q.delta - q.bpt) * q.rpp - 0.5 * pp * r3 * (1.0 + q.bpt);
+              q.zeta = fma(L, dz, q.zeta);
+              break;
+            }
+            case K_MULT_CURV: {
+              horner_n(q, prm, order);
+              const double* cv = prm + 2 * (order + 1);
+              const double hxl = cv[0], k0h = cv[1], lr = cv[2];
+              double dpx = hxl * (1.0 + q.delta);
+              if (lr > 0.0) dpx = dpx - k0h * q.x / lr;
+              const double dz = hxl * q.x * (1.0 + q.bpt) * q.rpp;
+              q.px = q.px + dpx;
+              q.zeta = q.zeta - dz;
+              break;
+            }
+            case K_RF: {
+              const double s = sin(prm[2] - prm[1] * q.zeta);
+              q.ptau = q.ptau + prm[0] * s;
+              const double v = q.ptau * (q.ptau + r.two_over_beta0);
+              q.delta = v / (1.0 + sqrt(1.0 + v));
+              q.rpp = 1.0 / (1.0 + q.delta);
+              q.rvv = (1.0 + q.delta) / (1.0 + beta0 * q.ptau);
+              refresh(q, beta0);
+              break;
+            }
+            case K_SHIFT:
+              q.x = q.x - prm[0];
+              q.y = q.y - prm[1];
+              break;
+            case K_SROT: {
+              const double c = prm[0], s = prm[1];
+              const double x = c * q.x + s * q.y;
+              const double y = c * q.y - s * q.x;
+              const double px = c * q.px + s * q.py;
+              const double py = c * q.py - s * q.px;
+              q.x = x; q.y = y; q.px = px; q.py = py;
+              break;
+            }
+            case K_AP_ELL:
+              if (!(q.x * q.x * prm[0] + q.y * q.y * prm[1] <= 1.0) && !lost) {
+                freeze(P, p, q, 0, e, t, n_el, t0, backward);
+                lost = true;
+              }
+              break;
+            case K_AP_RECT:
+              if (!((prm[0] <= q.x) & (q.x <= prm[1]) & (prm[2] <= q.y) & (q.y <= prm[3])) &&
+                  !lost) {
+                freeze(P, p, q, 0, e, t, n_el, t0, backward);
+                lost = true;
+              }
+              break;
+            default:
+              break;
+          }
+        }
+        off += 1 + nw;
+      }
+      e_base += n_here;
+    }
+    if (__syncthreads_and(lost)) return;
+  }
+  if (!lost) {
+    P.x[p] = q.x; P.px[p] = q.px; P.y[p] = q.y; P.py[p] = q.py; P.zeta[p] = q.zeta;
+    P.delta[p] = q.delta; P.ptau[p] = q.ptau; P.rpp[p] = q.rpp; P.rvv[p] = q.rvv;
+    P.at_turn[p] = backward ? t0 - n_turns : t0 + n_turns;
+    P.at_element[p] = 0;
+  }
+}
+
 // -------------------------------------------------------- chunk epilogue
 // Block-wide exclusive scan of a 0/1 flag over kScanBlock threads (16 wave64s).
 __device__ __forceinline__ int32_t block_rank(bool flag, int32_t* s_wave, int32_t* total) {
@@ -532,12 +686,15 @@ hipError_t launch_fill_i64(int64_t* p, int64_t v, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_track(const uint64_t* tab, int32_t n_el, SoA P, const int32_t* idx,
-                        const int32_t* ctrl, int64_t grid_upper, int32_t block, int32_t n_turns,
-                        int32_t t0, int32_t backward, KernelRef r, int32_t variant,
-                        hipStream_t s) {
+hipError_t launch_track(const uint64_t* tab, const int32_t* seg, int32_t n_seg, int32_t n_el,
+                        SoA P, const int32_t* idx, const int32_t* ctrl, int64_t grid_upper,
+                        int32_t block, int32_t n_turns, int32_t t0, int32_t backward, KernelRef r,
+                        int32_t variant, hipStream_t s) {
   if (grid_upper <= 0 || n_turns <= 0) return hipSuccess;
-  if (variant == 1)
+  if (variant == 3)
+    hipLaunchKernelGGL(k_track3<kSegWords>, dim3(blocks_for(grid_upper, block)), dim3(block), 0,
+                       s, tab, seg, n_seg, n_el, P, idx, ctrl, n_turns, t0, backward, r);
+  else if (variant == 1)
     hipLaunchKernelGGL(k_track, dim3(blocks_for(grid_upper, block)), dim3(block), 0, s, tab, n_el,
                        P, idx, ctrl, n_turns, t0, backward, r);
   else

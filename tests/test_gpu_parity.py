@@ -142,6 +142,7 @@ def test_resume_bitwise(P):
 
 @pytest.mark.parametrize("opts", [dict(turns_per_chunk=1), dict(turns_per_chunk=7, block=64),
                                   dict(variant=1), dict(variant=1, turns_per_chunk=13),
+                                  dict(variant=3), dict(variant=3, block=64, turns_per_chunk=9),
                                   dict(turns_per_chunk=100, block=128, compact=False),
                                   dict(turns_per_chunk=33, block=192)])
 def test_launch_shape_invariance(P, opts):
@@ -237,3 +238,18 @@ def test_cfg2_lattice_reduced(P, oracle_mod):
     o, op = oracle_run(oracle_mod, el, REF, c, 5)
     assert_parity(g, o, rtol=1e-12)
     assert gp == op
+
+
+@pytest.mark.parametrize("variant", [1, 3])
+def test_kernel_variants_on_multisegment_lattice(P, variant):
+    """The 20,000-element lattice spans many LDS segments: every kernel variant
+    must give bitwise the same result as the default one."""
+    banner(f"cfg2 lattice, variant {variant} vs default")
+    el = I.cfg2_lattice()
+    c, _, _ = I.cfg2_grid(n_r=100, n_theta=6, r_max_sigma=14.0)
+    a, pa, _, _, _ = gpu_run(P, el, REF, c, 6)
+    b, pb, _, _, _ = gpu_run(P, el, REF, c, 6, variant=variant, turns_per_chunk=2)
+    assert (a["state"] != 1).any()
+    assert pa == pb
+    for f in a:
+        assert np.array_equal(a[f], b[f], equal_nan=True), f
