@@ -246,7 +246,7 @@ def test_kernel_variants_on_multisegment_lattice(P, variant):
     must give bitwise the same result as the default one."""
     banner(f"cfg2 lattice, variant {variant} vs default")
     el = I.cfg2_lattice()
-    c, _, _ = I.cfg2_grid(n_r=100, n_theta=6, r_max_sigma=14.0)
+    c, _, _ = I.cfg2_grid(n_r=100, n_theta=6, r_max_sigma=40.0)  # 22% lost within 6 turns
     a, pa, _, _, _ = gpu_run(P, el, REF, c, 6)
     b, pb, _, _, _ = gpu_run(P, el, REF, c, 6, variant=variant, turns_per_chunk=2)
     assert (a["state"] != 1).any()
