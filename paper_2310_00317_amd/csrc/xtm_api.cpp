@@ -69,7 +69,26 @@ struct xtm_lattice_s {
   int32_t* bwd_seg_d = nullptr;
 };
 
+struct GraphKey {
+  const void* lat;
+  int32_t n_turns, chunk, block, variant, backward, compact, cur;
+  int64_t alive_upper;
+  bool operator==(const GraphKey& o) const {
+    return lat == o.lat && n_turns == o.n_turns && chunk == o.chunk && block == o.block &&
+           variant == o.variant && backward == o.backward && compact == o.compact &&
+           cur == o.cur && alive_upper == o.alive_upper;
+  }
+};
+
+struct GraphEntry {
+  GraphKey key;
+  hipGraphExec_t exec;
+  int32_t launches;
+};
+
 struct xtm_particles_s {
+  std::vector<GraphEntry> graphs;      // captured chunk sequences (use_graph)
+  hipStream_t capture_stream = nullptr;
   xtm_arrays a{};
   RefQ ref{};
   int64_t n = 0;
@@ -243,6 +262,98 @@ int32_t auto_chunk(int64_t n, int32_t n_el, int32_t n_turns) {
   return (int32_t)k;
 }
 
+struct ChunkPlan {
+  const uint64_t* tab;
+  const int32_t* seg;
+  int32_t n_seg;
+  int32_t n_turns, chunk, block, variant;
+  bool backward, compact;
+};
+
+// Enqueue the whole chunk sequence on stream s: per chunk the tracking launch,
+// the epilogue (passes + compaction) and the device-side turn advance.  The
+// alive-list buffer alternates per compaction starting from `cur`.  Optional
+// events bracket each tracking launch.
+hipError_t enqueue_chunks(xtm_lattice_s* L, xtm_particles_s* P, const ChunkPlan& c, int32_t cur,
+                          hipStream_t s, std::vector<hipEvent_t>* ev, int32_t* launches) {
+  const SoA soa = soa_of(P);
+  const KernelRef kr = kref(L->ref);
+  int32_t done = 0;
+  *launches = 0;
+  if (P->alive_upper <= 0) return c.n_turns > 0 ? launch_advance(P->ctrl, c.backward ? -c.n_turns : c.n_turns, s) : hipSuccess;
+  while (done < c.n_turns) {
+    const int32_t k = (c.n_turns - done < c.chunk) ? c.n_turns - done : c.chunk;
+    int32_t* in = P->idx[cur];
+    int32_t* out = c.compact ? P->idx[1 - cur] : nullptr;
+    hipError_t e;
+    if (ev) {
+      hipEvent_t a, b;
+      if ((e = hipEventCreate(&a)) != hipSuccess) return e;
+      if ((e = hipEventCreate(&b)) != hipSuccess) return e;
+      ev->push_back(a);
+      ev->push_back(b);
+      if ((e = hipEventRecord(a, s)) != hipSuccess) return e;
+    }
+    e = launch_track(c.tab, c.seg, c.n_seg, L->n_el, soa, in, P->ctrl, P->alive_upper, c.block, k,
+                     c.backward ? 1 : 0, kr, c.variant, s);
+    if (e != hipSuccess) return e;
+    if (ev && (e = hipEventRecord(ev->back(), s)) != hipSuccess) return e;
+    ++*launches;
+    e = launch_epilogue(in, out, P->alive_upper, soa, P->ctrl, P->blockcnt, P->passes, L->n_el, k,
+                        c.backward ? 1 : 0, s);
+    if (e != hipSuccess) return e;
+    e = launch_advance(P->ctrl, c.backward ? -k : k, s);
+    if (e != hipSuccess) return e;
+    if (c.compact) cur = 1 - cur;
+    done += k;
+  }
+  return hipSuccess;
+}
+
+int32_t flips(const ChunkPlan& c) {
+  if (!c.compact || c.n_turns <= 0) return 0;
+  return (c.n_turns + c.chunk - 1) / c.chunk;
+}
+
+xtm_status run_graph(xtm_lattice_s* L, xtm_particles_s* P, const ChunkPlan& c, hipStream_t s,
+                     int32_t* launches) {
+  GraphKey key{L, c.n_turns, c.chunk, c.block, c.variant, c.backward ? 1 : 0, c.compact ? 1 : 0,
+               P->cur, P->alive_upper};
+  for (const GraphEntry& g : P->graphs) {
+    if (g.key == key) {
+      HIP_TRY(hipGraphLaunch(g.exec, s), "graph launch");
+      *launches = g.launches;
+      return XTM_OK;
+    }
+  }
+  if (!P->capture_stream)
+    HIP_TRY(hipStreamCreateWithFlags(&P->capture_stream, hipStreamNonBlocking), "capture stream");
+  HIP_TRY(hipStreamBeginCapture(P->capture_stream, hipStreamCaptureModeThreadLocal), "begin capture");
+  int32_t n = 0;
+  hipError_t e = enqueue_chunks(L, P, c, P->cur, P->capture_stream, nullptr, &n);
+  hipGraph_t graph = nullptr;
+  hipError_t e2 = hipStreamEndCapture(P->capture_stream, &graph);
+  if (e != hipSuccess) { if (graph) hipGraphDestroy(graph); return hip_fail(e, "capture"); }
+  if (e2 != hipSuccess) return hip_fail(e2, "end capture");
+  hipGraphExec_t exec = nullptr;
+  e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  hipGraphDestroy(graph);
+  if (e != hipSuccess) return hip_fail(e, "graph instantiate");
+  if (P->graphs.size() >= 8) {  // keep the cache small
+    hipGraphExecDestroy(P->graphs.front().exec);
+    P->graphs.erase(P->graphs.begin());
+  }
+  P->graphs.push_back(GraphEntry{key, exec, n});
+  HIP_TRY(hipGraphLaunch(exec, s), "graph launch");
+  *launches = n;
+  return XTM_OK;
+}
+
+void drop_graphs(xtm_particles_s* P) {
+  for (GraphEntry& g : P->graphs) hipGraphExecDestroy(g.exec);
+  P->graphs.clear();
+}
+
 xtm_status run_turns(xtm_lattice_s* L, xtm_particles_s* P, int32_t n_turns,
                      const xtm_track_opts* o, hipStream_t s, xtm_track_stats* stats,
                      bool backward) {
@@ -253,48 +364,42 @@ xtm_status run_turns(xtm_lattice_s* L, xtm_particles_s* P, int32_t n_turns,
     return fail(XTM_E_REFERENCE, "lattice and particle set have different references");
   if (backward && P->turn - n_turns < INT32_MIN / 2) return fail(XTM_E_ARG, "turn underflow");
   if (!backward && (int64_t)P->turn + n_turns > INT32_MAX / 2) return fail(XTM_E_ARG, "turn overflow");
-  int32_t block = (o && o->block) ? o->block : 256;
-  if (block < 64 || block > 256 || block % 64)
+  ChunkPlan c;
+  c.block = (o && o->block) ? o->block : 256;
+  if (c.block < 64 || c.block > 256 || c.block % 64)
     return fail(XTM_E_ARG, "block must be 64, 128, 192 or 256");
-  const bool compact = !(o && o->no_compact) || backward;
-  const int32_t variant = (o && o->variant) ? o->variant : 2;
-  if (variant < 1 || variant > 3) return fail(XTM_E_ARG, "kernel variant must be 0..3");
-  int32_t chunk = (o && o->turns_per_chunk > 0) ? o->turns_per_chunk
-                                                 : auto_chunk(P->alive_upper, L->n_el, n_turns);
+  c.compact = !(o && o->no_compact) || backward;
+  c.variant = (o && o->variant) ? o->variant : 2;
+  if (c.variant < 1 || c.variant > 3) return fail(XTM_E_ARG, "kernel variant must be 0..3");
+  c.chunk = (o && o->turns_per_chunk > 0) ? o->turns_per_chunk
+                                           : auto_chunk(P->alive_upper, L->n_el, n_turns);
+  if (c.chunk < 1) c.chunk = 1;
+  c.n_turns = n_turns;
+  c.backward = backward;
+  c.tab = backward ? L->bwd_d : L->fwd_d;
+  c.seg = backward ? L->bwd_seg_d : L->fwd_seg_d;
+  c.n_seg = (int32_t)((backward ? L->bwd_seg_h.size() : L->fwd_seg_h.size()) / 3);
+  const bool graph = o && o->use_graph;
   if (stats) HIP_TRY(launch_fill_i64(P->passes, 0, s), "clear passes");
-  const uint64_t* tab = backward ? L->bwd_d : L->fwd_d;
-  const SoA soa = soa_of(P);
-  const KernelRef kr = kref(L->ref);
   const bool timing = stats && o && o->time_kernels;
   std::vector<hipEvent_t> ev;
   int32_t launches = 0;
-  int32_t done = 0;
-  while (done < n_turns && L->n_el > 0 && P->alive_upper > 0) {
-    const int32_t k = (n_turns - done < chunk) ? n_turns - done : chunk;
-    const int32_t t0 = backward ? P->turn - done : P->turn + done;
-    int32_t* in = P->idx[P->cur];
-    int32_t* out = compact ? P->idx[1 - P->cur] : nullptr;
+  if (graph && n_turns > 0) {
+    hipEvent_t a = nullptr, b = nullptr;
     if (timing) {
-      hipEvent_t a, b;
       HIP_TRY(hipEventCreate(&a), "event");
       HIP_TRY(hipEventCreate(&b), "event");
       ev.push_back(a);
       ev.push_back(b);
       HIP_TRY(hipEventRecord(a, s), "event record");
     }
-    HIP_TRY(launch_track(tab, backward ? L->bwd_seg_d : L->fwd_seg_d,
-                         (int32_t)((backward ? L->bwd_seg_h.size() : L->fwd_seg_h.size()) / 3),
-                         L->n_el, soa, in, P->ctrl, P->alive_upper, block, k, t0,
-                         backward ? 1 : 0, kr, variant, s),
-            "track kernel launch");
-    if (timing) HIP_TRY(hipEventRecord(ev.back(), s), "event record");
-    ++launches;
-    HIP_TRY(launch_epilogue(in, out, P->alive_upper, soa, P->ctrl, P->blockcnt, P->passes,
-                            L->n_el, k, t0, backward ? 1 : 0, s),
-            "epilogue launch");
-    if (compact) P->cur = 1 - P->cur;
-    done += k;
+    xtm_status st = run_graph(L, P, c, s, &launches);
+    if (st != XTM_OK) return st;
+    if (timing) HIP_TRY(hipEventRecord(b, s), "event record");
+  } else if (n_turns > 0) {
+    HIP_TRY(enqueue_chunks(L, P, c, P->cur, s, timing ? &ev : nullptr, &launches), "chunk launch");
   }
+  if (flips(c) & 1) P->cur = 1 - P->cur;
   P->turn = backward ? P->turn - n_turns : P->turn + n_turns;
   if (stats) {
     int64_t alive = 0, passes = 0;
@@ -440,6 +545,8 @@ xtm_status xtm_particles_bind(const xtm_arrays* a, const xtm_reference* ref, xtm
 
 xtm_status xtm_particles_release(xtm_particles P) {
   if (!P) return XTM_OK;
+  drop_graphs(P);
+  if (P->capture_stream) hipStreamDestroy(P->capture_stream);
   hipFree(P->idx[0]);
   hipFree(P->idx[1]);
   hipFree(P->ctrl);
@@ -466,7 +573,7 @@ xtm_status xtm_particles_init(xtm_particles P, const double* coords, int64_t fir
       dc = tmp;
     }
     hipError_t e = launch_init(dc, P->n, first_id, soa_of(P), kref(P->ref), s);
-    if (e == hipSuccess) e = launch_iota(P->idx[0], P->n, P->ctrl, (int32_t)P->n, s);
+    if (e == hipSuccess) e = launch_iota(P->idx[0], P->n, P->ctrl, (int32_t)P->n, 0, s);
     if (e == hipSuccess) e = launch_fill_i64(P->passes, 0, s);
     if (tmp) {
       hipError_t e2 = hipStreamSynchronize(s);
@@ -487,10 +594,10 @@ xtm_status xtm_particles_reset(xtm_particles P, int32_t turn, void* stream) {
     if (!P) return fail(XTM_E_ARG, "null particle set");
     hipStream_t s = (hipStream_t)stream;
     // all indices into the spare buffer, then one compaction into the live one
-    hipError_t e = launch_iota(P->idx[1 - P->cur], P->n, P->ctrl, (int32_t)P->n, s);
+    hipError_t e = launch_iota(P->idx[1 - P->cur], P->n, P->ctrl, (int32_t)P->n, turn, s);
     if (e == hipSuccess)
       e = launch_epilogue(P->idx[1 - P->cur], P->idx[P->cur], P->n > 0 ? P->n : 1, soa_of(P),
-                          P->ctrl, P->blockcnt, P->passes, 0, 0, turn, 0, s);
+                          P->ctrl, P->blockcnt, P->passes, 0, 0, 0, s);
     if (e != hipSuccess) return hip_fail(e, "alive-list rebuild");
     P->turn = turn;
     P->alive_upper = P->n;

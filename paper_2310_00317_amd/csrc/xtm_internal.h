@@ -7,6 +7,9 @@
 
 namespace xtm {
 
+// Device control block of a particle set (int32): [0] alive count, [1] turn
+// of the alive particles, [2] alive count scanned by the last epilogue.
+
 // Device element-table record: one 64-bit header word followed by `nw`
 // FP64 parameter words.  Header bits: [0,8) kernel type, [8,16) multipole
 // order, [16,32) parameter word count, [32,64) user element index.
@@ -44,20 +47,21 @@ struct KernelRef {
 // launch helpers implemented in xtm_kernels.hip; all are stream-ordered
 hipError_t launch_init(const double* coords6, int64_t n, int64_t first_id, SoA P, KernelRef r,
                        hipStream_t s);
-hipError_t launch_iota(int32_t* idx, int64_t n, int32_t* ctrl, int32_t n_alive, hipStream_t s);
+hipError_t launch_iota(int32_t* idx, int64_t n, int32_t* ctrl, int32_t n_alive, int32_t turn,
+                       hipStream_t s);
+hipError_t launch_advance(int32_t* ctrl, int32_t dk, hipStream_t s);
 // words per LDS segment of the element table (variant 3); a record never
 // straddles two segments
 constexpr int kSegWords = 4096;
 hipError_t launch_track(const uint64_t* tab, const int32_t* seg, int32_t n_seg, int32_t n_el,
                         SoA P, const int32_t* idx, const int32_t* ctrl, int64_t grid_upper,
-                        int32_t block, int32_t n_turns, int32_t t0, int32_t backward, KernelRef r,
+                        int32_t block, int32_t n_turns, int32_t backward, KernelRef r,
                         int32_t variant, hipStream_t s);
 // end-of-chunk bookkeeping: passes of the chunk (added to *passes), then an
 // order-preserving compaction of the alive list into idx_out (if idx_out != null)
 hipError_t launch_epilogue(const int32_t* idx_in, int32_t* idx_out, int64_t grid_upper,
                            SoA P, int32_t* ctrl, int32_t* blockcnt, int64_t* passes,
-                           int32_t n_el, int32_t chunk_turns, int32_t t0, int32_t backward,
-                           hipStream_t s);
+                           int32_t n_el, int32_t chunk_turns, int32_t backward, hipStream_t s);
 hipError_t launch_fill_i64(int64_t* p, int64_t v, hipStream_t s);
 
 constexpr int kScanBlock = 1024;

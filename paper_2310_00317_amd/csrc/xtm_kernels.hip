@@ -54,13 +54,19 @@ __global__ void __launch_bounds__(256) k_init(const double* __restrict__ c6, int
 }
 
 __global__ void __launch_bounds__(256) k_iota(int32_t* idx, int64_t n, int32_t* ctrl,
-                                              int32_t n_alive) {
+                                              int32_t n_alive, int32_t turn) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) idx[i] = (int32_t)i;
   if (i == 0) {
     ctrl[0] = n_alive;
+    ctrl[1] = turn;
     ctrl[2] = n_alive;
   }
+}
+
+// end of a chunk: the alive particles are dk turns further
+__global__ void k_advance(int32_t* ctrl, int32_t dk) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) ctrl[1] += dk;
 }
 
 __global__ void k_fill_i64(int64_t* p, int64_t v) {
@@ -119,7 +125,10 @@ __device__ __forceinline__ void horner_n(Pt& q, const double* __restrict__ c, ui
 __global__ void __launch_bounds__(256) k_track(const uint64_t* __restrict__ tab, int32_t n_el,
                                                SoA P, const int32_t* __restrict__ idx,
                                                const int32_t* __restrict__ ctrl, int32_t n_turns,
-                                               int32_t t0, int32_t backward, KernelRef r) {
+                                               int32_t backward, KernelRef r) {
+  // the turn of the alive particles lives on the device, so a captured
+  // chunk sequence replays correctly from any starting turn
+  const int32_t t0 = ctrl[1];
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= ctrl[0]) return;
   const int32_t p = idx[i];
@@ -293,7 +302,10 @@ __device__ __forceinline__ void freeze(const SoA& P, int32_t p, const Pt& q, int
 __global__ void __launch_bounds__(256) k_track2(const uint64_t* __restrict__ tab, int32_t n_el,
                                                 SoA P, const int32_t* __restrict__ idx,
                                                 const int32_t* __restrict__ ctrl, int32_t n_turns,
-                                                int32_t t0, int32_t backward, KernelRef r) {
+                                                int32_t backward, KernelRef r) {
+  // the turn of the alive particles lives on the device, so a captured
+  // chunk sequence replays correctly from any starting turn
+  const int32_t t0 = ctrl[1];
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int32_t n_alive = ctrl[0];
   const bool in_range = i < n_alive;
@@ -431,7 +443,10 @@ __global__ void __launch_bounds__(256) k_track3(const uint64_t* __restrict__ tab
                                                 int32_t n_el, SoA P,
                                                 const int32_t* __restrict__ idx,
                                                 const int32_t* __restrict__ ctrl, int32_t n_turns,
-                                                int32_t t0, int32_t backward, KernelRef r) {
+                                                int32_t backward, KernelRef r) {
+  // the turn of the alive particles lives on the device, so a captured
+  // chunk sequence replays correctly from any starting turn
+  const int32_t t0 = ctrl[1];
   __shared__ uint64_t lds[kSegWords];
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int32_t n_alive = ctrl[0];
@@ -596,8 +611,8 @@ __device__ __forceinline__ int32_t block_rank(bool flag, int32_t* s_wave, int32_
 __global__ void __launch_bounds__(kScanBlock) k_count(const int32_t* __restrict__ idx, SoA P,
                                                       int32_t* ctrl, int32_t* blockcnt,
                                                       unsigned long long* passes, int32_t n_el,
-                                                      int32_t chunk_turns, int32_t t0,
-                                                      int32_t backward) {
+                                                      int32_t chunk_turns, int32_t backward) {
+  const int32_t t0 = ctrl[1];
   __shared__ int32_t s_wave[kScanBlock / 64];
   __shared__ unsigned long long s_pass[kScanBlock / 64];
   const int32_t n_alive = ctrl[0];
@@ -675,9 +690,16 @@ hipError_t launch_init(const double* coords6, int64_t n, int64_t first_id, SoA P
   return hipGetLastError();
 }
 
-hipError_t launch_iota(int32_t* idx, int64_t n, int32_t* ctrl, int32_t n_alive, hipStream_t s) {
+hipError_t launch_iota(int32_t* idx, int64_t n, int32_t* ctrl, int32_t n_alive, int32_t turn,
+                       hipStream_t s) {
   int64_t m = n > 0 ? n : 1;
-  hipLaunchKernelGGL(k_iota, dim3(blocks_for(m, 256)), dim3(256), 0, s, idx, n, ctrl, n_alive);
+  hipLaunchKernelGGL(k_iota, dim3(blocks_for(m, 256)), dim3(256), 0, s, idx, n, ctrl, n_alive,
+                     turn);
+  return hipGetLastError();
+}
+
+hipError_t launch_advance(int32_t* ctrl, int32_t dk, hipStream_t s) {
+  hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, s, ctrl, dk);
   return hipGetLastError();
 }
 
@@ -688,29 +710,28 @@ hipError_t launch_fill_i64(int64_t* p, int64_t v, hipStream_t s) {
 
 hipError_t launch_track(const uint64_t* tab, const int32_t* seg, int32_t n_seg, int32_t n_el,
                         SoA P, const int32_t* idx, const int32_t* ctrl, int64_t grid_upper,
-                        int32_t block, int32_t n_turns, int32_t t0, int32_t backward, KernelRef r,
+                        int32_t block, int32_t n_turns, int32_t backward, KernelRef r,
                         int32_t variant, hipStream_t s) {
   if (grid_upper <= 0 || n_turns <= 0) return hipSuccess;
   if (variant == 3)
     hipLaunchKernelGGL(k_track3<kSegWords>, dim3(blocks_for(grid_upper, block)), dim3(block), 0,
-                       s, tab, seg, n_seg, n_el, P, idx, ctrl, n_turns, t0, backward, r);
+                       s, tab, seg, n_seg, n_el, P, idx, ctrl, n_turns, backward, r);
   else if (variant == 1)
     hipLaunchKernelGGL(k_track, dim3(blocks_for(grid_upper, block)), dim3(block), 0, s, tab, n_el,
-                       P, idx, ctrl, n_turns, t0, backward, r);
+                       P, idx, ctrl, n_turns, backward, r);
   else
     hipLaunchKernelGGL(k_track2, dim3(blocks_for(grid_upper, block)), dim3(block), 0, s, tab, n_el,
-                       P, idx, ctrl, n_turns, t0, backward, r);
+                       P, idx, ctrl, n_turns, backward, r);
   return hipGetLastError();
 }
 
 hipError_t launch_epilogue(const int32_t* idx_in, int32_t* idx_out, int64_t grid_upper, SoA P,
                            int32_t* ctrl, int32_t* blockcnt, int64_t* passes, int32_t n_el,
-                           int32_t chunk_turns, int32_t t0, int32_t backward, hipStream_t s) {
+                           int32_t chunk_turns, int32_t backward, hipStream_t s) {
   if (grid_upper <= 0) return hipSuccess;
   const unsigned nb = blocks_for(grid_upper, kScanBlock);
   hipLaunchKernelGGL(k_count, dim3(nb), dim3(kScanBlock), 0, s, idx_in, P, ctrl, blockcnt,
-                     reinterpret_cast<unsigned long long*>(passes), n_el, chunk_turns, t0,
-                     backward);
+                     reinterpret_cast<unsigned long long*>(passes), n_el, chunk_turns, backward);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || idx_out == nullptr) return e;
   hipLaunchKernelGGL(k_scatter, dim3(nb), dim3(kScanBlock), 0, s, idx_in, idx_out, P, ctrl,

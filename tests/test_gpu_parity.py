@@ -253,3 +253,33 @@ def test_kernel_variants_on_multisegment_lattice(P, variant):
     assert pa == pb
     for f in a:
         assert np.array_equal(a[f], b[f], equal_nan=True), f
+
+
+def test_graph_replay_matches_eager(P):
+    """The chunk sequence captured as a hipGraph and replayed several times
+    (with eager work and synchronisations in between) gives bitwise the eager
+    result after every replay."""
+    banner("hipGraph replay vs eager")
+    el = I.cfg1_lattice()
+    c = I.cfg1_particles(3000, seed=21)
+    c[::40, 0] *= 25.0
+    lat = P.Lattice(el, REF)
+    eager = P.Particles(len(c), REF).init(c)
+    graph = P.Particles(len(c), REF).init(c)
+    for rep in range(4):
+        pe = P.track(lat, eager, 30, turns_per_chunk=7)
+        pg = P.track(lat, graph, 30, turns_per_chunk=7, graph=True, stats=(rep % 2 == 0))
+        if pg is not None:
+            assert pg == pe
+        a, b = eager.to_numpy(), graph.to_numpy()
+        for f in a:
+            assert np.array_equal(a[f], b[f], equal_nan=True), (rep, f)
+        assert graph.turn == eager.turn == 30 * (rep + 1)
+
+
+def test_empty_lattice_counts_turns(P, oracle_mod):
+    c = I.cfg1_particles(8)
+    g, gp, ga, _, _ = gpu_run(P, I.line([]), REF, c, 10)
+    o, op = oracle_run(oracle_mod, I.line([]), REF, c, 10)
+    assert gp == op == 0 and ga == 8
+    assert np.array_equal(g["at_turn"], o.at_turn) and np.all(o.at_turn == 10)
