@@ -160,9 +160,15 @@ typedef struct xtm_track_opts {
   int32_t no_compact;      /* 1 = keep lost particles in the alive list between chunks */
   int32_t use_graph;       /* 1 = replay the chunk sequence as a captured hipGraph    */
   int32_t time_kernels;    /* 1 = time each tracking launch with HIP events (stats)   */
-  int32_t variant;         /* tracking kernel: 0 = default, 1 = exit-on-loss,
-                              2 = freeze-on-loss, 3 = freeze-on-loss with the element
-                              table staged in LDS (same results, different schedule) */
+  int32_t variant;         /* tracking kernel (all give bitwise the same results):
+                              0 = default (5 when the line has a compact periodic
+                              cell structure, else 4); 1 = interpreter, exit on loss;
+                              2 = interpreter, store on loss; 3 = as 2 with the
+                              element table staged in LDS; 4 = interpreter, losses
+                              kept in registers and replayed after the chunk;
+                              5 = per-line kernel generated from the lattice's cell
+                              structure and compiled at first use (as 4 for losses);
+                              XTM_E_UNSUPPORTED if it cannot be built */
 } xtm_track_opts;
 
 typedef struct xtm_track_stats {

@@ -19,13 +19,21 @@ BUILD = os.path.join(ROOT, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", "-fno-fast-math",
-          "-I", os.path.join(ROOT, "include"), "-I", CSRC]
+          "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-I", BUILD]
 DEVICE = ["-x", "hip", f"--offload-arch={ARCH}",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-munsafe-fp-atomics"]
 
 KERNEL_SOURCES = ["xtm_kernels.hip"]
-HOST_SOURCES = ["xtm_api.cpp"]
+HOST_SOURCES = ["xtm_api.cpp", "xtm_jit.cpp"]
+
+
+def _embed_maps() -> None:
+    """The run-time line compiler needs the element-map header as a string."""
+    src = open(os.path.join(CSRC, "xtm_maps.h")).read()
+    assert ")XTMMAPS\"" not in src
+    with open(os.path.join(BUILD, "xtm_maps_src.inc"), "w") as f:
+        f.write('R"XTMMAPS(' + src + ')XTMMAPS"\n')
 
 
 def _run(cmd):
@@ -38,6 +46,7 @@ def _run(cmd):
 
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
+    _embed_maps()
     objs = []
     for src in KERNEL_SOURCES:
         obj = os.path.join(BUILD, src + ".o")
@@ -48,7 +57,7 @@ def build(verbose: bool = False) -> str:
         _run([HIPCC, *COMMON, "-c", os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)
     tmp = LIB + ".tmp%d" % os.getpid()
-    _run([HIPCC, "-shared", f"--offload-arch={ARCH}", "-fPIC", *objs, "-o", tmp])
+    _run([HIPCC, "-shared", f"--offload-arch={ARCH}", "-fPIC", *objs, "-o", tmp, "-lhiprtc"])
     os.replace(tmp, LIB)
     if verbose:
         print("built", LIB)

@@ -67,6 +67,8 @@ struct xtm_lattice_s {
   std::vector<int32_t> fwd_seg_h, bwd_seg_h;
   int32_t* fwd_seg_d = nullptr;
   int32_t* bwd_seg_d = nullptr;
+  // per-line kernels, compiled on first use
+  xtm::LineKernel fwd_line, bwd_line;
 };
 
 struct GraphKey {
@@ -95,6 +97,7 @@ struct xtm_particles_s {
   int32_t turn = 0;
   bool initialised = false;
   int32_t* idx[2] = {nullptr, nullptr};
+  int32_t* lost = nullptr;  // particles lost during the last chunk
   int32_t cur = 0;          // which idx buffer holds the alive list
   int32_t* ctrl = nullptr;  // [0] alive count, [2] count scanned by the last epilogue
   int32_t* blockcnt = nullptr;
@@ -263,6 +266,7 @@ int32_t auto_chunk(int64_t n, int32_t n_el, int32_t n_turns) {
 }
 
 struct ChunkPlan {
+  const LineKernel* line;  // variant 5
   const uint64_t* tab;
   const int32_t* seg;
   int32_t n_seg;
@@ -294,14 +298,24 @@ hipError_t enqueue_chunks(xtm_lattice_s* L, xtm_particles_s* P, const ChunkPlan&
       ev->push_back(b);
       if ((e = hipEventRecord(a, s)) != hipSuccess) return e;
     }
-    e = launch_track(c.tab, c.seg, c.n_seg, L->n_el, soa, in, P->ctrl, P->alive_upper, c.block, k,
-                     c.backward ? 1 : 0, kr, c.variant, s);
+    if (c.variant == 5)
+      e = launch_line(*c.line, L->n_el, soa, in, P->ctrl, P->alive_upper, c.block, k,
+                      c.backward ? 1 : 0, kr, s);
+    else
+      e = launch_track(c.tab, c.seg, c.n_seg, L->n_el, soa, in, P->ctrl, P->alive_upper, c.block,
+                       k, c.backward ? 1 : 0, kr, c.variant, s);
     if (e != hipSuccess) return e;
     if (ev && (e = hipEventRecord(ev->back(), s)) != hipSuccess) return e;
     ++*launches;
-    e = launch_epilogue(in, out, P->alive_upper, soa, P->ctrl, P->blockcnt, P->passes, L->n_el, k,
-                        c.backward ? 1 : 0, s);
+    const bool replay = (c.variant >= 4);
+    e = launch_epilogue(in, out, replay ? P->lost : nullptr, P->alive_upper, soa, P->ctrl,
+                        P->blockcnt, P->passes, L->n_el, k, c.backward ? 1 : 0, s);
     if (e != hipSuccess) return e;
+    if (replay) {
+      e = launch_replay(c.tab, L->n_el, soa, P->lost, P->ctrl, P->alive_upper, c.backward ? 1 : 0,
+                        kr, s);
+      if (e != hipSuccess) return e;
+    }
     e = launch_advance(P->ctrl, c.backward ? -k : k, s);
     if (e != hipSuccess) return e;
     if (c.compact) cur = 1 - cur;
@@ -369,11 +383,31 @@ xtm_status run_turns(xtm_lattice_s* L, xtm_particles_s* P, int32_t n_turns,
   if (c.block < 64 || c.block > 256 || c.block % 64)
     return fail(XTM_E_ARG, "block must be 64, 128, 192 or 256");
   c.compact = !(o && o->no_compact) || backward;
-  c.variant = (o && o->variant) ? o->variant : 2;
-  if (c.variant < 1 || c.variant > 3) return fail(XTM_E_ARG, "kernel variant must be 0..3");
+  c.variant = (o && o->variant) ? o->variant : 0;
+  if (c.variant < 0 || c.variant > 5) return fail(XTM_E_ARG, "kernel variant must be 0..5");
+  c.line = nullptr;
+  if (c.variant == 0 || c.variant == 5) {
+    // the per-line kernel, compiled on first use; the default falls back to
+    // the register-loss interpreter if the line has no compact cell structure
+    LineKernel& lk = backward ? L->bwd_line : L->fwd_line;
+    if (!lk.tried && L->n_el > 0) {
+      lk.tried = true;
+      build_line_kernel(backward ? L->bwd_h : L->fwd_h, L->n_el, &lk);
+    }
+    if (lk.ok) {
+      c.variant = 5;
+      c.line = &lk;
+    } else if (c.variant == 5 && L->n_el > 0) {
+      return fail(XTM_E_UNSUPPORTED, "per-line kernel unavailable: " + lk.error);
+    } else {
+      c.variant = 4;
+    }
+  }
   c.chunk = (o && o->turns_per_chunk > 0) ? o->turns_per_chunk
                                            : auto_chunk(P->alive_upper, L->n_el, n_turns);
   if (c.chunk < 1) c.chunk = 1;
+  if (L->n_el > 0 && (int64_t)c.chunk * L->n_el > INT32_MAX - 1)
+    c.chunk = (int32_t)((INT32_MAX - 1) / L->n_el);
   c.n_turns = n_turns;
   c.backward = backward;
   c.tab = backward ? L->bwd_d : L->fwd_d;
@@ -498,6 +532,8 @@ xtm_status xtm_lattice_destroy(xtm_lattice L) {
   hipFree(L->bwd_d);
   hipFree(L->fwd_seg_d);
   hipFree(L->bwd_seg_d);
+  free_line_kernel(&L->fwd_line);
+  free_line_kernel(&L->bwd_line);
   delete L;
   return XTM_OK;
 }
@@ -529,11 +565,13 @@ xtm_status xtm_particles_bind(const xtm_arrays* a, const xtm_reference* ref, xtm
     const int64_t nb = (m + kScanBlock - 1) / kScanBlock;
     bool ok = hipMalloc(&P->idx[0], m * sizeof(int32_t)) == hipSuccess &&
               hipMalloc(&P->idx[1], m * sizeof(int32_t)) == hipSuccess &&
+              hipMalloc(&P->lost, m * sizeof(int32_t)) == hipSuccess &&
               hipMalloc(&P->ctrl, 4 * sizeof(int32_t)) == hipSuccess &&
-              hipMalloc(&P->blockcnt, nb * sizeof(int32_t)) == hipSuccess &&
+              hipMalloc(&P->blockcnt, 2 * nb * sizeof(int32_t)) == hipSuccess &&
               hipMalloc(&P->passes, sizeof(int64_t)) == hipSuccess;
     if (!ok) {
-      hipFree(P->idx[0]); hipFree(P->idx[1]); hipFree(P->ctrl); hipFree(P->blockcnt);
+      hipFree(P->idx[0]); hipFree(P->idx[1]); hipFree(P->lost); hipFree(P->ctrl);
+      hipFree(P->blockcnt);
       hipFree(P->passes);
       delete P;
       return fail(XTM_E_NOMEM, "device allocation of particle work buffers failed");
@@ -549,6 +587,7 @@ xtm_status xtm_particles_release(xtm_particles P) {
   if (P->capture_stream) hipStreamDestroy(P->capture_stream);
   hipFree(P->idx[0]);
   hipFree(P->idx[1]);
+  hipFree(P->lost);
   hipFree(P->ctrl);
   hipFree(P->blockcnt);
   hipFree(P->passes);
@@ -596,8 +635,8 @@ xtm_status xtm_particles_reset(xtm_particles P, int32_t turn, void* stream) {
     // all indices into the spare buffer, then one compaction into the live one
     hipError_t e = launch_iota(P->idx[1 - P->cur], P->n, P->ctrl, (int32_t)P->n, turn, s);
     if (e == hipSuccess)
-      e = launch_epilogue(P->idx[1 - P->cur], P->idx[P->cur], P->n > 0 ? P->n : 1, soa_of(P),
-                          P->ctrl, P->blockcnt, P->passes, 0, 0, 0, s);
+      e = launch_epilogue(P->idx[1 - P->cur], P->idx[P->cur], nullptr, P->n > 0 ? P->n : 1,
+                          soa_of(P), P->ctrl, P->blockcnt, P->passes, 0, 0, 0, s);
     if (e != hipSuccess) return hip_fail(e, "alive-list rebuild");
     P->turn = turn;
     P->alive_upper = P->n;

@@ -5,10 +5,14 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <string>
+#include <vector>
+
 namespace xtm {
 
 // Device control block of a particle set (int32): [0] alive count, [1] turn
-// of the alive particles, [2] alive count scanned by the last epilogue.
+// of the alive particles, [2] alive count scanned by the last epilogue,
+// [3] number of particles lost during the last chunk.
 
 // Device element-table record: one 64-bit header word followed by `nw`
 // FP64 parameter words.  Header bits: [0,8) kernel type, [8,16) multipole
@@ -58,12 +62,38 @@ hipError_t launch_track(const uint64_t* tab, const int32_t* seg, int32_t n_seg, 
                         int32_t block, int32_t n_turns, int32_t backward, KernelRef r,
                         int32_t variant, hipStream_t s);
 // end-of-chunk bookkeeping: passes of the chunk (added to *passes), then an
-// order-preserving compaction of the alive list into idx_out (if idx_out != null)
-hipError_t launch_epilogue(const int32_t* idx_in, int32_t* idx_out, int64_t grid_upper,
-                           SoA P, int32_t* ctrl, int32_t* blockcnt, int64_t* passes,
-                           int32_t n_el, int32_t chunk_turns, int32_t backward, hipStream_t s);
+// order-preserving compaction of the alive list into idx_out (if non-null)
+// and of the particles lost during the chunk into lost_out (if non-null);
+// ctrl[0] = new alive count, ctrl[3] = lost count
+hipError_t launch_epilogue(const int32_t* idx_in, int32_t* idx_out, int32_t* lost_out,
+                           int64_t grid_upper, SoA P, int32_t* ctrl, int32_t* blockcnt,
+                           int64_t* passes, int32_t n_el, int32_t chunk_turns, int32_t backward,
+                           hipStream_t s);
+// coordinates of the particles in lost[0..ctrl[3]) re-tracked from the chunk
+// start to their loss point (for kernels that record losses in registers)
+hipError_t launch_replay(const uint64_t* tab, int32_t n_el, SoA P, const int32_t* lost,
+                         const int32_t* ctrl, int64_t grid_upper, int32_t backward, KernelRef r,
+                         hipStream_t s);
 hipError_t launch_fill_i64(int64_t* p, int64_t v, hipStream_t s);
 
 constexpr int kScanBlock = 1024;
+
+// Per-line tracking kernel generated from the lattice's cell structure and
+// compiled at run time (xtm_jit.cpp).
+struct LineKernel {
+  bool ok = false;
+  bool tried = false;
+  hipFunction_t fn = nullptr;
+  int32_t period = 0, n_cells = 0, n_kinds = 0;
+  double* prm_d = nullptr;     // element parameters in element order, no headers
+  int32_t* cells_d = nullptr;  // per cell: kind, offset of its first parameter, word count
+  std::string source;
+  std::string error;
+};
+bool build_line_kernel(const std::vector<uint64_t>& tab, int32_t n_el, LineKernel* k);
+void free_line_kernel(LineKernel* k);
+hipError_t launch_line(const LineKernel& k, int32_t n_el, SoA P, const int32_t* idx,
+                       const int32_t* ctrl, int64_t grid_upper, int32_t block, int32_t n_turns,
+                       int32_t backward, KernelRef r, hipStream_t s);
 
 }  // namespace xtm

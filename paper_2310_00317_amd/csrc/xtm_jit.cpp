@@ -1,0 +1,378 @@
+// xtm_jit.cpp -- per-line tracking kernels generated and compiled at run time.
+//
+// The paper's tracker assembles and compiles one kernel that tracks the whole
+// beam line.  On gfx950 the reason to do so is sharper than on a CPU: with
+// one particle per lane and often fewer than two waves per SIMD, a generic
+// element interpreter spends more issue slots on scalar dispatch (type
+// decode, compare tree, loop control, register shuffling between switch arms)
+// than on the FP64 maps.  Here the element-type sequence is cut into cells of
+// a fixed period; each distinct cell signature ("kind") becomes one
+// straight-line block of map calls with compile-time parameter offsets, and
+// the kernel loops over the cells of a turn with one scalar branch per cell.
+// Element parameters stay data (one array, read with scalar loads), so all
+// lattices with the same structure share one compiled kernel.
+#include <hip/hip_runtime.h>
+#include <hip/hiprtc.h>
+
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "xtm_internal.h"
+
+namespace xtm {
+
+static const char* kMapsSource =
+#include "xtm_maps_src.inc"
+    ;
+
+namespace {
+
+struct Compiled {
+  hipModule_t module = nullptr;
+  hipFunction_t fn = nullptr;
+  std::string error;
+};
+
+std::mutex g_mu;
+std::map<std::string, Compiled> g_cache;  // generated source -> compiled kernel
+
+uint32_t sig_of(uint64_t h) { return (uint32_t)(h & 0xffffu); }  // kernel type | order << 8
+
+struct Decomp {
+  int32_t period = 0;
+  std::vector<std::vector<uint32_t>> kinds;  // element signatures of each kind
+  std::vector<int32_t> cell_kind;
+};
+
+// Choose the period P (1..128) with the fewest cells per turn whose distinct
+// cell signatures need at most kMaxCode elements of generated code.
+constexpr int kMaxCode = 24;
+
+bool decompose(const std::vector<uint32_t>& sig, Decomp* out) {
+  const int32_t E = (int32_t)sig.size();
+  if (E == 0) return false;
+  int64_t best_cells = -1;
+  for (int32_t P = 1; P <= 128 && P <= E; ++P) {
+    const int32_t n_cells = (E + P - 1) / P;
+    std::map<std::vector<uint32_t>, int32_t> kinds;
+    int32_t code = 0;
+    bool too_big = false;
+    for (int32_t c = 0; c < n_cells && !too_big; ++c) {
+      std::vector<uint32_t> t(sig.begin() + (size_t)c * P,
+                              sig.begin() + std::min<size_t>((size_t)(c + 1) * P, (size_t)E));
+      if (kinds.find(t) == kinds.end()) {
+        code += (int32_t)t.size();
+        kinds.emplace(t, (int32_t)kinds.size());
+        if (code > kMaxCode) too_big = true;
+      }
+    }
+    if (too_big) continue;
+    if (best_cells < 0 || n_cells < best_cells) {
+      best_cells = n_cells;
+      out->period = P;
+      out->kinds.assign(kinds.size(), {});
+      for (auto& kv : kinds) out->kinds[kv.second] = kv.first;
+      out->cell_kind.resize(n_cells);
+      for (int32_t c = 0; c < n_cells; ++c) {
+        std::vector<uint32_t> t(sig.begin() + (size_t)c * P,
+                                sig.begin() + std::min<size_t>((size_t)(c + 1) * P, (size_t)E));
+        out->cell_kind[c] = kinds[t];
+      }
+    }
+  }
+  return best_cells > 0;
+}
+
+int32_t n_words(uint32_t s) {
+  const uint32_t kt = s & 0xffu, order = (s >> 8) & 0xffu;
+  switch (kt) {
+    case K_DRIFT: case K_DRIFT_EXP: case K_AP_CIRC: return 1;
+    case K_MULT: return 2 * ((int32_t)order + 1);
+    case K_MULT_CURV: return 2 * ((int32_t)order + 1) + 3;
+    case K_RF: return 3;
+    case K_SHIFT: case K_SROT: case K_AP_ELL: return 2;
+    case K_AP_RECT: return 4;
+    default: return 0;
+  }
+}
+
+// C++ statement applying one element whose parameters start at p[o]; `j` is
+// its position in the cell (the loss code is e0 + j).
+std::string emit(uint32_t s, int32_t o, int32_t j) {
+  const uint32_t kt = s & 0xffu, order = (s >> 8) & 0xffu;
+  std::ostringstream c;
+  switch (kt) {
+    case K_DRIFT:
+      c << "xtmm::mark(xtmm::drift_exact(q, p[" << o << "]), code, st, e0 + " << j << ", -1);";
+      break;
+    case K_DRIFT_EXP:
+      c << "xtmm::drift_expanded(q, p[" << o << "]);";
+      break;
+    case K_MULT:
+      c << "{ double kx, ky; xtmm::multipole<" << order << ">(q, p + " << o << ", kx, ky); }";
+      break;
+    case K_MULT_CURV: {
+      const int32_t v = o + 2 * ((int32_t)order + 1);
+      c << "{ double kx, ky; xtmm::multipole<" << order << ">(q, p + " << o
+        << ", kx, ky); xtmm::curvature(q, p[" << v << "], p[" << v + 1 << "], p[" << v + 2
+        << "]); }";
+      break;
+    }
+    case K_RF:
+      c << "xtmm::rf(q, p[" << o << "], p[" << o + 1 << "], p[" << o + 2
+        << "], beta0, two_over_beta0);";
+      break;
+    case K_SHIFT:
+      c << "xtmm::xyshift(q, p[" << o << "], p[" << o + 1 << "]);";
+      break;
+    case K_SROT:
+      c << "xtmm::srotation(q, p[" << o << "], p[" << o + 1 << "]);";
+      break;
+    case K_AP_CIRC:
+      c << "xtmm::mark(xtmm::in_circle(q, p[" << o << "]), code, st, e0 + " << j << ", 0);";
+      break;
+    case K_AP_ELL:
+      c << "xtmm::mark(xtmm::in_ellipse(q, p[" << o << "], p[" << o + 1 << "]), code, st, e0 + "
+        << j << ", 0);";
+      break;
+    case K_AP_RECT:
+      c << "xtmm::mark(xtmm::in_rect(q, p[" << o << "], p[" << o + 1 << "], p[" << o + 2
+        << "], p[" << o + 3 << "]), code, st, e0 + " << j << ", 0);";
+      break;
+    default:
+      break;  // marker
+  }
+  return c.str();
+}
+
+int32_t kind_words(const std::vector<uint32_t>& k) {
+  int32_t w = 0;
+  for (uint32_t s : k) w += n_words(s);
+  return w;
+}
+
+// Generated kernel.  Per cell the workgroup holds the cell's parameters in
+// one of two LDS slots: while the waves compute cell g from slot g&1, each
+// thread has already loaded its share of cell g+1's parameters from global
+// memory and writes it to the other slot before the cell barrier.  Element
+// code then reads its parameters as broadcast LDS reads at compile-time
+// offsets.
+std::string generate(const Decomp& d) {
+  int32_t maxw = 1;
+  for (const auto& k : d.kinds) maxw = std::max(maxw, kind_words(k));
+  const int32_t per_thread = (maxw + 255) / 256;
+  std::ostringstream s;
+  s << "#include \"xtm_maps.h\"\n"
+       "struct SoA { double *x, *px, *y, *py, *zeta, *delta, *ptau, *rpp, *rvv;\n"
+       "             int *state, *at_element, *at_turn; long long* pid; };\n"
+       "struct KRef { double beta0, two_over_beta0; };\n"
+       "#define MAXW " << maxw << "\n"
+       "#define PER_THREAD " << per_thread << "\n"
+       "extern \"C\" __global__ void __launch_bounds__(256)\n"
+       "xtm_line(const double* __restrict__ prm, const int* __restrict__ cells, int n_cells,\n"
+       "         int n_el, SoA P, const int* __restrict__ idx, const int* __restrict__ ctrl,\n"
+       "         int n_turns, int backward, KRef r) {\n"
+       "  __shared__ double slot[2 * MAXW];\n"
+       "  const int t0 = ctrl[1];\n"
+       "  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;\n"
+       "  const bool in_range = i < ctrl[0];\n"
+       "  const int pi = in_range ? idx[i] : 0;\n"
+       "  const bool tracked = in_range && P.state[pi] == 1;\n"
+       "  int code = tracked ? 0 : 1;\n"
+       "  int st = 1;\n"
+       "  if (__syncthreads_and(code != 0)) return;\n"
+       "  xtmm::Pt q;\n"
+       "  q.x = P.x[pi]; q.px = P.px[pi]; q.y = P.y[pi]; q.py = P.py[pi]; q.zeta = P.zeta[pi];\n"
+       "  q.delta = P.delta[pi]; q.ptau = P.ptau[pi]; q.rpp = P.rpp[pi]; q.rvv = P.rvv[pi];\n"
+       "  const double beta0 = r.beta0, two_over_beta0 = r.two_over_beta0;\n"
+       "  xtmm::refresh(q, beta0);\n"
+       "  {\n"
+       "    const int off0 = cells[1], nw0 = cells[2];\n"
+       "    for (int w = threadIdx.x; w < nw0; w += blockDim.x) slot[w] = prm[off0 + w];\n"
+       "  }\n"
+       "  __syncthreads();\n"
+       "  int b = 0;\n"
+       "  for (int t = 0; t < n_turns; ++t) {\n"
+       "    const int enc_t = t * n_el + 1;\n"
+       "    for (int c = 0; c < n_cells; ++c) {\n"
+       "      const int cn = (c + 1 == n_cells) ? 0 : c + 1;\n"
+       "      const int offn = cells[3 * cn + 1], nwn = cells[3 * cn + 2];\n"
+       "      double pre[PER_THREAD];\n"
+       "#pragma unroll\n"
+       "      for (int k = 0; k < PER_THREAD; ++k) {\n"
+       "        const int w = threadIdx.x + k * 256;\n"
+       "        pre[k] = (w < nwn) ? prm[offn + w] : 0.0;\n"
+       "      }\n"
+       "      const int kind = cells[3 * c];\n"
+       "      // slot base hidden behind a register move: element reads become\n"
+       "      // base + immediate-offset LDS loads instead of hoisted constant selects\n"
+       "      int base;\n"
+       "      asm volatile(\"v_mov_b32 %0, %1\" : \"=v\"(base) : \"s\"(b * MAXW));\n"
+       "      // (the mask tells the compiler the base is small and non-negative, which\n"
+       "      // lets it fold the element offsets into the LDS instructions)\n"
+       "      const double* p = &slot[base & 0x3fff];\n"
+       "      // the cell's loss-code base lives in a VGPR so the per-element codes\n"
+       "      // e0 + j are vector adds of literals, not hoisted scalar constants\n"
+       "      int e0;\n"
+       "      asm volatile(\"v_mov_b32 %0, %1\" : \"=v\"(e0) : \"s\"(enc_t + c * " << d.period << "));\n";
+  for (size_t k = 0; k < d.kinds.size(); ++k) {
+    s << "      " << (k ? "else if" : "if") << " (kind == " << k << ") {\n";
+    int32_t o = 0;
+    for (size_t j = 0; j < d.kinds[k].size(); ++j) {
+      const std::string stmt = emit(d.kinds[k][j], o, (int32_t)j);
+      if (!stmt.empty()) s << "        " << stmt << "\n";
+      o += n_words(d.kinds[k][j]);
+    }
+    s << "      }\n";
+  }
+  s << "#pragma unroll\n"
+       "      for (int k = 0; k < PER_THREAD; ++k) {\n"
+       "        const int w = threadIdx.x + k * 256;\n"
+       "        if (w < nwn) slot[(b ^ 1) * MAXW + w] = pre[k];\n"
+       "      }\n"
+       "      b ^= 1;\n"
+       "      __syncthreads();\n"
+       "    }\n"
+       "    if (__syncthreads_and(code != 0)) break;\n"
+       "  }\n"
+       "  if (!tracked) return;\n"
+       "  if (code == 0) {\n"
+       "    P.x[pi] = q.x; P.px[pi] = q.px; P.y[pi] = q.y; P.py[pi] = q.py; P.zeta[pi] = q.zeta;\n"
+       "    P.delta[pi] = q.delta; P.ptau[pi] = q.ptau; P.rpp[pi] = q.rpp; P.rvv[pi] = q.rvv;\n"
+       "    P.at_turn[pi] = backward ? t0 - n_turns : t0 + n_turns;\n"
+       "    P.at_element[pi] = 0;\n"
+       "  } else {\n"
+       "    const int tl = (code - 1) / n_el, el = (code - 1) - tl * n_el;\n"
+       "    P.state[pi] = st;\n"
+       "    P.at_element[pi] = backward ? n_el - 1 - el : el;\n"
+       "    P.at_turn[pi] = backward ? t0 - 1 - tl : t0 + tl;\n"
+       "  }\n"
+       "}\n";
+  return s.str();
+}
+
+Compiled compile(const std::string& src) {
+  Compiled out;
+  hiprtcProgram prog;
+  const char* hdr = kMapsSource;
+  const char* hname = "xtm_maps.h";
+  if (hiprtcCreateProgram(&prog, src.c_str(), "xtm_line.hip", 1, &hdr, &hname) != HIPRTC_SUCCESS) {
+    out.error = "hiprtcCreateProgram failed";
+    return out;
+  }
+  const char* opts[] = {"--offload-arch=gfx950", "-O3", "-std=c++17", "-ffp-contract=off",
+                        "-fno-fast-math", "-Xclang", "-target-feature", "-Xclang",
+                        "-packed-fp32-ops"};
+  hiprtcResult r = hiprtcCompileProgram(prog, (int)(sizeof(opts) / sizeof(opts[0])), opts);
+  if (r != HIPRTC_SUCCESS) {
+    size_t ls = 0;
+    hiprtcGetProgramLogSize(prog, &ls);
+    std::string log(ls, '\0');
+    if (ls) hiprtcGetProgramLog(prog, &log[0]);
+    out.error = "hiprtc: " + log;
+    hiprtcDestroyProgram(&prog);
+    return out;
+  }
+  size_t cs = 0;
+  hiprtcGetCodeSize(prog, &cs);
+  std::vector<char> code(cs);
+  hiprtcGetCode(prog, code.data());
+  hiprtcDestroyProgram(&prog);
+  if (hipModuleLoadData(&out.module, code.data()) != hipSuccess) {
+    out.error = "hipModuleLoadData failed";
+    return out;
+  }
+  if (hipModuleGetFunction(&out.fn, out.module, "xtm_line") != hipSuccess) {
+    out.error = "hipModuleGetFunction failed";
+    out.fn = nullptr;
+  }
+  return out;
+}
+
+}  // namespace
+
+bool build_line_kernel(const std::vector<uint64_t>& tab, int32_t n_el, LineKernel* k) {
+  std::vector<uint32_t> sig;
+  std::vector<int32_t> word_of;  // parameter-array offset of each element
+  std::vector<double> prm;
+  sig.reserve(n_el);
+  size_t off = 0;
+  for (int32_t e = 0; e < n_el; ++e) {
+    const uint64_t h = tab[off];
+    const uint32_t nw = (uint32_t)((h >> 16) & 0xffffu);
+    sig.push_back(sig_of(h));
+    word_of.push_back((int32_t)prm.size());
+    for (uint32_t w = 0; w < nw; ++w) {
+      double d;
+      std::memcpy(&d, &tab[off + 1 + w], 8);
+      prm.push_back(d);
+    }
+    off += 1 + nw;
+  }
+  Decomp d;
+  if (!decompose(sig, &d)) {
+    k->error = "no cell decomposition within the code budget";
+    return false;
+  }
+  k->source = generate(d);
+  {
+    std::lock_guard<std::mutex> lock(g_mu);
+    auto it = g_cache.find(k->source);
+    if (it == g_cache.end()) it = g_cache.emplace(k->source, compile(k->source)).first;
+    if (!it->second.fn) {
+      k->error = it->second.error;
+      return false;
+    }
+    k->fn = it->second.fn;
+  }
+  std::vector<int32_t> cells;  // per cell: kind, first parameter word, word count
+  for (size_t c = 0; c < d.cell_kind.size(); ++c) {
+    cells.push_back(d.cell_kind[c]);
+    cells.push_back(word_of[c * (size_t)d.period]);
+    cells.push_back(kind_words(d.kinds[d.cell_kind[c]]));
+  }
+  k->period = d.period;
+  k->n_cells = (int32_t)d.cell_kind.size();
+  k->n_kinds = (int32_t)d.kinds.size();
+  if (prm.empty()) prm.push_back(0.0);
+  if (hipMalloc(&k->prm_d, prm.size() * sizeof(double)) != hipSuccess ||
+      hipMalloc(&k->cells_d, cells.size() * sizeof(int32_t)) != hipSuccess ||
+      hipMemcpy(k->prm_d, prm.data(), prm.size() * sizeof(double), hipMemcpyHostToDevice) !=
+          hipSuccess ||
+      hipMemcpy(k->cells_d, cells.data(), cells.size() * sizeof(int32_t),
+                hipMemcpyHostToDevice) != hipSuccess) {
+    k->error = "device allocation for the line kernel failed";
+    free_line_kernel(k);
+    return false;
+  }
+  k->ok = true;
+  return true;
+}
+
+void free_line_kernel(LineKernel* k) {
+  hipFree(k->prm_d);
+  hipFree(k->cells_d);
+  k->prm_d = nullptr;
+  k->cells_d = nullptr;
+  k->ok = false;
+}
+
+hipError_t launch_line(const LineKernel& k, int32_t n_el, SoA P, const int32_t* idx,
+                       const int32_t* ctrl, int64_t grid_upper, int32_t block, int32_t n_turns,
+                       int32_t backward, KernelRef r, hipStream_t s) {
+  if (grid_upper <= 0 || n_turns <= 0) return hipSuccess;
+  const double* prm = k.prm_d;
+  const int32_t* cells = k.cells_d;
+  int32_t n_cells = k.n_cells;
+  void* args[] = {(void*)&prm, (void*)&cells, (void*)&n_cells, (void*)&n_el, (void*)&P,
+                  (void*)&idx, (void*)&ctrl, (void*)&n_turns, (void*)&backward, (void*)&r};
+  const unsigned grid = (unsigned)((grid_upper + block - 1) / block);
+  return hipModuleLaunchKernel(k.fn, grid, 1, 1, (unsigned)block, 1, 1, 0, s, args, nullptr);
+}
+
+}  // namespace xtm

@@ -25,6 +25,7 @@
 //                  v = ptau (ptau + 2/beta0); rpp = 1/(1+delta); rvv = (1+delta)/(1+beta0 ptau)
 //   apertures      lost iff !(inside), so NaN is lost and the boundary survives
 #include "xtm_internal.h"
+#include "xtm_maps.h"
 
 namespace xtm {
 
@@ -587,6 +588,171 @@ __global__ void __launch_bounds__(256) k_track3(const uint64_t* __restrict__ tab
   }
 }
 
+// ------------------------------------------------ track kernel, variant 4
+// Branch-free loss handling.  A lane never stores while tracking: a failed
+// check only records, in registers, the first loss (state and the position
+// (turn, element) in the chunk), and the lane keeps computing on whatever its
+// coordinates become.  At the end survivors store their state; lost
+// particles store only the loss record, their coordinates stay at the chunk
+// start, and k_replay re-tracks them to the loss point (the maps are
+// deterministic, so the replayed coordinates are bitwise the ones the lane had
+// when it was lost).  The element loop thus has no divergent control flow.
+__device__ __forceinline__ void apply_elem(xtmm::Pt& q, uint32_t ktype, uint32_t order,
+                                           const double* __restrict__ prm, const KernelRef& r,
+                                           bool& ok, int& lost_state) {
+  double kx, ky;
+  ok = true;
+  lost_state = 0;
+  if (ktype == K_MULT) {
+    switch (order) {
+      case 0: xtmm::multipole<0>(q, prm, kx, ky); break;
+      case 1: xtmm::multipole<1>(q, prm, kx, ky); break;
+      case 2: xtmm::multipole<2>(q, prm, kx, ky); break;
+      case 3: xtmm::multipole<3>(q, prm, kx, ky); break;
+      case 4: xtmm::multipole<4>(q, prm, kx, ky); break;
+      case 5: xtmm::multipole<5>(q, prm, kx, ky); break;
+      case 6: xtmm::multipole<6>(q, prm, kx, ky); break;
+      case 7: xtmm::multipole<7>(q, prm, kx, ky); break;
+      case 8: xtmm::multipole<8>(q, prm, kx, ky); break;
+      case 9: xtmm::multipole<9>(q, prm, kx, ky); break;
+      default: xtmm::multipole<10>(q, prm, kx, ky); break;
+    }
+    return;
+  }
+  switch (ktype) {
+    case K_DRIFT:
+      ok = xtmm::drift_exact(q, prm[0]);
+      lost_state = -1;
+      break;
+    case K_AP_CIRC:
+      ok = xtmm::in_circle(q, prm[0]);
+      break;
+    case K_DRIFT_EXP:
+      xtmm::drift_expanded(q, prm[0]);
+      break;
+    case K_MULT_CURV: {
+      switch (order) {
+        case 0: xtmm::multipole<0>(q, prm, kx, ky); break;
+        case 1: xtmm::multipole<1>(q, prm, kx, ky); break;
+        case 2: xtmm::multipole<2>(q, prm, kx, ky); break;
+        case 3: xtmm::multipole<3>(q, prm, kx, ky); break;
+        case 4: xtmm::multipole<4>(q, prm, kx, ky); break;
+        case 5: xtmm::multipole<5>(q, prm, kx, ky); break;
+        case 6: xtmm::multipole<6>(q, prm, kx, ky); break;
+        case 7: xtmm::multipole<7>(q, prm, kx, ky); break;
+        case 8: xtmm::multipole<8>(q, prm, kx, ky); break;
+        case 9: xtmm::multipole<9>(q, prm, kx, ky); break;
+        default: xtmm::multipole<10>(q, prm, kx, ky); break;
+      }
+      const double* cv = prm + 2 * (order + 1);
+      xtmm::curvature(q, cv[0], cv[1], cv[2]);
+      break;
+    }
+    case K_RF:
+      xtmm::rf(q, prm[0], prm[1], prm[2], r.beta0, r.two_over_beta0);
+      break;
+    case K_SHIFT:
+      xtmm::xyshift(q, prm[0], prm[1]);
+      break;
+    case K_SROT:
+      xtmm::srotation(q, prm[0], prm[1]);
+      break;
+    case K_AP_ELL:
+      ok = xtmm::in_ellipse(q, prm[0], prm[1]);
+      break;
+    case K_AP_RECT:
+      ok = xtmm::in_rect(q, prm[0], prm[1], prm[2], prm[3]);
+      break;
+    default:
+      break;
+  }
+}
+
+__device__ __forceinline__ void load_pt(const SoA& P, int32_t p, xtmm::Pt& q, double beta0) {
+  q.x = P.x[p]; q.px = P.px[p]; q.y = P.y[p]; q.py = P.py[p]; q.zeta = P.zeta[p];
+  q.delta = P.delta[p]; q.ptau = P.ptau[p]; q.rpp = P.rpp[p]; q.rvv = P.rvv[p];
+  xtmm::refresh(q, beta0);
+}
+
+__device__ __forceinline__ void store_pt(const SoA& P, int32_t p, const xtmm::Pt& q) {
+  P.x[p] = q.x; P.px[p] = q.px; P.y[p] = q.y; P.py[p] = q.py; P.zeta[p] = q.zeta;
+  P.delta[p] = q.delta; P.ptau[p] = q.ptau; P.rpp[p] = q.rpp; P.rvv[p] = q.rvv;
+}
+
+__global__ void __launch_bounds__(256) k_track4(const uint64_t* __restrict__ tab, int32_t n_el,
+                                                SoA P, const int32_t* __restrict__ idx,
+                                                const int32_t* __restrict__ ctrl, int32_t n_turns,
+                                                int32_t backward, KernelRef r) {
+  const int32_t t0 = ctrl[1];
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool in_range = i < ctrl[0];
+  const int32_t p = in_range ? idx[i] : 0;
+  const bool tracked = in_range && P.state[p] == 1;
+  int code = tracked ? 0 : 1;  // 0: alive; else (turn * n_el + element + 1)
+  int st = 1;
+  if (__all(code != 0)) return;
+  xtmm::Pt q;
+  load_pt(P, p, q, r.beta0);
+  for (int32_t t = 0; t < n_turns; ++t) {
+    uint32_t off = 0;
+    const int enc0 = t * n_el + 1;
+    for (int32_t e = 0; e < n_el; ++e) {
+      off = __builtin_amdgcn_readfirstlane(off);
+      const uint64_t* w = tab + off;
+      const uint64_t h = w[0];
+      const double* __restrict__ prm = reinterpret_cast<const double*>(w + 1);
+      bool ok;
+      int ls;
+      apply_elem(q, (uint32_t)(h & 0xffu), (uint32_t)((h >> 8) & 0xffu), prm, r, ok, ls);
+      xtmm::mark(ok, code, st, enc0 + e, ls);
+      off += 1 + (uint32_t)((h >> 16) & 0xffffu);
+    }
+    if (__all(code != 0)) break;
+  }
+  if (!tracked) return;
+  if (code == 0) {
+    store_pt(P, p, q);
+    P.at_turn[p] = backward ? t0 - n_turns : t0 + n_turns;
+    P.at_element[p] = 0;
+  } else {
+    const int32_t tl = (code - 1) / n_el, el = (code - 1) - tl * n_el;
+    P.state[p] = st;
+    P.at_element[p] = backward ? n_el - 1 - el : el;
+    P.at_turn[p] = backward ? t0 - 1 - tl : t0 + tl;
+  }
+}
+
+// Re-track particles lost during the chunk from their chunk-start state up to
+// (not including) the element that lost them, and store those coordinates.
+__global__ void __launch_bounds__(256) k_replay(const uint64_t* __restrict__ tab, int32_t n_el,
+                                                SoA P, const int32_t* __restrict__ lost,
+                                                const int32_t* __restrict__ ctrl,
+                                                int32_t backward, KernelRef r) {
+  const int32_t t0 = ctrl[1];
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ctrl[3]) return;
+  const int32_t p = lost[i];
+  const int32_t at = P.at_turn[p], ae = P.at_element[p];
+  const int32_t tl = backward ? t0 - 1 - at : at - t0;
+  const int32_t el = backward ? n_el - 1 - ae : ae;
+  int64_t remaining = (int64_t)tl * n_el + el;
+  xtmm::Pt q;
+  load_pt(P, p, q, r.beta0);
+  for (int32_t t = 0; t <= tl && remaining > 0; ++t) {
+    uint32_t off = 0;
+    for (int32_t e = 0; e < n_el && remaining > 0; ++e, --remaining) {
+      const uint64_t* w = tab + off;
+      const uint64_t h = w[0];
+      bool ok;
+      int ls;
+      apply_elem(q, (uint32_t)(h & 0xffu), (uint32_t)((h >> 8) & 0xffu),
+                 reinterpret_cast<const double*>(w + 1), r, ok, ls);
+      off += 1 + (uint32_t)((h >> 16) & 0xffffu);
+    }
+  }
+  store_pt(P, p, q);
+}
+
 // -------------------------------------------------------- chunk epilogue
 // Block-wide exclusive scan of a 0/1 flag over kScanBlock threads (16 wave64s).
 __device__ __forceinline__ int32_t block_rank(bool flag, int32_t* s_wave, int32_t* total) {
@@ -607,7 +773,13 @@ __device__ __forceinline__ int32_t block_rank(bool flag, int32_t* s_wave, int32_
   return before + in_wave;
 }
 
-// Pass 1: per-block alive counts and the chunk's pass count.
+// Pass 1: per-block counts of (alive, lost during this chunk) and the
+// chunk's pass count.
+__device__ __forceinline__ bool lost_in_chunk(int32_t at, int32_t t0, int32_t chunk_turns,
+                                              int32_t backward) {
+  return backward ? (at <= t0 - 1 && at >= t0 - chunk_turns) : (at >= t0 && at < t0 + chunk_turns);
+}
+
 __global__ void __launch_bounds__(kScanBlock) k_count(const int32_t* __restrict__ idx, SoA P,
                                                       int32_t* ctrl, int32_t* blockcnt,
                                                       unsigned long long* passes, int32_t n_el,
@@ -617,7 +789,7 @@ __global__ void __launch_bounds__(kScanBlock) k_count(const int32_t* __restrict_
   __shared__ unsigned long long s_pass[kScanBlock / 64];
   const int32_t n_alive = ctrl[0];
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  bool alive = false;
+  bool alive = false, gone = false;
   int64_t np = 0;
   if (i < n_alive) {
     const int32_t p = idx[i];
@@ -627,57 +799,83 @@ __global__ void __launch_bounds__(kScanBlock) k_count(const int32_t* __restrict_
       np = (int64_t)chunk_turns * n_el;
     } else {
       const int32_t at = P.at_turn[p], ae = P.at_element[p];
-      if (!backward && at >= t0 && at < t0 + chunk_turns)
-        np = (int64_t)(at - t0) * n_el + ae + 1;
-      else if (backward && at <= t0 - 1 && at >= t0 - chunk_turns)
-        np = (int64_t)(t0 - 1 - at) * n_el + (n_el - ae);
+      gone = lost_in_chunk(at, t0, chunk_turns, backward);
+      if (gone)
+        np = backward ? (int64_t)(t0 - 1 - at) * n_el + (n_el - ae)
+                      : (int64_t)(at - t0) * n_el + ae + 1;
     }
   }
-  int32_t total;
-  block_rank(alive, s_wave, &total);
-  // wave-level sum of passes, then one atomic per block
+  int32_t total_alive, total_gone;
+  block_rank(alive, s_wave, &total_alive);
+  __syncthreads();
+  block_rank(gone, s_wave, &total_gone);
   unsigned long long v = (unsigned long long)np;
   for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
   if ((threadIdx.x & 63) == 0) s_pass[threadIdx.x >> 6] = v;
   __syncthreads();
   if (threadIdx.x == 0) {
-    unsigned long long s = 0;
-    for (int k = 0; k < (int)(blockDim.x >> 6); ++k) s += s_pass[k];
-    if (s) atomicAdd(passes, s);
-    blockcnt[blockIdx.x] = total;
+    unsigned long long sum = 0;
+    for (int k = 0; k < (int)(blockDim.x >> 6); ++k) sum += s_pass[k];
+    if (sum) atomicAdd(passes, sum);
+    blockcnt[2 * blockIdx.x] = total_alive;
+    blockcnt[2 * blockIdx.x + 1] = total_gone;
     if (blockIdx.x == 0) ctrl[2] = n_alive;  // count this epilogue scanned
   }
 }
 
-// Pass 2: order-preserving scatter of alive entries; the last block writes
-// the new alive count.  Reads the old count from ctrl[2] (set by pass 1) so
-// the write of ctrl[0] cannot race with any reader of this launch.
+// Pass 2: order-preserving scatter of the alive entries (into idx_out, if
+// given) and of the entries lost during the chunk (into lost_out); the last
+// block writes the new alive count (ctrl[0]) and the lost count (ctrl[3]).
+// It reads the old count from ctrl[2] (set by pass 1), so writing ctrl[0]
+// cannot race with a reader of this launch.
 __global__ void __launch_bounds__(kScanBlock) k_scatter(const int32_t* __restrict__ idx_in,
-                                                        int32_t* __restrict__ idx_out, SoA P,
+                                                        int32_t* __restrict__ idx_out,
+                                                        int32_t* __restrict__ lost_out, SoA P,
                                                         int32_t* ctrl,
-                                                        const int32_t* __restrict__ blockcnt) {
+                                                        const int32_t* __restrict__ blockcnt,
+                                                        int32_t chunk_turns, int32_t backward) {
   __shared__ int32_t s_wave[kScanBlock / 64];
-  __shared__ int32_t s_red[kScanBlock / 64];
+  __shared__ int32_t s_red[2][kScanBlock / 64];
   const int32_t n_old = ctrl[2];
+  const int32_t t0 = ctrl[1];
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  // offset = sum of the counts of the preceding blocks
-  int32_t part = 0;
-  for (int32_t b = threadIdx.x; b < (int32_t)blockIdx.x; b += blockDim.x) part += blockcnt[b];
-  for (int off = 32; off > 0; off >>= 1) part += __shfl_down(part, off, 64);
-  if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = part;
+  int32_t part_a = 0, part_g = 0;
+  for (int32_t b = threadIdx.x; b < (int32_t)blockIdx.x; b += blockDim.x) {
+    part_a += blockcnt[2 * b];
+    part_g += blockcnt[2 * b + 1];
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    part_a += __shfl_down(part_a, off, 64);
+    part_g += __shfl_down(part_g, off, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    s_red[0][threadIdx.x >> 6] = part_a;
+    s_red[1][threadIdx.x >> 6] = part_g;
+  }
   __syncthreads();
-  int32_t offset = 0;
-  for (int k = 0; k < (int)(blockDim.x >> 6); ++k) offset += s_red[k];
-  bool alive = false;
+  int32_t off_a = 0, off_g = 0;
+  for (int k = 0; k < (int)(blockDim.x >> 6); ++k) {
+    off_a += s_red[0][k];
+    off_g += s_red[1][k];
+  }
+  bool alive = false, gone = false;
   int32_t p = 0;
   if (i < n_old) {
     p = idx_in[i];
-    alive = (P.state[p] == 1);
+    const int32_t st = P.state[p];
+    alive = (st == 1);
+    gone = !alive && lost_in_chunk(P.at_turn[p], t0, chunk_turns, backward);
   }
-  int32_t total;
-  const int32_t rank = block_rank(alive, s_wave, &total);
-  if (alive) idx_out[offset + rank] = p;
-  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) ctrl[0] = offset + total;
+  int32_t total_a, total_g;
+  const int32_t rank_a = block_rank(alive, s_wave, &total_a);
+  __syncthreads();
+  const int32_t rank_g = block_rank(gone, s_wave, &total_g);
+  if (alive && idx_out) idx_out[off_a + rank_a] = p;
+  if (gone) lost_out[off_g + rank_g] = p;
+  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) {
+    if (idx_out) ctrl[0] = off_a + total_a;
+    ctrl[3] = off_g + total_g;
+  }
 }
 
 // ------------------------------------------------------------- launchers
@@ -713,7 +911,10 @@ hipError_t launch_track(const uint64_t* tab, const int32_t* seg, int32_t n_seg, 
                         int32_t block, int32_t n_turns, int32_t backward, KernelRef r,
                         int32_t variant, hipStream_t s) {
   if (grid_upper <= 0 || n_turns <= 0) return hipSuccess;
-  if (variant == 3)
+  if (variant == 4)
+    hipLaunchKernelGGL(k_track4, dim3(blocks_for(grid_upper, block)), dim3(block), 0, s, tab, n_el,
+                       P, idx, ctrl, n_turns, backward, r);
+  else if (variant == 3)
     hipLaunchKernelGGL(k_track3<kSegWords>, dim3(blocks_for(grid_upper, block)), dim3(block), 0,
                        s, tab, seg, n_seg, n_el, P, idx, ctrl, n_turns, backward, r);
   else if (variant == 1)
@@ -725,17 +926,27 @@ hipError_t launch_track(const uint64_t* tab, const int32_t* seg, int32_t n_seg, 
   return hipGetLastError();
 }
 
-hipError_t launch_epilogue(const int32_t* idx_in, int32_t* idx_out, int64_t grid_upper, SoA P,
-                           int32_t* ctrl, int32_t* blockcnt, int64_t* passes, int32_t n_el,
-                           int32_t chunk_turns, int32_t backward, hipStream_t s) {
+hipError_t launch_epilogue(const int32_t* idx_in, int32_t* idx_out, int32_t* lost_out,
+                           int64_t grid_upper, SoA P, int32_t* ctrl, int32_t* blockcnt,
+                           int64_t* passes, int32_t n_el, int32_t chunk_turns, int32_t backward,
+                           hipStream_t s) {
   if (grid_upper <= 0) return hipSuccess;
   const unsigned nb = blocks_for(grid_upper, kScanBlock);
   hipLaunchKernelGGL(k_count, dim3(nb), dim3(kScanBlock), 0, s, idx_in, P, ctrl, blockcnt,
                      reinterpret_cast<unsigned long long*>(passes), n_el, chunk_turns, backward);
   hipError_t e = hipGetLastError();
-  if (e != hipSuccess || idx_out == nullptr) return e;
-  hipLaunchKernelGGL(k_scatter, dim3(nb), dim3(kScanBlock), 0, s, idx_in, idx_out, P, ctrl,
-                     blockcnt);
+  if (e != hipSuccess || (idx_out == nullptr && lost_out == nullptr)) return e;
+  hipLaunchKernelGGL(k_scatter, dim3(nb), dim3(kScanBlock), 0, s, idx_in, idx_out, lost_out, P,
+                     ctrl, blockcnt, chunk_turns, backward);
+  return hipGetLastError();
+}
+
+hipError_t launch_replay(const uint64_t* tab, int32_t n_el, SoA P, const int32_t* lost,
+                         const int32_t* ctrl, int64_t grid_upper, int32_t backward, KernelRef r,
+                         hipStream_t s) {
+  if (grid_upper <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_replay, dim3(blocks_for(grid_upper, 256)), dim3(256), 0, s, tab, n_el, P,
+                     lost, ctrl, backward, r);
   return hipGetLastError();
 }
 

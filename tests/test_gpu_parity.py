@@ -143,6 +143,8 @@ def test_resume_bitwise(P):
 @pytest.mark.parametrize("opts", [dict(turns_per_chunk=1), dict(turns_per_chunk=7, block=64),
                                   dict(variant=1), dict(variant=1, turns_per_chunk=13),
                                   dict(variant=3), dict(variant=3, block=64, turns_per_chunk=9),
+                                  dict(variant=4), dict(variant=4, turns_per_chunk=3, block=128),
+                                  dict(variant=2, turns_per_chunk=11),
                                   dict(turns_per_chunk=100, block=128, compact=False),
                                   dict(turns_per_chunk=33, block=192)])
 def test_launch_shape_invariance(P, opts):
@@ -240,7 +242,7 @@ def test_cfg2_lattice_reduced(P, oracle_mod):
     assert gp == op
 
 
-@pytest.mark.parametrize("variant", [1, 3])
+@pytest.mark.parametrize("variant", [1, 2, 3, 4])
 def test_kernel_variants_on_multisegment_lattice(P, variant):
     """The 20,000-element lattice spans many LDS segments: every kernel variant
     must give bitwise the same result as the default one."""
@@ -283,3 +285,17 @@ def test_empty_lattice_counts_turns(P, oracle_mod):
     o, op = oracle_run(oracle_mod, I.line([]), REF, c, 10)
     assert gp == op == 0 and ga == 8
     assert np.array_equal(g["at_turn"], o.at_turn) and np.all(o.at_turn == 10)
+
+
+def test_line_kernel_unavailable_for_irregular_lattice(P):
+    """An irregular 200-element line has no compact cell structure: asking for
+    the per-line kernel explicitly is an error, the default falls back."""
+    el = random_lattice(1)
+    c = np.zeros((64, 6))
+    lat = P.Lattice(el, REF)
+    parts = P.Particles(64, REF).init(c)
+    with pytest.raises(P.XtmError) as ei:
+        P.track(lat, parts, 1, variant=5)
+    assert ei.value.code == -6
+    P.track(lat, parts, 1)
+    assert parts.turn == 1
