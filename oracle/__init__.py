@@ -52,6 +52,12 @@ def lib():
         L.oracle_track_backward.restype = ctypes.c_int64
         L.oracle_init.restype = ctypes.c_int
         L.oracle_track_canonical.restype = ctypes.c_int
+        L.oracle_track_rad.restype = ctypes.c_int64
+        L.oracle_uniform.restype = ctypes.c_double
+        L.oracle_uniform.argtypes = [ctypes.c_uint32, ctypes.c_uint32]
+        L.oracle_gauss_at.restype = ctypes.c_double
+        L.oracle_gauss_at.argtypes = [ctypes.c_uint64, ctypes.c_int64, ctypes.c_int32,
+                                      ctypes.c_int32, ctypes.c_int32]
         _lib = L
     return _lib
 
@@ -129,15 +135,19 @@ def init(coords6, ref, first_id: int = 0) -> Particles:
     return p
 
 
-def track(elements, ref, parts: Particles, n_turns: int, nthreads: int = 0) -> int:
-    """Forward tracking in place from turn ``parts.turn``; returns passes."""
+def track(elements, ref, parts: Particles, n_turns: int, nthreads: int = 0,
+          radiation: int = 0, seed: int = 0) -> int:
+    """Forward tracking in place from turn ``parts.turn``; returns passes.
+    radiation: 0 off, 1 mean energy loss, 2 mean + Gaussian quantum excitation
+    (Philox stream keyed by ``seed``, counter (particle id, turn, element))."""
     el = _els(elements)
     r = _ref3(ref)
     s = parts._struct()
-    passes = lib().oracle_track(el.ctypes.data_as(ctypes.c_void_p), ctypes.c_int32(len(el)),
-                                r.ctypes.data_as(ctypes.c_void_p), ctypes.byref(s),
-                                ctypes.c_int32(parts.turn), ctypes.c_int32(n_turns),
-                                ctypes.c_int32(nthreads))
+    passes = lib().oracle_track_rad(el.ctypes.data_as(ctypes.c_void_p), ctypes.c_int32(len(el)),
+                                    r.ctypes.data_as(ctypes.c_void_p), ctypes.byref(s),
+                                    ctypes.c_int32(parts.turn), ctypes.c_int32(n_turns),
+                                    ctypes.c_int32(nthreads), ctypes.c_int32(radiation),
+                                    ctypes.c_uint64(seed))
     if passes < 0:
         raise ValueError("oracle_track rejected its input (code %d)" % passes)
     parts.turn += n_turns
@@ -249,3 +259,36 @@ def regular_mask(elements, ref, coords6, n_turns: int = 100, rtol: float = 1e-13
         sc = np.zeros(6)
     err = np.abs(ca - cb) / np.maximum(np.abs(ca), sc[None, :])
     return ok & np.all(err <= rtol, axis=1)
+
+
+# ------------------------------------------------------------------ RNG
+def philox(ctr, key) -> np.ndarray:
+    """One Philox4x32-10 block: 4 words from a 4-word counter and 2-word key."""
+    c = (ctypes.c_uint32 * 4)(*[int(v) & 0xFFFFFFFF for v in ctr])
+    k = (ctypes.c_uint32 * 2)(*[int(v) & 0xFFFFFFFF for v in key])
+    o = (ctypes.c_uint32 * 4)()
+    lib().oracle_philox4x32_10(c, k, o)
+    return np.array(list(o), dtype=np.uint32)
+
+
+def philox_stream(seed: int, ctr0, n_blocks: int) -> np.ndarray:
+    """n_blocks consecutive blocks from counter ctr0 (128-bit increment), key = seed."""
+    out = np.zeros(4 * n_blocks, dtype=np.uint32)
+    c = (ctypes.c_uint32 * 4)(*[int(v) & 0xFFFFFFFF for v in ctr0])
+    lib().oracle_philox_stream(ctypes.c_uint64(seed), c, ctypes.c_int64(n_blocks),
+                               out.ctypes.data_as(ctypes.c_void_p))
+    return out
+
+
+def philox_constants() -> np.ndarray:
+    o = (ctypes.c_uint32 * 4)()
+    lib().oracle_philox_constants(o)
+    return np.array(list(o), dtype=np.uint32)
+
+
+def uniform(wa: int, wb: int) -> float:
+    return float(lib().oracle_uniform(wa, wb))
+
+
+def gauss_at(seed: int, pid: int, turn: int, element: int, draw: int = 0) -> float:
+    return float(lib().oracle_gauss_at(seed, pid, turn, element, draw))

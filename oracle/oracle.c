@@ -550,3 +550,13 @@ double oracle_gauss_at(uint64_t seed, int64_t pid, int32_t turn, int32_t element
   oracle_philox4x32_10(ctr, key, w);
   return oracle_gauss(w);
 }
+
+/* the four Philox constants as used above: multipliers M0, M1 and the Weyl
+   key increments W0, W1 (exposed so tests can check the increments against
+   their closed forms) */
+void oracle_philox_constants(uint32_t out[4]) {
+  out[0] = O_PHILOX_M0;
+  out[1] = O_PHILOX_M1;
+  out[2] = O_PHILOX_W0;
+  out[3] = O_PHILOX_W1;
+}

@@ -401,3 +401,52 @@ def cfg3_counts(n_variants: int = 64, seed: int = 3003) -> np.ndarray:
 def cfg3_variant(v: int, n: int, lattice_seed_base: int = 30000,
                  particle_seed_base: int = 31000):
     return errored_cfg1_lattice(lattice_seed_base + v), gaussian_particles(n, particle_seed_base + v)
+
+
+# cfg5: electron ring for synchrotron radiation.  n_cells x [QF, SF, AP, D/2,
+# B, D/2, QD, SD, AP, D/2, B, D/2] with thin bends B (hxl = knl0 = theta over
+# the radiation length Lr) and n_rf RF cavities placed before the QF of evenly
+# spaced cells.  Lr is fixed so that the design energy loss per turn is
+# about u0_over_e0 of the beam energy (values below were chosen for
+# u0_over_e0 = 1e-3 with 1666 cells and 1e-2 with 100 cells); the RF voltage is
+# 3 x U0, phased for electrons (charge -1) at lag = -asin(U0/V).
+CFG5_CELLS = 1666
+CFG5_LR = {1666: 15.817206401282936, 100: 26.351465864537374}
+CFG5_U0_OVER_E0 = {1666: 1e-3, 100: 1e-2}
+
+
+def cfg5_lattice(n_cells: int = CFG5_CELLS, n_rf: int = 8, rf_factor: float = 3.0,
+                 sextupoles: bool = True, apertures: bool = True) -> np.ndarray:
+    ref = ELECTRON_45GEV6
+    e0 = math.sqrt(ref.p0c_eV ** 2 + ref.mass0_eV ** 2)
+    u0 = CFG5_U0_OVER_E0[n_cells] * e0
+    v_tot = rf_factor * u0
+    lag = -math.degrees(math.asin(u0 / v_tot))
+    theta = 2 * math.pi / (2 * n_cells)
+    lr = CFG5_LR[n_cells]
+    k = 1.0 / CFG1_F
+    bend = multipole(knl=[theta], hxl=theta, length=lr)
+    rf_cells = set(int(j * n_cells / n_rf) for j in range(n_rf))
+    els = []
+    for c in range(n_cells):
+        if c in rf_cells:
+            els.append(rf(v_tot / n_rf, 400e6, lag))
+        els += [
+            multipole(knl=[0.0, k]),
+            multipole(knl=[0.0, 0.0, CFG1_K2L]) if sextupoles else marker(),
+            ap_circle(CFG1_APERTURE) if apertures else marker(),
+            drift(CFG1_HALF / 2), bend.copy(), drift(CFG1_HALF / 2),
+            multipole(knl=[0.0, -k]),
+            multipole(knl=[0.0, 0.0, -CFG1_K2L]) if sextupoles else marker(),
+            ap_circle(CFG1_APERTURE) if apertures else marker(),
+            drift(CFG1_HALF / 2), bend.copy(), drift(CFG1_HALF / 2),
+        ]
+    return line(els)
+
+
+CFG5_SIGMAS = np.array([1e-4, 1e-6, 1e-5, 1e-7, 3e-3, 4e-4])
+
+
+def cfg5_particles(n: int = 1_000_000, seed: int = 50505) -> np.ndarray:
+    """6D Gaussian electrons with roughly equilibrium-sized sigmas."""
+    return gaussian_particles(n, seed, CFG5_SIGMAS)
