@@ -169,6 +169,12 @@ typedef struct xtm_track_opts {
                               5 = per-line kernel generated from the lattice's cell
                               structure and compiled at first use (as 4 for losses);
                               XTM_E_UNSUPPORTED if it cannot be built */
+  int32_t radiation;       /* synchrotron radiation in multipoles with length > 0:
+                              0 off, 1 mean energy loss, 2 mean + quantum excitation
+                              (Gaussian, see below); forward tracking with the
+                              default, 4 or 5 kernels only */
+  int32_t reserved;
+  uint64_t rng_seed;       /* key of the quantum-excitation deviates */
 } xtm_track_opts;
 
 typedef struct xtm_track_stats {
@@ -201,6 +207,21 @@ xtm_status xtm_track_backward(xtm_lattice lat, xtm_particles p, int32_t n_turns,
    NULL).  Synchronises the stream. */
 xtm_status xtm_get_losses(xtm_particles p, int32_t* h_state, int32_t* h_at_turn,
                           int32_t* h_at_element, void* stream);
+
+/* Raw Philox4x32-10 stream (Salmon et al., SC'11, "Parallel random numbers:
+   as easy as 1, 2, 3"): block j (0 <= j < n_blocks) is the 4-word output for
+   counter ctr0 + j (128-bit increment, ctr0 in host memory, word 0 least
+   significant) and key (seed_lo, seed_hi), written to d_out[4j .. 4j+3]
+   (device memory).  Radiation (paper section "Synchrotron radiation models
+   and compensation") draws its Gaussians from this generator: counter
+   (particle_id_lo, particle_id_hi, turn, element * 8), uniforms
+   u = ((w_a << 20 | w_b >> 12) + 1/2) 2^-52 from words (0,1) and (2,3), and
+   g = sqrt(-2 ln u1) cos(2 pi u2).  Mean radiation loss of a multipole of
+   length Lr with field kick k: dE = (2/3) r m gamma^4 h^2 Lr, h = |k| rpp / Lr;
+   quantum part sqrt(55/(24 sqrt 3) r m hbar_c gamma^7 |h|^3 Lr) g.
+   Stream-ordered. */
+xtm_status xtm_philox4x32_10(uint64_t seed, const uint32_t ctr0[4], int64_t n_blocks,
+                             uint32_t* d_out, void* stream);
 
 /* Synchronise the stream and report any asynchronous device error. */
 xtm_status xtm_sync(void* stream);

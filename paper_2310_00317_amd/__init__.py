@@ -46,7 +46,9 @@ class _Arrays(ctypes.Structure):
 class TrackOpts(ctypes.Structure):
     _fields_ = [("turns_per_chunk", ctypes.c_int32), ("block", ctypes.c_int32),
                 ("no_compact", ctypes.c_int32), ("use_graph", ctypes.c_int32),
-                ("time_kernels", ctypes.c_int32), ("variant", ctypes.c_int32)]
+                ("time_kernels", ctypes.c_int32), ("variant", ctypes.c_int32),
+                ("radiation", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("rng_seed", ctypes.c_uint64)]
 
 
 class TrackStats(ctypes.Structure):
@@ -82,6 +84,7 @@ def lib() -> ctypes.CDLL:
             "xtm_track_backward": ([vp, vp, i32, vp, vp], i32),
             "xtm_get_losses": ([vp, vp, vp, vp, vp], i32),
             "xtm_sync": ([vp], i32),
+            "xtm_philox4x32_10": ([ctypes.c_uint64, vp, i64, vp, vp], i32),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -236,11 +239,12 @@ class Particles:
 
 def track(lattice: Lattice, particles: Particles, n_turns: int, turns_per_chunk: int = 0,
           block: int = 0, compact: bool = True, graph: bool = False, stats: bool = True,
-          time_kernels: bool = False, variant: int = 0, stream=None, full_stats: bool = False):
+          time_kernels: bool = False, variant: int = 0, radiation: int = 0, seed: int = 0,
+          stream=None, full_stats: bool = False):
     """Track ``n_turns`` forward.  With ``stats`` (synchronising) returns
     (passes, alive), or the whole TrackStats if ``full_stats``."""
     o = TrackOpts(int(turns_per_chunk), int(block), 0 if compact else 1, 1 if graph else 0,
-                  1 if time_kernels else 0, int(variant))
+                  1 if time_kernels else 0, int(variant), int(radiation), 0, int(seed))
     s = TrackStats()
     check(lib().xtm_track(lattice.handle, particles.handle, int(n_turns), ctypes.byref(o),
                           _stream(stream), ctypes.byref(s) if (stats or full_stats) else None),
@@ -260,3 +264,13 @@ def track_backward(lattice: Lattice, particles: Particles, n_turns: int, stats: 
 
 def sync(stream=None):
     check(lib().xtm_sync(_stream(stream)), "xtm_sync")
+
+
+def philox(seed: int, ctr0, n_blocks: int, stream=None):
+    """Raw Philox4x32-10 words (torch uint32-as-int32 tensor of 4 n_blocks) on the GPU."""
+    import torch
+    out = torch.empty(max(4 * int(n_blocks), 1), dtype=torch.int32, device="cuda")
+    c = (ctypes.c_uint32 * 4)(*[int(v) & 0xFFFFFFFF for v in ctr0])
+    check(lib().xtm_philox4x32_10(int(seed), c, int(n_blocks), ctypes.c_void_p(out.data_ptr()),
+                                  _stream(stream)), "xtm_philox4x32_10")
+    return out[: 4 * int(n_blocks)]

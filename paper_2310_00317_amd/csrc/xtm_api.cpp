@@ -73,12 +73,14 @@ struct xtm_lattice_s {
 
 struct GraphKey {
   const void* lat;
-  int32_t n_turns, chunk, block, variant, backward, compact, cur;
+  int32_t n_turns, chunk, block, variant, backward, compact, cur, rad_mode;
   int64_t alive_upper;
+  uint64_t seed;
   bool operator==(const GraphKey& o) const {
     return lat == o.lat && n_turns == o.n_turns && chunk == o.chunk && block == o.block &&
            variant == o.variant && backward == o.backward && compact == o.compact &&
-           cur == o.cur && alive_upper == o.alive_upper;
+           cur == o.cur && rad_mode == o.rad_mode && alive_upper == o.alive_upper &&
+           seed == o.seed;
   }
 };
 
@@ -133,9 +135,12 @@ xtm_status pack(const xtm_element_desc& e, int32_t index, const RefQ& r, double 
     case XTM_MULTIPOLE: {
       if (e.order < 0 || e.order > XTM_MAX_ORDER)
         return fail(XTM_E_ELEMENT, where + "multipole order outside 0..10");
+      if (!std::isfinite(e.length)) return fail(XTM_E_ELEMENT, where + "non-finite multipole length");
       const bool curv = (e.hxl != 0.0);
+      const bool has_len = e.length > 0.0;  // radiation length
       const uint32_t N = (uint32_t)e.order;
-      hdr(curv ? K_MULT_CURV : K_MULT, N, 2 * (N + 1) + (curv ? 3 : 0));
+      hdr(curv ? K_MULT_CURV : (has_len ? K_MULT_LR : K_MULT), N,
+          2 * (N + 1) + (curv ? 3 : (has_len ? 1 : 0)));
       // c_n = (knl_n + i ksl_n)/n!, stored from the top order down
       double fact[XTM_MAX_ORDER + 1];
       fact[0] = 1.0;
@@ -149,6 +154,8 @@ xtm_status pack(const xtm_element_desc& e, int32_t index, const RefQ& r, double 
       if (curv) {
         put_d(out, sgn * e.hxl);
         put_d(out, sgn * (e.knl[0] * e.hxl));
+        put_d(out, e.length);
+      } else if (has_len) {
         put_d(out, e.length);
       }
       return XTM_OK;
@@ -236,10 +243,24 @@ SoA soa_of(const xtm_particles_s* p) {
   return s;
 }
 
-KernelRef kref(const RefQ& r) {
+// CODATA 2018, the same data the oracle and the input generators use
+constexpr double kRElectron = 2.8179403262e-15;  // m
+constexpr double kMElectronEV = 0.51099895000e6;
+constexpr double kHbarCEVM = 197.3269804e-9;     // eV m
+
+KernelRef kref(const RefQ& r, int32_t rad_mode = 0, uint64_t seed = 0) {
   KernelRef k;
   k.beta0 = r.beta0;
   k.two_over_beta0 = 2.0 / r.beta0;
+  k.gamma0 = r.gamma0;
+  // classical radius of the tracked species, scaled from the electron's
+  const double rclass = kRElectron * (kMElectronEV / r.mass0) * r.charge0 * r.charge0;
+  k.c_mean = 2.0 / 3.0 * rclass * r.mass0;
+  k.c_quant = 55.0 / (24.0 * std::sqrt(3.0)) * rclass * r.mass0 * kHbarCEVM;
+  k.p0c = r.p0c;
+  k.seed = seed;
+  k.rad_mode = rad_mode;
+  k.pad = 0;
   return k;
 }
 
@@ -266,6 +287,8 @@ int32_t auto_chunk(int64_t n, int32_t n_el, int32_t n_turns) {
 }
 
 struct ChunkPlan {
+  int32_t rad_mode;
+  uint64_t seed;
   const LineKernel* line;  // variant 5
   const uint64_t* tab;
   const int32_t* seg;
@@ -281,7 +304,7 @@ struct ChunkPlan {
 hipError_t enqueue_chunks(xtm_lattice_s* L, xtm_particles_s* P, const ChunkPlan& c, int32_t cur,
                           hipStream_t s, std::vector<hipEvent_t>* ev, int32_t* launches) {
   const SoA soa = soa_of(P);
-  const KernelRef kr = kref(L->ref);
+  const KernelRef kr = kref(L->ref, c.rad_mode, c.seed);
   int32_t done = 0;
   *launches = 0;
   if (P->alive_upper <= 0) return c.n_turns > 0 ? launch_advance(P->ctrl, c.backward ? -c.n_turns : c.n_turns, s) : hipSuccess;
@@ -332,7 +355,7 @@ int32_t flips(const ChunkPlan& c) {
 xtm_status run_graph(xtm_lattice_s* L, xtm_particles_s* P, const ChunkPlan& c, hipStream_t s,
                      int32_t* launches) {
   GraphKey key{L, c.n_turns, c.chunk, c.block, c.variant, c.backward ? 1 : 0, c.compact ? 1 : 0,
-               P->cur, P->alive_upper};
+               P->cur, c.rad_mode, P->alive_upper, c.seed};
   for (const GraphEntry& g : P->graphs) {
     if (g.key == key) {
       HIP_TRY(hipGraphLaunch(g.exec, s), "graph launch");
@@ -379,6 +402,10 @@ xtm_status run_turns(xtm_lattice_s* L, xtm_particles_s* P, int32_t n_turns,
   if (backward && P->turn - n_turns < INT32_MIN / 2) return fail(XTM_E_ARG, "turn underflow");
   if (!backward && (int64_t)P->turn + n_turns > INT32_MAX / 2) return fail(XTM_E_ARG, "turn overflow");
   ChunkPlan c;
+  c.rad_mode = o ? o->radiation : 0;
+  c.seed = o ? o->rng_seed : 0;
+  if (c.rad_mode < 0 || c.rad_mode > 2) return fail(XTM_E_ARG, "radiation must be 0, 1 or 2");
+  if (c.rad_mode && backward) return fail(XTM_E_ARG, "backward tracking with radiation is undefined");
   c.block = (o && o->block) ? o->block : 256;
   if (c.block < 64 || c.block > 256 || c.block % 64)
     return fail(XTM_E_ARG, "block must be 64, 128, 192 or 256");
@@ -386,6 +413,8 @@ xtm_status run_turns(xtm_lattice_s* L, xtm_particles_s* P, int32_t n_turns,
   c.variant = (o && o->variant) ? o->variant : 0;
   if (c.variant < 0 || c.variant > 5) return fail(XTM_E_ARG, "kernel variant must be 0..5");
   c.line = nullptr;
+  if (c.rad_mode && c.variant >= 1 && c.variant <= 3)
+    return fail(XTM_E_UNSUPPORTED, "kernel variants 1-3 do not implement radiation");
   if (c.variant == 0 || c.variant == 5) {
     // the per-line kernel, compiled on first use; the default falls back to
     // the register-loss interpreter if the line has no compact cell structure
@@ -680,6 +709,15 @@ xtm_status xtm_get_losses(xtm_particles P, int32_t* h_state, int32_t* h_at_turn,
     HIP_TRY(hipStreamSynchronize(s), "synchronise");
     return XTM_OK;
   });
+}
+
+xtm_status xtm_philox4x32_10(uint64_t seed, const uint32_t ctr0[4], int64_t n_blocks,
+                             uint32_t* d_out, void* stream) {
+  if (n_blocks < 0 || !ctr0 || (n_blocks > 0 && !d_out)) return fail(XTM_E_ARG, "bad arguments");
+  if (n_blocks > (int64_t)1 << 40) return fail(XTM_E_ARG, "too many blocks");
+  hipError_t e = launch_philox(seed, ctr0, n_blocks, d_out, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "philox launch");
+  return XTM_OK;
 }
 
 xtm_status xtm_sync(void* stream) {

@@ -22,6 +22,7 @@ enum KType : uint32_t {
   K_DRIFT_EXP = 2,
   K_MULT = 3,       // coefficients only:  cr_N, ci_N, ..., cr_0, ci_0
   K_MULT_CURV = 4,  // coefficients, then hxl, knl0*hxl, Lr
+  K_MULT_LR = 12,   // coefficients, then Lr (radiation length, no frame curvature)
   K_RF = 5,         // amp = charge0 V / p0c, k = 2 pi f / (beta0 c), phase [rad]
   K_SHIFT = 6,      // dx, dy
   K_SROT = 7,       // cos, sin
@@ -43,9 +44,18 @@ struct SoA {
   int64_t* pid;
 };
 
+// Reference quantities and per-call radiation settings passed by value to
+// every tracking kernel (the generated line kernels declare the same layout).
 struct KernelRef {
   double beta0;
   double two_over_beta0;
+  double gamma0;
+  double c_mean;   // (2/3) r m                     [eV m], r = classical radius
+  double c_quant;  // 55/(24 sqrt 3) r m hbar_c      [eV^2 m^2]
+  double p0c;
+  unsigned long long seed;
+  int32_t rad_mode;  // 0 off, 1 mean, 2 mean + quantum
+  int32_t pad;
 };
 
 // launch helpers implemented in xtm_kernels.hip; all are stream-ordered
@@ -84,9 +94,9 @@ struct LineKernel {
   bool ok = false;
   bool tried = false;
   hipFunction_t fn = nullptr;
-  int32_t period = 0, n_cells = 0, n_kinds = 0;
+  int32_t period = 0, n_cells = 0, n_kinds = 0;  // period = length of the repeating unit
   double* prm_d = nullptr;     // element parameters in element order, no headers
-  int32_t* cells_d = nullptr;  // per cell: kind, offset of its first parameter, word count
+  int32_t* cells_d = nullptr;  // per cell: kind, first parameter word, first element, words
   std::string source;
   std::string error;
 };
@@ -97,3 +107,8 @@ hipError_t launch_line(const LineKernel& k, int32_t n_el, SoA P, const int32_t* 
                        int32_t backward, KernelRef r, hipStream_t s);
 
 }  // namespace xtm
+
+namespace xtm {
+hipError_t launch_philox(unsigned long long seed, const uint32_t ctr0[4], int64_t n_blocks,
+                         uint32_t* out, hipStream_t s);
+}

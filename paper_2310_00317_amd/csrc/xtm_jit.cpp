@@ -44,44 +44,68 @@ std::map<std::string, Compiled> g_cache;  // generated source -> compiled kernel
 uint32_t sig_of(uint64_t h) { return (uint32_t)(h & 0xffffu); }  // kernel type | order << 8
 
 struct Decomp {
-  int32_t period = 0;
   std::vector<std::vector<uint32_t>> kinds;  // element signatures of each kind
-  std::vector<int32_t> cell_kind;
+  std::vector<int32_t> cell_kind;            // kind of each cell, in line order
+  std::vector<int32_t> cell_start;           // first element index of each cell
 };
 
-// Choose the period P (1..128) with the fewest cells per turn whose distinct
-// cell signatures need at most kMaxCode elements of generated code.
-constexpr int kMaxCode = 24;
+// Cover the line with cells: a repeating unit U of P elements wherever it
+// matches, and the stretches in between ("gaps", e.g. a lone RF cavity or a
+// cell whose sextupole slot holds a cavity) as further kinds, split into
+// pieces of at most kMaxUnit elements.  Among all units (P <= kMaxUnit,
+// every phase) keep the cover with the fewest cells whose distinct kinds
+// need at most kMaxCode elements of generated code.
+constexpr int kMaxUnit = 24;
+constexpr int kMaxCode = 48;
 
 bool decompose(const std::vector<uint32_t>& sig, Decomp* out) {
   const int32_t E = (int32_t)sig.size();
   if (E == 0) return false;
-  int64_t best_cells = -1;
-  for (int32_t P = 1; P <= 128 && P <= E; ++P) {
-    const int32_t n_cells = (E + P - 1) / P;
-    std::map<std::vector<uint32_t>, int32_t> kinds;
-    int32_t code = 0;
-    bool too_big = false;
-    for (int32_t c = 0; c < n_cells && !too_big; ++c) {
-      std::vector<uint32_t> t(sig.begin() + (size_t)c * P,
-                              sig.begin() + std::min<size_t>((size_t)(c + 1) * P, (size_t)E));
-      if (kinds.find(t) == kinds.end()) {
-        code += (int32_t)t.size();
-        kinds.emplace(t, (int32_t)kinds.size());
-        if (code > kMaxCode) too_big = true;
+  size_t best_cells = 0;
+  int32_t best_code = 0;
+  for (int32_t P = 1; P <= kMaxUnit && P <= E; ++P) {
+    for (int32_t o = 0; o < P && o + P <= E; ++o) {
+      const uint32_t* U = &sig[o];
+      std::map<std::vector<uint32_t>, int32_t> kinds;
+      kinds.emplace(std::vector<uint32_t>(U, U + P), 0);
+      int32_t code = P;
+      Decomp d;
+      d.kinds.push_back(std::vector<uint32_t>(U, U + P));
+      bool ok = true;
+      auto add = [&](int32_t start, int32_t len) {
+        std::vector<uint32_t> t(sig.begin() + start, sig.begin() + start + len);
+        auto it = kinds.find(t);
+        if (it == kinds.end()) {
+          code += len;
+          it = kinds.emplace(t, (int32_t)d.kinds.size()).first;
+          d.kinds.push_back(t);
+        }
+        d.cell_kind.push_back(it->second);
+        d.cell_start.push_back(start);
+      };
+      auto flush = [&](int32_t g0, int32_t g1) {  // gap [g0, g1)
+        for (int32_t s = g0; s < g1; s += kMaxUnit) add(s, std::min(kMaxUnit, g1 - s));
+      };
+      int32_t i = 0, gap = -1;
+      while (i < E && ok) {
+        if (i + P <= E && std::memcmp(&sig[i], U, P * sizeof(uint32_t)) == 0) {
+          if (gap >= 0) flush(gap, i), gap = -1;
+          d.cell_kind.push_back(0);
+          d.cell_start.push_back(i);
+          i += P;
+        } else {
+          if (gap < 0) gap = i;
+          ++i;
+        }
+        if (code > kMaxCode) ok = false;
       }
-    }
-    if (too_big) continue;
-    if (best_cells < 0 || n_cells < best_cells) {
-      best_cells = n_cells;
-      out->period = P;
-      out->kinds.assign(kinds.size(), {});
-      for (auto& kv : kinds) out->kinds[kv.second] = kv.first;
-      out->cell_kind.resize(n_cells);
-      for (int32_t c = 0; c < n_cells; ++c) {
-        std::vector<uint32_t> t(sig.begin() + (size_t)c * P,
-                                sig.begin() + std::min<size_t>((size_t)(c + 1) * P, (size_t)E));
-        out->cell_kind[c] = kinds[t];
+      if (ok && gap >= 0) flush(gap, E);
+      if (!ok || code > kMaxCode) continue;
+      if (best_cells == 0 || d.cell_kind.size() < best_cells ||
+          (d.cell_kind.size() == best_cells && code < best_code)) {
+        best_cells = d.cell_kind.size();
+        best_code = code;
+        *out = d;
       }
     }
   }
@@ -94,6 +118,7 @@ int32_t n_words(uint32_t s) {
     case K_DRIFT: case K_DRIFT_EXP: case K_AP_CIRC: return 1;
     case K_MULT: return 2 * ((int32_t)order + 1);
     case K_MULT_CURV: return 2 * ((int32_t)order + 1) + 3;
+    case K_MULT_LR: return 2 * ((int32_t)order + 1) + 1;
     case K_RF: return 3;
     case K_SHIFT: case K_SROT: case K_AP_ELL: return 2;
     case K_AP_RECT: return 4;
@@ -120,7 +145,13 @@ std::string emit(uint32_t s, int32_t o, int32_t j) {
       const int32_t v = o + 2 * ((int32_t)order + 1);
       c << "{ double kx, ky; xtmm::multipole<" << order << ">(q, p + " << o
         << ", kx, ky); xtmm::curvature(q, p[" << v << "], p[" << v + 1 << "], p[" << v + 2
-        << "]); }";
+        << "]); RAD(kx, ky, p[" << v + 2 << "], " << j << "); }";
+      break;
+    }
+    case K_MULT_LR: {
+      const int32_t v = o + 2 * ((int32_t)order + 1);
+      c << "{ double kx, ky; xtmm::multipole<" << order << ">(q, p + " << o
+        << ", kx, ky); RAD(kx, ky, p[" << v << "], " << j << "); }";
       break;
     }
     case K_RF:
@@ -170,7 +201,10 @@ std::string generate(const Decomp& d) {
   s << "#include \"xtm_maps.h\"\n"
        "struct SoA { double *x, *px, *y, *py, *zeta, *delta, *ptau, *rpp, *rvv;\n"
        "             int *state, *at_element, *at_turn; long long* pid; };\n"
-       "struct KRef { double beta0, two_over_beta0; };\n"
+       "struct KRef { double beta0, two_over_beta0, gamma0, c_mean, c_quant, p0c;\n"
+       "              unsigned long long seed; int rad_mode; int pad; };\n"
+       "#define RAD(kx, ky, lr, j) xtmm::radiate_at(q, kx, ky, lr, r.rad_mode, r.seed, pid, \\\n"
+       "    t0 + t, ec + (j), r.gamma0, r.c_mean, r.c_quant, r.p0c, beta0, two_over_beta0)\n"
        "#define MAXW " << maxw << "\n"
        "#define PER_THREAD " << per_thread << "\n"
        "extern \"C\" __global__ void __launch_bounds__(256)\n"
@@ -190,9 +224,10 @@ std::string generate(const Decomp& d) {
        "  q.x = P.x[pi]; q.px = P.px[pi]; q.y = P.y[pi]; q.py = P.py[pi]; q.zeta = P.zeta[pi];\n"
        "  q.delta = P.delta[pi]; q.ptau = P.ptau[pi]; q.rpp = P.rpp[pi]; q.rvv = P.rvv[pi];\n"
        "  const double beta0 = r.beta0, two_over_beta0 = r.two_over_beta0;\n"
+       "  const long long pid = P.pid[pi];\n"
        "  xtmm::refresh(q, beta0);\n"
        "  {\n"
-       "    const int off0 = cells[1], nw0 = cells[2];\n"
+       "    const int off0 = cells[1], nw0 = cells[3];\n"
        "    for (int w = threadIdx.x; w < nw0; w += blockDim.x) slot[w] = prm[off0 + w];\n"
        "  }\n"
        "  __syncthreads();\n"
@@ -201,14 +236,15 @@ std::string generate(const Decomp& d) {
        "    const int enc_t = t * n_el + 1;\n"
        "    for (int c = 0; c < n_cells; ++c) {\n"
        "      const int cn = (c + 1 == n_cells) ? 0 : c + 1;\n"
-       "      const int offn = cells[3 * cn + 1], nwn = cells[3 * cn + 2];\n"
+       "      const int offn = cells[4 * cn + 1], nwn = cells[4 * cn + 3];\n"
        "      double pre[PER_THREAD];\n"
        "#pragma unroll\n"
        "      for (int k = 0; k < PER_THREAD; ++k) {\n"
        "        const int w = threadIdx.x + k * 256;\n"
        "        pre[k] = (w < nwn) ? prm[offn + w] : 0.0;\n"
        "      }\n"
-       "      const int kind = cells[3 * c];\n"
+       "      const int kind = cells[4 * c];\n"
+       "      const int ec = cells[4 * c + 2];\n"
        "      // slot base hidden behind a register move: element reads become\n"
        "      // base + immediate-offset LDS loads instead of hoisted constant selects\n"
        "      int base;\n"
@@ -219,7 +255,7 @@ std::string generate(const Decomp& d) {
        "      // the cell's loss-code base lives in a VGPR so the per-element codes\n"
        "      // e0 + j are vector adds of literals, not hoisted scalar constants\n"
        "      int e0;\n"
-       "      asm volatile(\"v_mov_b32 %0, %1\" : \"=v\"(e0) : \"s\"(enc_t + c * " << d.period << "));\n";
+       "      asm volatile(\"v_mov_b32 %0, %1\" : \"=v\"(e0) : \"s\"(enc_t + ec));\n";
   for (size_t k = 0; k < d.kinds.size(); ++k) {
     s << "      " << (k ? "else if" : "if") << " (kind == " << k << ") {\n";
     int32_t o = 0;
@@ -330,13 +366,14 @@ bool build_line_kernel(const std::vector<uint64_t>& tab, int32_t n_el, LineKerne
     }
     k->fn = it->second.fn;
   }
-  std::vector<int32_t> cells;  // per cell: kind, first parameter word, word count
+  std::vector<int32_t> cells;  // per cell: kind, first parameter word, first element, words
   for (size_t c = 0; c < d.cell_kind.size(); ++c) {
     cells.push_back(d.cell_kind[c]);
-    cells.push_back(word_of[c * (size_t)d.period]);
+    cells.push_back(word_of[d.cell_start[c]]);
+    cells.push_back(d.cell_start[c]);
     cells.push_back(kind_words(d.kinds[d.cell_kind[c]]));
   }
-  k->period = d.period;
+  k->period = (int32_t)d.kinds[0].size();
   k->n_cells = (int32_t)d.cell_kind.size();
   k->n_kinds = (int32_t)d.kinds.size();
   if (prm.empty()) prm.push_back(0.0);

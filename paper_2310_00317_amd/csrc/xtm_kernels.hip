@@ -193,6 +193,7 @@ __global__ void __launch_bounds__(256) k_track(const uint64_t* __restrict__ tab,
           break;
         }
         case K_MULT:
+        case K_MULT_LR:
           horner_n(q, prm, order);
           break;
         case K_MULT_CURV: {
@@ -361,6 +362,7 @@ __global__ void __launch_bounds__(256) k_track2(const uint64_t* __restrict__ tab
           break;
         }
         case K_MULT:
+        case K_MULT_LR:
           horner_n(q, prm, order);
           break;
         case K_MULT_CURV: {
@@ -488,7 +490,7 @@ __global__ void __launch_bounds__(256) k_track3(const uint64_t* __restrict__ tab
         const uint32_t order = (uint32_t)((h >> 8) & 0xffu);
         const uint32_t nw = (uint32_t)((h >> 16) & 0xffffu);
         const double* prm = reinterpret_cast<const double*>(&lds[off + 1]);
-        if (ktype == K_MULT) {
+        if (ktype == K_MULT || ktype == K_MULT_LR) {
           horner_n(q, prm, order);
         } else if (ktype == K_DRIFT) {
           const double L = prm[0];
@@ -597,12 +599,44 @@ __global__ void __launch_bounds__(256) k_track3(const uint64_t* __restrict__ tab
 // start, and k_replay re-tracks them to the loss point (the maps are
 // deterministic, so the replayed coordinates are bitwise the ones the lane had
 // when it was lost).  The element loop thus has no divergent control flow.
+__device__ __forceinline__ void multipole_n(xtmm::Pt& q, const double* __restrict__ prm,
+                                            uint32_t order, double& kx, double& ky) {
+  switch (order) {
+    case 0: xtmm::multipole<0>(q, prm, kx, ky); break;
+    case 1: xtmm::multipole<1>(q, prm, kx, ky); break;
+    case 2: xtmm::multipole<2>(q, prm, kx, ky); break;
+    case 3: xtmm::multipole<3>(q, prm, kx, ky); break;
+    case 4: xtmm::multipole<4>(q, prm, kx, ky); break;
+    case 5: xtmm::multipole<5>(q, prm, kx, ky); break;
+    case 6: xtmm::multipole<6>(q, prm, kx, ky); break;
+    case 7: xtmm::multipole<7>(q, prm, kx, ky); break;
+    case 8: xtmm::multipole<8>(q, prm, kx, ky); break;
+    case 9: xtmm::multipole<9>(q, prm, kx, ky); break;
+    default: xtmm::multipole<10>(q, prm, kx, ky); break;
+  }
+}
+
+// radiation after a multipole of length lr (identity of the deviate: particle
+// id, absolute turn, user element index)
+__device__ __forceinline__ void maybe_radiate(xtmm::Pt& q, double kx, double ky, double lr,
+                                              const KernelRef& r, long long pid, int turn,
+                                              int element) {
+  xtmm::radiate_at(q, kx, ky, lr, r.rad_mode, r.seed, pid, turn, element, r.gamma0, r.c_mean,
+                   r.c_quant, r.p0c, r.beta0, r.two_over_beta0);
+}
+
 __device__ __forceinline__ void apply_elem(xtmm::Pt& q, uint32_t ktype, uint32_t order,
                                            const double* __restrict__ prm, const KernelRef& r,
-                                           bool& ok, int& lost_state) {
+                                           bool& ok, int& lost_state, long long pid, int turn,
+                                           int element) {
   double kx, ky;
   ok = true;
   lost_state = 0;
+  if (ktype == K_MULT_LR) {
+    multipole_n(q, prm, order, kx, ky);
+    maybe_radiate(q, kx, ky, prm[2 * (order + 1)], r, pid, turn, element);
+    return;
+  }
   if (ktype == K_MULT) {
     switch (order) {
       case 0: xtmm::multipole<0>(q, prm, kx, ky); break;
@@ -631,21 +665,10 @@ __device__ __forceinline__ void apply_elem(xtmm::Pt& q, uint32_t ktype, uint32_t
       xtmm::drift_expanded(q, prm[0]);
       break;
     case K_MULT_CURV: {
-      switch (order) {
-        case 0: xtmm::multipole<0>(q, prm, kx, ky); break;
-        case 1: xtmm::multipole<1>(q, prm, kx, ky); break;
-        case 2: xtmm::multipole<2>(q, prm, kx, ky); break;
-        case 3: xtmm::multipole<3>(q, prm, kx, ky); break;
-        case 4: xtmm::multipole<4>(q, prm, kx, ky); break;
-        case 5: xtmm::multipole<5>(q, prm, kx, ky); break;
-        case 6: xtmm::multipole<6>(q, prm, kx, ky); break;
-        case 7: xtmm::multipole<7>(q, prm, kx, ky); break;
-        case 8: xtmm::multipole<8>(q, prm, kx, ky); break;
-        case 9: xtmm::multipole<9>(q, prm, kx, ky); break;
-        default: xtmm::multipole<10>(q, prm, kx, ky); break;
-      }
+      multipole_n(q, prm, order, kx, ky);
       const double* cv = prm + 2 * (order + 1);
       xtmm::curvature(q, cv[0], cv[1], cv[2]);
+      maybe_radiate(q, kx, ky, cv[2], r, pid, turn, element);
       break;
     }
     case K_RF:
@@ -693,6 +716,7 @@ __global__ void __launch_bounds__(256) k_track4(const uint64_t* __restrict__ tab
   if (__all(code != 0)) return;
   xtmm::Pt q;
   load_pt(P, p, q, r.beta0);
+  const long long pid = P.pid[p];
   for (int32_t t = 0; t < n_turns; ++t) {
     uint32_t off = 0;
     const int enc0 = t * n_el + 1;
@@ -703,7 +727,8 @@ __global__ void __launch_bounds__(256) k_track4(const uint64_t* __restrict__ tab
       const double* __restrict__ prm = reinterpret_cast<const double*>(w + 1);
       bool ok;
       int ls;
-      apply_elem(q, (uint32_t)(h & 0xffu), (uint32_t)((h >> 8) & 0xffu), prm, r, ok, ls);
+      apply_elem(q, (uint32_t)(h & 0xffu), (uint32_t)((h >> 8) & 0xffu), prm, r, ok, ls, pid,
+                 t0 + t, e);
       xtmm::mark(ok, code, st, enc0 + e, ls);
       off += 1 + (uint32_t)((h >> 16) & 0xffffu);
     }
@@ -738,6 +763,7 @@ __global__ void __launch_bounds__(256) k_replay(const uint64_t* __restrict__ tab
   int64_t remaining = (int64_t)tl * n_el + el;
   xtmm::Pt q;
   load_pt(P, p, q, r.beta0);
+  const long long pid = P.pid[p];
   for (int32_t t = 0; t <= tl && remaining > 0; ++t) {
     uint32_t off = 0;
     for (int32_t e = 0; e < n_el && remaining > 0; ++e, --remaining) {
@@ -746,7 +772,8 @@ __global__ void __launch_bounds__(256) k_replay(const uint64_t* __restrict__ tab
       bool ok;
       int ls;
       apply_elem(q, (uint32_t)(h & 0xffu), (uint32_t)((h >> 8) & 0xffu),
-                 reinterpret_cast<const double*>(w + 1), r, ok, ls);
+                 reinterpret_cast<const double*>(w + 1), r, ok, ls, pid,
+                 backward ? t0 - 1 - t : t0 + t, e);
       off += 1 + (uint32_t)((h >> 16) & 0xffffu);
     }
   }
@@ -878,7 +905,34 @@ __global__ void __launch_bounds__(kScanBlock) k_scatter(const int32_t* __restric
   }
 }
 
+// Raw Philox4x32-10 blocks: block j uses counter ctr0 + j (128-bit carry),
+// key = (seed_lo, seed_hi).
+__global__ void __launch_bounds__(256) k_philox(unsigned long long seed, uint32_t c0,
+                                                uint32_t c1, uint32_t c2, uint32_t c3,
+                                                int64_t n_blocks, uint32_t* __restrict__ out) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n_blocks) return;
+  const unsigned long long lo0 = ((unsigned long long)c1 << 32) | c0;
+  const unsigned long long lo = lo0 + (unsigned long long)j;
+  const unsigned long long hi = (((unsigned long long)c3 << 32) | c2) + (lo < lo0 ? 1ull : 0ull);
+  xtmm::U4 c{(unsigned int)lo, (unsigned int)(lo >> 32), (unsigned int)hi,
+             (unsigned int)(hi >> 32)};
+  const xtmm::U4 w = xtmm::philox4x32_10(c, (unsigned int)seed, (unsigned int)(seed >> 32));
+  out[4 * j] = w.a;
+  out[4 * j + 1] = w.b;
+  out[4 * j + 2] = w.c;
+  out[4 * j + 3] = w.d;
+}
+
 // ------------------------------------------------------------- launchers
+hipError_t launch_philox(unsigned long long seed, const uint32_t ctr0[4], int64_t n_blocks,
+                         uint32_t* out, hipStream_t s) {
+  if (n_blocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_philox, dim3((unsigned)((n_blocks + 255) / 256)), dim3(256), 0, s, seed,
+                     ctr0[0], ctr0[1], ctr0[2], ctr0[3], n_blocks, out);
+  return hipGetLastError();
+}
+
 static inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
 hipError_t launch_init(const double* coords6, int64_t n, int64_t first_id, SoA P, KernelRef r,

@@ -135,6 +135,99 @@ __device__ __forceinline__ bool in_rect(const Pt& q, double x0, double x1, doubl
   return (x0 <= q.x) & (q.x <= x1) & (y0 <= q.y) & (q.y <= y1);
 }
 
+// ------------------------------------------------------------------ RNG
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): 128-bit counter, 64-bit
+// key, ten rounds of two 32x32->64 multiplications whose halves are mixed
+// with the other words and the key; the key advances by the Weyl increments
+// floor(2^32 (golden ratio - 1)) and floor(2^32 (sqrt(3) - 1)) between rounds.
+struct U4 {
+  unsigned int a, b, c, d;
+};
+
+__device__ __forceinline__ U4 philox4x32_10(U4 ctr, unsigned int k0, unsigned int k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r > 0) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    const unsigned int h0 = __umulhi(0xD2511F53u, ctr.a), l0 = 0xD2511F53u * ctr.a;
+    const unsigned int h1 = __umulhi(0xCD9E8D57u, ctr.c), l1 = 0xCD9E8D57u * ctr.c;
+    U4 n;
+    n.a = h1 ^ ctr.b ^ k0;
+    n.b = l1;
+    n.c = h0 ^ ctr.d ^ k1;
+    n.d = l0;
+    ctr = n;
+  }
+  return ctr;
+}
+
+// Uniform in (0,1), exact in binary64: k = (wa << 20) | (wb >> 12), u = (k + 1/2) 2^-52.
+__device__ __forceinline__ double uniform52(unsigned int wa, unsigned int wb) {
+  const unsigned long long k = ((unsigned long long)wa << 20) | (unsigned long long)(wb >> 12);
+  return ((double)k + 0.5) * 0x1p-52;
+}
+
+// Standard normal of (seed, particle id, turn, element, draw) by Box-Muller
+// on one Philox block with counter (pid_lo, pid_hi, turn, element * 8 + draw).
+__device__ __forceinline__ double gauss_at(unsigned long long seed, long long pid, int turn,
+                                           int element, int draw) {
+  U4 c;
+  c.a = (unsigned int)(unsigned long long)pid;
+  c.b = (unsigned int)((unsigned long long)pid >> 32);
+  c.c = (unsigned int)turn;
+  c.d = (unsigned int)element * 8u + (unsigned int)draw;
+  const U4 w = philox4x32_10(c, (unsigned int)seed, (unsigned int)(seed >> 32));
+  const double u1 = uniform52(w.a, w.b), u2 = uniform52(w.c, w.d);
+  return sqrt(-2.0 * log(u1)) * cos(2.0 * 3.141592653589793 * u2);
+}
+
+// ------------------------------------------------------------ radiation
+// Radiation in a thin multipole of radiation length Lr > 0, after its kick
+// (kx, ky = field kick): h = |k| rpp / Lr, gamma = gamma0 (1 + beta0 ptau),
+// mean loss dE = c_mean gamma^4 h^2 Lr with c_mean = (2/3) r m;
+// quantum (mode 2): dE += sqrt(c_quant gamma^7 |h|^3 Lr) g, c_quant =
+// 55/(24 sqrt 3) r m hbar_c; ptau -= dE/p0c, delta from ptau, and the
+// momenta keep their angles: px, py *= (1+delta_new)/(1+delta_old).
+struct Rad {
+  double gamma0, c_mean, c_quant, p0c;
+};
+
+__device__ __forceinline__ void radiate(Pt& q, double kx, double ky, double lr, const Rad& rr,
+                                        int mode, double g, double beta0, double two_over_beta0) {
+  const double h = sqrt(kx * kx + ky * ky) * q.rpp / lr;
+  const double gam = rr.gamma0 * (1.0 + q.bpt);
+  const double g2 = gam * gam;
+  const double g4 = g2 * g2;
+  double de = rr.c_mean * g4 * h * h * lr;
+  if (mode == 2) {
+    const double g7 = g4 * g2 * gam;
+    const double var = rr.c_quant * g7 * h * h * h * lr;
+    de = de + sqrt(var) * g;
+  }
+  const double opd_old = 1.0 + q.delta;
+  q.ptau = q.ptau - de / rr.p0c;
+  from_ptau(q, beta0, two_over_beta0);
+  const double f = (1.0 + q.delta) / opd_old;
+  q.px = q.px * f;
+  q.py = q.py * f;
+}
+
+// Radiation step of a multipole with radiation length lr (none if lr <= 0 or
+// mode 0); the Gaussian deviate is keyed by (seed, particle id, absolute
+// turn, user element index).
+__device__ __forceinline__ void radiate_at(Pt& q, double kx, double ky, double lr, int mode,
+                                           unsigned long long seed, long long pid, int turn,
+                                           int element, double gamma0, double c_mean,
+                                           double c_quant, double p0c, double beta0,
+                                           double two_over_beta0) {
+  if (mode == 0 || !(lr > 0.0)) return;
+  const double g = (mode == 2) ? gauss_at(seed, pid, turn, element, 0) : 0.0;
+  Rad rr{gamma0, c_mean, c_quant, p0c};
+  radiate(q, kx, ky, lr, rr, mode, g, beta0, two_over_beta0);
+}
+
 // Branch-free loss bookkeeping: the first failed check of a live lane
 // records code = (turn in chunk) * n_el + element + 1 and the state.
 __device__ __forceinline__ void mark(bool ok, int& code, int& st, int enc,

@@ -1,0 +1,100 @@
+"""GPU parity of the counter-based RNG (bit-exact words) and of tracking with
+synchrotron radiation (mean and quantum) against the oracle."""
+import ctypes
+
+import numpy as np
+import pytest
+
+from paper_2310_00317_amd import inputs as I
+from parity_util import assert_parity, gpu_run, oracle_run
+
+pytestmark = pytest.mark.gpu
+EREF = I.ELECTRON_45GEV6
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2310_00317_amd as P
+    P.lib()
+    return P
+
+
+@pytest.mark.parametrize("seed,ctr0", [(0, [0, 0, 0, 0]), (0x123456789ABCDEF, [5, 6, 7, 8]),
+                                       (42, [0xFFFFFFF0, 0xFFFFFFFF, 9, 0])])
+def test_philox_words_bit_exact(P, oracle_mod, seed, ctr0):
+    n = 4096
+    g = P.philox(seed, ctr0, n).cpu().numpy().view(np.uint32)
+    o = oracle_mod.philox_stream(seed, ctr0, n)
+    assert np.array_equal(g, o)
+
+
+def test_philox_first_block_matches_installed_rocrand(oracle_mod):
+    """Black-box check of the oracle generator: rocRAND's host Philox4x32-10
+    with seed s and offset 0 starts with the block (counter 0, key s)."""
+    try:
+        L = ctypes.CDLL("/opt/rocm/lib/librocrand.so")
+    except OSError:
+        pytest.skip("rocRAND not installed")
+    for seed in (0, 1, 0xDEADBEEF12345678):
+        gen = ctypes.c_void_p()
+        assert L.rocrand_create_generator_host_blocking(ctypes.byref(gen), 404) == 0
+        assert L.rocrand_set_seed(gen, ctypes.c_ulonglong(seed)) == 0
+        out = np.zeros(4, dtype=np.uint32)
+        st = L.rocrand_generate(gen, out.ctypes.data_as(ctypes.c_void_p), ctypes.c_size_t(4))
+        L.rocrand_destroy_generator(gen)
+        if st != 0:
+            pytest.skip(f"rocRAND host generator unavailable (status {st})")
+        ref = oracle_mod.philox([0, 0, 0, 0], [seed & 0xFFFFFFFF, seed >> 32])
+        assert np.array_equal(out, ref), (hex(seed), out, ref)
+
+
+def _ring():
+    # 100-cell electron ring without sextupoles: regular orbits, few losses
+    return I.cfg5_lattice(100, n_rf=4, sextupoles=False)
+
+
+@pytest.mark.parametrize("mode", [1, 2])
+def test_radiation_parity_small_ring(P, oracle_mod, mode):
+    el = _ring()
+    c = I.gaussian_particles(600, 99, [3e-4, 3e-6, 3e-5, 3e-7, 3e-3, 1.5e-3])
+    lat = P.Lattice(el, EREF)
+    parts = P.Particles(len(c), EREF).init(c, first_id=1000)
+    gp, _ = P.track(lat, parts, 60, radiation=mode, seed=2024)
+    g = parts.to_numpy()
+    o = oracle_mod.init(c, EREF, first_id=1000)
+    op = oracle_mod.track(el, EREF, o, 60, radiation=mode, seed=2024)
+    assert gp == op
+    assert_parity(g, o, rtol=1e-12)
+
+
+def test_radiation_full_electron_ring_short(P, oracle_mod):
+    el = I.cfg5_lattice()
+    c = I.cfg5_particles(256, seed=3)
+    g, gp, _, _, _ = gpu_run(P, el, EREF, c, 3, radiation=2, seed=7)
+    o = oracle_mod.init(c, EREF)
+    op = oracle_mod.track(el, EREF, o, 3, radiation=2, seed=7)
+    assert gp == op
+    assert_parity(g, o, rtol=1e-12)
+
+
+def test_radiation_graph_and_chunks_invariant(P):
+    el = _ring()
+    c = I.gaussian_particles(512, 5, [3e-4, 3e-6, 3e-5, 3e-7, 3e-3, 1.5e-3])
+    a, pa, _, _, _ = gpu_run(P, el, EREF, c, 40, radiation=2, seed=1)
+    b, pb, _, _, _ = gpu_run(P, el, EREF, c, 40, radiation=2, seed=1, turns_per_chunk=7,
+                             variant=4)
+    assert pa == pb
+    for f in a:
+        assert np.array_equal(a[f], b[f], equal_nan=True), f
+
+
+def test_radiation_argument_checks(P):
+    lat = P.Lattice(_ring(), EREF)
+    parts = P.Particles(4, EREF).init(np.zeros((4, 6)))
+    for kw, code in [(dict(radiation=3), -1), (dict(radiation=1, variant=2), -6)]:
+        with pytest.raises(P.XtmError) as ei:
+            P.track(lat, parts, 1, **kw)
+        assert ei.value.code == code
