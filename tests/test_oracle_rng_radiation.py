@@ -13,23 +13,24 @@ vertical damping partition number (exactly 1 in a flat ring), the Robinson
 sum (4), and the equilibrium energy spread C_q gamma^2 I3 / (J_z I2).
 """
 import math
-from decimal import Decimal, getcontext
+from decimal import Decimal, localcontext
 
 import numpy as np
 import pytest
 
 from paper_2310_00317_amd import inputs as I
 
-getcontext().prec = 50
 M32 = 0xFFFFFFFF
 
 
 def test_philox_key_increments_closed_form(oracle_mod):
     m0, m1, w0, w1 = [int(v) for v in oracle_mod.philox_constants()]
-    phi_m1 = (Decimal(5).sqrt() - 1) / 2          # golden ratio - 1
-    s3_m1 = Decimal(3).sqrt() - 1
-    assert w0 == int(phi_m1 * 2 ** 32)
-    assert w1 == int(s3_m1 * 2 ** 32)
+    with localcontext() as ctx:
+        ctx.prec = 50
+        phi_m1 = (Decimal(5).sqrt() - 1) / 2          # golden ratio - 1
+        s3_m1 = Decimal(3).sqrt() - 1
+        assert w0 == int(phi_m1 * 2 ** 32)
+        assert w1 == int(s3_m1 * 2 ** 32)
     assert m0 % 2 == 1 and m1 % 2 == 1              # odd: invertible mod 2^32
 
 
