@@ -173,8 +173,15 @@ typedef struct xtm_track_opts {
                               0 off, 1 mean energy loss, 2 mean + quantum excitation
                               (Gaussian, see below); forward tracking with the
                               default, 4 or 5 kernels only */
-  int32_t reserved;
+  int32_t record_turns;    /* with record_buf: record the start of turns 0 .. record_turns-1 */
   uint64_t rng_seed;       /* key of the quantum-excitation deviates */
+  float* record_buf;       /* early-turn recorder or NULL: device FP32
+                              [record_turns][4][n] with n the set's size, indexed by
+                              the particle's slot; at the start of each absolute turn
+                              t < record_turns, (x, px, y, py) of every particle alive
+                              at element 0 are written; lost particles leave their
+                              entries untouched (caller-owned, caller-cleared).
+                              Forward tracking with the default, 4 or 5 kernels only */
 } xtm_track_opts;
 
 typedef struct xtm_track_stats {
@@ -222,6 +229,87 @@ xtm_status xtm_get_losses(xtm_particles p, int32_t* h_state, int32_t* h_at_turn,
    Stream-ordered. */
 xtm_status xtm_philox4x32_10(uint64_t seed, const uint32_t ctr0[4], int64_t n_blocks,
                              uint32_t* d_out, void* stream);
+
+/* ---------------------------------------------------------------------------
+   Learned early stop.  The paper cites machine-learned dynamic-aperture
+   estimates beside chaos indicators (applications, dynamic aperture) without
+   fixing a model; the network, its features and the retire policy below are
+   this library's reading.  All buffers are caller-owned device memory, all
+   calls are ordered on `stream` and return without synchronising unless
+   stated otherwise.  Arithmetic: FP32 features; BF16 GEMM operands (round to
+   nearest even) with FP32 accumulation; FP32 bias, ReLU, sigmoid and loss.
+
+   Network 16 -> 128 (ReLU) -> 128 (ReLU) -> 1 logit.  Parameter vector theta,
+   XTM_MLP_PARAMS FP32: W1[16][128], b1[128], W2[128][128], b2[128], w3[128],
+   b3[1], with W[i][j] mapping input i to output j.  Input normalisation
+   `norm` (32 FP32): mean[16] then inverse standard deviation[16]; the network
+   sees (x - mean) * inv_std. */
+#define XTM_MLP_PARAMS 18817
+#define XTM_N_FEATURES 16
+#define XTM_RECORD_TURNS 1024
+
+/* 16 FP32 features per particle from a 1024-turn record (xtm_track_opts
+   record_buf, record_turns = 1024): with u = x / sqrt(beta),
+   pu = (alpha x + beta px) / sqrt(beta), J = (u^2 + pu^2) / 2 and
+   A = sqrt(2 J / emit):
+     f0, f1 A_x, A_y at turn 0; f2 hypot(f0, f1); f3 atan2(f1, f0);
+     f4, f5 tunes of turns 0..511; f6, f7 tunes of turns 512..1023 (Hann
+     window, 512-point DFT of u - i pu, peak bin with the Hann three-point
+     interpolation); f8, f9 log10 of the circular tune change + 1e-12;
+     f10, f11 mean J of the last quarter over that of the first (each + 1e-6
+     emit) - 1; f12, f13 std(J) / (mean(J) + 1e-6 emit) over all turns;
+     f14 max hypot(x, y) / r_aperture; f15 max (A_x^2 + A_y^2) / (f2^2 + 1e-6).
+   twiss4 = (beta_x, alpha_x, beta_y, alpha_y) at element 0; emit [m] defines
+   one sigma.  d_feat: [n][16].  Rows of particles lost before turn 1024 hold
+   values computed from a partly stale record; the caller masks them.
+   XTM_E_ARG for non-positive beta, emit or aperture. */
+xtm_status xtm_features(const float* d_record, int64_t n, const double twiss4[4], double emit,
+                        double r_aperture, float* d_feat, void* stream);
+
+/* Normalisation statistics of the rows i with d_mask[i] != 0 (all rows when
+   d_mask is NULL): d_norm[0..15] = mean, d_norm[16..31] = 1 / std (population
+   std; 1 when the std is 0 or no row is selected). */
+xtm_status xtm_feature_stats(const float* d_feat, const int32_t* d_mask, int64_t n, float* d_norm,
+                             void* stream);
+
+/* He-normal initialisation: weight k of theta (packed index) is
+   sqrt(2 / fan_in) times the Gaussian deviate of (seed, particle id k, turn 0,
+   element 0, draw 0) of the Philox stream used for radiation; biases 0. */
+xtm_status xtm_mlp_init(float* d_theta, uint64_t seed, void* stream);
+
+/* Logits of B rows of d_x [B][16] (raw features, normalised inside). */
+xtm_status xtm_mlp_forward(const float* d_theta, const float* d_norm, const float* d_x, int64_t B,
+                           float* d_logit, void* stream);
+
+/* Size in floats of the workspace xtm_mlp_grad needs for a batch of B. */
+xtm_status xtm_mlp_workspace(int64_t B, int64_t* n_floats);
+
+/* Gradient of the mean positively weighted binary cross-entropy
+   mean(-[w y log s(z) + (1 - y) log(1 - s(z))]) over the batch (y in {0, 1},
+   w = pos_weight) with respect to theta, into d_grad[XTM_MLP_PARAMS]; the
+   loss into d_loss[0] when d_loss is non-NULL.  The back-propagated signals
+   are rounded to BF16 where they enter a GEMM.  d_work: xtm_mlp_workspace
+   floats.  B >= 1. */
+xtm_status xtm_mlp_grad(const float* d_theta, const float* d_norm, const float* d_x,
+                        const float* d_y, int64_t B, float pos_weight, float* d_grad,
+                        float* d_loss, float* d_work, void* stream);
+
+/* One Adam step (Kingma & Ba 2015; beta1 0.9, beta2 0.999, eps 1e-8) on the
+   FP32 master parameters, step counted from 1; d_m, d_v start at zero. */
+xtm_status xtm_mlp_adam(float* d_theta, float* d_m, float* d_v, const float* d_grad, int32_t step,
+                        float lr, void* stream);
+
+/* Retire policy: every alive particle of the set (indexed by slot, as the
+   set's arrays) with d_logit[slot] >= logit_threshold is retired (state 2,
+   coordinates and at_turn left as they are, so it is no longer tracked and
+   counts as a survivor) unless it belongs to the audit set: audited iff the
+   first word of Philox4x32-10 with key audit_seed and counter (pid_lo, pid_hi,
+   0xFFFFFFFF, 0) is below ceil(audit_fraction 2^32).  Audited particles stay
+   alive.  Rebuilds the alive list; synchronises; the counts go to the host
+   when non-NULL. */
+xtm_status xtm_retire(xtm_particles P, const float* d_logit, float logit_threshold,
+                      uint64_t audit_seed, double audit_fraction, int64_t* h_retired,
+                      int64_t* h_audited, void* stream);
 
 /* Synchronise the stream and report any asynchronous device error. */
 xtm_status xtm_sync(void* stream);

@@ -47,8 +47,8 @@ class TrackOpts(ctypes.Structure):
     _fields_ = [("turns_per_chunk", ctypes.c_int32), ("block", ctypes.c_int32),
                 ("no_compact", ctypes.c_int32), ("use_graph", ctypes.c_int32),
                 ("time_kernels", ctypes.c_int32), ("variant", ctypes.c_int32),
-                ("radiation", ctypes.c_int32), ("reserved", ctypes.c_int32),
-                ("rng_seed", ctypes.c_uint64)]
+                ("radiation", ctypes.c_int32), ("record_turns", ctypes.c_int32),
+                ("rng_seed", ctypes.c_uint64), ("record_buf", ctypes.c_void_p)]
 
 
 class TrackStats(ctypes.Structure):
@@ -85,6 +85,15 @@ def lib() -> ctypes.CDLL:
             "xtm_get_losses": ([vp, vp, vp, vp, vp], i32),
             "xtm_sync": ([vp], i32),
             "xtm_philox4x32_10": ([ctypes.c_uint64, vp, i64, vp, vp], i32),
+            "xtm_features": ([vp, i64, vp, ctypes.c_double, ctypes.c_double, vp, vp], i32),
+            "xtm_feature_stats": ([vp, vp, i64, vp, vp], i32),
+            "xtm_mlp_init": ([vp, ctypes.c_uint64, vp], i32),
+            "xtm_mlp_forward": ([vp, vp, vp, i64, vp, vp], i32),
+            "xtm_mlp_workspace": ([i64, vp], i32),
+            "xtm_mlp_grad": ([vp, vp, vp, vp, i64, ctypes.c_float, vp, vp, vp, vp], i32),
+            "xtm_mlp_adam": ([vp, vp, vp, vp, i32, ctypes.c_float, vp], i32),
+            "xtm_retire": ([vp, vp, ctypes.c_float, ctypes.c_uint64, ctypes.c_double, vp, vp, vp],
+                           i32),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -240,11 +249,19 @@ class Particles:
 def track(lattice: Lattice, particles: Particles, n_turns: int, turns_per_chunk: int = 0,
           block: int = 0, compact: bool = True, graph: bool = False, stats: bool = True,
           time_kernels: bool = False, variant: int = 0, radiation: int = 0, seed: int = 0,
-          stream=None, full_stats: bool = False):
+          stream=None, full_stats: bool = False, record=None):
     """Track ``n_turns`` forward.  With ``stats`` (synchronising) returns
-    (passes, alive), or the whole TrackStats if ``full_stats``."""
+    (passes, alive), or the whole TrackStats if ``full_stats``.  ``record``:
+    a float32 cuda tensor [T, 4, n] that receives (x, px, y, py) at the start
+    of absolute turns < T."""
+    rec_turns, rec_ptr = 0, None
+    if record is not None:
+        if tuple(record.shape[1:]) != (4, particles.n) or not record.is_contiguous():
+            raise ValueError("record must be a contiguous [T, 4, n] tensor")
+        rec_turns, rec_ptr = int(record.shape[0]), record.data_ptr()
     o = TrackOpts(int(turns_per_chunk), int(block), 0 if compact else 1, 1 if graph else 0,
-                  1 if time_kernels else 0, int(variant), int(radiation), 0, int(seed))
+                  1 if time_kernels else 0, int(variant), int(radiation), rec_turns, int(seed),
+                  rec_ptr)
     s = TrackStats()
     check(lib().xtm_track(lattice.handle, particles.handle, int(n_turns), ctypes.byref(o),
                           _stream(stream), ctypes.byref(s) if (stats or full_stats) else None),
@@ -274,3 +291,85 @@ def philox(seed: int, ctr0, n_blocks: int, stream=None):
     check(lib().xtm_philox4x32_10(int(seed), c, int(n_blocks), ctypes.c_void_p(out.data_ptr()),
                                   _stream(stream)), "xtm_philox4x32_10")
     return out[: 4 * int(n_blocks)]
+
+
+# ------------------------------------------------------------ learned early stop
+MLP_PARAMS = 18817
+N_FEATURES = 16
+RECORD_TURNS = 1024
+
+
+def _p(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def features(record, twiss4, emit: float, r_aperture: float, stream=None):
+    """16 FP32 features per particle from a [1024, 4, n] float32 record."""
+    import torch
+    n = int(record.shape[2])
+    out = torch.empty((max(n, 1), N_FEATURES), dtype=torch.float32, device=record.device)
+    tw = (ctypes.c_double * 4)(*[float(v) for v in twiss4])
+    check(lib().xtm_features(_p(record), n, tw, float(emit), float(r_aperture), _p(out),
+                             _stream(stream)), "xtm_features")
+    return out[:n]
+
+
+def feature_stats(feat, mask=None, stream=None):
+    """[32] float32: column means then inverse standard deviations."""
+    import torch
+    norm = torch.empty(32, dtype=torch.float32, device=feat.device)
+    check(lib().xtm_feature_stats(_p(feat), _p(mask), int(feat.shape[0]), _p(norm),
+                                  _stream(stream)), "xtm_feature_stats")
+    return norm
+
+
+def mlp_init(seed: int, device="cuda", stream=None):
+    import torch
+    theta = torch.empty(MLP_PARAMS, dtype=torch.float32, device=device)
+    check(lib().xtm_mlp_init(_p(theta), int(seed), _stream(stream)), "xtm_mlp_init")
+    return theta
+
+
+def mlp_forward(theta, norm, x, stream=None):
+    import torch
+    B = int(x.shape[0])
+    out = torch.empty(max(B, 1), dtype=torch.float32, device=x.device)
+    check(lib().xtm_mlp_forward(_p(theta), _p(norm), _p(x), B, _p(out), _stream(stream)),
+          "xtm_mlp_forward")
+    return out[:B]
+
+
+def mlp_workspace(B: int) -> int:
+    n = ctypes.c_int64()
+    check(lib().xtm_mlp_workspace(int(B), ctypes.byref(n)), "xtm_mlp_workspace")
+    return int(n.value)
+
+
+def mlp_grad(theta, norm, x, y, pos_weight: float, work=None, stream=None):
+    """(grad [MLP_PARAMS], loss [1]) float32 tensors."""
+    import torch
+    B = int(x.shape[0])
+    if work is None:
+        work = torch.empty(mlp_workspace(B), dtype=torch.float32, device=x.device)
+    grad = torch.empty(MLP_PARAMS, dtype=torch.float32, device=x.device)
+    loss = torch.empty(1, dtype=torch.float32, device=x.device)
+    check(lib().xtm_mlp_grad(_p(theta), _p(norm), _p(x), _p(y), B, float(pos_weight), _p(grad),
+                             _p(loss), _p(work), _stream(stream)), "xtm_mlp_grad")
+    return grad, loss
+
+
+def mlp_adam(theta, m, v, grad, step: int, lr: float, stream=None):
+    check(lib().xtm_mlp_adam(_p(theta), _p(m), _p(v), _p(grad), int(step), float(lr),
+                             _stream(stream)), "xtm_mlp_adam")
+
+
+def retire(particles: Particles, logit, threshold: float, audit_seed: int,
+           audit_fraction: float = 0.05, stream=None):
+    """Retire alive particles with logit >= threshold outside the audit set;
+    returns (retired, audited)."""
+    r = ctypes.c_int64()
+    a = ctypes.c_int64()
+    check(lib().xtm_retire(particles.handle, _p(logit), float(threshold), int(audit_seed),
+                           float(audit_fraction), ctypes.byref(r), ctypes.byref(a),
+                           _stream(stream)), "xtm_retire")
+    return int(r.value), int(a.value)

@@ -24,7 +24,7 @@ DEVICE = ["-x", "hip", f"--offload-arch={ARCH}",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-munsafe-fp-atomics"]
 
-KERNEL_SOURCES = ["xtm_kernels.hip"]
+KERNEL_SOURCES = ["xtm_kernels.hip", "xtm_learn.hip"]
 HOST_SOURCES = ["xtm_api.cpp", "xtm_jit.cpp"]
 
 

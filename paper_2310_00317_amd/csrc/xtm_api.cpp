@@ -76,11 +76,13 @@ struct GraphKey {
   int32_t n_turns, chunk, block, variant, backward, compact, cur, rad_mode;
   int64_t alive_upper;
   uint64_t seed;
+  const float* rec;
+  int32_t rec_turns;
   bool operator==(const GraphKey& o) const {
     return lat == o.lat && n_turns == o.n_turns && chunk == o.chunk && block == o.block &&
            variant == o.variant && backward == o.backward && compact == o.compact &&
            cur == o.cur && rad_mode == o.rad_mode && alive_upper == o.alive_upper &&
-           seed == o.seed;
+           seed == o.seed && rec == o.rec && rec_turns == o.rec_turns;
   }
 };
 
@@ -249,7 +251,7 @@ constexpr double kMElectronEV = 0.51099895000e6;
 constexpr double kHbarCEVM = 197.3269804e-9;     // eV m
 
 KernelRef kref(const RefQ& r, int32_t rad_mode = 0, uint64_t seed = 0) {
-  KernelRef k;
+  KernelRef k{};
   k.beta0 = r.beta0;
   k.two_over_beta0 = 2.0 / r.beta0;
   k.gamma0 = r.gamma0;
@@ -289,6 +291,8 @@ int32_t auto_chunk(int64_t n, int32_t n_el, int32_t n_turns) {
 struct ChunkPlan {
   int32_t rad_mode;
   uint64_t seed;
+  float* rec;
+  int32_t rec_turns;
   const LineKernel* line;  // variant 5
   const uint64_t* tab;
   const int32_t* seg;
@@ -304,7 +308,10 @@ struct ChunkPlan {
 hipError_t enqueue_chunks(xtm_lattice_s* L, xtm_particles_s* P, const ChunkPlan& c, int32_t cur,
                           hipStream_t s, std::vector<hipEvent_t>* ev, int32_t* launches) {
   const SoA soa = soa_of(P);
-  const KernelRef kr = kref(L->ref, c.rad_mode, c.seed);
+  KernelRef kr = kref(L->ref, c.rad_mode, c.seed);
+  kr.rec = c.rec;
+  kr.rec_turns = c.rec_turns;
+  kr.rec_n = (int32_t)P->n;
   int32_t done = 0;
   *launches = 0;
   if (P->alive_upper <= 0) return c.n_turns > 0 ? launch_advance(P->ctrl, c.backward ? -c.n_turns : c.n_turns, s) : hipSuccess;
@@ -355,7 +362,7 @@ int32_t flips(const ChunkPlan& c) {
 xtm_status run_graph(xtm_lattice_s* L, xtm_particles_s* P, const ChunkPlan& c, hipStream_t s,
                      int32_t* launches) {
   GraphKey key{L, c.n_turns, c.chunk, c.block, c.variant, c.backward ? 1 : 0, c.compact ? 1 : 0,
-               P->cur, c.rad_mode, P->alive_upper, c.seed};
+               P->cur, c.rad_mode, P->alive_upper, c.seed, c.rec, c.rec_turns};
   for (const GraphEntry& g : P->graphs) {
     if (g.key == key) {
       HIP_TRY(hipGraphLaunch(g.exec, s), "graph launch");
@@ -404,6 +411,10 @@ xtm_status run_turns(xtm_lattice_s* L, xtm_particles_s* P, int32_t n_turns,
   ChunkPlan c;
   c.rad_mode = o ? o->radiation : 0;
   c.seed = o ? o->rng_seed : 0;
+  c.rec = o ? o->record_buf : nullptr;
+  c.rec_turns = (o && o->record_buf) ? o->record_turns : 0;
+  if (c.rec && (c.rec_turns < 0 || backward))
+    return fail(XTM_E_ARG, "the recorder needs record_turns >= 0 and forward tracking");
   if (c.rad_mode < 0 || c.rad_mode > 2) return fail(XTM_E_ARG, "radiation must be 0, 1 or 2");
   if (c.rad_mode && backward) return fail(XTM_E_ARG, "backward tracking with radiation is undefined");
   c.block = (o && o->block) ? o->block : 256;
@@ -413,8 +424,8 @@ xtm_status run_turns(xtm_lattice_s* L, xtm_particles_s* P, int32_t n_turns,
   c.variant = (o && o->variant) ? o->variant : 0;
   if (c.variant < 0 || c.variant > 5) return fail(XTM_E_ARG, "kernel variant must be 0..5");
   c.line = nullptr;
-  if (c.rad_mode && c.variant >= 1 && c.variant <= 3)
-    return fail(XTM_E_UNSUPPORTED, "kernel variants 1-3 do not implement radiation");
+  if ((c.rad_mode || c.rec) && c.variant >= 1 && c.variant <= 3)
+    return fail(XTM_E_UNSUPPORTED, "kernel variants 1-3 implement neither radiation nor the recorder");
   if (c.variant == 0 || c.variant == 5) {
     // the per-line kernel, compiled on first use; the default falls back to
     // the register-loss interpreter if the line has no compact cell structure
@@ -718,6 +729,139 @@ xtm_status xtm_philox4x32_10(uint64_t seed, const uint32_t ctr0[4], int64_t n_bl
   hipError_t e = launch_philox(seed, ctr0, n_blocks, d_out, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "philox launch");
   return XTM_OK;
+}
+
+// ------------------------------------------------------ learned early stop
+namespace {
+float2* g_twiddle = nullptr;  // (cos, sin)(2 pi k / 512), k < 256
+float* g_window = nullptr;    // sin^2(pi n / 512)
+
+xtm_status fft_tables() {
+  if (g_twiddle) return XTM_OK;
+  std::vector<float2> tw(256);
+  std::vector<float> win(512);
+  for (int k = 0; k < 256; ++k) {
+    tw[k].x = (float)std::cos(2.0 * M_PI * k / 512.0);
+    tw[k].y = (float)std::sin(2.0 * M_PI * k / 512.0);
+  }
+  for (int n = 0; n < 512; ++n) {
+    const double sn = std::sin(M_PI * n / 512.0);
+    win[n] = (float)(sn * sn);
+  }
+  float2* t = nullptr;
+  float* w = nullptr;
+  if (hipMalloc(&t, 256 * sizeof(float2)) != hipSuccess ||
+      hipMalloc(&w, 512 * sizeof(float)) != hipSuccess) {
+    hipFree(t);
+    return fail(XTM_E_NOMEM, "feature tables");
+  }
+  HIP_TRY(hipMemcpy(t, tw.data(), 256 * sizeof(float2), hipMemcpyHostToDevice), "tables");
+  HIP_TRY(hipMemcpy(w, win.data(), 512 * sizeof(float), hipMemcpyHostToDevice), "tables");
+  g_twiddle = t;
+  g_window = w;
+  return XTM_OK;
+}
+}  // namespace
+
+xtm_status xtm_features(const float* d_record, int64_t n, const double twiss4[4], double emit,
+                        double r_aperture, float* d_feat, void* stream) {
+  return guarded([&]() -> xtm_status {
+    if (n < 0 || !twiss4 || (n > 0 && (!d_record || !d_feat)))
+      return fail(XTM_E_ARG, "bad feature arguments");
+    if (!(twiss4[0] > 0) || !(twiss4[2] > 0) || !(emit > 0) || !(r_aperture > 0))
+      return fail(XTM_E_ARG, "beta, emittance and aperture must be positive");
+    xtm_status st = fft_tables();
+    if (st != XTM_OK) return st;
+    hipError_t e = launch_features(d_record, n, twiss4, emit, r_aperture, g_twiddle, g_window,
+                                   d_feat, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "features launch");
+    return XTM_OK;
+  });
+}
+
+xtm_status xtm_feature_stats(const float* d_feat, const int32_t* d_mask, int64_t n, float* d_norm,
+                             void* stream) {
+  if (n < 0 || !d_norm || (n > 0 && !d_feat)) return fail(XTM_E_ARG, "bad arguments");
+  hipError_t e = launch_feature_stats(d_feat, d_mask, n, d_norm, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "feature stats launch");
+  return XTM_OK;
+}
+
+xtm_status xtm_mlp_init(float* d_theta, uint64_t seed, void* stream) {
+  if (!d_theta) return fail(XTM_E_ARG, "null parameters");
+  hipError_t e = launch_mlp_init(d_theta, seed, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "mlp init launch");
+  return XTM_OK;
+}
+
+xtm_status xtm_mlp_forward(const float* d_theta, const float* d_norm, const float* d_x, int64_t B,
+                           float* d_logit, void* stream) {
+  if (B < 0 || !d_theta || !d_norm || (B > 0 && (!d_x || !d_logit)))
+    return fail(XTM_E_ARG, "bad arguments");
+  hipError_t e = launch_mlp_forward(d_theta, d_norm, d_x, B, d_logit, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "mlp forward launch");
+  return XTM_OK;
+}
+
+xtm_status xtm_mlp_workspace(int64_t B, int64_t* n_floats) {
+  if (B < 0 || !n_floats) return fail(XTM_E_ARG, "bad arguments");
+  *n_floats = mlp_workspace_floats(B);
+  return XTM_OK;
+}
+
+xtm_status xtm_mlp_grad(const float* d_theta, const float* d_norm, const float* d_x,
+                        const float* d_y, int64_t B, float pos_weight, float* d_grad,
+                        float* d_loss, float* d_work, void* stream) {
+  if (B <= 0 || !d_theta || !d_norm || !d_x || !d_y || !d_grad || !d_work)
+    return fail(XTM_E_ARG, "bad arguments");
+  hipError_t e = launch_mlp_grad(d_theta, d_norm, d_x, d_y, B, pos_weight, d_grad, d_loss, d_work,
+                                 (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "mlp grad launch");
+  return XTM_OK;
+}
+
+xtm_status xtm_mlp_adam(float* d_theta, float* d_m, float* d_v, const float* d_grad, int32_t step,
+                        float lr, void* stream) {
+  if (!d_theta || !d_m || !d_v || !d_grad || step < 1) return fail(XTM_E_ARG, "bad arguments");
+  hipError_t e = launch_adam(d_theta, d_m, d_v, d_grad, step, lr, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "adam launch");
+  return XTM_OK;
+}
+
+xtm_status xtm_retire(xtm_particles P, const float* d_logit, float logit_threshold,
+                      uint64_t audit_seed, double audit_fraction, int64_t* h_retired,
+                      int64_t* h_audited, void* stream) {
+  return guarded([&]() -> xtm_status {
+    if (!P || !d_logit) return fail(XTM_E_ARG, "null argument");
+    if (!(audit_fraction >= 0.0) || audit_fraction > 1.0)
+      return fail(XTM_E_ARG, "audit fraction must be in [0, 1]");
+    if (!P->initialised) return fail(XTM_E_STATE, "particle set not initialised");
+    hipStream_t s = (hipStream_t)stream;
+    // audited iff word < ceil(fraction 2^32) (exact integer compare)
+    const double th = std::ceil(audit_fraction * 4294967296.0);
+    const unsigned int at = th >= 4294967295.0 ? 0xFFFFFFFFu : (unsigned int)th;
+    unsigned int* counts = nullptr;
+    if (hipMalloc(&counts, 2 * sizeof(unsigned int)) != hipSuccess)
+      return fail(XTM_E_NOMEM, "retire counters");
+    hipError_t e = hipMemsetAsync(counts, 0, 2 * sizeof(unsigned int), s);
+    if (e == hipSuccess)
+      e = launch_retire(soa_of(P), P->idx[P->cur], P->ctrl, P->alive_upper, d_logit,
+                        logit_threshold, audit_seed, at, counts, s);
+    // rebuild the alive list without the retired particles
+    if (e == hipSuccess) e = launch_iota(P->idx[1 - P->cur], P->n, P->ctrl, (int32_t)P->n, P->turn, s);
+    if (e == hipSuccess)
+      e = launch_epilogue(P->idx[1 - P->cur], P->idx[P->cur], nullptr, P->n > 0 ? P->n : 1,
+                          soa_of(P), P->ctrl, P->blockcnt, P->passes, 0, 0, 0, s);
+    unsigned int hc[2] = {0, 0};
+    if (e == hipSuccess) e = hipMemcpyAsync(hc, counts, sizeof hc, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    hipFree(counts);
+    if (e != hipSuccess) return hip_fail(e, "retire");
+    if (h_retired) *h_retired = hc[0];
+    if (h_audited) *h_audited = hc[1];
+    int64_t alive = 0;
+    return read_alive(P, s, &alive, nullptr);
+  });
 }
 
 xtm_status xtm_sync(void* stream) {

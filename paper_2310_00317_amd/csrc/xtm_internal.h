@@ -56,6 +56,9 @@ struct KernelRef {
   unsigned long long seed;
   int32_t rad_mode;  // 0 off, 1 mean, 2 mean + quantum
   int32_t pad;
+  float* rec;          // early-turn recorder [rec_turns][4][rec_n] (x, px, y, py) or null
+  int32_t rec_turns;   // record the start of absolute turns 0 .. rec_turns-1
+  int32_t rec_n;       // particles in the set (record stride)
 };
 
 // launch helpers implemented in xtm_kernels.hip; all are stream-ordered
@@ -111,4 +114,22 @@ hipError_t launch_line(const LineKernel& k, int32_t n_el, SoA P, const int32_t* 
 namespace xtm {
 hipError_t launch_philox(unsigned long long seed, const uint32_t ctr0[4], int64_t n_blocks,
                          uint32_t* out, hipStream_t s);
+// learned early stop (xtm_learn.hip)
+hipError_t launch_mlp_forward(const float* theta, const float* norm, const float* X, int64_t B,
+                              float* logit, hipStream_t s);
+int64_t mlp_workspace_floats(int64_t B);
+hipError_t launch_mlp_grad(const float* theta, const float* norm, const float* X, const float* Y,
+                           int64_t B, float pos_weight, float* grad, float* loss, float* work,
+                           hipStream_t s);
+hipError_t launch_adam(float* theta, float* m, float* v, const float* grad, int32_t step, float lr,
+                       hipStream_t s);
+hipError_t launch_mlp_init(float* theta, unsigned long long seed, hipStream_t s);
+hipError_t launch_features(const float* rec, int64_t n, const double twiss4[4], double emit,
+                           double r_ap, const float2* tw, const float* win, float* out,
+                           hipStream_t s);
+hipError_t launch_feature_stats(const float* f, const int32_t* mask, int64_t n, float* norm,
+                                hipStream_t s);
+hipError_t launch_retire(SoA P, const int32_t* idx, const int32_t* ctrl, int64_t grid_upper,
+                         const float* logit, float threshold, unsigned long long audit_seed,
+                         unsigned int audit_threshold, unsigned int* counts, hipStream_t s);
 }

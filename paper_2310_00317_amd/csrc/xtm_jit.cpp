@@ -202,7 +202,8 @@ std::string generate(const Decomp& d) {
        "struct SoA { double *x, *px, *y, *py, *zeta, *delta, *ptau, *rpp, *rvv;\n"
        "             int *state, *at_element, *at_turn; long long* pid; };\n"
        "struct KRef { double beta0, two_over_beta0, gamma0, c_mean, c_quant, p0c;\n"
-       "              unsigned long long seed; int rad_mode; int pad; };\n"
+       "              unsigned long long seed; int rad_mode; int pad;\n"
+       "              float* rec; int rec_turns; int rec_n; };\n"
        "#define RAD(kx, ky, lr, j) xtmm::radiate_at(q, kx, ky, lr, r.rad_mode, r.seed, pid, \\\n"
        "    t0 + t, ec + (j), r.gamma0, r.c_mean, r.c_quant, r.p0c, beta0, two_over_beta0)\n"
        "#define MAXW " << maxw << "\n"
@@ -234,6 +235,13 @@ std::string generate(const Decomp& d) {
        "  int b = 0;\n"
        "  for (int t = 0; t < n_turns; ++t) {\n"
        "    const int enc_t = t * n_el + 1;\n"
+       "    if (r.rec && t0 + t < r.rec_turns && code == 0) {\n"
+       "      const unsigned long long base = (unsigned long long)(t0 + t) * 4 * r.rec_n + pi;\n"
+       "      r.rec[base] = (float)q.x;\n"
+       "      r.rec[base + r.rec_n] = (float)q.px;\n"
+       "      r.rec[base + 2ull * r.rec_n] = (float)q.y;\n"
+       "      r.rec[base + 3ull * r.rec_n] = (float)q.py;\n"
+       "    }\n"
        "    for (int c = 0; c < n_cells; ++c) {\n"
        "      const int cn = (c + 1 == n_cells) ? 0 : c + 1;\n"
        "      const int offn = cells[4 * cn + 1], nwn = cells[4 * cn + 3];\n"

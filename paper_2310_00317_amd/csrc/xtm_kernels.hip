@@ -720,6 +720,13 @@ __global__ void __launch_bounds__(256) k_track4(const uint64_t* __restrict__ tab
   for (int32_t t = 0; t < n_turns; ++t) {
     uint32_t off = 0;
     const int enc0 = t * n_el + 1;
+    if (r.rec && t0 + t < r.rec_turns && code == 0) {
+      const size_t base = (size_t)(t0 + t) * 4 * r.rec_n + p;
+      r.rec[base] = (float)q.x;
+      r.rec[base + r.rec_n] = (float)q.px;
+      r.rec[base + 2 * (size_t)r.rec_n] = (float)q.y;
+      r.rec[base + 3 * (size_t)r.rec_n] = (float)q.py;
+    }
     for (int32_t e = 0; e < n_el; ++e) {
       off = __builtin_amdgcn_readfirstlane(off);
       const uint64_t* w = tab + off;
