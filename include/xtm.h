@@ -231,6 +231,43 @@ xtm_status xtm_philox4x32_10(uint64_t seed, const uint32_t ctr0[4], int64_t n_bl
                              uint32_t* d_out, void* stream);
 
 /* ---------------------------------------------------------------------------
+   Batched tracking of lattice variants (e.g. the same machine under different
+   field-error seeds) in one launch per chunk.  A batch references
+   n_variants lattices (not copied: they must outlive the batch) with the same
+   element count and reference.  One particle set holds all variants' particles:
+   variant v owns slots first_slot[v] .. first_slot[v+1]-1 (host array of
+   n_variants + 1 ascending values from 0 to the set's size).  Each particle
+   follows exactly the maps of its own variant, so the results equal tracking
+   each variant's particles through its lattice alone, bit for bit.  Forward
+   only; the register-loss interpreter (variant 0 or 4); the options and
+   statistics are those of xtm_track.  XTM_E_ARG for a bad partition,
+   XTM_E_REFERENCE for mixed references, XTM_E_UNSUPPORTED for other kernel
+   variants or backward tracking. */
+typedef struct xtm_batch_s* xtm_batch;
+xtm_status xtm_batch_create(const xtm_lattice* lattices, int32_t n_variants, xtm_batch* out);
+xtm_status xtm_batch_destroy(xtm_batch b);
+xtm_status xtm_track_batched(xtm_batch b, xtm_particles p, const int64_t* first_slot,
+                             int32_t n_turns, const xtm_track_opts* opts, void* stream,
+                             xtm_track_stats* stats);
+
+/* Launch-plan autotuner.  Times every candidate (kernel variant 5 when the
+   line has one, 4; blocks of 64, 128 and 256 lanes) for probe_turns turns on
+   a scratch copy of the set (the set itself is not advanced), keeps the
+   fastest as the plan of the lattice (or batch), and reports it.  Later
+   xtm_track / xtm_track_batched calls whose options leave both `variant`
+   and `block` at 0 use the plan.  Give exactly one of `lat` and `batch`
+   (`first_slot` as for xtm_track_batched with a batch, else ignored).
+   Synchronises; allocates a scratch set of the same size. */
+typedef struct xtm_plan {
+  int32_t variant;      /* kernel variant chosen (4 or 5) */
+  int32_t block;        /* lanes per workgroup chosen */
+  double passes_per_s;  /* its measured rate, chunk epilogues included */
+} xtm_plan;
+xtm_status xtm_autotune(xtm_lattice lat, xtm_batch batch, xtm_particles p,
+                        const int64_t* first_slot, int32_t probe_turns, void* stream,
+                        xtm_plan* out);
+
+/* ---------------------------------------------------------------------------
    Learned early stop.  The paper cites machine-learned dynamic-aperture
    estimates beside chaos indicators (applications, dynamic aperture) without
    fixing a model; the network, its features and the retire policy below are

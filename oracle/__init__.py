@@ -292,3 +292,33 @@ def uniform(wa: int, wb: int) -> float:
 
 def gauss_at(seed: int, pid: int, turn: int, element: int, draw: int = 0) -> float:
     return float(lib().oracle_gauss_at(seed, pid, turn, element, draw))
+
+
+# ------------------------------------------------------------ retire policy
+def audit_mask(seed: int, pids, fraction: float = 0.05) -> np.ndarray:
+    """Audit set of the retire policy: particle id k is audited iff the first
+    word of Philox4x32-10 with key = seed and counter (k_lo, k_hi, 2^32 - 1, 0)
+    is below ceil(fraction 2^32), an exact integer comparison."""
+    import math
+    th = min(math.ceil(fraction * 2.0 ** 32), 0xFFFFFFFF)
+    key = (seed & 0xFFFFFFFF, (seed >> 32) & 0xFFFFFFFF)
+    out = np.zeros(len(pids), dtype=bool)
+    for i, k in enumerate(np.asarray(pids, dtype=np.int64)):
+        k = int(k) & 0xFFFFFFFFFFFFFFFF
+        w = philox((k & 0xFFFFFFFF, k >> 32, 0xFFFFFFFF, 0), key)
+        out[i] = int(w[0]) < th
+    return out
+
+
+def dynamic_aperture(state, radii, n_r: int, n_theta: int) -> np.ndarray:
+    """Per-ray dynamic aperture of a polar scan (particle index j n_r + i is
+    radius i of ray j): the smallest radius on the ray whose particle was lost
+    (state <= 0); rays with no loss get +inf (censored at the scan's edge)."""
+    st = np.asarray(state).reshape(n_theta, n_r)
+    r = np.asarray(radii, dtype=np.float64).reshape(n_theta, n_r)
+    out = np.full(n_theta, np.inf)
+    for j in range(n_theta):
+        lost = np.nonzero(st[j] <= 0)[0]
+        if len(lost):
+            out[j] = r[j, lost].min()
+    return out

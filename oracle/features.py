@@ -89,13 +89,20 @@ def features(rec: np.ndarray, twiss4, emit: float, r_aperture: float) -> np.ndar
     return f
 
 
-def record(elements, ref, coords, turns: int = 2 * WINDOW, nthreads: int = 0) -> tuple:
+def record(elements, ref, coords, turns: int = 2 * WINDOW, nthreads: int = 0,
+           fp32: bool = False) -> tuple:
     """Track with the oracle and record (x, px, y, py) at element 0 at the
-    start of each turn; returns (rec [turns, 4, N], oracle particles)."""
+    start of each turn; returns (rec [turns, 4, N], oracle particles).  A
+    particle lost during turn u keeps, from turn u + 1 on, the coordinates it
+    had when it entered the element that lost it.  ``fp32`` rounds the record
+    to single precision, the recorder's storage format (values returned as
+    float64)."""
     import oracle
     p = oracle.init(coords, ref)
     rec = np.zeros((turns, 4, p.n))
     for t in range(turns):
         rec[t] = np.stack([p.x, p.px, p.y, p.py])
         oracle.track(elements, ref, p, 1, nthreads=nthreads)
+    if fp32:
+        rec = rec.astype(np.float32).astype(np.float64)
     return rec, p

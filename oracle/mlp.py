@@ -55,6 +55,16 @@ def bf16(x) -> np.ndarray:
     return np.where(np.isnan(f), np.nan, out)
 
 
+def standardise(x, norm) -> np.ndarray:
+    """Network input from raw features: (x - mean) * inv_std with
+    norm = [mean[16], inv_std[16]], evaluated in FP32 (two correctly rounded
+    operations) as the kernels do, so that the BF16 rounding that follows
+    sees the same value."""
+    x = np.asarray(x, dtype=np.float32)
+    nm = np.asarray(norm, dtype=np.float32)
+    return ((x - nm[:N_IN]) * nm[N_IN:]).astype(np.float64)
+
+
 def forward(theta, x, rounding: bool = True) -> dict:
     """Returns a dict of the intermediate values and the logits z3 [B]."""
     p = unpack(theta)

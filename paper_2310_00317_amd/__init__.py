@@ -57,6 +57,11 @@ class TrackStats(ctypes.Structure):
                 ("kernel_ms", ctypes.c_double)]
 
 
+class Plan(ctypes.Structure):
+    _fields_ = [("variant", ctypes.c_int32), ("block", ctypes.c_int32),
+                ("passes_per_s", ctypes.c_double)]
+
+
 _lib = None
 
 
@@ -85,6 +90,10 @@ def lib() -> ctypes.CDLL:
             "xtm_get_losses": ([vp, vp, vp, vp, vp], i32),
             "xtm_sync": ([vp], i32),
             "xtm_philox4x32_10": ([ctypes.c_uint64, vp, i64, vp, vp], i32),
+            "xtm_batch_create": ([vp, i32, vp], i32),
+            "xtm_batch_destroy": ([vp], i32),
+            "xtm_track_batched": ([vp, vp, vp, i32, vp, vp, vp], i32),
+            "xtm_autotune": ([vp, vp, vp, vp, i32, vp, vp], i32),
             "xtm_features": ([vp, i64, vp, ctypes.c_double, ctypes.c_double, vp, vp], i32),
             "xtm_feature_stats": ([vp, vp, i64, vp, vp], i32),
             "xtm_mlp_init": ([vp, ctypes.c_uint64, vp], i32),
@@ -269,6 +278,69 @@ def track(lattice: Lattice, particles: Particles, n_turns: int, turns_per_chunk:
     if full_stats:
         return s
     return (int(s.passes), int(s.alive)) if stats else None
+
+
+class Batch:
+    """Lattice variants tracked together; keeps the lattices alive."""
+
+    def __init__(self, lattices):
+        self.lattices = list(lattices)
+        arr = (ctypes.c_void_p * len(self.lattices))(*[l.handle.value for l in self.lattices])
+        h = ctypes.c_void_p()
+        check(lib().xtm_batch_create(arr, len(self.lattices), ctypes.byref(h)), "xtm_batch_create")
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().xtm_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _opts(turns_per_chunk=0, block=0, compact=True, graph=False, time_kernels=False, variant=0,
+          radiation=0, seed=0, record=None, n=0):
+    rec_turns, rec_ptr = 0, None
+    if record is not None:
+        if tuple(record.shape[1:]) != (4, n) or not record.is_contiguous():
+            raise ValueError("record must be a contiguous [T, 4, n] tensor")
+        rec_turns, rec_ptr = int(record.shape[0]), record.data_ptr()
+    return TrackOpts(int(turns_per_chunk), int(block), 0 if compact else 1, 1 if graph else 0,
+                     1 if time_kernels else 0, int(variant), int(radiation), rec_turns, int(seed),
+                     rec_ptr)
+
+
+def track_batched(batch: Batch, particles: Particles, first_slot, n_turns: int,
+                  stream=None, full_stats: bool = False, **kw):
+    """Track all variants n_turns; variant v owns slots first_slot[v]..first_slot[v+1]-1."""
+    fs = np.ascontiguousarray(first_slot, dtype=np.int64)
+    o = _opts(n=particles.n, **kw)
+    s = TrackStats()
+    check(lib().xtm_track_batched(batch.handle, particles.handle,
+                                  fs.ctypes.data_as(ctypes.c_void_p), int(n_turns),
+                                  ctypes.byref(o), _stream(stream), ctypes.byref(s)),
+          "xtm_track_batched")
+    return s if full_stats else (int(s.passes), int(s.alive))
+
+
+def autotune(particles: Particles, lattice: Lattice = None, batch: Batch = None, first_slot=None,
+             probe_turns: int = 2, stream=None) -> Plan:
+    fs = None if first_slot is None else np.ascontiguousarray(first_slot, dtype=np.int64)
+    plan = Plan()
+    check(lib().xtm_autotune(None if lattice is None else lattice.handle,
+                             None if batch is None else batch.handle, particles.handle,
+                             None if fs is None else fs.ctypes.data_as(ctypes.c_void_p),
+                             int(probe_turns), _stream(stream), ctypes.byref(plan)),
+          "xtm_autotune")
+    return plan
 
 
 def track_backward(lattice: Lattice, particles: Particles, n_turns: int, stats: bool = True,

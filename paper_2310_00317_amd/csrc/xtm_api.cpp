@@ -69,6 +69,19 @@ struct xtm_lattice_s {
   int32_t* bwd_seg_d = nullptr;
   // per-line kernels, compiled on first use
   xtm::LineKernel fwd_line, bwd_line;
+  // launch plan chosen by xtm_autotune (0 = none): used when the caller's
+  // options leave the kernel variant and block size at 0
+  int32_t plan_variant = 0, plan_block = 0;
+};
+
+struct xtm_batch_s {
+  std::vector<xtm_lattice_s*> lats;
+  int32_t n_el = 0;
+  RefQ ref{};
+  uint64_t** tabs_d = nullptr;       // forward element table of each variant
+  int32_t* first_d = nullptr;        // slot partition (n_variants + 1), device
+  std::vector<int64_t> first_h;      // the partition last uploaded
+  int32_t plan_block = 0;
 };
 
 struct GraphKey {
@@ -289,6 +302,7 @@ int32_t auto_chunk(int64_t n, int32_t n_el, int32_t n_turns) {
 }
 
 struct ChunkPlan {
+  const xtm_batch_s* batch;  // batched tracking, or null
   int32_t rad_mode;
   uint64_t seed;
   float* rec;
@@ -328,7 +342,11 @@ hipError_t enqueue_chunks(xtm_lattice_s* L, xtm_particles_s* P, const ChunkPlan&
       ev->push_back(b);
       if ((e = hipEventRecord(a, s)) != hipSuccess) return e;
     }
-    if (c.variant == 5)
+    if (c.batch)
+      e = launch_track_batched(c.batch->tabs_d, c.batch->first_d, (int32_t)c.batch->lats.size(),
+                               L->n_el, soa, in, P->ctrl, P->alive_upper, c.block, k,
+                               c.backward ? 1 : 0, kr, s);
+    else if (c.variant == 5)
       e = launch_line(*c.line, L->n_el, soa, in, P->ctrl, P->alive_upper, c.block, k,
                       c.backward ? 1 : 0, kr, s);
     else
@@ -341,7 +359,12 @@ hipError_t enqueue_chunks(xtm_lattice_s* L, xtm_particles_s* P, const ChunkPlan&
     e = launch_epilogue(in, out, replay ? P->lost : nullptr, P->alive_upper, soa, P->ctrl,
                         P->blockcnt, P->passes, L->n_el, k, c.backward ? 1 : 0, s);
     if (e != hipSuccess) return e;
-    if (replay) {
+    if (replay && c.batch) {
+      e = launch_replay_batched(c.batch->tabs_d, c.batch->first_d, (int32_t)c.batch->lats.size(),
+                                L->n_el, soa, P->lost, P->ctrl, P->alive_upper,
+                                c.backward ? 1 : 0, kr, s);
+      if (e != hipSuccess) return e;
+    } else if (replay) {
       e = launch_replay(c.tab, L->n_el, soa, P->lost, P->ctrl, P->alive_upper, c.backward ? 1 : 0,
                         kr, s);
       if (e != hipSuccess) return e;
@@ -361,7 +384,7 @@ int32_t flips(const ChunkPlan& c) {
 
 xtm_status run_graph(xtm_lattice_s* L, xtm_particles_s* P, const ChunkPlan& c, hipStream_t s,
                      int32_t* launches) {
-  GraphKey key{L, c.n_turns, c.chunk, c.block, c.variant, c.backward ? 1 : 0, c.compact ? 1 : 0,
+  GraphKey key{c.batch ? (const void*)c.batch : (const void*)L, c.n_turns, c.chunk, c.block, c.variant, c.backward ? 1 : 0, c.compact ? 1 : 0,
                P->cur, c.rad_mode, P->alive_upper, c.seed, c.rec, c.rec_turns};
   for (const GraphEntry& g : P->graphs) {
     if (g.key == key) {
@@ -400,7 +423,7 @@ void drop_graphs(xtm_particles_s* P) {
 
 xtm_status run_turns(xtm_lattice_s* L, xtm_particles_s* P, int32_t n_turns,
                      const xtm_track_opts* o, hipStream_t s, xtm_track_stats* stats,
-                     bool backward) {
+                     bool backward, const xtm_batch_s* B = nullptr) {
   if (!L || !P) return fail(XTM_E_ARG, "null handle");
   if (n_turns < 0) return fail(XTM_E_ARG, "n_turns must be >= 0");
   if (!P->initialised) return fail(XTM_E_STATE, "particle set not initialised");
@@ -409,6 +432,7 @@ xtm_status run_turns(xtm_lattice_s* L, xtm_particles_s* P, int32_t n_turns,
   if (backward && P->turn - n_turns < INT32_MIN / 2) return fail(XTM_E_ARG, "turn underflow");
   if (!backward && (int64_t)P->turn + n_turns > INT32_MAX / 2) return fail(XTM_E_ARG, "turn overflow");
   ChunkPlan c;
+  c.batch = B;
   c.rad_mode = o ? o->radiation : 0;
   c.seed = o ? o->rng_seed : 0;
   c.rec = o ? o->record_buf : nullptr;
@@ -417,16 +441,24 @@ xtm_status run_turns(xtm_lattice_s* L, xtm_particles_s* P, int32_t n_turns,
     return fail(XTM_E_ARG, "the recorder needs record_turns >= 0 and forward tracking");
   if (c.rad_mode < 0 || c.rad_mode > 2) return fail(XTM_E_ARG, "radiation must be 0, 1 or 2");
   if (c.rad_mode && backward) return fail(XTM_E_ARG, "backward tracking with radiation is undefined");
-  c.block = (o && o->block) ? o->block : 256;
+  const bool use_plan = !(o && (o->block || o->variant));
+  const int32_t plan_block = B ? B->plan_block : L->plan_block;
+  c.block = (o && o->block) ? o->block : (use_plan && plan_block ? plan_block : 256);
   if (c.block < 64 || c.block > 256 || c.block % 64)
     return fail(XTM_E_ARG, "block must be 64, 128, 192 or 256");
   c.compact = !(o && o->no_compact) || backward;
-  c.variant = (o && o->variant) ? o->variant : 0;
+  c.variant = (o && o->variant) ? o->variant : (use_plan && !B ? L->plan_variant : 0);
   if (c.variant < 0 || c.variant > 5) return fail(XTM_E_ARG, "kernel variant must be 0..5");
+  if (B) {
+    if (backward) return fail(XTM_E_UNSUPPORTED, "batched tracking is forward only");
+    if (c.variant != 0 && c.variant != 4)
+      return fail(XTM_E_UNSUPPORTED, "batched tracking runs the register-loss interpreter (variant 4)");
+    c.variant = 4;
+  }
   c.line = nullptr;
   if ((c.rad_mode || c.rec) && c.variant >= 1 && c.variant <= 3)
     return fail(XTM_E_UNSUPPORTED, "kernel variants 1-3 implement neither radiation nor the recorder");
-  if (c.variant == 0 || c.variant == 5) {
+  if (!B && (c.variant == 0 || c.variant == 5)) {
     // the per-line kernel, compiled on first use; the default falls back to
     // the register-loss interpreter if the line has no compact cell structure
     LineKernel& lk = backward ? L->bwd_line : L->fwd_line;
@@ -702,6 +734,202 @@ xtm_status xtm_track_backward(xtm_lattice L, xtm_particles P, int32_t n_turns, v
                               xtm_track_stats* stats) {
   return guarded([&]() {
     return run_turns(L, P, n_turns, nullptr, (hipStream_t)stream, stats, true);
+  });
+}
+
+// ------------------------------------------------------------ batches
+xtm_status xtm_batch_create(const xtm_lattice* lattices, int32_t n_variants, xtm_batch* out) {
+  return guarded([&]() -> xtm_status {
+    if (!out) return fail(XTM_E_ARG, "out is null");
+    *out = nullptr;
+    if (!lattices || n_variants < 1) return fail(XTM_E_ARG, "need at least one lattice");
+    for (int32_t v = 0; v < n_variants; ++v) {
+      if (!lattices[v]) return fail(XTM_E_ARG, "null lattice " + std::to_string(v));
+      if (lattices[v]->n_el != lattices[0]->n_el)
+        return fail(XTM_E_ARG, "all lattices of a batch need the same element count");
+      if (!same_ref(lattices[v]->ref, lattices[0]->ref))
+        return fail(XTM_E_REFERENCE, "all lattices of a batch need the same reference");
+    }
+    auto* B = new xtm_batch_s();
+    B->lats.assign(lattices, lattices + n_variants);
+    B->n_el = lattices[0]->n_el;
+    B->ref = lattices[0]->ref;
+    std::vector<uint64_t*> t(n_variants);
+    for (int32_t v = 0; v < n_variants; ++v) t[v] = lattices[v]->fwd_d;
+    if (hipMalloc(&B->tabs_d, n_variants * sizeof(uint64_t*)) != hipSuccess ||
+        hipMalloc(&B->first_d, (n_variants + 1) * sizeof(int32_t)) != hipSuccess ||
+        hipMemcpy(B->tabs_d, t.data(), n_variants * sizeof(uint64_t*), hipMemcpyHostToDevice) !=
+            hipSuccess) {
+      hipFree(B->tabs_d);
+      hipFree(B->first_d);
+      delete B;
+      return fail(XTM_E_NOMEM, "batch tables");
+    }
+    *out = B;
+    return XTM_OK;
+  });
+}
+
+xtm_status xtm_batch_destroy(xtm_batch B) {
+  if (!B) return XTM_OK;
+  hipFree(B->tabs_d);
+  hipFree(B->first_d);
+  delete B;
+  return XTM_OK;
+}
+
+namespace {
+xtm_status set_partition(xtm_batch_s* B, xtm_particles_s* P, const int64_t* first_slot,
+                         hipStream_t s) {
+  const size_t nv = B->lats.size();
+  if (!first_slot) return fail(XTM_E_ARG, "null slot partition");
+  if (first_slot[0] != 0 || first_slot[nv] != P->n)
+    return fail(XTM_E_ARG, "the slot partition must run from 0 to the set's size");
+  for (size_t v = 0; v < nv; ++v)
+    if (first_slot[v + 1] < first_slot[v]) return fail(XTM_E_ARG, "slot partition not ascending");
+  std::vector<int64_t> f(first_slot, first_slot + nv + 1);
+  if (f == B->first_h) return XTM_OK;
+  std::vector<int32_t> f32(f.begin(), f.end());
+  // the previous partition may still be read by queued kernels
+  HIP_TRY(hipStreamSynchronize(s), "synchronise");
+  HIP_TRY(hipMemcpy(B->first_d, f32.data(), f32.size() * sizeof(int32_t), hipMemcpyHostToDevice),
+          "partition upload");
+  B->first_h = f;
+  return XTM_OK;
+}
+}  // namespace
+
+xtm_status xtm_track_batched(xtm_batch B, xtm_particles P, const int64_t* first_slot,
+                             int32_t n_turns, const xtm_track_opts* opts, void* stream,
+                             xtm_track_stats* stats) {
+  return guarded([&]() -> xtm_status {
+    if (!B || !P) return fail(XTM_E_ARG, "null handle");
+    xtm_status st = set_partition(B, P, first_slot, (hipStream_t)stream);
+    if (st != XTM_OK) return st;
+    return run_turns(B->lats[0], P, n_turns, opts, (hipStream_t)stream, stats, false, B);
+  });
+}
+
+// ------------------------------------------------------------ autotuner
+namespace {
+// A scratch copy of a particle set: its own arrays, bound as a set.
+struct Scratch {
+  void* mem = nullptr;
+  xtm_particles_s* P = nullptr;
+  ~Scratch() {
+    if (P) xtm_particles_release(P);
+    hipFree(mem);
+  }
+};
+
+xtm_status make_scratch(const xtm_particles_s* src, Scratch* sc) {
+  const int64_t m = src->n > 0 ? src->n : 1;
+  const size_t bytes = (size_t)m * (9 * sizeof(double) + 3 * sizeof(int32_t) + sizeof(int64_t));
+  HIP_TRY(hipMalloc(&sc->mem, bytes), "scratch particles");
+  char* b = static_cast<char*>(sc->mem);
+  xtm_arrays a{};
+  double** f[9] = {&a.x, &a.px, &a.y, &a.py, &a.zeta, &a.delta, &a.ptau, &a.rpp, &a.rvv};
+  for (int k = 0; k < 9; ++k) { *f[k] = reinterpret_cast<double*>(b); b += m * sizeof(double); }
+  a.particle_id = reinterpret_cast<int64_t*>(b); b += m * sizeof(int64_t);
+  int32_t** g[3] = {&a.state, &a.at_element, &a.at_turn};
+  for (int k = 0; k < 3; ++k) { *g[k] = reinterpret_cast<int32_t*>(b); b += m * sizeof(int32_t); }
+  a.n = src->n;
+  xtm_reference r{src->ref.mass0, src->ref.charge0, src->ref.p0c};
+  return xtm_particles_bind(&a, &r, &sc->P);
+}
+
+xtm_status copy_set(const xtm_particles_s* src, xtm_particles_s* dst, hipStream_t s) {
+  const size_t nd = (size_t)src->n * sizeof(double), ni = (size_t)src->n * sizeof(int32_t);
+  const xtm_arrays &a = src->a, &b = dst->a;
+  const double* fs[9] = {a.x, a.px, a.y, a.py, a.zeta, a.delta, a.ptau, a.rpp, a.rvv};
+  double* fd[9] = {b.x, b.px, b.y, b.py, b.zeta, b.delta, b.ptau, b.rpp, b.rvv};
+  for (int k = 0; k < 9; ++k) HIP_TRY(hipMemcpyAsync(fd[k], fs[k], nd, hipMemcpyDeviceToDevice, s), "copy");
+  const int32_t* is[3] = {a.state, a.at_element, a.at_turn};
+  int32_t* id[3] = {b.state, b.at_element, b.at_turn};
+  for (int k = 0; k < 3; ++k) HIP_TRY(hipMemcpyAsync(id[k], is[k], ni, hipMemcpyDeviceToDevice, s), "copy");
+  HIP_TRY(hipMemcpyAsync(b.particle_id, a.particle_id, src->n * sizeof(int64_t),
+                         hipMemcpyDeviceToDevice, s), "copy");
+  HIP_TRY(launch_fill_i64(dst->passes, 0, s), "clear passes");
+  return xtm_particles_reset(dst, src->turn, s);
+}
+}  // namespace
+
+xtm_status xtm_autotune(xtm_lattice L, xtm_batch B, xtm_particles P, const int64_t* first_slot,
+                        int32_t probe_turns, void* stream, xtm_plan* out) {
+  return guarded([&]() -> xtm_status {
+    if ((!L && !B) || (L && B) || !P) return fail(XTM_E_ARG, "give one of lattice or batch, and a set");
+    if (probe_turns < 1) return fail(XTM_E_ARG, "probe_turns must be >= 1");
+    if (!P->initialised) return fail(XTM_E_STATE, "particle set not initialised");
+    hipStream_t s = (hipStream_t)stream;
+    xtm_lattice_s* lat = B ? B->lats[0] : L;
+    if (!same_ref(lat->ref, P->ref)) return fail(XTM_E_REFERENCE, "reference mismatch");
+    if (B) {
+      xtm_status st = set_partition(B, P, first_slot, s);
+      if (st != XTM_OK) return st;
+    }
+    Scratch sc;
+    xtm_status st = make_scratch(P, &sc);
+    if (st != XTM_OK) return st;
+    std::vector<int32_t> variants;
+    if (!B && lat->n_el > 0) {
+      if (!lat->fwd_line.tried) {
+        lat->fwd_line.tried = true;
+        build_line_kernel(lat->fwd_h, lat->n_el, &lat->fwd_line);
+      }
+      if (lat->fwd_line.ok) variants.push_back(5);
+    }
+    variants.push_back(4);
+    const int32_t blocks[3] = {64, 128, 256};
+    xtm_plan best{};
+    double best_rate = -1.0;
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0), "event");
+    HIP_TRY(hipEventCreate(&e1), "event");
+    for (int32_t v : variants) {
+      for (int32_t blk : blocks) {
+        xtm_track_opts o{};
+        o.variant = v;
+        o.block = blk;
+        // one untimed run (first use), then the timed one
+        for (int rep = 0; rep < 2 && st == XTM_OK; ++rep) {
+          st = copy_set(P, sc.P, s);
+          if (st != XTM_OK) break;
+          if (hipEventRecord(e0, s) != hipSuccess) { st = fail(XTM_E_HIP, "event"); break; }
+          st = run_turns(lat, sc.P, probe_turns, &o, s, nullptr, false, B);
+          if (st != XTM_OK) break;
+          if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+            st = fail(XTM_E_HIP, "event");
+            break;
+          }
+          int64_t alive = 0, passes = 0;
+          st = read_alive(sc.P, s, &alive, &passes);
+          float ms = 0.f;
+          hipEventElapsedTime(&ms, e0, e1);
+          if (rep == 1 && st == XTM_OK) {
+            const double rate = ms > 0 ? (double)passes / (ms * 1e-3) : 0.0;
+            if (rate > best_rate) {
+              best_rate = rate;
+              best.variant = v;
+              best.block = blk;
+              best.passes_per_s = rate;
+            }
+          }
+        }
+        if (st != XTM_OK) break;
+      }
+      if (st != XTM_OK) break;
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (st != XTM_OK) return st;
+    if (B) {
+      B->plan_block = best.block;
+    } else {
+      L->plan_variant = best.variant;
+      L->plan_block = best.block;
+    }
+    if (out) *out = best;
+    return XTM_OK;
   });
 }
 

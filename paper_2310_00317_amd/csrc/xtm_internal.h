@@ -84,6 +84,14 @@ hipError_t launch_epilogue(const int32_t* idx_in, int32_t* idx_out, int32_t* los
                            hipStream_t s);
 // coordinates of the particles in lost[0..ctrl[3]) re-tracked from the chunk
 // start to their loss point (for kernels that record losses in registers)
+hipError_t launch_track_batched(const uint64_t* const* tabs, const int32_t* first_slot, int32_t nv,
+                                int32_t n_el, SoA P, const int32_t* idx, const int32_t* ctrl,
+                                int64_t grid_upper, int32_t block, int32_t n_turns,
+                                int32_t backward, KernelRef r, hipStream_t s);
+hipError_t launch_replay_batched(const uint64_t* const* tabs, const int32_t* first_slot, int32_t nv,
+                                 int32_t n_el, SoA P, const int32_t* lost, const int32_t* ctrl,
+                                 int64_t grid_upper, int32_t backward, KernelRef r,
+                                 hipStream_t s);
 hipError_t launch_replay(const uint64_t* tab, int32_t n_el, SoA P, const int32_t* lost,
                          const int32_t* ctrl, int64_t grid_upper, int32_t backward, KernelRef r,
                          hipStream_t s);

@@ -702,16 +702,15 @@ __device__ __forceinline__ void store_pt(const SoA& P, int32_t p, const xtmm::Pt
   P.delta[p] = q.delta; P.ptau[p] = q.ptau; P.rpp[p] = q.rpp; P.rvv[p] = q.rvv;
 }
 
-__global__ void __launch_bounds__(256) k_track4(const uint64_t* __restrict__ tab, int32_t n_el,
-                                                SoA P, const int32_t* __restrict__ idx,
-                                                const int32_t* __restrict__ ctrl, int32_t n_turns,
-                                                int32_t backward, KernelRef r) {
-  const int32_t t0 = ctrl[1];
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const bool in_range = i < ctrl[0];
-  const int32_t p = in_range ? idx[i] : 0;
-  const bool tracked = in_range && P.state[p] == 1;
-  int code = tracked ? 0 : 1;  // 0: alive; else (turn * n_el + element + 1)
+// One chunk of n_turns for the lanes with `active` set (the others idle):
+// element parameters through scalar loads (the table pointer is wave-uniform),
+// a loss recorded in registers (code = turn * n_el + element + 1) and the
+// coordinates at the lost element's entry restored afterwards by k_replay.
+__device__ __forceinline__ void track_lanes(const uint64_t* __restrict__ tab, int32_t n_el,
+                                            SoA P, int32_t p, bool active, int32_t t0,
+                                            int32_t n_turns, int32_t backward,
+                                            const KernelRef& r) {
+  int code = active ? 0 : 1;
   int st = 1;
   if (__all(code != 0)) return;
   xtmm::Pt q;
@@ -741,7 +740,7 @@ __global__ void __launch_bounds__(256) k_track4(const uint64_t* __restrict__ tab
     }
     if (__all(code != 0)) break;
   }
-  if (!tracked) return;
+  if (!active) return;
   if (code == 0) {
     store_pt(P, p, q);
     P.at_turn[p] = backward ? t0 - n_turns : t0 + n_turns;
@@ -754,16 +753,64 @@ __global__ void __launch_bounds__(256) k_track4(const uint64_t* __restrict__ tab
   }
 }
 
-// Re-track particles lost during the chunk from their chunk-start state up to
-// (not including) the element that lost them, and store those coordinates.
-__global__ void __launch_bounds__(256) k_replay(const uint64_t* __restrict__ tab, int32_t n_el,
-                                                SoA P, const int32_t* __restrict__ lost,
-                                                const int32_t* __restrict__ ctrl,
+__global__ void __launch_bounds__(256) k_track4(const uint64_t* __restrict__ tab, int32_t n_el,
+                                                SoA P, const int32_t* __restrict__ idx,
+                                                const int32_t* __restrict__ ctrl, int32_t n_turns,
                                                 int32_t backward, KernelRef r) {
   const int32_t t0 = ctrl[1];
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= ctrl[3]) return;
-  const int32_t p = lost[i];
+  const bool in_range = i < ctrl[0];
+  const int32_t p = in_range ? idx[i] : 0;
+  const bool tracked = in_range && P.state[p] == 1;
+  track_lanes(tab, n_el, P, p, tracked, t0, n_turns, backward, r);
+}
+
+// Variant of the slot: the v with first_slot[v] <= p < first_slot[v + 1].
+__device__ __forceinline__ int32_t variant_of(const int32_t* __restrict__ first_slot, int32_t nv,
+                                              int32_t p) {
+  int32_t lo = 0, hi = nv;  // first_slot[lo] <= p < first_slot[hi]
+  while (hi - lo > 1) {
+    const int32_t mid = (lo + hi) >> 1;
+    if (first_slot[mid] <= p) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+// Batched form: the set's slots are split into nv contiguous variant ranges,
+// each tracked through its own element table.  A wave whose lanes span k
+// variants makes k passes, one per variant in ascending order, each with the
+// other lanes idle; with order-preserving compaction only waves at a range
+// boundary have k > 1.
+__global__ void __launch_bounds__(256) k_track4_batched(const uint64_t* const* __restrict__ tabs,
+                                                        const int32_t* __restrict__ first_slot,
+                                                        int32_t nv, int32_t n_el, SoA P,
+                                                        const int32_t* __restrict__ idx,
+                                                        const int32_t* __restrict__ ctrl,
+                                                        int32_t n_turns, int32_t backward,
+                                                        KernelRef r) {
+  const int32_t t0 = ctrl[1];
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool in_range = i < ctrl[0];
+  const int32_t p = in_range ? idx[i] : 0;
+  bool pending = in_range && P.state[p] == 1;
+  const int32_t v = pending ? variant_of(first_slot, nv, p) : 0x7fffffff;
+  while (__any(pending)) {
+    // smallest pending variant of the wave
+    int32_t m = pending ? v : 0x7fffffff;
+    for (int off = 32; off > 0; off >>= 1) m = min(m, __shfl_xor(m, off, 64));
+    const int32_t vu = __builtin_amdgcn_readfirstlane(m);
+    const bool active = pending && v == vu;
+    const uint64_t* tab = tabs[vu];
+    track_lanes(tab, n_el, P, p, active, t0, n_turns, backward, r);
+    pending = pending && !active;
+  }
+}
+
+// Re-track particles lost during the chunk from their chunk-start state up to
+// (not including) the element that lost them, and store those coordinates.
+__device__ __forceinline__ void replay_one(const uint64_t* __restrict__ tab, int32_t n_el, SoA P,
+                                           int32_t p, int32_t t0, int32_t backward,
+                                           const KernelRef& r) {
   const int32_t at = P.at_turn[p], ae = P.at_element[p];
   const int32_t tl = backward ? t0 - 1 - at : at - t0;
   const int32_t el = backward ? n_el - 1 - ae : ae;
@@ -785,6 +832,27 @@ __global__ void __launch_bounds__(256) k_replay(const uint64_t* __restrict__ tab
     }
   }
   store_pt(P, p, q);
+}
+
+__global__ void __launch_bounds__(256) k_replay(const uint64_t* __restrict__ tab, int32_t n_el,
+                                                SoA P, const int32_t* __restrict__ lost,
+                                                const int32_t* __restrict__ ctrl,
+                                                int32_t backward, KernelRef r) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ctrl[3]) return;
+  replay_one(tab, n_el, P, lost[i], ctrl[1], backward, r);
+}
+
+__global__ void __launch_bounds__(256) k_replay_batched(const uint64_t* const* __restrict__ tabs,
+                                                        const int32_t* __restrict__ first_slot,
+                                                        int32_t nv, int32_t n_el, SoA P,
+                                                        const int32_t* __restrict__ lost,
+                                                        const int32_t* __restrict__ ctrl,
+                                                        int32_t backward, KernelRef r) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ctrl[3]) return;
+  const int32_t p = lost[i];
+  replay_one(tabs[variant_of(first_slot, nv, p)], n_el, P, p, ctrl[1], backward, r);
 }
 
 // -------------------------------------------------------- chunk epilogue
@@ -999,6 +1067,26 @@ hipError_t launch_epilogue(const int32_t* idx_in, int32_t* idx_out, int32_t* los
   if (e != hipSuccess || (idx_out == nullptr && lost_out == nullptr)) return e;
   hipLaunchKernelGGL(k_scatter, dim3(nb), dim3(kScanBlock), 0, s, idx_in, idx_out, lost_out, P,
                      ctrl, blockcnt, chunk_turns, backward);
+  return hipGetLastError();
+}
+
+hipError_t launch_track_batched(const uint64_t* const* tabs, const int32_t* first_slot, int32_t nv,
+                                int32_t n_el, SoA P, const int32_t* idx, const int32_t* ctrl,
+                                int64_t grid_upper, int32_t block, int32_t n_turns,
+                                int32_t backward, KernelRef r, hipStream_t s) {
+  if (grid_upper <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_track4_batched, dim3(blocks_for(grid_upper, block)), dim3(block), 0, s, tabs,
+                     first_slot, nv, n_el, P, idx, ctrl, n_turns, backward, r);
+  return hipGetLastError();
+}
+
+hipError_t launch_replay_batched(const uint64_t* const* tabs, const int32_t* first_slot, int32_t nv,
+                                 int32_t n_el, SoA P, const int32_t* lost, const int32_t* ctrl,
+                                 int64_t grid_upper, int32_t backward, KernelRef r,
+                                 hipStream_t s) {
+  if (grid_upper <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_replay_batched, dim3(blocks_for(grid_upper, 256)), dim3(256), 0, s, tabs,
+                     first_slot, nv, n_el, P, lost, ctrl, backward, r);
   return hipGetLastError();
 }
 
