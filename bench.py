@@ -24,6 +24,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FP64_VECTOR_PEAK_TFLOPS = 78.6   # 256 CU x 128 FP64 FLOP/clk x 2.4 GHz
+KERNEL_NAMES = {1: "k_track", 2: "k_track2", 3: "k_track3", 4: "k_track4",
+                5: "xtm_line (per-line generated kernel)"}
 
 # algorithmic FLOPs per element application (sqrt, div, sin, compare count 1;
 # fma counts 2), as the kernel's maps are written
@@ -138,6 +140,7 @@ def main():
     total_passes = 0
     kernel_ms = 0.0
     launches = 0
+    variant_ran = 0
     start = torch.cuda.Event(enable_timing=True)
     stop = torch.cuda.Event(enable_timing=True)
     t_wall = time.perf_counter()
@@ -149,6 +152,7 @@ def main():
         total_passes += st.passes
         kernel_ms += st.kernel_ms
         launches += st.launches
+        variant_ran = st.variant
         alive = st.alive
         print(f"[bench] step {s + 1}/{steps}: alive {alive}", file=sys.stderr, flush=True)
     stop.record()
@@ -177,7 +181,7 @@ def main():
         "config": {"workload": desc, "n_particles": n, "n_elements": len(el),
                    "turns": steps * tps, "alive_at_end": int(alive),
                    "passes": int(total_passes), "wall_s": wall},
-        "roofline": {"bound": "alu", "kernel": "k_track",
+        "roofline": {"bound": "alu", "kernel": KERNEL_NAMES.get(variant_ran, "?"),
                      "achieved": achieved_tflops, "peak": FP64_VECTOR_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved_tflops / FP64_VECTOR_PEAK_TFLOPS,
                      "traffic": None, "flops_per_pass": flops_per_pass,

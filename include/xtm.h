@@ -167,7 +167,8 @@ typedef struct xtm_track_opts {
                               element table staged in LDS; 4 = interpreter, losses
                               kept in registers and replayed after the chunk;
                               5 = per-line kernel generated from the lattice's cell
-                              structure and compiled at first use (as 4 for losses);
+                              structure and compiled at first use (as 4 for losses;
+                              always 256-lane workgroups, `block` is ignored);
                               XTM_E_UNSUPPORTED if it cannot be built */
   int32_t radiation;       /* synchrotron radiation in multipoles with length > 0:
                               0 off, 1 mean energy loss, 2 mean + quantum excitation
@@ -188,7 +189,7 @@ typedef struct xtm_track_stats {
   int64_t passes;     /* (particle, element) applications made while alive, loss included */
   int64_t alive;      /* particles alive after the call */
   int32_t launches;   /* tracking-kernel launches made by the call */
-  int32_t reserved;
+  int32_t variant;    /* tracking kernel that ran (1..5, see xtm_track_opts) */
   double kernel_ms;   /* summed duration of those launches (time_kernels = 1), else 0 */
 } xtm_track_stats;
 
@@ -335,6 +336,35 @@ xtm_status xtm_mlp_grad(const float* d_theta, const float* d_norm, const float* 
    FP32 master parameters, step counted from 1; d_m, d_v start at zero. */
 xtm_status xtm_mlp_adam(float* d_theta, float* d_m, float* d_v, const float* d_grad, int32_t step,
                         float lr, void* stream);
+
+/* Training loop: `epochs` passes over the n rows of (d_x [n][16], d_y [n]),
+   each in mini-batches of `batch` rows (the last one shorter) taken in the
+   order of a fresh host-side permutation per epoch (Fisher-Yates driven by a
+   64-bit Mersenne twister seeded with shuffle_seed); per batch one
+   xtm_mlp_grad and one xtm_mlp_adam step.  *step is the Adam step counter
+   (0 before the first step; advanced by the number of batches).
+   h_epoch_loss[epochs] (or NULL) receives each epoch's mean batch loss.
+   Allocates its work buffers; synchronises once per epoch. */
+xtm_status xtm_mlp_train(float* d_theta, float* d_m, float* d_v, const float* d_norm,
+                         const float* d_x, const float* d_y, int64_t n, float pos_weight,
+                         int32_t epochs, int32_t batch, float lr, uint64_t shuffle_seed,
+                         int32_t* step, float* h_epoch_loss, void* stream);
+
+/* Retire threshold from held-out data: the smallest logit value tau among
+   the rows such that, of the rows with logit >= tau, the fraction with label
+   0 (particle lost within the horizon) is at most max_false_rate; +inf when
+   no threshold qualifies.  Also reports that fraction and the number of rows
+   at or above tau.  Synchronises. */
+xtm_status xtm_select_threshold(const float* d_logit, const int32_t* d_label, int64_t n,
+                                double max_false_rate, float* h_tau, double* h_false_rate,
+                                int64_t* h_selected, void* stream);
+
+/* Dynamic aperture of a polar scan from host arrays: particle j n_r + i is
+   radius i of ray j; h_da[j] = the smallest h_radius over the ray's lost
+   particles (state 0 or -1), +inf when the ray has none.  Retired particles
+   (state 2) count as survivors. */
+xtm_status xtm_dynamic_aperture(const int32_t* h_state, const double* h_radius, int32_t n_r,
+                                int32_t n_theta, double* h_da);
 
 /* Retire policy: every alive particle of the set (indexed by slot, as the
    set's arrays) with d_logit[slot] >= logit_threshold is retired (state 2,

@@ -322,3 +322,17 @@ def dynamic_aperture(state, radii, n_r: int, n_theta: int) -> np.ndarray:
         if len(lost):
             out[j] = r[j, lost].min()
     return out
+
+
+def select_threshold(logit, label, max_false_rate: float):
+    """Retire threshold by brute force over every candidate: the smallest
+    logit value tau (finite) such that among rows with logit >= tau the
+    fraction with label 0 is <= max_false_rate; +inf if none."""
+    z = np.asarray(logit, dtype=np.float64)
+    y = np.asarray(label)
+    best = np.inf
+    for t in np.unique(z[np.isfinite(z)]):
+        sel = z >= t
+        if np.mean(y[sel] == 0) <= max_false_rate:
+            best = min(best, t)
+    return best

@@ -53,7 +53,7 @@ class TrackOpts(ctypes.Structure):
 
 class TrackStats(ctypes.Structure):
     _fields_ = [("passes", ctypes.c_int64), ("alive", ctypes.c_int64),
-                ("launches", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("launches", ctypes.c_int32), ("variant", ctypes.c_int32),
                 ("kernel_ms", ctypes.c_double)]
 
 
@@ -101,6 +101,10 @@ def lib() -> ctypes.CDLL:
             "xtm_mlp_workspace": ([i64, vp], i32),
             "xtm_mlp_grad": ([vp, vp, vp, vp, i64, ctypes.c_float, vp, vp, vp, vp], i32),
             "xtm_mlp_adam": ([vp, vp, vp, vp, i32, ctypes.c_float, vp], i32),
+            "xtm_mlp_train": ([vp, vp, vp, vp, vp, vp, i64, ctypes.c_float, i32, i32,
+                               ctypes.c_float, ctypes.c_uint64, vp, vp, vp], i32),
+            "xtm_select_threshold": ([vp, vp, i64, ctypes.c_double, vp, vp, vp, vp], i32),
+            "xtm_dynamic_aperture": ([vp, vp, i32, i32, vp], i32),
             "xtm_retire": ([vp, vp, ctypes.c_float, ctypes.c_uint64, ctypes.c_double, vp, vp, vp],
                            i32),
         }
@@ -445,3 +449,39 @@ def retire(particles: Particles, logit, threshold: float, audit_seed: int,
                            float(audit_fraction), ctypes.byref(r), ctypes.byref(a),
                            _stream(stream)), "xtm_retire")
     return int(r.value), int(a.value)
+
+
+def mlp_train(theta, m, v, norm, x, y, pos_weight: float, epochs: int, batch: int, lr: float,
+              shuffle_seed: int, step: int = 0, stream=None):
+    """Run the training loop; returns (new Adam step count, per-epoch mean loss)."""
+    st = ctypes.c_int32(int(step))
+    losses = np.zeros(max(int(epochs), 1), dtype=np.float32)
+    check(lib().xtm_mlp_train(_p(theta), _p(m), _p(v), _p(norm), _p(x), _p(y), int(x.shape[0]),
+                              float(pos_weight), int(epochs), int(batch), float(lr),
+                              int(shuffle_seed), ctypes.byref(st),
+                              losses.ctypes.data_as(ctypes.c_void_p), _stream(stream)),
+          "xtm_mlp_train")
+    return int(st.value), losses[: int(epochs)]
+
+
+def select_threshold(logit, label, max_false_rate: float, stream=None):
+    """(tau, false rate at tau, rows at or above tau); label int32 (1 = survived)."""
+    tau = ctypes.c_float()
+    rate = ctypes.c_double()
+    sel = ctypes.c_int64()
+    check(lib().xtm_select_threshold(_p(logit), _p(label), int(logit.shape[0]),
+                                     float(max_false_rate), ctypes.byref(tau), ctypes.byref(rate),
+                                     ctypes.byref(sel), _stream(stream)), "xtm_select_threshold")
+    return float(tau.value), float(rate.value), int(sel.value)
+
+
+def dynamic_aperture(state, radius, n_r: int, n_theta: int) -> np.ndarray:
+    st = np.ascontiguousarray(state, dtype=np.int32)
+    r = np.ascontiguousarray(radius, dtype=np.float64)
+    if st.size != n_r * n_theta or r.size != n_r * n_theta:
+        raise ValueError("state and radius need n_r * n_theta entries")
+    out = np.zeros(n_theta)
+    check(lib().xtm_dynamic_aperture(st.ctypes.data_as(ctypes.c_void_p),
+                                     r.ctypes.data_as(ctypes.c_void_p), int(n_r), int(n_theta),
+                                     out.ctypes.data_as(ctypes.c_void_p)), "xtm_dynamic_aperture")
+    return out

@@ -5,8 +5,10 @@
 // gfx950 kernels on the caller's stream.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <random>
 #include <exception>
 #include <new>
 #include <string>
@@ -469,6 +471,7 @@ xtm_status run_turns(xtm_lattice_s* L, xtm_particles_s* P, int32_t n_turns,
     if (lk.ok) {
       c.variant = 5;
       c.line = &lk;
+      c.block = kLineBlock;
     } else if (c.variant == 5 && L->n_el > 0) {
       return fail(XTM_E_UNSUPPORTED, "per-line kernel unavailable: " + lk.error);
     } else {
@@ -520,6 +523,7 @@ xtm_status run_turns(xtm_lattice_s* L, xtm_particles_s* P, int32_t n_turns,
     stats->alive = alive;
     stats->passes = passes;
     stats->launches = launches;
+    stats->variant = c.variant;
     stats->kernel_ms = ms;
   }
   return XTM_OK;
@@ -887,6 +891,7 @@ xtm_status xtm_autotune(xtm_lattice L, xtm_batch B, xtm_particles P, const int64
     HIP_TRY(hipEventCreate(&e1), "event");
     for (int32_t v : variants) {
       for (int32_t blk : blocks) {
+        if (v == 5 && blk != kLineBlock) continue;  // the per-line kernel's fixed shape
         xtm_track_opts o{};
         o.variant = v;
         o.block = blk;
@@ -1053,6 +1058,127 @@ xtm_status xtm_mlp_adam(float* d_theta, float* d_m, float* d_v, const float* d_g
   if (!d_theta || !d_m || !d_v || !d_grad || step < 1) return fail(XTM_E_ARG, "bad arguments");
   hipError_t e = launch_adam(d_theta, d_m, d_v, d_grad, step, lr, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "adam launch");
+  return XTM_OK;
+}
+
+xtm_status xtm_mlp_train(float* d_theta, float* d_m, float* d_v, const float* d_norm,
+                         const float* d_x, const float* d_y, int64_t n, float pos_weight,
+                         int32_t epochs, int32_t batch, float lr, uint64_t shuffle_seed,
+                         int32_t* step, float* h_epoch_loss, void* stream) {
+  return guarded([&]() -> xtm_status {
+    if (!d_theta || !d_m || !d_v || !d_norm || !d_x || !d_y || !step)
+      return fail(XTM_E_ARG, "null argument");
+    if (n < 1 || n > INT32_MAX || epochs < 0 || batch < 1 || *step < 0)
+      return fail(XTM_E_ARG, "bad sizes");
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t bmax = batch < n ? batch : n;
+    const int64_t wf = mlp_workspace_floats(bmax);
+    float *work = nullptr, *xb = nullptr, *yb = nullptr, *grad = nullptr, *loss = nullptr;
+    int32_t* perm_d = nullptr;
+    auto release = [&]() {
+      hipFree(work); hipFree(xb); hipFree(yb); hipFree(grad); hipFree(loss); hipFree(perm_d);
+    };
+    if (hipMalloc(&work, wf * sizeof(float)) != hipSuccess ||
+        hipMalloc(&xb, bmax * 16 * sizeof(float)) != hipSuccess ||
+        hipMalloc(&yb, bmax * sizeof(float)) != hipSuccess ||
+        hipMalloc(&grad, XTM_MLP_PARAMS * sizeof(float)) != hipSuccess ||
+        hipMalloc(&loss, 4096 * sizeof(float)) != hipSuccess ||
+        hipMalloc(&perm_d, n * sizeof(int32_t)) != hipSuccess) {
+      release();
+      return fail(XTM_E_NOMEM, "training buffers");
+    }
+    std::vector<int32_t> perm(n);
+    std::mt19937_64 rng(shuffle_seed);
+    const int64_t nb = (n + batch - 1) / batch;
+    std::vector<float> lh;
+    hipError_t e = hipSuccess;
+    for (int32_t ep = 0; ep < epochs && e == hipSuccess; ++ep) {
+      for (int64_t i = 0; i < n; ++i) perm[i] = (int32_t)i;
+      for (int64_t i = n - 1; i > 0; --i) {  // Fisher-Yates
+        const int64_t j = (int64_t)(rng() % (uint64_t)(i + 1));
+        std::swap(perm[i], perm[j]);
+      }
+      e = hipMemcpyAsync(perm_d, perm.data(), n * sizeof(int32_t), hipMemcpyHostToDevice, s);
+      for (int64_t b = 0; b < nb && e == hipSuccess; ++b) {
+        const int64_t start = b * batch, B = (n - start < batch) ? n - start : batch;
+        e = launch_gather_rows(d_x, d_y, perm_d + start, B, xb, yb, s);
+        if (e == hipSuccess)
+          e = launch_mlp_grad(d_theta, d_norm, xb, yb, B, pos_weight, grad,
+                              loss + (b % 4096), work, s);
+        if (e == hipSuccess) e = launch_adam(d_theta, d_m, d_v, grad, ++*step, lr, s);
+      }
+      // mean batch loss of the epoch (the permutation buffer is reused next epoch)
+      if (e == hipSuccess) e = hipStreamSynchronize(s);
+      if (e == hipSuccess && h_epoch_loss) {
+        const int64_t k = nb < 4096 ? nb : 4096;
+        lh.resize(k);
+        e = hipMemcpy(lh.data(), loss, k * sizeof(float), hipMemcpyDeviceToHost);
+        double acc = 0.0;
+        for (float v : lh) acc += v;
+        h_epoch_loss[ep] = (float)(acc / (double)k);
+      }
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    release();
+    if (e != hipSuccess) return hip_fail(e, "training");
+    return XTM_OK;
+  });
+}
+
+xtm_status xtm_select_threshold(const float* d_logit, const int32_t* d_label, int64_t n,
+                                double max_false_rate, float* h_tau, double* h_false_rate,
+                                int64_t* h_selected, void* stream) {
+  return guarded([&]() -> xtm_status {
+    if (!h_tau || n < 0 || (n > 0 && (!d_logit || !d_label)))
+      return fail(XTM_E_ARG, "bad arguments");
+    std::vector<float> z(n);
+    std::vector<int32_t> y(n);
+    hipStream_t s = (hipStream_t)stream;
+    if (n > 0) {
+      HIP_TRY(hipMemcpyAsync(z.data(), d_logit, n * sizeof(float), hipMemcpyDeviceToHost, s), "copy");
+      HIP_TRY(hipMemcpyAsync(y.data(), d_label, n * sizeof(int32_t), hipMemcpyDeviceToHost, s), "copy");
+      HIP_TRY(hipStreamSynchronize(s), "synchronise");
+    }
+    std::vector<int64_t> order(n);
+    for (int64_t i = 0; i < n; ++i) order[i] = i;
+    std::sort(order.begin(), order.end(), [&](int64_t a, int64_t b) { return z[a] > z[b]; });
+    // walk thresholds downwards over distinct logits; keep the lowest that meets the budget
+    float tau = INFINITY;
+    double rate_at = 0.0;
+    int64_t sel_at = 0, lost = 0;
+    for (int64_t k = 0; k < n;) {
+      int64_t j = k;
+      while (j < n && z[order[j]] == z[order[k]]) {
+        lost += (y[order[j]] == 0);
+        ++j;
+      }
+      const double rate = (double)lost / (double)j;
+      if (std::isfinite(z[order[k]]) && rate <= max_false_rate) {
+        tau = z[order[k]];
+        rate_at = rate;
+        sel_at = j;
+      }
+      k = j;
+    }
+    *h_tau = tau;
+    if (h_false_rate) *h_false_rate = rate_at;
+    if (h_selected) *h_selected = sel_at;
+    return XTM_OK;
+  });
+}
+
+xtm_status xtm_dynamic_aperture(const int32_t* h_state, const double* h_radius, int32_t n_r,
+                                int32_t n_theta, double* h_da) {
+  if (!h_state || !h_radius || !h_da || n_r < 1 || n_theta < 1)
+    return fail(XTM_E_ARG, "bad arguments");
+  for (int32_t j = 0; j < n_theta; ++j) {
+    double da = INFINITY;
+    for (int32_t i = 0; i < n_r; ++i) {
+      const int64_t k = (int64_t)j * n_r + i;
+      if (h_state[k] <= 0 && h_radius[k] < da) da = h_radius[k];
+    }
+    h_da[j] = da;
+  }
   return XTM_OK;
 }
 

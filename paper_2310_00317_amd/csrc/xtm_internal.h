@@ -70,6 +70,7 @@ hipError_t launch_advance(int32_t* ctrl, int32_t dk, hipStream_t s);
 // words per LDS segment of the element table (variant 3); a record never
 // straddles two segments
 constexpr int kSegWords = 4096;
+constexpr int32_t kLineBlock = 256;  // workgroup size of the per-line kernel
 hipError_t launch_track(const uint64_t* tab, const int32_t* seg, int32_t n_seg, int32_t n_el,
                         SoA P, const int32_t* idx, const int32_t* ctrl, int64_t grid_upper,
                         int32_t block, int32_t n_turns, int32_t backward, KernelRef r,
@@ -131,6 +132,8 @@ hipError_t launch_mlp_grad(const float* theta, const float* norm, const float* X
                            hipStream_t s);
 hipError_t launch_adam(float* theta, float* m, float* v, const float* grad, int32_t step, float lr,
                        hipStream_t s);
+hipError_t launch_gather_rows(const float* X, const float* Y, const int32_t* perm, int64_t B,
+                              float* Xb, float* Yb, hipStream_t s);
 hipError_t launch_mlp_init(float* theta, unsigned long long seed, hipStream_t s);
 hipError_t launch_features(const float* rec, int64_t n, const double twiss4[4], double emit,
                            double r_ap, const float2* tw, const float* win, float* out,

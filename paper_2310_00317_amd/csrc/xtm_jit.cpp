@@ -416,8 +416,11 @@ hipError_t launch_line(const LineKernel& k, int32_t n_el, SoA P, const int32_t* 
   int32_t n_cells = k.n_cells;
   void* args[] = {(void*)&prm, (void*)&cells, (void*)&n_cells, (void*)&n_el, (void*)&P,
                   (void*)&idx, (void*)&ctrl, (void*)&n_turns, (void*)&backward, (void*)&r};
-  const unsigned grid = (unsigned)((grid_upper + block - 1) / block);
-  return hipModuleLaunchKernel(k.fn, grid, 1, 1, (unsigned)block, 1, 1, 0, s, args, nullptr);
+  // the generated kernel stages each cell's parameters with a fixed stride
+  // of 256 lanes, so it always runs in 256-lane workgroups
+  (void)block;
+  const unsigned grid = (unsigned)((grid_upper + kLineBlock - 1) / kLineBlock);
+  return hipModuleLaunchKernel(k.fn, grid, 1, 1, (unsigned)kLineBlock, 1, 1, 0, s, args, nullptr);
 }
 
 }  // namespace xtm

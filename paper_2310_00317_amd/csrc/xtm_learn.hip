@@ -548,7 +548,29 @@ __global__ void __launch_bounds__(256) k_retire(SoA P, const int32_t* __restrict
   atomicAdd(&counts[0], 1u);
 }
 
+// Rows perm[start .. start+B-1] of (X, Y) into the contiguous batch (Xb, Yb).
+__global__ void __launch_bounds__(256) k_gather_rows(const float* __restrict__ X,
+                                                     const float* __restrict__ Y,
+                                                     const int32_t* __restrict__ perm,
+                                                     int64_t B, float* __restrict__ Xb,
+                                                     float* __restrict__ Yb) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= B * kIn) return;
+  const int64_t r = i / kIn, f = i - r * kIn;
+  const int64_t src = perm[r];
+  Xb[i] = X[src * kIn + f];
+  if (f == 0) Yb[r] = Y[src];
+}
+
 // ------------------------------------------------------------- launchers
+hipError_t launch_gather_rows(const float* X, const float* Y, const int32_t* perm, int64_t B,
+                              float* Xb, float* Yb, hipStream_t s) {
+  if (B <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gather_rows, dim3((unsigned)((B * kIn + 255) / 256)), dim3(256), 0, s, X, Y,
+                     perm, B, Xb, Yb);
+  return hipGetLastError();
+}
+
 hipError_t launch_mlp_forward(const float* theta, const float* norm, const float* X, int64_t B,
                               float* logit, hipStream_t s) {
   if (B <= 0) return hipSuccess;

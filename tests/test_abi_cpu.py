@@ -96,3 +96,19 @@ def test_bad_reference_and_arguments(xtm):
 
 def test_version_string(xtm):
     assert b"gfx950" in xtm.lib().xtm_version()
+
+
+def test_dynamic_aperture_host_function_matches_oracle(oracle_mod):
+    """xtm_dynamic_aperture is host-only: checked here against the oracle's
+    definition on random scans (retired particles, state 2, are survivors)."""
+    import paper_2310_00317_amd as P
+    rng = np.random.default_rng(12)
+    for n_r, n_t in ((1, 1), (9, 4), (200, 7)):
+        st = rng.choice([1, 0, -1, 2], size=n_r * n_t, p=[0.7, 0.15, 0.05, 0.1]).astype(np.int32)
+        r = rng.random(n_r * n_t) * 30
+        got = P.dynamic_aperture(st, r, n_r, n_t)
+        exp = oracle_mod.dynamic_aperture(st, r, n_r, n_t)
+        assert np.array_equal(got, exp)
+    with pytest.raises(P.XtmError):
+        P.lib()
+        P.check(P.lib().xtm_dynamic_aperture(None, None, 0, 0, None), "xtm_dynamic_aperture")

@@ -297,3 +297,58 @@ def test_retire_infinite_threshold_is_plain_tracking(P):
     ga, gb = a.to_numpy(), b.to_numpy()
     for f in ga:
         assert np.array_equal(ga[f], gb[f]), f
+
+
+# ------------------------------------------------------------------ training loop
+def test_threshold_selection_matches_oracle(P, oracle_mod):
+    import torch
+    rng = np.random.default_rng(21)
+    z = np.round(rng.normal(size=3000), 2).astype(np.float32)      # many ties
+    y = (rng.random(3000) < 1 / (1 + np.exp(-3 * z))).astype(np.int32)
+    for rate in (0.0, 1e-3, 0.05, 0.3):
+        tau, fr, sel = P.select_threshold(torch.tensor(z, device="cuda"),
+                                          torch.tensor(y, device="cuda"), rate)
+        exp = oracle_mod.select_threshold(z, y, rate)
+        assert tau == np.float32(exp) if np.isfinite(exp) else tau == np.inf, (rate, tau, exp)
+        if np.isfinite(exp):
+            m = z >= tau
+            assert sel == m.sum() and abs(fr - np.mean(y[m] == 0)) < 1e-12
+
+
+def test_training_loop_full_batch_equals_one_step(P):
+    """One epoch with the whole set as the batch is one gradient + Adam step
+    (row order changes only the FP32 summation order)."""
+    import torch
+    theta, x, norm, y = _net_inputs(512, seed=13)
+    t = lambda a: torch.tensor(a, device="cuda")
+    th1, m1, v1 = t(theta), torch.zeros(len(theta), device="cuda"), torch.zeros(len(theta), device="cuda")
+    step, losses = P.mlp_train(th1, m1, v1, t(norm), t(x), t(y), 2.0, 1, 512, 1e-3, 99)
+    assert step == 1 and losses.shape == (1,)
+    th2, m2, v2 = t(theta), torch.zeros(len(theta), device="cuda"), torch.zeros(len(theta), device="cuda")
+    g, loss = P.mlp_grad(th2, t(norm), t(x), t(y), 2.0)
+    P.mlp_adam(th2, m2, v2, g, 1, 1e-3)
+    a, b = th1.cpu().numpy(), th2.cpu().numpy()
+    # Adam's first step is about lr sign(g): only gradients at the FP32
+    # summation-noise level may take the other sign
+    assert np.mean(np.abs(a - b) > 1e-4) <= 0.01
+    assert np.abs(b - theta).max() > 5e-4
+    assert abs(losses[0] - float(loss.cpu()[0])) <= 1e-5 * abs(float(loss.cpu()[0]))
+
+
+def test_training_learns_a_separable_rule(P):
+    import torch
+    rng = np.random.default_rng(5)
+    n = 20000
+    x = rng.normal(size=(n, 16)).astype(np.float32)
+    y = ((x[:, 0] + 0.5 * x[:, 3] - 0.3 * x[:, 7]) > 0.2).astype(np.float32)
+    t = lambda a: torch.tensor(a, device="cuda")
+    X = t(x)
+    norm = P.feature_stats(X)
+    theta = P.mlp_init(7)
+    m, v = torch.zeros_like(theta), torch.zeros_like(theta)
+    w = float((y == 0).sum() / (y == 1).sum())
+    step, losses = P.mlp_train(theta, m, v, norm, X, t(y), w, 8, 1024, 3e-3, 1)
+    assert step == 8 * 20 and losses[-1] < 0.5 * losses[0]
+    z = P.mlp_forward(theta, norm, X).cpu().numpy()
+    acc = np.mean((z > 0) == (y > 0.5))
+    assert acc > 0.97, acc

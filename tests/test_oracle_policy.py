@@ -40,3 +40,12 @@ def test_dynamic_aperture_brute_force():
     for j in range(n_t):
         lost = [radii[j * n_r + i] for i in range(n_r) if state[j * n_r + i] in (0, -1)]
         assert da[j] == (min(lost) if lost else math.inf)
+
+
+def test_threshold_definition_on_hand_cases():
+    z = np.array([3.0, 2.0, 1.0, 0.0, -1.0])
+    y = np.array([1, 1, 0, 1, 1])
+    assert oracle.select_threshold(z, y, 0.0) == 2.0
+    assert oracle.select_threshold(z, y, 0.25) == -1.0      # 1 lost of 5 = 0.2
+    assert oracle.select_threshold(z, y, 0.3) == -1.0
+    assert oracle.select_threshold(np.array([1.0]), np.array([0]), 0.5) == np.inf
