@@ -91,13 +91,85 @@ def cpu_baseline(el, c, ref, sample_every: int, turns: int):
                       f"= {passes} passes in {dt:.1f} s"}
 
 
+def learned_da(args):
+    """Dynamic-aperture scan of the cfg1 ring: plain tracking to the horizon
+    versus learned early stop (network) and the tune-diffusion rule, on the
+    same GPU with the same kernels.  Training data: random amplitudes tracked
+    to the horizon with the recorder on (reported separately, not part of the
+    scan wall time)."""
+    import torch
+    import paper_2310_00317_amd as P
+    from paper_2310_00317_amd import inputs as I
+    from paper_2310_00317_amd import learned as L
+    el, ref = I.cfg1_lattice(), I.PROTON_450GEV
+    tw, emit, rap = I.cfg1_twiss(), I.CFG2_EMIT, I.CFG1_APERTURE
+    lat = P.Lattice(el, ref)
+    log = lambda m: print(f"[cfg4] {m}", file=sys.stderr, flush=True)
+    H = args.horizon
+    t = time.perf_counter()
+    tc, _, _ = I.random_amplitudes(args.train_particles, args.da_rmax, tw, seed=404)
+    data = L.collect(lat, ref, tc, H, tw, emit, rap, first_id=10 ** 9)
+    t_label = time.perf_counter() - t
+    log(f"labels: {args.train_particles} particles x {H} turns in {t_label:.1f} s; "
+        f"stable fraction {data.label.mean():.3f}")
+    t = time.perf_counter()
+    pred = L.train(data, epochs=args.epochs)
+    t_train = time.perf_counter() - t
+    rule = L.rule_threshold(data)
+    log(f"trained in {t_train:.1f} s, tau {pred.tau:.3f} (held-out false rate "
+        f"{pred.val_false_rate:.2e}, {pred.val_retired} retired); rule threshold {rule:.3f}")
+    gc, gr, _ = I.polar_grid(args.da_radii, args.da_rays, args.da_rmax, tw, emit)
+    plain = L.scan(lat, ref, gc, H)
+    log(f"plain scan {plain['wall_s']:.1f} s")
+    learned = L.scan(lat, ref, gc, H, tw, emit, rap, predictor=pred)
+    log(f"learned scan {learned['wall_s']:.1f} s, retired {learned['retired']}")
+    ruled = L.scan(lat, ref, gc, H, tw, emit, rap, rule_tau=rule)
+    log(f"rule scan {ruled['wall_s']:.1f} s, retired {ruled['retired']}")
+    nr, nt = args.da_radii, args.da_rays
+    e_l = L.da_error(learned["state"], plain["state"], gr, nr, nt)
+    e_r = L.da_error(ruled["state"], plain["state"], gr, nr, nt)
+    da = P.dynamic_aperture(plain["state"], gr, nr, nt)
+    keys = ("retired", "audited", "audit_lost", "audit_upper", "fallback", "wall_s")
+    out = {
+        "metric": "DA wall-clock speedup, learned early stop vs plain tracking",
+        "value": plain["wall_s"] / learned["wall_s"],
+        "unit": "x",
+        "n_gpus": 1,
+        "higher_is_better": True,
+        "vs_baseline": None,
+        "dtype": "f64 tracking; bf16/fp32 network",
+        "data": "synthetic",
+        "config": {"workload": f"cfg1 ring DA scan, {nr}x{nt} polar grid 0-{args.da_rmax} sigma, "
+                               f"{H} turns; predictor trained on {args.train_particles} random "
+                               "amplitudes", "horizon": H},
+        "da_error_sigma": {"network_mean": e_l[0], "network_max": e_l[1],
+                           "rule_mean": e_r[0], "rule_max": e_r[1]},
+        "plain": {"wall_s": plain["wall_s"], "da_mean_sigma": float(np.mean(np.where(
+            np.isfinite(da), da, args.da_rmax))), "da_min_sigma": float(np.min(da))},
+        "network": {k: learned[k] for k in keys if k in learned},
+        "rule": {k: ruled[k] for k in keys if k in ruled},
+        "rule_speedup": plain["wall_s"] / ruled["wall_s"],
+        "training": {"label_s": t_label, "train_s": t_train, "tau": pred.tau,
+                     "val_false_rate": pred.val_false_rate,
+                     "loss_first_last": [float(pred.losses[0]), float(pred.losses[-1])]},
+    }
+    print(json.dumps(out, default=lambda o: bool(o) if isinstance(o, np.bool_) else float(o)),
+          flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--turns-per-step", type=int, default=None)
-    ap.add_argument("--workload", default="cfg2", choices=["cfg2", "cfg1", "cfg1sat"])
+    ap.add_argument("--workload", default="cfg2", choices=["cfg2", "cfg1", "cfg1sat", "cfg4"])
+    ap.add_argument("--da-rays", type=int, default=500, help="cfg4: rays of the evaluation grid")
+    ap.add_argument("--da-radii", type=int, default=2000, help="cfg4: radii per ray")
+    ap.add_argument("--da-rmax", type=float, default=30.0, help="cfg4: grid edge [sigma]")
+    ap.add_argument("--train-particles", type=int, default=200000)
+    ap.add_argument("--horizon", type=int, default=100000, help="cfg4: turns")
+    ap.add_argument("--epochs", type=int, default=30)
     ap.add_argument("--particles", type=int, default=None)
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--chunk", type=int, default=0)
@@ -116,6 +188,8 @@ def main():
     import torch
     import paper_2310_00317_amd as P
 
+    if args.workload == "cfg4":
+        return learned_da(args)
     el, coords, ref, desc, tps_default, steps_default = workload(args.workload, args.particles)
     tps = args.turns_per_step or tps_default
     steps = args.steps if args.steps is not None else steps_default

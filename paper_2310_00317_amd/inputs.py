@@ -380,6 +380,31 @@ def polar_grid(n_r: int = 2000, n_theta: int = 50, r_max_sigma: float = 10.0,
     return c, rr, tt
 
 
+def random_amplitudes(n: int, r_max_sigma: float, twiss, seed: int, emit: float = CFG2_EMIT,
+                      delta: float = CFG2_DELTA) -> tuple[np.ndarray, np.ndarray, np.ndarray]:
+    """Training set of the loss predictor: r ~ U(0, r_max) [sigma],
+    theta ~ U(0, pi/2), zero normalised momenta, zeta = 0, fixed delta.
+    Returns (coords (n, 6), r_sigma, theta)."""
+    rng = np.random.default_rng(seed)
+    r = rng.random(n) * r_max_sigma
+    th = rng.random(n) * 0.5 * math.pi
+    bx, ax, by, ay = twiss
+    c = np.zeros((n, 6))
+    c[:, 0] = r * np.cos(th) * math.sqrt(bx * emit)
+    c[:, 2] = r * np.sin(th) * math.sqrt(by * emit)
+    c[:, 1] = -ax * c[:, 0] / bx
+    c[:, 3] = -ay * c[:, 2] / by
+    c[:, 5] = delta
+    return c, r, th
+
+
+def cfg1_twiss():
+    """(beta_x, alpha_x, beta_y, alpha_y) at element 0 of cfg1 (the RF is thin
+    and longitudinal, so this is the QF entry of the periodic cell)."""
+    k = 1.0 / CFG1_F
+    return cell_twiss_at_qf_entry(k, -k, CFG1_HALF)
+
+
 def cfg2_grid(n_r: int = 2000, n_theta: int = 50, r_max_sigma: float = 10.0):
     kf, kd = cfg2_quads()
     tw = cell_twiss_at_qf_entry(kf, kd, 2 * CFG2_D)
