@@ -972,11 +972,12 @@ __global__ void __launch_bounds__(kScanBlock) k_scatter(const int32_t* __restric
   const int32_t rank_a = block_rank(alive, s_wave, &total_a);
   __syncthreads();
   const int32_t rank_g = block_rank(gone, s_wave, &total_g);
+  // either list is optional (the store-on-loss kernels keep no lost list)
   if (alive && idx_out) idx_out[off_a + rank_a] = p;
-  if (gone) lost_out[off_g + rank_g] = p;
+  if (gone && lost_out) lost_out[off_g + rank_g] = p;
   if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) {
     if (idx_out) ctrl[0] = off_a + total_a;
-    ctrl[3] = off_g + total_g;
+    ctrl[3] = lost_out ? off_g + total_g : 0;
   }
 }
 
