@@ -170,6 +170,9 @@ def main():
     ap.add_argument("--train-particles", type=int, default=200000)
     ap.add_argument("--horizon", type=int, default=100000, help="cfg4: turns")
     ap.add_argument("--epochs", type=int, default=30)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device-to-device copy of BYTES (3 times), the "
+                         "reference for scaling HBM byte counters")
     ap.add_argument("--particles", type=int, default=None)
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--chunk", type=int, default=0)
@@ -188,6 +191,15 @@ def main():
     import torch
     import paper_2310_00317_amd as P
 
+    if args.copy_calibration:
+        n = args.copy_calibration // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4, "copies": 3}))
+        return
     if args.workload == "cfg4":
         return learned_da(args)
     el, coords, ref, desc, tps_default, steps_default = workload(args.workload, args.particles)
