@@ -55,6 +55,9 @@ def lib():
         L.oracle_track_rad.restype = ctypes.c_int64
         L.oracle_uniform.restype = ctypes.c_double
         L.oracle_uniform.argtypes = [ctypes.c_uint32, ctypes.c_uint32]
+        for fn in ("oracle_sin", "oracle_cos", "oracle_log"):
+            getattr(L, fn).restype = ctypes.c_double
+            getattr(L, fn).argtypes = [ctypes.c_double]
         L.oracle_gauss_at.restype = ctypes.c_double
         L.oracle_gauss_at.argtypes = [ctypes.c_uint64, ctypes.c_int64, ctypes.c_int32,
                                       ctypes.c_int32, ctypes.c_int32]
@@ -336,3 +339,17 @@ def select_threshold(logit, label, max_false_rate: float):
         if np.mean(y[sel] == 0) <= max_false_rate:
             best = min(best, t)
     return best
+
+
+# ---------------------------------------------------- elementary functions
+def xsin(x: float) -> float:
+    """The tracker's sine (series evaluation shared by both implementations)."""
+    return float(lib().oracle_sin(x))
+
+
+def xcos(x: float) -> float:
+    return float(lib().oracle_cos(x))
+
+
+def xlog(x: float) -> float:
+    return float(lib().oracle_log(x))

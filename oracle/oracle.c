@@ -168,6 +168,102 @@ static void multipole_kick(orc_pt* q, const orc_elem* e, const orc_coef* c, doub
   }
 }
 
+/* Elementary functions of the tracking maps (RF sine, Box-Muller logarithm
+   and cosine), written from their series so that any two implementations of
+   the same steps agree bit for bit (libm's results may differ by an ulp
+   between platforms, which chaotic or strongly damped motion amplifies).
+   sin/cos: n = nearest integer to x (2/pi); r = x - n pi/2 with pi/2 split
+   into P1 = pi/2 rounded to double, P2 = the rest rounded, P3 = what remains,
+   each product applied by one fused multiply-add; then the Taylor series of sin and cos in r
+   (|r| <= pi/4, truncated after r^21 and r^20, truncation below 1e-23),
+   Horner in r^2, and the quadrant n mod 4 picks +-sin r or +-cos r.
+   log: x = m 2^e with m in [sqrt(1/2), sqrt(2)); log m = 2 atanh(s),
+   s = (m - 1)/(m + 1), by its series in s^2 up to s^25; log x = e ln 2 +
+   log m with ln 2 split like pi/2.  Accuracy (checked against libm in the
+   tests): within two ulps over the ranges used. */
+#define O_2_PI 0.6366197723675814          /* 2/pi rounded to double */
+#define O_P1 1.5707963267948966            /* pi/2 rounded to double */
+#define O_P2 6.123233995736766e-17          /* pi/2 - O_P1 rounded to double */
+#define O_P3 -1.4973849048591698e-33        /* pi/2 - O_P1 - O_P2 */
+#define O_LN2_1 0.6931471805599453          /* ln 2 rounded to double */
+#define O_LN2_2 2.3190468138462996e-17      /* ln 2 - O_LN2_1 */
+#define O_2PI 6.283185307179586             /* 2 pi rounded to double */
+
+static void sincos_reduced(double x, double* sr, double* cr, int64_t* quadrant) {
+  double n = rint(x * O_2_PI);
+  double r = fma(-n, O_P1, x);
+  r = fma(-n, O_P2, r);
+  r = fma(-n, O_P3, r);
+  double z = r * r;
+  /* sin r = r + r z (S1 + z (S2 + ... + z S10)), S_k = (-1)^k / (2k+1)! */
+  double ps = 1.0 / 51090942171709440000.0;
+  ps = fma(ps, z, -1.0 / 121645100408832000.0);
+  ps = fma(ps, z, 1.0 / 355687428096000.0);
+  ps = fma(ps, z, -1.0 / 1307674368000.0);
+  ps = fma(ps, z, 1.0 / 6227020800.0);
+  ps = fma(ps, z, -1.0 / 39916800.0);
+  ps = fma(ps, z, 1.0 / 362880.0);
+  ps = fma(ps, z, -1.0 / 5040.0);
+  ps = fma(ps, z, 1.0 / 120.0);
+  ps = fma(ps, z, -1.0 / 6.0);
+  *sr = fma(r * z, ps, r);
+  /* cos r = 1 + z (C1 + z (C2 + ...)), C_k = (-1)^k / (2k)! */
+  double pc = 1.0 / 2432902008176640000.0;
+  pc = fma(pc, z, -1.0 / 6402373705728000.0);
+  pc = fma(pc, z, 1.0 / 20922789888000.0);
+  pc = fma(pc, z, -1.0 / 87178291200.0);
+  pc = fma(pc, z, 1.0 / 479001600.0);
+  pc = fma(pc, z, -1.0 / 3628800.0);
+  pc = fma(pc, z, 1.0 / 40320.0);
+  pc = fma(pc, z, -1.0 / 720.0);
+  pc = fma(pc, z, 1.0 / 24.0);
+  pc = fma(pc, z, -1.0 / 2.0);
+  *cr = fma(z, pc, 1.0);
+  *quadrant = (int64_t)n & 3;
+}
+
+double oracle_sin(double x) {
+  double sr, cr;
+  int64_t q;
+  sincos_reduced(x, &sr, &cr, &q);
+  return q == 0 ? sr : q == 1 ? cr : q == 2 ? -sr : -cr;
+}
+
+double oracle_cos(double x) {
+  double sr, cr;
+  int64_t q;
+  sincos_reduced(x, &sr, &cr, &q);
+  return q == 0 ? cr : q == 1 ? -sr : q == 2 ? -cr : sr;
+}
+
+double oracle_log(double x) {
+  int e;
+  double m = frexp(x, &e);
+  if (m < 0.70710678118654752440) {
+    m = m * 2.0;
+    e = e - 1;
+  }
+  double s = (m - 1.0) / (m + 1.0);
+  double z = s * s;
+  /* log m = 2 s (1 + z/3 + z^2/5 + ... + z^12/25) */
+  double p = 1.0 / 25.0;
+  p = fma(p, z, 1.0 / 23.0);
+  p = fma(p, z, 1.0 / 21.0);
+  p = fma(p, z, 1.0 / 19.0);
+  p = fma(p, z, 1.0 / 17.0);
+  p = fma(p, z, 1.0 / 15.0);
+  p = fma(p, z, 1.0 / 13.0);
+  p = fma(p, z, 1.0 / 11.0);
+  p = fma(p, z, 1.0 / 9.0);
+  p = fma(p, z, 1.0 / 7.0);
+  p = fma(p, z, 1.0 / 5.0);
+  p = fma(p, z, 1.0 / 3.0);
+  double t = 2.0 * s;
+  double lm = fma(t * z, p, t);
+  double de = (double)e;
+  return fma(de, O_LN2_1, fma(de, O_LN2_2, lm));
+}
+
 /* RF cavity (thin): ptau += (q V / p0c) sin(lag pi/180 - k zeta), k = 2 pi f/(beta0 c);
    then delta, rpp, rvv from ptau.  No transverse kick. */
 static void rf_kick(orc_pt* q, const orc_elem* e, const orc_ref* r, double sgn) {
@@ -175,7 +271,7 @@ static void rf_kick(orc_pt* q, const orc_elem* e, const orc_ref* r, double sgn) 
   double amp = r->charge0 * e->p[0] / r->p0c;
   double k = 2.0 * M_PI * e->p[1] / (r->beta0 * clight);
   double phi = e->p[2] * M_PI / 180.0;
-  double s = sin(phi - k * q->zeta);
+  double s = oracle_sin(phi - k * q->zeta);
   if (sgn > 0)
     q->ptau = q->ptau + amp * s;
   else
@@ -537,7 +633,7 @@ double oracle_uniform(uint32_t wa, uint32_t wb) {
 double oracle_gauss(const uint32_t w[4]) {
   double u1 = oracle_uniform(w[0], w[1]);
   double u2 = oracle_uniform(w[2], w[3]);
-  return sqrt(-2.0 * log(u1)) * cos(2.0 * M_PI * u2);
+  return sqrt(-2.0 * oracle_log(u1)) * oracle_cos(O_2PI * u2);
 }
 
 /* Gaussian deviate of (seed, particle id, turn, element): counter

@@ -208,7 +208,7 @@ __global__ void __launch_bounds__(256) k_track(const uint64_t* __restrict__ tab,
           break;
         }
         case K_RF: {
-          const double s = sin(prm[2] - prm[1] * q.zeta);
+          const double s = xtmm::xsin(prm[2] - prm[1] * q.zeta);
           q.ptau = q.ptau + prm[0] * s;
           const double v = q.ptau * (q.ptau + r.two_over_beta0);
           q.delta = v / (1.0 + sqrt(1.0 + v));
@@ -377,7 +377,7 @@ __global__ void __launch_bounds__(256) k_track2(const uint64_t* __restrict__ tab
           break;
         }
         case K_RF: {
-          const double s = sin(prm[2] - prm[1] * q.zeta);
+          const double s = xtmm::xsin(prm[2] - prm[1] * q.zeta);
           q.ptau = q.ptau + prm[0] * s;
           const double v = q.ptau * (q.ptau + r.two_over_beta0);
           q.delta = v / (1.0 + sqrt(1.0 + v));
@@ -537,7 +537,7 @@ __global__ void __launch_bounds__(256) k_track3(const uint64_t* __restrict__ tab
               break;
             }
             case K_RF: {
-              const double s = sin(prm[2] - prm[1] * q.zeta);
+              const double s = xtmm::xsin(prm[2] - prm[1] * q.zeta);
               q.ptau = q.ptau + prm[0] * s;
               const double v = q.ptau * (q.ptau + r.two_over_beta0);
               q.delta = v / (1.0 + sqrt(1.0 + v));

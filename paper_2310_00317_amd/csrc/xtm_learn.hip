@@ -279,20 +279,22 @@ __global__ void __launch_bounds__(256) k_mlp_reduce(const float* __restrict__ pa
 
 // Adam (Kingma & Ba): m <- b1 m + (1-b1) g, v <- b2 v + (1-b2) g^2,
 // theta <- theta - lr mhat / (sqrt(vhat) + eps), bias-corrected with step t >= 1.
+// The update is evaluated in FP64 from the FP32 masters and moments (b1 = 0.9,
+// b2 = 0.999 exactly, not their FP32 roundings) and stored back in FP32.
 __global__ void __launch_bounds__(256) k_adam(float* __restrict__ theta, float* __restrict__ m,
                                               float* __restrict__ v,
                                               const float* __restrict__ grad, int step, float lr,
-                                              float b1, float b2, float eps) {
+                                              double b1, double b2, double eps) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= kParams) return;
-  const float g = grad[i];
-  const float mi = b1 * m[i] + (1.f - b1) * g;
-  const float vi = b2 * v[i] + (1.f - b2) * g * g;
-  m[i] = mi;
-  v[i] = vi;
-  const float mh = mi / (1.f - powf(b1, (float)step));
-  const float vh = vi / (1.f - powf(b2, (float)step));
-  theta[i] = theta[i] - lr * mh / (sqrtf(vh) + eps);
+  const double g = grad[i];
+  const double mi = b1 * (double)m[i] + (1.0 - b1) * g;
+  const double vi = b2 * (double)v[i] + (1.0 - b2) * g * g;
+  m[i] = (float)mi;
+  v[i] = (float)vi;
+  const double mh = mi / (1.0 - pow(b1, (double)step));
+  const double vh = vi / (1.0 - pow(b2, (double)step));
+  theta[i] = (float)((double)theta[i] - (double)lr * mh / (sqrt(vh) + eps));
 }
 
 // He-normal initialisation: weights std sqrt(2/fan_in) times the Philox
@@ -603,7 +605,7 @@ hipError_t launch_mlp_grad(const float* theta, const float* norm, const float* X
 hipError_t launch_adam(float* theta, float* m, float* v, const float* grad, int32_t step, float lr,
                        hipStream_t s) {
   hipLaunchKernelGGL(k_adam, dim3((kParams + 255) / 256), dim3(256), 0, s, theta, m, v, grad, step,
-                     lr, 0.9f, 0.999f, 1e-8f);
+                     lr, 0.9, 0.999, 1e-8);
   return hipGetLastError();
 }
 

@@ -87,6 +87,91 @@ __device__ __forceinline__ void curvature(Pt& q, double hxl, double k0h, double 
   q.zeta = q.zeta - dz;
 }
 
+// Elementary functions used by the maps: the RF sine and the Box-Muller
+// logarithm and cosine are evaluated from their series, step by step as the
+// reference implementation does, so results agree bit for bit instead of
+// within the ulp by which two math libraries may differ.
+//   sin/cos: n = rint(x 2/pi); r = x - n pi/2 by three fused multiply-adds
+//   with pi/2 = P1 + P2 + P3 (P1 = pi/2 rounded, P2 the remainder rounded,
+//   P3 what is left); Taylor series of
+//   sin r (to r^21) and cos r (to r^20) by Horner in r^2; quadrant n mod 4.
+//   log: x = m 2^e, m in [sqrt(1/2), sqrt(2)); log m = 2 atanh((m-1)/(m+1))
+//   by its odd series up to the 25th power; log x = e ln2 + log m, ln 2 split
+//   like pi/2.  Domain: finite x (sin, cos); finite x > 0 (log).
+__device__ __forceinline__ void sincos_core(double x, double& sr, double& cr, int& quad) {
+  const double n = rint(x * 0.6366197723675814);
+  double r = fma(-n, 1.5707963267948966, x);
+  r = fma(-n, 6.123233995736766e-17, r);
+  r = fma(-n, -1.4973849048591698e-33, r);
+  const double z = r * r;
+  double a = 1.0 / 51090942171709440000.0;     // 1/21!
+  a = fma(a, z, -1.0 / 121645100408832000.0);  // -1/19!
+  a = fma(a, z, 1.0 / 355687428096000.0);      // 1/17!
+  a = fma(a, z, -1.0 / 1307674368000.0);       // -1/15!
+  a = fma(a, z, 1.0 / 6227020800.0);           // 1/13!
+  a = fma(a, z, -1.0 / 39916800.0);            // -1/11!
+  a = fma(a, z, 1.0 / 362880.0);               // 1/9!
+  a = fma(a, z, -1.0 / 5040.0);                // -1/7!
+  a = fma(a, z, 1.0 / 120.0);                  // 1/5!
+  a = fma(a, z, -1.0 / 6.0);                   // -1/3!
+  sr = fma(r * z, a, r);
+  double b = 1.0 / 2432902008176640000.0;      // 1/20!
+  b = fma(b, z, -1.0 / 6402373705728000.0);    // -1/18!
+  b = fma(b, z, 1.0 / 20922789888000.0);       // 1/16!
+  b = fma(b, z, -1.0 / 87178291200.0);         // -1/14!
+  b = fma(b, z, 1.0 / 479001600.0);            // 1/12!
+  b = fma(b, z, -1.0 / 3628800.0);             // -1/10!
+  b = fma(b, z, 1.0 / 40320.0);                // 1/8!
+  b = fma(b, z, -1.0 / 720.0);                 // -1/6!
+  b = fma(b, z, 1.0 / 24.0);                   // 1/4!
+  b = fma(b, z, -1.0 / 2.0);                   // -1/2!
+  cr = fma(z, b, 1.0);
+  quad = (int)((long long)n & 3);
+}
+
+__device__ __forceinline__ double xsin(double x) {
+  double sr, cr;
+  int k;
+  sincos_core(x, sr, cr, k);
+  const double v = (k & 1) ? cr : sr;
+  return (k & 2) ? -v : v;
+}
+
+__device__ __forceinline__ double xcos(double x) {
+  double sr, cr;
+  int k;
+  sincos_core(x, sr, cr, k);
+  const double v = (k & 1) ? sr : cr;
+  return ((k + 1) & 2) ? -v : v;
+}
+
+__device__ __forceinline__ double xlog(double x) {
+  int e;
+  double m = frexp(x, &e);
+  if (m < 0.70710678118654752440) {
+    m = m * 2.0;
+    e = e - 1;
+  }
+  const double s = (m - 1.0) / (m + 1.0);
+  const double z = s * s;
+  double p = 1.0 / 25.0;
+  p = fma(p, z, 1.0 / 23.0);
+  p = fma(p, z, 1.0 / 21.0);
+  p = fma(p, z, 1.0 / 19.0);
+  p = fma(p, z, 1.0 / 17.0);
+  p = fma(p, z, 1.0 / 15.0);
+  p = fma(p, z, 1.0 / 13.0);
+  p = fma(p, z, 1.0 / 11.0);
+  p = fma(p, z, 1.0 / 9.0);
+  p = fma(p, z, 1.0 / 7.0);
+  p = fma(p, z, 1.0 / 5.0);
+  p = fma(p, z, 1.0 / 3.0);
+  const double t = 2.0 * s;
+  const double lm = fma(t * z, p, t);
+  const double de = (double)e;
+  return fma(de, 0.6931471805599453, fma(de, 2.3190468138462996e-17, lm));
+}
+
 // delta, rpp, rvv from ptau: v = ptau (ptau + 2/beta0), delta = v/(1 + sqrt(1+v)),
 // rpp = 1/(1+delta), rvv = (1+delta)/(1 + beta0 ptau).
 __device__ __forceinline__ void from_ptau(Pt& q, double beta0, double two_over_beta0) {
@@ -101,7 +186,7 @@ __device__ __forceinline__ void from_ptau(Pt& q, double beta0, double two_over_b
 // k = 2 pi f / (beta0 c).
 __device__ __forceinline__ void rf(Pt& q, double amp, double k, double phase, double beta0,
                                    double two_over_beta0) {
-  const double s = sin(phase - k * q.zeta);
+  const double s = xsin(phase - k * q.zeta);
   q.ptau = q.ptau + amp * s;
   from_ptau(q, beta0, two_over_beta0);
 }
@@ -180,7 +265,7 @@ __device__ __forceinline__ double gauss_at(unsigned long long seed, long long pi
   c.d = (unsigned int)element * 8u + (unsigned int)draw;
   const U4 w = philox4x32_10(c, (unsigned int)seed, (unsigned int)(seed >> 32));
   const double u1 = uniform52(w.a, w.b), u2 = uniform52(w.c, w.d);
-  return sqrt(-2.0 * log(u1)) * cos(2.0 * 3.141592653589793 * u2);
+  return sqrt(-2.0 * xlog(u1)) * xcos(6.283185307179586 * u2);
 }
 
 // ------------------------------------------------------------ radiation

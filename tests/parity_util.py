@@ -60,3 +60,15 @@ def bitwise_fraction(g, o, mask):
     for f in ALL_FLOAT:
         eq &= (g[f] == getattr(o, f)) | (np.isnan(g[f]) & np.isnan(getattr(o, f)))
     return float(eq[mask].mean()) if mask.any() else 1.0
+
+
+def assert_bitwise(g, o, fields=ALL_FLOAT + ("state", "at_turn", "at_element")):
+    """Every listed field equal bit for bit (NaN matches NaN): the rounding
+    contract of the two implementations (same operation order, explicit
+    fused multiply-adds, correctly rounded IEEE operations and the same
+    series for sin, cos and log)."""
+    for f in fields:
+        a, b = g[f], (o[f] if isinstance(o, dict) else getattr(o, f))
+        same = (a == b) | (np.isnan(a) & np.isnan(b)) if a.dtype.kind == "f" else (a == b)
+        bad = np.nonzero(~same)[0]
+        assert bad.size == 0, f"{f}: {bad.size} differ, first {bad[:5]}: {a[bad[:3]]} vs {b[bad[:3]]}"

@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 from paper_2310_00317_amd import inputs as I
-from parity_util import assert_parity, gpu_run, oracle_run
+from parity_util import assert_bitwise, assert_parity, gpu_run, oracle_run
 
 pytestmark = pytest.mark.gpu
 EREF = I.ELECTRON_45GEV6
@@ -68,6 +68,7 @@ def test_radiation_parity_small_ring(P, oracle_mod, mode):
     op = oracle_mod.track(el, EREF, o, 60, radiation=mode, seed=2024)
     assert gp == op
     assert_parity(g, o, rtol=1e-12)
+    assert_bitwise(g, o)
 
 
 def test_radiation_full_electron_ring_short(P, oracle_mod):
@@ -78,6 +79,7 @@ def test_radiation_full_electron_ring_short(P, oracle_mod):
     op = oracle_mod.track(el, EREF, o, 3, radiation=2, seed=7)
     assert gp == op
     assert_parity(g, o, rtol=1e-12)
+    assert_bitwise(g, o)
 
 
 def test_radiation_graph_and_chunks_invariant(P):
