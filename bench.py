@@ -74,17 +74,36 @@ def workload(name: str, n_override: int | None):
         c = I.cfg1_particles(n_override or (1 << 20))
         desc = f"thin FODO ring, 801 elements, {len(c)} Gaussian protons at 450 GeV"
         return el, c, I.PROTON_450GEV, desc, 100, 1
+    if name == "cfg5":
+        el = I.cfg5_lattice()
+        c = I.cfg5_particles(n_override or 1_000_000)
+        desc = (f"electron ring, 20,000 thin elements (bends with radiation length, 8 RF), "
+                f"{len(c)} electrons at 45.6 GeV, mean + quantum radiation (Philox deviates)")
+        return el, c, I.ELECTRON_45GEV6, desc, 10, 2
+    if name == "cfg3":
+        counts = I.cfg3_counts()
+        if n_override:
+            counts = np.maximum(1, (counts * (n_override / counts.sum())).astype(np.int64))
+        els, cs = [], []
+        for v, n in enumerate(counts):
+            e, c = I.cfg3_variant(v, int(n))
+            els.append(e)
+            cs.append(c)
+        desc = (f"64 errored variants of the thin FODO ring (801 elements each), "
+                f"{int(counts.sum())} Gaussian protons in total (2,000-50,000 per variant), "
+                "one batched launch per chunk")
+        return els, (np.concatenate(cs), counts), I.PROTON_450GEV, desc, 200, 2
     raise SystemExit(f"unknown workload {name}")
 
 
-def cpu_baseline(el, c, ref, sample_every: int, turns: int):
+def cpu_baseline(el, c, ref, sample_every: int, turns: int, radiation: int = 0, seed: int = 0):
     import oracle
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     threads = max(1, min(threads, os.cpu_count() or 1))
     sub = c[::sample_every]
     p = oracle.init(sub, ref)
     t = time.perf_counter()
-    passes = oracle.track(el, ref, p, turns, nthreads=threads)
+    passes = oracle.track(el, ref, p, turns, nthreads=threads, radiation=radiation, seed=seed)
     dt = time.perf_counter() - t
     return {"value": passes / dt, "unit": "passes/s", "cores": threads, "kind": "oracle",
             "sample": f"every {sample_every}th particle ({len(sub)}) x {turns} turns "
@@ -163,7 +182,8 @@ def main():
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--turns-per-step", type=int, default=None)
-    ap.add_argument("--workload", default="cfg2", choices=["cfg2", "cfg1", "cfg1sat", "cfg4"])
+    ap.add_argument("--workload", default="cfg2",
+                    choices=["cfg2", "cfg1", "cfg1sat", "cfg3", "cfg4", "cfg5"])
     ap.add_argument("--da-rays", type=int, default=500, help="cfg4: rays of the evaluation grid")
     ap.add_argument("--da-radii", type=int, default=2000, help="cfg4: radii per ray")
     ap.add_argument("--da-rmax", type=float, default=30.0, help="cfg4: grid edge [sigma]")
@@ -179,7 +199,8 @@ def main():
     ap.add_argument("--variant", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-every", type=int, default=100)
-    ap.add_argument("--cpu-turns", type=int, default=500)
+    ap.add_argument("--cpu-turns", type=int, default=None,
+                    help="turns of the CPU oracle sample (default 500; 50 with radiation)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -205,19 +226,38 @@ def main():
     el, coords, ref, desc, tps_default, steps_default = workload(args.workload, args.particles)
     tps = args.turns_per_step or tps_default
     steps = args.steps if args.steps is not None else steps_default
+    batched = args.workload == "cfg3"
+    if batched:
+        coords, counts = coords
+        first = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+        el_all = np.concatenate(el)
+    else:
+        el_all = el
     n = len(coords)
-    print(f"[bench] workload {args.workload}: {n} particles, {len(el)} elements, "
+    n_el = len(el[0]) if batched else len(el)
+    print(f"[bench] workload {args.workload}: {n} particles, {n_el} elements, "
           f"{steps} x {tps} turns (+{args.warmup} warmup steps)", file=sys.stderr, flush=True)
 
     torch.cuda.set_device(0)
-    lat = P.Lattice(el, ref)
+    if batched:
+        lats = [P.Lattice(e, ref) for e in el]
+        batch = P.Batch(lats)
+    else:
+        lat = P.Lattice(el, ref)
     coords_dev = torch.from_numpy(np.ascontiguousarray(coords)).to("cuda")
+    extra = dict(radiation=2, seed=20231002) if args.workload == "cfg5" else {}
+
+    def run(parts, turns, **kw):
+        if batched:
+            return P.track_batched(batch, parts, first, turns, block=args.block,
+                                   turns_per_chunk=args.chunk, full_stats=True, **kw)
+        return P.track(lat, parts, turns, block=args.block, turns_per_chunk=args.chunk,
+                       variant=args.variant, full_stats=True, **extra, **kw)
 
     if args.warmup > 0:
         w = P.Particles(n, ref).init(coords_dev)
         for _ in range(args.warmup):
-            P.track(lat, w, tps, block=args.block, turns_per_chunk=args.chunk,
-                    variant=args.variant)
+            run(w, tps)
         w.close()
         del w
 
@@ -233,8 +273,7 @@ def main():
     start.record()
     alive = n
     for s in range(steps):
-        st = P.track(lat, parts, tps, block=args.block, turns_per_chunk=args.chunk,
-                     variant=args.variant, time_kernels=True, full_stats=True)
+        st = run(parts, tps, time_kernels=True)
         total_passes += st.passes
         kernel_ms += st.kernel_ms
         launches += st.launches
@@ -247,8 +286,8 @@ def main():
     ms = start.elapsed_time(stop)
     value = total_passes / (ms / 1e3)
 
-    flops = element_flops(el)
-    flops_per_pass = float(flops.sum() / len(el))
+    flops = element_flops(el_all)
+    flops_per_pass = float(flops.sum() / len(el_all))
     achieved_tflops = total_passes * flops_per_pass / (kernel_ms / 1e3) / 1e12 if kernel_ms > 0 else 0.0
 
     out = {
@@ -264,7 +303,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": desc, "n_particles": n, "n_elements": len(el),
+        "config": {"workload": desc, "n_particles": n, "n_elements": n_el,
                    "turns": steps * tps, "alive_at_end": int(alive),
                    "passes": int(total_passes), "wall_s": wall},
         "roofline": {"bound": "alu", "kernel": KERNEL_NAMES.get(variant_ran, "?"),
@@ -275,7 +314,14 @@ def main():
     }
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a sample", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(el, coords, ref, args.cpu_sample_every, args.cpu_turns)
+        if args.cpu_turns is None:
+            args.cpu_turns = 50 if extra else 500
+        if batched:
+            out["cpu_baseline"] = cpu_baseline(el[0], coords[: counts[0]], ref,
+                                               args.cpu_sample_every, args.cpu_turns)
+        else:
+            out["cpu_baseline"] = cpu_baseline(el, coords, ref, args.cpu_sample_every,
+                                               args.cpu_turns, **extra)
     print(json.dumps(out), flush=True)
 
 
