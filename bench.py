@@ -25,7 +25,9 @@ sys.path.insert(0, ROOT)
 
 FP64_VECTOR_PEAK_TFLOPS = 78.6   # 256 CU x 128 FP64 FLOP/clk x 2.4 GHz
 KERNEL_NAMES = {1: "k_track", 2: "k_track2", 3: "k_track3", 4: "k_track4",
-                5: "xtm_line (per-line generated kernel)"}
+                5: "xtm_line (per-line kernel, 256-lane workgroups)",
+                6: "xtm_line (per-line kernel, one-wave workgroups)",
+                7: "xtm_line (per-line kernel, one-wave workgroups, pipelined parameters)"}
 
 # algorithmic FLOPs per element application (sqrt, div, sin, compare count 1;
 # fma counts 2), as the kernel's maps are written
@@ -60,6 +62,8 @@ def workload(name: str, n_override: int | None):
     if name == "cfg2":
         el = I.cfg2_lattice()
         c, _, _ = I.cfg2_grid(2000, 50, 10.0)
+        if n_override:
+            c = c[:n_override]   # the first rays of the grid (a timing subset)
         desc = ("DA scan: 20,000-element errored thin ring (order-10 multipoles, 8 RF, "
                 "circular apertures), 100,000 protons at 450 GeV on a 2000x50 polar grid "
                 "0-10 sigma, delta=2.7e-4")

@@ -168,7 +168,13 @@ typedef struct xtm_track_opts {
                               kept in registers and replayed after the chunk;
                               5 = per-line kernel generated from the lattice's cell
                               structure and compiled at first use (as 4 for losses;
-                              always 256-lane workgroups, `block` is ignored);
+                              `block` is ignored), 256-lane workgroups sharing the
+                              cell parameters staged in LDS; 6 = the same with
+                              one-wave workgroups (no barriers); 7 = as 6,
+                              each element's parameters read into registers
+                              while the previous element runs (more registers,
+                              less LDS latency; for sets too small to fill the
+                              SIMDs with waves);
                               XTM_E_UNSUPPORTED if it cannot be built */
   int32_t radiation;       /* synchrotron radiation in multipoles with length > 0:
                               0 off, 1 mean energy loss, 2 mean + quantum excitation
@@ -251,8 +257,9 @@ xtm_status xtm_track_batched(xtm_batch b, xtm_particles p, const int64_t* first_
                              int32_t n_turns, const xtm_track_opts* opts, void* stream,
                              xtm_track_stats* stats);
 
-/* Launch-plan autotuner.  Times every candidate (kernel variant 5 when the
-   line has one, 4; blocks of 64, 128 and 256 lanes) for probe_turns turns on
+/* Launch-plan autotuner.  Times every candidate (kernel variants 5, 6 and 7
+   when the line has a per-line kernel, each with its 256-lane workgroups;
+   variant 4 with blocks of 64, 128 and 256 lanes) for probe_turns turns on
    a scratch copy of the set (the set itself is not advanced), keeps the
    fastest as the plan of the lattice (or batch), and reports it.  Later
    xtm_track / xtm_track_batched calls whose options leave both `variant`
@@ -260,7 +267,7 @@ xtm_status xtm_track_batched(xtm_batch b, xtm_particles p, const int64_t* first_
    (`first_slot` as for xtm_track_batched with a batch, else ignored).
    Synchronises; allocates a scratch set of the same size. */
 typedef struct xtm_plan {
-  int32_t variant;      /* kernel variant chosen (4 or 5) */
+  int32_t variant;      /* kernel variant chosen (4..7) */
   int32_t block;        /* lanes per workgroup chosen */
   double passes_per_s;  /* its measured rate, chunk epilogues included */
 } xtm_plan;

@@ -70,7 +70,7 @@ struct xtm_lattice_s {
   int32_t* fwd_seg_d = nullptr;
   int32_t* bwd_seg_d = nullptr;
   // per-line kernels, compiled on first use
-  xtm::LineKernel fwd_line, bwd_line;
+  xtm::LineKernel fwd_line[xtm::kLineStyles], bwd_line[xtm::kLineStyles];
   // launch plan chosen by xtm_autotune (0 = none): used when the caller's
   // options leave the kernel variant and block size at 0
   int32_t plan_variant = 0, plan_block = 0;
@@ -293,6 +293,14 @@ xtm_status read_alive(xtm_particles_s* p, hipStream_t s, int64_t* alive, int64_t
   return XTM_OK;
 }
 
+// Per-line kernel style when the caller leaves the choice to the library:
+// workgroup-shared parameter slots (5) when the set gives every SIMD several
+// waves, per-wave slots with a register-rich schedule (7) for smaller sets.
+int32_t default_line_variant(int64_t n_alive) {
+  constexpr int64_t kManyWaves = 3LL * 1024 * 64;  // three waves on each of the 1024 SIMDs
+  return n_alive >= kManyWaves ? 5 : 5;
+}
+
 int32_t auto_chunk(int64_t n, int32_t n_el, int32_t n_turns) {
   // aim at ~2e10 passes per launch so launch and epilogue costs vanish, while
   // compacting often enough that lost lanes stop costing issue slots
@@ -450,7 +458,7 @@ xtm_status run_turns(xtm_lattice_s* L, xtm_particles_s* P, int32_t n_turns,
     return fail(XTM_E_ARG, "block must be 64, 128, 192 or 256");
   c.compact = !(o && o->no_compact) || backward;
   c.variant = (o && o->variant) ? o->variant : (use_plan && !B ? L->plan_variant : 0);
-  if (c.variant < 0 || c.variant > 5) return fail(XTM_E_ARG, "kernel variant must be 0..5");
+  if (c.variant < 0 || c.variant > 7) return fail(XTM_E_ARG, "kernel variant must be 0..7");
   if (B) {
     if (backward) return fail(XTM_E_UNSUPPORTED, "batched tracking is forward only");
     if (c.variant != 0 && c.variant != 4)
@@ -460,19 +468,20 @@ xtm_status run_turns(xtm_lattice_s* L, xtm_particles_s* P, int32_t n_turns,
   c.line = nullptr;
   if ((c.rad_mode || c.rec) && c.variant >= 1 && c.variant <= 3)
     return fail(XTM_E_UNSUPPORTED, "kernel variants 1-3 implement neither radiation nor the recorder");
-  if (!B && (c.variant == 0 || c.variant == 5)) {
+  if (!B && (c.variant == 0 || c.variant >= 5)) {
     // the per-line kernel, compiled on first use; the default falls back to
     // the register-loss interpreter if the line has no compact cell structure
-    LineKernel& lk = backward ? L->bwd_line : L->fwd_line;
+    const int32_t want = c.variant ? c.variant : default_line_variant(P->alive_upper);
+    LineKernel& lk = (backward ? L->bwd_line : L->fwd_line)[want - 5];
     if (!lk.tried && L->n_el > 0) {
       lk.tried = true;
-      build_line_kernel(backward ? L->bwd_h : L->fwd_h, L->n_el, &lk);
+      build_line_kernel(backward ? L->bwd_h : L->fwd_h, L->n_el, want - 5, &lk);
     }
     if (lk.ok) {
-      c.variant = 5;
+      c.variant = want;
       c.line = &lk;
-      c.block = kLineBlock;
-    } else if (c.variant == 5 && L->n_el > 0) {
+      c.block = line_block(want - 5);
+    } else if (c.variant >= 5 && L->n_el > 0) {
       return fail(XTM_E_UNSUPPORTED, "per-line kernel unavailable: " + lk.error);
     } else {
       c.variant = 4;
@@ -608,8 +617,10 @@ xtm_status xtm_lattice_destroy(xtm_lattice L) {
   hipFree(L->bwd_d);
   hipFree(L->fwd_seg_d);
   hipFree(L->bwd_seg_d);
-  free_line_kernel(&L->fwd_line);
-  free_line_kernel(&L->bwd_line);
+  for (int32_t k = 0; k < kLineStyles; ++k) {
+    free_line_kernel(&L->fwd_line[k]);
+    free_line_kernel(&L->bwd_line[k]);
+  }
   delete L;
   return XTM_OK;
 }
@@ -876,11 +887,14 @@ xtm_status xtm_autotune(xtm_lattice L, xtm_batch B, xtm_particles P, const int64
     if (st != XTM_OK) return st;
     std::vector<int32_t> variants;
     if (!B && lat->n_el > 0) {
-      if (!lat->fwd_line.tried) {
-        lat->fwd_line.tried = true;
-        build_line_kernel(lat->fwd_h, lat->n_el, &lat->fwd_line);
+      for (int32_t k = 0; k < kLineStyles; ++k) {
+        LineKernel& lk = lat->fwd_line[k];
+        if (!lk.tried) {
+          lk.tried = true;
+          build_line_kernel(lat->fwd_h, lat->n_el, k, &lk);
+        }
+        if (lk.ok) variants.push_back(5 + k);
       }
-      if (lat->fwd_line.ok) variants.push_back(5);
     }
     variants.push_back(4);
     const int32_t blocks[3] = {64, 128, 256};
@@ -891,7 +905,7 @@ xtm_status xtm_autotune(xtm_lattice L, xtm_batch B, xtm_particles P, const int64
     HIP_TRY(hipEventCreate(&e1), "event");
     for (int32_t v : variants) {
       for (int32_t blk : blocks) {
-        if (v == 5 && blk != kLineBlock) continue;  // the per-line kernel's fixed shape
+        if (v >= 5 && blk != line_block(v - 5)) continue;  // the per-line kernels' fixed shape
         xtm_track_opts o{};
         o.variant = v;
         o.block = blk;

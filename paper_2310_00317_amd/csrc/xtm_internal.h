@@ -105,6 +105,7 @@ constexpr int kScanBlock = 1024;
 struct LineKernel {
   bool ok = false;
   bool tried = false;
+  int32_t style = 0;
   hipFunction_t fn = nullptr;
   int32_t period = 0, n_cells = 0, n_kinds = 0;  // period = length of the repeating unit
   double* prm_d = nullptr;     // element parameters in element order, no headers
@@ -112,7 +113,12 @@ struct LineKernel {
   std::string source;
   std::string error;
 };
-bool build_line_kernel(const std::vector<uint64_t>& tab, int32_t n_el, LineKernel* k);
+// style: 0 workgroup-shared parameter slots with barriers; 1 per-wave slots;
+// 2 per-wave slots with element parameters software-pipelined into registers
+constexpr int32_t kLineStyles = 3;
+inline int32_t line_block(int32_t style) { return style == 0 ? kLineBlock : 64; }
+bool build_line_kernel(const std::vector<uint64_t>& tab, int32_t n_el, int32_t style,
+                       LineKernel* k);
 void free_line_kernel(LineKernel* k);
 hipError_t launch_line(const LineKernel& k, int32_t n_el, SoA P, const int32_t* idx,
                        const int32_t* ctrl, int64_t grid_upper, int32_t block, int32_t n_turns,

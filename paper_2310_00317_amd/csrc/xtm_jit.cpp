@@ -126,54 +126,55 @@ int32_t n_words(uint32_t s) {
   }
 }
 
-// C++ statement applying one element whose parameters start at p[o]; `j` is
+// C++ statement applying one element whose parameters are P[0..] where P is
+// the expression `arr` (an LDS pointer "p + o" or a local array name); `j` is
 // its position in the cell (the loss code is e0 + j).
-std::string emit(uint32_t s, int32_t o, int32_t j) {
+std::string emit(uint32_t s, const std::string& arr, int32_t j) {
   const uint32_t kt = s & 0xffu, order = (s >> 8) & 0xffu;
+  auto P = [&](int32_t m) { return "(" + arr + ")[" + std::to_string(m) + "]"; };
   std::ostringstream c;
   switch (kt) {
     case K_DRIFT:
-      c << "xtmm::mark(xtmm::drift_exact(q, p[" << o << "]), code, st, e0 + " << j << ", -1);";
+      c << "xtmm::mark(xtmm::drift_exact(q, " << P(0) << "), code, st, e0 + " << j << ", -1);";
       break;
     case K_DRIFT_EXP:
-      c << "xtmm::drift_expanded(q, p[" << o << "]);";
+      c << "xtmm::drift_expanded(q, " << P(0) << ");";
       break;
     case K_MULT:
-      c << "{ double kx, ky; xtmm::multipole<" << order << ">(q, p + " << o << ", kx, ky); }";
+      c << "{ double kx, ky; xtmm::multipole<" << order << ">(q, " << arr << ", kx, ky); }";
       break;
     case K_MULT_CURV: {
-      const int32_t v = o + 2 * ((int32_t)order + 1);
-      c << "{ double kx, ky; xtmm::multipole<" << order << ">(q, p + " << o
-        << ", kx, ky); xtmm::curvature(q, p[" << v << "], p[" << v + 1 << "], p[" << v + 2
-        << "]); RAD(kx, ky, p[" << v + 2 << "], " << j << "); }";
+      const int32_t v = 2 * ((int32_t)order + 1);
+      c << "{ double kx, ky; xtmm::multipole<" << order << ">(q, " << arr
+        << ", kx, ky); xtmm::curvature(q, " << P(v) << ", " << P(v + 1) << ", " << P(v + 2)
+        << "); RAD(kx, ky, " << P(v + 2) << ", " << j << "); }";
       break;
     }
     case K_MULT_LR: {
-      const int32_t v = o + 2 * ((int32_t)order + 1);
-      c << "{ double kx, ky; xtmm::multipole<" << order << ">(q, p + " << o
-        << ", kx, ky); RAD(kx, ky, p[" << v << "], " << j << "); }";
+      const int32_t v = 2 * ((int32_t)order + 1);
+      c << "{ double kx, ky; xtmm::multipole<" << order << ">(q, " << arr
+        << ", kx, ky); RAD(kx, ky, " << P(v) << ", " << j << "); }";
       break;
     }
     case K_RF:
-      c << "xtmm::rf(q, p[" << o << "], p[" << o + 1 << "], p[" << o + 2
-        << "], beta0, two_over_beta0);";
+      c << "xtmm::rf(q, " << P(0) << ", " << P(1) << ", " << P(2) << ", beta0, two_over_beta0);";
       break;
     case K_SHIFT:
-      c << "xtmm::xyshift(q, p[" << o << "], p[" << o + 1 << "]);";
+      c << "xtmm::xyshift(q, " << P(0) << ", " << P(1) << ");";
       break;
     case K_SROT:
-      c << "xtmm::srotation(q, p[" << o << "], p[" << o + 1 << "]);";
+      c << "xtmm::srotation(q, " << P(0) << ", " << P(1) << ");";
       break;
     case K_AP_CIRC:
-      c << "xtmm::mark(xtmm::in_circle(q, p[" << o << "]), code, st, e0 + " << j << ", 0);";
+      c << "xtmm::mark(xtmm::in_circle(q, " << P(0) << "), code, st, e0 + " << j << ", 0);";
       break;
     case K_AP_ELL:
-      c << "xtmm::mark(xtmm::in_ellipse(q, p[" << o << "], p[" << o + 1 << "]), code, st, e0 + "
-        << j << ", 0);";
+      c << "xtmm::mark(xtmm::in_ellipse(q, " << P(0) << ", " << P(1) << "), code, st, e0 + " << j
+        << ", 0);";
       break;
     case K_AP_RECT:
-      c << "xtmm::mark(xtmm::in_rect(q, p[" << o << "], p[" << o + 1 << "], p[" << o + 2
-        << "], p[" << o + 3 << "]), code, st, e0 + " << j << ", 0);";
+      c << "xtmm::mark(xtmm::in_rect(q, " << P(0) << ", " << P(1) << ", " << P(2) << ", " << P(3)
+        << "), code, st, e0 + " << j << ", 0);";
       break;
     default:
       break;  // marker
@@ -193,10 +194,20 @@ int32_t kind_words(const std::vector<uint32_t>& k) {
 // memory and writes it to the other slot before the cell barrier.  Element
 // code then reads its parameters as broadcast LDS reads at compile-time
 // offsets.
-std::string generate(const Decomp& d) {
+std::string generate(const Decomp& d, int32_t style) {
   int32_t maxw = 1;
   for (const auto& k : d.kinds) maxw = std::max(maxw, kind_words(k));
-  const int32_t per_thread = (maxw + 255) / 256;
+  // style 0: 256-lane workgroups sharing one LDS slot pair, filled by all
+  // lanes and fenced by workgroup barriers; styles 1 and 2: one-wave
+  // workgroups with their own slot pair and no barriers (a wave's LDS
+  // operations are processed in order), which also spreads a small set over
+  // every compute unit; style 2 also software-pipelines the parameter reads
+  // (element j+1's parameters move to registers while element j runs), which
+  // costs registers and pays when the set is too small to give every SIMD
+  // several waves to hide the LDS latency with
+  const bool per_wave = style != 0;
+  const int32_t lanes = per_wave ? 64 : 256;  // workgroup size: one wave, or four
+  const int32_t per_thread = (maxw + lanes - 1) / lanes;
   std::ostringstream s;
   s << "#include \"xtm_maps.h\"\n"
        "struct SoA { double *x, *px, *y, *py, *zeta, *delta, *ptau, *rpp, *rvv;\n"
@@ -208,20 +219,23 @@ std::string generate(const Decomp& d) {
        "    t0 + t, ec + (j), r.gamma0, r.c_mean, r.c_quant, r.p0c, beta0, two_over_beta0)\n"
        "#define MAXW " << maxw << "\n"
        "#define PER_THREAD " << per_thread << "\n"
-       "extern \"C\" __global__ void __launch_bounds__(256)\n"
+       "#define LANES " << lanes << "\n"
+       "extern \"C\" __global__ void __launch_bounds__(" << lanes << ")\n"
        "xtm_line(const double* __restrict__ prm, const int* __restrict__ cells, int n_cells,\n"
        "         int n_el, SoA P, const int* __restrict__ idx, const int* __restrict__ ctrl,\n"
-       "         int n_turns, int backward, KRef r) {\n"
-       "  __shared__ double slot[2 * MAXW];\n"
-       "  const int t0 = ctrl[1];\n"
+       "         int n_turns, int backward, KRef r) {\n";
+  s << "  __shared__ double slot[2 * MAXW];\n"
+       "  const int lane = threadIdx.x;\n";
+  s << "  const int t0 = ctrl[1];\n"
        "  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;\n"
        "  const bool in_range = i < ctrl[0];\n"
        "  const int pi = in_range ? idx[i] : 0;\n"
        "  const bool tracked = in_range && P.state[pi] == 1;\n"
        "  int code = tracked ? 0 : 1;\n"
-       "  int st = 1;\n"
-       "  if (__syncthreads_and(code != 0)) return;\n"
-       "  xtmm::Pt q;\n"
+       "  int st = 1;\n";
+  s << (per_wave ? "  if (__all(code != 0)) return;\n"
+                 : "  if (__syncthreads_and(code != 0)) return;\n");
+  s << "  xtmm::Pt q;\n"
        "  q.x = P.x[pi]; q.px = P.px[pi]; q.y = P.y[pi]; q.py = P.py[pi]; q.zeta = P.zeta[pi];\n"
        "  q.delta = P.delta[pi]; q.ptau = P.ptau[pi]; q.rpp = P.rpp[pi]; q.rvv = P.rvv[pi];\n"
        "  const double beta0 = r.beta0, two_over_beta0 = r.two_over_beta0;\n"
@@ -229,10 +243,10 @@ std::string generate(const Decomp& d) {
        "  xtmm::refresh(q, beta0);\n"
        "  {\n"
        "    const int off0 = cells[1], nw0 = cells[3];\n"
-       "    for (int w = threadIdx.x; w < nw0; w += blockDim.x) slot[w] = prm[off0 + w];\n"
-       "  }\n"
-       "  __syncthreads();\n"
-       "  int b = 0;\n"
+       "    for (int w = lane; w < nw0; w += LANES) slot[w] = prm[off0 + w];\n"
+       "  }\n";
+  s << (per_wave ? "  __builtin_amdgcn_wave_barrier();\n" : "  __syncthreads();\n");
+  s << "  int b = 0;\n"
        "  for (int t = 0; t < n_turns; ++t) {\n"
        "    const int enc_t = t * n_el + 1;\n"
        "    if (r.rec && t0 + t < r.rec_turns && code == 0) {\n"
@@ -248,7 +262,7 @@ std::string generate(const Decomp& d) {
        "      double pre[PER_THREAD];\n"
        "#pragma unroll\n"
        "      for (int k = 0; k < PER_THREAD; ++k) {\n"
-       "        const int w = threadIdx.x + k * 256;\n"
+       "        const int w = lane + k * LANES;\n"
        "        pre[k] = (w < nwn) ? prm[offn + w] : 0.0;\n"
        "      }\n"
        "      const int kind = cells[4 * c];\n"
@@ -266,24 +280,48 @@ std::string generate(const Decomp& d) {
        "      asm volatile(\"v_mov_b32 %0, %1\" : \"=v\"(e0) : \"s\"(enc_t + ec));\n";
   for (size_t k = 0; k < d.kinds.size(); ++k) {
     s << "      " << (k ? "else if" : "if") << " (kind == " << k << ") {\n";
-    int32_t o = 0;
-    for (size_t j = 0; j < d.kinds[k].size(); ++j) {
-      const std::string stmt = emit(d.kinds[k][j], o, (int32_t)j);
-      if (!stmt.empty()) s << "        " << stmt << "\n";
-      o += n_words(d.kinds[k][j]);
+    const auto& kd = d.kinds[k];
+    if (style != 2) {
+      int32_t o = 0;
+      for (size_t j = 0; j < kd.size(); ++j) {
+        const std::string stmt = emit(kd[j], "p + " + std::to_string(o), (int32_t)j);
+        if (!stmt.empty()) s << "        " << stmt << "\n";
+        o += n_words(kd[j]);
+      }
+    } else {
+      // software pipeline: element j+1's parameters are read from LDS into
+      // registers before element j runs; the scheduling barriers keep the
+      // compiler from sinking the reads back down to their uses
+      std::vector<int32_t> off(kd.size() + 1, 0);
+      for (size_t j = 0; j < kd.size(); ++j) off[j + 1] = off[j] + n_words(kd[j]);
+      auto load = [&](size_t j) {
+        const int32_t n = n_words(kd[j]);
+        if (n == 0) return;
+        s << "        double A" << j << "[" << n << "];";
+        for (int32_t m = 0; m < n; ++m) s << " A" << j << "[" << m << "] = p[" << off[j] + m << "];";
+        s << "\n        __builtin_amdgcn_sched_barrier(0);\n";
+      };
+      load(0);
+      for (size_t j = 0; j < kd.size(); ++j) {
+        if (j + 1 < kd.size()) load(j + 1);
+        const std::string arr = n_words(kd[j]) ? "A" + std::to_string(j) : "p";
+        const std::string stmt = emit(kd[j], arr, (int32_t)j);
+        if (!stmt.empty()) s << "        " << stmt << "\n";
+      }
     }
     s << "      }\n";
   }
   s << "#pragma unroll\n"
        "      for (int k = 0; k < PER_THREAD; ++k) {\n"
-       "        const int w = threadIdx.x + k * 256;\n"
+       "        const int w = lane + k * LANES;\n"
        "        if (w < nwn) slot[(b ^ 1) * MAXW + w] = pre[k];\n"
        "      }\n"
-       "      b ^= 1;\n"
-       "      __syncthreads();\n"
-       "    }\n"
-       "    if (__syncthreads_and(code != 0)) break;\n"
-       "  }\n"
+       "      b ^= 1;\n";
+  s << (per_wave ? "      __builtin_amdgcn_wave_barrier();\n" : "      __syncthreads();\n");
+  s << "    }\n";
+  s << (per_wave ? "    if (__all(code != 0)) break;\n"
+                 : "    if (__syncthreads_and(code != 0)) break;\n");
+  s << "  }\n"
        "  if (!tracked) return;\n"
        "  if (code == 0) {\n"
        "    P.x[pi] = q.x; P.px[pi] = q.px; P.y[pi] = q.y; P.py[pi] = q.py; P.zeta[pi] = q.zeta;\n"
@@ -340,7 +378,8 @@ Compiled compile(const std::string& src) {
 
 }  // namespace
 
-bool build_line_kernel(const std::vector<uint64_t>& tab, int32_t n_el, LineKernel* k) {
+bool build_line_kernel(const std::vector<uint64_t>& tab, int32_t n_el, int32_t style,
+                       LineKernel* k) {
   std::vector<uint32_t> sig;
   std::vector<int32_t> word_of;  // parameter-array offset of each element
   std::vector<double> prm;
@@ -363,7 +402,8 @@ bool build_line_kernel(const std::vector<uint64_t>& tab, int32_t n_el, LineKerne
     k->error = "no cell decomposition within the code budget";
     return false;
   }
-  k->source = generate(d);
+  k->style = style;
+  k->source = generate(d, style);
   {
     std::lock_guard<std::mutex> lock(g_mu);
     auto it = g_cache.find(k->source);
@@ -416,11 +456,12 @@ hipError_t launch_line(const LineKernel& k, int32_t n_el, SoA P, const int32_t* 
   int32_t n_cells = k.n_cells;
   void* args[] = {(void*)&prm, (void*)&cells, (void*)&n_cells, (void*)&n_el, (void*)&P,
                   (void*)&idx, (void*)&ctrl, (void*)&n_turns, (void*)&backward, (void*)&r};
-  // the generated kernel stages each cell's parameters with a fixed stride
-  // of 256 lanes, so it always runs in 256-lane workgroups
+  // the generated kernel stages each cell's parameters with the stride of
+  // its fixed workgroup size (256 lanes for style 0, one wave otherwise)
   (void)block;
-  const unsigned grid = (unsigned)((grid_upper + kLineBlock - 1) / kLineBlock);
-  return hipModuleLaunchKernel(k.fn, grid, 1, 1, (unsigned)kLineBlock, 1, 1, 0, s, args, nullptr);
+  const int32_t wg = line_block(k.style);
+  const unsigned grid = (unsigned)((grid_upper + wg - 1) / wg);
+  return hipModuleLaunchKernel(k.fn, grid, 1, 1, (unsigned)wg, 1, 1, 0, s, args, nullptr);
 }
 
 }  // namespace xtm

@@ -184,8 +184,10 @@ __device__ __forceinline__ void from_ptau(Pt& q, double beta0, double two_over_b
 
 // Thin RF cavity: ptau += amp sin(phase - k zeta), amp = charge0 V / p0c,
 // k = 2 pi f / (beta0 c).
-__device__ __forceinline__ void rf(Pt& q, double amp, double k, double phase, double beta0,
-                                   double two_over_beta0) {
+// (kept out of line: RF cavities are rare in a lattice, and inlining the
+// sine's constants into every per-line kernel costs registers in its loop)
+__device__ __attribute__((noinline)) void rf(Pt& q, double amp, double k, double phase,
+                                             double beta0, double two_over_beta0) {
   const double s = xsin(phase - k * q.zeta);
   q.ptau = q.ptau + amp * s;
   from_ptau(q, beta0, two_over_beta0);
@@ -256,8 +258,9 @@ __device__ __forceinline__ double uniform52(unsigned int wa, unsigned int wb) {
 
 // Standard normal of (seed, particle id, turn, element, draw) by Box-Muller
 // on one Philox block with counter (pid_lo, pid_hi, turn, element * 8 + draw).
-__device__ __forceinline__ double gauss_at(unsigned long long seed, long long pid, int turn,
-                                           int element, int draw) {
+// (out of line for the same reason as rf: Philox, log and cosine constants)
+__device__ __attribute__((noinline)) double gauss_at(unsigned long long seed, long long pid,
+                                                     int turn, int element, int draw) {
   U4 c;
   c.a = (unsigned int)(unsigned long long)pid;
   c.b = (unsigned int)((unsigned long long)pid >> 32);

@@ -5,7 +5,7 @@ import numpy as np
 import pytest
 
 from paper_2310_00317_amd import inputs as I
-from parity_util import assert_parity
+from parity_util import assert_bitwise, assert_parity
 
 pytestmark = pytest.mark.gpu
 REF = I.PROTON_450GEV
@@ -74,8 +74,8 @@ def test_batched_matches_oracle(P, oracle_mod):
         o = oracle_mod.init(coords[v], REF, first_id=int(first[v]))
         oracle_mod.track(els[v], REF, o, 200)
         gv = {f: g[f][first[v]:first[v + 1]] for f in FIELDS}
-        # RF sine may differ by an ulp: the general parity gate
-        assert_parity(gv, o, rtol=1e-10)
+        assert_parity(gv, o, rtol=1e-12)
+        assert_bitwise(gv, o)
 
 
 def test_batch_argument_errors(P):
@@ -101,7 +101,7 @@ def test_autotune_leaves_set_and_results_unchanged(P):
     P.track(lat, a, 5)
     before = a.to_numpy()
     plan = P.autotune(a, lattice=lat, probe_turns=3)
-    assert plan.variant in (4, 5) and plan.block in (64, 128, 256) and plan.passes_per_s > 0
+    assert plan.variant in (4, 5, 6, 7) and plan.block in (64, 128, 256) and plan.passes_per_s > 0
     after = a.to_numpy()
     for f in FIELDS:
         assert np.array_equal(before[f], after[f]), f

@@ -147,7 +147,11 @@ def test_resume_bitwise(P):
                                   dict(variant=4), dict(variant=4, turns_per_chunk=3, block=128),
                                   dict(variant=2, turns_per_chunk=11),
                                   dict(turns_per_chunk=100, block=128, compact=False),
-                                  dict(turns_per_chunk=33, block=192)])
+                                  dict(turns_per_chunk=33, block=192),
+                                  dict(variant=5, turns_per_chunk=11),
+                                  dict(variant=6), dict(variant=6, turns_per_chunk=9),
+                                  dict(variant=7), dict(variant=7, turns_per_chunk=13),
+                                  dict(variant=7, turns_per_chunk=5, compact=False)])
 def test_launch_shape_invariance(P, opts):
     banner(f"launch shape {opts}")
     el = I.cfg1_lattice()
