@@ -168,13 +168,11 @@ typedef struct xtm_track_opts {
                               kept in registers and replayed after the chunk;
                               5 = per-line kernel generated from the lattice's cell
                               structure and compiled at first use (as 4 for losses;
-                              `block` is ignored), 256-lane workgroups sharing the
-                              cell parameters staged in LDS; 6 = the same with
-                              one-wave workgroups (no barriers); 7 = as 6,
-                              each element's parameters read into registers
-                              while the previous element runs (more registers,
-                              less LDS latency; for sets too small to fill the
-                              SIMDs with waves);
+                              256-lane workgroups sharing the cell parameters
+                              staged in LDS, `block` is ignored); 6 = as 5, each
+                              element's parameters read into registers while the
+                              previous element runs (more registers, less LDS
+                              latency; for sets too small to fill the SIMDs);
                               XTM_E_UNSUPPORTED if it cannot be built */
   int32_t radiation;       /* synchrotron radiation in multipoles with length > 0:
                               0 off, 1 mean energy loss, 2 mean + quantum excitation
@@ -267,7 +265,7 @@ xtm_status xtm_track_batched(xtm_batch b, xtm_particles p, const int64_t* first_
    (`first_slot` as for xtm_track_batched with a batch, else ignored).
    Synchronises; allocates a scratch set of the same size. */
 typedef struct xtm_plan {
-  int32_t variant;      /* kernel variant chosen (4..7) */
+  int32_t variant;      /* kernel variant chosen (4..6) */
   int32_t block;        /* lanes per workgroup chosen */
   double passes_per_s;  /* its measured rate, chunk epilogues included */
 } xtm_plan;

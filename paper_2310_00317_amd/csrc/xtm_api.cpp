@@ -93,11 +93,12 @@ struct GraphKey {
   uint64_t seed;
   const float* rec;
   int32_t rec_turns;
+  int32_t ramp;
   bool operator==(const GraphKey& o) const {
     return lat == o.lat && n_turns == o.n_turns && chunk == o.chunk && block == o.block &&
            variant == o.variant && backward == o.backward && compact == o.compact &&
            cur == o.cur && rad_mode == o.rad_mode && alive_upper == o.alive_upper &&
-           seed == o.seed && rec == o.rec && rec_turns == o.rec_turns;
+           seed == o.seed && rec == o.rec && rec_turns == o.rec_turns && ramp == o.ramp;
   }
 };
 
@@ -293,9 +294,9 @@ xtm_status read_alive(xtm_particles_s* p, hipStream_t s, int64_t* alive, int64_t
   return XTM_OK;
 }
 
-// Per-line kernel style when the caller leaves the choice to the library:
-// workgroup-shared parameter slots (5) when the set gives every SIMD several
-// waves, per-wave slots with a register-rich schedule (7) for smaller sets.
+// Per-line kernel when the caller leaves the choice to the library: plain
+// parameter reads (5) when the set gives every SIMD several waves, the
+// software-pipelined reads (6) for smaller sets.
 int32_t default_line_variant(int64_t n_alive) {
   constexpr int64_t kManyWaves = 3LL * 1024 * 64;  // three waves on each of the 1024 SIMDs
   return n_alive >= kManyWaves ? 5 : 5;
@@ -323,7 +324,25 @@ struct ChunkPlan {
   int32_t n_seg;
   int32_t n_turns, chunk, block, variant;
   bool backward, compact;
+  bool ramp;  // chunk lengths 1, 2, 4, ... up to `chunk` (automatic chunking)
 };
+
+// Turns of each launch: with automatic chunking the lengths start at one
+// turn and double up to the target, so the losses of a fresh set (most of a
+// dynamic-aperture grid is lost in its first turns) are replayed over short
+// chunks; the sequence is a fixed function of the plan, so a captured graph
+// replays it exactly.
+std::vector<int32_t> chunk_sizes(const ChunkPlan& c) {
+  std::vector<int32_t> v;
+  int32_t done = 0, next = c.ramp ? 1 : c.chunk;
+  while (done < c.n_turns) {
+    const int32_t k = std::min(std::min(next, c.chunk), c.n_turns - done);
+    v.push_back(k);
+    done += k;
+    if (next < c.chunk) next = (next > c.chunk / 2) ? c.chunk : 2 * next;
+  }
+  return v;
+}
 
 // Enqueue the whole chunk sequence on stream s: per chunk the tracking launch,
 // the epilogue (passes + compaction) and the device-side turn advance.  The
@@ -336,11 +355,9 @@ hipError_t enqueue_chunks(xtm_lattice_s* L, xtm_particles_s* P, const ChunkPlan&
   kr.rec = c.rec;
   kr.rec_turns = c.rec_turns;
   kr.rec_n = (int32_t)P->n;
-  int32_t done = 0;
   *launches = 0;
   if (P->alive_upper <= 0) return c.n_turns > 0 ? launch_advance(P->ctrl, c.backward ? -c.n_turns : c.n_turns, s) : hipSuccess;
-  while (done < c.n_turns) {
-    const int32_t k = (c.n_turns - done < c.chunk) ? c.n_turns - done : c.chunk;
+  for (const int32_t k : chunk_sizes(c)) {
     int32_t* in = P->idx[cur];
     int32_t* out = c.compact ? P->idx[1 - cur] : nullptr;
     hipError_t e;
@@ -382,20 +399,19 @@ hipError_t enqueue_chunks(xtm_lattice_s* L, xtm_particles_s* P, const ChunkPlan&
     e = launch_advance(P->ctrl, c.backward ? -k : k, s);
     if (e != hipSuccess) return e;
     if (c.compact) cur = 1 - cur;
-    done += k;
   }
   return hipSuccess;
 }
 
 int32_t flips(const ChunkPlan& c) {
   if (!c.compact || c.n_turns <= 0) return 0;
-  return (c.n_turns + c.chunk - 1) / c.chunk;
+  return (int32_t)chunk_sizes(c).size();
 }
 
 xtm_status run_graph(xtm_lattice_s* L, xtm_particles_s* P, const ChunkPlan& c, hipStream_t s,
                      int32_t* launches) {
   GraphKey key{c.batch ? (const void*)c.batch : (const void*)L, c.n_turns, c.chunk, c.block, c.variant, c.backward ? 1 : 0, c.compact ? 1 : 0,
-               P->cur, c.rad_mode, P->alive_upper, c.seed, c.rec, c.rec_turns};
+               P->cur, c.rad_mode, P->alive_upper, c.seed, c.rec, c.rec_turns, c.ramp ? 1 : 0};
   for (const GraphEntry& g : P->graphs) {
     if (g.key == key) {
       HIP_TRY(hipGraphLaunch(g.exec, s), "graph launch");
@@ -458,7 +474,7 @@ xtm_status run_turns(xtm_lattice_s* L, xtm_particles_s* P, int32_t n_turns,
     return fail(XTM_E_ARG, "block must be 64, 128, 192 or 256");
   c.compact = !(o && o->no_compact) || backward;
   c.variant = (o && o->variant) ? o->variant : (use_plan && !B ? L->plan_variant : 0);
-  if (c.variant < 0 || c.variant > 7) return fail(XTM_E_ARG, "kernel variant must be 0..7");
+  if (c.variant < 0 || c.variant > 6) return fail(XTM_E_ARG, "kernel variant must be 0..6");
   if (B) {
     if (backward) return fail(XTM_E_UNSUPPORTED, "batched tracking is forward only");
     if (c.variant != 0 && c.variant != 4)
@@ -487,6 +503,7 @@ xtm_status run_turns(xtm_lattice_s* L, xtm_particles_s* P, int32_t n_turns,
       c.variant = 4;
     }
   }
+  c.ramp = !(o && o->turns_per_chunk > 0);
   c.chunk = (o && o->turns_per_chunk > 0) ? o->turns_per_chunk
                                            : auto_chunk(P->alive_upper, L->n_el, n_turns);
   if (c.chunk < 1) c.chunk = 1;
@@ -498,6 +515,7 @@ xtm_status run_turns(xtm_lattice_s* L, xtm_particles_s* P, int32_t n_turns,
   c.seg = backward ? L->bwd_seg_d : L->fwd_seg_d;
   c.n_seg = (int32_t)((backward ? L->bwd_seg_h.size() : L->fwd_seg_h.size()) / 3);
   const bool graph = o && o->use_graph;
+  const int64_t alive_before = P->alive_upper;
   if (stats) HIP_TRY(launch_fill_i64(P->passes, 0, s), "clear passes");
   const bool timing = stats && o && o->time_kernels;
   std::vector<hipEvent_t> ev;
@@ -517,7 +535,8 @@ xtm_status run_turns(xtm_lattice_s* L, xtm_particles_s* P, int32_t n_turns,
   } else if (n_turns > 0) {
     HIP_TRY(enqueue_chunks(L, P, c, P->cur, s, timing ? &ev : nullptr, &launches), "chunk launch");
   }
-  if (flips(c) & 1) P->cur = 1 - P->cur;
+  // (an empty alive list enqueues no compaction, so the buffers do not swap)
+  if (alive_before > 0 && (flips(c) & 1)) P->cur = 1 - P->cur;
   P->turn = backward ? P->turn - n_turns : P->turn + n_turns;
   if (stats) {
     int64_t alive = 0, passes = 0;

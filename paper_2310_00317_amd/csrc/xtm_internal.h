@@ -113,10 +113,10 @@ struct LineKernel {
   std::string source;
   std::string error;
 };
-// style: 0 workgroup-shared parameter slots with barriers; 1 per-wave slots;
-// 2 per-wave slots with element parameters software-pipelined into registers
-constexpr int32_t kLineStyles = 3;
-inline int32_t line_block(int32_t style) { return style == 0 ? kLineBlock : 64; }
+// style: 0 element parameters read from the LDS slot where used; 1 the next
+// element's parameters software-pipelined into registers
+constexpr int32_t kLineStyles = 2;
+inline int32_t line_block(int32_t) { return kLineBlock; }
 bool build_line_kernel(const std::vector<uint64_t>& tab, int32_t n_el, int32_t style,
                        LineKernel* k);
 void free_line_kernel(LineKernel* k);

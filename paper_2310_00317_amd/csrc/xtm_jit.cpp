@@ -129,7 +129,7 @@ int32_t n_words(uint32_t s) {
 // C++ statement applying one element whose parameters are P[0..] where P is
 // the expression `arr` (an LDS pointer "p + o" or a local array name); `j` is
 // its position in the cell (the loss code is e0 + j).
-std::string emit(uint32_t s, const std::string& arr, int32_t j) {
+std::string emit(uint32_t s, const std::string& arr, int32_t j, bool far_rf) {
   const uint32_t kt = s & 0xffu, order = (s >> 8) & 0xffu;
   auto P = [&](int32_t m) { return "(" + arr + ")[" + std::to_string(m) + "]"; };
   std::ostringstream c;
@@ -157,7 +157,8 @@ std::string emit(uint32_t s, const std::string& arr, int32_t j) {
       break;
     }
     case K_RF:
-      c << "xtmm::rf(q, " << P(0) << ", " << P(1) << ", " << P(2) << ", beta0, two_over_beta0);";
+      c << (far_rf ? "xtmm::rf_far(q, " : "xtmm::rf(q, ") << P(0) << ", " << P(1) << ", " << P(2)
+        << ", beta0, two_over_beta0);";
       break;
     case K_SHIFT:
       c << "xtmm::xyshift(q, " << P(0) << ", " << P(1) << ");";
@@ -197,16 +198,17 @@ int32_t kind_words(const std::vector<uint32_t>& k) {
 std::string generate(const Decomp& d, int32_t style) {
   int32_t maxw = 1;
   for (const auto& k : d.kinds) maxw = std::max(maxw, kind_words(k));
-  // style 0: 256-lane workgroups sharing one LDS slot pair, filled by all
-  // lanes and fenced by workgroup barriers; styles 1 and 2: one-wave
-  // workgroups with their own slot pair and no barriers (a wave's LDS
-  // operations are processed in order), which also spreads a small set over
-  // every compute unit; style 2 also software-pipelines the parameter reads
-  // (element j+1's parameters move to registers while element j runs), which
-  // costs registers and pays when the set is too small to give every SIMD
-  // several waves to hide the LDS latency with
-  const bool per_wave = style != 0;
-  const int32_t lanes = per_wave ? 64 : 256;  // workgroup size: one wave, or four
+  // 256-lane workgroups share one LDS slot pair, filled by all lanes and
+  // fenced by workgroup barriers.  Style 1 also software-pipelines the
+  // parameter reads (element j+1's parameters move to registers while
+  // element j runs), which costs registers and pays when the set is too small
+  // to give every SIMD several waves to hide the LDS latency with.
+  const bool pipelined = style == 1;
+  const int32_t lanes = 256;
+  // a line with radiating multipoles calls its RF sine out of line
+  bool far_rf = false;
+  for (const auto& k : d.kinds)
+    for (uint32_t e : k) far_rf |= ((e & 0xffu) == K_MULT_CURV || (e & 0xffu) == K_MULT_LR);
   const int32_t per_thread = (maxw + lanes - 1) / lanes;
   std::ostringstream s;
   s << "#include \"xtm_maps.h\"\n"
@@ -215,7 +217,7 @@ std::string generate(const Decomp& d, int32_t style) {
        "struct KRef { double beta0, two_over_beta0, gamma0, c_mean, c_quant, p0c;\n"
        "              unsigned long long seed; int rad_mode; int pad;\n"
        "              float* rec; int rec_turns; int rec_n; };\n"
-       "#define RAD(kx, ky, lr, j) xtmm::radiate_at(q, kx, ky, lr, r.rad_mode, r.seed, pid, \\\n"
+       "#define RAD(kx, ky, lr, j) xtmm::radiate_at<true>(q, kx, ky, lr, r.rad_mode, r.seed, pid, \\\n"
        "    t0 + t, ec + (j), r.gamma0, r.c_mean, r.c_quant, r.p0c, beta0, two_over_beta0)\n"
        "#define MAXW " << maxw << "\n"
        "#define PER_THREAD " << per_thread << "\n"
@@ -233,8 +235,7 @@ std::string generate(const Decomp& d, int32_t style) {
        "  const bool tracked = in_range && P.state[pi] == 1;\n"
        "  int code = tracked ? 0 : 1;\n"
        "  int st = 1;\n";
-  s << (per_wave ? "  if (__all(code != 0)) return;\n"
-                 : "  if (__syncthreads_and(code != 0)) return;\n");
+  s << "  if (__syncthreads_and(code != 0)) return;\n";
   s << "  xtmm::Pt q;\n"
        "  q.x = P.x[pi]; q.px = P.px[pi]; q.y = P.y[pi]; q.py = P.py[pi]; q.zeta = P.zeta[pi];\n"
        "  q.delta = P.delta[pi]; q.ptau = P.ptau[pi]; q.rpp = P.rpp[pi]; q.rvv = P.rvv[pi];\n"
@@ -245,7 +246,7 @@ std::string generate(const Decomp& d, int32_t style) {
        "    const int off0 = cells[1], nw0 = cells[3];\n"
        "    for (int w = lane; w < nw0; w += LANES) slot[w] = prm[off0 + w];\n"
        "  }\n";
-  s << (per_wave ? "  __builtin_amdgcn_wave_barrier();\n" : "  __syncthreads();\n");
+  s << "  __syncthreads();\n";
   s << "  int b = 0;\n"
        "  for (int t = 0; t < n_turns; ++t) {\n"
        "    const int enc_t = t * n_el + 1;\n"
@@ -281,10 +282,10 @@ std::string generate(const Decomp& d, int32_t style) {
   for (size_t k = 0; k < d.kinds.size(); ++k) {
     s << "      " << (k ? "else if" : "if") << " (kind == " << k << ") {\n";
     const auto& kd = d.kinds[k];
-    if (style != 2) {
+    if (!pipelined) {
       int32_t o = 0;
       for (size_t j = 0; j < kd.size(); ++j) {
-        const std::string stmt = emit(kd[j], "p + " + std::to_string(o), (int32_t)j);
+        const std::string stmt = emit(kd[j], "p + " + std::to_string(o), (int32_t)j, far_rf);
         if (!stmt.empty()) s << "        " << stmt << "\n";
         o += n_words(kd[j]);
       }
@@ -305,7 +306,7 @@ std::string generate(const Decomp& d, int32_t style) {
       for (size_t j = 0; j < kd.size(); ++j) {
         if (j + 1 < kd.size()) load(j + 1);
         const std::string arr = n_words(kd[j]) ? "A" + std::to_string(j) : "p";
-        const std::string stmt = emit(kd[j], arr, (int32_t)j);
+        const std::string stmt = emit(kd[j], arr, (int32_t)j, far_rf);
         if (!stmt.empty()) s << "        " << stmt << "\n";
       }
     }
@@ -317,10 +318,9 @@ std::string generate(const Decomp& d, int32_t style) {
        "        if (w < nwn) slot[(b ^ 1) * MAXW + w] = pre[k];\n"
        "      }\n"
        "      b ^= 1;\n";
-  s << (per_wave ? "      __builtin_amdgcn_wave_barrier();\n" : "      __syncthreads();\n");
+  s << "      __syncthreads();\n";
   s << "    }\n";
-  s << (per_wave ? "    if (__all(code != 0)) break;\n"
-                 : "    if (__syncthreads_and(code != 0)) break;\n");
+  s << "    if (__syncthreads_and(code != 0)) break;\n";
   s << "  }\n"
        "  if (!tracked) return;\n"
        "  if (code == 0) {\n"

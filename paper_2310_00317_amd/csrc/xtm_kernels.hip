@@ -621,7 +621,7 @@ __device__ __forceinline__ void multipole_n(xtmm::Pt& q, const double* __restric
 __device__ __forceinline__ void maybe_radiate(xtmm::Pt& q, double kx, double ky, double lr,
                                               const KernelRef& r, long long pid, int turn,
                                               int element) {
-  xtmm::radiate_at(q, kx, ky, lr, r.rad_mode, r.seed, pid, turn, element, r.gamma0, r.c_mean,
+  xtmm::radiate_at<true>(q, kx, ky, lr, r.rad_mode, r.seed, pid, turn, element, r.gamma0, r.c_mean,
                    r.c_quant, r.p0c, r.beta0, r.two_over_beta0);
 }
 
@@ -834,13 +834,59 @@ __device__ __forceinline__ void replay_one(const uint64_t* __restrict__ tab, int
   store_pt(P, p, q);
 }
 
+// Every lane of a wave walks the same (turn, element) sequence from the
+// chunk start, so the walk position is wave-uniform and the element records
+// come through scalar loads; each lane applies the maps only until its own
+// loss point, and the wave runs to the furthest loss point among its lanes.
 __global__ void __launch_bounds__(256) k_replay(const uint64_t* __restrict__ tab, int32_t n_el,
                                                 SoA P, const int32_t* __restrict__ lost,
                                                 const int32_t* __restrict__ ctrl,
                                                 int32_t backward, KernelRef r) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= ctrl[3]) return;
-  replay_one(tab, n_el, P, lost[i], ctrl[1], backward, r);
+  const bool act = i < ctrl[3];
+  if (__all(!act)) return;
+  const int32_t t0 = ctrl[1];
+  const int32_t p = act ? lost[i] : 0;
+  int64_t remaining = 0;
+  xtmm::Pt q;
+  long long pid = 0;
+  if (act) {
+    const int32_t at = P.at_turn[p], ae = P.at_element[p];
+    const int32_t tl = backward ? t0 - 1 - at : at - t0;
+    const int32_t el = backward ? n_el - 1 - ae : ae;
+    remaining = (int64_t)tl * n_el + el;
+    load_pt(P, p, q, r.beta0);
+    pid = P.pid[p];
+  }
+  int64_t m = remaining;
+  for (int s = 32; s > 0; s >>= 1) {
+    const int64_t o = __shfl_xor(m, s, 64);
+    m = o > m ? o : m;
+  }
+  const uint32_t m_lo = __builtin_amdgcn_readfirstlane((uint32_t)(uint64_t)m);
+  const uint32_t m_hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)m >> 32));
+  const int64_t wave_max = (int64_t)(((uint64_t)m_hi << 32) | m_lo);
+  uint32_t off = 0;
+  int32_t t = 0, e = 0;
+  for (int64_t k = 0; k < wave_max; ++k) {
+    off = __builtin_amdgcn_readfirstlane(off);
+    const uint64_t* w = tab + off;
+    const uint64_t h = w[0];
+    if (k < remaining) {
+      bool ok;
+      int ls;
+      apply_elem(q, (uint32_t)(h & 0xffu), (uint32_t)((h >> 8) & 0xffu),
+                 reinterpret_cast<const double*>(w + 1), r, ok, ls, pid,
+                 backward ? t0 - 1 - t : t0 + t, e);
+    }
+    off += 1 + (uint32_t)((h >> 16) & 0xffffu);
+    if (++e == n_el) {
+      e = 0;
+      ++t;
+      off = 0;
+    }
+  }
+  if (act) store_pt(P, p, q);
 }
 
 __global__ void __launch_bounds__(256) k_replay_batched(const uint64_t* const* __restrict__ tabs,

@@ -184,13 +184,20 @@ __device__ __forceinline__ void from_ptau(Pt& q, double beta0, double two_over_b
 
 // Thin RF cavity: ptau += amp sin(phase - k zeta), amp = charge0 V / p0c,
 // k = 2 pi f / (beta0 c).
-// (kept out of line: RF cavities are rare in a lattice, and inlining the
-// sine's constants into every per-line kernel costs registers in its loop)
-__device__ __attribute__((noinline)) void rf(Pt& q, double amp, double k, double phase,
-                                             double beta0, double two_over_beta0) {
+__device__ __forceinline__ void rf(Pt& q, double amp, double k, double phase, double beta0,
+                                   double two_over_beta0) {
   const double s = xsin(phase - k * q.zeta);
   q.ptau = q.ptau + amp * s;
   from_ptau(q, beta0, two_over_beta0);
+}
+
+// Out-of-line forms for per-line kernels of radiating lattices: there the
+// inlined sine, Philox and logarithm constants would hold registers across
+// the whole element loop (RF cavities are rare, and the radiation deviates
+// are a small part of a bend's work).
+__device__ __attribute__((noinline)) void rf_far(Pt& q, double amp, double k, double phase,
+                                                 double beta0, double two_over_beta0) {
+  rf(q, amp, k, phase, beta0, two_over_beta0);
 }
 
 __device__ __forceinline__ void xyshift(Pt& q, double dx, double dy) {
@@ -258,9 +265,8 @@ __device__ __forceinline__ double uniform52(unsigned int wa, unsigned int wb) {
 
 // Standard normal of (seed, particle id, turn, element, draw) by Box-Muller
 // on one Philox block with counter (pid_lo, pid_hi, turn, element * 8 + draw).
-// (out of line for the same reason as rf: Philox, log and cosine constants)
-__device__ __attribute__((noinline)) double gauss_at(unsigned long long seed, long long pid,
-                                                     int turn, int element, int draw) {
+__device__ __forceinline__ double gauss_at(unsigned long long seed, long long pid, int turn,
+                                           int element, int draw) {
   U4 c;
   c.a = (unsigned int)(unsigned long long)pid;
   c.b = (unsigned int)((unsigned long long)pid >> 32);
@@ -269,6 +275,11 @@ __device__ __attribute__((noinline)) double gauss_at(unsigned long long seed, lo
   const U4 w = philox4x32_10(c, (unsigned int)seed, (unsigned int)(seed >> 32));
   const double u1 = uniform52(w.a, w.b), u2 = uniform52(w.c, w.d);
   return sqrt(-2.0 * xlog(u1)) * xcos(6.283185307179586 * u2);
+}
+
+__device__ __attribute__((noinline)) double gauss_at_far(unsigned long long seed, long long pid,
+                                                         int turn, int element, int draw) {
+  return gauss_at(seed, pid, turn, element, draw);
 }
 
 // ------------------------------------------------------------ radiation
@@ -305,13 +316,16 @@ __device__ __forceinline__ void radiate(Pt& q, double kx, double ky, double lr, 
 // Radiation step of a multipole with radiation length lr (none if lr <= 0 or
 // mode 0); the Gaussian deviate is keyed by (seed, particle id, absolute
 // turn, user element index).
+template <bool kFar = false>
 __device__ __forceinline__ void radiate_at(Pt& q, double kx, double ky, double lr, int mode,
                                            unsigned long long seed, long long pid, int turn,
                                            int element, double gamma0, double c_mean,
                                            double c_quant, double p0c, double beta0,
                                            double two_over_beta0) {
   if (mode == 0 || !(lr > 0.0)) return;
-  const double g = (mode == 2) ? gauss_at(seed, pid, turn, element, 0) : 0.0;
+  const double g = (mode == 2) ? (kFar ? gauss_at_far(seed, pid, turn, element, 0)
+                                        : gauss_at(seed, pid, turn, element, 0))
+                               : 0.0;
   Rad rr{gamma0, c_mean, c_quant, p0c};
   radiate(q, kx, ky, lr, rr, mode, g, beta0, two_over_beta0);
 }
