@@ -161,13 +161,14 @@ typedef struct xtm_track_opts {
   int32_t use_graph;       /* 1 = replay the chunk sequence as a captured hipGraph    */
   int32_t time_kernels;    /* 1 = time each tracking launch with HIP events (stats)   */
   int32_t variant;         /* tracking kernel (all give bitwise the same results):
-                              0 = default (5 when the line has a compact periodic
-                              cell structure, else 4); 1 = interpreter, exit on loss;
+                              0 = default (when the line has a compact periodic
+                              cell structure 5, or 6 with radiation; else 4); 1 = interpreter, exit on loss;
                               2 = interpreter, store on loss; 3 = as 2 with the
                               element table staged in LDS; 4 = interpreter, losses
                               kept in registers and replayed after the chunk;
                               5 = per-line kernel generated from the lattice's cell
-                              structure and compiled at first use (as 4 for losses;
+                              structure and compiled at first use (a lost particle's
+                              coordinates are stored as it is lost, no replay;
                               256-lane workgroups sharing the cell parameters
                               staged in LDS, `block` is ignored); 6 = as 5, each
                               element's parameters read into registers while the

@@ -294,13 +294,12 @@ xtm_status read_alive(xtm_particles_s* p, hipStream_t s, int64_t* alive, int64_t
   return XTM_OK;
 }
 
-// Per-line kernel when the caller leaves the choice to the library: plain
-// parameter reads (5) when the set gives every SIMD several waves, the
-// software-pipelined reads (6) for smaller sets.
-int32_t default_line_variant(int64_t n_alive) {
-  constexpr int64_t kManyWaves = 3LL * 1024 * 64;  // three waves on each of the 1024 SIMDs
-  return n_alive >= kManyWaves ? 5 : 5;
-}
+// Per-line kernel when the caller leaves the choice to the library, from
+// measurements on MI355X: parameters read where used (5) for plain tracking
+// (2-3x faster there than the pipelined form); pipelined parameter reads (6)
+// with radiation, whose out-of-line deviate calls break up the schedule
+// (1.6x faster there).
+int32_t default_line_variant(int32_t rad_mode) { return rad_mode ? 6 : 5; }
 
 int32_t auto_chunk(int64_t n, int32_t n_el, int32_t n_turns) {
   // aim at ~2e10 passes per launch so launch and epilogue costs vanish, while
@@ -382,7 +381,9 @@ hipError_t enqueue_chunks(xtm_lattice_s* L, xtm_particles_s* P, const ChunkPlan&
     if (e != hipSuccess) return e;
     if (ev && (e = hipEventRecord(ev->back(), s)) != hipSuccess) return e;
     ++*launches;
-    const bool replay = (c.variant >= 4);
+    // the interpreter keeps losses in registers and replays them; the
+    // per-line kernels store a lost particle's coordinates as it is lost
+    const bool replay = (c.variant == 4);
     e = launch_epilogue(in, out, replay ? P->lost : nullptr, P->alive_upper, soa, P->ctrl,
                         P->blockcnt, P->passes, L->n_el, k, c.backward ? 1 : 0, s);
     if (e != hipSuccess) return e;
@@ -487,7 +488,7 @@ xtm_status run_turns(xtm_lattice_s* L, xtm_particles_s* P, int32_t n_turns,
   if (!B && (c.variant == 0 || c.variant >= 5)) {
     // the per-line kernel, compiled on first use; the default falls back to
     // the register-loss interpreter if the line has no compact cell structure
-    const int32_t want = c.variant ? c.variant : default_line_variant(P->alive_upper);
+    const int32_t want = c.variant ? c.variant : default_line_variant(c.rad_mode);
     LineKernel& lk = (backward ? L->bwd_line : L->fwd_line)[want - 5];
     if (!lk.tried && L->n_el > 0) {
       lk.tried = true;

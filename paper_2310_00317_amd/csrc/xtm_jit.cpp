@@ -135,7 +135,8 @@ std::string emit(uint32_t s, const std::string& arr, int32_t j, bool far_rf) {
   std::ostringstream c;
   switch (kt) {
     case K_DRIFT:
-      c << "xtmm::mark(xtmm::drift_exact(q, " << P(0) << "), code, st, e0 + " << j << ", -1);";
+      c << "{ if (!xtmm::drift_ok(q) && code == 0) SAVE(); xtmm::mark(xtmm::drift_exact(q, "
+        << P(0) << "), code, st, e0 + " << j << ", -1); }";
       break;
     case K_DRIFT_EXP:
       c << "xtmm::drift_expanded(q, " << P(0) << ");";
@@ -167,16 +168,16 @@ std::string emit(uint32_t s, const std::string& arr, int32_t j, bool far_rf) {
       c << "xtmm::srotation(q, " << P(0) << ", " << P(1) << ");";
       break;
     case K_AP_CIRC:
-      c << "xtmm::mark(xtmm::in_circle(q, " << P(0) << "), code, st, e0 + " << j << ", 0);";
-      break;
     case K_AP_ELL:
-      c << "xtmm::mark(xtmm::in_ellipse(q, " << P(0) << ", " << P(1) << "), code, st, e0 + " << j
-        << ", 0);";
+    case K_AP_RECT: {
+      std::string test;
+      if (kt == K_AP_CIRC) test = "xtmm::in_circle(q, " + P(0) + ")";
+      else if (kt == K_AP_ELL) test = "xtmm::in_ellipse(q, " + P(0) + ", " + P(1) + ")";
+      else test = "xtmm::in_rect(q, " + P(0) + ", " + P(1) + ", " + P(2) + ", " + P(3) + ")";
+      c << "{ const bool ok = " << test << "; if (!ok && code == 0) SAVE(); xtmm::mark(ok, code, "
+        << "st, e0 + " << j << ", 0); }";
       break;
-    case K_AP_RECT:
-      c << "xtmm::mark(xtmm::in_rect(q, " << P(0) << ", " << P(1) << ", " << P(2) << ", " << P(3)
-        << "), code, st, e0 + " << j << ", 0);";
-      break;
+    }
     default:
       break;  // marker
   }
@@ -219,6 +220,11 @@ std::string generate(const Decomp& d, int32_t style) {
        "              float* rec; int rec_turns; int rec_n; };\n"
        "#define RAD(kx, ky, lr, j) xtmm::radiate_at<true>(q, kx, ky, lr, r.rad_mode, r.seed, pid, \\\n"
        "    t0 + t, ec + (j), r.gamma0, r.c_mean, r.c_quant, r.p0c, beta0, two_over_beta0)\n"
+       "// a lane that fails a loss test stores the coordinates it entered the\n"
+       "// element with (a rare, divergent store); the loss record follows at the end\n"
+       "#define SAVE() do { P.x[pi] = q.x; P.px[pi] = q.px; P.y[pi] = q.y; P.py[pi] = q.py; \\\n"
+       "    P.zeta[pi] = q.zeta; P.delta[pi] = q.delta; P.ptau[pi] = q.ptau; P.rpp[pi] = q.rpp; \\\n"
+       "    P.rvv[pi] = q.rvv; } while (0)\n"
        "#define MAXW " << maxw << "\n"
        "#define PER_THREAD " << per_thread << "\n"
        "#define LANES " << lanes << "\n"
@@ -300,7 +306,8 @@ std::string generate(const Decomp& d, int32_t style) {
         if (n == 0) return;
         s << "        double A" << j << "[" << n << "];";
         for (int32_t m = 0; m < n; ++m) s << " A" << j << "[" << m << "] = p[" << off[j] + m << "];";
-        s << "\n        __builtin_amdgcn_sched_barrier(0);\n";
+        // (mask 1: arithmetic may still move across, memory operations may not)
+        s << "\n        __builtin_amdgcn_sched_barrier(1);\n";
       };
       load(0);
       for (size_t j = 0; j < kd.size(); ++j) {

@@ -44,6 +44,14 @@ __device__ __forceinline__ bool drift_exact(Pt& q, double L) {
   return ok;
 }
 
+// The exact drift's loss test alone (the same operations drift_exact starts
+// with, so a compiler evaluates them once when both are used).
+__device__ __forceinline__ bool drift_ok(const Pt& q) {
+  const double px2 = q.px * q.px;
+  const double py2 = q.py * q.py;
+  return q.opd2 - px2 - py2 > 0.0;
+}
+
 // Drift of H = pzeta - (1+d) + (px^2+py^2)/(2(1+d)) over L.
 __device__ __forceinline__ void drift_expanded(Pt& q, double L) {
   const double lr = L * q.rpp;
