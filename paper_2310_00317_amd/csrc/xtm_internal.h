@@ -113,9 +113,8 @@ struct LineKernel {
   std::string source;
   std::string error;
 };
-// style: 0 element parameters read from the LDS slot where used; 1 the next
-// element's parameters software-pipelined into registers
-constexpr int32_t kLineStyles = 2;
+// one generated-kernel form (style 0); kept as a parameter for further forms
+constexpr int32_t kLineStyles = 1;
 inline int32_t line_block(int32_t) { return kLineBlock; }
 bool build_line_kernel(const std::vector<uint64_t>& tab, int32_t n_el, int32_t style,
                        LineKernel* k);

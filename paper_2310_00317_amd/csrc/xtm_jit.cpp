@@ -200,11 +200,8 @@ std::string generate(const Decomp& d, int32_t style) {
   int32_t maxw = 1;
   for (const auto& k : d.kinds) maxw = std::max(maxw, kind_words(k));
   // 256-lane workgroups share one LDS slot pair, filled by all lanes and
-  // fenced by workgroup barriers.  Style 1 also software-pipelines the
-  // parameter reads (element j+1's parameters move to registers while
-  // element j runs), which costs registers and pays when the set is too small
-  // to give every SIMD several waves to hide the LDS latency with.
-  const bool pipelined = style == 1;
+  // fenced by workgroup barriers
+  (void)style;
   const int32_t lanes = 256;
   // a line with radiating multipoles calls its RF sine out of line
   bool far_rf = false;
@@ -288,34 +285,11 @@ std::string generate(const Decomp& d, int32_t style) {
   for (size_t k = 0; k < d.kinds.size(); ++k) {
     s << "      " << (k ? "else if" : "if") << " (kind == " << k << ") {\n";
     const auto& kd = d.kinds[k];
-    if (!pipelined) {
-      int32_t o = 0;
-      for (size_t j = 0; j < kd.size(); ++j) {
-        const std::string stmt = emit(kd[j], "p + " + std::to_string(o), (int32_t)j, far_rf);
-        if (!stmt.empty()) s << "        " << stmt << "\n";
-        o += n_words(kd[j]);
-      }
-    } else {
-      // software pipeline: element j+1's parameters are read from LDS into
-      // registers before element j runs; the scheduling barriers keep the
-      // compiler from sinking the reads back down to their uses
-      std::vector<int32_t> off(kd.size() + 1, 0);
-      for (size_t j = 0; j < kd.size(); ++j) off[j + 1] = off[j] + n_words(kd[j]);
-      auto load = [&](size_t j) {
-        const int32_t n = n_words(kd[j]);
-        if (n == 0) return;
-        s << "        double A" << j << "[" << n << "];";
-        for (int32_t m = 0; m < n; ++m) s << " A" << j << "[" << m << "] = p[" << off[j] + m << "];";
-        // (mask 1: arithmetic may still move across, memory operations may not)
-        s << "\n        __builtin_amdgcn_sched_barrier(1);\n";
-      };
-      load(0);
-      for (size_t j = 0; j < kd.size(); ++j) {
-        if (j + 1 < kd.size()) load(j + 1);
-        const std::string arr = n_words(kd[j]) ? "A" + std::to_string(j) : "p";
-        const std::string stmt = emit(kd[j], arr, (int32_t)j, far_rf);
-        if (!stmt.empty()) s << "        " << stmt << "\n";
-      }
+    int32_t o = 0;
+    for (size_t j = 0; j < kd.size(); ++j) {
+      const std::string stmt = emit(kd[j], "p + " + std::to_string(o), (int32_t)j, far_rf);
+      if (!stmt.empty()) s << "        " << stmt << "\n";
+      o += n_words(kd[j]);
     }
     s << "      }\n";
   }
