@@ -199,10 +199,10 @@ int32_t kind_words(const std::vector<uint32_t>& k) {
 std::string generate(const Decomp& d, int32_t style) {
   int32_t maxw = 1;
   for (const auto& k : d.kinds) maxw = std::max(maxw, kind_words(k));
-  // 256-lane workgroups share one LDS slot pair, filled by all lanes and
-  // fenced by workgroup barriers
-  (void)style;
-  const int32_t lanes = 256;
+  // the lanes of a workgroup share one LDS slot pair, filled by all of them
+  // and fenced by workgroup barriers; style 0 uses 256-lane workgroups, style
+  // 1 one-wave workgroups (which spread a small set over all compute units)
+  const int32_t lanes = line_block(style);
   // a line with radiating multipoles calls its RF sine out of line
   bool far_rf = false;
   for (const auto& k : d.kinds)

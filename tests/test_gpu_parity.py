@@ -149,7 +149,9 @@ def test_resume_bitwise(P):
                                   dict(turns_per_chunk=100, block=128, compact=False),
                                   dict(turns_per_chunk=33, block=192),
                                   dict(variant=5, turns_per_chunk=11),
-                                  dict(variant=5, turns_per_chunk=5, compact=False)])
+                                  dict(variant=5, turns_per_chunk=5, compact=False),
+                                  dict(variant=6), dict(variant=6, turns_per_chunk=9),
+                                  dict(variant=6, turns_per_chunk=4, compact=False)])
 def test_launch_shape_invariance(P, opts):
     banner(f"launch shape {opts}")
     el = I.cfg1_lattice()
