@@ -25,8 +25,7 @@ sys.path.insert(0, ROOT)
 
 FP64_VECTOR_PEAK_TFLOPS = 78.6   # 256 CU x 128 FP64 FLOP/clk x 2.4 GHz
 KERNEL_NAMES = {1: "k_track", 2: "k_track2", 3: "k_track3", 4: "k_track4",
-                5: "xtm_line (per-line generated kernel)",
-                6: "xtm_line (per-line generated kernel, one-wave workgroups)"}
+                5: "xtm_line (per-line generated kernel)"}
 
 # algorithmic FLOPs per element application (sqrt, div, sin, compare count 1;
 # fma counts 2), as the kernel's maps are written

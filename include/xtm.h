@@ -161,9 +161,8 @@ typedef struct xtm_track_opts {
   int32_t use_graph;       /* 1 = replay the chunk sequence as a captured hipGraph    */
   int32_t time_kernels;    /* 1 = time each tracking launch with HIP events (stats)   */
   int32_t variant;         /* tracking kernel (all give bitwise the same results):
-                              0 = default (when the line has a compact periodic
-                              cell structure 5, or 6 for sets under 65,536
-                              particles; else 4); 1 = interpreter, exit on loss;
+                              0 = default (5 when the line has a compact periodic
+                              cell structure, else 4); 1 = interpreter, exit on loss;
                               2 = interpreter, store on loss; 3 = as 2 with the
                               element table staged in LDS; 4 = interpreter, losses
                               kept in registers and replayed after the chunk;
@@ -171,8 +170,7 @@ typedef struct xtm_track_opts {
                               structure and compiled at first use (a lost particle's
                               coordinates are stored as it is lost, no replay;
                               256-lane workgroups sharing the cell parameters
-                              staged in LDS, `block` is ignored); 6 = as 5 in
-                              one-wave workgroups;
+                              staged in LDS, `block` is ignored);
                               XTM_E_UNSUPPORTED if it cannot be built */
   int32_t radiation;       /* synchrotron radiation in multipoles with length > 0:
                               0 off, 1 mean energy loss, 2 mean + quantum excitation
@@ -265,7 +263,7 @@ xtm_status xtm_track_batched(xtm_batch b, xtm_particles p, const int64_t* first_
    (`first_slot` as for xtm_track_batched with a batch, else ignored).
    Synchronises; allocates a scratch set of the same size. */
 typedef struct xtm_plan {
-  int32_t variant;      /* kernel variant chosen (4..6) */
+  int32_t variant;      /* kernel variant chosen (4 or 5) */
   int32_t block;        /* lanes per workgroup chosen */
   double passes_per_s;  /* its measured rate, chunk epilogues included */
 } xtm_plan;

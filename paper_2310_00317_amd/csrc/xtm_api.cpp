@@ -294,11 +294,8 @@ xtm_status read_alive(xtm_particles_s* p, hipStream_t s, int64_t* alive, int64_t
   return XTM_OK;
 }
 
-// Per-line kernel when the caller leaves the choice to the library:
-// 256-lane workgroups (5) once the set fills every compute unit with one,
-// one-wave workgroups (6) below that, so a small set still reaches all 256
-// compute units.
-int32_t default_line_variant(int64_t n_alive) { return n_alive >= 256LL * 256 ? 5 : 6; }
+// Per-line kernel when the caller leaves the choice to the library.
+int32_t default_line_variant(int64_t) { return 5; }
 
 int32_t auto_chunk(int64_t n, int32_t n_el, int32_t n_turns) {
   // aim at ~2e10 passes per launch so launch and epilogue costs vanish, while
@@ -474,7 +471,7 @@ xtm_status run_turns(xtm_lattice_s* L, xtm_particles_s* P, int32_t n_turns,
     return fail(XTM_E_ARG, "block must be 64, 128, 192 or 256");
   c.compact = !(o && o->no_compact) || backward;
   c.variant = (o && o->variant) ? o->variant : (use_plan && !B ? L->plan_variant : 0);
-  if (c.variant < 0 || c.variant > 6) return fail(XTM_E_ARG, "kernel variant must be 0..6");
+  if (c.variant < 0 || c.variant > 5) return fail(XTM_E_ARG, "kernel variant must be 0..5");
   if (B) {
     if (backward) return fail(XTM_E_UNSUPPORTED, "batched tracking is forward only");
     if (c.variant != 0 && c.variant != 4)

@@ -113,10 +113,10 @@ struct LineKernel {
   std::string source;
   std::string error;
 };
-// generated-kernel forms: style 0 in 256-lane workgroups, style 1 in
-// one-wave workgroups (same code and barriers, smaller groups)
-constexpr int32_t kLineStyles = 2;
-inline int32_t line_block(int32_t style) { return style == 1 ? 64 : kLineBlock; }
+// one generated-kernel form (style 0, 256-lane workgroups); the style index
+// is kept for further forms
+constexpr int32_t kLineStyles = 1;
+inline int32_t line_block(int32_t) { return kLineBlock; }
 bool build_line_kernel(const std::vector<uint64_t>& tab, int32_t n_el, int32_t style,
                        LineKernel* k);
 void free_line_kernel(LineKernel* k);
