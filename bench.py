@@ -27,6 +27,30 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6   # 256 CU x 128 FP64 FLOP/clk x 2.4 GHz
 KERNEL_NAMES = {1: "k_track", 2: "k_track2", 3: "k_track3", 4: "k_track4",
                 5: "xtm_line (per-line generated kernel)"}
 
+# HBM bytes per tracking-kernel launch over the timed region, from one
+# FETCH_SIZE and one WRITE_SIZE counter pass of this benchmark, each scaled by
+# what the same counter reads for a plain 1 GiB device copy (x2.000, x1.000).
+# A figure holds only for the workload, step shape and kernel it was taken on:
+# the key carries a hash of the sources the per-line kernel is generated from,
+# and any change to them makes the bench report no traffic until the counters
+# are taken again.
+TRAFFIC_SOURCES = ("xtm_jit.cpp", "xtm_maps.h")
+MEASURED_TRAFFIC = {
+    # (workload, particles, turns per step, steps, kernel variant, source hash)
+    ("cfg2", 100000, 1000, 10, 5, "a2d3a2c942316f09"):
+        (20682943.0, "profiles/xtm_line_cfg2_hbm_counters.txt"),
+}
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, "paper_2310_00317_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
 # algorithmic FLOPs per element application (sqrt, div, sin, compare count 1;
 # fma counts 2), as the kernel's maps are written
 def element_flops(el) -> np.ndarray:
@@ -292,6 +316,9 @@ def main():
     flops_per_pass = float(flops.sum() / len(el_all))
     achieved_tflops = total_passes * flops_per_pass / (kernel_ms / 1e3) / 1e12 if kernel_ms > 0 else 0.0
 
+    key = (args.workload, n, tps, steps, variant_ran, kernel_source_hash())
+    traffic, traffic_src = MEASURED_TRAFFIC.get(key, (None, None))
+
     out = {
         "metric": "particle-element passes/s (FP64); DA wall-clock learned vs plain at 0.1 sigma",
         "value": value,
@@ -311,8 +338,9 @@ def main():
         "roofline": {"bound": "alu", "kernel": KERNEL_NAMES.get(variant_ran, "?"),
                      "achieved": achieved_tflops, "peak": FP64_VECTOR_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved_tflops / FP64_VECTOR_PEAK_TFLOPS,
-                     "traffic": None, "flops_per_pass": flops_per_pass,
-                     "avg_launch_ms": kernel_ms / max(launches, 1), "launches": launches},
+                     "traffic": traffic, "flops_per_pass": flops_per_pass,
+                     "avg_launch_ms": kernel_ms / max(launches, 1), "launches": launches,
+                     "traffic_unit": "bytes per launch", "traffic_profile": traffic_src},
     }
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a sample", file=sys.stderr, flush=True)
