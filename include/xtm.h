@@ -117,6 +117,9 @@ typedef struct xtm_arrays {
 
 const char* xtm_last_error(void);
 const char* xtm_version(void);
+/* Highest kernel number accepted in xtm_track_opts.variant (variants 5 to
+   this value are the forms of the per-line kernel). */
+int32_t xtm_max_variant(void);
 
 /* Build a lattice from n element descriptions (host memory, copied; the
    caller may free `el` on return).  Validates every element (unknown type,
@@ -166,16 +169,22 @@ typedef struct xtm_track_opts {
                               2 = interpreter, store on loss; 3 = as 2 with the
                               element table staged in LDS; 4 = interpreter, losses
                               kept in registers and replayed after the chunk;
-                              5 = per-line kernel generated from the lattice's cell
-                              structure and compiled at first use (a lost particle's
-                              coordinates are stored as it is lost, no replay;
-                              256-lane workgroups sharing the cell parameters
-                              staged in LDS, `block` is ignored);
+                              5..xtm_max_variant() = per-line kernel generated from
+                              the lattice's cell structure and compiled at first
+                              use (a lost particle's coordinates are stored as it
+                              is lost, no replay; the workgroup shares each cell's
+                              parameters staged in LDS; `block` is ignored).
+                              Variant 5 + s, s = 0..5: s & 1 selects one-wave
+                              workgroups instead of 256 lanes; s >> 1 how element
+                              code reads its parameters from LDS: 0 at each use,
+                              1 all of an element's words in one group before its
+                              arithmetic, 2 the next element's group issued
+                              before the current element's arithmetic.
                               XTM_E_UNSUPPORTED if it cannot be built */
   int32_t radiation;       /* synchrotron radiation in multipoles with length > 0:
                               0 off, 1 mean energy loss, 2 mean + quantum excitation
                               (Gaussian, see below); forward tracking with the
-                              default, 4 or 5 kernels only */
+                              default, 4 or per-line kernels only */
   int32_t record_turns;    /* with record_buf: record the start of turns 0 .. record_turns-1 */
   uint64_t rng_seed;       /* key of the quantum-excitation deviates */
   float* record_buf;       /* early-turn recorder or NULL: device FP32
@@ -184,14 +193,15 @@ typedef struct xtm_track_opts {
                               t < record_turns, (x, px, y, py) of every particle alive
                               at element 0 are written; lost particles leave their
                               entries untouched (caller-owned, caller-cleared).
-                              Forward tracking with the default, 4 or 5 kernels only */
+                              Forward tracking with the default, 4 or per-line
+                              kernels only */
 } xtm_track_opts;
 
 typedef struct xtm_track_stats {
   int64_t passes;     /* (particle, element) applications made while alive, loss included */
   int64_t alive;      /* particles alive after the call */
   int32_t launches;   /* tracking-kernel launches made by the call */
-  int32_t variant;    /* tracking kernel that ran (1..5, see xtm_track_opts) */
+  int32_t variant;    /* tracking kernel that ran (see xtm_track_opts) */
   double kernel_ms;   /* summed duration of those launches (time_kernels = 1), else 0 */
 } xtm_track_stats;
 
@@ -253,9 +263,9 @@ xtm_status xtm_track_batched(xtm_batch b, xtm_particles p, const int64_t* first_
                              int32_t n_turns, const xtm_track_opts* opts, void* stream,
                              xtm_track_stats* stats);
 
-/* Launch-plan autotuner.  Times every candidate (kernel variants 5, 6 and 7
-   when the line has a per-line kernel, each with its 256-lane workgroups;
-   variant 4 with blocks of 64, 128 and 256 lanes) for probe_turns turns on
+/* Launch-plan autotuner.  Times every candidate (each form of the per-line
+   kernel, variants 5..xtm_max_variant(), when the line has one, each with its
+   own workgroup size; variant 4 with blocks of 64, 128 and 256 lanes) for probe_turns turns on
    a scratch copy of the set (the set itself is not advanced), keeps the
    fastest as the plan of the lattice (or batch), and reports it.  Later
    xtm_track / xtm_track_batched calls whose options leave both `variant`
@@ -263,7 +273,7 @@ xtm_status xtm_track_batched(xtm_batch b, xtm_particles p, const int64_t* first_
    (`first_slot` as for xtm_track_batched with a batch, else ignored).
    Synchronises; allocates a scratch set of the same size. */
 typedef struct xtm_plan {
-  int32_t variant;      /* kernel variant chosen (4 or 5) */
+  int32_t variant;      /* kernel variant chosen (4 or a per-line form) */
   int32_t block;        /* lanes per workgroup chosen */
   double passes_per_s;  /* its measured rate, chunk epilogues included */
 } xtm_plan;

@@ -77,6 +77,7 @@ def lib() -> ctypes.CDLL:
         sig = {
             "xtm_last_error": ([], ctypes.c_char_p),
             "xtm_version": ([], ctypes.c_char_p),
+            "xtm_max_variant": ([], ctypes.c_int32),
             "xtm_lattice_create": ([vp, i32, vp, vp], i32),
             "xtm_lattice_destroy": ([vp], i32),
             "xtm_lattice_info": ([vp, vp, vp], i32),
@@ -257,6 +258,11 @@ class Particles:
             self.close()
         except Exception:
             pass
+
+
+def line_variants() -> list:
+    """Kernel numbers of the per-line kernel's forms (5 .. xtm_max_variant())."""
+    return list(range(5, int(lib().xtm_max_variant()) + 1))
 
 
 def track(lattice: Lattice, particles: Particles, n_turns: int, turns_per_chunk: int = 0,

@@ -368,7 +368,7 @@ hipError_t enqueue_chunks(xtm_lattice_s* L, xtm_particles_s* P, const ChunkPlan&
       e = launch_track_batched(c.batch->tabs_d, c.batch->first_d, (int32_t)c.batch->lats.size(),
                                L->n_el, soa, in, P->ctrl, P->alive_upper, c.block, k,
                                c.backward ? 1 : 0, kr, s);
-    else if (c.variant == 5)
+    else if (c.line)
       e = launch_line(*c.line, L->n_el, soa, in, P->ctrl, P->alive_upper, c.block, k,
                       c.backward ? 1 : 0, kr, s);
     else
@@ -471,7 +471,8 @@ xtm_status run_turns(xtm_lattice_s* L, xtm_particles_s* P, int32_t n_turns,
     return fail(XTM_E_ARG, "block must be 64, 128, 192 or 256");
   c.compact = !(o && o->no_compact) || backward;
   c.variant = (o && o->variant) ? o->variant : (use_plan && !B ? L->plan_variant : 0);
-  if (c.variant < 0 || c.variant > 5) return fail(XTM_E_ARG, "kernel variant must be 0..5");
+  if (c.variant < 0 || c.variant > 4 + kLineStyles)
+    return fail(XTM_E_ARG, "kernel variant must be 0.." + std::to_string(4 + kLineStyles));
   if (B) {
     if (backward) return fail(XTM_E_UNSUPPORTED, "batched tracking is forward only");
     if (c.variant != 0 && c.variant != 4)
@@ -572,6 +573,7 @@ xtm_status guarded(F&& f) {
 extern "C" {
 
 const char* xtm_last_error(void) { return g_err.c_str(); }
+int32_t xtm_max_variant(void) { return 4 + xtm::kLineStyles; }
 
 const char* xtm_version(void) { return "xtm 0.1 (gfx950, FP64 thin-lattice tracker)"; }
 

@@ -113,10 +113,12 @@ struct LineKernel {
   std::string source;
   std::string error;
 };
-// one generated-kernel form (style 0, 256-lane workgroups); the style index
-// is kept for further forms
-constexpr int32_t kLineStyles = 1;
-inline int32_t line_block(int32_t) { return kLineBlock; }
+// Generated-kernel forms ("styles"), all computing the same maps in the same
+// order: bit 0 selects the workgroup (0: 256 lanes, 1: one wave), the rest the
+// way element code reads its parameters from the LDS slot (line_fetch).
+constexpr int32_t kLineStyles = 6;
+inline int32_t line_block(int32_t style) { return (style & 1) ? 64 : kLineBlock; }
+inline int32_t line_fetch(int32_t style) { return style >> 1; }
 bool build_line_kernel(const std::vector<uint64_t>& tab, int32_t n_el, int32_t style,
                        LineKernel* k);
 void free_line_kernel(LineKernel* k);

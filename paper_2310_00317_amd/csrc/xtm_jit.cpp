@@ -200,9 +200,14 @@ std::string generate(const Decomp& d, int32_t style) {
   int32_t maxw = 1;
   for (const auto& k : d.kinds) maxw = std::max(maxw, kind_words(k));
   // the lanes of a workgroup share one LDS slot pair, filled by all of them
-  // and fenced by workgroup barriers; style 0 uses 256-lane workgroups, style
-  // 1 one-wave workgroups (which spread a small set over all compute units)
+  // and fenced by workgroup barriers (line_block: 256 lanes, or one wave)
   const int32_t lanes = line_block(style);
+  // how element code reads its parameters from the slot (line_fetch):
+  // 0 = at each use (the compiler interleaves the reads with the arithmetic),
+  // 1 = all of an element's words in one group before its arithmetic,
+  // 2 = the next element's group issued before the current element's
+  //     arithmetic, so the read latency overlaps one element of work
+  const int32_t fetch = line_fetch(style);
   // a line with radiating multipoles calls its RF sine out of line
   bool far_rf = false;
   for (const auto& k : d.kinds)
@@ -285,11 +290,30 @@ std::string generate(const Decomp& d, int32_t style) {
   for (size_t k = 0; k < d.kinds.size(); ++k) {
     s << "      " << (k ? "else if" : "if") << " (kind == " << k << ") {\n";
     const auto& kd = d.kinds[k];
-    int32_t o = 0;
+    std::vector<int32_t> off(kd.size() + 1, 0);
+    for (size_t j = 0; j < kd.size(); ++j) off[j + 1] = off[j] + n_words(kd[j]);
+    // registers of element j's parameters, loaded from the slot in one group
+    auto load = [&](size_t j) {
+      const int32_t nw = n_words(kd[j]);
+      if (nw == 0) return;
+      s << "        double w" << j << "[" << nw << "];\n"
+        << "#pragma unroll\n"
+        << "        for (int m = 0; m < " << nw << "; ++m) w" << j << "[m] = p[" << off[j]
+        << " + m];\n";
+    };
+    if (fetch == 2 && !kd.empty()) load(0);
     for (size_t j = 0; j < kd.size(); ++j) {
-      const std::string stmt = emit(kd[j], "p + " + std::to_string(o), (int32_t)j, far_rf);
+      std::string arr = "p + " + std::to_string(off[j]);
+      if (fetch == 1) {
+        load(j);
+        s << "        __builtin_amdgcn_sched_barrier(0);\n";
+      } else if (fetch == 2) {
+        if (j + 1 < kd.size()) load(j + 1);
+        s << "        __builtin_amdgcn_sched_barrier(0);\n";
+      }
+      if (fetch != 0 && n_words(kd[j]) > 0) arr = "w" + std::to_string(j);
+      const std::string stmt = emit(kd[j], arr, (int32_t)j, far_rf);
       if (!stmt.empty()) s << "        " << stmt << "\n";
-      o += n_words(kd[j]);
     }
     s << "      }\n";
   }
@@ -438,7 +462,7 @@ hipError_t launch_line(const LineKernel& k, int32_t n_el, SoA P, const int32_t* 
   void* args[] = {(void*)&prm, (void*)&cells, (void*)&n_cells, (void*)&n_el, (void*)&P,
                   (void*)&idx, (void*)&ctrl, (void*)&n_turns, (void*)&backward, (void*)&r};
   // the generated kernel stages each cell's parameters with the stride of
-  // its fixed workgroup size (256 lanes for style 0, one wave otherwise)
+  // its style's fixed workgroup size (line_block)
   (void)block;
   const int32_t wg = line_block(k.style);
   const unsigned grid = (unsigned)((grid_upper + wg - 1) / wg);

@@ -1096,6 +1096,8 @@ hipError_t launch_track(const uint64_t* tab, const int32_t* seg, int32_t n_seg, 
   else if (variant == 1)
     hipLaunchKernelGGL(k_track, dim3(blocks_for(grid_upper, block)), dim3(block), 0, s, tab, n_el,
                        P, idx, ctrl, n_turns, backward, r);
+  else if (variant != 2)
+    return hipErrorInvalidValue;  // not an interpreter variant
   else
     hipLaunchKernelGGL(k_track2, dim3(blocks_for(grid_upper, block)), dim3(block), 0, s, tab, n_el,
                        P, idx, ctrl, n_turns, backward, r);

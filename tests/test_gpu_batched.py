@@ -101,7 +101,8 @@ def test_autotune_leaves_set_and_results_unchanged(P):
     P.track(lat, a, 5)
     before = a.to_numpy()
     plan = P.autotune(a, lattice=lat, probe_turns=3)
-    assert plan.variant in (4, 5) and plan.block in (64, 128, 256) and plan.passes_per_s > 0
+    assert plan.variant in [4] + P.line_variants() and plan.block in (64, 128, 256)
+    assert plan.passes_per_s > 0
     after = a.to_numpy()
     for f in FIELDS:
         assert np.array_equal(before[f], after[f]), f

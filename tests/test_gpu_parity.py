@@ -149,7 +149,11 @@ def test_resume_bitwise(P):
                                   dict(turns_per_chunk=100, block=128, compact=False),
                                   dict(turns_per_chunk=33, block=192),
                                   dict(variant=5, turns_per_chunk=11),
-                                  dict(variant=5, turns_per_chunk=5, compact=False)])
+                                  dict(variant=5, turns_per_chunk=5, compact=False),
+                                  dict(variant=6, turns_per_chunk=11),
+                                  dict(variant=7, turns_per_chunk=9),
+                                  dict(variant=8), dict(variant=9, turns_per_chunk=4),
+                                  dict(variant=10, turns_per_chunk=6, compact=False)])
 def test_launch_shape_invariance(P, opts):
     banner(f"launch shape {opts}")
     el = I.cfg1_lattice()
@@ -240,7 +244,7 @@ def test_cfg2_lattice_reduced(P, oracle_mod):
     assert gp == op
 
 
-@pytest.mark.parametrize("variant", [1, 2, 3, 4])
+@pytest.mark.parametrize("variant", [1, 2, 3, 4, 5, 6, 7, 8, 9, 10])
 def test_kernel_variants_on_multisegment_lattice(P, variant):
     """The 20,000-element lattice spans many LDS segments: every kernel variant
     must give bitwise the same result as the default one."""
@@ -285,6 +289,16 @@ def test_empty_lattice_counts_turns(P, oracle_mod):
     assert np.array_equal(g["at_turn"], o.at_turn) and np.all(o.at_turn == 10)
 
 
+def test_variant_numbers(P):
+    """Every per-line form is a kernel number; one past the last is refused."""
+    assert P.line_variants() == list(range(5, 11))
+    lat = P.Lattice(I.cfg1_lattice(), REF)
+    parts = P.Particles(8, REF).init(np.zeros((8, 6)))
+    with pytest.raises(P.XtmError) as ei:
+        P.track(lat, parts, 1, variant=11)
+    assert ei.value.code == -1
+
+
 def test_line_kernel_unavailable_for_irregular_lattice(P):
     """An irregular 200-element line has no compact cell structure: asking for
     the per-line kernel explicitly is an error, the default falls back."""
@@ -322,7 +336,7 @@ def large_cell_lattice(seed=3, units=30):
     return I.line(els)
 
 
-@pytest.mark.parametrize("variant", [0, 4])
+@pytest.mark.parametrize("variant", [0, 4, 6, 7, 8, 9, 10])
 def test_line_kernel_with_multi_pass_staging(P, oracle_mod, variant):
     banner(f"large-cell lattice, variant {variant}")
     el = large_cell_lattice()

@@ -71,10 +71,11 @@ def test_radiation_parity_small_ring(P, oracle_mod, mode):
     assert_bitwise(g, o)
 
 
-def test_radiation_full_electron_ring_short(P, oracle_mod):
+@pytest.mark.parametrize("variant", [0, 7, 9, 10])
+def test_radiation_full_electron_ring_short(P, oracle_mod, variant):
     el = I.cfg5_lattice()
     c = I.cfg5_particles(256, seed=3)
-    g, gp, _, _, _ = gpu_run(P, el, EREF, c, 3, radiation=2, seed=7)
+    g, gp, _, _, _ = gpu_run(P, el, EREF, c, 3, radiation=2, seed=7, variant=variant)
     o = oracle_mod.init(c, EREF)
     op = oracle_mod.track(el, EREF, o, 3, radiation=2, seed=7)
     assert gp == op
@@ -86,7 +87,9 @@ def test_radiation_graph_and_chunks_invariant(P):
     el = _ring()
     c = I.gaussian_particles(512, 5, [3e-4, 3e-6, 3e-5, 3e-7, 3e-3, 1.5e-3])
     a, pa, _, _, _ = gpu_run(P, el, EREF, c, 40, radiation=2, seed=1)
-    for kw in (dict(turns_per_chunk=7, variant=4), dict(variant=5, turns_per_chunk=9)):
+    for kw in (dict(turns_per_chunk=7, variant=4), dict(variant=5, turns_per_chunk=9),
+               dict(variant=6, turns_per_chunk=5), dict(variant=7), dict(variant=8),
+               dict(variant=9, turns_per_chunk=3), dict(variant=10, turns_per_chunk=11)):
         b, pb, _, _, _ = gpu_run(P, el, EREF, c, 40, radiation=2, seed=1, **kw)
         assert pa == pb, kw
         for f in a:
