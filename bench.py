@@ -25,10 +25,11 @@ sys.path.insert(0, ROOT)
 
 FP64_VECTOR_PEAK_TFLOPS = 78.6   # 256 CU x 128 FP64 FLOP/clk x 2.4 GHz
 KERNEL_NAMES = {1: "k_track", 2: "k_track2", 3: "k_track3", 4: "k_track4"}
-for _s in range(6):
+for _s in range(8):
     KERNEL_NAMES[5 + _s] = "xtm_line (per-line generated kernel, %s workgroups, parameters %s)" % (
         "one-wave" if _s & 1 else "256-lane",
-        ("read at use", "grouped per element", "fetched one element ahead")[_s >> 1])
+        ("read at use", "grouped per element", "fetched one element ahead",
+         "fetched one element ahead, one loss test per cell")[_s >> 1])
 
 # HBM bytes per tracking-kernel launch over the timed region, from one
 # FETCH_SIZE and one WRITE_SIZE counter pass of this benchmark, each scaled by

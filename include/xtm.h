@@ -174,12 +174,16 @@ typedef struct xtm_track_opts {
                               use (a lost particle's coordinates are stored as it
                               is lost, no replay; the workgroup shares each cell's
                               parameters staged in LDS; `block` is ignored).
-                              Variant 5 + s, s = 0..5: s & 1 selects one-wave
+                              Variant 5 + s, s = 0..7: s & 1 selects one-wave
                               workgroups instead of 256 lanes; s >> 1 how element
                               code reads its parameters from LDS: 0 at each use,
                               1 all of an element's words in one group before its
                               arithmetic, 2 the next element's group issued
-                              before the current element's arithmetic.
+                              before the current element's arithmetic, 3 as 2
+                              with one loss test per cell instead of a store at
+                              every loss test (lanes lost in a cell re-apply the
+                              cell's maps from its entry to find the coordinates
+                              to store).
                               XTM_E_UNSUPPORTED if it cannot be built */
   int32_t radiation;       /* synchrotron radiation in multipoles with length > 0:
                               0 off, 1 mean energy loss, 2 mean + quantum excitation

@@ -115,10 +115,13 @@ struct LineKernel {
 };
 // Generated-kernel forms ("styles"), all computing the same maps in the same
 // order: bit 0 selects the workgroup (0: 256 lanes, 1: one wave), the rest the
-// way element code reads its parameters from the LDS slot (line_fetch).
-constexpr int32_t kLineStyles = 6;
+// way element code reads its parameters from the LDS slot (line_fetch) and
+// where a lost particle's coordinates are stored (line_deferred).
+constexpr int32_t kLineStyles = 8;
 inline int32_t line_block(int32_t style) { return (style & 1) ? 64 : kLineBlock; }
-inline int32_t line_fetch(int32_t style) { return style >> 1; }
+inline int32_t line_fetch(int32_t style) { return (style >> 1) < 2 ? (style >> 1) : 2; }
+// styles 6 and 7: fetch 2 with loss handling deferred to one test per cell
+inline bool line_deferred(int32_t style) { return (style >> 1) == 3; }
 bool build_line_kernel(const std::vector<uint64_t>& tab, int32_t n_el, int32_t style,
                        LineKernel* k);
 void free_line_kernel(LineKernel* k);

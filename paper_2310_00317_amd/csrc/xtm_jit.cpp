@@ -129,14 +129,25 @@ int32_t n_words(uint32_t s) {
 // C++ statement applying one element whose parameters are P[0..] where P is
 // the expression `arr` (an LDS pointer "p + o" or a local array name); `j` is
 // its position in the cell (the loss code is e0 + j).
-std::string emit(uint32_t s, const std::string& arr, int32_t j, bool far_rf) {
+// Loss handling (`mode`): kSaveAtLoss stores a failing lane's entry
+// coordinates at the element; kMarkOnly only records the loss code (the cell
+// is replayed for lanes lost in it, see generate); kReplay applies the map
+// alone (the replay itself).
+enum EmitMode { kSaveAtLoss = 0, kMarkOnly = 1, kReplay = 2 };
+
+std::string emit(uint32_t s, const std::string& arr, int32_t j, bool far_rf, EmitMode mode) {
   const uint32_t kt = s & 0xffu, order = (s >> 8) & 0xffu;
   auto P = [&](int32_t m) { return "(" + arr + ")[" + std::to_string(m) + "]"; };
   std::ostringstream c;
   switch (kt) {
     case K_DRIFT:
-      c << "{ if (!xtmm::drift_ok(q) && code == 0) SAVE(); xtmm::mark(xtmm::drift_exact(q, "
-        << P(0) << "), code, st, e0 + " << j << ", -1); }";
+      if (mode == kReplay)
+        c << "(void)xtmm::drift_exact(q, " << P(0) << ");";
+      else if (mode == kMarkOnly)
+        c << "xtmm::mark(xtmm::drift_exact(q, " << P(0) << "), code, st, e0 + " << j << ", -1);";
+      else
+        c << "{ if (!xtmm::drift_ok(q) && code == 0) SAVE(); xtmm::mark(xtmm::drift_exact(q, "
+          << P(0) << "), code, st, e0 + " << j << ", -1); }";
       break;
     case K_DRIFT_EXP:
       c << "xtmm::drift_expanded(q, " << P(0) << ");";
@@ -170,12 +181,14 @@ std::string emit(uint32_t s, const std::string& arr, int32_t j, bool far_rf) {
     case K_AP_CIRC:
     case K_AP_ELL:
     case K_AP_RECT: {
+      if (mode == kReplay) break;  // a test, no change of coordinates
       std::string test;
       if (kt == K_AP_CIRC) test = "xtmm::in_circle(q, " + P(0) + ")";
       else if (kt == K_AP_ELL) test = "xtmm::in_ellipse(q, " + P(0) + ", " + P(1) + ")";
       else test = "xtmm::in_rect(q, " + P(0) + ", " + P(1) + ", " + P(2) + ", " + P(3) + ")";
-      c << "{ const bool ok = " << test << "; if (!ok && code == 0) SAVE(); xtmm::mark(ok, code, "
-        << "st, e0 + " << j << ", 0); }";
+      c << "{ const bool ok = " << test << "; ";
+      if (mode == kSaveAtLoss) c << "if (!ok && code == 0) SAVE(); ";
+      c << "xtmm::mark(ok, code, st, e0 + " << j << ", 0); }";
       break;
     }
     default:
@@ -208,6 +221,10 @@ std::string generate(const Decomp& d, int32_t style) {
   // 2 = the next element's group issued before the current element's
   //     arithmetic, so the read latency overlaps one element of work
   const int32_t fetch = line_fetch(style);
+  // loss handling: at each loss test (a divergent store per test), or once
+  // per cell (line_deferred: the tests only record the loss code; lanes lost
+  // in the cell replay it afterwards)
+  const bool deferred = line_deferred(style);
   // a line with radiating multipoles calls its RF sine out of line
   bool far_rf = false;
   for (const auto& k : d.kinds)
@@ -224,9 +241,12 @@ std::string generate(const Decomp& d, int32_t style) {
        "    t0 + t, ec + (j), r.gamma0, r.c_mean, r.c_quant, r.p0c, beta0, two_over_beta0)\n"
        "// a lane that fails a loss test stores the coordinates it entered the\n"
        "// element with (a rare, divergent store); the loss record follows at the end\n"
-       "#define SAVE() do { P.x[pi] = q.x; P.px[pi] = q.px; P.y[pi] = q.y; P.py[pi] = q.py; \\\n"
-       "    P.zeta[pi] = q.zeta; P.delta[pi] = q.delta; P.ptau[pi] = q.ptau; P.rpp[pi] = q.rpp; \\\n"
-       "    P.rvv[pi] = q.rvv; } while (0)\n"
+       "// (its slot index passes through a register move, so the nine store\n"
+       "// addresses are formed on this rare path instead of held in registers)\n"
+       "#define SAVE() do { int pj_; asm volatile(\"v_mov_b32 %0, %1\" : \"=v\"(pj_) : \"v\"(pi)); \\\n"
+       "    P.x[pj_] = q.x; P.px[pj_] = q.px; P.y[pj_] = q.y; P.py[pj_] = q.py; \\\n"
+       "    P.zeta[pj_] = q.zeta; P.delta[pj_] = q.delta; P.ptau[pj_] = q.ptau; \\\n"
+       "    P.rpp[pj_] = q.rpp; P.rvv[pj_] = q.rvv; } while (0)\n"
        "#define MAXW " << maxw << "\n"
        "#define PER_THREAD " << per_thread << "\n"
        "#define LANES " << lanes << "\n"
@@ -287,6 +307,9 @@ std::string generate(const Decomp& d, int32_t style) {
        "      // e0 + j are vector adds of literals, not hoisted scalar constants\n"
        "      int e0;\n"
        "      asm volatile(\"v_mov_b32 %0, %1\" : \"=v\"(e0) : \"s\"(enc_t + ec));\n";
+  if (deferred)
+    s << "      const int code_in = code;\n"
+         "      const xtmm::Pt qc = q;\n";
   for (size_t k = 0; k < d.kinds.size(); ++k) {
     s << "      " << (k ? "else if" : "if") << " (kind == " << k << ") {\n";
     const auto& kd = d.kinds[k];
@@ -312,10 +335,35 @@ std::string generate(const Decomp& d, int32_t style) {
         s << "        __builtin_amdgcn_sched_barrier(0);\n";
       }
       if (fetch != 0 && n_words(kd[j]) > 0) arr = "w" + std::to_string(j);
-      const std::string stmt = emit(kd[j], arr, (int32_t)j, far_rf);
+      const std::string stmt =
+          emit(kd[j], arr, (int32_t)j, far_rf, deferred ? kMarkOnly : kSaveAtLoss);
       if (!stmt.empty()) s << "        " << stmt << "\n";
     }
     s << "      }\n";
+  }
+  if (deferred) {
+    // one wave-uniform test per cell; a lane lost in the cell re-applies the
+    // cell's maps up to its lost element from the cell-entry copy (the same
+    // operations, so the same values) and stores those entry coordinates
+    s << "      if (__any(code != code_in)) {\n"
+         "        if (code != code_in) {\n"
+         "          const int jl = code - e0;\n"
+         "          xtmm::Pt q = qc;\n";
+    for (size_t k = 0; k < d.kinds.size(); ++k) {
+      s << "          " << (k ? "else if" : "if") << " (kind == " << k << ") {\n";
+      const auto& kd = d.kinds[k];
+      int32_t o = 0;
+      for (size_t j = 0; j < kd.size(); ++j) {
+        const std::string stmt =
+            emit(kd[j], "p + " + std::to_string(o), (int32_t)j, far_rf, kReplay);
+        if (!stmt.empty()) s << "            if (" << j << " < jl) " << stmt << "\n";
+        o += n_words(kd[j]);
+      }
+      s << "          }\n";
+    }
+    s << "          SAVE();\n"
+         "        }\n"
+         "      }\n";
   }
   s << "#pragma unroll\n"
        "      for (int k = 0; k < PER_THREAD; ++k) {\n"
