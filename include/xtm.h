@@ -164,7 +164,7 @@ typedef struct xtm_track_opts {
   int32_t use_graph;       /* 1 = replay the chunk sequence as a captured hipGraph    */
   int32_t time_kernels;    /* 1 = time each tracking launch with HIP events (stats)   */
   int32_t variant;         /* tracking kernel (all give bitwise the same results):
-                              0 = default (5 when the line has a compact periodic
+                              0 = default (10 when the line has a compact periodic
                               cell structure, else 4); 1 = interpreter, exit on loss;
                               2 = interpreter, store on loss; 3 = as 2 with the
                               element table staged in LDS; 4 = interpreter, losses

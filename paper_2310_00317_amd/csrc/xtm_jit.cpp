@@ -128,14 +128,15 @@ int32_t n_words(uint32_t s) {
 
 // C++ statement applying one element whose parameters are P[0..] where P is
 // the expression `arr` (an LDS pointer "p + o" or a local array name); `j` is
-// its position in the cell (the loss code is e0 + j).
+// the expression of its position in the cell (the loss code is e0 + j).
 // Loss handling (`mode`): kSaveAtLoss stores a failing lane's entry
 // coordinates at the element; kMarkOnly only records the loss code (the cell
 // is replayed for lanes lost in it, see generate); kReplay applies the map
 // alone (the replay itself).
 enum EmitMode { kSaveAtLoss = 0, kMarkOnly = 1, kReplay = 2 };
 
-std::string emit(uint32_t s, const std::string& arr, int32_t j, bool far_rf, EmitMode mode) {
+std::string emit(uint32_t s, const std::string& arr, const std::string& j, bool far_rf,
+                 EmitMode mode) {
   const uint32_t kt = s & 0xffu, order = (s >> 8) & 0xffu;
   auto P = [&](int32_t m) { return "(" + arr + ")[" + std::to_string(m) + "]"; };
   std::ostringstream c;
@@ -225,6 +226,29 @@ std::string generate(const Decomp& d, int32_t style) {
   // per cell (line_deferred: the tests only record the loss code; lanes lost
   // in the cell replay it afterwards)
   const bool deferred = line_deferred(style);
+  std::vector<uint32_t> sigs;  // distinct element signatures of the line
+  std::string replay_tables;   // per kind: first entry; per entry: signature, offset
+  if (deferred) {
+    std::ostringstream kf, es, eo;
+    int32_t n = 0;
+    for (const auto& k : d.kinds) {
+      kf << n << ", ";
+      int32_t o = 0;
+      for (uint32_t e : k) {
+        size_t g = 0;
+        while (g < sigs.size() && sigs[g] != e) ++g;
+        if (g == sigs.size()) sigs.push_back(e);
+        es << g << ", ";
+        eo << o << ", ";
+        o += n_words(e);
+        ++n;
+      }
+    }
+    kf << n;
+    replay_tables = "__constant__ int kind_first[] = {" + kf.str() + "};\n"
+                    "__constant__ int elem_sig[] = {" + es.str() + "};\n"
+                    "__constant__ int elem_off[] = {" + eo.str() + "};\n";
+  }
   // a line with radiating multipoles calls its RF sine out of line
   bool far_rf = false;
   for (const auto& k : d.kinds)
@@ -250,6 +274,7 @@ std::string generate(const Decomp& d, int32_t style) {
        "#define MAXW " << maxw << "\n"
        "#define PER_THREAD " << per_thread << "\n"
        "#define LANES " << lanes << "\n"
+       << replay_tables <<
        "extern \"C\" __global__ void __launch_bounds__(" << lanes << ")\n"
        "xtm_line(const double* __restrict__ prm, const int* __restrict__ cells, int n_cells,\n"
        "         int n_el, SoA P, const int* __restrict__ idx, const int* __restrict__ ctrl,\n"
@@ -336,7 +361,7 @@ std::string generate(const Decomp& d, int32_t style) {
       }
       if (fetch != 0 && n_words(kd[j]) > 0) arr = "w" + std::to_string(j);
       const std::string stmt =
-          emit(kd[j], arr, (int32_t)j, far_rf, deferred ? kMarkOnly : kSaveAtLoss);
+          emit(kd[j], arr, std::to_string(j), far_rf, deferred ? kMarkOnly : kSaveAtLoss);
       if (!stmt.empty()) s << "        " << stmt << "\n";
     }
     s << "      }\n";
@@ -344,24 +369,24 @@ std::string generate(const Decomp& d, int32_t style) {
   if (deferred) {
     // one wave-uniform test per cell; a lane lost in the cell re-applies the
     // cell's maps up to its lost element from the cell-entry copy (the same
-    // operations, so the same values) and stores those entry coordinates
+    // operations, so the same values) and stores those entry coordinates.
+    // The replay walks the cell's element list with one switch over the
+    // line's element signatures, so this rare path adds little code.
     s << "      if (__any(code != code_in)) {\n"
          "        if (code != code_in) {\n"
          "          const int jl = code - e0;\n"
-         "          xtmm::Pt q = qc;\n";
-    for (size_t k = 0; k < d.kinds.size(); ++k) {
-      s << "          " << (k ? "else if" : "if") << " (kind == " << k << ") {\n";
-      const auto& kd = d.kinds[k];
-      int32_t o = 0;
-      for (size_t j = 0; j < kd.size(); ++j) {
-        const std::string stmt =
-            emit(kd[j], "p + " + std::to_string(o), (int32_t)j, far_rf, kReplay);
-        if (!stmt.empty()) s << "            if (" << j << " < jl) " << stmt << "\n";
-        o += n_words(kd[j]);
-      }
-      s << "          }\n";
+         "          xtmm::Pt q = qc;\n"
+         "          for (int j = kind_first[kind]; j < kind_first[kind] + jl; ++j) {\n"
+         "            const double* pe = p + elem_off[j];\n"
+         "            switch (elem_sig[j]) {\n";
+    for (size_t g = 0; g < sigs.size(); ++g) {
+      const std::string stmt = emit(sigs[g], "pe", "(j - kind_first[kind])", far_rf, kReplay);
+      if (!stmt.empty()) s << "              case " << g << ": " << stmt << " break;\n";
     }
-    s << "          SAVE();\n"
+    s << "              default: break;\n"
+         "            }\n"
+         "          }\n"
+         "          SAVE();\n"
          "        }\n"
          "      }\n";
   }
