@@ -127,10 +127,18 @@ def wilson_upper(k: int, n: int, z: float = 1.6449) -> float:
 def scan(lat, ref, coords, horizon: int, twiss4=None, emit=None, r_aperture=None,
          predictor: Predictor | None = None, rule_tau: float | None = None,
          audit_fraction: float = 0.05, audit_seed: int = 0x5EED, fallback_rate: float = 5e-3,
-         first_id: int = 0) -> dict:
+         first_id: int = 0, tune_turns: int = 0, variant: int = 0) -> dict:
     """One DA scan.  Plain when neither a predictor nor a rule threshold is
     given; otherwise learned (network) or rule-based early stop.  Returns the
-    final states, the GPU wall time and the retire/audit counts."""
+    final states, the GPU wall time and the retire/audit counts.
+
+    tune_turns > 0: before each long tracking stretch (the whole horizon of a
+    plain scan; the turns after retirement otherwise) the launch-plan
+    autotuner times every kernel form on a scratch copy of the particles
+    still tracked, for that many turns, and the stretch runs with the
+    fastest (inside the timed wall time; results are the same bit for bit).
+    The plan stays set on the lattice afterwards.  variant != 0 runs that
+    tracking kernel throughout instead (see xtm_track_opts.variant)."""
     import torch
     n = len(coords)
     coords_dev = torch.as_tensor(np.ascontiguousarray(coords), device="cuda")
@@ -139,10 +147,12 @@ def scan(lat, ref, coords, horizon: int, twiss4=None, emit=None, r_aperture=None
     t0 = time.perf_counter()
     out = {"retired": 0, "audited": 0, "audit_lost": 0, "fallback": False}
     if predictor is None and rule_tau is None:
-        P.track(lat, parts, horizon)
+        if tune_turns > 0:
+            P.autotune(parts, lattice=lat, probe_turns=tune_turns)
+        P.track(lat, parts, horizon, variant=variant)
     else:
         rec = torch.zeros((RECORD_TURNS, 4, n), dtype=torch.float32, device="cuda")
-        P.track(lat, parts, RECORD_TURNS, record=rec)
+        P.track(lat, parts, RECORD_TURNS, record=rec, variant=variant)
         feat = P.features(rec, twiss4, emit, r_aperture)
         del rec
         if predictor is not None:
@@ -155,7 +165,9 @@ def scan(lat, ref, coords, horizon: int, twiss4=None, emit=None, r_aperture=None
         snap = parts.to_numpy() if retired else None
         sc = score.cpu().numpy()
         audit_mask = (st_pre == 1) & (sc >= tau) & (st_post == 1)
-        P.track(lat, parts, horizon - RECORD_TURNS)
+        if tune_turns > 0:
+            P.autotune(parts, lattice=lat, probe_turns=tune_turns)
+        P.track(lat, parts, horizon - RECORD_TURNS, variant=variant)
         st_end, _, _ = parts.losses()
         lost_audit = int(((st_end != 1) & audit_mask).sum())
         out.update(retired=retired, audited=audited, audit_lost=lost_audit,
