@@ -157,7 +157,8 @@ def learned_da(args):
     H = args.horizon
     t = time.perf_counter()
     tc, _, _ = I.random_amplitudes(args.train_particles, args.da_rmax, tw, seed=404)
-    data = L.collect(lat, ref, tc, H, tw, emit, rap, first_id=10 ** 9)
+    data = L.collect(lat, ref, tc, H, tw, emit, rap, first_id=10 ** 9,
+                     windows=max(args.windows, args.stages))
     t_label = time.perf_counter() - t
     log(f"labels: {args.train_particles} particles x {H} turns in {t_label:.1f} s; "
         f"stable fraction {data.label.mean():.3f}")
@@ -168,14 +169,18 @@ def learned_da(args):
     log(f"trained in {t_train:.1f} s, tau {pred.tau:.3f} (held-out false rate "
         f"{pred.val_false_rate:.2e}, {pred.val_retired} retired); rule threshold {rule:.3f}")
     gc, gr, _ = I.polar_grid(args.da_radii, args.da_rays, args.da_rmax, tw, emit)
-    # compile every kernel form of this line once, outside the timed scans
+    # compile the kernel forms the scans will use once, outside the timed scans
     warm = P.Particles(4096, ref).init(gc[:4096])
-    P.autotune(warm, lattice=lat, probe_turns=1)
-    warm.close()
     tt = args.tune_turns
+    if tt > 0:
+        P.autotune(warm, lattice=lat, probe_turns=1)
+    else:
+        P.track(lat, warm, 2)
+    warm.close()
     plain = L.scan(lat, ref, gc, H, tune_turns=tt)
     log(f"plain scan {plain['wall_s']:.1f} s")
-    learned = L.scan(lat, ref, gc, H, tw, emit, rap, predictor=pred, tune_turns=tt)
+    learned = L.scan(lat, ref, gc, H, tw, emit, rap, predictor=pred, tune_turns=tt,
+                     stages=args.stages)
     log(f"learned scan {learned['wall_s']:.1f} s, retired {learned['retired']}")
     if args.no_rule_scan:
         ruled = None
@@ -198,7 +203,8 @@ def learned_da(args):
         "data": "synthetic",
         "config": {"workload": f"cfg1 ring DA scan, {nr}x{nt} polar grid 0-{args.da_rmax} sigma, "
                                f"{H} turns; predictor trained on {args.train_particles} random "
-                               "amplitudes", "horizon": H},
+                               "amplitudes", "horizon": H, "max_false_rate": args.max_false_rate,
+                   "stages": args.stages, "windows": max(args.windows, args.stages)},
         "da_error_sigma": {"network_mean": e_l[0], "network_max": e_l[1],
                            "rule_mean": e_r[0], "rule_max": e_r[1]},
         "plain": {"wall_s": plain["wall_s"], "da_mean_sigma": float(np.mean(np.where(
@@ -206,7 +212,9 @@ def learned_da(args):
         "network": {k: learned[k] for k in keys if k in learned},
         "rule": {k: ruled[k] for k in keys if k in ruled} if ruled else None,
         "rule_speedup": plain["wall_s"] / ruled["wall_s"] if ruled else None,
+        "network_stages": learned.get("stages"),
         "training": {"label_s": t_label, "train_s": t_train, "tau": pred.tau,
+                     "taus": [float(t) for t in pred.taus],
                      "val_false_rate": pred.val_false_rate,
                      "loss_first_last": [float(pred.losses[0]), float(pred.losses[-1])]},
     }
@@ -228,10 +236,14 @@ def main():
     ap.add_argument("--train-particles", type=int, default=200000)
     ap.add_argument("--horizon", type=int, default=100000, help="cfg4: turns")
     ap.add_argument("--epochs", type=int, default=30)
-    ap.add_argument("--tune-turns", type=int, default=50,
+    ap.add_argument("--tune-turns", type=int, default=0,
                     help="cfg4: autotuner probe turns before each long tracking stretch (0 = off)")
-    ap.add_argument("--max-false-rate", type=float, default=1e-3,
+    ap.add_argument("--max-false-rate", type=float, default=5e-4,
                     help="cfg4: held-out false-retire budget that fixes the threshold")
+    ap.add_argument("--stages", type=int, default=1,
+                    help="cfg4: retirement decisions at the end of this many 1024-turn windows")
+    ap.add_argument("--windows", type=int, default=1,
+                    help="cfg4: recorded 1024-turn windows per training particle (pooled)")
     ap.add_argument("--no-rule-scan", action="store_true", help="cfg4: skip the rule-only scan")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES (3 times), the "

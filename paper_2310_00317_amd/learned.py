@@ -11,8 +11,17 @@ those with logit >= tau are retired (state 2) unless they fall in the
 Philox-drawn audit set, which is tracked to the horizon like the rest and
 measures the false-retire rate of the run itself.  If the audit's upper 95 %
 bound on that rate exceeds ``fallback_rate``, every retired particle is
-resumed from its turn-1024 state and tracked to the horizon (full-tracking
-fallback).
+resumed from the state it was retired in and tracked to the horizon
+(full-tracking fallback).
+
+Stages (an extension of the single decision at turn 1024): with K stages the
+same decision is repeated at the end of each consecutive 1024-turn window
+(turns 1024, 2048, ..., K*1024) for the particles still tracked, from the
+features of that window.  The network is trained on the windows of the
+training set pooled (a window's features and the particle's survival to the
+horizon), and each stage has its own threshold from the held-out rows of its
+window.  Audited particles stay audited at every stage (the audit draw is a
+function of the particle id), so the audit still judges every retirement.
 """
 from __future__ import annotations
 
@@ -31,63 +40,93 @@ RECORD_TURNS = P.RECORD_TURNS
 class Predictor:
     theta: object          # torch float32 [MLP_PARAMS]
     norm: object           # torch float32 [32]
-    tau: float             # retire threshold on the logit
+    tau: float             # retire threshold on the logit (first window)
     val_false_rate: float  # held-out false-retire fraction at tau
     val_retired: int       # held-out rows at or above tau
     losses: np.ndarray     # per-epoch mean training loss
+    taus: tuple = ()       # per-window thresholds (window k: taus[k]); () = (tau,)
+
+    def tau_at(self, k: int) -> float:
+        t = self.taus or (self.tau,)
+        return float(t[min(k, len(t) - 1)])
 
 
 @dataclass
 class Collected:
-    feat: object           # torch float32 [n, 16]
+    feat: object           # torch float32 [n, 16] (first window)
     label: np.ndarray      # int32 (1 = alive after the horizon)
-    alive_at_record: np.ndarray  # bool: alive after the record turns
+    alive_at_record: np.ndarray  # bool: alive after the first window
     state: np.ndarray
     at_turn: np.ndarray
+    feats: tuple = ()      # per window k: torch float32 [n, 16]
+    alive: tuple = ()      # per window k: bool, alive after window k
 
 
 def collect(lat, ref, coords, horizon: int, twiss4, emit: float, r_aperture: float,
-            first_id: int = 0) -> Collected:
-    """Track the set to the horizon with the recorder on; features from the
-    first 1024 turns and survival labels."""
+            first_id: int = 0, windows: int = 1) -> Collected:
+    """Track the set to the horizon with the recorder on; features from each
+    of the first `windows` 1024-turn windows and survival labels."""
     import torch
     n = len(coords)
     parts = P.Particles(n, ref).init(coords, first_id=first_id)
-    rec = torch.zeros((RECORD_TURNS, 4, n), dtype=torch.float32, device="cuda")
-    P.track(lat, parts, RECORD_TURNS, record=rec)
-    st1, _, _ = parts.losses()
-    feat = P.features(rec, twiss4, emit, r_aperture)
+    rec = torch.zeros((windows * RECORD_TURNS, 4, n), dtype=torch.float32, device="cuda")
+    feats, alive = [], []
+    for k in range(windows):
+        P.track(lat, parts, RECORD_TURNS, record=rec)
+        st_k, _, _ = parts.losses()
+        alive.append(st_k == 1)
+        feats.append(P.features(rec[k * RECORD_TURNS:(k + 1) * RECORD_TURNS], twiss4, emit,
+                                r_aperture))
     del rec
-    P.track(lat, parts, horizon - RECORD_TURNS)
+    P.track(lat, parts, horizon - windows * RECORD_TURNS)
     st, at, _ = parts.losses()
-    return Collected(feat, (st == 1).astype(np.int32), st1 == 1, st, at)
+    return Collected(feats[0], (st == 1).astype(np.int32), alive[0], st, at, tuple(feats),
+                     tuple(alive))
 
 
 def train(data: Collected, max_false_rate: float = 1e-3, val_frac: float = 0.1,
           epochs: int = 30, batch: int = 4096, lr: float = 1e-3, seed: int = 1) -> Predictor:
-    """Fit the network on the rows alive after the record turns; pick tau on
-    a held-out split."""
+    """Fit the network on the rows alive after each recorded window (pooled
+    over the windows); pick each window's threshold on a held-out split of
+    the particles."""
     import torch
-    rows = np.nonzero(data.alive_at_record)[0]
+    feats = data.feats or (data.feat,)
+    alive = data.alive or (data.alive_at_record,)
+    n = len(data.label)
     rng = np.random.default_rng(seed)
-    rows = rows[rng.permutation(len(rows))]
-    n_val = max(1, int(len(rows) * val_frac))
-    val, tr = rows[:n_val], rows[n_val:]
+    perm = rng.permutation(n)
+    is_val = np.zeros(n, dtype=bool)
+    # the held-out particles: val_frac of those alive after the first window
+    first = perm[alive[0][perm]]
+    is_val[first[: max(1, int(len(first) * val_frac))]] = True
     dev = data.feat.device
-    X = data.feat[torch.as_tensor(tr, device=dev)].contiguous()
-    Y = torch.as_tensor(data.label[tr].astype(np.float32), device=dev)
-    Xv = data.feat[torch.as_tensor(val, device=dev)].contiguous()
-    Yv = torch.as_tensor(data.label[val], device=dev)
+    Xs, Ys, val_sets = [], [], []
+    for f, a in zip(feats, alive):
+        tr = np.nonzero(a & ~is_val)[0]
+        tr = tr[rng.permutation(len(tr))]
+        Xs.append(f[torch.as_tensor(tr, device=dev)])
+        Ys.append(data.label[tr])
+        val_sets.append((f, np.nonzero(a & is_val)[0]))
+    X = torch.cat(Xs).contiguous()
+    y = np.concatenate(Ys)
+    Y = torch.as_tensor(y.astype(np.float32), device=dev)
     norm = P.feature_stats(X)
     theta = P.mlp_init(seed)
     m = torch.zeros_like(theta)
     v = torch.zeros_like(theta)
-    n_pos = int(data.label[tr].sum())
-    pos_weight = (len(tr) - n_pos) / max(n_pos, 1)
+    n_pos = int(y.sum())
+    pos_weight = (len(y) - n_pos) / max(n_pos, 1)
     _, losses = P.mlp_train(theta, m, v, norm, X, Y, pos_weight, epochs, batch, lr, seed)
-    z = P.mlp_forward(theta, norm, Xv)
-    tau, rate, sel = P.select_threshold(z, Yv, max_false_rate)
-    return Predictor(theta, norm, tau, rate, sel, losses)
+    taus, first_rate, first_sel = [], 0.0, 0
+    for k, (f, val) in enumerate(val_sets):
+        Xv = f[torch.as_tensor(val, device=dev)].contiguous()
+        Yv = torch.as_tensor(data.label[val], device=dev)
+        z = P.mlp_forward(theta, norm, Xv)
+        tau, rate, sel = P.select_threshold(z, Yv, max_false_rate)
+        taus.append(tau)
+        if k == 0:
+            first_rate, first_sel = rate, sel
+    return Predictor(theta, norm, taus[0], first_rate, first_sel, losses, tuple(taus))
 
 
 def rule_threshold(data: Collected, max_false_rate: float = 1e-3, val_frac: float = 0.1,
@@ -127,13 +166,14 @@ def wilson_upper(k: int, n: int, z: float = 1.6449) -> float:
 def scan(lat, ref, coords, horizon: int, twiss4=None, emit=None, r_aperture=None,
          predictor: Predictor | None = None, rule_tau: float | None = None,
          audit_fraction: float = 0.05, audit_seed: int = 0x5EED, fallback_rate: float = 5e-3,
-         first_id: int = 0, tune_turns: int = 0, variant: int = 0) -> dict:
+         first_id: int = 0, tune_turns: int = 0, variant: int = 0, stages: int = 1) -> dict:
     """One DA scan.  Plain when neither a predictor nor a rule threshold is
-    given; otherwise learned (network) or rule-based early stop.  Returns the
+    given; otherwise learned (network) or rule-based early stop, decided at
+    the end of each of the first `stages` 1024-turn windows.  Returns the
     final states, the GPU wall time and the retire/audit counts.
 
     tune_turns > 0: before each long tracking stretch (the whole horizon of a
-    plain scan; the turns after retirement otherwise) the launch-plan
+    plain scan; the turns after the last stage otherwise) the launch-plan
     autotuner times every kernel form on a scratch copy of the particles
     still tracked, for that many turns, and the stretch runs with the
     fastest (inside the timed wall time; results are the same bit for bit).
@@ -145,50 +185,74 @@ def scan(lat, ref, coords, horizon: int, twiss4=None, emit=None, r_aperture=None
     parts = P.Particles(n, ref).init(coords_dev, first_id=first_id)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    out = {"retired": 0, "audited": 0, "audit_lost": 0, "fallback": False}
+    out = {"retired": 0, "audited": 0, "audit_lost": 0, "fallback": False, "stages": []}
     if predictor is None and rule_tau is None:
         if tune_turns > 0:
             P.autotune(parts, lattice=lat, probe_turns=tune_turns)
         P.track(lat, parts, horizon, variant=variant)
     else:
-        rec = torch.zeros((RECORD_TURNS, 4, n), dtype=torch.float32, device="cuda")
-        P.track(lat, parts, RECORD_TURNS, record=rec, variant=variant)
-        feat = P.features(rec, twiss4, emit, r_aperture)
+        stages = max(1, min(int(stages), horizon // RECORD_TURNS))
+        rec = torch.zeros((stages * RECORD_TURNS, 4, n), dtype=torch.float32, device="cuda")
+        audit_mask = np.zeros(n, dtype=bool)
+        snaps = []  # per stage: (retired slots, their coordinates, turn)
+        for k in range(stages):
+            P.track(lat, parts, RECORD_TURNS, record=rec, variant=variant)
+            feat = P.features(rec[k * RECORD_TURNS:(k + 1) * RECORD_TURNS], twiss4, emit,
+                              r_aperture)
+            if predictor is not None:
+                score, tau = P.mlp_forward(predictor.theta, predictor.norm, feat), \
+                    predictor.tau_at(k)
+            else:
+                score, tau = rule_scores(feat), rule_tau
+            st_pre, _, _ = parts.losses()
+            retired, audited = P.retire(parts, score, tau, audit_seed, audit_fraction)
+            st_post, _, _ = parts.losses()
+            sc = score.cpu().numpy()
+            audit_mask |= (st_pre == 1) & (sc >= tau) & (st_post == 1)
+            if retired:
+                # device copy of the full state of the particles just retired,
+                # for the fallback to resume from exactly where they stopped
+                ret = np.nonzero((st_pre == 1) & (st_post == 2))[0]
+                ix = torch.as_tensor(ret, device="cuda")
+                snap = {f: getattr(parts, f)[ix].clone() for f in P.FLOAT_FIELDS + ("particle_id",)}
+                snaps.append((ret, snap, (k + 1) * RECORD_TURNS))
+            out["retired"] += retired
+            out["audited"] += audited
+            out["stages"].append({"turn": (k + 1) * RECORD_TURNS, "tau": float(tau),
+                                  "retired": retired, "audited": audited,
+                                  "tracked_after": int((st_post == 1).sum())})
         del rec
-        if predictor is not None:
-            score, tau = P.mlp_forward(predictor.theta, predictor.norm, feat), predictor.tau
-        else:
-            score, tau = rule_scores(feat), rule_tau
-        st_pre, _, _ = parts.losses()
-        retired, audited = P.retire(parts, score, tau, audit_seed, audit_fraction)
-        st_post, _, _ = parts.losses()
-        snap = parts.to_numpy() if retired else None
-        sc = score.cpu().numpy()
-        audit_mask = (st_pre == 1) & (sc >= tau) & (st_post == 1)
         if tune_turns > 0:
             P.autotune(parts, lattice=lat, probe_turns=tune_turns)
-        P.track(lat, parts, horizon - RECORD_TURNS, variant=variant)
+        P.track(lat, parts, horizon - stages * RECORD_TURNS, variant=variant)
         st_end, _, _ = parts.losses()
         lost_audit = int(((st_end != 1) & audit_mask).sum())
-        out.update(retired=retired, audited=audited, audit_lost=lost_audit,
+        out.update(audit_lost=lost_audit,
                    audit_upper=wilson_upper(lost_audit, int(audit_mask.sum())))
-        if retired and out["audit_upper"] > fallback_rate:
-            # full-tracking fallback: resume the retired particles from turn 1024
-            ret = np.nonzero(st_post == 2)[0]
-            c6 = np.stack([snap[f][ret] for f in ("x", "px", "y", "py", "zeta", "delta")], 1)
-            res = P.Particles(len(ret), ref).init(c6)
-            res.reset(RECORD_TURNS)
-            P.track(lat, res, horizon - RECORD_TURNS)
-            rs, ra, re = res.losses()
+        if out["retired"] and out["audit_upper"] > fallback_rate:
+            # full-tracking fallback: each retired particle resumes from the
+            # turn it was retired at
+            resumed = []
+            for ret, snap, turn in snaps:
+                m = len(ret)
+                res = P.Particles(m, ref)
+                for f, v in snap.items():
+                    getattr(res, f)[:m] = v
+                res.state[:m] = 1
+                res.at_element[:m] = 0
+                res.at_turn[:m] = turn
+                res.reset(turn)
+                P.track(lat, res, horizon - turn, variant=variant)
+                resumed.append((ret,) + tuple(res.losses()))
             out["fallback"] = True
-            out["resumed"] = (ret, rs, ra, re)
+            out["resumed"] = resumed
     torch.cuda.synchronize()
     out["wall_s"] = time.perf_counter() - t0
     st, at, ae = parts.losses()
-    if out.get("resumed") is not None:
-        ret, rs, ra, re = out["resumed"]
+    if out.get("resumed"):
         st, at, ae = st.copy(), at.copy(), ae.copy()
-        st[ret], at[ret], ae[ret] = rs, ra, re
+        for ret, rs, ra, re in out["resumed"]:
+            st[ret], at[ret], ae[ret] = rs, ra, re
     out["state"], out["at_turn"], out["at_element"] = st, at, ae
     return out
 
