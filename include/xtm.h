@@ -227,6 +227,18 @@ xtm_status xtm_track(xtm_lattice lat, xtm_particles p, int32_t n_turns,
 xtm_status xtm_track_backward(xtm_lattice lat, xtm_particles p, int32_t n_turns,
                               void* stream, xtm_track_stats* stats);
 
+/* Measurement baseline, not a tracking path to use: the same maps applied by
+   one kernel launch per element and turn (n_turns x n_el launches), each
+   launch reading every alive particle's state from HBM and writing it back,
+   as a one-kernel-per-element tracker would.  Forward, from the set's turn;
+   no radiation, recorder, chunking or graph.  Results (coordinates, states,
+   loss turns and elements) equal xtm_track's bit for bit; the set's alive
+   list is rebuilt afterwards.  With stats (synchronising): passes counted on
+   the host from the states before and after, launches = n_turns x n_el,
+   variant 0, kernel_ms = all launches together. */
+xtm_status xtm_track_per_element(xtm_lattice lat, xtm_particles p, int32_t n_turns, void* stream,
+                                 xtm_track_stats* stats);
+
 /* Copy the loss record into host buffers of the bound length (any may be
    NULL).  Synchronises the stream. */
 xtm_status xtm_get_losses(xtm_particles p, int32_t* h_state, int32_t* h_at_turn,

@@ -88,6 +88,7 @@ def lib() -> ctypes.CDLL:
             "xtm_particles_turn": ([vp, vp], i32),
             "xtm_track": ([vp, vp, i32, vp, vp, vp], i32),
             "xtm_track_backward": ([vp, vp, i32, vp, vp], i32),
+            "xtm_track_per_element": ([vp, vp, i32, vp, vp], i32),
             "xtm_get_losses": ([vp, vp, vp, vp, vp], i32),
             "xtm_sync": ([vp], i32),
             "xtm_philox4x32_10": ([ctypes.c_uint64, vp, i64, vp, vp], i32),
@@ -351,6 +352,15 @@ def autotune(particles: Particles, lattice: Lattice = None, batch: Batch = None,
                              int(probe_turns), _stream(stream), ctypes.byref(plan)),
           "xtm_autotune")
     return plan
+
+
+def track_per_element(lattice: Lattice, particles: Particles, n_turns: int, stream=None):
+    """Measurement baseline: one kernel launch per element and turn, state
+    through HBM each time (same results as track).  Returns TrackStats."""
+    s = TrackStats()
+    check(lib().xtm_track_per_element(lattice.handle, particles.handle, int(n_turns),
+                                      _stream(stream), ctypes.byref(s)), "xtm_track_per_element")
+    return s
 
 
 def track_backward(lattice: Lattice, particles: Particles, n_turns: int, stats: bool = True,

@@ -773,6 +773,76 @@ xtm_status xtm_track_backward(xtm_lattice L, xtm_particles P, int32_t n_turns, v
   });
 }
 
+xtm_status xtm_track_per_element(xtm_lattice L, xtm_particles P, int32_t n_turns, void* stream,
+                                 xtm_track_stats* stats) {
+  return guarded([&]() -> xtm_status {
+    if (!L || !P) return fail(XTM_E_ARG, "null lattice or particle set");
+    if (n_turns < 0) return fail(XTM_E_ARG, "n_turns must be >= 0");
+    if (!P->initialised) return fail(XTM_E_STATE, "particle set not initialised");
+    if (!same_ref(L->ref, P->ref)) return fail(XTM_E_REFERENCE, "reference mismatch");
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<uint32_t> off;  // word position of each element's record
+    off.reserve(L->n_el);
+    for (size_t w = 0; off.size() < (size_t)L->n_el && w < L->fwd_h.size();
+         w += 1 + ((L->fwd_h[w] >> 16) & 0xffffu))
+      off.push_back((uint32_t)w);
+    if (off.size() != (size_t)L->n_el) return fail(XTM_E_STATE, "element table inconsistent");
+    std::vector<int32_t> st0, at, ae, st1;
+    if (stats) {  // passes are counted on the host from the states before and after
+      st0.resize(P->n);
+      if (P->n > 0)
+        HIP_TRY(hipMemcpyAsync(st0.data(), P->a.state, P->n * sizeof(int32_t),
+                               hipMemcpyDeviceToHost, s), "copy state");
+      HIP_TRY(hipStreamSynchronize(s), "synchronise");
+    }
+    hipEvent_t a = nullptr, b = nullptr;
+    if (stats) {
+      HIP_TRY(hipEventCreate(&a), "event");
+      HIP_TRY(hipEventCreate(&b), "event");
+      HIP_TRY(hipEventRecord(a, s), "event record");
+    }
+    const KernelRef kr = kref(L->ref, 0, 0);
+    HIP_TRY(launch_per_element(L->fwd_d, off.data(), L->n_el, soa_of(P), P->n, P->turn, n_turns,
+                               kr, s), "per-element launch");
+    if (stats) HIP_TRY(hipEventRecord(b, s), "event record");
+    const int32_t t0 = P->turn;
+    xtm_status rs = xtm_particles_reset(P, t0 + n_turns, stream);
+    if (rs != XTM_OK) return rs;
+    if (stats) {
+      st1.resize(P->n);
+      at.resize(P->n);
+      ae.resize(P->n);
+      const size_t bytes = P->n * sizeof(int32_t);
+      if (P->n > 0) {
+        HIP_TRY(hipMemcpyAsync(st1.data(), P->a.state, bytes, hipMemcpyDeviceToHost, s), "copy");
+        HIP_TRY(hipMemcpyAsync(at.data(), P->a.at_turn, bytes, hipMemcpyDeviceToHost, s), "copy");
+        HIP_TRY(hipMemcpyAsync(ae.data(), P->a.at_element, bytes, hipMemcpyDeviceToHost, s), "copy");
+      }
+      HIP_TRY(hipStreamSynchronize(s), "synchronise");
+      int64_t passes = 0, alive = 0;
+      for (int64_t i = 0; i < P->n; ++i) {
+        if (st0[i] != 1) continue;
+        if (st1[i] == 1) {
+          passes += (int64_t)n_turns * L->n_el;
+          ++alive;
+        } else {
+          passes += (int64_t)(at[i] - t0) * L->n_el + ae[i] + 1;
+        }
+      }
+      float ms = 0.f;
+      hipEventElapsedTime(&ms, a, b);
+      hipEventDestroy(a);
+      hipEventDestroy(b);
+      stats->passes = passes;
+      stats->alive = alive;
+      stats->launches = n_turns * L->n_el;
+      stats->variant = 0;
+      stats->kernel_ms = ms;
+    }
+    return XTM_OK;
+  });
+}
+
 // ------------------------------------------------------------ batches
 xtm_status xtm_batch_create(const xtm_lattice* lattices, int32_t n_variants, xtm_batch* out) {
   return guarded([&]() -> xtm_status {

@@ -97,6 +97,11 @@ hipError_t launch_replay(const uint64_t* tab, int32_t n_el, SoA P, const int32_t
                          const int32_t* ctrl, int64_t grid_upper, int32_t backward, KernelRef r,
                          hipStream_t s);
 hipError_t launch_fill_i64(int64_t* p, int64_t v, hipStream_t s);
+// One kernel launch per element and turn (the measurement baseline); offsets:
+// host array of each element's record position in `tab` (word index).
+hipError_t launch_per_element(const uint64_t* tab, const uint32_t* offsets, int32_t n_el,
+                              SoA P, int64_t n, int32_t t0, int32_t n_turns, KernelRef r,
+                              hipStream_t s);
 
 constexpr int kScanBlock = 1024;
 

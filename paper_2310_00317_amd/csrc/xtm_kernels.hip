@@ -1082,6 +1082,58 @@ hipError_t launch_fill_i64(int64_t* p, int64_t v, hipStream_t s) {
   return hipGetLastError();
 }
 
+// ------------------------------------------------------ one launch per element
+// Baseline for the persistent kernels, kept for measurement: element `e`
+// (its record at word `off` of the table) is applied to every alive particle
+// by a launch of its own, which reads the particle's state from HBM and
+// writes it back.  A particle failing the element's loss test keeps the
+// coordinates it entered with (they are not written) and records the
+// element and the turn.
+__global__ void __launch_bounds__(256) k_elem(const uint64_t* __restrict__ tab, uint32_t off,
+                                              int32_t e, SoA P, int64_t n, int32_t turn,
+                                              KernelRef r) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n || P.state[p] != 1) return;
+  const uint64_t h = tab[off];
+  xtmm::Pt q;
+  load_pt(P, (int32_t)p, q, r.beta0);
+  bool ok;
+  int ls;
+  apply_elem(q, (uint32_t)(h & 0xffu), (uint32_t)((h >> 8) & 0xffu),
+             reinterpret_cast<const double*>(tab + off + 1), r, ok, ls, 0, turn, e);
+  if (!ok) {
+    P.state[p] = ls;
+    P.at_element[p] = e;
+    P.at_turn[p] = turn;
+    return;
+  }
+  store_pt(P, (int32_t)p, q);
+}
+
+// After the last turn: survivors stand at element 0 of turn `turn`.
+__global__ void __launch_bounds__(256) k_elem_finish(SoA P, int64_t n, int32_t turn) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n || P.state[p] != 1) return;
+  P.at_turn[p] = turn;
+  P.at_element[p] = 0;
+}
+
+hipError_t launch_per_element(const uint64_t* tab, const uint32_t* offsets, int32_t n_el,
+                              SoA P, int64_t n, int32_t t0, int32_t n_turns, KernelRef r,
+                              hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const unsigned nb = blocks_for(n, 256);
+  for (int32_t t = 0; t < n_turns; ++t) {
+    for (int32_t e = 0; e < n_el; ++e) {
+      hipLaunchKernelGGL(k_elem, dim3(nb), dim3(256), 0, s, tab, offsets[e], e, P, n, t0 + t, r);
+      const hipError_t err = hipGetLastError();
+      if (err != hipSuccess) return err;
+    }
+  }
+  hipLaunchKernelGGL(k_elem_finish, dim3(nb), dim3(256), 0, s, P, n, t0 + n_turns);
+  return hipGetLastError();
+}
+
 hipError_t launch_track(const uint64_t* tab, const int32_t* seg, int32_t n_seg, int32_t n_el,
                         SoA P, const int32_t* idx, const int32_t* ctrl, int64_t grid_upper,
                         int32_t block, int32_t n_turns, int32_t backward, KernelRef r,

@@ -349,3 +349,31 @@ def test_line_kernel_with_multi_pass_staging(P, oracle_mod, variant):
     assert gp == op
     assert_bitwise(g, o)
     assert 0.05 < np.mean(o.state == 1) < 0.98
+
+
+@pytest.mark.parametrize("lattice", ["cfg1", "cfg2"])
+def test_per_element_baseline_equals_tracking(P, lattice):
+    """The one-launch-per-element baseline applies the same maps: every
+    coordinate, state, loss turn and element equal the default tracker's bit
+    for bit, and so do the pass counts (losses included)."""
+    banner(f"per-element baseline, {lattice}")
+    if lattice == "cfg1":
+        el, turns = I.cfg1_lattice(), 60
+        c = I.cfg1_particles(3000, seed=8)
+        c[::40, 0] *= 25.0
+    else:
+        el, turns = I.cfg2_lattice(), 3
+        c, _, _ = I.cfg2_grid(n_r=60, n_theta=5, r_max_sigma=40.0)
+    a, pa, aa, _, _ = gpu_run(P, el, REF, c, turns)
+    lat = P.Lattice(el, REF)
+    parts = P.Particles(len(c), REF).init(c)
+    st = P.track_per_element(lat, parts, turns)
+    b = parts.to_numpy()
+    assert (a["state"] != 1).any()
+    assert st.passes == pa and st.alive == aa and st.launches == turns * len(el)
+    assert parts.turn == turns
+    for f in a:
+        assert np.array_equal(a[f], b[f], equal_nan=True), f
+    # the rebuilt alive list lets ordinary tracking continue from here
+    P.track(lat, parts, 2)
+    assert parts.turn == turns + 2
