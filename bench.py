@@ -313,7 +313,8 @@ def main():
             return P.track_per_element(lat, parts, turns)
         if batched:
             return P.track_batched(batch, parts, first, turns, block=args.block,
-                                   turns_per_chunk=args.chunk, full_stats=True, **kw)
+                                   turns_per_chunk=args.chunk, variant=args.variant,
+                                   full_stats=True, **kw)
         return P.track(lat, parts, turns, block=args.block, turns_per_chunk=args.chunk,
                        variant=args.variant, full_stats=True, **extra, **kw)
 

@@ -268,10 +268,16 @@ xtm_status xtm_philox4x32_10(uint64_t seed, const uint32_t ctr0[4], int64_t n_bl
    n_variants + 1 ascending values from 0 to the set's size).  Each particle
    follows exactly the maps of its own variant, so the results equal tracking
    each variant's particles through its lattice alone, bit for bit.  Forward
-   only; the register-loss interpreter (variant 0 or 4); the options and
-   statistics are those of xtm_track.  XTM_E_ARG for a bad partition,
-   XTM_E_REFERENCE for mixed references, XTM_E_UNSUPPORTED for other kernel
-   variants or backward tracking. */
+   only.  Kernels: when every variant has the same element structure (types
+   and orders, element by element; only parameter values differ, as for
+   error seeds) the one-wave per-line forms (6, 8, 10, 12; the default is 10):
+   one generated kernel holds every variant's parameters and a wave whose
+   lanes span several variants makes one pass per variant; otherwise, or with
+   variant 4, the register-loss interpreter.  The options and statistics are
+   those of xtm_track.  XTM_E_ARG for a bad partition, XTM_E_REFERENCE for
+   mixed references, XTM_E_UNSUPPORTED for other kernel variants, for a
+   per-line form asked of variants with different structures, or backward
+   tracking. */
 typedef struct xtm_batch_s* xtm_batch;
 xtm_status xtm_batch_create(const xtm_lattice* lattices, int32_t n_variants, xtm_batch* out);
 xtm_status xtm_batch_destroy(xtm_batch b);

@@ -84,6 +84,10 @@ struct xtm_batch_s {
   int32_t* first_d = nullptr;        // slot partition (n_variants + 1), device
   std::vector<int64_t> first_h;      // the partition last uploaded
   int32_t plan_block = 0;
+  int32_t plan_variant = 0;
+  // batched per-line kernels (one-wave forms), built on first use when every
+  // variant has the same element structure
+  xtm::LineKernel line[xtm::kLineStyles];
 };
 
 struct GraphKey {
@@ -367,7 +371,10 @@ hipError_t enqueue_chunks(xtm_lattice_s* L, xtm_particles_s* P, const ChunkPlan&
       ev->push_back(b);
       if ((e = hipEventRecord(a, s)) != hipSuccess) return e;
     }
-    if (c.batch)
+    if (c.batch && c.line)
+      e = launch_line_batched(*c.line, L->n_el, soa, in, P->ctrl, P->alive_upper, k,
+                              c.backward ? 1 : 0, kr, c.batch->first_d, s);
+    else if (c.batch)
       e = launch_track_batched(c.batch->tabs_d, c.batch->first_d, (int32_t)c.batch->lats.size(),
                                L->n_el, soa, in, P->ctrl, P->alive_upper, c.block, k,
                                c.backward ? 1 : 0, kr, s);
@@ -449,7 +456,7 @@ void drop_graphs(xtm_particles_s* P) {
 
 xtm_status run_turns(xtm_lattice_s* L, xtm_particles_s* P, int32_t n_turns,
                      const xtm_track_opts* o, hipStream_t s, xtm_track_stats* stats,
-                     bool backward, const xtm_batch_s* B = nullptr) {
+                     bool backward, xtm_batch_s* B = nullptr) {
   if (!L || !P) return fail(XTM_E_ARG, "null handle");
   if (n_turns < 0) return fail(XTM_E_ARG, "n_turns must be >= 0");
   if (!P->initialised) return fail(XTM_E_STATE, "particle set not initialised");
@@ -473,26 +480,34 @@ xtm_status run_turns(xtm_lattice_s* L, xtm_particles_s* P, int32_t n_turns,
   if (c.block < 64 || c.block > 256 || c.block % 64)
     return fail(XTM_E_ARG, "block must be 64, 128, 192 or 256");
   c.compact = !(o && o->no_compact) || backward;
-  c.variant = (o && o->variant) ? o->variant : (use_plan && !B ? L->plan_variant : 0);
+  c.variant = (o && o->variant) ? o->variant
+                                : (use_plan ? (B ? B->plan_variant : L->plan_variant) : 0);
   if (c.variant < 0 || c.variant > 4 + kLineStyles)
     return fail(XTM_E_ARG, "kernel variant must be 0.." + std::to_string(4 + kLineStyles));
   if (B) {
     if (backward) return fail(XTM_E_UNSUPPORTED, "batched tracking is forward only");
-    if (c.variant != 0 && c.variant != 4)
-      return fail(XTM_E_UNSUPPORTED, "batched tracking runs the register-loss interpreter (variant 4)");
-    c.variant = 4;
+    if (c.variant != 0 && c.variant != 4 && !(c.variant >= 5 && line_block(c.variant - 5) == 64))
+      return fail(XTM_E_UNSUPPORTED,
+                  "batched tracking runs the interpreter (4) or a one-wave per-line form");
   }
   c.line = nullptr;
   if ((c.rad_mode || c.rec) && c.variant >= 1 && c.variant <= 3)
     return fail(XTM_E_UNSUPPORTED, "kernel variants 1-3 implement neither radiation nor the recorder");
-  if (!B && (c.variant == 0 || c.variant >= 5)) {
+  if (c.variant == 0 || c.variant >= 5) {
     // the per-line kernel, compiled on first use; the default falls back to
     // the register-loss interpreter if the line has no compact cell structure
+    // (a batch: if its variants differ in element structure)
     const int32_t want = c.variant ? c.variant : default_line_variant(P->alive_upper);
-    LineKernel& lk = (backward ? L->bwd_line : L->fwd_line)[want - 5];
+    LineKernel& lk = B ? B->line[want - 5] : (backward ? L->bwd_line : L->fwd_line)[want - 5];
     if (!lk.tried && L->n_el > 0) {
       lk.tried = true;
-      build_line_kernel(backward ? L->bwd_h : L->fwd_h, L->n_el, want - 5, &lk);
+      if (B) {
+        std::vector<const std::vector<uint64_t>*> tabs;
+        for (const xtm_lattice_s* l : B->lats) tabs.push_back(&l->fwd_h);
+        build_line_kernel_multi(tabs, L->n_el, want - 5, true, &lk);
+      } else {
+        build_line_kernel(backward ? L->bwd_h : L->fwd_h, L->n_el, want - 5, &lk);
+      }
     }
     if (lk.ok) {
       c.variant = want;
@@ -878,6 +893,7 @@ xtm_status xtm_batch_create(const xtm_lattice* lattices, int32_t n_variants, xtm
 
 xtm_status xtm_batch_destroy(xtm_batch B) {
   if (!B) return XTM_OK;
+  for (int32_t k = 0; k < kLineStyles; ++k) free_line_kernel(&B->line[k]);
   hipFree(B->tabs_d);
   hipFree(B->first_d);
   delete B;
@@ -977,12 +993,19 @@ xtm_status xtm_autotune(xtm_lattice L, xtm_batch B, xtm_particles P, const int64
     xtm_status st = make_scratch(P, &sc);
     if (st != XTM_OK) return st;
     std::vector<int32_t> variants;
-    if (!B && lat->n_el > 0) {
+    if (lat->n_el > 0) {
+      std::vector<const std::vector<uint64_t>*> tabs;
+      if (B)
+        for (const xtm_lattice_s* l : B->lats) tabs.push_back(&l->fwd_h);
       for (int32_t k = 0; k < kLineStyles; ++k) {
-        LineKernel& lk = lat->fwd_line[k];
+        if (B && line_block(k) != 64) continue;  // batches: the one-wave forms
+        LineKernel& lk = B ? B->line[k] : lat->fwd_line[k];
         if (!lk.tried) {
           lk.tried = true;
-          build_line_kernel(lat->fwd_h, lat->n_el, k, &lk);
+          if (B)
+            build_line_kernel_multi(tabs, lat->n_el, k, true, &lk);
+          else
+            build_line_kernel(lat->fwd_h, lat->n_el, k, &lk);
         }
         if (lk.ok) variants.push_back(5 + k);
       }
@@ -1033,6 +1056,7 @@ xtm_status xtm_autotune(xtm_lattice L, xtm_batch B, xtm_particles P, const int64
     hipEventDestroy(e1);
     if (st != XTM_OK) return st;
     if (B) {
+      B->plan_variant = best.variant;
       B->plan_block = best.block;
     } else {
       L->plan_variant = best.variant;

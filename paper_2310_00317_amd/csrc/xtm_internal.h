@@ -111,9 +111,13 @@ struct LineKernel {
   bool ok = false;
   bool tried = false;
   int32_t style = 0;
+  bool batched = false;  // variants of one cell structure, parameters per variant
+  int32_t nv = 1;        // variants (batched)
+  int64_t stride = 0;    // parameter words per variant
   hipFunction_t fn = nullptr;
   int32_t period = 0, n_cells = 0, n_kinds = 0;  // period = length of the repeating unit
   double* prm_d = nullptr;     // element parameters in element order, no headers
+                               // (batched: one such block per variant)
   int32_t* cells_d = nullptr;  // per cell: kind, first parameter word, first element, words
   std::string source;
   std::string error;
@@ -129,10 +133,19 @@ inline int32_t line_fetch(int32_t style) { return (style >> 1) < 2 ? (style >> 1
 inline bool line_deferred(int32_t style) { return (style >> 1) == 3; }
 bool build_line_kernel(const std::vector<uint64_t>& tab, int32_t n_el, int32_t style,
                        LineKernel* k);
+// The same for a batch of lattice variants (batched = true: the kernel takes
+// the slot partition and reads each variant's parameters); fails if the
+// variants' element structures differ.
+bool build_line_kernel_multi(const std::vector<const std::vector<uint64_t>*>& tabs, int32_t n_el,
+                             int32_t style, bool batched, LineKernel* k);
 void free_line_kernel(LineKernel* k);
 hipError_t launch_line(const LineKernel& k, int32_t n_el, SoA P, const int32_t* idx,
                        const int32_t* ctrl, int64_t grid_upper, int32_t block, int32_t n_turns,
                        int32_t backward, KernelRef r, hipStream_t s);
+hipError_t launch_line_batched(const LineKernel& k, int32_t n_el, SoA P, const int32_t* idx,
+                               const int32_t* ctrl, int64_t grid_upper, int32_t n_turns,
+                               int32_t backward, KernelRef r, const int32_t* first_slot,
+                               hipStream_t s);
 
 }  // namespace xtm
 

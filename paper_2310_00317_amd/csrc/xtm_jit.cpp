@@ -210,7 +210,7 @@ int32_t kind_words(const std::vector<uint32_t>& k) {
 // memory and writes it to the other slot before the cell barrier.  Element
 // code then reads its parameters as broadcast LDS reads at compile-time
 // offsets.
-std::string generate(const Decomp& d, int32_t style) {
+std::string generate(const Decomp& d, int32_t style, bool batched) {
   int32_t maxw = 1;
   for (const auto& k : d.kinds) maxw = std::max(maxw, kind_words(k));
   // the lanes of a workgroup share one LDS slot pair, filled by all of them
@@ -276,19 +276,47 @@ std::string generate(const Decomp& d, int32_t style) {
        "#define LANES " << lanes << "\n"
        << replay_tables <<
        "extern \"C\" __global__ void __launch_bounds__(" << lanes << ")\n"
-       "xtm_line(const double* __restrict__ prm, const int* __restrict__ cells, int n_cells,\n"
+       "xtm_line(const double* __restrict__ " << (batched ? "prm_all" : "prm")
+    << ", const int* __restrict__ cells, int n_cells,\n"
        "         int n_el, SoA P, const int* __restrict__ idx, const int* __restrict__ ctrl,\n"
-       "         int n_turns, int backward, KRef r) {\n";
+       "         int n_turns, int backward, KRef r"
+    << (batched ? ",\n         const int* __restrict__ first_slot, int nv, long long prm_stride"
+                : "")
+    << ") {\n";
   s << "  __shared__ double slot[2 * MAXW];\n"
        "  const int lane = threadIdx.x;\n";
   s << "  const int t0 = ctrl[1];\n"
        "  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;\n"
        "  const bool in_range = i < ctrl[0];\n"
-       "  const int pi = in_range ? idx[i] : 0;\n"
-       "  const bool tracked = in_range && P.state[pi] == 1;\n"
-       "  int code = tracked ? 0 : 1;\n"
+       "  const int pi = in_range ? idx[i] : 0;\n";
+  // a batch of lattice variants with one cell structure: each slot belongs
+  // to the variant whose slot range holds it; the wave makes one pass per
+  // variant among its lanes (smallest first), reading that variant's
+  // parameters, with the lanes of the other variants idle
+  const std::string exit_stmt = batched ? "break;" : "return;";
+  if (batched)
+    s << "  const bool tracked0 = in_range && P.state[pi] == 1;\n"
+         "  int v = 0x7fffffff;\n"
+         "  if (tracked0) {\n"
+         "    int lo = 0, hi = nv;\n"
+         "    while (hi - lo > 1) { const int mid = (lo + hi) >> 1; "
+         "if (first_slot[mid] <= pi) lo = mid; else hi = mid; }\n"
+         "    v = lo;\n"
+         "  }\n"
+         "  bool pending = tracked0;\n"
+         "  while (__any(pending)) {\n"
+         "  int m_ = pending ? v : 0x7fffffff;\n"
+         "  for (int o_ = 32; o_ > 0; o_ >>= 1) m_ = min(m_, __shfl_xor(m_, o_, 64));\n"
+         "  const int vu = __builtin_amdgcn_readfirstlane(m_);\n"
+         "  const bool tracked = pending && v == vu;\n"
+         "  pending = pending && !tracked;\n"
+         "  const double* __restrict__ prm = prm_all + (long long)vu * prm_stride;\n"
+         "  do {\n";
+  else
+    s << "  const bool tracked = in_range && P.state[pi] == 1;\n";
+  s << "  int code = tracked ? 0 : 1;\n"
        "  int st = 1;\n";
-  s << "  if (__syncthreads_and(code != 0)) return;\n";
+  s << "  if (__syncthreads_and(code != 0)) " << exit_stmt << "\n";
   s << "  xtmm::Pt q;\n"
        "  q.x = P.x[pi]; q.px = P.px[pi]; q.y = P.y[pi]; q.py = P.py[pi]; q.zeta = P.zeta[pi];\n"
        "  q.delta = P.delta[pi]; q.ptau = P.ptau[pi]; q.rpp = P.rpp[pi]; q.rvv = P.rvv[pi];\n"
@@ -400,7 +428,7 @@ std::string generate(const Decomp& d, int32_t style) {
   s << "    }\n";
   s << "    if (__syncthreads_and(code != 0)) break;\n";
   s << "  }\n"
-       "  if (!tracked) return;\n"
+       "  if (!tracked) " << exit_stmt << "\n"
        "  if (code == 0) {\n"
        "    P.x[pi] = q.x; P.px[pi] = q.px; P.y[pi] = q.y; P.py[pi] = q.py; P.zeta[pi] = q.zeta;\n"
        "    P.delta[pi] = q.delta; P.ptau[pi] = q.ptau; P.rpp[pi] = q.rpp; P.rvv[pi] = q.rvv;\n"
@@ -411,8 +439,11 @@ std::string generate(const Decomp& d, int32_t style) {
        "    P.state[pi] = st;\n"
        "    P.at_element[pi] = backward ? n_el - 1 - el : el;\n"
        "    P.at_turn[pi] = backward ? t0 - 1 - tl : t0 + tl;\n"
-       "  }\n"
-       "}\n";
+       "  }\n";
+  if (batched)
+    s << "  } while (0);\n"
+         "  }\n";
+  s << "}\n";
   return s.str();
 }
 
@@ -456,24 +487,56 @@ Compiled compile(const std::string& src) {
 
 }  // namespace
 
-bool build_line_kernel(const std::vector<uint64_t>& tab, int32_t n_el, int32_t style,
-                       LineKernel* k) {
-  std::vector<uint32_t> sig;
-  std::vector<int32_t> word_of;  // parameter-array offset of each element
-  std::vector<double> prm;
-  sig.reserve(n_el);
+namespace {
+// Signature, parameter-word position and parameter words of each element of
+// a host element table.
+void split_table(const std::vector<uint64_t>& tab, int32_t n_el, std::vector<uint32_t>* sig,
+                 std::vector<int32_t>* word_of, std::vector<double>* prm) {
   size_t off = 0;
   for (int32_t e = 0; e < n_el; ++e) {
     const uint64_t h = tab[off];
     const uint32_t nw = (uint32_t)((h >> 16) & 0xffffu);
-    sig.push_back(sig_of(h));
-    word_of.push_back((int32_t)prm.size());
+    sig->push_back(sig_of(h));
+    word_of->push_back((int32_t)prm->size());
     for (uint32_t w = 0; w < nw; ++w) {
       double d;
       std::memcpy(&d, &tab[off + 1 + w], 8);
-      prm.push_back(d);
+      prm->push_back(d);
     }
     off += 1 + nw;
+  }
+}
+}  // namespace
+
+bool build_line_kernel(const std::vector<uint64_t>& tab, int32_t n_el, int32_t style,
+                       LineKernel* k) {
+  return build_line_kernel_multi({&tab}, n_el, style, false, k);
+}
+
+bool build_line_kernel_multi(const std::vector<const std::vector<uint64_t>*>& tabs, int32_t n_el,
+                             int32_t style, bool batched, LineKernel* k) {
+  std::vector<uint32_t> sig;
+  std::vector<int32_t> word_of;  // parameter-array offset of each element
+  std::vector<double> prm;
+  sig.reserve(n_el);
+  split_table(*tabs[0], n_el, &sig, &word_of, &prm);
+  if (prm.empty()) prm.push_back(0.0);
+  const size_t stride = prm.size();
+  for (size_t v = 1; v < tabs.size(); ++v) {
+    std::vector<uint32_t> sv;
+    std::vector<int32_t> wv;
+    std::vector<double> pv;
+    split_table(*tabs[v], n_el, &sv, &wv, &pv);
+    if (pv.empty()) pv.push_back(0.0);
+    if (sv != sig || pv.size() != stride) {
+      k->error = "lattice variant " + std::to_string(v) + " differs in element structure";
+      return false;
+    }
+    prm.insert(prm.end(), pv.begin(), pv.end());
+  }
+  if (batched && line_block(style) != 64) {
+    k->error = "batched per-line kernels use one-wave workgroups";
+    return false;
   }
   Decomp d;
   if (!decompose(sig, &d)) {
@@ -481,7 +544,10 @@ bool build_line_kernel(const std::vector<uint64_t>& tab, int32_t n_el, int32_t s
     return false;
   }
   k->style = style;
-  k->source = generate(d, style);
+  k->batched = batched;
+  k->nv = (int32_t)tabs.size();
+  k->stride = (int64_t)stride;
+  k->source = generate(d, style, batched);
   {
     std::lock_guard<std::mutex> lock(g_mu);
     auto it = g_cache.find(k->source);
@@ -502,7 +568,6 @@ bool build_line_kernel(const std::vector<uint64_t>& tab, int32_t n_el, int32_t s
   k->period = (int32_t)d.kinds[0].size();
   k->n_cells = (int32_t)d.cell_kind.size();
   k->n_kinds = (int32_t)d.kinds.size();
-  if (prm.empty()) prm.push_back(0.0);
   if (hipMalloc(&k->prm_d, prm.size() * sizeof(double)) != hipSuccess ||
       hipMalloc(&k->cells_d, cells.size() * sizeof(int32_t)) != hipSuccess ||
       hipMemcpy(k->prm_d, prm.data(), prm.size() * sizeof(double), hipMemcpyHostToDevice) !=
@@ -537,6 +602,24 @@ hipError_t launch_line(const LineKernel& k, int32_t n_el, SoA P, const int32_t* 
   // the generated kernel stages each cell's parameters with the stride of
   // its style's fixed workgroup size (line_block)
   (void)block;
+  const int32_t wg = line_block(k.style);
+  const unsigned grid = (unsigned)((grid_upper + wg - 1) / wg);
+  return hipModuleLaunchKernel(k.fn, grid, 1, 1, (unsigned)wg, 1, 1, 0, s, args, nullptr);
+}
+
+hipError_t launch_line_batched(const LineKernel& k, int32_t n_el, SoA P, const int32_t* idx,
+                               const int32_t* ctrl, int64_t grid_upper, int32_t n_turns,
+                               int32_t backward, KernelRef r, const int32_t* first_slot,
+                               hipStream_t s) {
+  if (grid_upper <= 0 || n_turns <= 0) return hipSuccess;
+  if (!k.batched) return hipErrorInvalidValue;
+  const double* prm = k.prm_d;
+  const int32_t* cells = k.cells_d;
+  int32_t n_cells = k.n_cells, nv = k.nv;
+  long long stride = (long long)k.stride;
+  void* args[] = {(void*)&prm,  (void*)&cells, (void*)&n_cells, (void*)&n_el,
+                  (void*)&P,    (void*)&idx,   (void*)&ctrl,    (void*)&n_turns,
+                  (void*)&backward, (void*)&r, (void*)&first_slot, (void*)&nv, (void*)&stride};
   const int32_t wg = line_block(k.style);
   const unsigned grid = (unsigned)((grid_upper + wg - 1) / wg);
   return hipModuleLaunchKernel(k.fn, grid, 1, 1, (unsigned)wg, 1, 1, 0, s, args, nullptr);

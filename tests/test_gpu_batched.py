@@ -37,8 +37,14 @@ def _variants(counts):
     return lats, coords
 
 
-@pytest.mark.parametrize("chunk,graph", [(64, False), (0, False), (50, True)])
-def test_batched_equals_separate(P, chunk, graph):
+@pytest.mark.parametrize("chunk,graph,variant", [(64, False, 4), (0, False, 4), (50, True, 4),
+                                               (0, False, 0), (64, False, 6), (0, False, 8),
+                                               (50, True, 10), (0, False, 12), (7, False, 10)])
+def test_batched_equals_separate(P, chunk, graph, variant):
+    """Every batched kernel (the interpreter, and the one-wave per-line forms
+    reading each variant's parameters) gives bit for bit what tracking each
+    variant alone gives; the slot ranges are uneven, one is empty, and waves
+    straddle variant boundaries."""
     counts = [37, 300, 0, 129, 64]
     els, coords = _variants(counts)
     first = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
@@ -46,7 +52,10 @@ def test_batched_equals_separate(P, chunk, graph):
     batch = P.Batch(lats)
     allc = np.concatenate(coords)
     big = P.Particles(len(allc), REF).init(allc)
-    P.track_batched(batch, big, first, 300, turns_per_chunk=chunk, graph=graph)
+    st = P.track_batched(batch, big, first, 300, turns_per_chunk=chunk, graph=graph,
+                         variant=variant, full_stats=not graph)
+    if not graph:
+        assert st.variant == (10 if variant == 0 else variant)
     g = big.to_numpy()
     n_lost = 0
     for v, n in enumerate(counts):
@@ -123,5 +132,33 @@ def test_autotune_batch(P):
     batch = P.Batch([P.Lattice(e, REF) for e in els])
     big = P.Particles(700, REF).init(np.concatenate(coords))
     plan = P.autotune(big, batch=batch, first_slot=first, probe_turns=2)
-    assert plan.variant == 4 and plan.block in (64, 128, 256)
+    assert plan.variant in (4, 6, 8, 10, 12) and plan.block in (64, 128, 256)
     assert big.turn == 0
+
+
+def test_batch_of_different_structures_uses_the_interpreter(P):
+    """Variants whose element structures differ (one multipole of another
+    order) cannot share a per-line kernel: the default falls back to the
+    interpreter, with the same results as separate tracking; asking for a
+    per-line form is an error."""
+    el_a = I.cfg1_lattice()
+    el_b = el_a.copy()
+    k = int(np.nonzero(el_b["type"] == I.MULTIPOLE)[0][3])
+    el_b["order"][k] = 3
+    lats = [P.Lattice(el_a, REF), P.Lattice(el_b, REF)]
+    c = I.gaussian_particles(200, 5)
+    first = np.array([0, 100, 200], dtype=np.int64)
+    big = P.Particles(200, REF).init(c)
+    st = P.track_batched(P.Batch(lats), big, first, 50, full_stats=True)
+    assert st.variant == 4
+    g = big.to_numpy()
+    for v in range(2):
+        one = P.Particles(100, REF).init(c[100 * v:100 * (v + 1)], first_id=100 * v)
+        P.track(lats[v], one, 50, variant=4)
+        o = one.to_numpy()
+        for f in FIELDS:
+            assert np.array_equal(g[f][100 * v:100 * (v + 1)], o[f], equal_nan=True), (v, f)
+    big2 = P.Particles(200, REF).init(c)
+    with pytest.raises(P.XtmError) as ei:
+        P.track_batched(P.Batch(lats), big2, first, 5, variant=10)
+    assert ei.value.code == -6
