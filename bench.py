@@ -30,6 +30,8 @@ for _s in range(8):
         "one-wave" if _s & 1 else "256-lane",
         ("read at use", "grouped per element", "fetched one element ahead",
          "fetched one element ahead, one loss test per cell")[_s >> 1])
+KERNEL_NAMES[13] = ("xtm_line (per-line generated kernel, one-wave workgroups, parameters "
+                    "fetched one element ahead, two particles per lane)")
 
 # HBM bytes per tracking-kernel launch over the timed region, from one
 # FETCH_SIZE and one WRITE_SIZE counter pass of this benchmark, each scaled by

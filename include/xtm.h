@@ -183,7 +183,9 @@ typedef struct xtm_track_opts {
                               with one loss test per cell instead of a store at
                               every loss test (lanes lost in a cell re-apply the
                               cell's maps from its entry to find the coordinates
-                              to store).
+                              to store).  Variant 13: as 10 with two particles
+                              per lane (slots i and i + 64 of a workgroup's
+                              range), their maps interleaved.
                               XTM_E_UNSUPPORTED if it cannot be built */
   int32_t radiation;       /* synchrotron radiation in multipoles with length > 0:
                               0 off, 1 mean energy loss, 2 mean + quantum excitation
@@ -270,7 +272,7 @@ xtm_status xtm_philox4x32_10(uint64_t seed, const uint32_t ctr0[4], int64_t n_bl
    each variant's particles through its lattice alone, bit for bit.  Forward
    only.  Kernels: when every variant has the same element structure (types
    and orders, element by element; only parameter values differ, as for
-   error seeds) the one-wave per-line forms (6, 8, 10, 12; the default is 10):
+   error seeds) the one-wave per-line forms (6, 8, 10, 12, 13; the default is 10):
    one generated kernel holds every variant's parameters and a wave whose
    lanes span several variants makes one pass per variant; otherwise, or with
    variant 4, the register-loss interpreter.  The options and statistics are

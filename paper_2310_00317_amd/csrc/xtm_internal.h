@@ -123,14 +123,27 @@ struct LineKernel {
   std::string error;
 };
 // Generated-kernel forms ("styles"), all computing the same maps in the same
-// order: bit 0 selects the workgroup (0: 256 lanes, 1: one wave), the rest the
-// way element code reads its parameters from the LDS slot (line_fetch) and
-// where a lost particle's coordinates are stored (line_deferred).
-constexpr int32_t kLineStyles = 8;
-inline int32_t line_block(int32_t style) { return (style & 1) ? 64 : kLineBlock; }
-inline int32_t line_fetch(int32_t style) { return (style >> 1) < 2 ? (style >> 1) : 2; }
-// styles 6 and 7: fetch 2 with loss handling deferred to one test per cell
-inline bool line_deferred(int32_t style) { return (style >> 1) == 3; }
+// order: the workgroup (256 lanes or one wave), the way element code reads
+// its parameters from the LDS slot (line_fetch), where a lost particle's
+// coordinates are stored (line_deferred) and how many particles each lane
+// carries (line_ppt).  Kernel variant 5 + style.
+struct LineStyle {
+  int32_t lanes, fetch;
+  bool deferred;
+  int32_t ppt;
+};
+constexpr LineStyle kLineStyle[] = {
+    {256, 0, false, 1}, {64, 0, false, 1},  // 5, 6: parameters read at each use
+    {256, 1, false, 1}, {64, 1, false, 1},  // 7, 8: an element's words in one group
+    {256, 2, false, 1}, {64, 2, false, 1},  // 9, 10: the next element's group ahead
+    {256, 2, true, 1},  {64, 2, true, 1},   // 11, 12: as 9, 10, one loss test per cell
+    {64, 2, false, 2},                      // 13: as 10, two particles per lane
+};
+constexpr int32_t kLineStyles = (int32_t)(sizeof(kLineStyle) / sizeof(kLineStyle[0]));
+inline int32_t line_block(int32_t style) { return kLineStyle[style].lanes; }
+inline int32_t line_fetch(int32_t style) { return kLineStyle[style].fetch; }
+inline bool line_deferred(int32_t style) { return kLineStyle[style].deferred; }
+inline int32_t line_ppt(int32_t style) { return kLineStyle[style].ppt; }
 bool build_line_kernel(const std::vector<uint64_t>& tab, int32_t n_el, int32_t style,
                        LineKernel* k);
 // The same for a batch of lattice variants (batched = true: the kernel takes

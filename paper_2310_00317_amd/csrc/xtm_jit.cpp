@@ -226,6 +226,8 @@ std::string generate(const Decomp& d, int32_t style, bool batched) {
   // per cell (line_deferred: the tests only record the loss code; lanes lost
   // in the cell replay it afterwards)
   const bool deferred = line_deferred(style);
+  // particles per lane (line_ppt): one, or two whose maps interleave
+  const int32_t ppt = line_ppt(style);
   std::vector<uint32_t> sigs;  // distinct element signatures of the line
   std::string replay_tables;   // per kind: first entry; per entry: signature, offset
   if (deferred) {
@@ -274,6 +276,7 @@ std::string generate(const Decomp& d, int32_t style, bool batched) {
        "#define MAXW " << maxw << "\n"
        "#define PER_THREAD " << per_thread << "\n"
        "#define LANES " << lanes << "\n"
+       "#define PPT " << ppt << "\n"
        << replay_tables <<
        "extern \"C\" __global__ void __launch_bounds__(" << lanes << ")\n"
        "xtm_line(const double* __restrict__ " << (batched ? "prm_all" : "prm")
@@ -285,59 +288,128 @@ std::string generate(const Decomp& d, int32_t style, bool batched) {
     << ") {\n";
   s << "  __shared__ double slot[2 * MAXW];\n"
        "  const int lane = threadIdx.x;\n";
-  s << "  const int t0 = ctrl[1];\n"
-       "  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;\n"
-       "  const bool in_range = i < ctrl[0];\n"
-       "  const int pi = in_range ? idx[i] : 0;\n";
   // a batch of lattice variants with one cell structure: each slot belongs
   // to the variant whose slot range holds it; the wave makes one pass per
   // variant among its lanes (smallest first), reading that variant's
   // parameters, with the lanes of the other variants idle
   const std::string exit_stmt = batched ? "break;" : "return;";
-  if (batched)
-    s << "  const bool tracked0 = in_range && P.state[pi] == 1;\n"
-         "  int v = 0x7fffffff;\n"
-         "  if (tracked0) {\n"
-         "    int lo = 0, hi = nv;\n"
-         "    while (hi - lo > 1) { const int mid = (lo + hi) >> 1; "
-         "if (first_slot[mid] <= pi) lo = mid; else hi = mid; }\n"
-         "    v = lo;\n"
+  if (ppt == 1) {
+    s << "  const int t0 = ctrl[1];\n"
+         "  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;\n"
+         "  const bool in_range = i < ctrl[0];\n"
+         "  const int pi = in_range ? idx[i] : 0;\n";
+    if (batched)
+      s << "  const bool tracked0 = in_range && P.state[pi] == 1;\n"
+           "  int v = 0x7fffffff;\n"
+           "  if (tracked0) {\n"
+           "    int lo = 0, hi = nv;\n"
+           "    while (hi - lo > 1) { const int mid = (lo + hi) >> 1; "
+           "if (first_slot[mid] <= pi) lo = mid; else hi = mid; }\n"
+           "    v = lo;\n"
+           "  }\n"
+           "  bool pending = tracked0;\n"
+           "  while (__any(pending)) {\n"
+           "  int m_ = pending ? v : 0x7fffffff;\n"
+           "  for (int o_ = 32; o_ > 0; o_ >>= 1) m_ = min(m_, __shfl_xor(m_, o_, 64));\n"
+           "  const int vu = __builtin_amdgcn_readfirstlane(m_);\n"
+           "  const bool tracked = pending && v == vu;\n"
+           "  pending = pending && !tracked;\n"
+           "  const double* __restrict__ prm = prm_all + (long long)vu * prm_stride;\n"
+           "  do {\n";
+    else
+      s << "  const bool tracked = in_range && P.state[pi] == 1;\n";
+    s << "  int code = tracked ? 0 : 1;\n"
+         "  int st = 1;\n";
+    s << "  if (__syncthreads_and(code != 0)) " << exit_stmt << "\n";
+    s << "  xtmm::Pt q;\n"
+         "  q.x = P.x[pi]; q.px = P.px[pi]; q.y = P.y[pi]; q.py = P.py[pi]; q.zeta = P.zeta[pi];\n"
+         "  q.delta = P.delta[pi]; q.ptau = P.ptau[pi]; q.rpp = P.rpp[pi]; q.rvv = P.rvv[pi];\n"
+         "  const double beta0 = r.beta0, two_over_beta0 = r.two_over_beta0;\n"
+         "  const long long pid = P.pid[pi];\n"
+         "  xtmm::refresh(q, beta0);\n";
+  } else {
+    // two particles per lane: slots i0 and i0 + LANES of the workgroup's range
+    s << "  const int t0 = ctrl[1];\n"
+         "  const long long i0 = (long long)blockIdx.x * (PPT * LANES) + threadIdx.x;\n"
+         "  bool in_range_[PPT];\n"
+         "  int pi_[PPT];\n"
+         "#pragma unroll\n"
+         "  for (int k_ = 0; k_ < PPT; ++k_) {\n"
+         "    in_range_[k_] = i0 + k_ * LANES < ctrl[0];\n"
+         "    pi_[k_] = in_range_[k_] ? idx[i0 + k_ * LANES] : 0;\n"
          "  }\n"
-         "  bool pending = tracked0;\n"
-         "  while (__any(pending)) {\n"
-         "  int m_ = pending ? v : 0x7fffffff;\n"
-         "  for (int o_ = 32; o_ > 0; o_ >>= 1) m_ = min(m_, __shfl_xor(m_, o_, 64));\n"
-         "  const int vu = __builtin_amdgcn_readfirstlane(m_);\n"
-         "  const bool tracked = pending && v == vu;\n"
-         "  pending = pending && !tracked;\n"
-         "  const double* __restrict__ prm = prm_all + (long long)vu * prm_stride;\n"
-         "  do {\n";
-  else
-    s << "  const bool tracked = in_range && P.state[pi] == 1;\n";
-  s << "  int code = tracked ? 0 : 1;\n"
-       "  int st = 1;\n";
-  s << "  if (__syncthreads_and(code != 0)) " << exit_stmt << "\n";
-  s << "  xtmm::Pt q;\n"
-       "  q.x = P.x[pi]; q.px = P.px[pi]; q.y = P.y[pi]; q.py = P.py[pi]; q.zeta = P.zeta[pi];\n"
-       "  q.delta = P.delta[pi]; q.ptau = P.ptau[pi]; q.rpp = P.rpp[pi]; q.rvv = P.rvv[pi];\n"
-       "  const double beta0 = r.beta0, two_over_beta0 = r.two_over_beta0;\n"
-       "  const long long pid = P.pid[pi];\n"
-       "  xtmm::refresh(q, beta0);\n"
-       "  {\n"
+         "  bool tracked_[PPT];\n";
+    if (batched)
+      s << "  int v_[PPT];\n"
+           "  bool pending_[PPT];\n"
+           "#pragma unroll\n"
+           "  for (int k_ = 0; k_ < PPT; ++k_) {\n"
+           "    const int pi = pi_[k_];\n"
+           "    pending_[k_] = in_range_[k_] && P.state[pi] == 1;\n"
+           "    v_[k_] = 0x7fffffff;\n"
+           "    if (pending_[k_]) {\n"
+           "      int lo = 0, hi = nv;\n"
+           "      while (hi - lo > 1) { const int mid = (lo + hi) >> 1; "
+           "if (first_slot[mid] <= pi) lo = mid; else hi = mid; }\n"
+           "      v_[k_] = lo;\n"
+           "    }\n"
+           "  }\n"
+           "  while (__any(pending_[0] || pending_[1])) {\n"
+           "  int m_ = min(pending_[0] ? v_[0] : 0x7fffffff, pending_[1] ? v_[1] : 0x7fffffff);\n"
+           "  for (int o_ = 32; o_ > 0; o_ >>= 1) m_ = min(m_, __shfl_xor(m_, o_, 64));\n"
+           "  const int vu = __builtin_amdgcn_readfirstlane(m_);\n"
+           "#pragma unroll\n"
+           "  for (int k_ = 0; k_ < PPT; ++k_) {\n"
+           "    tracked_[k_] = pending_[k_] && v_[k_] == vu;\n"
+           "    pending_[k_] = pending_[k_] && !tracked_[k_];\n"
+           "  }\n"
+           "  const double* __restrict__ prm = prm_all + (long long)vu * prm_stride;\n"
+           "  do {\n";
+    else
+      s << "#pragma unroll\n"
+           "  for (int k_ = 0; k_ < PPT; ++k_) tracked_[k_] = in_range_[k_] && P.state[pi_[k_]] == 1;\n";
+    s << "  int code_[PPT], st_[PPT];\n"
+         "#pragma unroll\n"
+         "  for (int k_ = 0; k_ < PPT; ++k_) { code_[k_] = tracked_[k_] ? 0 : 1; st_[k_] = 1; }\n"
+         "  if (__syncthreads_and(code_[0] != 0 && code_[1] != 0)) " << exit_stmt << "\n"
+         "  const double beta0 = r.beta0, two_over_beta0 = r.two_over_beta0;\n"
+         "  xtmm::Pt q_[PPT];\n"
+         "  long long pid_[PPT];\n"
+         "#pragma unroll\n"
+         "  for (int k_ = 0; k_ < PPT; ++k_) {\n"
+         "    xtmm::Pt& q = q_[k_];\n"
+         "    const int pi = pi_[k_];\n"
+         "    q.x = P.x[pi]; q.px = P.px[pi]; q.y = P.y[pi]; q.py = P.py[pi]; q.zeta = P.zeta[pi];\n"
+         "    q.delta = P.delta[pi]; q.ptau = P.ptau[pi]; q.rpp = P.rpp[pi]; q.rvv = P.rvv[pi];\n"
+         "    pid_[k_] = P.pid[pi];\n"
+         "    xtmm::refresh(q, beta0);\n"
+         "  }\n";
+  }
+  s <<        "  {\n"
        "    const int off0 = cells[1], nw0 = cells[3];\n"
        "    for (int w = lane; w < nw0; w += LANES) slot[w] = prm[off0 + w];\n"
        "  }\n";
   s << "  __syncthreads();\n";
   s << "  int b = 0;\n"
        "  for (int t = 0; t < n_turns; ++t) {\n"
-       "    const int enc_t = t * n_el + 1;\n"
+       "    const int enc_t = t * n_el + 1;\n";
+  const std::string rec_body =
        "    if (r.rec && t0 + t < r.rec_turns && code == 0) {\n"
        "      const unsigned long long base = (unsigned long long)(t0 + t) * 4 * r.rec_n + pi;\n"
        "      r.rec[base] = (float)q.x;\n"
        "      r.rec[base + r.rec_n] = (float)q.px;\n"
        "      r.rec[base + 2ull * r.rec_n] = (float)q.y;\n"
        "      r.rec[base + 3ull * r.rec_n] = (float)q.py;\n"
-       "    }\n"
+       "    }\n";
+  if (ppt == 1)
+    s << rec_body;
+  else
+    s << "#pragma unroll\n"
+         "    for (int k_ = 0; k_ < PPT; ++k_) {\n"
+         "    const xtmm::Pt& q = q_[k_];\n"
+         "    const int pi = pi_[k_], code = code_[k_];\n"
+      << rec_body << "    }\n";
+  s <<
        "    for (int c = 0; c < n_cells; ++c) {\n"
        "      const int cn = (c + 1 == n_cells) ? 0 : c + 1;\n"
        "      const int offn = cells[4 * cn + 1], nwn = cells[4 * cn + 3];\n"
@@ -390,7 +462,18 @@ std::string generate(const Decomp& d, int32_t style, bool batched) {
       if (fetch != 0 && n_words(kd[j]) > 0) arr = "w" + std::to_string(j);
       const std::string stmt =
           emit(kd[j], arr, std::to_string(j), far_rf, deferred ? kMarkOnly : kSaveAtLoss);
-      if (!stmt.empty()) s << "        " << stmt << "\n";
+      if (stmt.empty()) continue;
+      if (ppt == 1) {
+        s << "        " << stmt << "\n";
+      } else {
+        // the same element for each particle of the lane, through references
+        // that give each copy the one-particle names
+        for (int32_t k = 0; k < ppt; ++k)
+          s << "        { xtmm::Pt& q = q_[" << k << "]; int& code = code_[" << k
+            << "]; int& st = st_[" << k << "]; const int pi = pi_[" << k
+            << "]; const long long pid = pid_[" << k << "]; (void)pid; (void)pi; " << stmt
+            << " }\n";
+      }
     }
     s << "      }\n";
   }
@@ -426,9 +509,11 @@ std::string generate(const Decomp& d, int32_t style, bool batched) {
        "      b ^= 1;\n";
   s << "      __syncthreads();\n";
   s << "    }\n";
-  s << "    if (__syncthreads_and(code != 0)) break;\n";
-  s << "  }\n"
-       "  if (!tracked) " << exit_stmt << "\n"
+  if (ppt == 1)
+    s << "    if (__syncthreads_and(code != 0)) break;\n";
+  else
+    s << "    if (__syncthreads_and(code_[0] != 0 && code_[1] != 0)) break;\n";
+  const std::string store_body =
        "  if (code == 0) {\n"
        "    P.x[pi] = q.x; P.px[pi] = q.px; P.y[pi] = q.y; P.py[pi] = q.py; P.zeta[pi] = q.zeta;\n"
        "    P.delta[pi] = q.delta; P.ptau[pi] = q.ptau; P.rpp[pi] = q.rpp; P.rvv[pi] = q.rvv;\n"
@@ -440,6 +525,16 @@ std::string generate(const Decomp& d, int32_t style, bool batched) {
        "    P.at_element[pi] = backward ? n_el - 1 - el : el;\n"
        "    P.at_turn[pi] = backward ? t0 - 1 - tl : t0 + tl;\n"
        "  }\n";
+  s << "  }\n";
+  if (ppt == 1)
+    s << "  if (!tracked) " << exit_stmt << "\n" << store_body;
+  else
+    s << "#pragma unroll\n"
+         "  for (int k_ = 0; k_ < PPT; ++k_) {\n"
+         "  if (!tracked_[k_]) continue;\n"
+         "  const xtmm::Pt& q = q_[k_];\n"
+         "  const int pi = pi_[k_], code = code_[k_], st = st_[k_];\n"
+      << store_body << "  }\n";
   if (batched)
     s << "  } while (0);\n"
          "  }\n";
@@ -603,7 +698,8 @@ hipError_t launch_line(const LineKernel& k, int32_t n_el, SoA P, const int32_t* 
   // its style's fixed workgroup size (line_block)
   (void)block;
   const int32_t wg = line_block(k.style);
-  const unsigned grid = (unsigned)((grid_upper + wg - 1) / wg);
+  const int64_t per_wg = (int64_t)wg * line_ppt(k.style);  // particles per workgroup
+  const unsigned grid = (unsigned)((grid_upper + per_wg - 1) / per_wg);
   return hipModuleLaunchKernel(k.fn, grid, 1, 1, (unsigned)wg, 1, 1, 0, s, args, nullptr);
 }
 
@@ -621,7 +717,8 @@ hipError_t launch_line_batched(const LineKernel& k, int32_t n_el, SoA P, const i
                   (void*)&P,    (void*)&idx,   (void*)&ctrl,    (void*)&n_turns,
                   (void*)&backward, (void*)&r, (void*)&first_slot, (void*)&nv, (void*)&stride};
   const int32_t wg = line_block(k.style);
-  const unsigned grid = (unsigned)((grid_upper + wg - 1) / wg);
+  const int64_t per_wg = (int64_t)wg * line_ppt(k.style);  // particles per workgroup
+  const unsigned grid = (unsigned)((grid_upper + per_wg - 1) / per_wg);
   return hipModuleLaunchKernel(k.fn, grid, 1, 1, (unsigned)wg, 1, 1, 0, s, args, nullptr);
 }
 

@@ -156,6 +156,8 @@ def test_resume_bitwise(P):
                                   dict(variant=10, turns_per_chunk=6, compact=False),
                                   dict(variant=11, turns_per_chunk=8),
                                   dict(variant=12), dict(variant=12, turns_per_chunk=3,
+                                                         compact=False),
+                                  dict(variant=13), dict(variant=13, turns_per_chunk=5,
                                                          compact=False)])
 def test_launch_shape_invariance(P, opts):
     banner(f"launch shape {opts}")
@@ -247,7 +249,7 @@ def test_cfg2_lattice_reduced(P, oracle_mod):
     assert gp == op
 
 
-@pytest.mark.parametrize("variant", [1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12])
+@pytest.mark.parametrize("variant", [1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13])
 def test_kernel_variants_on_multisegment_lattice(P, variant):
     """The 20,000-element lattice spans many LDS segments: every kernel variant
     must give bitwise the same result as the default one."""
@@ -294,11 +296,11 @@ def test_empty_lattice_counts_turns(P, oracle_mod):
 
 def test_variant_numbers(P):
     """Every per-line form is a kernel number; one past the last is refused."""
-    assert P.line_variants() == list(range(5, 13))
+    assert P.line_variants() == list(range(5, 14))
     lat = P.Lattice(I.cfg1_lattice(), REF)
     parts = P.Particles(8, REF).init(np.zeros((8, 6)))
     with pytest.raises(P.XtmError) as ei:
-        P.track(lat, parts, 1, variant=13)
+        P.track(lat, parts, 1, variant=14)
     assert ei.value.code == -1
 
 
@@ -339,7 +341,7 @@ def large_cell_lattice(seed=3, units=30):
     return I.line(els)
 
 
-@pytest.mark.parametrize("variant", [0, 4, 6, 7, 8, 9, 10, 11, 12])
+@pytest.mark.parametrize("variant", [0, 4, 6, 7, 8, 9, 10, 11, 12, 13])
 def test_line_kernel_with_multi_pass_staging(P, oracle_mod, variant):
     banner(f"large-cell lattice, variant {variant}")
     el = large_cell_lattice()

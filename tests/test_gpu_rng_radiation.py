@@ -71,7 +71,7 @@ def test_radiation_parity_small_ring(P, oracle_mod, mode):
     assert_bitwise(g, o)
 
 
-@pytest.mark.parametrize("variant", [0, 7, 9, 10, 11, 12])
+@pytest.mark.parametrize("variant", [0, 7, 9, 10, 11, 12, 13])
 def test_radiation_full_electron_ring_short(P, oracle_mod, variant):
     el = I.cfg5_lattice()
     c = I.cfg5_particles(256, seed=3)
@@ -90,7 +90,8 @@ def test_radiation_graph_and_chunks_invariant(P):
     for kw in (dict(turns_per_chunk=7, variant=4), dict(variant=5, turns_per_chunk=9),
                dict(variant=6, turns_per_chunk=5), dict(variant=7), dict(variant=8),
                dict(variant=9, turns_per_chunk=3), dict(variant=10, turns_per_chunk=11),
-               dict(variant=11, turns_per_chunk=6), dict(variant=12)):
+               dict(variant=11, turns_per_chunk=6), dict(variant=12),
+               dict(variant=13, turns_per_chunk=7)):
         b, pb, _, _, _ = gpu_run(P, el, EREF, c, 40, radiation=2, seed=1, **kw)
         assert pa == pb, kw
         for f in a:
