@@ -105,3 +105,34 @@ def test_radiation_argument_checks(P):
         with pytest.raises(P.XtmError) as ei:
             P.track(lat, parts, 1, **kw)
         assert ei.value.code == code
+
+
+@pytest.mark.parametrize("variant", [0, 4, 13])
+def test_batched_radiation_and_recorder_equal_separate(P, variant):
+    """Two variants of the small electron ring (the second with its bending
+    multipoles 1e-3 stronger: same structure, other values) tracked as one
+    batch with quantum excitation and the early-turn recorder on: states,
+    coordinates and records equal tracking each variant alone (the deviates
+    are keyed by particle id, turn and element, not by slot or variant)."""
+    import torch
+    el_a = _ring()
+    el_b = el_a.copy()
+    bends = el_b["hxl"] != 0
+    el_b["knl"][bends, 0] *= 1.001
+    lats = [P.Lattice(el_a, EREF), P.Lattice(el_b, EREF)]
+    c = I.gaussian_particles(300, 17, [3e-4, 3e-6, 3e-5, 3e-7, 3e-3, 1.5e-3])
+    first = np.array([0, 130, 300], dtype=np.int64)
+    big = P.Particles(300, EREF).init(c, first_id=500)
+    rec = torch.full((16, 4, 300), float("nan"), dtype=torch.float32, device="cuda")
+    P.track_batched(P.Batch(lats), big, first, 25, radiation=2, seed=77, record=rec,
+                    variant=variant)
+    g, gr = big.to_numpy(), rec.cpu().numpy()
+    for v in range(2):
+        a, b = int(first[v]), int(first[v + 1])
+        one = P.Particles(b - a, EREF).init(c[a:b], first_id=500 + a)
+        r1 = torch.full((16, 4, b - a), float("nan"), dtype=torch.float32, device="cuda")
+        P.track(lats[v], one, 25, radiation=2, seed=77, record=r1, variant=4)
+        o = one.to_numpy()
+        for f in o:
+            assert np.array_equal(g[f][a:b], o[f], equal_nan=True), (v, f)
+        assert np.array_equal(gr[:, :, a:b], r1.cpu().numpy(), equal_nan=True), v
