@@ -43,8 +43,8 @@ KERNEL_NAMES[13] = ("xtm_line (per-line generated kernel, one-wave workgroups, p
 TRAFFIC_SOURCES = ("xtm_jit.cpp", "xtm_maps.h")
 MEASURED_TRAFFIC = {
     # (workload, particles, turns per step, steps, kernel variant, source hash)
-    ("cfg2", 100000, 1000, 10, 10, "61888ecca968a6b7"):
-        (21431036.0, "profiles/xtm_line_cfg2_hbm_counters.txt"),
+    ("cfg2", 100000, 1000, 10, 10, "486fd14141e80fbc"):
+        (21431109.0, "profiles/xtm_line_cfg2_hbm_counters.txt"),
 }
 
 
