@@ -235,12 +235,12 @@ def main():
     ap.add_argument("--da-rays", type=int, default=500, help="cfg4: rays of the evaluation grid")
     ap.add_argument("--da-radii", type=int, default=2000, help="cfg4: radii per ray")
     ap.add_argument("--da-rmax", type=float, default=30.0, help="cfg4: grid edge [sigma]")
-    ap.add_argument("--train-particles", type=int, default=600000)
+    ap.add_argument("--train-particles", type=int, default=1200000)
     ap.add_argument("--horizon", type=int, default=100000, help="cfg4: turns")
-    ap.add_argument("--epochs", type=int, default=120)
+    ap.add_argument("--epochs", type=int, default=60)
     ap.add_argument("--tune-turns", type=int, default=0,
                     help="cfg4: autotuner probe turns before each long tracking stretch (0 = off)")
-    ap.add_argument("--max-false-rate", type=float, default=2e-3,
+    ap.add_argument("--max-false-rate", type=float, default=3e-3,
                     help="cfg4: held-out false-retire budget that fixes the threshold")
     ap.add_argument("--stages", type=int, default=1,
                     help="cfg4: retirement decisions at the end of this many 1024-turn windows")
