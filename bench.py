@@ -254,6 +254,8 @@ def main():
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--chunk", type=int, default=0)
     ap.add_argument("--variant", type=int, default=0)
+    ap.add_argument("--graph", action="store_true",
+                    help="replay each step's chunk sequence as a captured hipGraph")
     ap.add_argument("--per-element", action="store_true",
                     help="time the measurement baseline instead: one kernel launch per element "
                          "and turn, particle state through HBM at every element")
@@ -316,9 +318,9 @@ def main():
         if batched:
             return P.track_batched(batch, parts, first, turns, block=args.block,
                                    turns_per_chunk=args.chunk, variant=args.variant,
-                                   full_stats=True, **kw)
+                                   graph=args.graph, full_stats=True, **kw)
         return P.track(lat, parts, turns, block=args.block, turns_per_chunk=args.chunk,
-                       variant=args.variant, full_stats=True, **extra, **kw)
+                       variant=args.variant, graph=args.graph, full_stats=True, **extra, **kw)
 
     if args.warmup > 0:
         w = P.Particles(n, ref).init(coords_dev)
