@@ -13,9 +13,9 @@
 // explicit fma(); everything else is a correctly rounded IEEE operation, and
 // the library is built with -ffp-contract=off, so the operation order below
 // is the rounding contract:
-//   exact drift    pz = sqrt((1+d)^2 - px^2 - py^2), lp = L/pz,
+//   exact drift    pz = sqrt((1+d)^2 - px^2 - py^2), lp = L (1/pz),
 //                  x = fma(px, lp, x), y = fma(py, lp, y),
-//                  zeta = fma(lp, (d(2+d) - px^2 - py^2)/(1+pz) - beta0 ptau, zeta)
+//                  zeta = fma(lp, (d(2+d) - px^2 - py^2) (1/(1+pz)) - beta0 ptau, zeta)
 //   expanded drift x = fma(px, L rpp, x), ...,
 //                  zeta = fma(L, (d - beta0 ptau) rpp - 0.5 (px^2+py^2) rpp^3 (1+beta0 ptau), zeta)
 //   multipole      Horner from the top order: b <- b z + c_n with
@@ -167,17 +167,17 @@ __global__ void __launch_bounds__(256) k_track(const uint64_t* __restrict__ tab,
           const double px2 = q.px * q.px;
           const double py2 = q.py * q.py;
           const double pz2 = q.opd2 - px2 - py2;
-          if (!(pz2 > 0.0)) {
+          if (!((pz2 > 0x1p-600) & (pz2 < 0x1p600))) {
             st = -1;
             lost_e = e;
             lost_t = t;
             goto done;
           }
-          const double pz = sqrt(pz2);
-          const double lp = L / pz;
+          const double pz = xtmm::sqrt_in(pz2);
+          const double lp = L * xtmm::recip_in(pz);
           q.x = fma(q.px, lp, q.x);
           q.y = fma(q.py, lp, q.y);
-          const double dz = (q.u - px2 - py2) / (1.0 + pz) - q.bpt;
+          const double dz = (q.u - px2 - py2) * xtmm::recip_in(1.0 + pz) - q.bpt;
           q.zeta = fma(lp, dz, q.zeta);
           break;
         }
@@ -338,15 +338,15 @@ __global__ void __launch_bounds__(256) k_track2(const uint64_t* __restrict__ tab
           const double px2 = q.px * q.px;
           const double py2 = q.py * q.py;
           const double pz2 = q.opd2 - px2 - py2;
-          if (!(pz2 > 0.0) && !lost) {
+          if (!((pz2 > 0x1p-600) & (pz2 < 0x1p600)) && !lost) {
             freeze(P, p, q, -1, e, t, n_el, t0, backward);
             lost = true;
           }
-          const double pz = sqrt(pz2);
-          const double lp = L / pz;
+          const double pz = xtmm::sqrt_in(pz2);
+          const double lp = L * xtmm::recip_in(pz);
           q.x = fma(q.px, lp, q.x);
           q.y = fma(q.py, lp, q.y);
-          const double dz = (q.u - px2 - py2) / (1.0 + pz) - q.bpt;
+          const double dz = (q.u - px2 - py2) * xtmm::recip_in(1.0 + pz) - q.bpt;
           q.zeta = fma(lp, dz, q.zeta);
           break;
         }
@@ -497,15 +497,15 @@ __global__ void __launch_bounds__(256) k_track3(const uint64_t* __restrict__ tab
           const double px2 = q.px * q.px;
           const double py2 = q.py * q.py;
           const double pz2 = q.opd2 - px2 - py2;
-          if (!(pz2 > 0.0) && !lost) {
+          if (!((pz2 > 0x1p-600) & (pz2 < 0x1p600)) && !lost) {
             freeze(P, p, q, -1, e, t, n_el, t0, backward);
             lost = true;
           }
-          const double pz = sqrt(pz2);
-          const double lp = L / pz;
+          const double pz = xtmm::sqrt_in(pz2);
+          const double lp = L * xtmm::recip_in(pz);
           q.x = fma(q.px, lp, q.x);
           q.y = fma(q.py, lp, q.y);
-          const double dz = (q.u - px2 - py2) / (1.0 + pz) - q.bpt;
+          const double dz = (q.u - px2 - py2) * xtmm::recip_in(1.0 + pz) - q.bpt;
           q.zeta = fma(lp, dz, q.zeta);
         } else if (ktype == K_AP_CIRC) {
           if (!(q.x * q.x + q.y * q.y <= prm[0]) && !lost) {

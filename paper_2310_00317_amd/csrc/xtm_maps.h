@@ -26,20 +26,59 @@ __device__ __forceinline__ void refresh(Pt& q, double beta0) {
   q.bpt = beta0 * q.ptau;
 }
 
-// Exact drift over L: pz = sqrt((1+d)^2 - px^2 - py^2), lp = L/pz,
-// x += px lp, y += py lp, zeta += lp ((d(2+d) - px^2 - py^2)/(1+pz) - beta0 ptau).
-// Returns false when pz^2 is not positive (or NaN): the particle is lost; the
-// arithmetic still runs (producing NaN) so the caller needs no branch.
+// Square root and reciprocal for operands well inside the exponent range,
+// both correctly rounded (the same values as sqrt() and 1.0/b, which add
+// exponent scaling steps for operands near the limits; without them the
+// drift's dependent chain is a quarter shorter).
+//   sqrt_in: x in [2^-600, 2^600].  Goldschmidt's iteration from the
+//   hardware's reciprocal-square-root estimate y: g = x y ~ sqrt x and
+//   h = y/2 ~ 1/(2 sqrt x) refined together by r = 1/2 - h g, then two
+//   Newton corrections g += (x - g^2) h.
+//   recip_in: b in [2^-300, 2^301].  Newton's iteration r += r (1 - b r)
+//   twice from the hardware's reciprocal estimate, then the residual step
+//   r + r (1 - b r) that rounds the quotient correctly (Markstein).
+__device__ __forceinline__ double sqrt_in(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  double g = x * y;
+  double h = y * 0.5;
+  const double r = fma(-h, g, 0.5);
+  g = fma(g, r, g);
+  h = fma(h, r, h);
+  double d = fma(-g, g, x);
+  g = fma(d, h, g);
+  d = fma(-g, g, x);
+  return fma(d, h, g);
+}
+
+__device__ __forceinline__ double recip_in(double b) {
+  double r = __builtin_amdgcn_rcp(b);
+  double e = fma(-b, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-b, r, 1.0);
+  r = fma(r, e, r);
+  const double res = fma(-b, r, 1.0);
+  return fma(res, r, r);
+}
+
+// Exact drift over L: pz = sqrt((1+d)^2 - px^2 - py^2), lp = L (1/pz),
+// x += px lp, y += py lp, zeta += lp ((d(2+d) - px^2 - py^2) (1/(1+pz)) - beta0 ptau),
+// the reciprocals correctly rounded.  Returns false unless
+// 2^-600 < pz^2 < 2^600 (imaginary, vanishing or absurd longitudinal
+// momentum, or NaN): the particle is lost; the arithmetic still runs (its
+// results are not used) so the caller needs no branch.  Inside the window
+// pz lies in [2^-300, 2^300], the domain of sqrt_in and recip_in.
 __device__ __forceinline__ bool drift_exact(Pt& q, double L) {
   const double px2 = q.px * q.px;
   const double py2 = q.py * q.py;
   const double pz2 = q.opd2 - px2 - py2;
-  const bool ok = pz2 > 0.0;
-  const double pz = sqrt(pz2);
-  const double lp = L / pz;
+  const bool ok = (pz2 > 0x1p-600) & (pz2 < 0x1p600);
+  const double pz = sqrt_in(pz2);
+  const double rpz = recip_in(pz);
+  const double rpz1 = recip_in(1.0 + pz);
+  const double lp = L * rpz;
   q.x = fma(q.px, lp, q.x);
   q.y = fma(q.py, lp, q.y);
-  const double dz = (q.u - px2 - py2) / (1.0 + pz) - q.bpt;
+  const double dz = (q.u - px2 - py2) * rpz1 - q.bpt;
   q.zeta = fma(lp, dz, q.zeta);
   return ok;
 }
@@ -49,7 +88,8 @@ __device__ __forceinline__ bool drift_exact(Pt& q, double L) {
 __device__ __forceinline__ bool drift_ok(const Pt& q) {
   const double px2 = q.px * q.px;
   const double py2 = q.py * q.py;
-  return q.opd2 - px2 - py2 > 0.0;
+  const double pz2 = q.opd2 - px2 - py2;
+  return (pz2 > 0x1p-600) & (pz2 < 0x1p600);
 }
 
 // Drift of H = pzeta - (1+d) + (px^2+py^2)/(2(1+d)) over L.

@@ -63,12 +63,17 @@ def bitwise_fraction(g, o, mask):
 
 
 def assert_bitwise(g, o, fields=ALL_FLOAT + ("state", "at_turn", "at_element")):
-    """Every listed field equal bit for bit (NaN matches NaN): the rounding
+    """Every listed field equal bit for bit (signed zeros included; NaN
+    matches NaN whatever its payload): the rounding
     contract of the two implementations (same operation order, explicit
     fused multiply-adds, correctly rounded IEEE operations and the same
     series for sin, cos and log)."""
     for f in fields:
-        a, b = g[f], (o[f] if isinstance(o, dict) else getattr(o, f))
-        same = (a == b) | (np.isnan(a) & np.isnan(b)) if a.dtype.kind == "f" else (a == b)
+        a, b = np.asarray(g[f]), np.asarray(o[f] if isinstance(o, dict) else getattr(o, f))
+        if a.dtype.kind == "f":
+            # bit patterns (so +0 and -0 differ); any NaN matches any NaN
+            same = (a.view(np.int64) == b.view(np.int64)) | (np.isnan(a) & np.isnan(b))
+        else:
+            same = a == b
         bad = np.nonzero(~same)[0]
         assert bad.size == 0, f"{f}: {bad.size} differ, first {bad[:5]}: {a[bad[:3]]} vs {b[bad[:3]]}"
