@@ -147,8 +147,8 @@ std::string emit(uint32_t s, const std::string& arr, const std::string& j, bool 
       else if (mode == kMarkOnly)
         c << "xtmm::mark(xtmm::drift_exact(q, " << P(0) << "), code, st, e0 + " << j << ", -1);";
       else
-        c << "{ if (!xtmm::drift_ok(q) && code == 0) SAVE(); xtmm::mark(xtmm::drift_exact(q, "
-          << P(0) << "), code, st, e0 + " << j << ", -1); }";
+        c << "{ if (!xtmm::drift_ok(q) && live) { SAVE(); code = e0 + " << j
+          << "; st = -1; live = false; } (void)xtmm::drift_exact(q, " << P(0) << "); }";
       break;
     case K_DRIFT_EXP:
       c << "xtmm::drift_expanded(q, " << P(0) << ");";
@@ -188,8 +188,10 @@ std::string emit(uint32_t s, const std::string& arr, const std::string& j, bool 
       else if (kt == K_AP_ELL) test = "xtmm::in_ellipse(q, " + P(0) + ", " + P(1) + ")";
       else test = "xtmm::in_rect(q, " + P(0) + ", " + P(1) + ", " + P(2) + ", " + P(3) + ")";
       c << "{ const bool ok = " << test << "; ";
-      if (mode == kSaveAtLoss) c << "if (!ok && code == 0) SAVE(); ";
-      c << "xtmm::mark(ok, code, st, e0 + " << j << ", 0); }";
+      if (mode == kSaveAtLoss)
+        c << "if (!ok && live) { SAVE(); code = e0 + " << j << "; st = 0; live = false; } }";
+      else
+        c << "xtmm::mark(ok, code, st, e0 + " << j << ", 0); }";
       break;
     }
     default:
@@ -319,7 +321,8 @@ std::string generate(const Decomp& d, int32_t style, bool batched) {
     else
       s << "  const bool tracked = in_range && P.state[pi] == 1;\n";
     s << "  int code = tracked ? 0 : 1;\n"
-         "  int st = 1;\n";
+         "  int st = 1;\n"
+         "  bool live = tracked;\n";
     s << "  if (__syncthreads_and(code != 0)) " << exit_stmt << "\n";
     s << "  xtmm::Pt q;\n"
          "  q.x = P.x[pi]; q.px = P.px[pi]; q.y = P.y[pi]; q.py = P.py[pi]; q.zeta = P.zeta[pi];\n"
@@ -369,8 +372,11 @@ std::string generate(const Decomp& d, int32_t style, bool batched) {
       s << "#pragma unroll\n"
            "  for (int k_ = 0; k_ < PPT; ++k_) tracked_[k_] = in_range_[k_] && P.state[pi_[k_]] == 1;\n";
     s << "  int code_[PPT], st_[PPT];\n"
+         "  bool live_[PPT];\n"
          "#pragma unroll\n"
-         "  for (int k_ = 0; k_ < PPT; ++k_) { code_[k_] = tracked_[k_] ? 0 : 1; st_[k_] = 1; }\n"
+         "  for (int k_ = 0; k_ < PPT; ++k_) {\n"
+         "    code_[k_] = tracked_[k_] ? 0 : 1; st_[k_] = 1; live_[k_] = tracked_[k_];\n"
+         "  }\n"
          "  if (__syncthreads_and(code_[0] != 0 && code_[1] != 0)) " << exit_stmt << "\n"
          "  const double beta0 = r.beta0, two_over_beta0 = r.two_over_beta0;\n"
          "  xtmm::Pt q_[PPT];\n"
@@ -470,7 +476,8 @@ std::string generate(const Decomp& d, int32_t style, bool batched) {
         // that give each copy the one-particle names
         for (int32_t k = 0; k < ppt; ++k)
           s << "        { xtmm::Pt& q = q_[" << k << "]; int& code = code_[" << k
-            << "]; int& st = st_[" << k << "]; const int pi = pi_[" << k
+            << "]; int& st = st_[" << k << "]; bool& live = live_[" << k
+            << "]; (void)live; const int pi = pi_[" << k
             << "]; const long long pid = pid_[" << k << "]; (void)pid; (void)pi; " << stmt
             << " }\n";
       }
