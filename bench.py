@@ -43,8 +43,8 @@ KERNEL_NAMES[13] = ("xtm_line (per-line generated kernel, one-wave workgroups, p
 TRAFFIC_SOURCES = ("xtm_jit.cpp", "xtm_maps.h")
 MEASURED_TRAFFIC = {
     # (workload, particles, turns per step, steps, kernel variant, source hash)
-    ("cfg2", 100000, 1000, 10, 10, "36f8ea4af09ba25d"):
-        (21406773.0, "profiles/xtm_line_cfg2_hbm_counters.txt"),
+    ("cfg2", 100000, 1000, 10, 10, "8654d53112d7bce3"):
+        (21407925.0, "profiles/xtm_line_cfg2_hbm_counters.txt"),
 }
 
 
