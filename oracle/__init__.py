@@ -172,6 +172,27 @@ def track_backward(elements, ref, parts: Particles, n_turns: int, nthreads: int 
     return int(passes)
 
 
+def refine_losses(elements, ref, parts: Particles, n_vertices: int = 64, ds: float = 0.01,
+                  n_bisect: int = 30):
+    """Loss-location refinement of the particles lost on an aperture: (s, x, y)
+    of the first exit from the polygon-interpolated aperture between the
+    previous aperture and the one that caught each particle, NaN elsewhere
+    (the reading is stated at oracle_refine_losses in oracle.c)."""
+    el = _els(elements)
+    r = _ref3(ref)
+    st = parts._struct()
+    out = [np.zeros(parts.n, dtype=np.float64) for _ in range(3)]
+    f = lib().oracle_refine_losses
+    f.restype = ctypes.c_int
+    rc = f(el.ctypes.data_as(ctypes.c_void_p), ctypes.c_int32(len(el)),
+           r.ctypes.data_as(ctypes.c_void_p), ctypes.byref(st), ctypes.c_int32(n_vertices),
+           ctypes.c_double(ds), ctypes.c_int32(n_bisect),
+           *[a.ctypes.data_as(ctypes.c_void_p) for a in out])
+    if rc != 0:
+        raise ValueError("oracle_refine_losses rejected its input (code %d)" % rc)
+    return tuple(out)
+
+
 def reference(ref) -> tuple[float, float]:
     """(beta0, gamma0) as the oracle computes them."""
     out = np.zeros(2)

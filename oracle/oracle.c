@@ -664,3 +664,218 @@ void oracle_philox_constants(uint32_t out[4]) {
   out[2] = O_PHILOX_W0;
   out[3] = O_PHILOX_W1;
 }
+
+/* ------------------------------------------------ loss-location refinement */
+
+/* Loss-location refinement (paper section "Simulation of beam losses",
+   aperture figure: losses localised beyond the per-element aperture checks
+   by backtracking each lost particle and testing it against an aperture
+   model refined by polygonal interpolation).  The paper gives no steps; the
+   reading here:
+
+   Geometry.  s of element e is the summed length of the drifts before it
+   (thin elements have none); C = s of the line end.  Each XYShift (x -= dx,
+   y -= dy) and SRotation ((x, y) <- (c x + s y, c y - s x)) changes the
+   frame of the coordinates after it; G_e maps the coordinates a particle
+   has entering element e to the frame of the line start:
+   line = A_e u + b_e, G_0 = identity, a shift gives b += A d, a rotation
+   gives A <- A R^T.  Each aperture becomes a polygon of M vertices: the
+   points where rays from its own origin at angles 2 pi k / M meet its
+   boundary (circle r; ellipse 1/sqrt(c^2/a^2 + s^2/b^2); rectangle: the
+   nearest side along the ray, which needs the origin inside it), mapped to
+   the line frame by G of the aperture.
+
+   Path.  A particle lost on aperture e_L (its stored coordinates are those
+   it entered e_L with) is backtracked through the inverse maps of the
+   elements after the previous aperture e_P (cyclic: the previous turn's
+   last aperture when e_L is the first), then tracked forward again over the
+   same elements.  Inside a drift its line-frame position moves on the
+   straight segment between the drift's entry and exit points.
+
+   Aperture between e_P and e_L: vertex k is P_k + w (L_k - P_k),
+   w = (s - s_P)/(s_L - s_P), with P and L the two polygons.
+
+   Search.  Each drift is cut into K = ceil(length/ds) equal sub-steps; the
+   end of each sub-step is tested (even-odd crossing rule against the
+   interpolated polygon); the first sub-step whose end lies outside is
+   bisected n_bisect times.  s_loss is the outer end of the final interval
+   and (x, y) its line-frame position.  A particle whose path never leaves
+   the interpolated polygon, or whose backtracking fails, keeps s_L and its
+   position at e_L.  Radiation is not undone (the inverse of a radiating
+   multipole is its kick alone).
+
+   Rounding.  lerp(a, b, f) = fma(f, b - a, a); G is applied as
+   (a11 x + a12 y) + b1; the crossing test compares
+   (xj - xi)(py - yi) - (px - xi)(yj - yi) with zero; everything else is one
+   correctly rounded operation per written operator.
+   Returns 0, -1 on bad arguments, -2 on bad elements, -6 when a
+   rectangle does not contain its origin. */
+typedef struct { double a11, a12, a21, a22, b1, b2; } orc_frame;
+
+static double o_lerp(double a, double b, double f) { return fma(f, b - a, a); }
+
+static void o_to_line(const orc_frame* g, double ux, double uy, double* lx, double* ly) {
+  double t1 = g->a11 * ux;
+  double t2 = g->a12 * uy;
+  double t3 = g->a21 * ux;
+  double t4 = g->a22 * uy;
+  *lx = (t1 + t2) + g->b1;
+  *ly = (t3 + t4) + g->b2;
+}
+
+static int o_is_ap(int t) { return t == O_AP_CIRC || t == O_AP_ELL || t == O_AP_RECT; }
+static int o_is_drift(int t) { return t == O_DRIFT || t == O_DRIFT_EXP; }
+
+/* even-odd crossing test of (px, py) against polygon P + w (L - P) */
+static int o_in_poly(double px, double py, const double* P, const double* Lp, int M, double w) {
+  int in = 0;
+  for (int k = 0; k < M; ++k) {
+    int kn = (k + 1 == M) ? 0 : k + 1;
+    double xi = o_lerp(P[2 * k], Lp[2 * k], w);
+    double yi = o_lerp(P[2 * k + 1], Lp[2 * k + 1], w);
+    double xj = o_lerp(P[2 * kn], Lp[2 * kn], w);
+    double yj = o_lerp(P[2 * kn + 1], Lp[2 * kn + 1], w);
+    if ((yi > py) != (yj > py)) {
+      double t1 = (xj - xi) * (py - yi);
+      double t2 = (px - xi) * (yj - yi);
+      double cr = t1 - t2;
+      if (yj > yi ? cr > 0.0 : cr < 0.0) in = !in;
+    }
+  }
+  return in;
+}
+
+int oracle_refine_losses(const orc_elem* el, int32_t n_el, const double ref3[3],
+                         const orc_parts* P, int32_t M, double ds, int32_t n_bisect,
+                         double* s_out, double* x_out, double* y_out) {
+  if (n_el <= 0 || M < 4 || !(ds > 0.0) || n_bisect < 0 || n_bisect > 60) return -1;
+  if (validate(el, n_el)) return -2;
+  orc_ref r = make_ref(ref3);
+  orc_coef* c = build_coefs(el, n_el);
+  double* s = (double*)malloc(sizeof(double) * (size_t)(n_el + 1));
+  orc_frame* G = (orc_frame*)malloc(sizeof(orc_frame) * (size_t)(n_el + 1));
+  int32_t* prev = (int32_t*)malloc(sizeof(int32_t) * (size_t)n_el);
+  double* poly = (double*)calloc((size_t)n_el * 2 * (size_t)M, sizeof(double));
+  int rc = 0;
+  /* s positions and frames */
+  s[0] = 0.0;
+  G[0].a11 = 1.0; G[0].a12 = 0.0; G[0].a21 = 0.0; G[0].a22 = 1.0; G[0].b1 = 0.0; G[0].b2 = 0.0;
+  for (int32_t e = 0; e < n_el; ++e) {
+    s[e + 1] = o_is_drift(el[e].type) ? s[e] + el[e].length : s[e];
+    orc_frame g = G[e];
+    if (el[e].type == O_SHIFT) {
+      double dx = el[e].p[0], dy = el[e].p[1];
+      double t1 = g.a11 * dx, t2 = g.a12 * dy, t3 = g.a21 * dx, t4 = g.a22 * dy;
+      g.b1 = (t1 + t2) + g.b1;
+      g.b2 = (t3 + t4) + g.b2;
+    } else if (el[e].type == O_SROT) {
+      double cs = cos(el[e].p[0]), sn = sin(el[e].p[0]);
+      double a11 = g.a11 * cs + g.a12 * sn;
+      double a12 = g.a12 * cs - g.a11 * sn;
+      double a21 = g.a21 * cs + g.a22 * sn;
+      double a22 = g.a22 * cs - g.a21 * sn;
+      g.a11 = a11; g.a12 = a12; g.a21 = a21; g.a22 = a22;
+    }
+    G[e + 1] = g;
+  }
+  const double C = s[n_el];
+  /* aperture polygons in the line frame and the previous aperture of each */
+  int32_t last_ap = -1;
+  for (int32_t e = 0; e < n_el; ++e)
+    if (o_is_ap(el[e].type)) last_ap = e;
+  for (int32_t e = 0, pa = last_ap; e < n_el; ++e) {
+    if (!o_is_ap(el[e].type)) continue;
+    prev[e] = pa;
+    pa = e;
+    const double* p = el[e].p;
+    if (el[e].type == O_AP_RECT && !(p[0] < 0.0 && 0.0 < p[1] && p[2] < 0.0 && 0.0 < p[3])) {
+      rc = -6;
+      goto done;
+    }
+    for (int32_t k = 0; k < M; ++k) {
+      double ang = 2.0 * M_PI * (double)k / (double)M;
+      double cs = cos(ang), sn = sin(ang);
+      double rad;
+      if (el[e].type == O_AP_CIRC) {
+        rad = p[0];
+      } else if (el[e].type == O_AP_ELL) {
+        double q = (cs * cs) / (p[0] * p[0]) + (sn * sn) / (p[1] * p[1]);
+        rad = 1.0 / sqrt(q);
+      } else {
+        rad = INFINITY;
+        if (cs > 0.0) rad = fmin(rad, p[1] / cs);
+        if (cs < 0.0) rad = fmin(rad, p[0] / cs);
+        if (sn > 0.0) rad = fmin(rad, p[3] / sn);
+        if (sn < 0.0) rad = fmin(rad, p[2] / sn);
+      }
+      o_to_line(&G[e], rad * cs, rad * sn, &poly[((size_t)e * M + k) * 2],
+                &poly[((size_t)e * M + k) * 2 + 1]);
+    }
+  }
+  for (int64_t i = 0; i < P->n; ++i) {
+    s_out[i] = NAN; x_out[i] = NAN; y_out[i] = NAN;
+    int32_t eL = P->at_element[i];
+    if (P->state[i] != 0 || eL < 0 || eL >= n_el || !o_is_ap(el[eL].type)) continue;
+    int32_t eP = prev[eL];
+    double sL = s[eL];
+    double sP = eP < eL ? s[eP] : s[eP] - C;
+    orc_pt q;
+    load_pt(P, i, &q);
+    o_to_line(&G[eL], q.x, q.y, &x_out[i], &y_out[i]);
+    s_out[i] = sL;
+    if (!(sL - sP > 0.0)) continue;
+    /* backtrack to the exit of the previous aperture */
+    int ok = 1;
+    for (int32_t j = (eL + n_el - 1) % n_el; j != eP; j = (j + n_el - 1) % n_el) {
+      double fkx, fky;
+      if (apply(&q, &el[j], &c[j], &r, -1.0, &fkx, &fky) != 1) { ok = 0; break; }
+    }
+    if (!ok) continue;
+    /* forward again, searching each drift */
+    const double* PP = &poly[(size_t)eP * M * 2];
+    const double* PL = &poly[(size_t)eL * M * 2];
+    double sc = sP;
+    for (int32_t j = (eP + 1) % n_el; j != eL; j = (j + 1) % n_el) {
+      double fkx, fky;
+      if (!o_is_drift(el[j].type)) {
+        apply(&q, &el[j], &c[j], &r, 1.0, &fkx, &fky);
+        continue;
+      }
+      double L = el[j].length;
+      double v0x, v0y, v1x, v1y;
+      o_to_line(&G[j], q.x, q.y, &v0x, &v0y);
+      if (apply(&q, &el[j], &c[j], &r, 1.0, &fkx, &fky) != 1) { ok = 0; break; }
+      o_to_line(&G[j], q.x, q.y, &v1x, &v1y);
+      if (L > 0.0) {
+        int64_t K = (int64_t)ceil(L / ds);
+        if (K < 1) K = 1;
+        int found = 0;
+        for (int64_t k = 1; k <= K && !found; ++k) {
+          double f = (double)k / (double)K;
+          double sf = sc + L * f;
+          double w = (sf - sP) / (sL - sP);
+          if (o_in_poly(o_lerp(v0x, v1x, f), o_lerp(v0y, v1y, f), PP, PL, M, w)) continue;
+          double lo = (double)(k - 1) / (double)K, hi = f;
+          for (int32_t b = 0; b < n_bisect; ++b) {
+            double m = 0.5 * (lo + hi);
+            double sm = sc + L * m;
+            double wm = (sm - sP) / (sL - sP);
+            if (o_in_poly(o_lerp(v0x, v1x, m), o_lerp(v0y, v1y, m), PP, PL, M, wm))
+              lo = m;
+            else
+              hi = m;
+          }
+          s_out[i] = sc + L * hi;
+          x_out[i] = o_lerp(v0x, v1x, hi);
+          y_out[i] = o_lerp(v0y, v1y, hi);
+          found = 1;
+        }
+        if (found) break;
+      }
+      sc = sc + L;
+    }
+  }
+done:
+  free(c); free(s); free(G); free(prev); free(poly);
+  return rc;
+}
