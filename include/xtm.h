@@ -241,6 +241,39 @@ xtm_status xtm_track_backward(xtm_lattice lat, xtm_particles p, int32_t n_turns,
 xtm_status xtm_track_per_element(xtm_lattice lat, xtm_particles p, int32_t n_turns, void* stream,
                                  xtm_track_stats* stats);
 
+/* Loss-location refinement (paper section on beam losses and its aperture
+   figure: losses localised below the spacing of the aperture checks by
+   backtracking each lost particle against an aperture model refined by
+   polygonal interpolation).  For each particle i of p whose state is 0
+   (lost on an aperture element e_L; its stored coordinates are those it
+   entered e_L with): the particle is backtracked through the inverse maps to
+   the exit of the previous aperture e_P (cyclically: the last aperture of
+   the line when e_L is the first), then tracked forward again; in each drift
+   its position in the frame of the line start (the coordinates mapped back
+   through every XYShift and SRotation before the element) moves on a
+   straight segment.  Each aperture is a polygon of n_vertices vertices: the
+   points where rays from the aperture's own origin at angles
+   2 pi k / n_vertices meet its boundary, in the line frame; between e_P and
+   e_L vertex k moves linearly in s.  Each drift is cut into ceil(L / ds)
+   equal sub-steps; the first sub-step whose end is outside the interpolated
+   polygon (even-odd rule) is bisected n_bisect times.
+   Output (device arrays of the set's length): d_s[i] = s of the loss [m]
+   (s = 0 at the line start, increasing through the drifts, negative for a
+   loss before the line start on the way from the previous turn's last
+   aperture), d_x[i], d_y[i] = its position in the line frame [m]; NaN for
+   particles not lost on an aperture.  A particle whose path never leaves the
+   interpolated polygon, or whose backtracking meets an imaginary
+   longitudinal momentum, gets s of e_L and its position there.  Radiation is
+   not undone.  Arguments: n_vertices 4..4096, ds > 0 (at most 1e8 sub-steps
+   per drift), n_bisect 0..60.  XTM_E_UNSUPPORTED when a rectangular aperture
+   does not contain its own origin.  The polygon geometry is built on the
+   host and kept on the lattice for the last n_vertices (first call with a
+   new n_vertices synchronises); the kernel is stream-ordered, one thread per
+   particle. */
+xtm_status xtm_refine_losses(xtm_lattice lat, xtm_particles p, int32_t n_vertices, double ds,
+                             int32_t n_bisect, double* d_s, double* d_x, double* d_y,
+                             void* stream);
+
 /* Copy the loss record into host buffers of the bound length (any may be
    NULL).  Synchronises the stream. */
 xtm_status xtm_get_losses(xtm_particles p, int32_t* h_state, int32_t* h_at_turn,

@@ -74,6 +74,12 @@ struct xtm_lattice_s {
   // launch plan chosen by xtm_autotune (0 = none): used when the caller's
   // options leave the kernel variant and block size at 0
   int32_t plan_variant = 0, plan_block = 0;
+  // the element descriptions as given (geometry of the loss refinement)
+  std::vector<xtm_element_desc> desc_h;
+  // loss-refinement geometry for one polygon size, built on first use
+  int32_t refine_M = 0;
+  void* refine_buf = nullptr;
+  xtm::RefineGeom refine{};
 };
 
 struct xtm_batch_s {
@@ -606,6 +612,7 @@ xtm_status xtm_lattice_create(const xtm_element_desc* el, int32_t n, const xtm_r
     auto* L = new xtm_lattice_s();
     L->n_el = n;
     L->ref = r;
+    if (n > 0) L->desc_h.assign(el, el + n);
     for (int32_t i = 0; i < n; ++i) {
       xtm_status st = pack(el[i], i, r, 1.0, L->fwd_h);
       if (st != XTM_OK) { delete L; return st; }
@@ -653,6 +660,7 @@ xtm_status xtm_lattice_destroy(xtm_lattice L) {
   hipFree(L->bwd_d);
   hipFree(L->fwd_seg_d);
   hipFree(L->bwd_seg_d);
+  hipFree(L->refine_buf);
   for (int32_t k = 0; k < kLineStyles; ++k) {
     free_line_kernel(&L->fwd_line[k]);
     free_line_kernel(&L->bwd_line[k]);
@@ -1344,6 +1352,161 @@ xtm_status xtm_retire(xtm_particles P, const float* d_logit, float logit_thresho
     if (h_audited) *h_audited = hc[1];
     int64_t alive = 0;
     return read_alive(P, s, &alive, nullptr);
+  });
+}
+
+namespace {
+bool is_ap_type(int32_t t) { return t == XTM_AP_CIRCLE || t == XTM_AP_ELLIPSE || t == XTM_AP_RECT; }
+bool is_drift_type(int32_t t) { return t == XTM_DRIFT || t == XTM_DRIFT_EXPANDED; }
+
+// Host geometry of the loss refinement: s of each element, the line frame of
+// each element's entry coordinates (a shift d gives b += A d, a rotation by t
+// gives A <- A R(t)^T), aperture polygons (rays from the aperture's origin at
+// angles 2 pi k / M meeting its boundary, mapped to the line frame), table
+// record positions, previous aperture and aperture ordinal of each element.
+xtm_status build_refine_geometry(xtm_lattice_s* L, int32_t M) {
+  const int32_t n = L->n_el;
+  const auto& el = L->desc_h;
+  std::vector<double> sv(n + 1), G(6 * (size_t)(n + 1));
+  sv[0] = 0.0;
+  G[0] = 1.0; G[1] = 0.0; G[2] = 0.0; G[3] = 1.0; G[4] = 0.0; G[5] = 0.0;
+  for (int32_t e = 0; e < n; ++e) {
+    sv[e + 1] = is_drift_type(el[e].type) ? sv[e] + el[e].length : sv[e];
+    double a11 = G[6 * e], a12 = G[6 * e + 1], a21 = G[6 * e + 2], a22 = G[6 * e + 3];
+    double b1 = G[6 * e + 4], b2 = G[6 * e + 5];
+    if (el[e].type == XTM_XYSHIFT) {
+      const double dx = el[e].p[0], dy = el[e].p[1];
+      const double t1 = a11 * dx, t2 = a12 * dy, t3 = a21 * dx, t4 = a22 * dy;
+      b1 = (t1 + t2) + b1;
+      b2 = (t3 + t4) + b2;
+    } else if (el[e].type == XTM_SROTATION) {
+      const double c = std::cos(el[e].p[0]), sn = std::sin(el[e].p[0]);
+      const double u11 = a11 * c, u12 = a12 * sn, u21 = a12 * c, u22 = a11 * sn;
+      const double w11 = a21 * c, w12 = a22 * sn, w21 = a22 * c, w22 = a21 * sn;
+      a11 = u11 + u12;
+      a12 = u21 - u22;
+      a21 = w11 + w12;
+      a22 = w21 - w22;
+    }
+    double* g = &G[6 * (size_t)(e + 1)];
+    g[0] = a11; g[1] = a12; g[2] = a21; g[3] = a22; g[4] = b1; g[5] = b2;
+  }
+  std::vector<int32_t> prev(n, -1), ord(n, -1), off_f(n), off_b(n);
+  int32_t last = -1, n_ap = 0;
+  for (int32_t e = 0; e < n; ++e)
+    if (is_ap_type(el[e].type)) last = e;
+  std::vector<double> poly;
+  for (int32_t e = 0, pa = last; e < n; ++e) {
+    if (!is_ap_type(el[e].type)) continue;
+    prev[e] = pa;
+    pa = e;
+    ord[e] = n_ap++;
+    const double* p = el[e].p;
+    if (el[e].type == XTM_AP_RECT && !(p[0] < 0.0 && 0.0 < p[1] && p[2] < 0.0 && 0.0 < p[3]))
+      return fail(XTM_E_UNSUPPORTED, "element " + std::to_string(e) +
+                                         ": loss refinement needs the rectangle to contain its origin");
+    const double* g = &G[6 * (size_t)e];
+    for (int32_t k = 0; k < M; ++k) {
+      const double ang = 2.0 * M_PI * (double)k / (double)M;
+      const double c = std::cos(ang), sn = std::sin(ang);
+      double rad;
+      if (el[e].type == XTM_AP_CIRCLE) {
+        rad = p[0];
+      } else if (el[e].type == XTM_AP_ELLIPSE) {
+        const double q = (c * c) / (p[0] * p[0]) + (sn * sn) / (p[1] * p[1]);
+        rad = 1.0 / std::sqrt(q);
+      } else {
+        rad = INFINITY;
+        if (c > 0.0) rad = std::fmin(rad, p[1] / c);
+        if (c < 0.0) rad = std::fmin(rad, p[0] / c);
+        if (sn > 0.0) rad = std::fmin(rad, p[3] / sn);
+        if (sn < 0.0) rad = std::fmin(rad, p[2] / sn);
+      }
+      const double ux = rad * c, uy = rad * sn;
+      const double t1 = g[0] * ux, t2 = g[1] * uy, t3 = g[2] * ux, t4 = g[3] * uy;
+      poly.push_back((t1 + t2) + g[4]);
+      poly.push_back((t3 + t4) + g[5]);
+    }
+  }
+  // record positions: the backward table holds the elements in reverse order
+  {
+    size_t w = 0;
+    for (int32_t e = 0; e < n; ++e) {
+      off_f[e] = (int32_t)w;
+      w += 1 + ((L->fwd_h[w] >> 16) & 0xffffu);
+    }
+    w = 0;
+    for (int32_t j = 0; j < n; ++j) {
+      off_b[n - 1 - j] = (int32_t)w;
+      w += 1 + ((L->bwd_h[w] >> 16) & 0xffffu);
+    }
+  }
+  const size_t nd = sv.size() + G.size() + poly.size();
+  const size_t ni = 4 * (size_t)n;
+  const size_t bytes = nd * sizeof(double) + ni * sizeof(int32_t);
+  hipFree(L->refine_buf);
+  L->refine_buf = nullptr;
+  L->refine_M = 0;
+  void* buf = nullptr;
+  if (hipMalloc(&buf, bytes) != hipSuccess) return fail(XTM_E_NOMEM, "refinement geometry allocation");
+  std::vector<unsigned char> h(bytes);
+  unsigned char* q = h.data();
+  auto put = [&](const void* src, size_t nb) { std::memcpy(q, src, nb); q += nb; };
+  put(sv.data(), sv.size() * sizeof(double));
+  put(G.data(), G.size() * sizeof(double));
+  if (!poly.empty()) put(poly.data(), poly.size() * sizeof(double));
+  put(off_f.data(), n * sizeof(int32_t));
+  put(off_b.data(), n * sizeof(int32_t));
+  put(prev.data(), n * sizeof(int32_t));
+  put(ord.data(), n * sizeof(int32_t));
+  if (hipMemcpy(buf, h.data(), bytes, hipMemcpyHostToDevice) != hipSuccess) {
+    hipFree(buf);
+    return fail(XTM_E_HIP, "refinement geometry copy");
+  }
+  RefineGeom& rg = L->refine;
+  const double* d = (const double*)buf;
+  rg.n_el = n;
+  rg.M = M;
+  rg.s = d;
+  rg.G = d + sv.size();
+  rg.poly = d + sv.size() + G.size();
+  const int32_t* ip = (const int32_t*)(d + nd);
+  rg.off_f = ip;
+  rg.off_b = ip + n;
+  rg.prev = ip + 2 * n;
+  rg.ap_ord = ip + 3 * n;
+  L->refine_buf = buf;
+  L->refine_M = M;
+  return XTM_OK;
+}
+}  // namespace
+
+xtm_status xtm_refine_losses(xtm_lattice L, xtm_particles P, int32_t n_vertices, double ds,
+                             int32_t n_bisect, double* d_s, double* d_x, double* d_y,
+                             void* stream) {
+  return guarded([&]() -> xtm_status {
+    if (!L || !P) return fail(XTM_E_ARG, "null lattice or particle set");
+    if (!P->initialised) return fail(XTM_E_STATE, "particle set not initialised");
+    if (!same_ref(L->ref, P->ref)) return fail(XTM_E_REFERENCE, "reference mismatch");
+    if (n_vertices < 4 || n_vertices > 4096) return fail(XTM_E_ARG, "n_vertices must be in 4..4096");
+    if (!(ds > 0.0) || !std::isfinite(ds)) return fail(XTM_E_ARG, "ds must be finite and > 0");
+    if (n_bisect < 0 || n_bisect > 60) return fail(XTM_E_ARG, "n_bisect must be in 0..60");
+    if (P->n > 0 && (!d_s || !d_x || !d_y)) return fail(XTM_E_ARG, "null output array");
+    if (L->n_el == 0) return fail(XTM_E_ARG, "empty lattice");
+    for (int32_t e = 0; e < L->n_el; ++e)
+      if (is_drift_type(L->desc_h[e].type) && std::fabs(L->desc_h[e].length) / ds > 1e8)
+        return fail(XTM_E_ARG, "ds too small: more than 1e8 sub-steps in a drift");
+    if (L->refine_M != n_vertices) {
+      const xtm_status st = build_refine_geometry(L, n_vertices);
+      if (st != XTM_OK) return st;
+    }
+    RefineGeom g = L->refine;
+    g.ds = ds;
+    g.n_bisect = n_bisect;
+    HIP_TRY(launch_refine(L->fwd_d, L->bwd_d, g, soa_of(P), P->n, kref(L->ref, 0, 0), d_s, d_x,
+                          d_y, (hipStream_t)stream),
+            "refinement launch");
+    return XTM_OK;
   });
 }
 

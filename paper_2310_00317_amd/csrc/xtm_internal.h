@@ -105,6 +105,28 @@ hipError_t launch_per_element(const uint64_t* tab, const uint32_t* offsets, int3
 
 constexpr int kScanBlock = 1024;
 
+// Loss-location refinement geometry (device pointers into one buffer):
+// s of each element and of the line end (n_el + 1), line frame of each
+// element's entry coordinates as (a11, a12, a21, a22, b1, b2) (n_el + 1),
+// aperture polygons in the line frame (M vertices, x and y, per aperture),
+// record positions of each element in the forward and backward tables, the
+// previous aperture of each aperture and each element's aperture ordinal
+// (-1: not an aperture).
+struct RefineGeom {
+  int32_t n_el, M, n_bisect;
+  double ds;
+  const double* s;
+  const double* G;
+  const double* poly;
+  const int32_t* off_f;
+  const int32_t* off_b;
+  const int32_t* prev;
+  const int32_t* ap_ord;
+};
+hipError_t launch_refine(const uint64_t* fwd, const uint64_t* bwd, const RefineGeom& g, SoA P,
+                         int64_t n, KernelRef r, double* s_out, double* x_out, double* y_out,
+                         hipStream_t s);
+
 // Per-line tracking kernel generated from the lattice's cell structure and
 // compiled at run time (xtm_jit.cpp).
 struct LineKernel {

@@ -1,0 +1,158 @@
+"""GPU parity of the loss-location refinement (backtracking against a
+polygon-interpolated aperture) through the C ABI: the HIP kernel against the
+CPU oracle on the same post-tracking particle states, bit for bit (the same
+operations in the same order on both sides; NaN for particles not lost on an
+aperture)."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2310_00317_amd import inputs as I
+from parity_util import assert_bitwise, gpu_run, oracle_run
+
+pytestmark = pytest.mark.gpu
+REF = I.PROTON_450GEV
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2310_00317_amd as P
+    P.lib()
+    return P
+
+
+def banner(msg):
+    print(f"[gpu-refine] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def refine_both(P, oracle_mod, el, lat, parts, o, M, ds, nb):
+    import torch
+    s, x, y = P.refine_losses(lat, parts, M, ds, nb)
+    torch.cuda.synchronize()
+    g = {"s": s.cpu().numpy(), "x": x.cpu().numpy(), "y": y.cpu().numpy()}
+    so, xo, yo = oracle_mod.refine_losses(el, REF, o, M, ds, nb)
+    assert_bitwise(g, {"s": so, "x": xo, "y": yo}, fields=("s", "x", "y"))
+    lost = o.state == 0
+    assert np.isnan(g["s"][~lost]).all() and not np.isnan(g["s"][lost]).any()
+    return g
+
+
+def tracked(P, oracle_mod, el, coords, n_turns):
+    g, _, _, lat, parts = gpu_run(P, el, REF, coords, n_turns)
+    o, _ = oracle_run(oracle_mod, el, REF, coords, n_turns)
+    assert_bitwise(g, o)
+    return lat, parts, o
+
+
+@pytest.mark.parametrize("M,ds,nb", [(64, 0.01, 30), (8, 0.05, 0), (128, 0.02, 45)])
+def test_fodo_ring_losses(P, oracle_mod, M, ds, nb):
+    banner(f"cfg1 ring, 3000 large-amplitude protons, 40 turns, M={M} ds={ds} n_bisect={nb}")
+    el = I.cfg1_lattice()
+    c = I.gaussian_particles(3000, seed=71, sigmas=I.CFG1_SIGMAS * np.array([9, 9, 9, 9, 1, 1]))
+    lat, parts, o = tracked(P, oracle_mod, el, c, 40)
+    n_lost = int((o.state == 0).sum())
+    assert n_lost > 100
+    g = refine_both(P, oracle_mod, el, lat, parts, o, M, ds, nb)
+    # the refined location lies between the previous aperture and the one
+    # that caught the particle (half a cell, 50 m of drift, before it)
+    lost = o.state == 0
+    s_el = np.concatenate([[0.0], np.cumsum(np.where(el["type"] == I.DRIFT, el["length"], 0.0))])
+    sL = s_el[o.at_element[lost]]
+    assert np.all(g["s"][lost] <= sL) and np.all(g["s"][lost] >= sL - I.CFG1_HALF - 1e-9)
+    banner(f"{n_lost} losses refined; mean distance before the aperture "
+           f"{np.mean(sL - g['s'][lost]):.2f} m")
+
+
+def test_wrap_to_previous_turn(P, oracle_mod):
+    banner("short ring: losses at the first aperture refine back into the previous turn")
+    k = 0.05
+    el = I.line([I.multipole(knl=[0.0, k]), I.ap_circle(0.02), I.drift(5.0),
+                 I.multipole(knl=[0.0, -k]), I.ap_ellipse(0.025, 0.015), I.drift(5.0)])
+    rng = np.random.default_rng(5)
+    c = np.zeros((2000, 6))
+    c[:, 0] = rng.uniform(-0.02, 0.02, 2000)
+    c[:, 2] = rng.uniform(-0.015, 0.015, 2000)
+    c[:, 1] = rng.normal(0, 2e-3, 2000)
+    c[:, 3] = rng.normal(0, 2e-3, 2000)
+    lat, parts, o = tracked(P, oracle_mod, el, c, 20)
+    lost = o.state == 0
+    assert (o.at_element[lost] == 1).sum() > 20 and (o.at_element[lost] == 4).sum() > 20
+    g = refine_both(P, oracle_mod, el, lat, parts, o, 64, 0.01, 30)
+    first = lost & (o.at_element == 1)
+    assert np.all(g["s"][first] <= 0.0) and np.all(g["s"][first] >= -5.0 - 1e-12)
+
+
+def test_shifted_tilted_rect_to_ellipse(P, oracle_mod):
+    banner("rectangular to shifted and tilted elliptic aperture (the paper's aperture figure)")
+    k, th, dx, dy = 0.04, 0.15, 0.002, -0.001
+    cell = [I.multipole(knl=[0.0, k]), I.ap_rect(-0.03, 0.025, -0.012, 0.014), I.drift(3.0),
+            I.multipole(knl=[0.0, 0.0, 2.0]), I.drift(3.0), I.xyshift(dx, dy), I.srotation(th),
+            I.ap_ellipse(0.022, 0.011), I.srotation(-th), I.xyshift(-dx, -dy),
+            I.multipole(knl=[0.0, -k]), I.drift(6.0)]
+    el = I.line(cell * 10)
+    c = I.gaussian_particles(4000, seed=81, sigmas=np.array([8e-3, 1e-3, 5e-3, 1e-3, 0.1, 1e-4]))
+    lat, parts, o = tracked(P, oracle_mod, el, c, 15)
+    lost = o.state == 0
+    assert lost.sum() > 200
+    for M, ds, nb in ((128, 0.01, 30), (16, 0.1, 10)):
+        refine_both(P, oracle_mod, el, lat, parts, o, M, ds, nb)
+
+
+def test_no_losses_gives_nan_and_empty_set(P, oracle_mod):
+    import torch
+    el = I.cfg1_lattice()
+    c = I.cfg1_particles(64)
+    lat, parts, o = tracked(P, oracle_mod, el, c, 2)
+    assert (o.state == 1).all()
+    s, x, y = P.refine_losses(lat, parts)
+    torch.cuda.synchronize()
+    assert torch.isnan(s).all() and torch.isnan(x).all() and torch.isnan(y).all()
+    empty = P.Particles(0, REF).init(np.zeros((0, 6)))
+    s, _, _ = P.refine_losses(lat, empty)
+    assert s.numel() == 0
+
+
+def test_rejects_rectangle_without_origin(P):
+    el = I.line([I.ap_rect(0.001, 0.02, -0.01, 0.01), I.drift(1.0)])
+    lat = P.Lattice(el, REF)
+    parts = P.Particles(4, REF).init(np.zeros((4, 6)) + [0.005, 0, 0, 0, 0, 0])
+    with pytest.raises(P.XtmError, match="origin"):
+        P.refine_losses(lat, parts)
+    with pytest.raises(P.XtmError):
+        P.refine_losses(lat, parts, n_vertices=2)
+    with pytest.raises(P.XtmError):
+        P.refine_losses(lat, parts, ds=0.0)
+
+
+def test_da_ring_full_size_sampled(P, oracle_mod):
+    """The 20,000-element DA ring with the 100,000-particle grid, tracked on
+    the GPU; the refinement launch the benchmark times, checked on a sample of
+    the lost particles recomputed one by one by the oracle."""
+    import torch
+    banner("DA ring, 100,000 particles, 300 turns on the GPU; oracle on 1,500 sampled losses")
+    el = I.cfg2_lattice()
+    coords, _, _ = I.cfg2_grid()
+    lat = P.Lattice(el, REF)
+    parts = P.Particles(len(coords), REF).init(coords)
+    P.track(lat, parts, 300)
+    g = parts.to_numpy()
+    s, x, y = P.refine_losses(lat, parts, 64, 0.01, 30)
+    torch.cuda.synchronize()
+    lost = np.nonzero(g["state"] == 0)[0]
+    assert lost.size > 1000
+    pick = np.random.default_rng(3).choice(lost, 1500, replace=False)
+    o = oracle_mod.Particles(len(pick))
+    for f in ("x", "px", "y", "py", "zeta", "delta", "ptau", "rpp", "rvv", "state", "at_element",
+              "at_turn"):
+        getattr(o, f)[:] = g[f][pick]
+    o.particle_id[:] = g["particle_id"][pick]
+    so, xo, yo = oracle_mod.refine_losses(el, REF, o, 64, 0.01, 30)
+    assert_bitwise({"s": s.cpu().numpy()[pick], "x": x.cpu().numpy()[pick],
+                    "y": y.cpu().numpy()[pick]}, {"s": so, "x": xo, "y": yo}, fields=("s", "x", "y"))
+    banner(f"{lost.size} losses; sample of {pick.size} bitwise equal")
