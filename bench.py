@@ -142,6 +142,97 @@ def cpu_baseline(el, c, ref, sample_every: int, turns: int, radiation: int = 0, 
                       f"= {passes} passes in {dt:.1f} s"}
 
 
+def refine_bench(args):
+    """Loss-location refinement of the DA-scan ring's losses: the 100,000-particle
+    grid tracked (untimed) for --turns-per-step turns, then the refinement
+    kernel launched --steps times on the same losses, each launch timed with
+    HIP events on its stream.  Algorithmic FLOPs per polygon test: the
+    interpolation of the M vertices (x and y: a subtraction and a fused
+    multiply-add each, 6 M), the point on the path and the weight (10) and
+    two straddling edges (16)."""
+    import torch
+    import paper_2310_00317_amd as P
+    I = P.inputs
+    el = I.cfg2_lattice()
+    coords, _, _ = I.cfg2_grid()
+    ref = I.PROTON_450GEV
+    turns = args.turns_per_step or 1000
+    steps = args.steps if args.steps is not None else 3
+    M, ds, nb = args.refine_vertices, args.refine_ds, args.refine_bisect
+    n = len(coords)
+    print(f"[bench] refine: {n} particles, {len(el)} elements, {turns} turns tracked, "
+          f"M={M} ds={ds} n_bisect={nb}", file=sys.stderr, flush=True)
+    lat = P.Lattice(el, ref)
+    parts = P.Particles(n, ref).init(coords)
+    P.track(lat, parts, turns)
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        P.refine_losses(lat, parts, M, ds, nb, stream=st)
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(steps)]
+    t0 = time.perf_counter()
+    out = None
+    for a, b in evs:
+        a.record(st)
+        out = P.refine_losses(lat, parts, M, ds, nb, stream=st, with_tests=True)
+        b.record(st)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kernel_ms = sum(a.elapsed_time(b) for a, b in evs)
+    s_loss, _, _, tests = out
+    state = parts.state[:n]
+    n_lost = int((state == 0).sum().item())
+    total_tests = int(tests.to(torch.int64).sum().item())
+    flops_per_test = 6 * M + 26
+    avg_ms = kernel_ms / max(steps, 1)
+    value = n_lost / (avg_ms / 1e3) if avg_ms > 0 else 0.0
+    achieved = total_tests * flops_per_test / (avg_ms / 1e3) / 1e12 if avg_ms > 0 else 0.0
+    out_line = {
+        "metric": "refined loss locations/s (FP64)",
+        "value": value,
+        "unit": "losses/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": args.warmup,
+        "ms_per_step": avg_ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "loss-location refinement of the DA-scan ring (20,000 elements, "
+                               f"100,000-particle grid tracked {turns} turns)",
+                   "n_particles": n, "n_lost": n_lost, "n_vertices": M, "ds": ds,
+                   "n_bisect": nb, "polygon_tests": total_tests, "wall_s": wall},
+        "roofline": {"bound": "alu", "kernel": "k_refine (one thread per particle)",
+                     "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": None,
+                     "flops_per_test": flops_per_test, "avg_launch_ms": avg_ms,
+                     "launches": steps},
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        print("[bench] timing the CPU oracle on a sample of the losses", file=sys.stderr,
+              flush=True)
+        g = parts.to_numpy()
+        lost = np.nonzero(g["state"] == 0)[0]
+        pick = lost[:: max(1, len(lost) // 2000)]
+        o = oracle.Particles(len(pick))
+        for f in oracle.FLOAT_FIELDS + oracle.INT_FIELDS:
+            getattr(o, f)[:] = g[f][pick]
+        o.particle_id[:] = g["particle_id"][pick]
+        t = time.perf_counter()
+        oracle.refine_losses(el, ref, o, M, ds, nb)
+        dt = time.perf_counter() - t
+        out_line["cpu_baseline"] = {"value": len(pick) / dt, "unit": "losses/s", "cores": 1,
+                                    "kind": "oracle",
+                                    "sample": f"{len(pick)} of the {len(lost)} losses "
+                                              f"(every {max(1, len(lost) // 2000)}th) in {dt:.1f} s"}
+    print(json.dumps(out_line), flush=True)
+
+
 def learned_da(args):
     """Dynamic-aperture scan of the cfg1 ring: plain tracking to the horizon
     versus learned early stop (network) and the tune-diffusion rule, on the
@@ -231,7 +322,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--turns-per-step", type=int, default=None)
     ap.add_argument("--workload", default="cfg2",
-                    choices=["cfg2", "cfg1", "cfg1sat", "cfg3", "cfg4", "cfg5"])
+                    choices=["cfg2", "cfg1", "cfg1sat", "cfg3", "cfg4", "cfg5", "refine"])
+    ap.add_argument("--refine-vertices", type=int, default=64,
+                    help="refine: polygon vertices per aperture")
+    ap.add_argument("--refine-ds", type=float, default=0.01, help="refine: sub-step [m]")
+    ap.add_argument("--refine-bisect", type=int, default=30, help="refine: bisection steps")
     ap.add_argument("--da-rays", type=int, default=500, help="cfg4: rays of the evaluation grid")
     ap.add_argument("--da-radii", type=int, default=2000, help="cfg4: radii per ray")
     ap.add_argument("--da-rmax", type=float, default=30.0, help="cfg4: grid edge [sigma]")
@@ -285,6 +380,8 @@ def main():
         return
     if args.workload == "cfg4":
         return learned_da(args)
+    if args.workload == "refine":
+        return refine_bench(args)
     el, coords, ref, desc, tps_default, steps_default = workload(args.workload, args.particles)
     tps = args.turns_per_step or tps_default
     steps = args.steps if args.steps is not None else steps_default

@@ -261,7 +261,10 @@ xtm_status xtm_track_per_element(xtm_lattice lat, xtm_particles p, int32_t n_tur
    (s = 0 at the line start, increasing through the drifts, negative for a
    loss before the line start on the way from the previous turn's last
    aperture), d_x[i], d_y[i] = its position in the line frame [m]; NaN for
-   particles not lost on an aperture.  A particle whose path never leaves the
+   particles not lost on an aperture; d_tests (device int32 array of the
+   set's length, or NULL): number of polygon tests made for each particle
+   (sub-step ends and bisection points; 0 for particles not refined).  A
+   particle whose path never leaves the
    interpolated polygon, or whose backtracking meets an imaginary
    longitudinal momentum, gets s of e_L and its position there.  Radiation is
    not undone.  Arguments: n_vertices 4..4096, ds > 0 (at most 1e8 sub-steps
@@ -272,7 +275,7 @@ xtm_status xtm_track_per_element(xtm_lattice lat, xtm_particles p, int32_t n_tur
    particle. */
 xtm_status xtm_refine_losses(xtm_lattice lat, xtm_particles p, int32_t n_vertices, double ds,
                              int32_t n_bisect, double* d_s, double* d_x, double* d_y,
-                             void* stream);
+                             int32_t* d_tests, void* stream);
 
 /* Copy the loss record into host buffers of the bound length (any may be
    NULL).  Synchronises the stream. */

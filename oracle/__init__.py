@@ -173,7 +173,7 @@ def track_backward(elements, ref, parts: Particles, n_turns: int, nthreads: int 
 
 
 def refine_losses(elements, ref, parts: Particles, n_vertices: int = 64, ds: float = 0.01,
-                  n_bisect: int = 30):
+                  n_bisect: int = 30, with_tests: bool = False):
     """Loss-location refinement of the particles lost on an aperture: (s, x, y)
     of the first exit from the polygon-interpolated aperture between the
     previous aperture and the one that caught each particle, NaN elsewhere
@@ -182,15 +182,16 @@ def refine_losses(elements, ref, parts: Particles, n_vertices: int = 64, ds: flo
     r = _ref3(ref)
     st = parts._struct()
     out = [np.zeros(parts.n, dtype=np.float64) for _ in range(3)]
+    tests = np.zeros(parts.n, dtype=np.int32)
     f = lib().oracle_refine_losses
     f.restype = ctypes.c_int
     rc = f(el.ctypes.data_as(ctypes.c_void_p), ctypes.c_int32(len(el)),
            r.ctypes.data_as(ctypes.c_void_p), ctypes.byref(st), ctypes.c_int32(n_vertices),
            ctypes.c_double(ds), ctypes.c_int32(n_bisect),
-           *[a.ctypes.data_as(ctypes.c_void_p) for a in out])
+           *[a.ctypes.data_as(ctypes.c_void_p) for a in out + [tests]])
     if rc != 0:
         raise ValueError("oracle_refine_losses rejected its input (code %d)" % rc)
-    return tuple(out)
+    return tuple(out) + ((tests,) if with_tests else ())
 
 
 def reference(ref) -> tuple[float, float]:

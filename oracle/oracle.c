@@ -708,6 +708,7 @@ void oracle_philox_constants(uint32_t out[4]) {
    (a11 x + a12 y) + b1; the crossing test compares
    (xj - xi)(py - yi) - (px - xi)(yj - yi) with zero; everything else is one
    correctly rounded operation per written operator.
+   tests (optional) receives the number of polygon tests made per particle.
    Returns 0, -1 on bad arguments, -2 on bad elements, -6 when a
    rectangle does not contain its origin. */
 typedef struct { double a11, a12, a21, a22, b1, b2; } orc_frame;
@@ -747,7 +748,7 @@ static int o_in_poly(double px, double py, const double* P, const double* Lp, in
 
 int oracle_refine_losses(const orc_elem* el, int32_t n_el, const double ref3[3],
                          const orc_parts* P, int32_t M, double ds, int32_t n_bisect,
-                         double* s_out, double* x_out, double* y_out) {
+                         double* s_out, double* x_out, double* y_out, int32_t* tests) {
   if (n_el <= 0 || M < 4 || !(ds > 0.0) || n_bisect < 0 || n_bisect > 60) return -1;
   if (validate(el, n_el)) return -2;
   orc_ref r = make_ref(ref3);
@@ -814,6 +815,8 @@ int oracle_refine_losses(const orc_elem* el, int32_t n_el, const double ref3[3],
   }
   for (int64_t i = 0; i < P->n; ++i) {
     s_out[i] = NAN; x_out[i] = NAN; y_out[i] = NAN;
+    int32_t nt = 0;
+    if (tests) tests[i] = 0;
     int32_t eL = P->at_element[i];
     if (P->state[i] != 0 || eL < 0 || eL >= n_el || !o_is_ap(el[eL].type)) continue;
     int32_t eP = prev[eL];
@@ -854,12 +857,16 @@ int oracle_refine_losses(const orc_elem* el, int32_t n_el, const double ref3[3],
           double f = (double)k / (double)K;
           double sf = sc + L * f;
           double w = (sf - sP) / (sL - sP);
+          ++nt;
+          if (tests) tests[i] = nt;
           if (o_in_poly(o_lerp(v0x, v1x, f), o_lerp(v0y, v1y, f), PP, PL, M, w)) continue;
           double lo = (double)(k - 1) / (double)K, hi = f;
           for (int32_t b = 0; b < n_bisect; ++b) {
             double m = 0.5 * (lo + hi);
             double sm = sc + L * m;
             double wm = (sm - sP) / (sL - sP);
+            ++nt;
+            if (tests) tests[i] = nt;
             if (o_in_poly(o_lerp(v0x, v1x, m), o_lerp(v0y, v1y, m), PP, PL, M, wm))
               lo = m;
             else

@@ -89,7 +89,7 @@ def lib() -> ctypes.CDLL:
             "xtm_track": ([vp, vp, i32, vp, vp, vp], i32),
             "xtm_track_backward": ([vp, vp, i32, vp, vp], i32),
             "xtm_track_per_element": ([vp, vp, i32, vp, vp], i32),
-            "xtm_refine_losses": ([vp, vp, i32, ctypes.c_double, i32, vp, vp, vp, vp], i32),
+            "xtm_refine_losses": ([vp, vp, i32, ctypes.c_double, i32, vp, vp, vp, vp, vp], i32),
             "xtm_get_losses": ([vp, vp, vp, vp, vp], i32),
             "xtm_sync": ([vp], i32),
             "xtm_philox4x32_10": ([ctypes.c_uint64, vp, i64, vp, vp], i32),
@@ -365,18 +365,21 @@ def track_per_element(lattice: Lattice, particles: Particles, n_turns: int, stre
 
 
 def refine_losses(lattice: Lattice, particles: Particles, n_vertices: int = 64, ds: float = 0.01,
-                  n_bisect: int = 30, stream=None):
+                  n_bisect: int = 30, stream=None, with_tests: bool = False):
     """Loss locations of the particles lost on an aperture (backtracking
     against a polygon-interpolated aperture; xtm_refine_losses): device
     tensors (s, x, y) of the set's length, NaN for particles not lost on an
-    aperture."""
+    aperture; with_tests adds the int32 tensor of polygon tests per particle."""
     import torch
-    out = [torch.empty(max(particles.n, 1), dtype=torch.float64, device=particles.device)
-           for _ in range(3)]
+    m = max(particles.n, 1)
+    out = [torch.empty(m, dtype=torch.float64, device=particles.device) for _ in range(3)]
+    tests = torch.empty(m, dtype=torch.int32, device=particles.device) if with_tests else None
     check(lib().xtm_refine_losses(lattice.handle, particles.handle, int(n_vertices), float(ds),
                                   int(n_bisect), *[ctypes.c_void_p(t.data_ptr()) for t in out],
+                                  ctypes.c_void_p(tests.data_ptr() if with_tests else 0),
                                   _stream(stream)), "xtm_refine_losses")
-    return tuple(t[:particles.n] for t in out)
+    res = tuple(t[:particles.n] for t in out)
+    return res + (tests[:particles.n],) if with_tests else res
 
 
 def track_backward(lattice: Lattice, particles: Particles, n_turns: int, stats: bool = True,

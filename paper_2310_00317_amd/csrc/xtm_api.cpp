@@ -1483,7 +1483,7 @@ xtm_status build_refine_geometry(xtm_lattice_s* L, int32_t M) {
 
 xtm_status xtm_refine_losses(xtm_lattice L, xtm_particles P, int32_t n_vertices, double ds,
                              int32_t n_bisect, double* d_s, double* d_x, double* d_y,
-                             void* stream) {
+                             int32_t* d_tests, void* stream) {
   return guarded([&]() -> xtm_status {
     if (!L || !P) return fail(XTM_E_ARG, "null lattice or particle set");
     if (!P->initialised) return fail(XTM_E_STATE, "particle set not initialised");
@@ -1504,7 +1504,7 @@ xtm_status xtm_refine_losses(xtm_lattice L, xtm_particles P, int32_t n_vertices,
     g.ds = ds;
     g.n_bisect = n_bisect;
     HIP_TRY(launch_refine(L->fwd_d, L->bwd_d, g, soa_of(P), P->n, kref(L->ref, 0, 0), d_s, d_x,
-                          d_y, (hipStream_t)stream),
+                          d_y, d_tests, (hipStream_t)stream),
             "refinement launch");
     return XTM_OK;
   });

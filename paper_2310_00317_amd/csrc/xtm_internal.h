@@ -125,7 +125,7 @@ struct RefineGeom {
 };
 hipError_t launch_refine(const uint64_t* fwd, const uint64_t* bwd, const RefineGeom& g, SoA P,
                          int64_t n, KernelRef r, double* s_out, double* x_out, double* y_out,
-                         hipStream_t s);
+                         int32_t* tests, hipStream_t s);
 
 // Per-line tracking kernel generated from the lattice's cell structure and
 // compiled at run time (xtm_jit.cpp).

@@ -1257,11 +1257,12 @@ __device__ __forceinline__ bool is_drift_k(uint32_t kt) { return kt == K_DRIFT |
 __global__ void __launch_bounds__(256)
 k_refine(const uint64_t* __restrict__ fwd, const uint64_t* __restrict__ bwd, RefineGeom g, SoA P,
          int64_t n, KernelRef r, double* __restrict__ s_out, double* __restrict__ x_out,
-         double* __restrict__ y_out) {
+         double* __restrict__ y_out, int32_t* __restrict__ tests) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const double nan = __builtin_nan("");
   double so = nan, xo = nan, yo = nan;
+  int32_t nt = 0;
   const int32_t eL = P.at_element[i];
   const int32_t n_el = g.n_el;
   if (P.state[i] == 0 && eL >= 0 && eL < n_el && g.ap_ord[eL] >= 0) {
@@ -1312,12 +1313,14 @@ k_refine(const uint64_t* __restrict__ fwd, const uint64_t* __restrict__ bwd, Ref
               const double f = (double)k / (double)K;
               const double sf = sc + L * f;
               const double w = (sf - sP) / (sL - sP);
+              ++nt;
               if (in_poly(lerp_f(v0x, v1x, f), lerp_f(v0y, v1y, f), A, B, g.M, w)) continue;
               double lo = (double)(k - 1) / (double)K, hi = f;
               for (int32_t b = 0; b < g.n_bisect; ++b) {
                 const double m = 0.5 * (lo + hi);
                 const double sm = sc + L * m;
                 const double wm = (sm - sP) / (sL - sP);
+                ++nt;
                 if (in_poly(lerp_f(v0x, v1x, m), lerp_f(v0y, v1y, m), A, B, g.M, wm))
                   lo = m;
                 else
@@ -1339,17 +1342,18 @@ k_refine(const uint64_t* __restrict__ fwd, const uint64_t* __restrict__ bwd, Ref
   s_out[i] = so;
   x_out[i] = xo;
   y_out[i] = yo;
+  if (tests) tests[i] = nt;
 }
 
 }  // namespace
 
 hipError_t launch_refine(const uint64_t* fwd, const uint64_t* bwd, const RefineGeom& g, SoA P,
                          int64_t n, KernelRef r, double* s_out, double* x_out, double* y_out,
-                         hipStream_t s) {
+                         int32_t* tests, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   const int64_t blocks = (n + 255) / 256;
   hipLaunchKernelGGL(k_refine, dim3((unsigned)blocks), dim3(256), 0, s, fwd, bwd, g, P, n, r,
-                     s_out, x_out, y_out);
+                     s_out, x_out, y_out, tests);
   return hipGetLastError();
 }
 

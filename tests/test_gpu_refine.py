@@ -33,11 +33,11 @@ def banner(msg):
 
 def refine_both(P, oracle_mod, el, lat, parts, o, M, ds, nb):
     import torch
-    s, x, y = P.refine_losses(lat, parts, M, ds, nb)
+    s, x, y, t = P.refine_losses(lat, parts, M, ds, nb, with_tests=True)
     torch.cuda.synchronize()
-    g = {"s": s.cpu().numpy(), "x": x.cpu().numpy(), "y": y.cpu().numpy()}
-    so, xo, yo = oracle_mod.refine_losses(el, REF, o, M, ds, nb)
-    assert_bitwise(g, {"s": so, "x": xo, "y": yo}, fields=("s", "x", "y"))
+    g = {"s": s.cpu().numpy(), "x": x.cpu().numpy(), "y": y.cpu().numpy(), "t": t.cpu().numpy()}
+    so, xo, yo, to = oracle_mod.refine_losses(el, REF, o, M, ds, nb, with_tests=True)
+    assert_bitwise(g, {"s": so, "x": xo, "y": yo, "t": to}, fields=("s", "x", "y", "t"))
     lost = o.state == 0
     assert np.isnan(g["s"][~lost]).all() and not np.isnan(g["s"][lost]).any()
     return g
