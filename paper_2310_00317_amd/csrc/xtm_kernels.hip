@@ -1203,14 +1203,17 @@ hipError_t launch_replay(const uint64_t* tab, int32_t n_el, SoA P, const int32_t
 }  // namespace xtm
 
 // ------------------------------------------------ loss-location refinement
-// One thread per particle of the set.  A particle lost on an aperture is
-// backtracked through the inverse maps to the exit of the previous aperture,
-// then tracked forward again; inside each drift its line-frame position runs
-// on the segment between the drift's entry and exit, and the ends of the
-// drift's sub-steps are tested against the aperture interpolated vertex by
-// vertex between the two polygons; the first failing sub-step is bisected.
-// Every operation is the one written in the refinement definition (explicit
-// fma for interpolation, separate products and sums elsewhere).
+// One wave per particle, one polygon edge per lane.  A particle lost on an
+// aperture is backtracked through the inverse maps to the exit of the
+// previous aperture, then tracked forward again (every lane carries the same
+// particle); inside each drift its line-frame position runs on the segment
+// between the drift's entry and exit, and the ends of the drift's sub-steps
+// are tested against the aperture interpolated vertex by vertex between the
+// two polygons: lane k tests edge (k, k+1), the even-odd parity is the
+// parity of the wave's ballot (the exclusive-or of the same per-edge tests
+// in any order).  The first failing sub-step is bisected.  Every operation
+// is the one written in the refinement definition (explicit fma for
+// interpolation, separate products and sums elsewhere).
 namespace xtm {
 namespace {
 
@@ -1226,19 +1229,59 @@ __device__ __forceinline__ void to_line(const double* __restrict__ g, double ux,
   ly = (t3 + t4) + g[5];
 }
 
-__device__ bool in_poly(double px, double py, const double* __restrict__ A,
-                        const double* __restrict__ B, int32_t M, double w) {
+// crossing of the horizontal ray from (px, py) with the edge from vertex i to
+// vertex j of the polygon A + w (B - A)
+__device__ __forceinline__ bool edge_toggle(double px, double py, double axi, double ayi,
+                                            double bxi, double byi, double axj, double ayj,
+                                            double bxj, double byj, double w) {
+  const double xi = lerp_f(axi, bxi, w), yi = lerp_f(ayi, byi, w);
+  const double xj = lerp_f(axj, bxj, w), yj = lerp_f(ayj, byj, w);
+  if ((yi > py) == (yj > py)) return false;
+  const double t1 = (xj - xi) * (py - yi);
+  const double t2 = (px - xi) * (yj - yi);
+  const double cr = t1 - t2;
+  return yj > yi ? cr > 0.0 : cr < 0.0;
+}
+
+// the lane's edge of a polygon of at most 64 vertices, held in registers
+struct Edge {
+  bool on;
+  double axi, ayi, bxi, byi, axj, ayj, bxj, byj;
+};
+
+__device__ __forceinline__ bool in_poly_wave(double px, double py, const Edge& e,
+                                             const double* __restrict__ A,
+                                             const double* __restrict__ B, int32_t M, double w) {
+  bool t = false;
+  if (M <= 64) {
+    t = e.on && edge_toggle(px, py, e.axi, e.ayi, e.bxi, e.byi, e.axj, e.ayj, e.bxj, e.byj, w);
+  } else {
+    for (int32_t k = threadIdx.x; k < M; k += 64) {
+      const int32_t kn = (k + 1 == M) ? 0 : k + 1;
+      t ^= edge_toggle(px, py, A[2 * k], A[2 * k + 1], B[2 * k], B[2 * k + 1], A[2 * kn],
+                       A[2 * kn + 1], B[2 * kn], B[2 * kn + 1], w);
+    }
+  }
+  return (__popcll(__ballot(t)) & 1) != 0;
+}
+
+// the whole polygon A + w (B - A) for one lane's point, vertices from LDS
+// ((x, y) pairs), each vertex interpolated once and carried to the next edge
+__device__ __forceinline__ bool in_poly_lane(double px, double py, const double2* A,
+                                             const double2* B, int32_t M, double w) {
   bool in = false;
-  double xi = lerp_f(A[0], B[0], w), yi = lerp_f(A[1], B[1], w);
-  const double x0 = xi, y0 = yi;
+  const double2 a0 = A[0], b0 = B[0];
+  const double x0 = lerp_f(a0.x, b0.x, w), y0 = lerp_f(a0.y, b0.y, w);
+  double xi = x0, yi = y0;
   for (int32_t k = 0; k < M; ++k) {
     double xj, yj;
     if (k + 1 == M) {
       xj = x0;
       yj = y0;
     } else {
-      xj = lerp_f(A[2 * k + 2], B[2 * k + 2], w);
-      yj = lerp_f(A[2 * k + 3], B[2 * k + 3], w);
+      const double2 a = A[k + 1], b = B[k + 1];
+      xj = lerp_f(a.x, b.x, w);
+      yj = lerp_f(a.y, b.y, w);
     }
     if ((yi > py) != (yj > py)) {
       const double t1 = (xj - xi) * (py - yi);
@@ -1254,11 +1297,15 @@ __device__ bool in_poly(double px, double py, const double* __restrict__ A,
 
 __device__ __forceinline__ bool is_drift_k(uint32_t kt) { return kt == K_DRIFT || kt == K_DRIFT_EXP; }
 
-__global__ void __launch_bounds__(256)
+// polygons of up to this many vertices are staged in LDS and the drift scan
+// tests 64 consecutive sub-steps at once (one per lane)
+constexpr int32_t kRefineLdsVerts = 256;
+
+__global__ void __launch_bounds__(64)
 k_refine(const uint64_t* __restrict__ fwd, const uint64_t* __restrict__ bwd, RefineGeom g, SoA P,
          int64_t n, KernelRef r, double* __restrict__ s_out, double* __restrict__ x_out,
          double* __restrict__ y_out, int32_t* __restrict__ tests) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t i = blockIdx.x;
   if (i >= n) return;
   const double nan = __builtin_nan("");
   double so = nan, xo = nan, yo = nan;
@@ -1286,8 +1333,26 @@ k_refine(const uint64_t* __restrict__ fwd, const uint64_t* __restrict__ bwd, Ref
         if (!okj) { ok = false; break; }
       }
       if (ok) {
-        const double* A = g.poly + (size_t)g.ap_ord[eP] * 2 * g.M;
-        const double* B = g.poly + (size_t)g.ap_ord[eL] * 2 * g.M;
+        const int32_t M = g.M;
+        const double* A = g.poly + (size_t)g.ap_ord[eP] * 2 * M;
+        const double* B = g.poly + (size_t)g.ap_ord[eL] * 2 * M;
+        __shared__ double2 polyA[kRefineLdsVerts], polyB[kRefineLdsVerts];
+        const bool lds = M <= kRefineLdsVerts;
+        if (lds) {
+          for (int32_t v = threadIdx.x; v < M; v += 64) {
+            polyA[v] = make_double2(A[2 * v], A[2 * v + 1]);
+            polyB[v] = make_double2(B[2 * v], B[2 * v + 1]);
+          }
+          __syncthreads();
+        }
+        Edge e{};
+        const int32_t k = threadIdx.x;
+        e.on = M <= 64 && k < M;
+        if (e.on) {
+          const int32_t kn = (k + 1 == M) ? 0 : k + 1;
+          e.axi = A[2 * k]; e.ayi = A[2 * k + 1]; e.bxi = B[2 * k]; e.byi = B[2 * k + 1];
+          e.axj = A[2 * kn]; e.ayj = A[2 * kn + 1]; e.bxj = B[2 * kn]; e.byj = B[2 * kn + 1];
+        }
         double sc = sP;
         for (int32_t j = (eP + 1) % n_el; j != eL; j = (j + 1) % n_el) {
           const uint64_t h = fwd[g.off_f[j]];
@@ -1309,19 +1374,50 @@ k_refine(const uint64_t* __restrict__ fwd, const uint64_t* __restrict__ bwd, Ref
           if (L > 0.0) {
             long long K = (long long)ceil(L / g.ds);
             if (K < 1) K = 1;
-            for (long long k = 1; k <= K; ++k) {
-              const double f = (double)k / (double)K;
-              const double sf = sc + L * f;
-              const double w = (sf - sP) / (sL - sP);
-              ++nt;
-              if (in_poly(lerp_f(v0x, v1x, f), lerp_f(v0y, v1y, f), A, B, g.M, w)) continue;
-              double lo = (double)(k - 1) / (double)K, hi = f;
+            long long kf = 0;  // first sub-step whose end is outside (0: none)
+            if (lds) {
+              // 64 sub-steps per pass, lane l testing sub-step base + 1 + l
+              for (long long base = 0; base < K && kf == 0; base += 64) {
+                const long long kk = base + 1 + threadIdx.x;
+                bool out = false;
+                if (kk <= K) {
+                  const double f = (double)kk / (double)K;
+                  const double sf = sc + L * f;
+                  const double w = (sf - sP) / (sL - sP);
+                  out = !in_poly_lane(lerp_f(v0x, v1x, f), lerp_f(v0y, v1y, f), polyA, polyB,
+                                      M, w);
+                }
+                const unsigned long long mask = __ballot(out);
+                if (mask) {
+                  const int first = __ffsll((long long)mask) - 1;
+                  kf = base + 1 + first;
+                  nt += first + 1;
+                } else {
+                  nt += (int32_t)((K - base) < 64 ? (K - base) : 64);
+                }
+              }
+            } else {
+              for (long long kk = 1; kk <= K; ++kk) {
+                const double f = (double)kk / (double)K;
+                const double sf = sc + L * f;
+                const double w = (sf - sP) / (sL - sP);
+                ++nt;
+                if (!in_poly_wave(lerp_f(v0x, v1x, f), lerp_f(v0y, v1y, f), e, A, B, M, w)) {
+                  kf = kk;
+                  break;
+                }
+              }
+            }
+            if (kf > 0) {
+              const long long kk = kf;
+              const double f = (double)kk / (double)K;
+              double lo = (double)(kk - 1) / (double)K, hi = f;
               for (int32_t b = 0; b < g.n_bisect; ++b) {
                 const double m = 0.5 * (lo + hi);
                 const double sm = sc + L * m;
                 const double wm = (sm - sP) / (sL - sP);
                 ++nt;
-                if (in_poly(lerp_f(v0x, v1x, m), lerp_f(v0y, v1y, m), A, B, g.M, wm))
+                if (in_poly_wave(lerp_f(v0x, v1x, m), lerp_f(v0y, v1y, m), e, A, B, M, wm))
                   lo = m;
                 else
                   hi = m;
@@ -1330,7 +1426,6 @@ k_refine(const uint64_t* __restrict__ fwd, const uint64_t* __restrict__ bwd, Ref
               xo = lerp_f(v0x, v1x, hi);
               yo = lerp_f(v0y, v1y, hi);
               found = true;
-              break;
             }
           }
           if (found) break;
@@ -1339,10 +1434,12 @@ k_refine(const uint64_t* __restrict__ fwd, const uint64_t* __restrict__ bwd, Ref
       }
     }
   }
-  s_out[i] = so;
-  x_out[i] = xo;
-  y_out[i] = yo;
-  if (tests) tests[i] = nt;
+  if (threadIdx.x == 0) {
+    s_out[i] = so;
+    x_out[i] = xo;
+    y_out[i] = yo;
+    if (tests) tests[i] = nt;
+  }
 }
 
 }  // namespace
@@ -1351,9 +1448,9 @@ hipError_t launch_refine(const uint64_t* fwd, const uint64_t* bwd, const RefineG
                          int64_t n, KernelRef r, double* s_out, double* x_out, double* y_out,
                          int32_t* tests, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  const int64_t blocks = (n + 255) / 256;
-  hipLaunchKernelGGL(k_refine, dim3((unsigned)blocks), dim3(256), 0, s, fwd, bwd, g, P, n, r,
-                     s_out, x_out, y_out, tests);
+  if (n > 0x7fffffffLL) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_refine, dim3((unsigned)n), dim3(64), 0, s, fwd, bwd, g, P, n, r, s_out,
+                     x_out, y_out, tests);
   return hipGetLastError();
 }
 
