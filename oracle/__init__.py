@@ -194,6 +194,111 @@ def refine_losses(elements, ref, parts: Particles, n_vertices: int = 64, ds: flo
     return tuple(out) + ((tests,) if with_tests else ())
 
 
+def track_record(elements, ref, coords6) -> np.ndarray:
+    """One turn from the line start with the coordinates recorded at every
+    element entry and after the last element: array (n_el + 1, n, 6) of
+    (x, px, y, py, zeta, delta); apertures are not checked."""
+    el = _els(elements)
+    r = _ref3(ref)
+    c = np.ascontiguousarray(coords6, dtype=np.float64).reshape(-1, 6)
+    out = np.zeros((len(el) + 1, c.shape[0], 6))
+    f = lib().oracle_track_record
+    f.restype = ctypes.c_int
+    rc = f(el.ctypes.data_as(ctypes.c_void_p), ctypes.c_int32(len(el)),
+           r.ctypes.data_as(ctypes.c_void_p), c.ctypes.data_as(ctypes.c_void_p),
+           ctypes.c_int64(c.shape[0]), out.ctypes.data_as(ctypes.c_void_p))
+    if rc != 0:
+        raise ValueError("oracle_track_record rejected its input (code %d)" % rc)
+    return out
+
+
+def twiss(elements, ref, delta0: float = 0.0, h: float = 1e-8, hd: float = 1e-7,
+          max_iter: int = 30, tol: float = 1e-15, guess=None) -> dict:
+    """Optics by tracking (paper section "Twiss module"), transverse and
+    uncoupled, at fixed momentum deviation delta0 (RF and longitudinal motion
+    frozen: zeta starts at 0 and is not part of the orbit):
+      1. closed orbit u* = T(u*) of the one-turn map on (x, px, y, py) by
+         Newton's method, u <- u + (I - J)^-1 (T(u) - u), until the largest
+         component of T(u) - u is below tol (or stops decreasing);
+      2. Jacobian J of the one-turn map by central differences of particles
+         displaced by +-h along each coordinate, and the momentum column m by
+         +-hd in delta;
+      3. the same differences at every element give the map M_e from the line
+         start to element e and its momentum column m_e;
+      4. per plane, from the one-turn 2x2 block [[a, b], [c, d]]:
+         cos mu = (a + d)/2, sin mu = sign(b) sqrt(1 - cos^2 mu),
+         beta0 = b / sin mu, alpha0 = (a - d)/(2 sin mu); at element e with
+         block [[p, q], [r, t]] of M_e: beta = ((p beta0 - q alpha0)^2 + q^2)/beta0,
+         alpha = -((p beta0 - q alpha0)(r beta0 - t alpha0) + q t)/beta0,
+         phase = atan2(q, p beta0 - q alpha0), unwrapped to increase;
+      5. dispersion eta_0 = (I - J)^-1 m, eta_e = M_e eta_0 + m_e.
+    Returns the per-element table (n_el + 1 rows) and the tunes."""
+    el = _els(elements)
+    n_el = len(el)
+    u = np.zeros(4) if guess is None else np.array(guess, dtype=np.float64)
+    I4 = np.eye(4)
+
+    def probe(u, with_delta):
+        rows = [np.r_[u, 0.0, delta0]]
+        for k in range(4):
+            for sgn in (1.0, -1.0):
+                v = np.r_[u, 0.0, delta0]
+                v[k] += sgn * h
+                rows.append(v)
+        if with_delta:
+            for sgn in (1.0, -1.0):
+                rows.append(np.r_[u, 0.0, delta0 + sgn * hd])
+        return np.array(rows)
+
+    it, res, best = 0, np.inf, np.inf
+    while True:
+        out = track_record(el, ref, probe(u, False))
+        end = out[n_el]
+        J = np.empty((4, 4))
+        for k in range(4):
+            J[:, k] = (end[1 + 2 * k, :4] - end[2 + 2 * k, :4]) / (2.0 * h)
+        F = end[0, :4] - u
+        res = float(np.max(np.abs(F)))
+        if res <= tol or it >= max_iter or res >= best:
+            break
+        best = res
+        u = u + np.linalg.solve(I4 - J, F)
+        it += 1
+    out = track_record(el, ref, probe(u, True))
+    M = np.empty((n_el + 1, 4, 4))
+    for k in range(4):
+        M[:, :, k] = (out[:, 1 + 2 * k, :4] - out[:, 2 + 2 * k, :4]) / (2.0 * h)
+    md = (out[:, 9, :4] - out[:, 10, :4]) / (2.0 * hd)
+    J = M[n_el]
+    eta0 = np.linalg.solve(I4 - J, md[n_el])
+    eta = np.einsum("eij,j->ei", M, eta0) + md
+    tab = {"s": np.concatenate([[0.0], np.cumsum(np.where(np.isin(el["type"], (1, 2)),
+                                                          el["length"], 0.0))]),
+           "x": out[:, 0, 0], "px": out[:, 0, 1], "y": out[:, 0, 2], "py": out[:, 0, 3],
+           "dx": eta[:, 0], "dpx": eta[:, 1], "dy": eta[:, 2], "dpy": eta[:, 3]}
+    q = {}
+    for name, o in (("x", 0), ("y", 2)):
+        a, b, c, d = J[o, o], J[o, o + 1], J[o + 1, o], J[o + 1, o + 1]
+        cmu = 0.5 * (a + d)
+        smu = math.copysign(math.sqrt(max(0.0, 1.0 - cmu * cmu)), b)
+        b0 = b / smu
+        a0 = (a - d) / (2.0 * smu)
+        p_, q_, r_, t_ = M[:, o, o], M[:, o, o + 1], M[:, o + 1, o], M[:, o + 1, o + 1]
+        bb = p_ * b0 - q_ * a0
+        tab["bet" + name] = (bb * bb + q_ * q_) / b0
+        tab["alf" + name] = -(bb * (r_ * b0 - t_ * a0) + q_ * t_) / b0
+        th = np.arctan2(q_, bb)
+        mu = np.zeros(n_el + 1)
+        for e in range(1, n_el + 1):
+            mu[e] = mu[e - 1] + (th[e] - th[e - 1]) % (2.0 * math.pi)
+        tab["mu" + name] = mu
+        q["q" + name] = mu[n_el] / (2.0 * math.pi)
+    tab.update(q)
+    tab["iterations"] = it
+    tab["residual"] = res
+    return tab
+
+
 def reference(ref) -> tuple[float, float]:
     """(beta0, gamma0) as the oracle computes them."""
     out = np.zeros(2)

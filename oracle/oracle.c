@@ -886,3 +886,43 @@ done:
   free(c); free(s); free(G); free(prev); free(poly);
   return rc;
 }
+
+/* ------------------------------------------------------ optics by tracking */
+
+/* One turn of n particles from the line start with the coordinates
+   (x, px, y, py, zeta, delta) recorded at the entry of every element and
+   after the last: out[(e n + i) 6 + c], e = 0..n_el.  Apertures are not
+   checked (the optics of the bare lattice, paper section "Twiss module");
+   a particle whose drift leaves the longitudinal-momentum window keeps the
+   coordinates it entered that drift with.  Set-up as oracle_init. */
+int oracle_track_record(const orc_elem* el, int32_t n_el, const double ref3[3],
+                        const double* coords6, int64_t n, double* out) {
+  if (n_el < 0 || n < 0) return -1;
+  if (validate(el, n_el)) return -2;
+  orc_ref r = make_ref(ref3);
+  orc_coef* c = build_coefs(el, n_el);
+  for (int64_t i = 0; i < n; ++i) {
+    orc_pt q;
+    memset(&q, 0, sizeof q);
+    q.x = coords6[6 * i + 0]; q.px = coords6[6 * i + 1];
+    q.y = coords6[6 * i + 2]; q.py = coords6[6 * i + 3];
+    q.zeta = coords6[6 * i + 4]; q.delta = coords6[6 * i + 5];
+    set_from_delta(&q, r.beta0);
+    int alive = 1;
+    for (int32_t e = 0; e <= n_el; ++e) {
+      double* o = out + ((size_t)e * (size_t)n + (size_t)i) * 6;
+      o[0] = q.x; o[1] = q.px; o[2] = q.y; o[3] = q.py; o[4] = q.zeta; o[5] = q.delta;
+      if (e == n_el || !alive || el[e].type == O_AP_CIRC || el[e].type == O_AP_ELL ||
+          el[e].type == O_AP_RECT)
+        continue;
+      orc_pt q0 = q;
+      double fkx, fky;
+      if (apply(&q, &el[e], &c[e], &r, 1.0, &fkx, &fky) != 1) {
+        q = q0;
+        alive = 0;
+      }
+    }
+  }
+  free(c);
+  return 0;
+}

@@ -1,0 +1,96 @@
+"""Pins of the oracle's optics by tracking (closed orbit by Newton's method,
+central-difference Jacobian, uncoupled normal form, propagation through the
+line; paper section "Twiss module") against thin-lens closed forms, the
+drift propagation law, the closed orbit of a single kick, and dispersion
+taken as the momentum derivative of closed orbits found independently."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2310_00317_amd import inputs as I
+
+REF = I.PROTON_450GEV
+
+
+def fodo_closed_form():
+    f, L = I.CFG1_F, I.CFG1_HALF
+    mu = math.acos(1.0 - L * L / (2.0 * f * f))
+    bmax = 2.0 * L * (1.0 + math.sin(mu / 2)) / math.sin(mu)
+    bmin = 2.0 * L * (1.0 - math.sin(mu / 2)) / math.sin(mu)
+    return f, L, mu, bmax, bmin
+
+
+@pytest.mark.parametrize("sext", [False, True])
+def test_fodo_ring_thin_lens_closed_forms(oracle_mod, sext):
+    el = I.cfg1_lattice(rf_on=False, sextupoles=sext)
+    tw = oracle_mod.twiss(el, REF, h=1e-10)
+    f, L, mu, bmax, bmin = fodo_closed_form()
+    assert tw["iterations"] == 0 and tw["residual"] == 0.0  # the orbit is the axis
+    assert abs(tw["qx"] - 100 * mu / (2 * math.pi)) < 1e-9
+    assert abs(tw["qy"] - 100 * mu / (2 * math.pi)) < 1e-9
+    qf, qd = 1 + 8 * np.arange(100), 5 + 8 * np.arange(100)
+    for b, a, m, big, small in (("betx", "alfx", "mux", qf, qd), ("bety", "alfy", "muy", qd, qf)):
+        assert np.allclose(tw[b][big], bmax, rtol=1e-9, atol=0)
+        assert np.allclose(tw[b][small], bmin, rtol=1e-9, atol=0)
+        # entry of a thin focusing lens of the symmetric cell: alpha = -beta / (2 f)
+        assert np.allclose(tw[a][big], -bmax / (2 * f), rtol=1e-8, atol=0)
+        assert np.allclose(np.diff(tw[m][qf]), mu, rtol=0, atol=1e-10)
+    assert np.allclose(tw["dx"], 0.0, atol=1e-9) and np.allclose(tw["dy"], 0.0, atol=1e-9)
+
+
+def test_drift_propagation_law(oracle_mod):
+    el = I.cfg1_lattice(rf_on=False)
+    tw = oracle_mod.twiss(el, REF, h=1e-10)
+    drifts = np.nonzero(el["type"] == I.DRIFT)[0]
+    for p in ("x", "y"):
+        b, a = tw["bet" + p], tw["alf" + p]
+        g = (1 + a * a) / b
+        L = el["length"][drifts]
+        e = drifts
+        assert np.allclose(b[e + 1], b[e] - 2 * a[e] * L + g[e] * L * L, rtol=1e-9)
+        assert np.allclose(a[e + 1], a[e] - g[e] * L, rtol=1e-9, atol=1e-9)
+        # phase advance through a drift: atan of L / (beta - alpha L)
+        dmu = np.arctan2(L, b[e] - a[e] * L)
+        assert np.allclose(tw["mu" + p][e + 1] - tw["mu" + p][e], dmu, atol=1e-10)
+
+
+def test_single_kick_closed_orbit(oracle_mod):
+    # near the integer tune the orbit is 40x the kick's local amplitude; a
+    # small kick keeps the exact drift's nonlinearity out of the comparison
+    theta = 1e-8
+    base = list(I.cfg1_lattice(rf_on=False, sextupoles=False))
+    k = 41  # a corrector after the drift ending cell 5
+    el = I.line(base[:k] + [I.multipole(knl=[-theta])] + base[k:])
+    tw0 = oracle_mod.twiss(I.line(base), REF, h=1e-10)
+    tw = oracle_mod.twiss(el, REF, h=1e-10)
+    assert tw["iterations"] >= 1 and tw["residual"] < 1e-15
+    Q = tw0["qx"]
+    # rows of the kicked ring without the corrector map onto the plain ring
+    rows = np.r_[np.arange(0, k + 1), np.arange(k + 2, len(el) + 1)]
+    bk, mk = tw0["betx"][k], tw0["mux"][k]
+    b, m = tw0["betx"], tw0["mux"]
+    xco = theta * np.sqrt(b * bk) * np.cos(math.pi * Q - np.abs(m - mk)) / (2 * math.sin(math.pi * Q))
+    got = tw["x"][rows]
+    assert np.max(np.abs(got - xco)) < 1e-7 * np.max(np.abs(xco))
+    assert np.max(np.abs(tw["y"])) == 0.0
+
+
+def bend_ring(n_cells=20, theta=0.05, k=0.04, L=10.0):
+    cell = [I.multipole(knl=[0.0, k]), I.multipole(knl=[theta], hxl=theta, length=2.0), I.drift(L),
+            I.multipole(knl=[0.0, -k]), I.multipole(knl=[theta], hxl=theta, length=2.0),
+            I.drift(L)]
+    return I.line(cell * n_cells)
+
+
+def test_dispersion_is_the_momentum_derivative_of_the_closed_orbit(oracle_mod):
+    el = bend_ring()
+    tw = oracle_mod.twiss(el, REF, h=1e-9, hd=1e-8)
+    eps = 1e-6
+    tp = oracle_mod.twiss(el, REF, delta0=eps, h=1e-9)
+    tm = oracle_mod.twiss(el, REF, delta0=-eps, h=1e-9)
+    for c, d in (("x", "dx"), ("px", "dpx")):
+        fd = (tp[c] - tm[c]) / (2 * eps)
+        assert np.max(np.abs(fd - tw[d])) < 1e-6 * np.max(np.abs(tw[d]))
+    assert np.max(np.abs(tw["dx"])) > 1.0  # the bends make it sizeable
+    assert np.allclose(tw["dy"], 0.0, atol=1e-9)
