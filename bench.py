@@ -233,6 +233,66 @@ def refine_bench(args):
     print(json.dumps(out_line), flush=True)
 
 
+def twiss_bench(args):
+    """Optics by tracking of the 20,000-element DA-scan ring: the whole
+    xtm_twiss call (closed-orbit Newton steps and the final 11-particle
+    recorded turn on the GPU, the 4x4 algebra and the table on the host),
+    timed on the host clock after one warmup call.  Algorithmic FLOPs: the
+    element maps of the tracked turns (apertures are not applied)."""
+    import torch
+    import paper_2310_00317_amd as P
+    I = P.inputs
+    el = I.cfg2_lattice()
+    ref = I.PROTON_450GEV
+    steps = args.steps if args.steps is not None else 5
+    lat = P.Lattice(el, ref)
+    for _ in range(max(args.warmup, 0)):
+        P.twiss(lat)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tw = None
+    for _ in range(steps):
+        tw = P.twiss(lat)
+    wall = time.perf_counter() - t0
+    ms = wall / steps * 1e3
+    f = element_flops(el)
+    f[np.isin(el["type"], (I.AP_CIRCLE, I.AP_ELLIPSE, I.AP_RECT))] = 0.0
+    turns = (tw["iterations"] + 1) * 9 + 11  # particle-turns per call
+    flops = turns * float(f.sum())
+    achieved = flops / (ms / 1e3) / 1e12
+    out = {
+        "metric": "optics computations/s (closed orbit, beta, alpha, phase, dispersion)",
+        "value": 1e3 / ms,
+        "unit": "twiss/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "optics of the DA-scan ring (20,000 thin elements, order-10 "
+                               "errors), 4D uncoupled, delta0 = 0",
+                   "n_elements": len(el), "newton_steps": tw["iterations"],
+                   "particle_turns": turns, "qx": tw["qx"], "qy": tw["qy"], "wall_s": wall},
+        "roofline": {"bound": "alu", "kernel": "k_record (one thread per particle, 9 or 11 "
+                                               "particles: one wave, latency-bound)",
+                     "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": None,
+                     "flops_per_call": flops},
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        t = time.perf_counter()
+        oracle.twiss(el, ref, h=1e-9, hd=1e-8)
+        dt = time.perf_counter() - t
+        out["cpu_baseline"] = {"value": 1.0 / dt, "unit": "twiss/s", "cores": 1, "kind": "oracle",
+                               "sample": f"one optics computation of the same ring in {dt:.2f} s"}
+    print(json.dumps(out), flush=True)
+
+
 def learned_da(args):
     """Dynamic-aperture scan of the cfg1 ring: plain tracking to the horizon
     versus learned early stop (network) and the tune-diffusion rule, on the
@@ -322,7 +382,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--turns-per-step", type=int, default=None)
     ap.add_argument("--workload", default="cfg2",
-                    choices=["cfg2", "cfg1", "cfg1sat", "cfg3", "cfg4", "cfg5", "refine"])
+                    choices=["cfg2", "cfg1", "cfg1sat", "cfg3", "cfg4", "cfg5", "refine",
+                             "twiss"])
     ap.add_argument("--refine-vertices", type=int, default=64,
                     help="refine: polygon vertices per aperture")
     ap.add_argument("--refine-ds", type=float, default=0.01, help="refine: sub-step [m]")
@@ -382,6 +443,8 @@ def main():
         return learned_da(args)
     if args.workload == "refine":
         return refine_bench(args)
+    if args.workload == "twiss":
+        return twiss_bench(args)
     el, coords, ref, desc, tps_default, steps_default = workload(args.workload, args.particles)
     tps = args.turns_per_step or tps_default
     steps = args.steps if args.steps is not None else steps_default

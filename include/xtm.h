@@ -277,6 +277,59 @@ xtm_status xtm_refine_losses(xtm_lattice lat, xtm_particles p, int32_t n_vertice
                              int32_t n_bisect, double* d_s, double* d_x, double* d_y,
                              int32_t* d_tests, void* stream);
 
+/* One turn of n particles (n <= 65536) from the line start, the coordinates
+   recorded at the entry of every element and after the last (paper section
+   "Twiss module": the lattice is probed by tracking).  d_in: device (n, 6)
+   rows (x, px, y, py, zeta, delta), set up as by xtm_particles_init;
+   d_out: device (n_el + 1) x n x 6, element-major: d_out[(e n + i) 6 + c]
+   holds particle i entering element e (e = n_el: after the turn).
+   Apertures are not checked (optics of the bare lattice); a particle whose
+   drift leaves the longitudinal-momentum window keeps the coordinates it
+   entered that drift with; no radiation.  One thread per particle;
+   stream-ordered. */
+xtm_status xtm_track_record(xtm_lattice lat, const double* d_in, int64_t n, double* d_out,
+                            void* stream);
+
+/* Linear optics by tracking (paper section "Twiss module"), transverse and
+   uncoupled, at a fixed momentum deviation delta0 (zeta starts at 0 and the
+   longitudinal plane is not part of the orbit):
+     1. closed orbit u* = T(u*) of the one-turn map on (x, px, y, py) by
+        Newton's method, u <- u + (I - J)^-1 (T(u) - u), from co_guess (host,
+        4 values, or NULL for 0) until the largest component of T(u) - u is
+        at most tol, stops decreasing, or max_iter steps were made;
+     2. J by central differences of particles displaced by +-h along each
+        coordinate, the momentum column by +-hd in delta (11 particles
+        tracked with xtm_track_record);
+     3. the same differences at every element give the map M_e from the line
+        start and its momentum column m_e;
+     4. per plane, from the one-turn block [[a, b], [c, d]]:
+        cos mu = (a + d)/2, sin mu = sign(b) sqrt(1 - cos^2 mu),
+        beta0 = b/sin mu, alpha0 = (a - d)/(2 sin mu); at element e with block
+        [[p, q], [r, t]] of M_e: beta = ((p beta0 - q alpha0)^2 + q^2)/beta0,
+        alpha = -((p beta0 - q alpha0)(r beta0 - t alpha0) + q t)/beta0,
+        phase = atan2(q, p beta0 - q alpha0), unwrapped to increase;
+     5. dispersion eta_0 = (I - J)^-1 m, eta_e = M_e eta_0 + m_e.
+   h_table: host, (n_el + 1) rows of 15 doubles: s, x, px, y, py (closed
+   orbit), betx, alfx, mux, bety, alfy, muy, dx, dpx, dy, dpy at the entry of
+   each element and at the line end.  summary: tunes (mu at the end / 2 pi),
+   the closed orbit at the start, Newton steps made and the last residual.
+   XTM_E_UNSUPPORTED for an unstable or integer/half-integer one-turn map.
+   Step sizes: the tracked coordinates carry rounding of about 1e-16 of the
+   orbit's size, so the maps carry about that divided by h; h ~ 1e-9 suits an
+   orbit on the axis, h ~ 1e-6 an orbit of millimetres (truncation stays
+   small for a nearly linear map).  Synchronising; allocates its own device
+   scratch. */
+typedef struct xtm_twiss_summary {
+  double qx, qy;
+  double co[4];
+  int32_t iterations;
+  int32_t pad;
+  double residual;
+} xtm_twiss_summary;
+xtm_status xtm_twiss(xtm_lattice lat, double delta0, double h, double hd, int32_t max_iter,
+                     double tol, const double* co_guess, double* h_table,
+                     xtm_twiss_summary* summary, void* stream);
+
 /* Copy the loss record into host buffers of the bound length (any may be
    NULL).  Synchronises the stream. */
 xtm_status xtm_get_losses(xtm_particles p, int32_t* h_state, int32_t* h_at_turn,

@@ -33,6 +33,16 @@ class XtmError(RuntimeError):
         self.code = code
 
 
+class _TwissSummary(ctypes.Structure):
+    _fields_ = [("qx", ctypes.c_double), ("qy", ctypes.c_double), ("co", ctypes.c_double * 4),
+                ("iterations", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("residual", ctypes.c_double)]
+
+
+TWISS_COLUMNS = ("s", "x", "px", "y", "py", "betx", "alfx", "mux", "bety", "alfy", "muy",
+                 "dx", "dpx", "dy", "dpy")
+
+
 class _Reference(ctypes.Structure):
     _fields_ = [("mass0_eV", ctypes.c_double), ("charge0", ctypes.c_double),
                 ("p0c_eV", ctypes.c_double)]
@@ -90,6 +100,9 @@ def lib() -> ctypes.CDLL:
             "xtm_track_backward": ([vp, vp, i32, vp, vp], i32),
             "xtm_track_per_element": ([vp, vp, i32, vp, vp], i32),
             "xtm_refine_losses": ([vp, vp, i32, ctypes.c_double, i32, vp, vp, vp, vp, vp], i32),
+            "xtm_track_record": ([vp, vp, i64, vp, vp], i32),
+            "xtm_twiss": ([vp, ctypes.c_double, ctypes.c_double, ctypes.c_double, i32,
+                           ctypes.c_double, vp, vp, vp, vp], i32),
             "xtm_get_losses": ([vp, vp, vp, vp, vp], i32),
             "xtm_sync": ([vp], i32),
             "xtm_philox4x32_10": ([ctypes.c_uint64, vp, i64, vp, vp], i32),
@@ -380,6 +393,40 @@ def refine_losses(lattice: Lattice, particles: Particles, n_vertices: int = 64, 
                                   _stream(stream)), "xtm_refine_losses")
     res = tuple(t[:particles.n] for t in out)
     return res + (tests[:particles.n],) if with_tests else res
+
+
+def track_record(lattice: Lattice, coords, stream=None):
+    """One turn of the (n, 6) coordinates (x, px, y, py, zeta, delta) with the
+    coordinates recorded at every element entry and after the last
+    (xtm_track_record): device tensor (n_el + 1, n, 6)."""
+    import torch
+    c = torch.as_tensor(np.asarray(coords, dtype=np.float64) if not isinstance(coords, torch.Tensor)
+                        else coords, dtype=torch.float64).to("cuda").contiguous()
+    n = c.shape[0]
+    out = torch.empty((lattice.n_elements + 1, max(n, 1), 6), dtype=torch.float64, device="cuda")
+    check(lib().xtm_track_record(lattice.handle, ctypes.c_void_p(c.data_ptr()), int(n),
+                                 ctypes.c_void_p(out.data_ptr()), _stream(stream)),
+          "xtm_track_record")
+    return out[:, :n]
+
+
+def twiss(lattice: Lattice, delta0: float = 0.0, h: float = 1e-9, hd: float = 1e-8,
+          max_iter: int = 30, tol: float = 1e-15, guess=None, stream=None) -> dict:
+    """Uncoupled linear optics by tracking (xtm_twiss): per-element columns
+    (TWISS_COLUMNS, numpy arrays of n_el + 1) plus qx, qy, the closed orbit at
+    the start (co), the Newton steps made and the last residual."""
+    n = lattice.n_elements
+    table = np.zeros((n + 1, len(TWISS_COLUMNS)), dtype=np.float64)
+    summ = _TwissSummary()
+    g = None if guess is None else np.ascontiguousarray(guess, dtype=np.float64)
+    check(lib().xtm_twiss(lattice.handle, float(delta0), float(h), float(hd), int(max_iter),
+                          float(tol), None if g is None else g.ctypes.data_as(ctypes.c_void_p),
+                          table.ctypes.data_as(ctypes.c_void_p), ctypes.byref(summ),
+                          _stream(stream)), "xtm_twiss")
+    out = {c: table[:, k].copy() for k, c in enumerate(TWISS_COLUMNS)}
+    out.update(qx=summ.qx, qy=summ.qy, co=np.array(summ.co[:]), iterations=summ.iterations,
+               residual=summ.residual)
+    return out
 
 
 def track_backward(lattice: Lattice, particles: Particles, n_turns: int, stats: bool = True,

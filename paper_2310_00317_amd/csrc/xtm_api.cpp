@@ -76,6 +76,8 @@ struct xtm_lattice_s {
   int32_t plan_variant = 0, plan_block = 0;
   // the element descriptions as given (geometry of the loss refinement)
   std::vector<xtm_element_desc> desc_h;
+  // forward-table record position of each element (device), built on first use
+  int32_t* off_f_d = nullptr;
   // loss-refinement geometry for one polygon size, built on first use
   int32_t refine_M = 0;
   void* refine_buf = nullptr;
@@ -661,6 +663,7 @@ xtm_status xtm_lattice_destroy(xtm_lattice L) {
   hipFree(L->fwd_seg_d);
   hipFree(L->bwd_seg_d);
   hipFree(L->refine_buf);
+  hipFree(L->off_f_d);
   for (int32_t k = 0; k < kLineStyles; ++k) {
     free_line_kernel(&L->fwd_line[k]);
     free_line_kernel(&L->bwd_line[k]);
@@ -1507,6 +1510,236 @@ xtm_status xtm_refine_losses(xtm_lattice L, xtm_particles P, int32_t n_vertices,
                           d_y, d_tests, (hipStream_t)stream),
             "refinement launch");
     return XTM_OK;
+  });
+}
+
+namespace {
+xtm_status ensure_offsets(xtm_lattice_s* L) {
+  if (L->off_f_d) return XTM_OK;
+  std::vector<int32_t> off(L->n_el);
+  size_t w = 0;
+  for (int32_t e = 0; e < L->n_el; ++e) {
+    off[e] = (int32_t)w;
+    w += 1 + ((L->fwd_h[w] >> 16) & 0xffffu);
+  }
+  int32_t* d = nullptr;
+  const size_t bytes = std::max<size_t>(1, off.size()) * sizeof(int32_t);
+  if (hipMalloc(&d, bytes) != hipSuccess) return fail(XTM_E_NOMEM, "record offsets allocation");
+  if (!off.empty() &&
+      hipMemcpy(d, off.data(), off.size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess) {
+    hipFree(d);
+    return fail(XTM_E_HIP, "record offsets copy");
+  }
+  L->off_f_d = d;
+  return XTM_OK;
+}
+
+// x = (I - A)^-1 b for a 4x4 A, Gaussian elimination with partial pivoting
+bool solve_i_minus(const double A[4][4], const double b[4], double x[4]) {
+  double m[4][5];
+  for (int i = 0; i < 4; ++i) {
+    for (int j = 0; j < 4; ++j) m[i][j] = (i == j ? 1.0 : 0.0) - A[i][j];
+    m[i][4] = b[i];
+  }
+  for (int c = 0; c < 4; ++c) {
+    int p = c;
+    for (int i = c + 1; i < 4; ++i)
+      if (std::fabs(m[i][c]) > std::fabs(m[p][c])) p = i;
+    if (!(std::fabs(m[p][c]) > 0.0)) return false;
+    if (p != c)
+      for (int j = 0; j < 5; ++j) std::swap(m[p][j], m[c][j]);
+    for (int i = c + 1; i < 4; ++i) {
+      const double f = m[i][c] / m[c][c];
+      for (int j = c; j < 5; ++j) m[i][j] -= f * m[c][j];
+    }
+  }
+  for (int i = 3; i >= 0; --i) {
+    double acc = m[i][4];
+    for (int j = i + 1; j < 4; ++j) acc -= m[i][j] * x[j];
+    x[i] = acc / m[i][i];
+  }
+  return true;
+}
+}  // namespace
+
+xtm_status xtm_track_record(xtm_lattice L, const double* d_in, int64_t n, double* d_out,
+                            void* stream) {
+  return guarded([&]() -> xtm_status {
+    if (!L) return fail(XTM_E_ARG, "null lattice");
+    if (n < 0 || n > 65536) return fail(XTM_E_ARG, "n must be in 0..65536");
+    if (n > 0 && (!d_in || !d_out)) return fail(XTM_E_ARG, "null array");
+    const xtm_status st = ensure_offsets(L);
+    if (st != XTM_OK) return st;
+    HIP_TRY(launch_record(L->fwd_d, L->off_f_d, L->n_el, d_in, n, d_out, kref(L->ref, 0, 0),
+                          (hipStream_t)stream),
+            "record launch");
+    return XTM_OK;
+  });
+}
+
+xtm_status xtm_twiss(xtm_lattice L, double delta0, double h, double hd, int32_t max_iter,
+                     double tol, const double* co_guess, double* h_table,
+                     xtm_twiss_summary* summary, void* stream) {
+  return guarded([&]() -> xtm_status {
+    if (!L) return fail(XTM_E_ARG, "null lattice");
+    if (!h_table || !summary) return fail(XTM_E_ARG, "null output");
+    if (!(h > 0.0) || !(hd > 0.0) || max_iter < 0 || !(tol >= 0.0) || !std::isfinite(delta0))
+      return fail(XTM_E_ARG, "need h > 0, hd > 0, max_iter >= 0, tol >= 0, finite delta0");
+    xtm_status st = ensure_offsets(L);
+    if (st != XTM_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    const int32_t n_el = L->n_el;
+    const int64_t np = 11;
+    double* d_in = nullptr;
+    double* d_out = nullptr;
+    const size_t out_n = (size_t)(n_el + 1) * np * 6;
+    if (hipMalloc(&d_in, np * 6 * sizeof(double)) != hipSuccess ||
+        hipMalloc(&d_out, out_n * sizeof(double)) != hipSuccess) {
+      hipFree(d_in);
+      return fail(XTM_E_NOMEM, "twiss scratch allocation");
+    }
+    std::vector<double> out(out_n);
+    auto run = [&](const double u[4], bool with_delta, bool all_rows) -> xtm_status {
+      const int64_t m = with_delta ? 11 : 9;
+      double c[11][6];
+      for (int64_t r = 0; r < m; ++r) {
+        for (int k = 0; k < 4; ++k) c[r][k] = u[k];
+        c[r][4] = 0.0;
+        c[r][5] = delta0;
+      }
+      for (int k = 0; k < 4; ++k) {
+        c[1 + 2 * k][k] += h;
+        c[2 + 2 * k][k] -= h;
+      }
+      if (with_delta) {
+        c[9][5] = delta0 + hd;
+        c[10][5] = delta0 - hd;
+      }
+      if (hipMemcpyAsync(d_in, c, m * 6 * sizeof(double), hipMemcpyHostToDevice, s) != hipSuccess)
+        return fail(XTM_E_HIP, "twiss upload");
+      if (launch_record(L->fwd_d, L->off_f_d, n_el, d_in, m, d_out, kref(L->ref, 0, 0), s) !=
+          hipSuccess)
+        return fail(XTM_E_HIP, "twiss record launch");
+      const size_t first = all_rows ? 0 : (size_t)n_el * m * 6;
+      const size_t cnt = (all_rows ? (size_t)(n_el + 1) : 1) * m * 6;
+      if (hipMemcpyAsync(out.data() + first, d_out + first, cnt * sizeof(double),
+                         hipMemcpyDeviceToHost, s) != hipSuccess ||
+          hipStreamSynchronize(s) != hipSuccess)
+        return fail(XTM_E_HIP, "twiss download");
+      return XTM_OK;
+    };
+    auto at = [&](int64_t m, int32_t e, int r, int k) {
+      return out[((size_t)e * m + r) * 6 + k];
+    };
+    double u[4] = {0.0, 0.0, 0.0, 0.0};
+    if (co_guess)
+      for (int k = 0; k < 4; ++k) u[k] = co_guess[k];
+    int32_t it = 0;
+    double res = INFINITY, best = INFINITY;
+    double J[4][4];
+    for (;;) {
+      st = run(u, false, false);
+      if (st != XTM_OK) break;
+      double F[4];
+      for (int k = 0; k < 4; ++k)
+        for (int i = 0; i < 4; ++i)
+          J[i][k] = (at(9, n_el, 1 + 2 * k, i) - at(9, n_el, 2 + 2 * k, i)) / (2.0 * h);
+      res = 0.0;
+      for (int i = 0; i < 4; ++i) {
+        F[i] = at(9, n_el, 0, i) - u[i];
+        res = std::max(res, std::fabs(F[i]));
+      }
+      if (std::isnan(F[0] + F[1] + F[2] + F[3])) res = NAN;
+      if (!(res > tol) || it >= max_iter || !(res < best)) break;
+      best = res;
+      double du[4];
+      if (!solve_i_minus(J, F, du)) {
+        st = fail(XTM_E_UNSUPPORTED, "closed orbit: singular I - J (integer tune)");
+        break;
+      }
+      for (int k = 0; k < 4; ++k) u[k] = u[k] + du[k];
+      ++it;
+    }
+    if (st == XTM_OK) st = run(u, true, true);
+    if (st == XTM_OK) {
+      // per-element maps, momentum columns, dispersion and uncoupled optics
+      std::vector<double> M((size_t)(n_el + 1) * 16), md((size_t)(n_el + 1) * 4);
+      for (int32_t e = 0; e <= n_el; ++e)
+        for (int i = 0; i < 4; ++i) {
+          for (int k = 0; k < 4; ++k)
+            M[(size_t)e * 16 + i * 4 + k] =
+                (at(11, e, 1 + 2 * k, i) - at(11, e, 2 + 2 * k, i)) / (2.0 * h);
+          md[(size_t)e * 4 + i] = (at(11, e, 9, i) - at(11, e, 10, i)) / (2.0 * hd);
+        }
+      double Jt[4][4], eta0[4];
+      for (int i = 0; i < 4; ++i)
+        for (int k = 0; k < 4; ++k) Jt[i][k] = M[(size_t)n_el * 16 + i * 4 + k];
+      if (!solve_i_minus(Jt, &md[(size_t)n_el * 4], eta0)) {
+        st = fail(XTM_E_UNSUPPORTED, "dispersion: singular I - J (integer tune)");
+      } else {
+        double s_acc = 0.0;
+        double q[2] = {0.0, 0.0};
+        double b0[2], a0[2];
+        for (int pl = 0; pl < 2 && st == XTM_OK; ++pl) {
+          const int o = 2 * pl;
+          const double a = Jt[o][o], b = Jt[o][o + 1], d = Jt[o + 1][o + 1];
+          const double cmu = 0.5 * (a + d);
+          if (!(1.0 - cmu * cmu > 0.0)) {
+            st = fail(XTM_E_UNSUPPORTED, "unstable or half-integer/integer one-turn map");
+            break;
+          }
+          const double smu = std::copysign(std::sqrt(1.0 - cmu * cmu), b);
+          b0[pl] = b / smu;
+          a0[pl] = (a - d) / (2.0 * smu);
+        }
+        if (st == XTM_OK) {
+          double th_prev[2] = {0.0, 0.0}, mu[2] = {0.0, 0.0};
+          for (int32_t e = 0; e <= n_el; ++e) {
+            double* row = h_table + (size_t)e * 15;
+            if (e > 0) {
+              const auto& de = L->desc_h[e - 1];
+              if (de.type == XTM_DRIFT || de.type == XTM_DRIFT_EXPANDED) s_acc = s_acc + de.length;
+            }
+            row[0] = s_acc;
+            for (int k = 0; k < 4; ++k) row[1 + k] = at(11, e, 0, k);
+            const double* Me = &M[(size_t)e * 16];
+            for (int pl = 0; pl < 2; ++pl) {
+              const int o = 2 * pl;
+              const double p_ = Me[o * 4 + o], q_ = Me[o * 4 + o + 1];
+              const double r_ = Me[(o + 1) * 4 + o], t_ = Me[(o + 1) * 4 + o + 1];
+              const double bb = p_ * b0[pl] - q_ * a0[pl];
+              const double beta = (bb * bb + q_ * q_) / b0[pl];
+              const double alpha = -(bb * (r_ * b0[pl] - t_ * a0[pl]) + q_ * t_) / b0[pl];
+              const double th = std::atan2(q_, bb);
+              if (e > 0) {
+                double dth = std::fmod(th - th_prev[pl], 2.0 * M_PI);
+                if (dth < 0.0) dth += 2.0 * M_PI;
+                mu[pl] = mu[pl] + dth;
+              }
+              th_prev[pl] = th;
+              row[5 + 3 * pl] = beta;
+              row[6 + 3 * pl] = alpha;
+              row[7 + 3 * pl] = mu[pl];
+            }
+            for (int i = 0; i < 4; ++i) {
+              double acc = 0.0;
+              for (int j = 0; j < 4; ++j) acc += Me[i * 4 + j] * eta0[j];
+              row[11 + i] = acc + md[(size_t)e * 4 + i];
+            }
+          }
+          q[0] = mu[0] / (2.0 * M_PI);
+          q[1] = mu[1] / (2.0 * M_PI);
+          summary->qx = q[0];
+          summary->qy = q[1];
+          for (int k = 0; k < 4; ++k) summary->co[k] = u[k];
+          summary->iterations = it;
+          summary->residual = res;
+        }
+      }
+    }
+    hipFree(d_in);
+    hipFree(d_out);
+    return st;
   });
 }
 

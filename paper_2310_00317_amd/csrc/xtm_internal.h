@@ -105,6 +105,11 @@ hipError_t launch_per_element(const uint64_t* tab, const uint32_t* offsets, int3
 
 constexpr int kScanBlock = 1024;
 
+// One turn of n particles with the coordinates (x, px, y, py, zeta, delta)
+// recorded at every element entry and after the last: out[(e n + i) 6 + c].
+hipError_t launch_record(const uint64_t* fwd, const int32_t* off_f, int32_t n_el,
+                         const double* c6, int64_t n, double* out, KernelRef r, hipStream_t s);
+
 // Loss-location refinement geometry (device pointers into one buffer):
 // s of each element and of the line end (n_el + 1), line frame of each
 // element's entry coordinates as (a11, a12, a21, a22, b1, b2) (n_el + 1),

@@ -1,0 +1,104 @@
+"""GPU parity of optics by tracking through the C ABI: the one-turn recorder
+bit for bit against the oracle's, and the optics table (closed orbit, beta,
+alpha, phase, dispersion) against the oracle's within tolerances set by the
+4x4 solves (Gaussian elimination against LAPACK) that feed the Newton steps
+and the dispersion."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2310_00317_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+REF = I.PROTON_450GEV
+COLS = ("s", "x", "px", "y", "py", "betx", "alfx", "mux", "bety", "alfy", "muy",
+        "dx", "dpx", "dy", "dpy")
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2310_00317_amd as P
+    P.lib()
+    return P
+
+
+def banner(msg):
+    print(f"[gpu-twiss] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def compare(g, o, rtol, atol_orbit=1e-15, atol_disp=0.0, qtol=1e-11):
+    """atol_disp: the dispersion columns are momentum derivatives by central
+    differences of step hd; closed orbits that differ in their last bits (the
+    two sides' 4x4 solves round differently) move them by about
+    ulp(orbit) / hd times the (I - J)^-1 amplification; for the same reason
+    the Jacobian, hence the tunes, carry about ulp(orbit) / h of noise when
+    the orbit is not the axis."""
+    for c in COLS:
+        a, b = np.asarray(g[c]), np.asarray(o[c])
+        scale = max(np.max(np.abs(b)), 1e-300)
+        tol = atol_orbit if c in ("x", "px", "y", "py") else 0.0
+        if c in ("dx", "dpx", "dy", "dpy"):
+            tol = atol_disp
+        err = np.max(np.abs(a - b))
+        assert err <= rtol * scale + tol, f"{c}: max |gpu - oracle| {err:.3e} (scale {scale:.3e})"
+    assert abs(g["qx"] - o["qx"]) < qtol and abs(g["qy"] - o["qy"]) < qtol
+
+
+def test_record_bitwise(P, oracle_mod):
+    banner("one-turn recorder, cfg1 ring with RF, 64 particles")
+    el = I.cfg1_lattice()
+    c = I.cfg1_particles(64, seed=3)
+    lat = P.Lattice(el, REF)
+    g = P.track_record(lat, c).cpu().numpy()
+    o = oracle_mod.track_record(el, REF, c)
+    assert g.shape == o.shape
+    same = (g.view(np.int64) == o.view(np.int64)) | (np.isnan(g) & np.isnan(o))
+    assert same.all(), f"{(~same).sum()} values differ"
+
+
+def test_fodo_optics(P, oracle_mod):
+    banner("cfg1 ring optics")
+    el = I.cfg1_lattice(rf_on=False)
+    g = P.twiss(P.Lattice(el, REF), h=1e-10)
+    o = oracle_mod.twiss(el, REF, h=1e-10)
+    compare(g, o, 1e-12)
+    for c in ("s", "x", "px", "y", "py"):  # the axis is the orbit: no solve, the same numbers
+        assert np.array_equal(g[c], o[c]), c
+
+
+def test_kicked_orbit_and_bends(P, oracle_mod):
+    banner("closed orbit of correctors and dispersion of thin bends")
+    cell = [I.multipole(knl=[0.0, 0.04]), I.multipole(knl=[0.05], hxl=0.05, length=2.0),
+            I.drift(10.0), I.multipole(knl=[0.0, -0.04], ksl=[2e-5]),
+            I.multipole(knl=[0.05], hxl=0.05, length=2.0), I.drift(10.0)]
+    el = I.line(cell * 20)
+    # millimetre orbits: the tracked coordinates carry ~1e-16 m of rounding,
+    # so differences over steps of 1e-6 keep the maps' noise near 1e-10
+    for d0 in (0.0, 3e-4):
+        g = P.twiss(P.Lattice(el, REF), delta0=d0, h=1e-6, hd=1e-6)
+        o = oracle_mod.twiss(el, REF, delta0=d0, h=1e-6, hd=1e-6)
+        assert g["iterations"] >= 1 and g["residual"] < 1e-14
+        compare(g, o, 5e-8, atol_orbit=1e-14, atol_disp=1e-9, qtol=1e-9)
+
+
+def test_da_ring_full_size(P, oracle_mod):
+    banner("20,000-element errored DA ring optics")
+    el = I.cfg2_lattice()
+    g = P.twiss(P.Lattice(el, REF))
+    o = oracle_mod.twiss(el, REF, h=1e-9, hd=1e-8)
+    compare(g, o, 1e-8, atol_orbit=1e-14, atol_disp=1e-9)
+    banner(f"qx {g['qx']:.6f} qy {g['qy']:.6f}, {g['iterations']} Newton steps")
+
+
+def test_unstable_map_is_an_error(P):
+    el = I.line([I.multipole(knl=[0.0, 1.0]), I.drift(10.0)])
+    with pytest.raises(P.XtmError, match="unstable"):
+        P.twiss(P.Lattice(el, REF))
+    with pytest.raises(P.XtmError):
+        P.twiss(P.Lattice(el, REF), h=0.0)
