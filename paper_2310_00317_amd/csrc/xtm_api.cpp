@@ -76,8 +76,6 @@ struct xtm_lattice_s {
   int32_t plan_variant = 0, plan_block = 0;
   // the element descriptions as given (geometry of the loss refinement)
   std::vector<xtm_element_desc> desc_h;
-  // forward-table record position of each element (device), built on first use
-  int32_t* off_f_d = nullptr;
   // loss-refinement geometry for one polygon size, built on first use
   int32_t refine_M = 0;
   void* refine_buf = nullptr;
@@ -663,7 +661,6 @@ xtm_status xtm_lattice_destroy(xtm_lattice L) {
   hipFree(L->fwd_seg_d);
   hipFree(L->bwd_seg_d);
   hipFree(L->refine_buf);
-  hipFree(L->off_f_d);
   for (int32_t k = 0; k < kLineStyles; ++k) {
     free_line_kernel(&L->fwd_line[k]);
     free_line_kernel(&L->bwd_line[k]);
@@ -1514,26 +1511,6 @@ xtm_status xtm_refine_losses(xtm_lattice L, xtm_particles P, int32_t n_vertices,
 }
 
 namespace {
-xtm_status ensure_offsets(xtm_lattice_s* L) {
-  if (L->off_f_d) return XTM_OK;
-  std::vector<int32_t> off(L->n_el);
-  size_t w = 0;
-  for (int32_t e = 0; e < L->n_el; ++e) {
-    off[e] = (int32_t)w;
-    w += 1 + ((L->fwd_h[w] >> 16) & 0xffffu);
-  }
-  int32_t* d = nullptr;
-  const size_t bytes = std::max<size_t>(1, off.size()) * sizeof(int32_t);
-  if (hipMalloc(&d, bytes) != hipSuccess) return fail(XTM_E_NOMEM, "record offsets allocation");
-  if (!off.empty() &&
-      hipMemcpy(d, off.data(), off.size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess) {
-    hipFree(d);
-    return fail(XTM_E_HIP, "record offsets copy");
-  }
-  L->off_f_d = d;
-  return XTM_OK;
-}
-
 // x = (I - A)^-1 b for a 4x4 A, Gaussian elimination with partial pivoting
 bool solve_i_minus(const double A[4][4], const double b[4], double x[4]) {
   double m[4][5];
@@ -1568,10 +1545,8 @@ xtm_status xtm_track_record(xtm_lattice L, const double* d_in, int64_t n, double
     if (!L) return fail(XTM_E_ARG, "null lattice");
     if (n < 0 || n > 65536) return fail(XTM_E_ARG, "n must be in 0..65536");
     if (n > 0 && (!d_in || !d_out)) return fail(XTM_E_ARG, "null array");
-    const xtm_status st = ensure_offsets(L);
-    if (st != XTM_OK) return st;
-    HIP_TRY(launch_record(L->fwd_d, L->off_f_d, L->n_el, d_in, n, d_out, kref(L->ref, 0, 0),
-                          (hipStream_t)stream),
+    HIP_TRY(launch_record(L->fwd_d, L->fwd_seg_d, (int32_t)(L->fwd_seg_h.size() / 3), L->n_el,
+                          d_in, n, d_out, kref(L->ref, 0, 0), (hipStream_t)stream),
             "record launch");
     return XTM_OK;
   });
@@ -1585,8 +1560,7 @@ xtm_status xtm_twiss(xtm_lattice L, double delta0, double h, double hd, int32_t 
     if (!h_table || !summary) return fail(XTM_E_ARG, "null output");
     if (!(h > 0.0) || !(hd > 0.0) || max_iter < 0 || !(tol >= 0.0) || !std::isfinite(delta0))
       return fail(XTM_E_ARG, "need h > 0, hd > 0, max_iter >= 0, tol >= 0, finite delta0");
-    xtm_status st = ensure_offsets(L);
-    if (st != XTM_OK) return st;
+    xtm_status st = XTM_OK;
     hipStream_t s = (hipStream_t)stream;
     const int32_t n_el = L->n_el;
     const int64_t np = 11;
@@ -1617,8 +1591,8 @@ xtm_status xtm_twiss(xtm_lattice L, double delta0, double h, double hd, int32_t 
       }
       if (hipMemcpyAsync(d_in, c, m * 6 * sizeof(double), hipMemcpyHostToDevice, s) != hipSuccess)
         return fail(XTM_E_HIP, "twiss upload");
-      if (launch_record(L->fwd_d, L->off_f_d, n_el, d_in, m, d_out, kref(L->ref, 0, 0), s) !=
-          hipSuccess)
+      if (launch_record(L->fwd_d, L->fwd_seg_d, (int32_t)(L->fwd_seg_h.size() / 3), n_el, d_in, m,
+                        d_out, kref(L->ref, 0, 0), s) != hipSuccess)
         return fail(XTM_E_HIP, "twiss record launch");
       const size_t first = all_rows ? 0 : (size_t)n_el * m * 6;
       const size_t cnt = (all_rows ? (size_t)(n_el + 1) : 1) * m * 6;

@@ -107,7 +107,8 @@ constexpr int kScanBlock = 1024;
 
 // One turn of n particles with the coordinates (x, px, y, py, zeta, delta)
 // recorded at every element entry and after the last: out[(e n + i) 6 + c].
-hipError_t launch_record(const uint64_t* fwd, const int32_t* off_f, int32_t n_el,
+// (seg: the table's LDS segments, as for launch_track)
+hipError_t launch_record(const uint64_t* fwd, const int32_t* seg, int32_t n_seg, int32_t n_el,
                          const double* c6, int64_t n, double* out, KernelRef r, hipStream_t s);
 
 // Loss-location refinement geometry (device pointers into one buffer):

@@ -1206,57 +1206,77 @@ hipError_t launch_replay(const uint64_t* tab, int32_t n_el, SoA P, const int32_t
 // One turn of a few particles from the line start, the coordinates recorded
 // at the entry of every element and after the last (apertures not checked;
 // a particle whose drift leaves the longitudinal-momentum window keeps the
-// coordinates it entered that drift with).  One thread per particle; the
-// set-up from (x, px, y, py, zeta, delta) is the one of particle
-// initialisation.
+// coordinates it entered that drift with).  One thread per particle, 64 per
+// workgroup; the element table passes through LDS segment by segment (the
+// table's segments of at most kSegWords words), so an element costs LDS
+// reads, not two dependent global loads.  The set-up from
+// (x, px, y, py, zeta, delta) is the one of particle initialisation.
 namespace xtm {
 namespace {
 __global__ void __launch_bounds__(64)
-k_record(const uint64_t* __restrict__ fwd, const int32_t* __restrict__ off_f, int32_t n_el,
-         const double* __restrict__ c6, int64_t n, double* __restrict__ out, KernelRef r) {
+k_record(const uint64_t* __restrict__ fwd, const int32_t* __restrict__ seg, int32_t n_seg,
+         int32_t n_el, const double* __restrict__ c6, int64_t n, double* __restrict__ out,
+         KernelRef r) {
+  __shared__ uint64_t lds[kSegWords];
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const double* c = c6 + 6 * i;
-  const double d = c[5];
-  const double u = d * (2.0 + d);
-  xtmm::Pt q;
-  q.x = c[0];
-  q.px = c[1];
-  q.y = c[2];
-  q.py = c[3];
-  q.zeta = c[4];
-  q.delta = d;
-  q.ptau = r.beta0 * u / (1.0 + sqrt(1.0 + r.beta0 * r.beta0 * u));
-  q.rpp = 1.0 / (1.0 + d);
-  q.rvv = (1.0 + d) / (1.0 + r.beta0 * q.ptau);
-  xtmm::refresh(q, r.beta0);
+  const bool act = i < n;
+  xtmm::Pt q{};
+  if (act) {
+    const double* c = c6 + 6 * i;
+    const double d = c[5];
+    const double u = d * (2.0 + d);
+    q.x = c[0];
+    q.px = c[1];
+    q.y = c[2];
+    q.py = c[3];
+    q.zeta = c[4];
+    q.delta = d;
+    q.ptau = r.beta0 * u / (1.0 + sqrt(1.0 + r.beta0 * r.beta0 * u));
+    q.rpp = 1.0 / (1.0 + d);
+    q.rvv = (1.0 + d) / (1.0 + r.beta0 * q.ptau);
+    xtmm::refresh(q, r.beta0);
+  }
   bool alive = true;
-  for (int32_t e = 0; e <= n_el; ++e) {
+  auto record = [&](int32_t e) {
     double* o = out + ((size_t)e * (size_t)n + (size_t)i) * 6;
     o[0] = q.x; o[1] = q.px; o[2] = q.y; o[3] = q.py; o[4] = q.zeta; o[5] = q.delta;
-    if (e == n_el || !alive) continue;
-    const uint64_t h = fwd[off_f[e]];
-    const uint32_t kt = (uint32_t)(h & 0xffu);
-    if (kt == K_AP_CIRC || kt == K_AP_ELL || kt == K_AP_RECT) continue;
-    const double* prm = reinterpret_cast<const double*>(fwd + off_f[e] + 1);
-    const xtmm::Pt q0 = q;
-    bool ok;
-    int lost_state;
-    apply_elem(q, kt, (uint32_t)((h >> 8) & 0xffu), prm, r, ok, lost_state, 0, 0, e);
-    if (!ok) {
-      q = q0;
-      alive = false;
+  };
+  int32_t e = 0;
+  for (int32_t sgi = 0; sgi < n_seg; ++sgi) {
+    const int32_t w0 = seg[3 * sgi], nwords = seg[3 * sgi + 1], n_here = seg[3 * sgi + 2];
+    __syncthreads();
+    for (int32_t k = threadIdx.x; k < nwords; k += blockDim.x) lds[k] = fwd[w0 + k];
+    __syncthreads();
+    uint32_t off = 0;
+    for (int32_t k = 0; k < n_here; ++k, ++e) {
+      const uint64_t h = lds[off];
+      const uint32_t kt = (uint32_t)(h & 0xffu);
+      const uint32_t nw = (uint32_t)((h >> 16) & 0xffffu);
+      const double* prm = reinterpret_cast<const double*>(&lds[off + 1]);
+      off += 1 + nw;
+      if (!act) continue;
+      record(e);
+      if (!alive || kt == K_AP_CIRC || kt == K_AP_ELL || kt == K_AP_RECT) continue;
+      const xtmm::Pt q0 = q;
+      bool ok;
+      int lost_state;
+      apply_elem(q, kt, (uint32_t)((h >> 8) & 0xffu), prm, r, ok, lost_state, 0, 0, e);
+      if (!ok) {
+        q = q0;
+        alive = false;
+      }
     }
   }
+  if (act) record(n_el);
 }
 }  // namespace
 
-hipError_t launch_record(const uint64_t* fwd, const int32_t* off_f, int32_t n_el,
+hipError_t launch_record(const uint64_t* fwd, const int32_t* seg, int32_t n_seg, int32_t n_el,
                          const double* c6, int64_t n, double* out, KernelRef r, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   const int64_t blocks = (n + 63) / 64;
-  hipLaunchKernelGGL(k_record, dim3((unsigned)blocks), dim3(64), 0, s, fwd, off_f, n_el, c6, n,
-                     out, r);
+  hipLaunchKernelGGL(k_record, dim3((unsigned)blocks), dim3(64), 0, s, fwd, seg, n_seg, n_el, c6,
+                     n, out, r);
   return hipGetLastError();
 }
 }  // namespace xtm
