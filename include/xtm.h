@@ -65,7 +65,9 @@ enum {
   XTM_AP_CIRCLE = 7,      /* circular aperture                                       */
   XTM_AP_ELLIPSE = 8,     /* elliptic aperture                                       */
   XTM_AP_RECT = 9,        /* rectangular aperture                                    */
-  XTM_MARKER = 10         /* no-op                                                   */
+  XTM_MARKER = 10,        /* no-op                                                   */
+  XTM_QUADRUPOLE = 11,    /* thick quadrupole, sliced at lattice creation            */
+  XTM_SBEND = 12          /* thick sector bend, sliced at lattice creation           */
 };
 #define XTM_MAX_ORDER 10
 
@@ -84,6 +86,18 @@ enum {
  *  AP_CIRCLE: p[0] = r > 0.  AP_ELLIPSE: p[0] = a > 0, p[1] = b > 0.
  *  AP_RECT: p[0..3] = xmin < xmax, ymin < ymax.  A particle exactly on the
  *    boundary survives; a NaN coordinate is outside.
+ *  QUADRUPOLE (thick; paper section on the tracking engine: thick elements
+ *    by symplectic splitting): length = L > 0 [m], p[0] = k1, p[1] = k1s
+ *    [m^-2], p[2] = N slices (an integer, 1..10000).  SBEND (thick sector
+ *    bend): length = L > 0, p[0] = bending angle theta [rad], p[1] = k1
+ *    [m^-2], p[2] = N.  xtm_lattice_create replaces each by N drift-kick-drift
+ *    slices (kicks at the slice midpoints): with d = L/N, DRIFT(d/2), then N
+ *    times [thin kick, DRIFT(d)] with the last drift d/2 instead:
+ *      QUADRUPOLE kick: MULTIPOLE of order 1, knl[1] = k1 d, ksl[1] = k1s d;
+ *      SBEND kick: MULTIPOLE of order 1, knl[0] = hxl = theta/N, length = d
+ *        (the curvature's weak focusing and path-length terms), knl[1] = k1 d.
+ *    Element indices everywhere (loss records, optics rows, refinement) then
+ *    refer to the sliced line; xtm_lattice_user_index maps them back.
  *  Unused fields are ignored.
  */
 typedef struct xtm_element_desc {
@@ -130,8 +144,14 @@ int32_t xtm_max_variant(void);
 xtm_status xtm_lattice_create(const xtm_element_desc* el, int32_t n, const xtm_reference* ref,
                               xtm_lattice* out);
 xtm_status xtm_lattice_destroy(xtm_lattice lat);
-/* Number of elements and size in bytes of the device table (forward). */
+/* Number of elements (of the sliced line) and size in bytes of the device
+   table (forward). */
 xtm_status xtm_lattice_info(xtm_lattice lat, int32_t* n_elements, int64_t* table_bytes);
+
+/* User element index of each element of the (sliced) line: h_out, host,
+   n_elements values (xtm_lattice_info); a thin element maps to its own
+   index, each slice of a thick element to the thick element's. */
+xtm_status xtm_lattice_user_index(xtm_lattice lat, int32_t* h_out);
 
 /* Bind caller-owned device arrays as a particle set for reference `ref`.
    Allocates the library's per-set work buffers (alive list, counters:

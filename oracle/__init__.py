@@ -120,10 +120,63 @@ def _ref3(ref) -> np.ndarray:
     return np.ascontiguousarray(np.asarray(ref, dtype=np.float64))
 
 
+THICK_QUAD, THICK_SBEND = 11, 12
+
+
+def expand_thick(elements) -> np.ndarray:
+    """Thick quadrupoles (length L, p = k1, k1s, N) and sector bends (length
+    L, p = angle, k1, N) as N drift-kick-drift slices with the kicks at the
+    slice midpoints (a second-order symplectic splitting of the thick map,
+    paper section on the tracking engine): with d = L/N, a drift d/2, then N
+    times [kick, drift d], the last drift d/2.  Quadrupole kick: thin
+    multipole of order 1 with knl1 = k1 d, ksl1 = k1s d.  Bend kick: thin
+    multipole with knl0 = hxl = angle/N over the length d (its curvature
+    terms give the weak focusing and the path-length change) and knl1 = k1 d.
+    Thin elements pass unchanged."""
+    el = np.ascontiguousarray(elements)
+    if not np.isin(el["type"], (THICK_QUAD, THICK_SBEND)).any():
+        return el
+    out = []
+    for e in el:
+        t = int(e["type"])
+        if t not in (THICK_QUAD, THICK_SBEND):
+            out.append(e.copy())
+            continue
+        L, Nf = float(e["length"]), float(e["p"][2])
+        if not (L > 0.0 and 1.0 <= Nf <= 10000.0 and Nf == math.floor(Nf)):
+            raise ValueError("thick element needs length > 0 and an integer slice count")
+        N = int(Nf)
+        d = L / float(N)
+        half = 0.5 * d
+        kick = np.zeros((), dtype=el.dtype)
+        kick["type"] = 3
+        kick["order"] = 1
+        if t == THICK_QUAD:
+            kick["knl"][1] = float(e["p"][0]) * d
+            kick["ksl"][1] = float(e["p"][1]) * d
+        else:
+            a = float(e["p"][0]) / float(N)
+            kick["knl"][0] = a
+            kick["hxl"] = a
+            kick["length"] = d
+            kick["knl"][1] = float(e["p"][1]) * d
+        for j in range(N + 1):
+            dr = np.zeros((), dtype=el.dtype)
+            dr["type"] = 1
+            dr["length"] = half if j in (0, N) else d
+            out.append(dr)
+            if j < N:
+                out.append(kick.copy())
+    res = np.zeros(len(out), dtype=el.dtype)
+    for i, e in enumerate(out):
+        res[i] = e
+    return res
+
+
 def _els(elements) -> np.ndarray:
     a = np.ascontiguousarray(elements)
     assert a.dtype.itemsize == 248, "element records must use the 248-byte layout"
-    return a
+    return expand_thick(a)
 
 
 def init(coords6, ref, first_id: int = 0) -> Particles:

@@ -91,6 +91,7 @@ def lib() -> ctypes.CDLL:
             "xtm_lattice_create": ([vp, i32, vp, vp], i32),
             "xtm_lattice_destroy": ([vp], i32),
             "xtm_lattice_info": ([vp, vp, vp], i32),
+            "xtm_lattice_user_index": ([vp, vp], i32),
             "xtm_particles_bind": ([vp, vp, vp], i32),
             "xtm_particles_release": ([vp], i32),
             "xtm_particles_init": ([vp, vp, i64, i32, vp], i32),
@@ -155,13 +156,24 @@ class Lattice:
         if el.dtype.itemsize != inputs.ELEMENT_DTYPE.itemsize:
             raise ValueError("elements must use inputs.ELEMENT_DTYPE")
         self.ref = ref
-        self.n_elements = len(el)
         self._el = el
         r = _ref_struct(ref)
         h = ctypes.c_void_p()
         check(lib().xtm_lattice_create(el.ctypes.data_as(ctypes.c_void_p), len(el),
                                        ctypes.byref(r), ctypes.byref(h)), "xtm_lattice_create")
         self._h = h
+        n = ctypes.c_int32()
+        b = ctypes.c_int64()
+        check(lib().xtm_lattice_info(self._h, ctypes.byref(n), ctypes.byref(b)), "xtm_lattice_info")
+        # elements of the line the library tracks (thick elements sliced)
+        self.n_elements = int(n.value)
+
+    def user_index(self) -> np.ndarray:
+        """User element of each element of the sliced line."""
+        out = np.zeros(max(self.n_elements, 1), dtype=np.int32)
+        check(lib().xtm_lattice_user_index(self._h, out.ctypes.data_as(ctypes.c_void_p)),
+              "xtm_lattice_user_index")
+        return out[: self.n_elements]
 
     @property
     def handle(self):

@@ -74,8 +74,10 @@ struct xtm_lattice_s {
   // launch plan chosen by xtm_autotune (0 = none): used when the caller's
   // options leave the kernel variant and block size at 0
   int32_t plan_variant = 0, plan_block = 0;
-  // the element descriptions as given (geometry of the loss refinement)
+  // the element descriptions of the sliced line (thick elements replaced by
+  // their slices) and the user element of each
   std::vector<xtm_element_desc> desc_h;
+  std::vector<int32_t> user_h;
   // loss-refinement geometry for one polygon size, built on first use
   int32_t refine_M = 0;
   void* refine_buf = nullptr;
@@ -601,6 +603,60 @@ int32_t xtm_max_variant(void) { return 4 + xtm::kLineStyles; }
 
 const char* xtm_version(void) { return "xtm 0.1 (gfx950, FP64 thin-lattice tracker)"; }
 
+namespace {
+// Thick elements as drift-kick-drift slices, kicks at the slice midpoints:
+// d = L/N; DRIFT(d/2), then N times [kick, DRIFT(d)], the last drift d/2.
+xtm_status expand_thick(const xtm_element_desc* el, int32_t n, std::vector<xtm_element_desc>* out,
+                        std::vector<int32_t>* user) {
+  for (int32_t i = 0; i < n; ++i) {
+    const xtm_element_desc& e = el[i];
+    if (e.type != XTM_QUADRUPOLE && e.type != XTM_SBEND) {
+      out->push_back(e);
+      user->push_back(i);
+      continue;
+    }
+    const std::string where = "element " + std::to_string(i) + ": ";
+    const double L = e.length, Nd = e.p[2];
+    if (!(L > 0.0) || !std::isfinite(L))
+      return fail(XTM_E_ELEMENT, where + "thick element needs a finite length > 0");
+    if (!(Nd >= 1.0 && Nd <= 10000.0) || Nd != std::floor(Nd))
+      return fail(XTM_E_ELEMENT, where + "slice count p[2] must be an integer in 1..10000");
+    if (!std::isfinite(e.p[0]) || !std::isfinite(e.p[1]))
+      return fail(XTM_E_ELEMENT, where + "non-finite strength");
+    const int32_t N = (int32_t)Nd;
+    const double d = L / (double)N;
+    const double half = 0.5 * d;
+    xtm_element_desc dr{};
+    dr.type = XTM_DRIFT;
+    xtm_element_desc k{};
+    k.type = XTM_MULTIPOLE;
+    k.order = 1;
+    if (e.type == XTM_QUADRUPOLE) {
+      k.knl[1] = e.p[0] * d;
+      k.ksl[1] = e.p[1] * d;
+    } else {
+      const double a = e.p[0] / (double)N;
+      k.knl[0] = a;
+      k.hxl = a;
+      k.length = d;
+      k.knl[1] = e.p[1] * d;
+    }
+    dr.length = half;
+    out->push_back(dr);
+    user->push_back(i);
+    for (int32_t j = 0; j < N; ++j) {
+      out->push_back(k);
+      user->push_back(i);
+      dr.length = (j + 1 == N) ? half : d;
+      out->push_back(dr);
+      user->push_back(i);
+    }
+  }
+  if (out->size() > (size_t)0x7fffffff) return fail(XTM_E_ELEMENT, "line too long");
+  return XTM_OK;
+}
+}  // namespace
+
 xtm_status xtm_lattice_create(const xtm_element_desc* el, int32_t n, const xtm_reference* ref,
                               xtm_lattice* out) {
   return guarded([&]() -> xtm_status {
@@ -610,15 +666,19 @@ xtm_status xtm_lattice_create(const xtm_element_desc* el, int32_t n, const xtm_r
     RefQ r;
     if (!make_ref(ref, &r)) return fail(XTM_E_REFERENCE, "reference needs mass > 0 and p0c > 0");
     auto* L = new xtm_lattice_s();
-    L->n_el = n;
     L->ref = r;
-    if (n > 0) L->desc_h.assign(el, el + n);
+    {
+      const xtm_status st = expand_thick(el, n, &L->desc_h, &L->user_h);
+      if (st != XTM_OK) { delete L; return st; }
+    }
+    n = (int32_t)L->desc_h.size();
+    L->n_el = n;
     for (int32_t i = 0; i < n; ++i) {
-      xtm_status st = pack(el[i], i, r, 1.0, L->fwd_h);
+      xtm_status st = pack(L->desc_h[i], L->user_h[i], r, 1.0, L->fwd_h);
       if (st != XTM_OK) { delete L; return st; }
     }
     for (int32_t i = n - 1; i >= 0; --i) {
-      xtm_status st = pack(el[i], i, r, -1.0, L->bwd_h);
+      xtm_status st = pack(L->desc_h[i], L->user_h[i], r, -1.0, L->bwd_h);
       if (st != XTM_OK) { delete L; return st; }
     }
     L->fwd_seg_h = segment(L->fwd_h, n);
@@ -667,6 +727,14 @@ xtm_status xtm_lattice_destroy(xtm_lattice L) {
   }
   delete L;
   return XTM_OK;
+}
+
+xtm_status xtm_lattice_user_index(xtm_lattice L, int32_t* h_out) {
+  return guarded([&]() -> xtm_status {
+    if (!L || (!h_out && L->n_el > 0)) return fail(XTM_E_ARG, "null lattice or output");
+    if (L->n_el > 0) std::memcpy(h_out, L->user_h.data(), L->n_el * sizeof(int32_t));
+    return XTM_OK;
+  });
 }
 
 xtm_status xtm_lattice_info(xtm_lattice L, int32_t* n_elements, int64_t* table_bytes) {

@@ -51,11 +51,14 @@ AP_CIRCLE = 7
 AP_ELLIPSE = 8
 AP_RECT = 9
 MARKER = 10
+QUADRUPOLE = 11
+SBEND = 12
 
 TYPE_NAMES = {DRIFT: "drift", DRIFT_EXPANDED: "drift_expanded",
               MULTIPOLE: "multipole", RF: "rf", XYSHIFT: "xyshift",
               SROTATION: "srotation", AP_CIRCLE: "ap_circle",
-              AP_ELLIPSE: "ap_ellipse", AP_RECT: "ap_rect", MARKER: "marker"}
+              AP_ELLIPSE: "ap_ellipse", AP_RECT: "ap_rect", MARKER: "marker",
+              QUADRUPOLE: "quadrupole", SBEND: "sbend"}
 
 ELEMENT_DTYPE = np.dtype([
     ("type", "<i4"), ("order", "<i4"), ("length", "<f8"),
@@ -159,6 +162,30 @@ def ap_rect(xmin: float, xmax: float, ymin: float, ymax: float) -> np.ndarray:
 def marker() -> np.ndarray:
     e = _blank()
     e["type"] = MARKER
+    return e
+
+
+def quadrupole(length: float, k1: float, k1s: float = 0.0, slices: int = 4) -> np.ndarray:
+    """Thick quadrupole of length [m] and gradient k1, k1s [m^-2], tracked as
+    `slices` drift-kick-drift slices."""
+    e = _blank()
+    e["type"] = QUADRUPOLE
+    e["length"] = length
+    e["p"][0] = k1
+    e["p"][1] = k1s
+    e["p"][2] = slices
+    return e
+
+
+def sbend(length: float, angle: float, k1: float = 0.0, slices: int = 4) -> np.ndarray:
+    """Thick sector bend of length [m], bending angle [rad] and gradient k1
+    [m^-2], tracked as `slices` drift-kick-drift slices."""
+    e = _blank()
+    e["type"] = SBEND
+    e["length"] = length
+    e["p"][0] = angle
+    e["p"][1] = k1
+    e["p"][2] = slices
     return e
 
 
