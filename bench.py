@@ -82,6 +82,10 @@ def element_flops(el) -> np.ndarray:
             f[i] = 6
         elif t == I.AP_RECT:
             f[i] = 4
+        elif t in (I.QUADRUPOLE, I.SBEND):
+            # N order-1 kicks (with curvature for a bend) and N + 1 drifts
+            n = int(e["p"][2])
+            f[i] = (n + 1) * 17 + n * (10 + (11 if t == I.SBEND else 0))
     return f
 
 
@@ -125,6 +129,14 @@ def workload(name: str, n_override: int | None):
                 f"{int(counts.sum())} Gaussian protons in total (2,000-50,000 per variant), "
                 "one batched launch per chunk")
         return els, (np.concatenate(cs), counts), I.PROTON_450GEV, desc, 200, 2
+    if name == "thick":
+        el = I.thick_ring()
+        c = I.gaussian_particles(n_override or (1 << 20), seed=23,
+                                 sigmas=np.array([1.5e-3, 5e-5, 1.2e-3, 5e-5, 0.1, 1e-4]))
+        desc = (f"ring of thick quadrupoles and sector bends sliced into drift-kick-drift "
+                f"slices (16 cells, 144 elements, 784 after slicing), {len(c)} Gaussian "
+                "protons at 450 GeV")
+        return el, c, I.PROTON_450GEV, desc, 100, 1
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -383,7 +395,7 @@ def main():
     ap.add_argument("--turns-per-step", type=int, default=None)
     ap.add_argument("--workload", default="cfg2",
                     choices=["cfg2", "cfg1", "cfg1sat", "cfg3", "cfg4", "cfg5", "refine",
-                             "twiss"])
+                             "twiss", "thick"])
     ap.add_argument("--refine-vertices", type=int, default=64,
                     help="refine: polygon vertices per aperture")
     ap.add_argument("--refine-ds", type=float, default=0.01, help="refine: sub-step [m]")
@@ -466,6 +478,7 @@ def main():
         batch = P.Batch(lats)
     else:
         lat = P.Lattice(el, ref)
+    n_el_tracked = 0 if batched else lat.n_elements
     coords_dev = torch.from_numpy(np.ascontiguousarray(coords)).to("cuda")
     extra = dict(radiation=2, seed=20231002) if args.workload == "cfg5" else {}
 
@@ -536,7 +549,9 @@ def main():
         return
 
     flops = element_flops(el_all)
-    flops_per_pass = float(flops.sum() / len(el_all))
+    # per element of the tracked line (thick elements count their slices)
+    n_tracked = n_el_tracked if n_el_tracked else len(el_all)
+    flops_per_pass = float(flops.sum() / n_tracked)
     achieved_tflops = total_passes * flops_per_pass / (kernel_ms / 1e3) / 1e12 if kernel_ms > 0 else 0.0
 
     key = (args.workload, n, tps, steps, variant_ran, kernel_source_hash())

@@ -189,6 +189,18 @@ def sbend(length: float, angle: float, k1: float = 0.0, slices: int = 4) -> np.n
     return e
 
 
+def thick_ring(n_cells: int = 16, k1: float = 0.06) -> np.ndarray:
+    """Ring of thick elements: n_cells x [QF (1 m, 4 slices), sector bend (6 m,
+    pi/n_cells, 6 slices), circular aperture 30 mm, drift 2 m, QD (1 m, with a
+    small skew gradient), bend, elliptic aperture 30 x 20 mm, drift 2 m, thin
+    sextupole]."""
+    ang = 2.0 * math.pi / (2 * n_cells)
+    cell = [quadrupole(1.0, k1, slices=4), sbend(6.0, ang, slices=6), ap_circle(0.03),
+            drift(2.0), quadrupole(1.0, -k1, k1s=1e-4, slices=4), sbend(6.0, ang, slices=6),
+            ap_ellipse(0.03, 0.02), drift(2.0), multipole(knl=[0.0, 0.0, 0.2])]
+    return line(cell * n_cells)
+
+
 def line(elements) -> np.ndarray:
     """Stack element records into a contiguous C-compatible array."""
     out = np.zeros(len(elements), dtype=ELEMENT_DTYPE)

@@ -24,18 +24,10 @@ def P():
     return P
 
 
-def thick_ring(n_cells=16):
-    cell = [I.quadrupole(1.0, 0.06, slices=4), I.sbend(6.0, 2 * np.pi / (2 * n_cells), slices=6),
-            I.ap_circle(0.03), I.drift(2.0), I.quadrupole(1.0, -0.06, k1s=1e-4, slices=4),
-            I.sbend(6.0, 2 * np.pi / (2 * n_cells), slices=6), I.ap_ellipse(0.03, 0.02),
-            I.drift(2.0), I.multipole(knl=[0.0, 0.0, 0.2])]
-    return I.line(cell * n_cells)
-
-
 def test_thick_ring_tracking_bitwise(P, oracle_mod):
     print("[gpu-thick] 16-cell ring of thick quadrupoles and bends, 600 protons, 60 turns",
           flush=True)
-    el = thick_ring()
+    el = I.thick_ring()
     thin = oracle_mod.expand_thick(el)
     c = I.gaussian_particles(600, seed=17, sigmas=np.array([6e-3, 5e-4, 4e-3, 5e-4, 0.1, 1e-3]))
     g, gp, _, lat, _ = gpu_run(P, el, REF, c, 60)
@@ -53,7 +45,7 @@ def test_thick_ring_tracking_bitwise(P, oracle_mod):
 
 
 def test_thick_ring_optics(P, oracle_mod):
-    el = thick_ring()
+    el = I.thick_ring()
     g = P.twiss(P.Lattice(el, REF))
     o = oracle_mod.twiss(el, REF, h=1e-9, hd=1e-8)
     for c in ("betx", "bety", "alfx", "alfy", "mux", "muy", "dx", "dpx"):
