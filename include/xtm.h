@@ -350,6 +350,14 @@ xtm_status xtm_twiss(xtm_lattice lat, double delta0, double h, double hd, int32_
                      double tol, const double* co_guess, double* h_table,
                      xtm_twiss_summary* summary, void* stream);
 
+/* Chromaticity by tracking (paper section "Twiss module": tunes and
+   chromaticities measured on the tracking model): out_dq[0..1] (host) =
+   (Q(delta0 + eps) - Q(delta0 - eps)) / (2 eps) for the horizontal and
+   vertical tunes of xtm_twiss (same h, hd, max_iter, tol; each side finds its
+   own closed orbit).  Synchronising. */
+xtm_status xtm_chromaticity(xtm_lattice lat, double delta0, double eps, double h, double hd,
+                            int32_t max_iter, double tol, double* out_dq, void* stream);
+
 /* Copy the loss record into host buffers of the bound length (any may be
    NULL).  Synchronises the stream. */
 xtm_status xtm_get_losses(xtm_particles p, int32_t* h_state, int32_t* h_at_turn,

@@ -352,6 +352,14 @@ def twiss(elements, ref, delta0: float = 0.0, h: float = 1e-8, hd: float = 1e-7,
     return tab
 
 
+def chromaticity(elements, ref, delta0: float = 0.0, eps: float = 1e-6, **kw):
+    """dQ/d delta as (Q(delta0 + eps) - Q(delta0 - eps)) / (2 eps), each tune from
+    the optics by tracking at that momentum (its own closed orbit)."""
+    p = twiss(elements, ref, delta0=delta0 + eps, **kw)
+    m = twiss(elements, ref, delta0=delta0 - eps, **kw)
+    return (p["qx"] - m["qx"]) / (2.0 * eps), (p["qy"] - m["qy"]) / (2.0 * eps)
+
+
 def reference(ref) -> tuple[float, float]:
     """(beta0, gamma0) as the oracle computes them."""
     out = np.zeros(2)

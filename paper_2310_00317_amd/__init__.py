@@ -102,6 +102,8 @@ def lib() -> ctypes.CDLL:
             "xtm_track_per_element": ([vp, vp, i32, vp, vp], i32),
             "xtm_refine_losses": ([vp, vp, i32, ctypes.c_double, i32, vp, vp, vp, vp, vp], i32),
             "xtm_track_record": ([vp, vp, i64, vp, vp], i32),
+            "xtm_chromaticity": ([vp, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                  ctypes.c_double, i32, ctypes.c_double, vp, vp], i32),
             "xtm_twiss": ([vp, ctypes.c_double, ctypes.c_double, ctypes.c_double, i32,
                            ctypes.c_double, vp, vp, vp, vp], i32),
             "xtm_get_losses": ([vp, vp, vp, vp, vp], i32),
@@ -439,6 +441,17 @@ def twiss(lattice: Lattice, delta0: float = 0.0, h: float = 1e-9, hd: float = 1e
     out.update(qx=summ.qx, qy=summ.qy, co=np.array(summ.co[:]), iterations=summ.iterations,
                residual=summ.residual)
     return out
+
+
+def chromaticity(lattice: Lattice, delta0: float = 0.0, eps: float = 1e-6, h: float = 1e-9,
+                 hd: float = 1e-8, max_iter: int = 30, tol: float = 1e-15, stream=None):
+    """(dQx/d delta, dQy/d delta) by central differences of the tracked tunes
+    (xtm_chromaticity)."""
+    out = np.zeros(2, dtype=np.float64)
+    check(lib().xtm_chromaticity(lattice.handle, float(delta0), float(eps), float(h), float(hd),
+                                 int(max_iter), float(tol), out.ctypes.data_as(ctypes.c_void_p),
+                                 _stream(stream)), "xtm_chromaticity")
+    return float(out[0]), float(out[1])
 
 
 def track_backward(lattice: Lattice, particles: Particles, n_turns: int, stats: bool = True,

@@ -1785,6 +1785,24 @@ xtm_status xtm_twiss(xtm_lattice L, double delta0, double h, double hd, int32_t 
   });
 }
 
+xtm_status xtm_chromaticity(xtm_lattice L, double delta0, double eps, double h, double hd,
+                            int32_t max_iter, double tol, double* out_dq, void* stream) {
+  return guarded([&]() -> xtm_status {
+    if (!L || !out_dq) return fail(XTM_E_ARG, "null lattice or output");
+    if (!(eps > 0.0) || !std::isfinite(eps)) return fail(XTM_E_ARG, "eps must be finite and > 0");
+    std::vector<double> table((size_t)(L->n_el + 1) * 15);
+    xtm_twiss_summary sp{}, sm{};
+    xtm_status st = xtm_twiss(L, delta0 + eps, h, hd, max_iter, tol, nullptr, table.data(), &sp,
+                              stream);
+    if (st != XTM_OK) return st;
+    st = xtm_twiss(L, delta0 - eps, h, hd, max_iter, tol, nullptr, table.data(), &sm, stream);
+    if (st != XTM_OK) return st;
+    out_dq[0] = (sp.qx - sm.qx) / (2.0 * eps);
+    out_dq[1] = (sp.qy - sm.qy) / (2.0 * eps);
+    return XTM_OK;
+  });
+}
+
 xtm_status xtm_sync(void* stream) {
   hipError_t e = hipStreamSynchronize((hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "stream synchronise");

@@ -102,3 +102,19 @@ def test_unstable_map_is_an_error(P):
         P.twiss(P.Lattice(el, REF))
     with pytest.raises(P.XtmError):
         P.twiss(P.Lattice(el, REF), h=0.0)
+
+
+def test_chromaticity(P, oracle_mod):
+    banner("chromaticity by tracking: FODO ring and the bend ring")
+    el = I.cfg1_lattice(rf_on=False)
+    g = P.chromaticity(P.Lattice(el, REF), eps=1e-7, h=1e-10, hd=1e-9)
+    o = oracle_mod.chromaticity(el, REF, eps=1e-7, h=1e-10, hd=1e-9)
+    assert abs(g[0] - o[0]) < 1e-9 * abs(o[0]) and abs(g[1] - o[1]) < 1e-9 * abs(o[1])
+    cell = [I.multipole(knl=[0.0, 0.04]), I.multipole(knl=[0.05], hxl=0.05, length=2.0),
+            I.drift(10.0), I.multipole(knl=[0.0, -0.04], ksl=[2e-5]),
+            I.multipole(knl=[0.05, 0.0, 0.3], hxl=0.05, length=2.0), I.drift(10.0)]
+    el = I.line(cell * 20)
+    g = P.chromaticity(P.Lattice(el, REF), eps=1e-5, h=1e-6, hd=1e-6)
+    o = oracle_mod.chromaticity(el, REF, eps=1e-5, h=1e-6, hd=1e-6)
+    # tunes carry ~1e-10 of finite-difference noise on millimetre orbits
+    assert abs(g[0] - o[0]) < 1e-4 and abs(g[1] - o[1]) < 1e-4

@@ -94,3 +94,16 @@ def test_dispersion_is_the_momentum_derivative_of_the_closed_orbit(oracle_mod):
         assert np.max(np.abs(fd - tw[d])) < 1e-6 * np.max(np.abs(tw[d]))
     assert np.max(np.abs(tw["dx"])) > 1.0  # the bends make it sizeable
     assert np.allclose(tw["dy"], 0.0, atol=1e-9)
+
+
+def test_natural_chromaticity_thin_fodo(oracle_mod):
+    # thin quadrupoles, kicks independent of delta, drifts advancing px/(1+delta):
+    # the effective focusing is K/(1+delta), so xi = -(1/4 pi) sum beta_i K_i L_i
+    el = I.cfg1_lattice(rf_on=False, sextupoles=False)
+    f, L, mu, bmax, bmin = fodo_closed_form()
+    xi = -100.0 * (bmax - bmin) / (4.0 * math.pi * f)
+    cx, cy = oracle_mod.chromaticity(el, REF, eps=1e-7, h=1e-10, hd=1e-9)
+    assert abs(cx - xi) < 1e-4 * abs(xi) and abs(cy - xi) < 1e-4 * abs(xi)
+    # sextupoles at the quadrupoles do nothing at zero dispersion
+    cx2, _ = oracle_mod.chromaticity(I.cfg1_lattice(rf_on=False), REF, eps=1e-7, h=1e-10, hd=1e-9)
+    assert abs(cx2 - cx) < 1e-4 * abs(xi)
