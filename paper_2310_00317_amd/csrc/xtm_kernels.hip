@@ -1345,12 +1345,14 @@ __device__ __forceinline__ bool in_poly_wave(double px, double py, const Edge& e
 }
 
 // the whole polygon A + w (B - A) for one lane's point, vertices from LDS
-// ((x, y) pairs), each vertex interpolated once and carried to the next edge
+// ((x, y) pairs of A and of the differences D = B - A, rounded once: the
+// same values lerp forms), each vertex interpolated once and carried to the
+// next edge
 __device__ __forceinline__ bool in_poly_lane(double px, double py, const double2* A,
-                                             const double2* B, int32_t M, double w) {
+                                             const double2* D, int32_t M, double w) {
   bool in = false;
-  const double2 a0 = A[0], b0 = B[0];
-  const double x0 = lerp_f(a0.x, b0.x, w), y0 = lerp_f(a0.y, b0.y, w);
+  const double2 a0 = A[0], d0 = D[0];
+  const double x0 = fma(w, d0.x, a0.x), y0 = fma(w, d0.y, a0.y);
   double xi = x0, yi = y0;
   for (int32_t k = 0; k < M; ++k) {
     double xj, yj;
@@ -1358,9 +1360,9 @@ __device__ __forceinline__ bool in_poly_lane(double px, double py, const double2
       xj = x0;
       yj = y0;
     } else {
-      const double2 a = A[k + 1], b = B[k + 1];
-      xj = lerp_f(a.x, b.x, w);
-      yj = lerp_f(a.y, b.y, w);
+      const double2 a = A[k + 1], d = D[k + 1];
+      xj = fma(w, d.x, a.x);
+      yj = fma(w, d.y, a.y);
     }
     if ((yi > py) != (yj > py)) {
       const double t1 = (xj - xi) * (py - yi);
@@ -1415,12 +1417,12 @@ k_refine(const uint64_t* __restrict__ fwd, const uint64_t* __restrict__ bwd, Ref
         const int32_t M = g.M;
         const double* A = g.poly + (size_t)g.ap_ord[eP] * 2 * M;
         const double* B = g.poly + (size_t)g.ap_ord[eL] * 2 * M;
-        __shared__ double2 polyA[kRefineLdsVerts], polyB[kRefineLdsVerts];
+        __shared__ double2 polyA[kRefineLdsVerts], polyD[kRefineLdsVerts];
         const bool lds = M <= kRefineLdsVerts;
         if (lds) {
           for (int32_t v = threadIdx.x; v < M; v += 64) {
             polyA[v] = make_double2(A[2 * v], A[2 * v + 1]);
-            polyB[v] = make_double2(B[2 * v], B[2 * v + 1]);
+            polyD[v] = make_double2(B[2 * v] - A[2 * v], B[2 * v + 1] - A[2 * v + 1]);
           }
           __syncthreads();
         }
@@ -1463,7 +1465,7 @@ k_refine(const uint64_t* __restrict__ fwd, const uint64_t* __restrict__ bwd, Ref
                   const double f = (double)kk / (double)K;
                   const double sf = sc + L * f;
                   const double w = (sf - sP) / (sL - sP);
-                  out = !in_poly_lane(lerp_f(v0x, v1x, f), lerp_f(v0y, v1y, f), polyA, polyB,
+                  out = !in_poly_lane(lerp_f(v0x, v1x, f), lerp_f(v0y, v1y, f), polyA, polyD,
                                       M, w);
                 }
                 const unsigned long long mask = __ballot(out);
