@@ -352,6 +352,76 @@ def twiss(elements, ref, delta0: float = 0.0, h: float = 1e-8, hd: float = 1e-7,
     return tab
 
 
+S4 = np.array([[0.0, 1.0, 0.0, 0.0], [-1.0, 0.0, 0.0, 0.0], [0.0, 0.0, 0.0, 1.0],
+               [0.0, 0.0, -1.0, 0.0]])
+
+
+def twiss_coupled(elements, ref, delta0: float = 0.0, h: float = 1e-9, hd: float = 1e-8,
+                  max_iter: int = 30, tol: float = 1e-15) -> dict:
+    """Transverse optics with linear coupling (paper section "Twiss module":
+    the normal form from the eigenvalues and eigenvectors of the one-turn
+    Jacobian, the eigenvectors propagated by tracking).  From the 4x4 one-turn
+    map J at the closed orbit (the same orbit and maps as twiss()):
+      eigenvalues e^{+-i mu_I}, e^{+-i mu_II}; of each conjugate pair the
+      eigenvector v with Im(v^H S v) > 0 is kept and scaled so that
+      v^H S v = 2i (S the 4x4 symplectic form); mode I is the one whose
+      summed horizontal beta along the line, sum_e |v_e,1|^2, exceeds its
+      summed vertical beta sum_e |v_e,3|^2 (the x-like mode);
+      at element e, v_e = M_e v: beta_xI = |v_e,1|^2, beta_yI = |v_e,3|^2 (and
+      likewise for mode II); the phase of mode I follows arg(v_e,1) and that
+      of mode II arg(v_e,3): through a drift the phase advances by the change
+      of the argument taken in [0, 2 pi), through a thin element (no length:
+      a kick or a frame change, which can turn the components) by the change
+      taken in (-pi, pi]; the eigen-tunes are the phases at the line end /
+      2 pi.
+    For an uncoupled ring beta_xI, beta_yII and the phases equal the
+    uncoupled ones (v = (sqrt(beta), (i - alpha)/sqrt(beta), 0, 0))."""
+    el = _els(elements)
+    base = twiss(el, ref, delta0=delta0, h=h, hd=hd, max_iter=max_iter, tol=tol)
+    u = np.array([base["x"][0], base["px"][0], base["y"][0], base["py"][0]])
+    rows = [np.r_[u, 0.0, delta0]]
+    for k in range(4):
+        for sgn in (1.0, -1.0):
+            v = np.r_[u, 0.0, delta0]
+            v[k] += sgn * h
+            rows.append(v)
+    out = track_record(el, ref, np.array(rows))
+    n_el = len(el)
+    M = np.empty((n_el + 1, 4, 4))
+    for k in range(4):
+        M[:, :, k] = (out[:, 1 + 2 * k, :4] - out[:, 2 + 2 * k, :4]) / (2.0 * h)
+    lam, vec = np.linalg.eig(M[n_el])
+    modes = []
+    for j in range(4):
+        v = vec[:, j]
+        c = np.conj(v) @ S4 @ v
+        if c.imag <= 0.0:
+            continue
+        v = v * math.sqrt(2.0 / c.imag)
+        modes.append(v)
+    if len(modes) != 2:
+        raise ValueError("one-turn map is not stably oscillating in two modes")
+    prop = [np.einsum("eij,j->ei", M, v) for v in modes]
+    xlike = [float(np.sum(np.abs(ve[:, 0]) ** 2) - np.sum(np.abs(ve[:, 2]) ** 2)) for ve in prop]
+    order = (0, 1) if xlike[0] >= xlike[1] else (1, 0)
+    res = {"s": base["s"], "qx_uncoupled": base["qx"], "qy_uncoupled": base["qy"]}
+    for name, j, comp in (("1", order[0], 0), ("2", order[1], 2)):
+        ve = prop[j]
+        res["betx" + name] = np.abs(ve[:, 0]) ** 2
+        res["bety" + name] = np.abs(ve[:, 2]) ** 2
+        th = np.angle(ve[:, comp])
+        mu = np.zeros(n_el + 1)
+        for e in range(1, n_el + 1):
+            dth = (th[e] - th[e - 1]) % (2.0 * math.pi)
+            if not (int(el["type"][e - 1]) in (1, 2) and el["length"][e - 1] > 0.0):
+                if dth > math.pi:
+                    dth -= 2.0 * math.pi
+            mu[e] = mu[e - 1] + dth
+        res["mu" + name] = mu
+        res["q" + name] = mu[n_el] / (2.0 * math.pi)
+    return res
+
+
 def chromaticity(elements, ref, delta0: float = 0.0, eps: float = 1e-6, **kw):
     """dQ/d delta as (Q(delta0 + eps) - Q(delta0 - eps)) / (2 eps), each tune from
     the optics by tracking at that momentum (its own closed orbit)."""

@@ -107,3 +107,38 @@ def test_natural_chromaticity_thin_fodo(oracle_mod):
     # sextupoles at the quadrupoles do nothing at zero dispersion
     cx2, _ = oracle_mod.chromaticity(I.cfg1_lattice(rf_on=False), REF, eps=1e-7, h=1e-10, hd=1e-9)
     assert abs(cx2 - cx) < 1e-4 * abs(xi)
+
+
+def coupled_bend_ring():
+    cell = [I.multipole(knl=[0.0, 0.04]), I.multipole(knl=[0.05], hxl=0.05, length=2.0), I.drift(10.0),
+            I.multipole(knl=[0.0, -0.04]), I.multipole(knl=[0.05], hxl=0.05, length=2.0), I.drift(10.0)]
+    return I.line(cell * 20)
+
+
+def test_coupled_optics_uncoupled_limit(oracle_mod):
+    el = coupled_bend_ring()
+    t = oracle_mod.twiss(el, REF, h=1e-6, hd=1e-6)
+    c = oracle_mod.twiss_coupled(el, REF, h=1e-6, hd=1e-6)
+    assert abs(c["q1"] - t["qx"]) < 1e-8 and abs(c["q2"] - t["qy"]) < 1e-8
+    assert np.allclose(c["betx1"], t["betx"], rtol=1e-7) and np.allclose(c["bety2"], t["bety"], rtol=1e-7)
+    assert np.allclose(c["mu1"], t["mux"], atol=1e-7) and np.allclose(c["mu2"], t["muy"], atol=1e-7)
+    assert np.max(c["bety1"]) < 1e-12 and np.max(c["betx2"]) < 1e-12
+
+
+@pytest.mark.parametrize("theta", [0.3, 1.2])
+def test_coupled_optics_in_a_rotated_frame(oracle_mod, theta):
+    # the same ring seen through a frame rotated by theta: the modes are the
+    # uncoupled ones, mixed at the line start as cos^2 / sin^2 of theta
+    el = coupled_bend_ring()
+    t = oracle_mod.twiss(el, REF, h=1e-6, hd=1e-6)
+    rot = I.line([I.srotation(theta)] + list(el) + [I.srotation(-theta)])
+    c = oracle_mod.twiss_coupled(rot, REF, h=1e-6, hd=1e-6)
+    assert abs(c["q1"] - t["qx"]) < 1e-8 and abs(c["q2"] - t["qy"]) < 1e-8
+    cs, sn = math.cos(theta) ** 2, math.sin(theta) ** 2
+    b0x, b0y = t["betx"][0], t["bety"][0]
+    assert abs(c["betx1"][0] - cs * b0x) < 1e-7 * b0x and abs(c["bety1"][0] - sn * b0x) < 1e-7 * b0x
+    assert abs(c["betx2"][0] - sn * b0y) < 1e-7 * b0y and abs(c["bety2"][0] - cs * b0y) < 1e-7 * b0y
+    # inside the rotated frame the motion is uncoupled again
+    assert np.allclose(c["betx1"][1:-1], t["betx"], rtol=1e-7)
+    assert np.allclose(c["bety2"][1:-1], t["bety"], rtol=1e-7)
+    assert np.max(c["bety1"][1:-1]) < 1e-9 * b0x
