@@ -350,6 +350,25 @@ xtm_status xtm_twiss(xtm_lattice lat, double delta0, double h, double hd, int32_
                      double tol, const double* co_guess, double* h_table,
                      xtm_twiss_summary* summary, void* stream);
 
+/* Transverse optics with linear coupling (paper section "Twiss module":
+   the linear normal form from the eigenvalues and eigenvectors of the
+   one-turn Jacobian, eigenvectors propagated by tracking).  From xtm_twiss's
+   closed orbit (same arguments), the 4x4 one-turn map J and the maps M_e to
+   every element (central differences of 9 recorded particles): the
+   eigenvalues from lambda + 1/lambda = t, t^2 - tr(J) t + (m2 - 2) = 0 (m2:
+   sum of the principal 2x2 minors); for each, the eigenvector with
+   Im(v^H S v) > 0, scaled so that v^H S v = 2i (S the 4x4 symplectic form);
+   mode I is the one whose summed |v_e,x|^2 along the line exceeds its summed
+   |v_e,y|^2.  h_table: host, (n_el + 1) rows of 7 doubles: s, beta_xI,
+   beta_yI, beta_xII, beta_yII (|component of v_e = M_e v|^2), phase of mode
+   I (argument of its x component) and of mode II (of its y component), each
+   advancing through a drift by the change of the argument in [0, 2 pi) and
+   through a thin element by the change in (-pi, pi].  out_q (host, 2): the
+   eigen-tunes, phases at the line end / 2 pi.  XTM_E_UNSUPPORTED for an
+   unstable or integer/half-integer map.  Synchronising. */
+xtm_status xtm_twiss_coupled(xtm_lattice lat, double delta0, double h, double hd, int32_t max_iter,
+                             double tol, double* h_table, double* out_q, void* stream);
+
 /* Chromaticity by tracking (paper section "Twiss module": tunes and
    chromaticities measured on the tracking model): out_dq[0..1] (host) =
    (Q(delta0 + eps) - Q(delta0 - eps)) / (2 eps) for the horizontal and

@@ -102,6 +102,8 @@ def lib() -> ctypes.CDLL:
             "xtm_track_per_element": ([vp, vp, i32, vp, vp], i32),
             "xtm_refine_losses": ([vp, vp, i32, ctypes.c_double, i32, vp, vp, vp, vp, vp], i32),
             "xtm_track_record": ([vp, vp, i64, vp, vp], i32),
+            "xtm_twiss_coupled": ([vp, ctypes.c_double, ctypes.c_double, ctypes.c_double, i32,
+                                   ctypes.c_double, vp, vp, vp], i32),
             "xtm_chromaticity": ([vp, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                   ctypes.c_double, i32, ctypes.c_double, vp, vp], i32),
             "xtm_twiss": ([vp, ctypes.c_double, ctypes.c_double, ctypes.c_double, i32,
@@ -440,6 +442,25 @@ def twiss(lattice: Lattice, delta0: float = 0.0, h: float = 1e-9, hd: float = 1e
     out = {c: table[:, k].copy() for k, c in enumerate(TWISS_COLUMNS)}
     out.update(qx=summ.qx, qy=summ.qy, co=np.array(summ.co[:]), iterations=summ.iterations,
                residual=summ.residual)
+    return out
+
+
+COUPLED_COLUMNS = ("s", "betx1", "bety1", "betx2", "bety2", "mu1", "mu2")
+
+
+def twiss_coupled(lattice: Lattice, delta0: float = 0.0, h: float = 1e-9, hd: float = 1e-8,
+                  max_iter: int = 30, tol: float = 1e-15, stream=None) -> dict:
+    """Transverse optics with linear coupling (xtm_twiss_coupled): per-element
+    mode betas and phases (COUPLED_COLUMNS) and the eigen-tunes q1, q2."""
+    n = lattice.n_elements
+    table = np.zeros((n + 1, len(COUPLED_COLUMNS)), dtype=np.float64)
+    q = np.zeros(2, dtype=np.float64)
+    check(lib().xtm_twiss_coupled(lattice.handle, float(delta0), float(h), float(hd), int(max_iter),
+                                  float(tol), table.ctypes.data_as(ctypes.c_void_p),
+                                  q.ctypes.data_as(ctypes.c_void_p), _stream(stream)),
+          "xtm_twiss_coupled")
+    out = {c: table[:, k].copy() for k, c in enumerate(COUPLED_COLUMNS)}
+    out.update(q1=float(q[0]), q2=float(q[1]))
     return out
 
 

@@ -7,6 +7,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <complex>
 #include <cstring>
 #include <random>
 #include <exception>
@@ -1782,6 +1783,167 @@ xtm_status xtm_twiss(xtm_lattice L, double delta0, double h, double hd, int32_t 
     hipFree(d_in);
     hipFree(d_out);
     return st;
+  });
+}
+
+namespace {
+using cplx = std::complex<double>;
+
+cplx det3(const cplx m[3][3]) {
+  return m[0][0] * (m[1][1] * m[2][2] - m[1][2] * m[2][1]) -
+         m[0][1] * (m[1][0] * m[2][2] - m[1][2] * m[2][0]) +
+         m[0][2] * (m[1][0] * m[2][1] - m[1][1] * m[2][0]);
+}
+
+// a null vector of the (numerically) rank-3 matrix J - lambda I: the row of
+// cofactors with the largest norm (a column of the adjugate)
+void null_vector(const double J[4][4], cplx lam, cplx v[4]) {
+  cplx A[4][4];
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j) A[i][j] = cplx(J[i][j], 0.0) - (i == j ? lam : cplx(0.0, 0.0));
+  double best = -1.0;
+  for (int r = 0; r < 4; ++r) {
+    cplx c[4];
+    double nrm = 0.0;
+    for (int col = 0; col < 4; ++col) {
+      cplx m[3][3];
+      for (int i = 0, ii = 0; i < 4; ++i) {
+        if (i == r) continue;
+        for (int j = 0, jj = 0; j < 4; ++j) {
+          if (j == col) continue;
+          m[ii][jj++] = A[i][j];
+        }
+        ++ii;
+      }
+      c[col] = ((r + col) % 2 ? -1.0 : 1.0) * det3(m);
+      nrm += std::norm(c[col]);
+    }
+    if (nrm > best) {
+      best = nrm;
+      for (int k = 0; k < 4; ++k) v[k] = c[k];
+    }
+  }
+}
+}  // namespace
+
+xtm_status xtm_twiss_coupled(xtm_lattice L, double delta0, double h, double hd, int32_t max_iter,
+                             double tol, double* h_table, double* out_q, void* stream) {
+  return guarded([&]() -> xtm_status {
+    if (!L || !h_table || !out_q) return fail(XTM_E_ARG, "null lattice or output");
+    const int32_t n_el = L->n_el;
+    std::vector<double> base((size_t)(n_el + 1) * 15);
+    xtm_twiss_summary sm{};
+    xtm_status st = xtm_twiss(L, delta0, h, hd, max_iter, tol, nullptr, base.data(), &sm, stream);
+    if (st != XTM_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    // the 9 probes around the closed orbit, one recorded turn
+    double c[9][6];
+    for (int r = 0; r < 9; ++r) {
+      for (int k = 0; k < 4; ++k) c[r][k] = base[1 + k];
+      c[r][4] = 0.0;
+      c[r][5] = delta0;
+    }
+    for (int k = 0; k < 4; ++k) {
+      c[1 + 2 * k][k] += h;
+      c[2 + 2 * k][k] -= h;
+    }
+    const size_t out_n = (size_t)(n_el + 1) * 9 * 6;
+    double* d_in = nullptr;
+    double* d_out = nullptr;
+    if (hipMalloc(&d_in, sizeof c) != hipSuccess || hipMalloc(&d_out, out_n * sizeof(double)) != hipSuccess) {
+      hipFree(d_in);
+      return fail(XTM_E_NOMEM, "coupled optics scratch allocation");
+    }
+    std::vector<double> out(out_n);
+    if (hipMemcpyAsync(d_in, c, sizeof c, hipMemcpyHostToDevice, s) != hipSuccess ||
+        launch_record(L->fwd_d, L->fwd_seg_d, (int32_t)(L->fwd_seg_h.size() / 3), n_el, d_in, 9,
+                      d_out, kref(L->ref, 0, 0), s) != hipSuccess ||
+        hipMemcpyAsync(out.data(), d_out, out_n * sizeof(double), hipMemcpyDeviceToHost, s) !=
+            hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      st = fail(XTM_E_HIP, "coupled optics record");
+    hipFree(d_in);
+    hipFree(d_out);
+    if (st != XTM_OK) return st;
+    auto at = [&](int32_t e, int r, int k) { return out[((size_t)e * 9 + r) * 6 + k]; };
+    std::vector<double> M((size_t)(n_el + 1) * 16);
+    for (int32_t e = 0; e <= n_el; ++e)
+      for (int i = 0; i < 4; ++i)
+        for (int k = 0; k < 4; ++k)
+          M[(size_t)e * 16 + i * 4 + k] = (at(e, 1 + 2 * k, i) - at(e, 2 + 2 * k, i)) / (2.0 * h);
+    double J[4][4];
+    for (int i = 0; i < 4; ++i)
+      for (int k = 0; k < 4; ++k) J[i][k] = M[(size_t)n_el * 16 + i * 4 + k];
+    // eigenvalues: lambda + 1/lambda = t, t^2 - tr(J) t + (m2 - 2) = 0, m2 the
+    // sum of the principal 2x2 minors
+    double tr = 0.0, tr2 = 0.0;
+    for (int i = 0; i < 4; ++i) {
+      tr += J[i][i];
+      for (int k = 0; k < 4; ++k) tr2 += J[i][k] * J[k][i];
+    }
+    const double m2 = 0.5 * (tr * tr - tr2);
+    const double disc = tr * tr - 4.0 * (m2 - 2.0);
+    if (!(disc >= 0.0)) return fail(XTM_E_UNSUPPORTED, "coupled optics: unstable one-turn map");
+    const double t[2] = {0.5 * (tr + std::sqrt(disc)), 0.5 * (tr - std::sqrt(disc))};
+    cplx modes[2][4];
+    for (int m = 0; m < 2; ++m) {
+      if (!(std::fabs(t[m]) < 2.0))
+        return fail(XTM_E_UNSUPPORTED, "coupled optics: unstable or integer/half-integer mode");
+      const double cm = 0.5 * t[m];
+      cplx lam(cm, std::sqrt(1.0 - cm * cm));
+      cplx v[4];
+      null_vector(J, lam, v);
+      // v^H S v with S = [[0,1,0,0],[-1,0,0,0],[0,0,0,1],[0,0,-1,0]]
+      cplx q = std::conj(v[0]) * v[1] - std::conj(v[1]) * v[0] + std::conj(v[2]) * v[3] -
+               std::conj(v[3]) * v[2];
+      if (q.imag() < 0.0) {
+        for (int k = 0; k < 4; ++k) v[k] = std::conj(v[k]);
+        q = std::conj(q);
+      }
+      if (!(q.imag() > 0.0)) return fail(XTM_E_UNSUPPORTED, "coupled optics: degenerate mode");
+      const double f = std::sqrt(2.0 / q.imag());
+      for (int k = 0; k < 4; ++k) modes[m][k] = v[k] * f;
+    }
+    // propagate, label (x-like mode first), phases
+    std::vector<cplx> ve[2];
+    double xlike[2] = {0.0, 0.0};
+    for (int m = 0; m < 2; ++m) {
+      ve[m].resize((size_t)(n_el + 1) * 4);
+      for (int32_t e = 0; e <= n_el; ++e) {
+        const double* Me = &M[(size_t)e * 16];
+        for (int i = 0; i < 4; ++i) {
+          cplx acc(0.0, 0.0);
+          for (int j = 0; j < 4; ++j) acc += Me[i * 4 + j] * modes[m][j];
+          ve[m][(size_t)e * 4 + i] = acc;
+        }
+        xlike[m] += std::norm(ve[m][(size_t)e * 4]) - std::norm(ve[m][(size_t)e * 4 + 2]);
+      }
+    }
+    const int order[2] = {xlike[0] >= xlike[1] ? 0 : 1, xlike[0] >= xlike[1] ? 1 : 0};
+    for (int slot = 0; slot < 2; ++slot) {
+      const auto& w = ve[order[slot]];
+      const int comp = slot == 0 ? 0 : 2;
+      double mu = 0.0, th_prev = 0.0;
+      for (int32_t e = 0; e <= n_el; ++e) {
+        double* row = h_table + (size_t)e * 7;
+        row[0] = base[(size_t)e * 15];
+        row[1 + 2 * slot] = std::norm(w[(size_t)e * 4]);
+        row[2 + 2 * slot] = std::norm(w[(size_t)e * 4 + 2]);
+        const double th = std::arg(w[(size_t)e * 4 + comp]);
+        if (e > 0) {
+          double d = std::fmod(th - th_prev, 2.0 * M_PI);
+          if (d < 0.0) d += 2.0 * M_PI;
+          const auto& de = L->desc_h[e - 1];
+          const bool drift = (de.type == XTM_DRIFT || de.type == XTM_DRIFT_EXPANDED) && de.length > 0.0;
+          if (!drift && d > M_PI) d -= 2.0 * M_PI;
+          mu += d;
+        }
+        th_prev = th;
+        row[5 + slot] = mu;
+      }
+      out_q[slot] = mu / (2.0 * M_PI);
+    }
+    return XTM_OK;
   });
 }
 

@@ -118,3 +118,24 @@ def test_chromaticity(P, oracle_mod):
     o = oracle_mod.chromaticity(el, REF, eps=1e-5, h=1e-6, hd=1e-6)
     # tunes carry ~1e-10 of finite-difference noise on millimetre orbits
     assert abs(g[0] - o[0]) < 1e-4 and abs(g[1] - o[1]) < 1e-4
+
+
+@pytest.mark.parametrize("case", ["rotated", "skew"])
+def test_coupled_optics(P, oracle_mod, case):
+    banner(f"coupled optics: {case}")
+    cell = [I.multipole(knl=[0.0, 0.04]), I.multipole(knl=[0.05], hxl=0.05, length=2.0),
+            I.drift(10.0), I.multipole(knl=[0.0, -0.04], ksl=[0.0, 0.004 if case == "skew" else 0.0]),
+            I.multipole(knl=[0.05], hxl=0.05, length=2.0), I.drift(10.0)]
+    el = I.line(cell * 20)
+    if case == "rotated":
+        el = I.line([I.srotation(1.2)] + list(el) + [I.srotation(-1.2)])
+    g = P.twiss_coupled(P.Lattice(el, REF), h=1e-6, hd=1e-6)
+    o = oracle_mod.twiss_coupled(el, REF, h=1e-6, hd=1e-6)
+    assert abs(g["q1"] - o["q1"]) < 1e-8 and abs(g["q2"] - o["q2"]) < 1e-8
+    for c in ("betx1", "bety1", "betx2", "bety2"):
+        scale = max(np.max(o["betx1"]), np.max(o["bety2"]))
+        assert np.max(np.abs(g[c] - o[c])) < 1e-6 * scale, c
+    for c in ("mu1", "mu2"):
+        assert np.max(np.abs(g[c] - o[c])) < 1e-6, c
+    if case == "skew":
+        assert np.max(o["bety1"]) > 1e-3 * np.max(o["betx1"])  # the skew gradients couple
