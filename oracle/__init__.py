@@ -352,6 +352,53 @@ def twiss(elements, ref, delta0: float = 0.0, h: float = 1e-8, hd: float = 1e-7,
     return tab
 
 
+def twiss_open(elements, ref, init, delta0: float = 0.0, h: float = 1e-9,
+               hd: float = 1e-8) -> dict:
+    """Optics of a line (or a portion of a ring given as its own element list)
+    from given initial conditions, for an assigned momentum deviation (paper
+    section "Twiss module"): init = (x, px, y, py, betx, alfx, bety, alfy, dx,
+    dpx, dy, dpy) at the line start.  The orbit is the tracked initial orbit;
+    the maps M_e and momentum columns m_e come from central differences of
+    particles displaced around it as in twiss(); per plane
+    beta = ((p beta0 - q alpha0)^2 + q^2)/beta0,
+    alpha = -((p beta0 - q alpha0)(r beta0 - t alpha0) + q t)/beta0,
+    phase = atan2(q, p beta0 - q alpha0) unwrapped from 0; dispersion
+    eta_e = M_e eta_0 + m_e.  Same columns as twiss()."""
+    el = _els(elements)
+    n_el = len(el)
+    init = np.asarray(init, dtype=np.float64)
+    u = init[:4]
+    rows = [np.r_[u, 0.0, delta0]]
+    for k in range(4):
+        for sgn in (1.0, -1.0):
+            v = np.r_[u, 0.0, delta0]
+            v[k] += sgn * h
+            rows.append(v)
+    for sgn in (1.0, -1.0):
+        rows.append(np.r_[u, 0.0, delta0 + sgn * hd])
+    out = track_record(el, ref, np.array(rows))
+    M = np.empty((n_el + 1, 4, 4))
+    for k in range(4):
+        M[:, :, k] = (out[:, 1 + 2 * k, :4] - out[:, 2 + 2 * k, :4]) / (2.0 * h)
+    md = (out[:, 9, :4] - out[:, 10, :4]) / (2.0 * hd)
+    eta = np.einsum("eij,j->ei", M, init[8:12]) + md
+    tab = {"s": np.concatenate([[0.0], np.cumsum(np.where(np.isin(el["type"], (1, 2)),
+                                                          el["length"], 0.0))]),
+           "x": out[:, 0, 0], "px": out[:, 0, 1], "y": out[:, 0, 2], "py": out[:, 0, 3],
+           "dx": eta[:, 0], "dpx": eta[:, 1], "dy": eta[:, 2], "dpy": eta[:, 3]}
+    for name, o, b0, a0 in (("x", 0, init[4], init[5]), ("y", 2, init[6], init[7])):
+        p_, q_, r_, t_ = M[:, o, o], M[:, o, o + 1], M[:, o + 1, o], M[:, o + 1, o + 1]
+        bb = p_ * b0 - q_ * a0
+        tab["bet" + name] = (bb * bb + q_ * q_) / b0
+        tab["alf" + name] = -(bb * (r_ * b0 - t_ * a0) + q_ * t_) / b0
+        th = np.arctan2(q_, bb)
+        mu = np.zeros(n_el + 1)
+        for e in range(1, n_el + 1):
+            mu[e] = mu[e - 1] + (th[e] - th[e - 1]) % (2.0 * math.pi)
+        tab["mu" + name] = mu
+    return tab
+
+
 S4 = np.array([[0.0, 1.0, 0.0, 0.0], [-1.0, 0.0, 0.0, 0.0], [0.0, 0.0, 0.0, 1.0],
                [0.0, 0.0, -1.0, 0.0]])
 

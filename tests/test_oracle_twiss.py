@@ -142,3 +142,24 @@ def test_coupled_optics_in_a_rotated_frame(oracle_mod, theta):
     assert np.allclose(c["betx1"][1:-1], t["betx"], rtol=1e-7)
     assert np.allclose(c["bety2"][1:-1], t["bety"], rtol=1e-7)
     assert np.max(c["bety1"][1:-1]) < 1e-9 * b0x
+
+
+def test_open_line_optics_drift_closed_form(oracle_mod):
+    b0, a0, d0, dp0 = 12.0, -1.5, 0.7, 0.02
+    el = I.line([I.drift(3.0), I.marker(), I.drift(4.5)])
+    t = oracle_mod.twiss_open(el, REF, [0, 0, 0, 0, b0, a0, 20.0, 0.5, d0, dp0, 0.0, 0.0], h=1e-9)
+    g0 = (1 + a0 * a0) / b0
+    for k, s in enumerate(t["s"]):
+        assert abs(t["betx"][k] - (b0 - 2 * a0 * s + g0 * s * s)) < 1e-9 * b0
+        assert abs(t["alfx"][k] - (a0 - g0 * s)) < 1e-9
+        assert abs(t["dx"][k] - (d0 + dp0 * s)) < 1e-9 and abs(t["dpx"][k] - dp0) < 1e-12
+
+
+def test_open_line_from_periodic_conditions_reproduces_the_ring(oracle_mod):
+    el = coupled_bend_ring()
+    t = oracle_mod.twiss(el, REF, h=1e-6, hd=1e-6)
+    init = [t["x"][0], t["px"][0], t["y"][0], t["py"][0], t["betx"][0], t["alfx"][0],
+            t["bety"][0], t["alfy"][0], t["dx"][0], t["dpx"][0], t["dy"][0], t["dpy"][0]]
+    o = oracle_mod.twiss_open(el, REF, init, h=1e-6, hd=1e-6)
+    for c in ("betx", "alfx", "mux", "bety", "alfy", "muy", "dx", "dpx"):
+        assert np.max(np.abs(o[c] - t[c])) < 1e-9 * max(1.0, np.max(np.abs(t[c]))), c
