@@ -369,6 +369,19 @@ xtm_status xtm_twiss(xtm_lattice lat, double delta0, double h, double hd, int32_
 xtm_status xtm_twiss_coupled(xtm_lattice lat, double delta0, double h, double hd, int32_t max_iter,
                              double tol, double* h_table, double* out_q, void* stream);
 
+/* Optics of a line (or of a portion of a ring, given as its own element
+   list) from given initial conditions, for an assigned momentum deviation
+   delta0 (paper section "Twiss module").  init (host, 12 values): x, px, y,
+   py, betx, alfx, bety, alfy, dx, dpx, dy, dpy at the line start (betas
+   > 0).  The orbit is the tracked initial orbit; the maps to every element
+   and their momentum columns come from central differences (+-h, +-hd) of
+   11 recorded particles as in xtm_twiss; beta, alpha and phase propagate as
+   there from the given beta and alpha (phase from 0), the dispersion as
+   M_e eta_0 + m_e from the given eta_0.  h_table: as xtm_twiss.
+   Synchronising. */
+xtm_status xtm_twiss_open(xtm_lattice lat, double delta0, double h, double hd, const double* init,
+                          double* h_table, void* stream);
+
 /* Chromaticity by tracking (paper section "Twiss module": tunes and
    chromaticities measured on the tracking model): out_dq[0..1] (host) =
    (Q(delta0 + eps) - Q(delta0 - eps)) / (2 eps) for the horizontal and

@@ -102,6 +102,8 @@ def lib() -> ctypes.CDLL:
             "xtm_track_per_element": ([vp, vp, i32, vp, vp], i32),
             "xtm_refine_losses": ([vp, vp, i32, ctypes.c_double, i32, vp, vp, vp, vp, vp], i32),
             "xtm_track_record": ([vp, vp, i64, vp, vp], i32),
+            "xtm_twiss_open": ([vp, ctypes.c_double, ctypes.c_double, ctypes.c_double, vp, vp,
+                                vp], i32),
             "xtm_twiss_coupled": ([vp, ctypes.c_double, ctypes.c_double, ctypes.c_double, i32,
                                    ctypes.c_double, vp, vp, vp], i32),
             "xtm_chromaticity": ([vp, ctypes.c_double, ctypes.c_double, ctypes.c_double,
@@ -443,6 +445,23 @@ def twiss(lattice: Lattice, delta0: float = 0.0, h: float = 1e-9, hd: float = 1e
     out.update(qx=summ.qx, qy=summ.qy, co=np.array(summ.co[:]), iterations=summ.iterations,
                residual=summ.residual)
     return out
+
+
+def twiss_open(lattice: Lattice, init, delta0: float = 0.0, h: float = 1e-9, hd: float = 1e-8,
+               stream=None) -> dict:
+    """Optics of a line from given initial conditions (xtm_twiss_open): init =
+    (x, px, y, py, betx, alfx, bety, alfy, dx, dpx, dy, dpy); the per-element
+    columns of TWISS_COLUMNS."""
+    n = lattice.n_elements
+    table = np.zeros((n + 1, len(TWISS_COLUMNS)), dtype=np.float64)
+    iv = np.ascontiguousarray(init, dtype=np.float64)
+    if iv.shape != (12,):
+        raise ValueError("init must hold 12 values")
+    check(lib().xtm_twiss_open(lattice.handle, float(delta0), float(h), float(hd),
+                               iv.ctypes.data_as(ctypes.c_void_p),
+                               table.ctypes.data_as(ctypes.c_void_p), _stream(stream)),
+          "xtm_twiss_open")
+    return {c: table[:, k].copy() for k, c in enumerate(TWISS_COLUMNS)}
 
 
 COUPLED_COLUMNS = ("s", "betx1", "bety1", "betx2", "bety2", "mu1", "mu2")

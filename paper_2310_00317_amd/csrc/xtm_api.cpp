@@ -1947,6 +1947,87 @@ xtm_status xtm_twiss_coupled(xtm_lattice L, double delta0, double h, double hd, 
   });
 }
 
+xtm_status xtm_twiss_open(xtm_lattice L, double delta0, double h, double hd, const double* init,
+                          double* h_table, void* stream) {
+  return guarded([&]() -> xtm_status {
+    if (!L || !init || !h_table) return fail(XTM_E_ARG, "null lattice, initial values or output");
+    if (!(h > 0.0) || !(hd > 0.0) || !std::isfinite(delta0))
+      return fail(XTM_E_ARG, "need h > 0, hd > 0, finite delta0");
+    if (!(init[4] > 0.0) || !(init[6] > 0.0)) return fail(XTM_E_ARG, "initial betas must be > 0");
+    const int32_t n_el = L->n_el;
+    hipStream_t s = (hipStream_t)stream;
+    double c[11][6];
+    for (int r = 0; r < 11; ++r) {
+      for (int k = 0; k < 4; ++k) c[r][k] = init[k];
+      c[r][4] = 0.0;
+      c[r][5] = delta0;
+    }
+    for (int k = 0; k < 4; ++k) {
+      c[1 + 2 * k][k] += h;
+      c[2 + 2 * k][k] -= h;
+    }
+    c[9][5] = delta0 + hd;
+    c[10][5] = delta0 - hd;
+    const size_t out_n = (size_t)(n_el + 1) * 11 * 6;
+    double* d_in = nullptr;
+    double* d_out = nullptr;
+    if (hipMalloc(&d_in, sizeof c) != hipSuccess || hipMalloc(&d_out, out_n * sizeof(double)) != hipSuccess) {
+      hipFree(d_in);
+      return fail(XTM_E_NOMEM, "open-line optics scratch allocation");
+    }
+    std::vector<double> out(out_n);
+    xtm_status st = XTM_OK;
+    if (hipMemcpyAsync(d_in, c, sizeof c, hipMemcpyHostToDevice, s) != hipSuccess ||
+        launch_record(L->fwd_d, L->fwd_seg_d, (int32_t)(L->fwd_seg_h.size() / 3), n_el, d_in, 11,
+                      d_out, kref(L->ref, 0, 0), s) != hipSuccess ||
+        hipMemcpyAsync(out.data(), d_out, out_n * sizeof(double), hipMemcpyDeviceToHost, s) !=
+            hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      st = fail(XTM_E_HIP, "open-line optics record");
+    hipFree(d_in);
+    hipFree(d_out);
+    if (st != XTM_OK) return st;
+    auto at = [&](int32_t e, int r, int k) { return out[((size_t)e * 11 + r) * 6 + k]; };
+    const double b0[2] = {init[4], init[6]}, a0[2] = {init[5], init[7]};
+    double s_acc = 0.0, th_prev[2] = {0.0, 0.0}, mu[2] = {0.0, 0.0};
+    for (int32_t e = 0; e <= n_el; ++e) {
+      double Me[4][4], md[4];
+      for (int i = 0; i < 4; ++i) {
+        for (int k = 0; k < 4; ++k) Me[i][k] = (at(e, 1 + 2 * k, i) - at(e, 2 + 2 * k, i)) / (2.0 * h);
+        md[i] = (at(e, 9, i) - at(e, 10, i)) / (2.0 * hd);
+      }
+      double* row = h_table + (size_t)e * 15;
+      if (e > 0) {
+        const auto& de = L->desc_h[e - 1];
+        if (de.type == XTM_DRIFT || de.type == XTM_DRIFT_EXPANDED) s_acc = s_acc + de.length;
+      }
+      row[0] = s_acc;
+      for (int k = 0; k < 4; ++k) row[1 + k] = at(e, 0, k);
+      for (int pl = 0; pl < 2; ++pl) {
+        const int o = 2 * pl;
+        const double p_ = Me[o][o], q_ = Me[o][o + 1], r_ = Me[o + 1][o], t_ = Me[o + 1][o + 1];
+        const double bb = p_ * b0[pl] - q_ * a0[pl];
+        row[5 + 3 * pl] = (bb * bb + q_ * q_) / b0[pl];
+        row[6 + 3 * pl] = -(bb * (r_ * b0[pl] - t_ * a0[pl]) + q_ * t_) / b0[pl];
+        const double th = std::atan2(q_, bb);
+        if (e > 0) {
+          double d = std::fmod(th - th_prev[pl], 2.0 * M_PI);
+          if (d < 0.0) d += 2.0 * M_PI;
+          mu[pl] = mu[pl] + d;
+        }
+        th_prev[pl] = th;
+        row[7 + 3 * pl] = mu[pl];
+      }
+      for (int i = 0; i < 4; ++i) {
+        double acc = 0.0;
+        for (int j = 0; j < 4; ++j) acc += Me[i][j] * init[8 + j];
+        row[11 + i] = acc + md[i];
+      }
+    }
+    return XTM_OK;
+  });
+}
+
 xtm_status xtm_chromaticity(xtm_lattice L, double delta0, double eps, double h, double hd,
                             int32_t max_iter, double tol, double* out_dq, void* stream) {
   return guarded([&]() -> xtm_status {

@@ -139,3 +139,20 @@ def test_coupled_optics(P, oracle_mod, case):
         assert np.max(np.abs(g[c] - o[c])) < 1e-6, c
     if case == "skew":
         assert np.max(o["bety1"]) > 1e-3 * np.max(o["betx1"])  # the skew gradients couple
+
+
+def test_open_line_optics(P, oracle_mod):
+    banner("optics of a line from given initial conditions")
+    cell = [I.multipole(knl=[0.0, 0.04]), I.multipole(knl=[0.05], hxl=0.05, length=2.0),
+            I.drift(10.0), I.multipole(knl=[0.0, -0.04], ksl=[1e-5]),
+            I.multipole(knl=[0.05], hxl=0.05, length=2.0), I.drift(10.0)]
+    el = I.line(cell * 7)
+    init = [1e-3, -2e-5, 5e-4, 1e-5, 30.0, -1.2, 18.0, 0.8, 2.0, 0.1, 0.0, 0.0]
+    for d0 in (0.0, 2e-4):
+        g = P.twiss_open(P.Lattice(el, REF), init, delta0=d0, h=1e-6, hd=1e-6)
+        o = oracle_mod.twiss_open(el, REF, init, delta0=d0, h=1e-6, hd=1e-6)
+        for c in ("s", "x", "px", "y", "py"):
+            assert np.array_equal(g[c], o[c]), c  # the same tracked orbit, bit for bit
+        for c in ("betx", "alfx", "mux", "bety", "alfy", "muy", "dx", "dpx", "dy", "dpy"):
+            scale = max(1.0, np.max(np.abs(o[c])))
+            assert np.max(np.abs(g[c] - o[c])) < 1e-12 * scale, c
