@@ -100,7 +100,9 @@ def test_shifted_tilted_rect_to_ellipse(P, oracle_mod):
     lat, parts, o = tracked(P, oracle_mod, el, c, 15)
     lost = o.state == 0
     assert lost.sum() > 200
-    for M, ds, nb in ((128, 0.01, 30), (16, 0.1, 10)):
+    # 512 vertices: above the LDS staging limit, the scan tests one edge per
+    # lane from global memory
+    for M, ds, nb in ((128, 0.01, 30), (16, 0.1, 10), (512, 0.05, 20)):
         refine_both(P, oracle_mod, el, lat, parts, o, M, ds, nb)
 
 
