@@ -59,3 +59,18 @@ def test_bad_thick_elements(P):
     for bad in (I.quadrupole(0.0, 0.1), I.quadrupole(1.0, 0.1, slices=0), I.sbend(1.0, 0.1, slices=2.5)):
         with pytest.raises(P.XtmError, match="element 1"):
             P.Lattice(I.line([I.marker(), bad]), REF)
+
+
+def test_refine_on_sliced_line(P, oracle_mod):
+    import torch
+    el = I.thick_ring()
+    c = I.gaussian_particles(600, seed=17, sigmas=np.array([6e-3, 5e-4, 4e-3, 5e-4, 0.1, 1e-3]))
+    g, _, _, lat, parts = gpu_run(P, el, REF, c, 30)
+    o, _ = oracle_run(oracle_mod, el, REF, c, 30)
+    assert_bitwise(g, o)
+    s, x, y = P.refine_losses(lat, parts, 64, 0.01, 30)
+    torch.cuda.synchronize()
+    so, xo, yo = oracle_mod.refine_losses(el, REF, o, 64, 0.01, 30)
+    assert_bitwise({"s": s.cpu().numpy(), "x": x.cpu().numpy(), "y": y.cpu().numpy()},
+                   {"s": so, "x": xo, "y": yo}, fields=("s", "x", "y"))
+    assert (o.state == 0).sum() > 20

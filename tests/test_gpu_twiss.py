@@ -156,3 +156,13 @@ def test_open_line_optics(P, oracle_mod):
         for c in ("betx", "alfx", "mux", "bety", "alfy", "muy", "dx", "dpx", "dy", "dpy"):
             scale = max(1.0, np.max(np.abs(o[c])))
             assert np.max(np.abs(g[c] - o[c])) < 1e-12 * scale, c
+
+
+def test_record_several_workgroups(P, oracle_mod):
+    # 200 particles: four workgroups of 64 lanes, the last one partly idle
+    el = I.cfg2_lattice(n_cells=40)
+    c = I.gaussian_particles(200, seed=8, sigmas=np.array([2e-3, 5e-5, 2e-3, 5e-5, 0.05, 2e-4]))
+    g = P.track_record(P.Lattice(el, REF), c).cpu().numpy()
+    o = oracle_mod.track_record(el, REF, c)
+    same = (g.view(np.int64) == o.view(np.int64)) | (np.isnan(g) & np.isnan(o))
+    assert same.all(), f"{(~same).sum()} values differ"
