@@ -1282,17 +1282,20 @@ hipError_t launch_record(const uint64_t* fwd, const int32_t* seg, int32_t n_seg,
 }  // namespace xtm
 
 // ------------------------------------------------ loss-location refinement
-// One wave per particle, one polygon edge per lane.  A particle lost on an
-// aperture is backtracked through the inverse maps to the exit of the
-// previous aperture, then tracked forward again (every lane carries the same
-// particle); inside each drift its line-frame position runs on the segment
-// between the drift's entry and exit, and the ends of the drift's sub-steps
-// are tested against the aperture interpolated vertex by vertex between the
-// two polygons: lane k tests edge (k, k+1), the even-odd parity is the
-// parity of the wave's ballot (the exclusive-or of the same per-edge tests
-// in any order).  The first failing sub-step is bisected.  Every operation
-// is the one written in the refinement definition (explicit fma for
-// interpolation, separate products and sums elsewhere).
+// One wave per particle.  A particle lost on an aperture is backtracked
+// through the inverse maps to the exit of the previous aperture, then tracked
+// forward again (every lane carries the same particle); inside each drift its
+// line-frame position runs on the segment between the drift's entry and exit,
+// and the ends of the drift's sub-steps are tested against the aperture
+// interpolated vertex by vertex between the two polygons.  The scan tests 64
+// consecutive sub-steps at once, lane l the sub-step base + 1 + l against the
+// whole polygon staged in LDS, the first failing one being the lowest set bit
+// of the wave's ballot (polygons above the LDS limit: one sub-step at a time,
+// one edge per lane).  The first failing sub-step is bisected with one edge
+// per lane: lane k tests edge (k, k+1) and the even-odd parity is the parity
+// of the wave's ballot (the exclusive-or of the same per-edge tests in any
+// order).  Every operation is the one written in the refinement definition
+// (explicit fma for interpolation, separate products and sums elsewhere).
 namespace xtm {
 namespace {
 
