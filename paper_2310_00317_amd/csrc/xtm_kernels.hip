@@ -1385,7 +1385,7 @@ __device__ __forceinline__ bool is_drift_k(uint32_t kt) { return kt == K_DRIFT |
 // tests 64 consecutive sub-steps at once (one per lane)
 constexpr int32_t kRefineLdsVerts = 256;
 
-__global__ void __launch_bounds__(64)
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 4)))
 k_refine(const uint64_t* __restrict__ fwd, const uint64_t* __restrict__ bwd, RefineGeom g, SoA P,
          int64_t n, KernelRef r, double* __restrict__ s_out, double* __restrict__ x_out,
          double* __restrict__ y_out, int32_t* __restrict__ tests) {
