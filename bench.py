@@ -305,6 +305,56 @@ def twiss_bench(args):
     print(json.dumps(out), flush=True)
 
 
+def cfg3_separate(args):
+    """The 64 lattice variants tracked one after another, each with its own
+    lattice, particle set and default launches (the comparison for the
+    batched launch): 1 warmup step, then the timed steps on the host clock
+    around all variants."""
+    import torch
+    import paper_2310_00317_amd as P
+    I = P.inputs
+    els, (coords, counts), ref, _, tps_default, steps_default = workload("cfg3", args.particles)
+    tps = args.turns_per_step or tps_default
+    steps = args.steps if args.steps is not None else steps_default
+    first = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+    lats = [P.Lattice(e, ref) for e in els]
+
+    def fresh():
+        return [P.Particles(int(counts[v]), ref).init(coords[first[v]:first[v + 1]])
+                for v in range(len(els))]
+
+    for _ in range(args.warmup):
+        sets = fresh()
+        for v in range(len(els)):
+            P.track(lats[v], sets[v], tps)
+    torch.cuda.synchronize()
+    sets = fresh()
+    torch.cuda.synchronize()
+    passes = 0
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        for v in range(len(els)):
+            pv, _ = P.track(lats[v], sets[v], tps)
+            passes += pv
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    f = element_flops(els[0])
+    fpp = float(f.sum() / len(els[0]))
+    achieved = passes * fpp / wall / 1e12
+    print(json.dumps({
+        "metric": "particle-element passes/s (FP64), lattice variants tracked one after another",
+        "value": passes / wall, "unit": "passes/s", "n_gpus": 1, "steps": steps,
+        "warmup": args.warmup, "ms_per_step": wall / steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"64 errored FODO variants, {int(counts.sum())} protons, each "
+                               "variant its own lattice, set and launches", "turns": steps * tps,
+                   "passes": int(passes), "wall_s": wall},
+        "roofline": {"bound": "alu", "kernel": "xtm_line, one lattice per launch sequence",
+                     "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": None,
+                     "flops_per_pass": fpp}}), flush=True)
+
+
 def learned_da(args):
     """Dynamic-aperture scan of the cfg1 ring: plain tracking to the horizon
     versus learned early stop (network) and the tune-diffusion rule, on the
@@ -427,6 +477,9 @@ def main():
     ap.add_argument("--per-element", action="store_true",
                     help="time the measurement baseline instead: one kernel launch per element "
                          "and turn, particle state through HBM at every element")
+    ap.add_argument("--separate", action="store_true",
+                    help="cfg3: track the variants one after another, each with its own "
+                         "lattice and particle set, instead of one batched launch per chunk")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-every", type=int, default=100)
     ap.add_argument("--cpu-turns", type=int, default=None,
@@ -457,6 +510,8 @@ def main():
         return refine_bench(args)
     if args.workload == "twiss":
         return twiss_bench(args)
+    if args.workload == "cfg3" and args.separate:
+        return cfg3_separate(args)
     el, coords, ref, desc, tps_default, steps_default = workload(args.workload, args.particles)
     tps = args.turns_per_step or tps_default
     steps = args.steps if args.steps is not None else steps_default
