@@ -477,6 +477,9 @@ def main():
     ap.add_argument("--per-element", action="store_true",
                     help="time the measurement baseline instead: one kernel launch per element "
                          "and turn, particle state through HBM at every element")
+    ap.add_argument("--autotune", action="store_true",
+                    help="run the launch-plan autotuner before the warmup and track with its "
+                         "pick (reported in config)")
     ap.add_argument("--separate", action="store_true",
                     help="cfg3: track the variants one after another, each with its own "
                          "lattice and particle set, instead of one batched launch per chunk")
@@ -550,6 +553,18 @@ def main():
         return P.track(lat, parts, turns, block=args.block, turns_per_chunk=args.chunk,
                        variant=args.variant, graph=args.graph, full_stats=True, **extra, **kw)
 
+    plan = None
+    if args.autotune:
+        # the autotuner times the candidate forms on a copy of the set for a
+        # few turns and keeps the fastest as the lattice's (or batch's) plan,
+        # which tracking then uses when no variant is forced
+        probe = P.Particles(n, ref).init(coords_dev)
+        if batched:
+            plan = P.autotune(probe, batch=batch, first_slot=first)
+        else:
+            plan = P.autotune(probe, lattice=lat)
+        torch.cuda.synchronize()
+        del probe
     if args.warmup > 0:
         w = P.Particles(n, ref).init(coords_dev)
         for _ in range(args.warmup):
@@ -626,6 +641,9 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": desc, "n_particles": n, "n_elements": n_el,
+                   **({"autotune_pick": {"variant": plan.variant, "block": plan.block,
+                                         "probe_passes_per_s": plan.passes_per_s}}
+                      if plan is not None else {}),
                    "turns": steps * tps, "alive_at_end": int(alive),
                    "passes": int(total_passes), "wall_s": wall},
         "roofline": {"bound": "alu", "kernel": KERNEL_NAMES.get(variant_ran, "?"),
