@@ -24,7 +24,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FP64_VECTOR_PEAK_TFLOPS = 78.6   # 256 CU x 128 FP64 FLOP/clk x 2.4 GHz
-KERNEL_NAMES = {1: "k_track", 2: "k_track2", 3: "k_track3", 4: "k_track4"}
+KERNEL_NAMES = {4: "k_track4 (element interpreter)"}
 for _s in range(8):
     KERNEL_NAMES[5 + _s] = "xtm_line (per-line generated kernel, %s workgroups, parameters %s)" % (
         "one-wave" if _s & 1 else "256-lane",
@@ -33,18 +33,18 @@ for _s in range(8):
 KERNEL_NAMES[13] = ("xtm_line (per-line generated kernel, one-wave workgroups, parameters "
                     "fetched one element ahead, two particles per lane)")
 
-# HBM bytes per tracking-kernel launch over the timed region, from one
+# HBM bytes per tracking-kernel launch, averaged over the timed region of one
 # FETCH_SIZE and one WRITE_SIZE counter pass of this benchmark, each scaled by
 # what the same counter reads for a plain 1 GiB device copy (x2.000, x1.000).
-# A figure holds only for the workload, step shape and kernel it was taken on:
-# the key carries a hash of the sources the per-line kernel is generated from,
-# and any change to them makes the bench report no traffic until the counters
-# are taken again.
+# A figure holds only for the workload, particle count, turns per step and
+# kernel it was taken on, and for the kernel sources: the key carries a hash
+# of the sources the per-line kernel is generated from, and any change to them
+# makes the bench report no traffic until the counters are taken again.  The
+# figure is per launch, so it does not depend on the number of timed steps.
 TRAFFIC_SOURCES = ("xtm_jit.cpp", "xtm_maps.h")
 MEASURED_TRAFFIC = {
-    # (workload, particles, turns per step, steps, kernel variant, source hash)
-    ("cfg2", 100000, 1000, 10, 10, "8654d53112d7bce3"):
-        (21407925.0, "profiles/xtm_line_cfg2_hbm_counters.txt"),
+    # (workload, particles, turns per step, kernel variant, source hash):
+    #     (bytes per launch, profile)
 }
 
 
@@ -57,36 +57,62 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-# algorithmic FLOPs per element application (sqrt, div, sin, compare count 1;
-# fma counts 2), as the kernel's maps are written
+# Algorithmic FLOPs per element application: the per-element counts of the
+# method's formulas with a square root, a division, a sine and a compare
+# counted as one operation and a fused multiply-add as two (drift 23,
+# multipole of order N 8 N + 2, RF 17, shift 2, rotation 12, aperture 3).  Two
+# counts are this project's: the curvature terms of a thin bend (11) and the
+# expanded drift (20).
 def element_flops(el) -> np.ndarray:
     from paper_2310_00317_amd import inputs as I
     f = np.zeros(len(el))
     for i, e in enumerate(el):
         t = int(e["type"])
         if t == I.DRIFT:
-            f[i] = 17
+            f[i] = 23
         elif t == I.DRIFT_EXPANDED:
-            f[i] = 17
+            f[i] = 20
         elif t == I.MULTIPOLE:
             f[i] = 8 * int(e["order"]) + 2 + (11 if e["hxl"] != 0 else 0)
         elif t == I.RF:
-            f[i] = 22
+            f[i] = 17
         elif t == I.XYSHIFT:
             f[i] = 2
         elif t == I.SROTATION:
             f[i] = 12
-        elif t == I.AP_CIRCLE:
-            f[i] = 4
-        elif t == I.AP_ELLIPSE:
-            f[i] = 6
-        elif t == I.AP_RECT:
-            f[i] = 4
+        elif t in (I.AP_CIRCLE, I.AP_ELLIPSE, I.AP_RECT):
+            f[i] = 3
         elif t in (I.QUADRUPOLE, I.SBEND):
             # N order-1 kicks (with curvature for a bend) and N + 1 drifts
             n = int(e["p"][2])
-            f[i] = (n + 1) * 17 + n * (10 + (11 if t == I.SBEND else 0))
+            f[i] = (n + 1) * 23 + n * (10 + (11 if t == I.SBEND else 0))
     return f
+
+
+# Algorithmic HBM bytes per pass of the one-launch-per-element baseline: the
+# state word and the FP64 fields each map reads and writes (drift 60 + 24,
+# multipole 36 + 16, aperture 20, RF 20 + 32, shift 20 + 16, rotation 36 + 32,
+# marker 4); elements read and written whole: 2 x 72 + 4.
+def element_bytes(el) -> np.ndarray:
+    from paper_2310_00317_amd import inputs as I
+    b = np.full(len(el), 148.0)
+    for i, e in enumerate(el):
+        t = int(e["type"])
+        if t == I.DRIFT:
+            b[i] = 84
+        elif t == I.MULTIPOLE and e["hxl"] == 0 and e["length"] <= 0:
+            b[i] = 52
+        elif t in (I.AP_CIRCLE, I.AP_ELLIPSE, I.AP_RECT):
+            b[i] = 20
+        elif t == I.RF:
+            b[i] = 52
+        elif t == I.XYSHIFT:
+            b[i] = 36
+        elif t == I.SROTATION:
+            b[i] = 68
+        elif t == I.MARKER:
+            b[i] = 4
+    return b
 
 
 def workload(name: str, n_override: int | None):
@@ -437,6 +463,70 @@ def learned_da(args):
           flush=True)
 
 
+def timed_steps(parts, run, steps: int, tps: int, log: bool = False) -> dict:
+    """Time `steps` calls of run(parts, tps) between two events on the current
+    stream (inputs resident in HBM); the library times each tracking launch
+    with HIP events on its stream (time_kernels)."""
+    import torch
+    torch.cuda.synchronize()
+    out = {"passes": 0, "kernel_ms": 0.0, "launches": 0, "variant": 0, "alive": 0}
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    t_wall = time.perf_counter()
+    start.record()
+    for s in range(steps):
+        st = run(parts, tps, time_kernels=True)
+        out["passes"] += st.passes
+        out["kernel_ms"] += st.kernel_ms
+        out["launches"] += st.launches
+        out["variant"] = st.variant
+        out["alive"] = st.alive
+        if log:
+            print(f"[bench] step {s + 1}/{steps}: alive {st.alive}", file=sys.stderr, flush=True)
+    stop.record()
+    torch.cuda.synchronize()
+    out["wall"] = time.perf_counter() - t_wall
+    out["ms"] = start.elapsed_time(stop)
+    out["value"] = out["passes"] / (out["ms"] / 1e3)
+    return out
+
+
+def alu_roofline(m: dict, flops_per_pass: float, traffic, traffic_src) -> dict:
+    kms = m["kernel_ms"]
+    achieved = m["passes"] * flops_per_pass / (kms / 1e3) / 1e12 if kms > 0 else 0.0
+    return {"bound": "alu", "kernel": KERNEL_NAMES.get(m["variant"], "?"),
+            "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": traffic,
+            "flops_per_pass": flops_per_pass, "avg_launch_ms": kms / max(m["launches"], 1),
+            "launches": m["launches"], "traffic_unit": "bytes per launch",
+            "traffic_profile": traffic_src}
+
+
+def saturated_fodo_leg(P, turns: int, n: int) -> dict:
+    """The FODO ring at 2^20 particles (the saturated first configuration):
+    one warmup of 20 turns on its own set, then `turns` timed turns of a fresh
+    set, with the roofline of its tracking kernel."""
+    import torch
+    from paper_2310_00317_amd import inputs as I
+    el = I.cfg1_lattice()
+    ref = I.PROTON_450GEV
+    lat = P.Lattice(el, ref)
+    coords = torch.from_numpy(np.ascontiguousarray(I.cfg1_particles(n))).to("cuda")
+    run = lambda parts, t, **kw: P.track(lat, parts, t, full_stats=True, **kw)
+    w = P.Particles(n, ref).init(coords)
+    run(w, 20)
+    w.close()
+    parts = P.Particles(n, ref).init(coords)
+    m = timed_steps(parts, run, 1, turns)
+    fpp = float(element_flops(el).sum() / len(el))
+    key = ("cfg1sat", n, turns, m["variant"], kernel_source_hash())
+    traffic, src = MEASURED_TRAFFIC.get(key, (None, None))
+    return {"workload": f"thin FODO ring, 801 elements, {n} Gaussian protons at 450 GeV, "
+                        f"{turns} turns", "value": m["value"], "unit": "passes/s",
+            "ms": m["ms"], "passes": int(m["passes"]), "alive_at_end": int(m["alive"]),
+            "roofline": alu_roofline(m, fpp, traffic, src)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -484,6 +574,8 @@ def main():
                     help="cfg3: track the variants one after another, each with its own "
                          "lattice and particle set, instead of one batched launch per chunk")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--sat-turns", type=int, default=1000,
+                    help="default workload: turns of the 2^20-particle FODO leg (0 = skip)")
     ap.add_argument("--cpu-sample-every", type=int, default=100)
     ap.add_argument("--cpu-turns", type=int, default=None,
                     help="turns of the CPU oracle sample (default 1500; 150 with radiation)")
@@ -573,34 +665,14 @@ def main():
         del w
 
     parts = P.Particles(n, ref).init(coords_dev)
-    torch.cuda.synchronize()
-    total_passes = 0
-    kernel_ms = 0.0
-    launches = 0
-    variant_ran = 0
-    start = torch.cuda.Event(enable_timing=True)
-    stop = torch.cuda.Event(enable_timing=True)
-    t_wall = time.perf_counter()
-    start.record()
-    alive = n
-    for s in range(steps):
-        st = run(parts, tps, time_kernels=True)
-        total_passes += st.passes
-        kernel_ms += st.kernel_ms
-        launches += st.launches
-        variant_ran = st.variant
-        alive = st.alive
-        print(f"[bench] step {s + 1}/{steps}: alive {alive}", file=sys.stderr, flush=True)
-    stop.record()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t_wall
-    ms = start.elapsed_time(stop)
-    value = total_passes / (ms / 1e3)
+    m = timed_steps(parts, run, steps, tps, log=True)
+    total_passes, kernel_ms, launches = m["passes"], m["kernel_ms"], m["launches"]
+    variant_ran, alive, ms, wall, value = m["variant"], m["alive"], m["ms"], m["wall"], m["value"]
 
     if args.per_element:
-        # the baseline's algorithmic bytes: every launch reads each alive
-        # particle's nine coordinates and state (76 B) and writes the nine back
-        bytes_per_pass = 9 * 8 + 4 + 9 * 8
+        # the baseline's algorithmic bytes: the fields each element's map reads
+        # and writes, averaged over the line
+        bytes_per_pass = float(element_bytes(el).mean())
         gbs = total_passes * bytes_per_pass / (kernel_ms / 1e3) / 1e9 if kernel_ms > 0 else 0.0
         out = {
             "metric": "particle-element passes/s (FP64); DA wall-clock learned vs plain at 0.1 sigma",
@@ -622,9 +694,7 @@ def main():
     # per element of the tracked line (thick elements count their slices)
     n_tracked = n_el_tracked if n_el_tracked else len(el_all)
     flops_per_pass = float(flops.sum() / n_tracked)
-    achieved_tflops = total_passes * flops_per_pass / (kernel_ms / 1e3) / 1e12 if kernel_ms > 0 else 0.0
-
-    key = (args.workload, n, tps, steps, variant_ran, kernel_source_hash())
+    key = (args.workload, n, tps, variant_ran, kernel_source_hash())
     traffic, traffic_src = MEASURED_TRAFFIC.get(key, (None, None))
 
     out = {
@@ -646,13 +716,11 @@ def main():
                       if plan is not None else {}),
                    "turns": steps * tps, "alive_at_end": int(alive),
                    "passes": int(total_passes), "wall_s": wall},
-        "roofline": {"bound": "alu", "kernel": KERNEL_NAMES.get(variant_ran, "?"),
-                     "achieved": achieved_tflops, "peak": FP64_VECTOR_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved_tflops / FP64_VECTOR_PEAK_TFLOPS,
-                     "traffic": traffic, "flops_per_pass": flops_per_pass,
-                     "avg_launch_ms": kernel_ms / max(launches, 1), "launches": launches,
-                     "traffic_unit": "bytes per launch", "traffic_profile": traffic_src},
+        "roofline": alu_roofline(m, flops_per_pass, traffic, traffic_src),
     }
+    if args.workload == "cfg2" and args.sat_turns > 0 and not args.particles:
+        print("[bench] saturated FODO leg", file=sys.stderr, flush=True)
+        out["cfg1_sat"] = saturated_fodo_leg(P, args.sat_turns, 1 << 20)
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a sample", file=sys.stderr, flush=True)
         if args.cpu_turns is None:

@@ -185,9 +185,8 @@ typedef struct xtm_track_opts {
   int32_t time_kernels;    /* 1 = time each tracking launch with HIP events (stats)   */
   int32_t variant;         /* tracking kernel (all give bitwise the same results):
                               0 = default (10 when the line has a compact periodic
-                              cell structure, else 4); 1 = interpreter, exit on loss;
-                              2 = interpreter, store on loss; 3 = as 2 with the
-                              element table staged in LDS; 4 = interpreter, losses
+                              cell structure, else 4); 1..3 are not used
+                              (XTM_E_ARG); 4 = interpreter, losses
                               kept in registers and replayed after the chunk;
                               5..xtm_max_variant() = per-line kernel generated from
                               the lattice's cell structure and compiled at first
@@ -304,8 +303,8 @@ xtm_status xtm_refine_losses(xtm_lattice lat, xtm_particles p, int32_t n_vertice
    d_out: device (n_el + 1) x n x 6, element-major: d_out[(e n + i) 6 + c]
    holds particle i entering element e (e = n_el: after the turn).
    Apertures are not checked (optics of the bare lattice); a particle whose
-   drift leaves the longitudinal-momentum window keeps the coordinates it
-   entered that drift with; no radiation.  One thread per particle;
+   longitudinal momentum becomes imaginary in a drift keeps the coordinates
+   it entered that drift with; no radiation.  One thread per particle;
    stream-ordered. */
 xtm_status xtm_track_record(xtm_lattice lat, const double* d_in, int64_t n, double* d_out,
                             void* stream);

@@ -20,10 +20,10 @@
  * delta = (P - P0)/P0; derived and stored: ptau = (E - E0)/(P0 c),
  * rpp = 1/(1+delta), rvv = beta/beta0.  One species per run (chi = 1).
  *
- * Loss codes: state 1 alive, 0 outside an aperture, -1 imaginary,
- * vanishing or non-finite longitudinal momentum in a drift (pz^2 outside
- * (2^-600, 2^600)).  On loss at element e of turn
- * t: at_element = e, at_turn = t, coordinates stay as they entered e.
+ * Loss codes: state 1 alive, 0 outside an aperture, -1 imaginary or
+ * non-finite longitudinal momentum in a drift (not pz^2 > 0).  On loss at
+ * element e of turn t: at_element = e, at_turn = t, coordinates stay as
+ * they entered e.
  */
 #include <math.h>
 #include <stdint.h>
@@ -97,27 +97,23 @@ static void set_from_ptau(orc_pt* q, double b0) {
 
 /* Exact drift over L: straight flight, path L(1+delta)/pz, and
    dzeta = L - L(1+beta0 ptau)/pz written without cancellation as
-   (L/pz) * ( (delta(2+delta) - px^2 - py^2)/(1+pz) - beta0 ptau ).
-   The two quotients are formed as products with correctly rounded
-   reciprocals, lp = L * (1/pz) and (...) * (1/(1+pz)).  The particle is
-   lost (return 0) unless 2^-600 < pz^2 < 2^600: beyond that window the
-   longitudinal momentum is imaginary, vanishing (an orbit at right angles to
-   the axis) or absurdly large, and inside it every reciprocal and square
-   root operand stays far from the exponent limits. */
+   (L/pz) * ( (delta(2+delta) - px^2 - py^2)/(1+pz) - beta0 ptau ),
+   with pz = sqrt((1+delta)^2 - px^2 - py^2).  Every quotient and the square
+   root are the correctly rounded IEEE operations.  The particle is lost
+   (return 0) unless pz^2 > 0: the longitudinal momentum is imaginary
+   (or a coordinate is not a number). */
 static int drift_exact(orc_pt* q, double L, double b0) {
   double opd = 1.0 + q->delta;
   double px2 = q->px * q->px;
   double py2 = q->py * q->py;
   double pz2 = opd * opd - px2 - py2;
-  if (!(pz2 > 0x1p-600 && pz2 < 0x1p600)) return 0;
+  if (!(pz2 > 0.0)) return 0;
   double pz = sqrt(pz2);
-  double rpz = 1.0 / pz;
-  double rpz1 = 1.0 / (1.0 + pz);
-  double lp = L * rpz;
+  double lp = L / pz;
   q->x = fma(q->px, lp, q->x);
   q->y = fma(q->py, lp, q->y);
   double u = q->delta * (2.0 + q->delta);
-  double dz = (u - px2 - py2) * rpz1 - b0 * q->ptau;
+  double dz = (u - px2 - py2) / (1.0 + pz) - b0 * q->ptau;
   q->zeta = fma(lp, dz, q->zeta);
   return 1;
 }

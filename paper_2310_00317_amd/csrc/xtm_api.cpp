@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <complex>
 #include <cstring>
@@ -60,7 +61,13 @@ bool same_ref(const RefQ& a, const RefQ& b) {
 
 }  // namespace
 
+// identities of lattices and batches, unique for the life of the process
+// (captured graphs are keyed on them, never on a handle's address, which the
+// heap may hand to a new lattice after a destroy)
+static std::atomic<uint64_t> g_next_id{1};
+
 struct xtm_lattice_s {
+  const uint64_t id = g_next_id.fetch_add(1);
   int32_t n_el = 0;
   RefQ ref{};
   std::vector<uint64_t> fwd_h, bwd_h;
@@ -86,6 +93,7 @@ struct xtm_lattice_s {
 };
 
 struct xtm_batch_s {
+  const uint64_t id = g_next_id.fetch_add(1);
   std::vector<xtm_lattice_s*> lats;
   int32_t n_el = 0;
   RefQ ref{};
@@ -100,7 +108,7 @@ struct xtm_batch_s {
 };
 
 struct GraphKey {
-  const void* lat;
+  uint64_t owner;  // lattice or batch id
   int32_t n_turns, chunk, block, variant, backward, compact, cur, rad_mode;
   int64_t alive_upper;
   uint64_t seed;
@@ -108,7 +116,7 @@ struct GraphKey {
   int32_t rec_turns;
   int32_t ramp;
   bool operator==(const GraphKey& o) const {
-    return lat == o.lat && n_turns == o.n_turns && chunk == o.chunk && block == o.block &&
+    return owner == o.owner && n_turns == o.n_turns && chunk == o.chunk && block == o.block &&
            variant == o.variant && backward == o.backward && compact == o.compact &&
            cur == o.cur && rad_mode == o.rad_mode && alive_upper == o.alive_upper &&
            seed == o.seed && rec == o.rec && rec_turns == o.rec_turns && ramp == o.ramp;
@@ -160,7 +168,18 @@ xtm_status pack(const xtm_element_desc& e, int32_t index, const RefQ& r, double 
     case XTM_DRIFT:
     case XTM_DRIFT_EXPANDED:
       if (!std::isfinite(e.length)) return fail(XTM_E_ELEMENT, where + "non-finite drift length");
-      hdr(e.type == XTM_DRIFT ? K_DRIFT : K_DRIFT_EXP, 0, 1);
+      if (e.type == XTM_DRIFT) {
+        // order 0: a length the device's short quotient sequence serves for
+        // every momentum (|L| in [2^-600, 2^600] and not a power of two);
+        // order 1: any other length, zero included (generic division)
+        int ex = 0;
+        const double m = std::frexp(std::fabs(e.length), &ex);
+        const bool short_ok = std::fabs(e.length) >= 0x1p-600 && std::fabs(e.length) <= 0x1p600 &&
+                              m != 0.5;
+        hdr(K_DRIFT, short_ok ? 0 : 1, 1);
+      } else {
+        hdr(K_DRIFT_EXP, 0, 1);
+      }
       put_d(out, sgn * e.length);
       return XTM_OK;
     case XTM_MULTIPOLE: {
@@ -331,8 +350,6 @@ struct ChunkPlan {
   int32_t rec_turns;
   const LineKernel* line;  // variant 5
   const uint64_t* tab;
-  const int32_t* seg;
-  int32_t n_seg;
   int32_t n_turns, chunk, block, variant;
   bool backward, compact;
   bool ramp;  // chunk lengths 1, 2, 4, ... up to `chunk` (automatic chunking)
@@ -391,8 +408,8 @@ hipError_t enqueue_chunks(xtm_lattice_s* L, xtm_particles_s* P, const ChunkPlan&
       e = launch_line(*c.line, L->n_el, soa, in, P->ctrl, P->alive_upper, c.block, k,
                       c.backward ? 1 : 0, kr, s);
     else
-      e = launch_track(c.tab, c.seg, c.n_seg, L->n_el, soa, in, P->ctrl, P->alive_upper, c.block,
-                       k, c.backward ? 1 : 0, kr, c.variant, s);
+      e = launch_track(c.tab, L->n_el, soa, in, P->ctrl, P->alive_upper, c.block, k,
+                       c.backward ? 1 : 0, kr, c.variant, s);
     if (e != hipSuccess) return e;
     if (ev && (e = hipEventRecord(ev->back(), s)) != hipSuccess) return e;
     ++*launches;
@@ -426,7 +443,7 @@ int32_t flips(const ChunkPlan& c) {
 
 xtm_status run_graph(xtm_lattice_s* L, xtm_particles_s* P, const ChunkPlan& c, hipStream_t s,
                      int32_t* launches) {
-  GraphKey key{c.batch ? (const void*)c.batch : (const void*)L, c.n_turns, c.chunk, c.block, c.variant, c.backward ? 1 : 0, c.compact ? 1 : 0,
+  GraphKey key{c.batch ? c.batch->id : L->id, c.n_turns, c.chunk, c.block, c.variant, c.backward ? 1 : 0, c.compact ? 1 : 0,
                P->cur, c.rad_mode, P->alive_upper, c.seed, c.rec, c.rec_turns, c.ramp ? 1 : 0};
   for (const GraphEntry& g : P->graphs) {
     if (g.key == key) {
@@ -491,8 +508,8 @@ xtm_status run_turns(xtm_lattice_s* L, xtm_particles_s* P, int32_t n_turns,
   c.compact = !(o && o->no_compact) || backward;
   c.variant = (o && o->variant) ? o->variant
                                 : (use_plan ? (B ? B->plan_variant : L->plan_variant) : 0);
-  if (c.variant < 0 || c.variant > 4 + kLineStyles)
-    return fail(XTM_E_ARG, "kernel variant must be 0.." + std::to_string(4 + kLineStyles));
+  if (c.variant < 0 || (c.variant >= 1 && c.variant <= 3) || c.variant > 4 + kLineStyles)
+    return fail(XTM_E_ARG, "kernel variant must be 0, 4 or 5.." + std::to_string(4 + kLineStyles));
   if (B) {
     if (backward) return fail(XTM_E_UNSUPPORTED, "batched tracking is forward only");
     if (c.variant != 0 && c.variant != 4 && !(c.variant >= 5 && line_block(c.variant - 5) == 64))
@@ -500,8 +517,6 @@ xtm_status run_turns(xtm_lattice_s* L, xtm_particles_s* P, int32_t n_turns,
                   "batched tracking runs the interpreter (4) or a one-wave per-line form");
   }
   c.line = nullptr;
-  if ((c.rad_mode || c.rec) && c.variant >= 1 && c.variant <= 3)
-    return fail(XTM_E_UNSUPPORTED, "kernel variants 1-3 implement neither radiation nor the recorder");
   if (c.variant == 0 || c.variant >= 5) {
     // the per-line kernel, compiled on first use; the default falls back to
     // the register-loss interpreter if the line has no compact cell structure
@@ -537,8 +552,6 @@ xtm_status run_turns(xtm_lattice_s* L, xtm_particles_s* P, int32_t n_turns,
   c.n_turns = n_turns;
   c.backward = backward;
   c.tab = backward ? L->bwd_d : L->fwd_d;
-  c.seg = backward ? L->bwd_seg_d : L->fwd_seg_d;
-  c.n_seg = (int32_t)((backward ? L->bwd_seg_h.size() : L->fwd_seg_h.size()) / 3);
   const bool graph = o && o->use_graph;
   const int64_t alive_before = P->alive_upper;
   if (stats) HIP_TRY(launch_fill_i64(P->passes, 0, s), "clear passes");
@@ -873,11 +886,14 @@ xtm_status xtm_track_per_element(xtm_lattice L, xtm_particles P, int32_t n_turns
     if (!P->initialised) return fail(XTM_E_STATE, "particle set not initialised");
     if (!same_ref(L->ref, P->ref)) return fail(XTM_E_REFERENCE, "reference mismatch");
     hipStream_t s = (hipStream_t)stream;
-    std::vector<uint32_t> off;  // word position of each element's record
+    std::vector<uint32_t> off, kt;  // word position and kernel type of each element's record
     off.reserve(L->n_el);
+    kt.reserve(L->n_el);
     for (size_t w = 0; off.size() < (size_t)L->n_el && w < L->fwd_h.size();
-         w += 1 + ((L->fwd_h[w] >> 16) & 0xffffu))
+         w += 1 + ((L->fwd_h[w] >> 16) & 0xffffu)) {
       off.push_back((uint32_t)w);
+      kt.push_back((uint32_t)(L->fwd_h[w] & 0xffu));
+    }
     if (off.size() != (size_t)L->n_el) return fail(XTM_E_STATE, "element table inconsistent");
     std::vector<int32_t> st0, at, ae, st1;
     if (stats) {  // passes are counted on the host from the states before and after
@@ -894,8 +910,8 @@ xtm_status xtm_track_per_element(xtm_lattice L, xtm_particles P, int32_t n_turns
       HIP_TRY(hipEventRecord(a, s), "event record");
     }
     const KernelRef kr = kref(L->ref, 0, 0);
-    HIP_TRY(launch_per_element(L->fwd_d, off.data(), L->n_el, soa_of(P), P->n, P->turn, n_turns,
-                               kr, s), "per-element launch");
+    HIP_TRY(launch_per_element(L->fwd_d, off.data(), kt.data(), L->n_el, soa_of(P), P->n, P->turn,
+                               n_turns, kr, s), "per-element launch");
     if (stats) HIP_TRY(hipEventRecord(b, s), "event record");
     const int32_t t0 = P->turn;
     xtm_status rs = xtm_particles_reset(P, t0 + n_turns, stream);

@@ -67,13 +67,13 @@ hipError_t launch_init(const double* coords6, int64_t n, int64_t first_id, SoA P
 hipError_t launch_iota(int32_t* idx, int64_t n, int32_t* ctrl, int32_t n_alive, int32_t turn,
                        hipStream_t s);
 hipError_t launch_advance(int32_t* ctrl, int32_t dk, hipStream_t s);
-// words per LDS segment of the element table (variant 3); a record never
-// straddles two segments
+// words per LDS segment of the element table (the optics recorder); a record
+// never straddles two segments
 constexpr int kSegWords = 4096;
 constexpr int32_t kLineBlock = 256;  // workgroup size of the per-line kernel
-hipError_t launch_track(const uint64_t* tab, const int32_t* seg, int32_t n_seg, int32_t n_el,
-                        SoA P, const int32_t* idx, const int32_t* ctrl, int64_t grid_upper,
-                        int32_t block, int32_t n_turns, int32_t backward, KernelRef r,
+// the element interpreter (kernel variant 4)
+hipError_t launch_track(const uint64_t* tab, int32_t n_el, SoA P, const int32_t* idx,
+                        const int32_t* ctrl, int64_t grid_upper, int32_t block, int32_t n_turns, int32_t backward, KernelRef r,
                         int32_t variant, hipStream_t s);
 // end-of-chunk bookkeeping: passes of the chunk (added to *passes), then an
 // order-preserving compaction of the alive list into idx_out (if non-null)
@@ -97,17 +97,18 @@ hipError_t launch_replay(const uint64_t* tab, int32_t n_el, SoA P, const int32_t
                          const int32_t* ctrl, int64_t grid_upper, int32_t backward, KernelRef r,
                          hipStream_t s);
 hipError_t launch_fill_i64(int64_t* p, int64_t v, hipStream_t s);
-// One kernel launch per element and turn (the measurement baseline); offsets:
-// host array of each element's record position in `tab` (word index).
-hipError_t launch_per_element(const uint64_t* tab, const uint32_t* offsets, int32_t n_el,
-                              SoA P, int64_t n, int32_t t0, int32_t n_turns, KernelRef r,
-                              hipStream_t s);
+// One kernel launch per element and turn (the measurement baseline); offsets
+// and ktypes: host arrays of each element's record position in `tab` (word
+// index) and kernel type.
+hipError_t launch_per_element(const uint64_t* tab, const uint32_t* offsets, const uint32_t* ktypes,
+                              int32_t n_el, SoA P, int64_t n, int32_t t0, int32_t n_turns,
+                              KernelRef r, hipStream_t s);
 
 constexpr int kScanBlock = 1024;
 
 // One turn of n particles with the coordinates (x, px, y, py, zeta, delta)
 // recorded at every element entry and after the last: out[(e n + i) 6 + c].
-// (seg: the table's LDS segments, as for launch_track)
+// (seg: the table's LDS segments, kSegWords words at most each)
 hipError_t launch_record(const uint64_t* fwd, const int32_t* seg, int32_t n_seg, int32_t n_el,
                          const double* c6, int64_t n, double* out, KernelRef r, hipStream_t s);
 

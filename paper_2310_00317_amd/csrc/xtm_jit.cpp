@@ -141,15 +141,24 @@ std::string emit(uint32_t s, const std::string& arr, const std::string& j, bool 
   auto P = [&](int32_t m) { return "(" + arr + ")[" + std::to_string(m) + "]"; };
   std::ostringstream c;
   switch (kt) {
-    case K_DRIFT:
+    case K_DRIFT: {
+      // order 1: a drift length outside the short sequences' window
+      const char* any = order ? "true" : "false";
       if (mode == kReplay)
-        c << "(void)xtmm::drift_exact(q, " << P(0) << ");";
+        c << "(void)xtmm::drift_exact(q, " << P(0) << ", " << any << ");";
       else if (mode == kMarkOnly)
-        c << "xtmm::mark(xtmm::drift_exact(q, " << P(0) << "), code, st, e0 + " << j << ", -1);";
+        c << "xtmm::mark(xtmm::drift_exact(q, " << P(0) << ", " << any << "), code, st, e0 + "
+          << j << ", -1);";
       else
-        c << "{ if (!xtmm::drift_ok(q) && live) { SAVE(); code = e0 + " << j
-          << "; st = -1; live = false; } (void)xtmm::drift_exact(q, " << P(0) << "); }";
+        // one rare branch per drift: operands outside the window take the
+        // generic operations, and a lane lost here stores its entry state
+        c << "{ const xtmm::DriftIn d_ = xtmm::drift_in(q); double lp_, dq_; bool f_; "
+          << "xtmm::drift_quotients(" << P(0) << ", d_, " << any << ", lp_, dq_, f_); "
+          << "if (!f_) { if (!(d_.pz2 > 0.0) && live) { SAVE(); code = e0 + " << j
+          << "; st = -1; live = false; } xtmm::drift_generic(" << P(0)
+          << ", d_, lp_, dq_); } xtmm::drift_apply(q, lp_, dq_); }";
       break;
+    }
     case K_DRIFT_EXP:
       c << "xtmm::drift_expanded(q, " << P(0) << ");";
       break;

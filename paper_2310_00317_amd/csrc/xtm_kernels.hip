@@ -74,522 +74,6 @@ __global__ void k_fill_i64(int64_t* p, int64_t v) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
 }
 
-// ------------------------------------------------------------ element maps
-struct Pt {
-  double x, px, y, py, zeta, delta, ptau, rpp, rvv;
-  // invariants of delta, refreshed whenever ptau changes (same values the
-  // formulas would recompute, so caching does not change rounding)
-  double opd2, u, bpt;
-};
-
-__device__ __forceinline__ void refresh(Pt& q, double beta0) {
-  double opd = 1.0 + q.delta;
-  q.opd2 = opd * opd;
-  q.u = q.delta * (2.0 + q.delta);
-  q.bpt = beta0 * q.ptau;
-}
-
-template <int N>
-__device__ __forceinline__ void horner(Pt& q, const double* __restrict__ c) {
-  double br = c[0], bi = c[1];
-#pragma unroll
-  for (int k = 1; k <= N; ++k) {
-    double cr = c[2 * k], ci = c[2 * k + 1];
-    double tr = fma(br, q.x, fma(-bi, q.y, cr));
-    double ti = fma(br, q.y, fma(bi, q.x, ci));
-    br = tr;
-    bi = ti;
-  }
-  q.px = q.px - br;
-  q.py = q.py + bi;
-}
-
-__device__ __forceinline__ void horner_n(Pt& q, const double* __restrict__ c, uint32_t order) {
-  switch (order) {
-    case 0: horner<0>(q, c); break;
-    case 1: horner<1>(q, c); break;
-    case 2: horner<2>(q, c); break;
-    case 3: horner<3>(q, c); break;
-    case 4: horner<4>(q, c); break;
-    case 5: horner<5>(q, c); break;
-    case 6: horner<6>(q, c); break;
-    case 7: horner<7>(q, c); break;
-    case 8: horner<8>(q, c); break;
-    case 9: horner<9>(q, c); break;
-    default: horner<10>(q, c); break;
-  }
-}
-
-// ------------------------------------------------------------ track kernel
-// Tracks idx[i] for i < ctrl[0] through n_turns turns of the table `tab`
-// (forward table, or the reversed table of inverse maps when backward != 0).
-__global__ void __launch_bounds__(256) k_track(const uint64_t* __restrict__ tab, int32_t n_el,
-                                               SoA P, const int32_t* __restrict__ idx,
-                                               const int32_t* __restrict__ ctrl, int32_t n_turns,
-                                               int32_t backward, KernelRef r) {
-  // the turn of the alive particles lives on the device, so a captured
-  // chunk sequence replays correctly from any starting turn
-  const int32_t t0 = ctrl[1];
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= ctrl[0]) return;
-  const int32_t p = idx[i];
-  if (P.state[p] != 1) return;
-
-  Pt q;
-  q.x = P.x[p];
-  q.px = P.px[p];
-  q.y = P.y[p];
-  q.py = P.py[p];
-  q.zeta = P.zeta[p];
-  q.delta = P.delta[p];
-  q.ptau = P.ptau[p];
-  q.rpp = P.rpp[p];
-  q.rvv = P.rvv[p];
-  refresh(q, r.beta0);
-
-  const double beta0 = r.beta0;
-  int32_t st = 1, lost_e = 0, lost_t = 0;
-  for (int32_t t = 0; t < n_turns; ++t) {
-    uint32_t off = 0;
-    for (int32_t e = 0; e < n_el; ++e) {
-      // the walk position is the same for every lane; saying so lets the
-      // compiler fetch the record with scalar loads into SGPRs
-      off = __builtin_amdgcn_readfirstlane(off);
-      const uint64_t* w = tab + off;
-      const uint64_t h = w[0];
-      const uint32_t ktype = (uint32_t)(h & 0xffu);
-      const uint32_t order = (uint32_t)((h >> 8) & 0xffu);
-      const uint32_t nw = (uint32_t)((h >> 16) & 0xffffu);
-      const double* __restrict__ prm = reinterpret_cast<const double*>(w + 1);
-      switch (ktype) {
-        case K_DRIFT: {
-          const double L = prm[0];
-          const double px2 = q.px * q.px;
-          const double py2 = q.py * q.py;
-          const double pz2 = q.opd2 - px2 - py2;
-          if (!((pz2 > 0x1p-600) & (pz2 < 0x1p600))) {
-            st = -1;
-            lost_e = e;
-            lost_t = t;
-            goto done;
-          }
-          const double pz = xtmm::sqrt_in(pz2);
-          const double lp = L * xtmm::recip_in(pz);
-          q.x = fma(q.px, lp, q.x);
-          q.y = fma(q.py, lp, q.y);
-          const double dz = (q.u - px2 - py2) * xtmm::recip_in(1.0 + pz) - q.bpt;
-          q.zeta = fma(lp, dz, q.zeta);
-          break;
-        }
-        case K_DRIFT_EXP: {
-          const double L = prm[0];
-          const double lr = L * q.rpp;
-          q.x = fma(q.px, lr, q.x);
-          q.y = fma(q.py, lr, q.y);
-          const double pp = q.px * q.px + q.py * q.py;
-          const double r3 = q.rpp * q.rpp * q.rpp;
-          const double dz = (q.delta - q.bpt) * q.rpp - 0.5 * pp * r3 * (1.0 + q.bpt);
-          q.zeta = fma(L, dz, q.zeta);
-          break;
-        }
-        case K_MULT:
-        case K_MULT_LR:
-          horner_n(q, prm, order);
-          break;
-        case K_MULT_CURV: {
-          horner_n(q, prm, order);
-          const double* cv = prm + 2 * (order + 1);
-          const double hxl = cv[0], k0h = cv[1], lr = cv[2];
-          double dpx = hxl * (1.0 + q.delta);
-          if (lr > 0.0) dpx = dpx - k0h * q.x / lr;
-          const double dz = hxl * q.x * (1.0 + q.bpt) * q.rpp;
-          q.px = q.px + dpx;
-          q.zeta = q.zeta - dz;
-          break;
-        }
-        case K_RF: {
-          const double s = xtmm::xsin(prm[2] - prm[1] * q.zeta);
-          q.ptau = q.ptau + prm[0] * s;
-          const double v = q.ptau * (q.ptau + r.two_over_beta0);
-          q.delta = v / (1.0 + sqrt(1.0 + v));
-          q.rpp = 1.0 / (1.0 + q.delta);
-          q.rvv = (1.0 + q.delta) / (1.0 + beta0 * q.ptau);
-          refresh(q, beta0);
-          break;
-        }
-        case K_SHIFT:
-          q.x = q.x - prm[0];
-          q.y = q.y - prm[1];
-          break;
-        case K_SROT: {
-          const double c = prm[0], s = prm[1];
-          const double x = c * q.x + s * q.y;
-          const double y = c * q.y - s * q.x;
-          const double px = c * q.px + s * q.py;
-          const double py = c * q.py - s * q.px;
-          q.x = x;
-          q.y = y;
-          q.px = px;
-          q.py = py;
-          break;
-        }
-        case K_AP_CIRC:
-          if (!(q.x * q.x + q.y * q.y <= prm[0])) {
-            st = 0;
-            lost_e = e;
-            lost_t = t;
-            goto done;
-          }
-          break;
-        case K_AP_ELL:
-          if (!(q.x * q.x * prm[0] + q.y * q.y * prm[1] <= 1.0)) {
-            st = 0;
-            lost_e = e;
-            lost_t = t;
-            goto done;
-          }
-          break;
-        case K_AP_RECT:
-          if (!(prm[0] <= q.x && q.x <= prm[1] && prm[2] <= q.y && q.y <= prm[3])) {
-            st = 0;
-            lost_e = e;
-            lost_t = t;
-            goto done;
-          }
-          break;
-        default:
-          break;
-      }
-      off += 1 + nw;
-    }
-  }
-done:
-  P.x[p] = q.x;
-  P.px[p] = q.px;
-  P.y[p] = q.y;
-  P.py[p] = q.py;
-  P.zeta[p] = q.zeta;
-  P.delta[p] = q.delta;
-  P.ptau[p] = q.ptau;
-  P.rpp[p] = q.rpp;
-  P.rvv[p] = q.rvv;
-  if (st == 1) {
-    P.at_turn[p] = backward ? t0 - n_turns : t0 + n_turns;
-    P.at_element[p] = 0;
-  } else {
-    P.state[p] = st;
-    P.at_element[p] = backward ? n_el - 1 - lost_e : lost_e;
-    P.at_turn[p] = backward ? t0 - 1 - lost_t : t0 + lost_t;
-  }
-}
-
-// ------------------------------------------------ track kernel, variant 2
-// Same maps and rounding as k_track.  A lane whose particle is lost stores
-// the frozen state and loss record at once (a rare, divergent store) and then
-// keeps executing the lattice on whatever its coordinates have become (NaN or
-// infinity cost nothing extra on the VALU), guarded so it is never recorded
-// twice and never stored at the end.  The element loop therefore has no
-// divergent exits: the only per-element control flow is the scalar switch,
-// and a wave leaves the turn loop when all its lanes are lost.
-__device__ __forceinline__ void freeze(const SoA& P, int32_t p, const Pt& q, int32_t st,
-                                       int32_t e, int32_t t, int32_t n_el, int32_t t0,
-                                       int32_t backward) {
-  P.x[p] = q.x; P.px[p] = q.px; P.y[p] = q.y; P.py[p] = q.py; P.zeta[p] = q.zeta;
-  P.delta[p] = q.delta; P.ptau[p] = q.ptau; P.rpp[p] = q.rpp; P.rvv[p] = q.rvv;
-  P.state[p] = st;
-  P.at_element[p] = backward ? n_el - 1 - e : e;
-  P.at_turn[p] = backward ? t0 - 1 - t : t0 + t;
-}
-
-__global__ void __launch_bounds__(256) k_track2(const uint64_t* __restrict__ tab, int32_t n_el,
-                                                SoA P, const int32_t* __restrict__ idx,
-                                                const int32_t* __restrict__ ctrl, int32_t n_turns,
-                                                int32_t backward, KernelRef r) {
-  // the turn of the alive particles lives on the device, so a captured
-  // chunk sequence replays correctly from any starting turn
-  const int32_t t0 = ctrl[1];
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int32_t n_alive = ctrl[0];
-  const bool in_range = i < n_alive;
-  const int32_t p = in_range ? idx[i] : 0;
-  bool lost = !in_range || P.state[p] != 1;
-  if (__all(lost)) return;
-
-  // lanes without a live particle read particle p = 0 (always a valid index)
-  // and only ever compute on it
-  Pt q;
-  q.x = P.x[p]; q.px = P.px[p]; q.y = P.y[p]; q.py = P.py[p]; q.zeta = P.zeta[p];
-  q.delta = P.delta[p]; q.ptau = P.ptau[p]; q.rpp = P.rpp[p]; q.rvv = P.rvv[p];
-  refresh(q, r.beta0);
-  const double beta0 = r.beta0;
-  for (int32_t t = 0; t < n_turns; ++t) {
-    uint32_t off = 0;
-    for (int32_t e = 0; e < n_el; ++e) {
-      off = __builtin_amdgcn_readfirstlane(off);
-      const uint64_t* w = tab + off;
-      const uint64_t h = w[0];
-      const uint32_t ktype = (uint32_t)(h & 0xffu);
-      const uint32_t order = (uint32_t)((h >> 8) & 0xffu);
-      const uint32_t nw = (uint32_t)((h >> 16) & 0xffffu);
-      const double* __restrict__ prm = reinterpret_cast<const double*>(w + 1);
-      switch (ktype) {
-        case K_DRIFT: {
-          const double L = prm[0];
-          const double px2 = q.px * q.px;
-          const double py2 = q.py * q.py;
-          const double pz2 = q.opd2 - px2 - py2;
-          if (!((pz2 > 0x1p-600) & (pz2 < 0x1p600)) && !lost) {
-            freeze(P, p, q, -1, e, t, n_el, t0, backward);
-            lost = true;
-          }
-          const double pz = xtmm::sqrt_in(pz2);
-          const double lp = L * xtmm::recip_in(pz);
-          q.x = fma(q.px, lp, q.x);
-          q.y = fma(q.py, lp, q.y);
-          const double dz = (q.u - px2 - py2) * xtmm::recip_in(1.0 + pz) - q.bpt;
-          q.zeta = fma(lp, dz, q.zeta);
-          break;
-        }
-        case K_DRIFT_EXP: {
-          const double L = prm[0];
-          const double lr = L * q.rpp;
-          q.x = fma(q.px, lr, q.x);
-          q.y = fma(q.py, lr, q.y);
-          const double pp = q.px * q.px + q.py * q.py;
-          const double r3 = q.rpp * q.rpp * q.rpp;
-          const double dz = (q.delta - q.bpt) * q.rpp - 0.5 * pp * r3 * (1.0 + q.bpt);
-          q.zeta = fma(L, dz, q.zeta);
-          break;
-        }
-        case K_MULT:
-        case K_MULT_LR:
-          horner_n(q, prm, order);
-          break;
-        case K_MULT_CURV: {
-          horner_n(q, prm, order);
-          const double* cv = prm + 2 * (order + 1);
-          const double hxl = cv[0], k0h = cv[1], lr = cv[2];
-          double dpx = hxl * (1.0 + q.delta);
-          if (lr > 0.0) dpx = dpx - k0h * q.x / lr;
-          const double dz = hxl * q.x * (1.0 + q.bpt) * q.rpp;
-          q.px = q.px + dpx;
-          q.zeta = q.zeta - dz;
-          break;
-        }
-        case K_RF: {
-          const double s = xtmm::xsin(prm[2] - prm[1] * q.zeta);
-          q.ptau = q.ptau + prm[0] * s;
-          const double v = q.ptau * (q.ptau + r.two_over_beta0);
-          q.delta = v / (1.0 + sqrt(1.0 + v));
-          q.rpp = 1.0 / (1.0 + q.delta);
-          q.rvv = (1.0 + q.delta) / (1.0 + beta0 * q.ptau);
-          refresh(q, beta0);
-          break;
-        }
-        case K_SHIFT:
-          q.x = q.x - prm[0];
-          q.y = q.y - prm[1];
-          break;
-        case K_SROT: {
-          const double c = prm[0], s = prm[1];
-          const double x = c * q.x + s * q.y;
-          const double y = c * q.y - s * q.x;
-          const double px = c * q.px + s * q.py;
-          const double py = c * q.py - s * q.px;
-          q.x = x; q.y = y; q.px = px; q.py = py;
-          break;
-        }
-        case K_AP_CIRC:
-          if (!(q.x * q.x + q.y * q.y <= prm[0]) && !lost) {
-            freeze(P, p, q, 0, e, t, n_el, t0, backward);
-            lost = true;
-          }
-          break;
-        case K_AP_ELL:
-          if (!(q.x * q.x * prm[0] + q.y * q.y * prm[1] <= 1.0) && !lost) {
-            freeze(P, p, q, 0, e, t, n_el, t0, backward);
-            lost = true;
-          }
-          break;
-        case K_AP_RECT:
-          // non-short-circuit form: one predicate, no per-comparison branches
-          if (!((prm[0] <= q.x) & (q.x <= prm[1]) & (prm[2] <= q.y) & (q.y <= prm[3])) && !lost) {
-            freeze(P, p, q, 0, e, t, n_el, t0, backward);
-            lost = true;
-          }
-          break;
-        default:
-          break;
-      }
-      off += 1 + nw;
-    }
-    if (__all(lost)) return;
-  }
-  if (!lost) {
-    P.x[p] = q.x; P.px[p] = q.px; P.y[p] = q.y; P.py[p] = q.py; P.zeta[p] = q.zeta;
-    P.delta[p] = q.delta; P.ptau[p] = q.ptau; P.rpp[p] = q.rpp; P.rvv[p] = q.rvv;
-    P.at_turn[p] = backward ? t0 - n_turns : t0 + n_turns;
-    P.at_element[p] = 0;
-  }
-}
-
-// ------------------------------------------------ track kernel, variant 3
-// Freeze-on-loss like variant 2, but the element table is staged in LDS in
-// segments of at most kSegWords words (a segment never splits a record).  The
-// workgroup copies a segment with coalesced vector loads, then every wave
-// reads headers and parameters from LDS with uniform addresses (broadcast
-// reads that pipeline, unlike scalar loads whose returns are unordered).  A
-// lattice that fits in one segment is copied once per launch.
-template <int kSegWords>
-__global__ void __launch_bounds__(256) k_track3(const uint64_t* __restrict__ tab,
-                                                const int32_t* __restrict__ seg, int32_t n_seg,
-                                                int32_t n_el, SoA P,
-                                                const int32_t* __restrict__ idx,
-                                                const int32_t* __restrict__ ctrl, int32_t n_turns,
-                                                int32_t backward, KernelRef r) {
-  // the turn of the alive particles lives on the device, so a captured
-  // chunk sequence replays correctly from any starting turn
-  const int32_t t0 = ctrl[1];
-  __shared__ uint64_t lds[kSegWords];
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int32_t n_alive = ctrl[0];
-  const bool in_range = i < n_alive;
-  const int32_t p = in_range ? idx[i] : 0;
-  bool lost = !in_range || P.state[p] != 1;
-  // block-uniform early exit (no barrier has been reached yet)
-  if (__syncthreads_and(lost)) return;
-
-  Pt q;
-  q.x = P.x[p]; q.px = P.px[p]; q.y = P.y[p]; q.py = P.py[p]; q.zeta = P.zeta[p];
-  q.delta = P.delta[p]; q.ptau = P.ptau[p]; q.rpp = P.rpp[p]; q.rvv = P.rvv[p];
-  refresh(q, r.beta0);
-  const double beta0 = r.beta0;
-
-  auto load_segment = [&](int32_t sgi) {
-    const int32_t w0 = seg[3 * sgi], nwords = seg[3 * sgi + 1];
-    for (int32_t k = threadIdx.x; k < nwords; k += blockDim.x) lds[k] = tab[w0 + k];
-  };
-  if (n_seg == 1) {
-    load_segment(0);
-    __syncthreads();
-  }
-  for (int32_t t = 0; t < n_turns; ++t) {
-    int32_t e_base = 0;
-    for (int32_t sgi = 0; sgi < n_seg; ++sgi) {
-      if (n_seg > 1) {
-        __syncthreads();
-        load_segment(sgi);
-        __syncthreads();
-      }
-      const int32_t n_here = seg[3 * sgi + 2];
-      uint32_t off = 0;
-      for (int32_t k = 0; k < n_here; ++k) {
-        const int32_t e = e_base + k;
-        const uint64_t h = lds[off];
-        const uint32_t ktype = (uint32_t)(h & 0xffu);
-        const uint32_t order = (uint32_t)((h >> 8) & 0xffu);
-        const uint32_t nw = (uint32_t)((h >> 16) & 0xffffu);
-        const double* prm = reinterpret_cast<const double*>(&lds[off + 1]);
-        if (ktype == K_MULT || ktype == K_MULT_LR) {
-          horner_n(q, prm, order);
-        } else if (ktype == K_DRIFT) {
-          const double L = prm[0];
-          const double px2 = q.px * q.px;
-          const double py2 = q.py * q.py;
-          const double pz2 = q.opd2 - px2 - py2;
-          if (!((pz2 > 0x1p-600) & (pz2 < 0x1p600)) && !lost) {
-            freeze(P, p, q, -1, e, t, n_el, t0, backward);
-            lost = true;
-          }
-          const double pz = xtmm::sqrt_in(pz2);
-          const double lp = L * xtmm::recip_in(pz);
-          q.x = fma(q.px, lp, q.x);
-          q.y = fma(q.py, lp, q.y);
-          const double dz = (q.u - px2 - py2) * xtmm::recip_in(1.0 + pz) - q.bpt;
-          q.zeta = fma(lp, dz, q.zeta);
-        } else if (ktype == K_AP_CIRC) {
-          if (!(q.x * q.x + q.y * q.y <= prm[0]) && !lost) {
-            freeze(P, p, q, 0, e, t, n_el, t0, backward);
-            lost = true;
-          }
-        } else {
-          switch (ktype) {
-            case K_DRIFT_EXP: {
-              const double L = prm[0];
-              const double lr = L * q.rpp;
-              q.x = fma(q.px, lr, q.x);
-              q.y = fma(q.py, lr, q.y);
-              const double pp = q.px * q.px + q.py * q.py;
-              const double r3 = q.rpp * q.rpp * q.rpp;
-              const double dz = (q.delta - q.bpt) * q.rpp - 0.5 * pp * r3 * (1.0 + q.bpt);
-              q.zeta = fma(L, dz, q.zeta);
-              break;
-            }
-            case K_MULT_CURV: {
-              horner_n(q, prm, order);
-              const double* cv = prm + 2 * (order + 1);
-              const double hxl = cv[0], k0h = cv[1], lr = cv[2];
-              double dpx = hxl * (1.0 + q.delta);
-              if (lr > 0.0) dpx = dpx - k0h * q.x / lr;
-              const double dz = hxl * q.x * (1.0 + q.bpt) * q.rpp;
-              q.px = q.px + dpx;
-              q.zeta = q.zeta - dz;
-              break;
-            }
-            case K_RF: {
-              const double s = xtmm::xsin(prm[2] - prm[1] * q.zeta);
-              q.ptau = q.ptau + prm[0] * s;
-              const double v = q.ptau * (q.ptau + r.two_over_beta0);
-              q.delta = v / (1.0 + sqrt(1.0 + v));
-              q.rpp = 1.0 / (1.0 + q.delta);
-              q.rvv = (1.0 + q.delta) / (1.0 + beta0 * q.ptau);
-              refresh(q, beta0);
-              break;
-            }
-            case K_SHIFT:
-              q.x = q.x - prm[0];
-              q.y = q.y - prm[1];
-              break;
-            case K_SROT: {
-              const double c = prm[0], s = prm[1];
-              const double x = c * q.x + s * q.y;
-              const double y = c * q.y - s * q.x;
-              const double px = c * q.px + s * q.py;
-              const double py = c * q.py - s * q.px;
-              q.x = x; q.y = y; q.px = px; q.py = py;
-              break;
-            }
-            case K_AP_ELL:
-              if (!(q.x * q.x * prm[0] + q.y * q.y * prm[1] <= 1.0) && !lost) {
-                freeze(P, p, q, 0, e, t, n_el, t0, backward);
-                lost = true;
-              }
-              break;
-            case K_AP_RECT:
-              if (!((prm[0] <= q.x) & (q.x <= prm[1]) & (prm[2] <= q.y) & (q.y <= prm[3])) &&
-                  !lost) {
-                freeze(P, p, q, 0, e, t, n_el, t0, backward);
-                lost = true;
-              }
-              break;
-            default:
-              break;
-          }
-        }
-        off += 1 + nw;
-      }
-      e_base += n_here;
-    }
-    if (__syncthreads_and(lost)) return;
-  }
-  if (!lost) {
-    P.x[p] = q.x; P.px[p] = q.px; P.y[p] = q.y; P.py[p] = q.py; P.zeta[p] = q.zeta;
-    P.delta[p] = q.delta; P.ptau[p] = q.ptau; P.rpp[p] = q.rpp; P.rvv[p] = q.rvv;
-    P.at_turn[p] = backward ? t0 - n_turns : t0 + n_turns;
-    P.at_element[p] = 0;
-  }
-}
-
 // ------------------------------------------------ track kernel, variant 4
 // Branch-free loss handling.  A lane never stores while tracking: a failed
 // check only records, in registers, the first loss (state and the position
@@ -655,7 +139,7 @@ __device__ __forceinline__ void apply_elem(xtmm::Pt& q, uint32_t ktype, uint32_t
   }
   switch (ktype) {
     case K_DRIFT:
-      ok = xtmm::drift_exact(q, prm[0]);
+      ok = xtmm::drift_exact(q, prm[0], order != 0);
       lost_state = -1;
       break;
     case K_AP_CIRC:
@@ -1085,29 +569,71 @@ hipError_t launch_fill_i64(int64_t* p, int64_t v, hipStream_t s) {
 // ------------------------------------------------------ one launch per element
 // Baseline for the persistent kernels, kept for measurement: element `e`
 // (its record at word `off` of the table) is applied to every alive particle
-// by a launch of its own, which reads the particle's state from HBM and
-// writes it back.  A particle failing the element's loss test keeps the
-// coordinates it entered with (they are not written) and records the
-// element and the turn.
+// by a launch of its own, which reads from HBM the fields of the particle's
+// state that the element's map uses and writes back the ones it changes
+// (drift: reads x, px, y, py, zeta, delta, ptau, writes x, y, zeta;
+// multipole: reads x, y, px, py, writes px, py; aperture: reads x, y; RF:
+// reads zeta, ptau, writes ptau, delta, rpp, rvv; shift: x, y; rotation: x,
+// px, y, py), plus the state word.  Other elements (bends with curvature,
+// radiating multipoles, expanded drifts) read and write the whole state.  A
+// particle failing the element's loss test keeps the coordinates it entered
+// with (they are not written) and records the element and the turn.
+__device__ __forceinline__ void elem_lost(const SoA& P, int64_t p, int st, int32_t e, int32_t turn) {
+  P.state[p] = st;
+  P.at_element[p] = e;
+  P.at_turn[p] = turn;
+}
+
+template <uint32_t KT>
 __global__ void __launch_bounds__(256) k_elem(const uint64_t* __restrict__ tab, uint32_t off,
                                               int32_t e, SoA P, int64_t n, int32_t turn,
                                               KernelRef r) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= n || P.state[p] != 1) return;
   const uint64_t h = tab[off];
+  const uint32_t order = (uint32_t)((h >> 8) & 0xffu);
+  const double* __restrict__ prm = reinterpret_cast<const double*>(tab + off + 1);
   xtmm::Pt q;
-  load_pt(P, (int32_t)p, q, r.beta0);
-  bool ok;
-  int ls;
-  apply_elem(q, (uint32_t)(h & 0xffu), (uint32_t)((h >> 8) & 0xffu),
-             reinterpret_cast<const double*>(tab + off + 1), r, ok, ls, 0, turn, e);
-  if (!ok) {
-    P.state[p] = ls;
-    P.at_element[p] = e;
-    P.at_turn[p] = turn;
-    return;
+  if constexpr (KT == K_DRIFT) {
+    q.x = P.x[p]; q.px = P.px[p]; q.y = P.y[p]; q.py = P.py[p]; q.zeta = P.zeta[p];
+    q.delta = P.delta[p]; q.ptau = P.ptau[p];
+    xtmm::refresh(q, r.beta0);
+    if (!xtmm::drift_exact(q, prm[0], order != 0)) return elem_lost(P, p, -1, e, turn);
+    P.x[p] = q.x; P.y[p] = q.y; P.zeta[p] = q.zeta;
+  } else if constexpr (KT == K_MULT) {
+    q.x = P.x[p]; q.y = P.y[p]; q.px = P.px[p]; q.py = P.py[p];
+    double kx, ky;
+    multipole_n(q, prm, order, kx, ky);
+    P.px[p] = q.px; P.py[p] = q.py;
+  } else if constexpr (KT == K_AP_CIRC || KT == K_AP_ELL || KT == K_AP_RECT) {
+    q.x = P.x[p]; q.y = P.y[p];
+    bool ok;
+    if constexpr (KT == K_AP_CIRC) ok = xtmm::in_circle(q, prm[0]);
+    else if constexpr (KT == K_AP_ELL) ok = xtmm::in_ellipse(q, prm[0], prm[1]);
+    else ok = xtmm::in_rect(q, prm[0], prm[1], prm[2], prm[3]);
+    if (!ok) elem_lost(P, p, 0, e, turn);
+  } else if constexpr (KT == K_RF) {
+    q.zeta = P.zeta[p]; q.ptau = P.ptau[p];
+    xtmm::rf(q, prm[0], prm[1], prm[2], r.beta0, r.two_over_beta0);
+    P.ptau[p] = q.ptau; P.delta[p] = q.delta; P.rpp[p] = q.rpp; P.rvv[p] = q.rvv;
+  } else if constexpr (KT == K_SHIFT) {
+    q.x = P.x[p]; q.y = P.y[p];
+    xtmm::xyshift(q, prm[0], prm[1]);
+    P.x[p] = q.x; P.y[p] = q.y;
+  } else if constexpr (KT == K_SROT) {
+    q.x = P.x[p]; q.px = P.px[p]; q.y = P.y[p]; q.py = P.py[p];
+    xtmm::srotation(q, prm[0], prm[1]);
+    P.x[p] = q.x; P.px[p] = q.px; P.y[p] = q.y; P.py[p] = q.py;
+  } else if constexpr (KT == K_MARKER) {
+    (void)prm;
+  } else {
+    load_pt(P, (int32_t)p, q, r.beta0);
+    bool ok;
+    int ls;
+    apply_elem(q, (uint32_t)(h & 0xffu), order, prm, r, ok, ls, 0, turn, e);
+    if (!ok) return elem_lost(P, p, ls, e, turn);
+    store_pt(P, (int32_t)p, q);
   }
-  store_pt(P, (int32_t)p, q);
 }
 
 // After the last turn: survivors stand at element 0 of turn `turn`.
@@ -1118,14 +644,29 @@ __global__ void __launch_bounds__(256) k_elem_finish(SoA P, int64_t n, int32_t t
   P.at_element[p] = 0;
 }
 
-hipError_t launch_per_element(const uint64_t* tab, const uint32_t* offsets, int32_t n_el,
-                              SoA P, int64_t n, int32_t t0, int32_t n_turns, KernelRef r,
-                              hipStream_t s) {
+hipError_t launch_per_element(const uint64_t* tab, const uint32_t* offsets, const uint32_t* ktypes,
+                              int32_t n_el, SoA P, int64_t n, int32_t t0, int32_t n_turns,
+                              KernelRef r, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   const unsigned nb = blocks_for(n, 256);
   for (int32_t t = 0; t < n_turns; ++t) {
     for (int32_t e = 0; e < n_el; ++e) {
-      hipLaunchKernelGGL(k_elem, dim3(nb), dim3(256), 0, s, tab, offsets[e], e, P, n, t0 + t, r);
+      const uint32_t o = offsets[e];
+      const int32_t tt = t0 + t;
+#define XTM_ELEM(KT) hipLaunchKernelGGL(k_elem<KT>, dim3(nb), dim3(256), 0, s, tab, o, e, P, n, tt, r)
+      switch (ktypes[e]) {
+        case K_DRIFT: XTM_ELEM(K_DRIFT); break;
+        case K_MULT: XTM_ELEM(K_MULT); break;
+        case K_AP_CIRC: XTM_ELEM(K_AP_CIRC); break;
+        case K_AP_ELL: XTM_ELEM(K_AP_ELL); break;
+        case K_AP_RECT: XTM_ELEM(K_AP_RECT); break;
+        case K_RF: XTM_ELEM(K_RF); break;
+        case K_SHIFT: XTM_ELEM(K_SHIFT); break;
+        case K_SROT: XTM_ELEM(K_SROT); break;
+        case K_MARKER: XTM_ELEM(K_MARKER); break;
+        default: XTM_ELEM(K_MULT_CURV); break;  // whole state through apply_elem
+      }
+#undef XTM_ELEM
       const hipError_t err = hipGetLastError();
       if (err != hipSuccess) return err;
     }
@@ -1134,25 +675,13 @@ hipError_t launch_per_element(const uint64_t* tab, const uint32_t* offsets, int3
   return hipGetLastError();
 }
 
-hipError_t launch_track(const uint64_t* tab, const int32_t* seg, int32_t n_seg, int32_t n_el,
-                        SoA P, const int32_t* idx, const int32_t* ctrl, int64_t grid_upper,
+hipError_t launch_track(const uint64_t* tab, int32_t n_el, SoA P, const int32_t* idx, const int32_t* ctrl, int64_t grid_upper,
                         int32_t block, int32_t n_turns, int32_t backward, KernelRef r,
                         int32_t variant, hipStream_t s) {
   if (grid_upper <= 0 || n_turns <= 0) return hipSuccess;
-  if (variant == 4)
-    hipLaunchKernelGGL(k_track4, dim3(blocks_for(grid_upper, block)), dim3(block), 0, s, tab, n_el,
-                       P, idx, ctrl, n_turns, backward, r);
-  else if (variant == 3)
-    hipLaunchKernelGGL(k_track3<kSegWords>, dim3(blocks_for(grid_upper, block)), dim3(block), 0,
-                       s, tab, seg, n_seg, n_el, P, idx, ctrl, n_turns, backward, r);
-  else if (variant == 1)
-    hipLaunchKernelGGL(k_track, dim3(blocks_for(grid_upper, block)), dim3(block), 0, s, tab, n_el,
-                       P, idx, ctrl, n_turns, backward, r);
-  else if (variant != 2)
-    return hipErrorInvalidValue;  // not an interpreter variant
-  else
-    hipLaunchKernelGGL(k_track2, dim3(blocks_for(grid_upper, block)), dim3(block), 0, s, tab, n_el,
-                       P, idx, ctrl, n_turns, backward, r);
+  if (variant != 4) return hipErrorInvalidValue;  // the interpreter is variant 4
+  hipLaunchKernelGGL(k_track4, dim3(blocks_for(grid_upper, block)), dim3(block), 0, s, tab, n_el,
+                     P, idx, ctrl, n_turns, backward, r);
   return hipGetLastError();
 }
 
@@ -1205,8 +734,8 @@ hipError_t launch_replay(const uint64_t* tab, int32_t n_el, SoA P, const int32_t
 // ------------------------------------------------ optics by tracking
 // One turn of a few particles from the line start, the coordinates recorded
 // at the entry of every element and after the last (apertures not checked;
-// a particle whose drift leaves the longitudinal-momentum window keeps the
-// coordinates it entered that drift with).  One thread per particle, 64 per
+// a particle whose longitudinal momentum becomes imaginary in a drift keeps
+// the coordinates it entered that drift with).  One thread per particle, 64 per
 // workgroup; the element table passes through LDS segment by segment (the
 // table's segments of at most kSegWords words), so an element costs LDS
 // reads, not two dependent global loads.  The set-up from
@@ -1451,7 +980,7 @@ k_refine(const uint64_t* __restrict__ fwd, const uint64_t* __restrict__ bwd, Ref
           const double L = prm[0];
           double v0x, v0y, v1x, v1y;
           to_line(g.G + 6 * j, q.x, q.y, v0x, v0y);
-          apply_elem(q, kt, 0, prm, r, okj, lost_state, pid, 0, j);
+          apply_elem(q, kt, (uint32_t)((h >> 8) & 0xffu), prm, r, okj, lost_state, pid, 0, j);
           if (!okj) break;
           to_line(g.G + 6 * j, q.x, q.y, v1x, v1y);
           bool found = false;

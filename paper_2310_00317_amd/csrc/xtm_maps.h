@@ -26,17 +26,23 @@ __device__ __forceinline__ void refresh(Pt& q, double beta0) {
   q.bpt = beta0 * q.ptau;
 }
 
-// Square root and reciprocal for operands well inside the exponent range,
-// both correctly rounded (the same values as sqrt() and 1.0/b, which add
-// exponent scaling steps for operands near the limits; without them the
-// drift's dependent chain is a quarter shorter).
+// Square root and quotient for operands well inside the exponent range,
+// both correctly rounded (the same values as sqrt() and a/b, whose generic
+// sequences add exponent-scaling and special-case steps for operands near
+// the limits; without them the drift's dependent chain is a quarter shorter).
 //   sqrt_in: x in [2^-600, 2^600].  Goldschmidt's iteration from the
 //   hardware's reciprocal-square-root estimate y: g = x y ~ sqrt x and
 //   h = y/2 ~ 1/(2 sqrt x) refined together by r = 1/2 - h g, then two
 //   Newton corrections g += (x - g^2) h.
-//   recip_in: b in [2^-300, 2^301].  Newton's iteration r += r (1 - b r)
-//   twice from the hardware's reciprocal estimate, then the residual step
-//   r + r (1 - b r) that rounds the quotient correctly (Markstein).
+//   div_in: a/b for |a| in [2^-600, 2^1000], b in [2^-300, 3], |a/b| within
+//   [2^-960, 2^1000].  Newton's iteration r += r (1 - b r) twice from the
+//   hardware's reciprocal estimate, the product q = a r, and one correction
+//   by the exact remainder, q + r (a - b q) (Markstein's quotient step).  The
+//   reciprocal converges from below and may stop one unit short of the
+//   rounded 1/b; the corrected quotient is then still the rounded a/b except
+//   in one family: a divisor whose significand is all ones (b = 2^k (2 -
+//   2^-52)) and a power-of-two numerator, where the exact q + r (a - b q) is
+//   a tie.  Callers keep that family out (the drift's window below).
 __device__ __forceinline__ double sqrt_in(double x) {
   const double y = __builtin_amdgcn_rsq(x);
   double g = x * y;
@@ -50,47 +56,87 @@ __device__ __forceinline__ double sqrt_in(double x) {
   return fma(d, h, g);
 }
 
-__device__ __forceinline__ double recip_in(double b) {
+__device__ __forceinline__ double div_in(double a, double b) {
   double r = __builtin_amdgcn_rcp(b);
   double e = fma(-b, r, 1.0);
   r = fma(r, e, r);
   e = fma(-b, r, 1.0);
   r = fma(r, e, r);
-  const double res = fma(-b, r, 1.0);
-  return fma(res, r, r);
+  const double q = a * r;
+  const double rho = fma(-b, q, a);
+  return fma(rho, r, q);
 }
 
-// Exact drift over L: pz = sqrt((1+d)^2 - px^2 - py^2), lp = L (1/pz),
-// x += px lp, y += py lp, zeta += lp ((d(2+d) - px^2 - py^2) (1/(1+pz)) - beta0 ptau),
-// the reciprocals correctly rounded.  Returns false unless
-// 2^-600 < pz^2 < 2^600 (imaginary, vanishing or absurd longitudinal
-// momentum, or NaN): the particle is lost; the arithmetic still runs (its
-// results are not used) so the caller needs no branch.  Inside the window
-// pz lies in [2^-300, 2^300], the domain of sqrt_in and recip_in.
-__device__ __forceinline__ bool drift_exact(Pt& q, double L) {
-  const double px2 = q.px * q.px;
-  const double py2 = q.py * q.py;
-  const double pz2 = q.opd2 - px2 - py2;
-  const bool ok = (pz2 > 0x1p-600) & (pz2 < 0x1p600);
-  const double pz = sqrt_in(pz2);
-  const double rpz = recip_in(pz);
-  const double rpz1 = recip_in(1.0 + pz);
-  const double lp = L * rpz;
+// Exact drift over L: pz = sqrt((1+d)^2 - px^2 - py^2), lp = L / pz,
+// x += px lp, y += py lp, zeta += lp ((d(2+d) - px^2 - py^2) / (1+pz) - beta0 ptau),
+// every square root and quotient correctly rounded.  The particle is lost
+// unless pz^2 > 0 (imaginary longitudinal momentum, or NaN).
+// The short sequences above serve the window
+//   pz^2 in (2^-600, 4), so pz in (2^-300, 2) and 1 + pz in (1, 3);
+//   a = d(2+d) - px^2 - py^2 with |a| >= 2^-600 (|a| < 2^1000 whenever pz^2
+//   is finite);
+//   1 + pz != 2 - 2^-52, the one all-ones divisor in (1, 3);
+//   a drift length the lattice packer marked as a non-power of two inside
+//   [2^-600, 2^600] (order-0 record; order 1 marks any other length, zero
+//   included), so L / pz never meets the all-ones family either.
+// Other operands take the generic operations on a rare branch.
+struct DriftIn {
+  double px2, py2, pz2, a;
+};
+
+__device__ __forceinline__ DriftIn drift_in(const Pt& q) {
+  DriftIn d;
+  d.px2 = q.px * q.px;
+  d.py2 = q.py * q.py;
+  d.pz2 = q.opd2 - d.px2 - d.py2;
+  d.a = q.u - d.px2 - d.py2;
+  return d;
+}
+
+// window test of the operands known before the square root
+__device__ __forceinline__ bool drift_window(const DriftIn& d) {
+  return (d.pz2 > 0x1p-600) & (d.pz2 < 4.0) & (fabs(d.a) >= 0x1p-600);
+}
+
+__device__ __forceinline__ void drift_apply(Pt& q, double lp, double dq) {
   q.x = fma(q.px, lp, q.x);
   q.y = fma(q.py, lp, q.y);
-  const double dz = (q.u - px2 - py2) * rpz1 - q.bpt;
-  q.zeta = fma(lp, dz, q.zeta);
-  return ok;
+  q.zeta = fma(lp, dq - q.bpt, q.zeta);
 }
 
-// The exact drift's loss test alone (the same operations drift_exact starts
-// with, so a compiler evaluates them once when both are used).
-__device__ __forceinline__ bool drift_ok(const Pt& q) {
-  const double px2 = q.px * q.px;
-  const double py2 = q.py * q.py;
-  const double pz2 = q.opd2 - px2 - py2;
-  return (pz2 > 0x1p-600) & (pz2 < 0x1p600);
+// Quotients of the drift: the short sequences where the window holds
+// (`fast` returns whether it did), else the generic operations (for a lost
+// particle the results are NaN and unused).
+__device__ __forceinline__ void drift_quotients(double L, const DriftIn& d, bool any_length,
+                                                double& lp, double& dq, bool& fast) {
+  const double pz = sqrt_in(d.pz2);
+  const double b1 = 1.0 + pz;
+  lp = div_in(L, pz);
+  dq = div_in(d.a, b1);
+  fast = !any_length & drift_window(d) & (b1 != 0x1.fffffffffffffp+0);
 }
+
+__device__ __forceinline__ void drift_generic(double L, const DriftIn& d, double& lp, double& dq) {
+  const double pz = sqrt(d.pz2);
+  lp = L / pz;
+  dq = d.a / (1.0 + pz);
+}
+
+// The whole drift; returns false if the particle is lost (its coordinates
+// are then NaN and must not be used).  any_length: the drift length is
+// outside the window (order-1 drift record).
+__device__ __forceinline__ bool drift_exact(Pt& q, double L, bool any_length = false) {
+  const DriftIn d = drift_in(q);
+  double lp, dq;
+  bool fast;
+  drift_quotients(L, d, any_length, lp, dq, fast);
+  if (!fast) drift_generic(L, d, lp, dq);
+  drift_apply(q, lp, dq);
+  return d.pz2 > 0.0;
+}
+
+// The exact drift's loss test alone.
+__device__ __forceinline__ bool drift_ok(const Pt& q) { return drift_in(q).pz2 > 0.0; }
 
 // Drift of H = pzeta - (1+d) + (px^2+py^2)/(2(1+d)) over L.
 __device__ __forceinline__ void drift_expanded(Pt& q, double L) {

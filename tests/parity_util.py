@@ -2,6 +2,17 @@
 import numpy as np
 
 COORDS = ("x", "px", "y", "py", "zeta", "delta")
+
+# Forward 100 turns then backward 100 turns of the FODO ring returns every
+# surviving particle of this sample to within this many times
+# max(|u0|, RMS of the coordinate): one bound for the oracle's own pin and
+# for the GPU, on the same particles.
+REVERSIBILITY_BOUND = 1e-11
+
+
+def reversibility_sample():
+    from paper_2310_00317_amd import inputs as I
+    return I.cfg1_particles(500, seed=12)
 ALL_FLOAT = COORDS + ("ptau", "rpp", "rvv")
 
 

@@ -101,7 +101,7 @@ def test_radiation_graph_and_chunks_invariant(P):
 def test_radiation_argument_checks(P):
     lat = P.Lattice(_ring(), EREF)
     parts = P.Particles(4, EREF).init(np.zeros((4, 6)))
-    for kw, code in [(dict(radiation=3), -1), (dict(radiation=1, variant=2), -6)]:
+    for kw, code in [(dict(radiation=3), -1), (dict(radiation=1, variant=2), -1)]:
         with pytest.raises(P.XtmError) as ei:
             P.track(lat, parts, 1, **kw)
         assert ei.value.code == code

@@ -14,6 +14,7 @@ import numpy as np
 import pytest
 
 from paper_2310_00317_amd import inputs as I
+from parity_util import REVERSIBILITY_BOUND, reversibility_sample
 
 getcontext().prec = 60
 REF = I.PROTON_450GEV
@@ -405,13 +406,14 @@ def test_threads_do_not_change_results(oracle_mod):
         assert np.array_equal(getattr(a, f), getattr(b, f)), f
 
 
-def test_forward_backward_reversibility(oracle_mod):
+@pytest.mark.parametrize("rf_on", [True, False])
+def test_forward_backward_reversibility(oracle_mod, rf_on):
     """Forward 100 turns then the inverse maps for 100 turns restore every
-    surviving particle to within 1e-11 x max(|u0|, RMS of that coordinate);
-    every inverse is algebraically exact, so only rounding remains (seen:
-    <= 6e-13 of the RMS)."""
-    el = I.cfg1_lattice()
-    c = I.cfg1_particles(200)
+    surviving particle to within REVERSIBILITY_BOUND x max(|u0|, RMS of that
+    coordinate), on the sample and with the bound the GPU test uses; every
+    inverse is algebraically exact, so only rounding remains."""
+    el = I.cfg1_lattice(rf_on=rf_on)
+    c = reversibility_sample()
     p = oracle_mod.init(c, REF)
     oracle_mod.track(el, REF, p, 100)
     alive = p.state == 1
@@ -420,7 +422,7 @@ def test_forward_backward_reversibility(oracle_mod):
     rms = np.sqrt(np.mean(c[alive] ** 2, axis=0))
     for j, f in enumerate(("x", "px", "y", "py", "zeta", "delta")):
         err = np.abs(getattr(p, f)[alive] - c[alive, j])
-        bound = 1e-11 * np.maximum(np.abs(c[alive, j]), rms[j])
+        bound = REVERSIBILITY_BOUND * np.maximum(np.abs(c[alive, j]), rms[j])
         assert np.all(err <= bound), (f, np.max(err / bound))
 
 
