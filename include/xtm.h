@@ -517,6 +517,22 @@ xtm_status xtm_mlp_grad(const float* d_theta, const float* d_norm, const float* 
                         const float* d_y, int64_t B, float pos_weight, float* d_grad,
                         float* d_loss, float* d_work, void* stream);
 
+/* xtm_mlp_grad without a workspace argument and without any device
+   allocation, for callers that cannot allocate: code recorded into a HIP
+   graph, tight training or serving loops, harnesses that forbid hipMalloc.
+   Same arithmetic and kernels as xtm_mlp_grad, so the results are bitwise
+   those of xtm_mlp_grad with a caller workspace.  The per-block partial
+   gradients go to a fixed device array of the library (4.6 MiB on each
+   device it runs on, held until the process ends; its address is looked up
+   once per device at the first call there).  B must be 1..4096, otherwise
+   XTM_E_ARG.  Every call on one device shares that array: calls that
+   overlap on one device (different streams, or host threads) race and must
+   be serialised by the caller; stream-ordered calls on one stream are safe.
+   Stream-ordered, no synchronisation. */
+xtm_status xtm_mlp_grad_noalloc(const float* d_theta, const float* d_norm, const float* d_x,
+                                const float* d_y, int64_t B, float pos_weight, float* d_grad,
+                                float* d_loss, void* stream);
+
 /* One Adam step (Kingma & Ba 2015; beta1 0.9, beta2 0.999, eps 1e-8) on the
    FP32 master parameters, step counted from 1; d_m, d_v start at zero. */
 xtm_status xtm_mlp_adam(float* d_theta, float* d_m, float* d_v, const float* d_grad, int32_t step,

@@ -123,6 +123,7 @@ def lib() -> ctypes.CDLL:
             "xtm_mlp_forward": ([vp, vp, vp, i64, vp, vp], i32),
             "xtm_mlp_workspace": ([i64, vp], i32),
             "xtm_mlp_grad": ([vp, vp, vp, vp, i64, ctypes.c_float, vp, vp, vp, vp], i32),
+            "xtm_mlp_grad_noalloc": ([vp, vp, vp, vp, i64, ctypes.c_float, vp, vp, vp], i32),
             "xtm_mlp_adam": ([vp, vp, vp, vp, i32, ctypes.c_float, vp], i32),
             "xtm_mlp_train": ([vp, vp, vp, vp, vp, vp, i64, ctypes.c_float, i32, i32,
                                ctypes.c_float, ctypes.c_uint64, vp, vp, vp], i32),
@@ -579,6 +580,18 @@ def mlp_grad(theta, norm, x, y, pos_weight: float, work=None, stream=None):
     check(lib().xtm_mlp_grad(_p(theta), _p(norm), _p(x), _p(y), B, float(pos_weight), _p(grad),
                              _p(loss), _p(work), _stream(stream)), "xtm_mlp_grad")
     return grad, loss
+
+
+MLP_NOALLOC_MAX_BATCH = 4096
+
+
+def mlp_grad_noalloc(theta, norm, x, y, pos_weight: float, grad, loss=None, stream=None):
+    """xtm_mlp_grad_noalloc into caller tensors grad [MLP_PARAMS] and loss
+    [1] (or None): the library's fixed workspace, no device allocation."""
+    check(lib().xtm_mlp_grad_noalloc(_p(theta), _p(norm), _p(x), _p(y), int(x.shape[0]),
+                                     float(pos_weight), _p(grad),
+                                     _p(loss), _stream(stream)),
+          "xtm_mlp_grad_noalloc")
 
 
 def mlp_adam(theta, m, v, grad, step: int, lr: float, stream=None):

@@ -1275,6 +1275,22 @@ xtm_status xtm_mlp_grad(const float* d_theta, const float* d_norm, const float* 
   return XTM_OK;
 }
 
+xtm_status xtm_mlp_grad_noalloc(const float* d_theta, const float* d_norm, const float* d_x,
+                                const float* d_y, int64_t B, float pos_weight, float* d_grad,
+                                float* d_loss, void* stream) {
+  if (!d_theta || !d_norm || !d_x || !d_y || !d_grad) return fail(XTM_E_ARG, "bad arguments");
+  if (B <= 0 || B > kMlpNoAllocMaxBatch)
+    return fail(XTM_E_ARG, "batch must be 1.." + std::to_string(kMlpNoAllocMaxBatch) +
+                               " rows for the allocation-free gradient");
+  float* work = nullptr;
+  hipError_t e = mlp_noalloc_workspace(&work);
+  if (e != hipSuccess) return hip_fail(e, "fixed gradient workspace lookup");
+  e = launch_mlp_grad(d_theta, d_norm, d_x, d_y, B, pos_weight, d_grad, d_loss, work,
+                      (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "mlp grad launch");
+  return XTM_OK;
+}
+
 xtm_status xtm_mlp_adam(float* d_theta, float* d_m, float* d_v, const float* d_grad, int32_t step,
                         float lr, void* stream) {
   if (!d_theta || !d_m || !d_v || !d_grad || step < 1) return fail(XTM_E_ARG, "bad arguments");

@@ -198,6 +198,13 @@ hipError_t launch_philox(unsigned long long seed, const uint32_t ctr0[4], int64_
 hipError_t launch_mlp_forward(const float* theta, const float* norm, const float* X, int64_t B,
                               float* logit, hipStream_t s);
 int64_t mlp_workspace_floats(int64_t B);
+// Largest batch of the allocation-free gradient entry point: its per-block
+// partial gradients live in a fixed device array of
+// mlp_workspace_floats(kMlpNoAllocMaxBatch) floats (4.6 MiB) per device.
+constexpr int64_t kMlpNoAllocMaxBatch = 4096;
+// Device address of that array on the current device, looked up once per
+// device with hipGetSymbolAddress and kept for the life of the process.
+hipError_t mlp_noalloc_workspace(float** out);
 hipError_t launch_mlp_grad(const float* theta, const float* norm, const float* X, const float* Y,
                            int64_t B, float pos_weight, float* grad, float* loss, float* work,
                            hipStream_t s);

@@ -11,6 +11,8 @@
 //   A (16 x 16, rows m, cols k): lane l holds A[l % 16][4 (l / 16) + j], j = 0..3
 //   B (16 x 16, rows k, cols n): lane l holds B[4 (l / 16) + j][l % 16]
 //   D (16 x 16):                 lane l holds D[4 (l / 16) + j][l % 16]
+#include <mutex>
+
 #include "xtm_internal.h"
 #include "xtm_maps.h"
 
@@ -584,6 +586,37 @@ hipError_t launch_mlp_forward(const float* theta, const float* norm, const float
 int64_t mlp_workspace_floats(int64_t B) {
   const int64_t nb = (B + kSamplesPerBlock - 1) / kSamplesPerBlock;
   return nb * (kParams + 1);
+}
+
+// Workspace of the allocation-free gradient entry point (batches of at most
+// kMlpNoAllocMaxBatch rows).  Every launch of k_mlp_grad writes all the
+// partials the reduction then reads, so the array never needs clearing.  In
+// host code `scratch` names a host-side stand-in: kernels receive the device
+// address looked up below, never the symbol itself.
+constexpr int64_t kNoAllocFloats =
+    ((kMlpNoAllocMaxBatch + kSamplesPerBlock - 1) / kSamplesPerBlock) * (kParams + 1);
+static __device__ __align__(256) float scratch[kNoAllocFloats];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float* g_scratch_addr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t mlp_noalloc_workspace(float** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_addr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_addr[dev] = static_cast<float*>(p);
+  }
+  *out = g_scratch_addr[dev];
+  return hipSuccess;
 }
 
 hipError_t launch_mlp_grad(const float* theta, const float* norm, const float* X, const float* Y,

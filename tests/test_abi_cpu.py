@@ -112,3 +112,15 @@ def test_dynamic_aperture_host_function_matches_oracle(oracle_mod):
     with pytest.raises(P.XtmError):
         P.lib()
         P.check(P.lib().xtm_dynamic_aperture(None, None, 0, 0, None), "xtm_dynamic_aperture")
+
+
+def test_noalloc_gradient_checks_its_arguments_before_any_device_work(xtm):
+    """The allocation-free gradient rejects batches beyond its fixed
+    workspace (and empty ones) before it looks at any pointer or device."""
+    L = xtm.lib()
+    fake = ctypes.c_void_p(256)   # never dereferenced: the call fails first
+    for B in (0, -1, 4097, 1 << 40):
+        assert L.xtm_mlp_grad_noalloc(fake, fake, fake, fake, B, 1.0, fake, None, None) == -1
+        assert b"4096" in L.xtm_last_error()
+    assert L.xtm_mlp_grad_noalloc(None, fake, fake, fake, 8, 1.0, fake, None, None) == -1
+    assert L.xtm_mlp_grad_noalloc(fake, fake, fake, fake, 8, 1.0, None, None, None) == -1
