@@ -45,6 +45,10 @@ TRAFFIC_SOURCES = ("xtm_jit.cpp", "xtm_maps.h")
 MEASURED_TRAFFIC = {
     # (workload, particles, turns per step, kernel variant, source hash):
     #     (bytes per launch, profile)
+    ("cfg2", 100000, 1000, 10, "e607783bd40dbf2c"):
+        (21453937.0, "profiles/xtm_line_cfg2_hbm_counters.txt"),
+    ("cfg1sat", 1048576, 1000, 10, "e607783bd40dbf2c"):
+        (189112442.0, "profiles/xtm_line_cfg2_hbm_counters.txt"),
 }
 
 

@@ -101,7 +101,7 @@ __device__ __forceinline__ void multipole_n(xtmm::Pt& q, const double* __restric
 }
 
 // radiation after a multipole of length lr (identity of the deviate: particle
-// id, absolute turn, user element index)
+// id, absolute turn, element index of the line as tracked, thick elements sliced)
 __device__ __forceinline__ void maybe_radiate(xtmm::Pt& q, double kx, double ky, double lr,
                                               const KernelRef& r, long long pid, int turn,
                                               int element) {

@@ -409,7 +409,7 @@ __device__ __forceinline__ void radiate(Pt& q, double kx, double ky, double lr, 
 
 // Radiation step of a multipole with radiation length lr (none if lr <= 0 or
 // mode 0); the Gaussian deviate is keyed by (seed, particle id, absolute
-// turn, user element index).
+// turn, element index of the line as tracked, thick elements sliced).
 template <bool kFar = false>
 __device__ __forceinline__ void radiate_at(Pt& q, double kx, double ky, double lr, int mode,
                                            unsigned long long seed, long long pid, int turn,

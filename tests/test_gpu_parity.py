@@ -250,6 +250,46 @@ def test_cfg2_lattice_reduced(P, oracle_mod):
     assert gp == op
 
 
+def test_cfg2_loss_parity_at_da_scale(P, oracle_mod):
+    """Lost/surviving agreement on the 20,000-element DA ring at a scan's
+    turn count: five rays of the 50-angle grid, 241 radii each from 1.5 to
+    9 sigma (spacing 1/32 sigma, straddling every ray's dynamic aperture),
+    1,000 turns, the oracle on all host threads.  Gates: >= 99.9 % of the
+    particles agree on lost/surviving, and any particle that disagrees lies
+    within 0.05 sigma of its ray's dynamic aperture (the smallest radius the
+    oracle loses on that ray); particles lost on both sides agree on turn
+    and element.  The identity rate of the whole record is reported."""
+    banner("cfg2 ring: 5 rays x 241 radii, 1,000 turns (loss parity at DA scale)")
+    el = I.cfg2_lattice()
+    c_all, r_all, _ = I.cfg2_grid(n_r=321, n_theta=50, r_max_sigma=10.0)
+    rays = (5, 15, 25, 35, 45)
+    ray_of = np.repeat(np.arange(50), 321)
+    sel = np.isin(ray_of, rays) & (r_all >= 1.5) & (r_all <= 9.0)
+    c, r, ray = c_all[sel], r_all[sel], ray_of[sel]
+    assert len(c) == 5 * 241
+    turns = 1000
+    g, gp, _, _, _ = gpu_run(P, el, REF, c, turns)
+    o, op = oracle_run(oracle_mod, el, REF, c, turns)
+    g_alive, o_alive = g["state"] == 1, o.state == 1
+    agree = g_alive == o_alive
+    same_record = ((g["state"] == o.state) & (g["at_turn"] == o.at_turn)
+                   & (g["at_element"] == o.at_element))
+    da = {j: float(np.min(r[(ray == j) & ~o_alive], initial=np.inf)) for j in rays}
+    banner(f"lost/surviving agreement {agree.mean():.5f}; identical loss records "
+           f"{same_record.mean():.5f}; bitwise-equal coordinates "
+           f"{bitwise_fraction(g, o, np.ones(len(c), bool)):.5f}; passes gpu {gp} oracle {op}; "
+           f"DA per ray " + ", ".join(f"{j}: {da[j]:.3f}" for j in rays))
+    assert 0.1 < o_alive.mean() < 0.9   # the radii straddle the aperture
+    assert all(1.5 < da[j] < 9.0 for j in rays)
+    assert agree.mean() >= 0.999
+    for i in np.nonzero(~agree)[0]:
+        assert abs(r[i] - da[int(ray[i])]) <= 0.05, (i, r[i], da[int(ray[i])])
+    both_lost = ~g_alive & ~o_alive
+    assert np.array_equal(g["at_turn"][both_lost], o.at_turn[both_lost])
+    assert np.array_equal(g["at_element"][both_lost], o.at_element[both_lost])
+    assert np.array_equal(g["state"][both_lost], o.state[both_lost])
+
+
 @pytest.mark.parametrize("variant", [4, 5, 6, 7, 8, 9, 10, 11, 12, 13])
 def test_kernel_variants_on_multisegment_lattice(P, variant):
     """The 20,000-element lattice spans many LDS segments: every kernel variant
