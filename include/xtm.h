@@ -573,11 +573,49 @@ xtm_status xtm_dynamic_aperture(const int32_t* h_state, const double* h_radius, 
    counts as a survivor) unless it belongs to the audit set: audited iff the
    first word of Philox4x32-10 with key audit_seed and counter (pid_lo, pid_hi,
    0xFFFFFFFF, 0) is below ceil(audit_fraction 2^32).  Audited particles stay
-   alive.  Rebuilds the alive list; synchronises; the counts go to the host
-   when non-NULL. */
+   alive and, when d_audit_flags (device int32, one per slot, caller-zeroed
+   before the first decision) is non-NULL, get d_audit_flags[slot] = 1; the
+   flags accumulate over repeated decisions and judge them all
+   (xtm_audit_verdict).  Rebuilds the alive list; synchronises; the counts go
+   to the host when non-NULL. */
 xtm_status xtm_retire(xtm_particles P, const float* d_logit, float logit_threshold,
-                      uint64_t audit_seed, double audit_fraction, int64_t* h_retired,
-                      int64_t* h_audited, void* stream);
+                      uint64_t audit_seed, double audit_fraction, int32_t* d_audit_flags,
+                      int64_t* h_retired, int64_t* h_audited, void* stream);
+
+/* Score of the same retire policy without the network: d_score[i] =
+   -max(f8, f9) of row i of d_feat [n][16] (the two tune-diffusion features of
+   xtm_features; NaN if either is NaN), to be thresholded like a logit. */
+xtm_status xtm_rule_score(const float* d_feat, int64_t n, float* d_score, void* stream);
+
+/* One-sided 95 % upper confidence bound of a loss fraction from n_lost of
+   n_audited audited particles, Wilson's score interval with z = 1.6448536...:
+   (p + z^2/(2n) + z sqrt(p (1-p)/n + z^2/(4n^2))) / (1 + z^2/n), p = k/n;
+   1 when n_audited = 0.  Host only. */
+xtm_status xtm_audit_upper_bound(int64_t n_lost, int64_t n_audited, double* out);
+
+/* The audit's verdict after tracking to the horizon: the particles flagged in
+   d_audit_flags (xtm_retire) are the audit; h_audited = their number,
+   h_lost = how many of them are lost (state 0 or -1), h_upper = the bound of
+   xtm_audit_upper_bound, h_fallback = 1 iff some particle is retired
+   (state 2) and h_upper > fallback_rate (the retirements are then not
+   trusted and xtm_resume_retired should follow).  Any output may be NULL.
+   Synchronises. */
+xtm_status xtm_audit_verdict(xtm_particles P, const int32_t* d_audit_flags, double fallback_rate,
+                             int64_t* h_audited, int64_t* h_lost, double* h_upper,
+                             int32_t* h_fallback, void* stream);
+
+/* Full-tracking fallback: every retired particle (state 2) resumes from the
+   coordinates and the turn (its at_turn) it was retired at and is tracked
+   through `lat` up to the set's current turn (the horizon), as if it had
+   never been retired; particles in other states are not touched.  The
+   particles retired at one turn are tracked together, joined by those of
+   the next retirement turn when they reach it, so the results equal those
+   of uninterrupted tracking bit for bit.  Afterwards the set's alive list
+   holds every particle alive at the horizon.  Options as for xtm_track
+   (no recorder, no graph); stats (or NULL) sum the launches made.
+   Synchronises. */
+xtm_status xtm_resume_retired(xtm_lattice lat, xtm_particles P, const xtm_track_opts* opts,
+                              void* stream, xtm_track_stats* stats);
 
 /* Synchronise the stream and report any asynchronous device error. */
 xtm_status xtm_sync(void* stream);

@@ -632,6 +632,39 @@ def dynamic_aperture(state, radii, n_r: int, n_theta: int) -> np.ndarray:
     return out
 
 
+def wilson_upper(k: int, n: int, z: float = 1.6448536269514722) -> float:
+    """Upper end of Wilson's score interval for k successes in n trials at
+    normal quantile z (one-sided 95 % by default); 1 for n = 0.  The audit of
+    the retire policy bounds its false-retire fraction with it."""
+    if n == 0:
+        return 1.0
+    p = k / n
+    centre = p + z * z / (2 * n)
+    half = z * math.sqrt(p * (1 - p) / n + z * z / (4 * n * n))
+    return min(1.0, (centre + half) / (1 + z * z / n))
+
+
+def audit_verdict(state, audit_flags, fallback_rate: float) -> dict:
+    """The audit after tracking to the horizon: the flagged particles are the
+    audit; lost ones have state 0 or -1; the retirements are rejected (full
+    tracking resumes) iff some particle is retired (state 2) and the Wilson
+    upper bound of the audit's loss fraction exceeds fallback_rate."""
+    st = np.asarray(state)
+    fl = np.asarray(audit_flags) != 0
+    audited = int(fl.sum())
+    lost = int((fl & ((st == 0) | (st == -1))).sum())
+    upper = wilson_upper(lost, audited)
+    return {"audited": audited, "lost": lost, "upper": upper,
+            "fallback": bool((st == 2).any() and upper > fallback_rate)}
+
+
+def rule_score(feat) -> np.ndarray:
+    """Score of the retire rule without the network: minus the larger of the
+    two tune-diffusion features (columns 8 and 9); NaN if either is NaN."""
+    f = np.asarray(feat, dtype=np.float32)
+    return -np.maximum(f[:, 8], f[:, 9])
+
+
 def select_threshold(logit, label, max_false_rate: float):
     """Retire threshold by brute force over every candidate: the smallest
     logit value tau (finite) such that among rows with logit >= tau the

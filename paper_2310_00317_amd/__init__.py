@@ -129,8 +129,12 @@ def lib() -> ctypes.CDLL:
                                ctypes.c_float, ctypes.c_uint64, vp, vp, vp], i32),
             "xtm_select_threshold": ([vp, vp, i64, ctypes.c_double, vp, vp, vp, vp], i32),
             "xtm_dynamic_aperture": ([vp, vp, i32, i32, vp], i32),
-            "xtm_retire": ([vp, vp, ctypes.c_float, ctypes.c_uint64, ctypes.c_double, vp, vp, vp],
-                           i32),
+            "xtm_retire": ([vp, vp, ctypes.c_float, ctypes.c_uint64, ctypes.c_double, vp, vp, vp,
+                            vp], i32),
+            "xtm_rule_score": ([vp, i64, vp, vp], i32),
+            "xtm_audit_upper_bound": ([i64, i64, vp], i32),
+            "xtm_audit_verdict": ([vp, vp, ctypes.c_double, vp, vp, vp, vp, vp], i32),
+            "xtm_resume_retired": ([vp, vp, vp, vp, vp], i32),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -600,15 +604,53 @@ def mlp_adam(theta, m, v, grad, step: int, lr: float, stream=None):
 
 
 def retire(particles: Particles, logit, threshold: float, audit_seed: int,
-           audit_fraction: float = 0.05, stream=None):
+           audit_fraction: float = 0.05, audit_flags=None, stream=None):
     """Retire alive particles with logit >= threshold outside the audit set;
-    returns (retired, audited)."""
+    the audited ones are flagged in audit_flags (int32 tensor, one per slot)
+    when given; returns (retired, audited)."""
     r = ctypes.c_int64()
     a = ctypes.c_int64()
     check(lib().xtm_retire(particles.handle, _p(logit), float(threshold), int(audit_seed),
-                           float(audit_fraction), ctypes.byref(r), ctypes.byref(a),
-                           _stream(stream)), "xtm_retire")
+                           float(audit_fraction), _p(audit_flags), ctypes.byref(r),
+                           ctypes.byref(a), _stream(stream)), "xtm_retire")
     return int(r.value), int(a.value)
+
+
+def rule_score(feat, stream=None):
+    """-max(f8, f9) per row of a [n, 16] float32 feature tensor (xtm_rule_score)."""
+    import torch
+    n = int(feat.shape[0])
+    out = torch.empty(max(n, 1), dtype=torch.float32, device=feat.device)
+    check(lib().xtm_rule_score(_p(feat), n, _p(out), _stream(stream)), "xtm_rule_score")
+    return out[:n]
+
+
+def audit_upper_bound(n_lost: int, n_audited: int) -> float:
+    out = ctypes.c_double()
+    check(lib().xtm_audit_upper_bound(int(n_lost), int(n_audited), ctypes.byref(out)),
+          "xtm_audit_upper_bound")
+    return float(out.value)
+
+
+def audit_verdict(particles: Particles, audit_flags, fallback_rate: float, stream=None) -> dict:
+    """xtm_audit_verdict: {audited, lost, upper, fallback}."""
+    a, l, f = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int32()
+    u = ctypes.c_double()
+    check(lib().xtm_audit_verdict(particles.handle, _p(audit_flags), float(fallback_rate),
+                                  ctypes.byref(a), ctypes.byref(l), ctypes.byref(u),
+                                  ctypes.byref(f), _stream(stream)), "xtm_audit_verdict")
+    return {"audited": int(a.value), "lost": int(l.value), "upper": float(u.value),
+            "fallback": bool(f.value)}
+
+
+def resume_retired(lattice: Lattice, particles: Particles, variant: int = 0, stream=None):
+    """xtm_resume_retired: the full-tracking fallback; returns (passes, alive)."""
+    o = TrackOpts()
+    o.variant = int(variant)
+    st = TrackStats()
+    check(lib().xtm_resume_retired(lattice.handle, particles.handle, ctypes.byref(o),
+                                   _stream(stream), ctypes.byref(st)), "xtm_resume_retired")
+    return int(st.passes), int(st.alive)
 
 
 def mlp_train(theta, m, v, norm, x, y, pos_weight: float, epochs: int, batch: int, lr: float,

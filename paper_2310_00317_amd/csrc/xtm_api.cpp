@@ -1421,8 +1421,8 @@ xtm_status xtm_dynamic_aperture(const int32_t* h_state, const double* h_radius, 
 }
 
 xtm_status xtm_retire(xtm_particles P, const float* d_logit, float logit_threshold,
-                      uint64_t audit_seed, double audit_fraction, int64_t* h_retired,
-                      int64_t* h_audited, void* stream) {
+                      uint64_t audit_seed, double audit_fraction, int32_t* d_audit_flags,
+                      int64_t* h_retired, int64_t* h_audited, void* stream) {
   return guarded([&]() -> xtm_status {
     if (!P || !d_logit) return fail(XTM_E_ARG, "null argument");
     if (!(audit_fraction >= 0.0) || audit_fraction > 1.0)
@@ -1438,7 +1438,7 @@ xtm_status xtm_retire(xtm_particles P, const float* d_logit, float logit_thresho
     hipError_t e = hipMemsetAsync(counts, 0, 2 * sizeof(unsigned int), s);
     if (e == hipSuccess)
       e = launch_retire(soa_of(P), P->idx[P->cur], P->ctrl, P->alive_upper, d_logit,
-                        logit_threshold, audit_seed, at, counts, s);
+                        logit_threshold, audit_seed, at, counts, d_audit_flags, s);
     // rebuild the alive list without the retired particles
     if (e == hipSuccess) e = launch_iota(P->idx[1 - P->cur], P->n, P->ctrl, (int32_t)P->n, P->turn, s);
     if (e == hipSuccess)
@@ -1453,6 +1453,159 @@ xtm_status xtm_retire(xtm_particles P, const float* d_logit, float logit_thresho
     if (h_audited) *h_audited = hc[1];
     int64_t alive = 0;
     return read_alive(P, s, &alive, nullptr);
+  });
+}
+
+xtm_status xtm_rule_score(const float* d_feat, int64_t n, float* d_score, void* stream) {
+  if (n < 0 || (n > 0 && (!d_feat || !d_score))) return fail(XTM_E_ARG, "bad arguments");
+  hipError_t e = launch_rule_score(d_feat, n, d_score, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "rule score launch");
+  return XTM_OK;
+}
+
+namespace {
+// one-sided 95 % quantile of the standard normal distribution
+constexpr double kAuditZ = 1.6448536269514722;
+
+// Wilson's score interval, upper end: (p + z^2/2n + z sqrt(p(1-p)/n + z^2/4n^2)) / (1 + z^2/n)
+double wilson_upper(int64_t k, int64_t n) {
+  if (n <= 0) return 1.0;
+  const double z2 = kAuditZ * kAuditZ, nn = (double)n;
+  const double p = (double)k / nn;
+  const double centre = p + z2 / (2.0 * nn);
+  const double half = kAuditZ * std::sqrt(p * (1.0 - p) / nn + z2 / (4.0 * nn * nn));
+  return std::min(1.0, (centre + half) / (1.0 + z2 / nn));
+}
+}  // namespace
+
+xtm_status xtm_audit_upper_bound(int64_t n_lost, int64_t n_audited, double* out) {
+  if (!out || n_lost < 0 || n_audited < 0 || n_lost > n_audited)
+    return fail(XTM_E_ARG, "need 0 <= n_lost <= n_audited and an output");
+  *out = wilson_upper(n_lost, n_audited);
+  return XTM_OK;
+}
+
+xtm_status xtm_audit_verdict(xtm_particles P, const int32_t* d_audit_flags, double fallback_rate,
+                             int64_t* h_audited, int64_t* h_lost, double* h_upper,
+                             int32_t* h_fallback, void* stream) {
+  return guarded([&]() -> xtm_status {
+    if (!P || (P->n > 0 && !d_audit_flags)) return fail(XTM_E_ARG, "null argument");
+    if (!P->initialised) return fail(XTM_E_STATE, "particle set not initialised");
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<int32_t> st((size_t)P->n), fl((size_t)P->n);
+    if (P->n > 0) {
+      HIP_TRY(hipMemcpyAsync(st.data(), P->a.state, P->n * sizeof(int32_t), hipMemcpyDeviceToHost,
+                             s),
+              "read states");
+      HIP_TRY(hipMemcpyAsync(fl.data(), d_audit_flags, P->n * sizeof(int32_t),
+                             hipMemcpyDeviceToHost, s),
+              "read audit flags");
+    }
+    HIP_TRY(hipStreamSynchronize(s), "synchronise");
+    int64_t audited = 0, lost = 0, retired = 0;
+    for (int64_t i = 0; i < P->n; ++i) {
+      if (st[i] == 2) ++retired;
+      if (fl[i] != 0) {
+        ++audited;
+        if (st[i] == 0 || st[i] == -1) ++lost;
+      }
+    }
+    const double upper = wilson_upper(lost, audited);
+    if (h_audited) *h_audited = audited;
+    if (h_lost) *h_lost = lost;
+    if (h_upper) *h_upper = upper;
+    if (h_fallback) *h_fallback = (retired > 0 && upper > fallback_rate) ? 1 : 0;
+    return XTM_OK;
+  });
+}
+
+xtm_status xtm_resume_retired(xtm_lattice L, xtm_particles P, const xtm_track_opts* opts,
+                              void* stream, xtm_track_stats* stats) {
+  return guarded([&]() -> xtm_status {
+    if (!L || !P) return fail(XTM_E_ARG, "null handle");
+    if (!P->initialised) return fail(XTM_E_STATE, "particle set not initialised");
+    if (opts && (opts->record_buf || opts->use_graph))
+      return fail(XTM_E_ARG, "resuming retired particles takes no recorder and no graph");
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t n = P->n;
+    const int32_t horizon = P->turn;
+    std::vector<int32_t> st((size_t)n), at((size_t)n);
+    if (n > 0) {
+      HIP_TRY(hipMemcpyAsync(st.data(), P->a.state, n * sizeof(int32_t), hipMemcpyDeviceToHost, s),
+              "read states");
+      HIP_TRY(hipMemcpyAsync(at.data(), P->a.at_turn, n * sizeof(int32_t), hipMemcpyDeviceToHost,
+                             s),
+              "read turns");
+    }
+    HIP_TRY(hipStreamSynchronize(s), "synchronise");
+    // retired slots ordered by the turn they were retired at, then by slot
+    std::vector<std::pair<int32_t, int32_t>> ret;  // (turn, slot)
+    for (int64_t i = 0; i < n; ++i)
+      if (st[i] == 2) {
+        if (at[i] > horizon) return fail(XTM_E_STATE, "a retired particle is ahead of the set");
+        ret.push_back({at[i], (int32_t)i});
+      }
+    std::sort(ret.begin(), ret.end());
+    xtm_track_opts o{};
+    if (opts) o = *opts;
+    int64_t passes = 0;
+    int32_t launches = 0, variant = 0;
+    double ms = 0.0;
+    std::vector<int32_t> list;  // slots tracked together, ascending
+    size_t g = 0;
+    while (g < ret.size()) {
+      const int32_t t = ret[g].first;
+      // keep the resumed particles still alive, add this turn's group, in
+      // slot order
+      std::vector<int32_t> next;
+      for (int32_t p : list)
+        if (st[p] == 1) next.push_back(p);
+      for (; g < ret.size() && ret[g].first == t; ++g) {
+        st[ret[g].second] = 1;
+        next.push_back(ret[g].second);
+      }
+      std::sort(next.begin(), next.end());
+      list.swap(next);
+      HIP_TRY(hipMemcpyAsync(P->a.state, st.data(), n * sizeof(int32_t), hipMemcpyHostToDevice, s),
+              "write states");
+      HIP_TRY(hipMemcpyAsync(P->idx[P->cur], list.data(), list.size() * sizeof(int32_t),
+                             hipMemcpyHostToDevice, s),
+              "write alive list");
+      HIP_TRY(launch_iota(P->idx[P->cur], 0, P->ctrl, (int32_t)list.size(), t, s), "alive count");
+      P->turn = t;
+      P->alive_upper = (int64_t)list.size();
+      const int32_t until = g < ret.size() ? ret[g].first : horizon;
+      xtm_track_stats ts{};
+      xtm_status r = run_turns(L, P, until - t, &o, s, &ts, false);
+      if (r != XTM_OK) return r;
+      passes += ts.passes;
+      launches += ts.launches;
+      variant = ts.variant;
+      ms += ts.kernel_ms;
+      if (n > 0)
+        HIP_TRY(hipMemcpyAsync(st.data(), P->a.state, n * sizeof(int32_t), hipMemcpyDeviceToHost,
+                               s),
+                "read states");
+      HIP_TRY(hipStreamSynchronize(s), "synchronise");
+    }
+    // every particle still alive is now at the horizon: rebuild the set's list
+    HIP_TRY(launch_iota(P->idx[1 - P->cur], n, P->ctrl, (int32_t)n, horizon, s), "alive-list rebuild");
+    HIP_TRY(launch_epilogue(P->idx[1 - P->cur], P->idx[P->cur], nullptr, n > 0 ? n : 1, soa_of(P),
+                            P->ctrl, P->blockcnt, P->passes, 0, 0, 0, s),
+            "alive-list rebuild");
+    P->turn = horizon;
+    P->alive_upper = n;
+    int64_t alive = 0;
+    xtm_status r = read_alive(P, s, &alive, nullptr);
+    if (r != XTM_OK) return r;
+    if (stats) {
+      stats->passes = passes;
+      stats->alive = alive;
+      stats->launches = launches;
+      stats->variant = variant;
+      stats->kernel_ms = ms;
+    }
+    return XTM_OK;
   });
 }
 

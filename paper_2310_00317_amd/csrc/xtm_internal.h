@@ -220,5 +220,7 @@ hipError_t launch_feature_stats(const float* f, const int32_t* mask, int64_t n, 
                                 hipStream_t s);
 hipError_t launch_retire(SoA P, const int32_t* idx, const int32_t* ctrl, int64_t grid_upper,
                          const float* logit, float threshold, unsigned long long audit_seed,
-                         unsigned int audit_threshold, unsigned int* counts, hipStream_t s);
+                         unsigned int audit_threshold, unsigned int* counts, int32_t* audit_flags,
+                         hipStream_t s);
+hipError_t launch_rule_score(const float* f, int64_t n, float* score, hipStream_t s);
 }

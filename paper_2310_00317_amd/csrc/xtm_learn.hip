@@ -528,13 +528,15 @@ __global__ void __launch_bounds__(256) k_feature_stats(const float* __restrict__
 // Retire alive particles whose logit >= threshold unless audited: audited iff
 // the first Philox word of (key audit_seed, counter (pid_lo, pid_hi,
 // 0xFFFFFFFF, 0)) is below audit_threshold.  Retired particles get state 2.
-// counts[0] += retired, counts[1] += audited (alive, eligible by logit).
+// counts[0] += retired, counts[1] += audited (alive, eligible by logit);
+// audit_flags[p] = 1 for each audited particle when the array is given.
 __global__ void __launch_bounds__(256) k_retire(SoA P, const int32_t* __restrict__ idx,
                                                 const int32_t* __restrict__ ctrl,
                                                 const float* __restrict__ logit,
                                                 float threshold, unsigned long long audit_seed,
                                                 unsigned int audit_threshold,
-                                                unsigned int* __restrict__ counts) {
+                                                unsigned int* __restrict__ counts,
+                                                int32_t* __restrict__ audit_flags) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= ctrl[0]) return;
   const int32_t p = idx[i];
@@ -546,10 +548,22 @@ __global__ void __launch_bounds__(256) k_retire(SoA P, const int32_t* __restrict
                                          (unsigned int)(audit_seed >> 32));
   if (w.a < audit_threshold) {
     atomicAdd(&counts[1], 1u);
+    if (audit_flags) audit_flags[p] = 1;
     return;
   }
   P.state[p] = 2;
   atomicAdd(&counts[0], 1u);
+}
+
+// Score of the retire rule without the network: -max(f8, f9), the larger of
+// the two tune-diffusion features negated (a NaN feature gives a NaN score,
+// which no threshold retires).
+__global__ void __launch_bounds__(256) k_rule_score(const float* __restrict__ f, int64_t n,
+                                                    float* __restrict__ score) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float a = f[i * kIn + 8], b = f[i * kIn + 9];
+  score[i] = (a != a || b != b) ? __builtin_nanf("") : -(a > b ? a : b);
 }
 
 // Rows perm[start .. start+B-1] of (X, Y) into the contiguous batch (Xb, Yb).
@@ -664,10 +678,17 @@ hipError_t launch_feature_stats(const float* f, const int32_t* mask, int64_t n, 
 
 hipError_t launch_retire(SoA P, const int32_t* idx, const int32_t* ctrl, int64_t grid_upper,
                          const float* logit, float threshold, unsigned long long audit_seed,
-                         unsigned int audit_threshold, unsigned int* counts, hipStream_t s) {
+                         unsigned int audit_threshold, unsigned int* counts, int32_t* audit_flags,
+                         hipStream_t s) {
   if (grid_upper <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_retire, dim3((unsigned)((grid_upper + 255) / 256)), dim3(256), 0, s, P, idx,
-                     ctrl, logit, threshold, audit_seed, audit_threshold, counts);
+                     ctrl, logit, threshold, audit_seed, audit_threshold, counts, audit_flags);
+  return hipGetLastError();
+}
+
+hipError_t launch_rule_score(const float* f, int64_t n, float* score, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_rule_score, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, f, n, score);
   return hipGetLastError();
 }
 

@@ -25,7 +25,6 @@ function of the particle id), so the audit still judges every retirement.
 """
 from __future__ import annotations
 
-import math
 import time
 from dataclasses import dataclass
 
@@ -134,33 +133,21 @@ def rule_threshold(data: Collected, max_false_rate: float = 1e-3, val_frac: floa
     """The method without the network: retire iff the larger of the two
     tune-diffusion features (f8, f9) is below a threshold, chosen on the same
     held-out split with the same budget.  Returned as a threshold on the
-    score -max(f8, f9)."""
+    library's rule score (xtm_rule_score, -max(f8, f9))."""
     import torch
     rows = np.nonzero(data.alive_at_record)[0]
     rng = np.random.default_rng(seed)
     rows = rows[rng.permutation(len(rows))]
     val = rows[: max(1, int(len(rows) * val_frac))]
-    f = data.feat[torch.as_tensor(val, device=data.feat.device)]
-    score = (-torch.maximum(f[:, 8], f[:, 9])).contiguous()
-    tau, _, _ = P.select_threshold(score, torch.as_tensor(data.label[val], device=f.device),
+    f = data.feat[torch.as_tensor(val, device=data.feat.device)].contiguous()
+    tau, _, _ = P.select_threshold(P.rule_score(f),
+                                   torch.as_tensor(data.label[val], device=f.device),
                                    max_false_rate)
     return tau
 
 
 def rule_scores(feat):
-    import torch
-    return (-torch.maximum(feat[:, 8], feat[:, 9])).contiguous()
-
-
-def wilson_upper(k: int, n: int, z: float = 1.6449) -> float:
-    """One-sided 95 % Wilson upper bound of a binomial proportion."""
-    if n == 0:
-        return 1.0
-    p = k / n
-    d = 1 + z * z / n
-    c = p + z * z / (2 * n)
-    h = z * math.sqrt(p * (1 - p) / n + z * z / (4 * n * n))
-    return (c + h) / d
+    return P.rule_score(feat.contiguous())
 
 
 def scan(lat, ref, coords, horizon: int, twiss4=None, emit=None, r_aperture=None,
@@ -193,8 +180,7 @@ def scan(lat, ref, coords, horizon: int, twiss4=None, emit=None, r_aperture=None
     else:
         stages = max(1, min(int(stages), horizon // RECORD_TURNS))
         rec = torch.zeros((stages * RECORD_TURNS, 4, n), dtype=torch.float32, device="cuda")
-        audit_mask = np.zeros(n, dtype=bool)
-        snaps = []  # per stage: (retired slots, their coordinates, turn)
+        audit_flags = torch.zeros(n, dtype=torch.int32, device="cuda")
         for k in range(stages):
             P.track(lat, parts, RECORD_TURNS, record=rec, variant=variant)
             feat = P.features(rec[k * RECORD_TURNS:(k + 1) * RECORD_TURNS], twiss4, emit,
@@ -203,56 +189,27 @@ def scan(lat, ref, coords, horizon: int, twiss4=None, emit=None, r_aperture=None
                 score, tau = P.mlp_forward(predictor.theta, predictor.norm, feat), \
                     predictor.tau_at(k)
             else:
-                score, tau = rule_scores(feat), rule_tau
-            st_pre, _, _ = parts.losses()
-            retired, audited = P.retire(parts, score, tau, audit_seed, audit_fraction)
-            st_post, _, _ = parts.losses()
-            sc = score.cpu().numpy()
-            audit_mask |= (st_pre == 1) & (sc >= tau) & (st_post == 1)
-            if retired:
-                # device copy of the full state of the particles just retired,
-                # for the fallback to resume from exactly where they stopped
-                ret = np.nonzero((st_pre == 1) & (st_post == 2))[0]
-                ix = torch.as_tensor(ret, device="cuda")
-                snap = {f: getattr(parts, f)[ix].clone() for f in P.FLOAT_FIELDS + ("particle_id",)}
-                snaps.append((ret, snap, (k + 1) * RECORD_TURNS))
+                score, tau = P.rule_score(feat), rule_tau
+            retired, audited = P.retire(parts, score, tau, audit_seed, audit_fraction,
+                                        audit_flags=audit_flags)
             out["retired"] += retired
-            out["audited"] += audited
             out["stages"].append({"turn": (k + 1) * RECORD_TURNS, "tau": float(tau),
                                   "retired": retired, "audited": audited,
-                                  "tracked_after": int((st_post == 1).sum())})
+                                  "tracked_after": int(np.count_nonzero(parts.losses()[0] == 1))})
         del rec
         if tune_turns > 0:
             P.autotune(parts, lattice=lat, probe_turns=tune_turns)
         P.track(lat, parts, horizon - stages * RECORD_TURNS, variant=variant)
-        st_end, _, _ = parts.losses()
-        lost_audit = int(((st_end != 1) & audit_mask).sum())
-        out.update(audit_lost=lost_audit,
-                   audit_upper=wilson_upper(lost_audit, int(audit_mask.sum())))
-        if out["retired"] and out["audit_upper"] > fallback_rate:
-            # full-tracking fallback: each retired particle resumes from the
-            # turn it was retired at
-            resumed = []
-            for ret, snap, turn in snaps:
-                m = len(ret)
-                res = P.Particles(m, ref)
-                for f, v in snap.items():
-                    getattr(res, f)[:m] = v
-                res.state[:m] = 1
-                res.at_element[:m] = 0
-                res.at_turn[:m] = turn
-                res.reset(turn)
-                P.track(lat, res, horizon - turn, variant=variant)
-                resumed.append((ret,) + tuple(res.losses()))
+        v = P.audit_verdict(parts, audit_flags, fallback_rate)
+        out.update(audited=v["audited"], audit_lost=v["lost"], audit_upper=v["upper"])
+        if v["fallback"]:
+            # full-tracking fallback: every retired particle resumes from the
+            # turn it was retired at (inside the library)
             out["fallback"] = True
-            out["resumed"] = resumed
+            out["resumed_passes"], _ = P.resume_retired(lat, parts, variant=variant)
     torch.cuda.synchronize()
     out["wall_s"] = time.perf_counter() - t0
     st, at, ae = parts.losses()
-    if out.get("resumed"):
-        st, at, ae = st.copy(), at.copy(), ae.copy()
-        for ret, rs, ra, re in out["resumed"]:
-            st[ret], at[ret], ae[ret] = rs, ra, re
     out["state"], out["at_turn"], out["at_element"] = st, at, ae
     return out
 

@@ -124,3 +124,15 @@ def test_noalloc_gradient_checks_its_arguments_before_any_device_work(xtm):
         assert b"4096" in L.xtm_last_error()
     assert L.xtm_mlp_grad_noalloc(None, fake, fake, fake, 8, 1.0, fake, None, None) == -1
     assert L.xtm_mlp_grad_noalloc(fake, fake, fake, fake, 8, 1.0, None, None, None) == -1
+
+
+def test_audit_upper_bound_host_function_matches_oracle(oracle_mod):
+    """xtm_audit_upper_bound is host-only: checked against the oracle's
+    Wilson bound, and its argument checks."""
+    import paper_2310_00317_amd as P
+    for k, n in ((0, 0), (0, 1), (0, 100), (1, 100), (41, 27449), (7, 20), (20, 20)):
+        got = P.audit_upper_bound(k, n)
+        assert abs(got - oracle_mod.wilson_upper(k, n)) <= 1e-15 * max(1.0, got), (k, n)
+    for k, n in ((-1, 5), (6, 5), (0, -1)):
+        with pytest.raises(P.XtmError):
+            P.audit_upper_bound(k, n)

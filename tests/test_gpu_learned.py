@@ -301,6 +301,70 @@ def test_retire_infinite_threshold_is_plain_tracking(P):
         assert np.array_equal(ga[f], gb[f]), f
 
 
+def test_audit_flags_verdict_and_resume_through_the_abi(P, oracle_mod):
+    """Two decisions (turns 20 and 45) with audit flags, tracking to turn 120,
+    the audit's verdict against the oracle's, then the library's fallback:
+    every retired particle resumes from the turn it was retired at, and the
+    whole set ends bit for bit as plain tracking to turn 120."""
+    import torch
+    el = I.cfg1_lattice(rf_on=False)
+    c, _, _ = I.polar_grid(40, 50, 32.0, _twiss(), EMIT, delta=2.7e-4)
+    n = len(c)
+    lat = P.Lattice(el, REF)
+    a = P.Particles(n, REF).init(c, first_id=500)
+    plain = P.Particles(n, REF).init(c, first_id=500)
+    P.track(lat, plain, 120)
+    flags = torch.zeros(n, dtype=torch.int32, device="cuda")
+    rng = np.random.default_rng(31)
+    seed, frac = 0xABCDEF, 0.2
+    eligible = np.zeros(n, dtype=bool)
+    for t_dec, t_next in ((20, 45), (45, 120)):
+        P.track(lat, a, t_dec - a.turn)
+        st0, _, _ = a.losses()
+        logit = torch.tensor(rng.normal(size=n).astype(np.float32), device="cuda")
+        P.retire(a, logit, 0.3, seed, frac, audit_flags=flags)
+        eligible |= (st0 == 1) & (logit.cpu().numpy() >= 0.3)
+    P.track(lat, a, 120 - a.turn)
+    aud = oracle_mod.audit_mask(seed, np.arange(n) + 500, frac)
+    fl = flags.cpu().numpy()
+    assert np.array_equal(fl != 0, eligible & aud)
+    st, _, _ = a.losses()
+    assert (st == 2).sum() == (eligible & ~aud).sum() > 0
+    for rate in (1.0, 0.0):
+        v = P.audit_verdict(a, flags, rate)
+        o = oracle_mod.audit_verdict(st, fl, rate)
+        assert (v["audited"], v["lost"], v["fallback"]) == (o["audited"], o["lost"], o["fallback"])
+        assert abs(v["upper"] - o["upper"]) <= 1e-15
+    assert P.audit_verdict(a, flags, 0.0)["fallback"]
+    passes, alive = P.resume_retired(lat, a)
+    assert a.turn == 120 and passes > 0
+    ga, gp = a.to_numpy(), plain.to_numpy()
+    for f in ("x", "px", "y", "py", "zeta", "delta", "ptau", "rpp", "rvv", "state", "at_turn",
+              "at_element"):
+        assert np.array_equal(ga[f].view(np.int64) if ga[f].dtype.kind == "f" else ga[f],
+                              gp[f].view(np.int64) if gp[f].dtype.kind == "f" else gp[f]), f
+    assert alive == int((gp["state"] == 1).sum())
+    # the set goes on as one: 10 more turns equal plain tracking
+    P.track(lat, a, 10)
+    P.track(lat, plain, 10)
+    ga, gp = a.to_numpy(), plain.to_numpy()
+    for f in ("x", "state", "at_turn", "at_element"):
+        assert np.array_equal(ga[f], gp[f]), f
+
+
+def test_rule_score_matches_oracle(P, oracle_mod):
+    import torch
+    rng = np.random.default_rng(4)
+    f = rng.normal(size=(1000, 16)).astype(np.float32)
+    f[::97, 8] = np.nan
+    f[5::101, 9] = np.nan
+    got = P.rule_score(torch.tensor(f, device="cuda")).cpu().numpy()
+    exp = oracle_mod.rule_score(f)
+    assert np.array_equal(np.isnan(got), np.isnan(exp))
+    m = ~np.isnan(exp)
+    assert np.array_equal(got[m], exp[m])
+
+
 # ------------------------------------------------------------------ training loop
 def test_threshold_selection_matches_oracle(P, oracle_mod):
     import torch

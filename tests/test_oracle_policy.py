@@ -49,3 +49,44 @@ def test_threshold_definition_on_hand_cases():
     assert oracle.select_threshold(z, y, 0.25) == -1.0      # 1 lost of 5 = 0.2
     assert oracle.select_threshold(z, y, 0.3) == -1.0
     assert oracle.select_threshold(np.array([1.0]), np.array([0]), 0.5) == np.inf
+
+
+def test_wilson_upper_bound_against_scipy_and_closed_forms():
+    """The audit's bound: the upper end of Wilson's score interval at the
+    one-sided 95 % normal quantile, i.e. the upper end of scipy's two-sided
+    90 % Wilson interval; with no loss it is z^2 / (n + z^2)."""
+    from scipy.stats import binomtest, norm
+    z = norm.ppf(0.95)
+    assert abs(z - 1.6448536269514722) < 1e-15
+    for k, n in ((0, 1), (0, 100), (1, 100), (41, 27449), (7, 20), (20, 20), (3, 5000)):
+        ci = binomtest(k, n).proportion_ci(confidence_level=0.90, method="wilson")
+        assert abs(oracle.wilson_upper(k, n) - ci.high) <= 1e-13, (k, n)
+    for n in (1, 10, 1000, 10 ** 6):
+        assert abs(oracle.wilson_upper(0, n) - z * z / (n + z * z)) <= 1e-15
+    assert oracle.wilson_upper(0, 0) == 1.0
+    assert abs(oracle.wilson_upper(5, 5) - 1.0) <= 2e-16
+    # more losses, or the same fraction on fewer particles, never lower it
+    ups = [oracle.wilson_upper(k, 1000) for k in range(0, 50)]
+    assert all(b > a for a, b in zip(ups, ups[1:]))
+    assert oracle.wilson_upper(1, 100) > oracle.wilson_upper(10, 1000)
+
+
+def test_audit_verdict_by_hand():
+    st = np.array([1, 1, 0, -1, 2, 2, 1, 0])
+    fl = np.array([1, 0, 1, 1, 0, 0, 1, 0])
+    v = oracle.audit_verdict(st, fl, 0.5)
+    assert (v["audited"], v["lost"]) == (4, 2)
+    assert abs(v["upper"] - oracle.wilson_upper(2, 4)) == 0.0
+    assert v["fallback"] is (v["upper"] > 0.5)
+    assert oracle.audit_verdict(st, fl, 0.99)["fallback"] is False
+    # no retired particle: never a fallback, however bad the audit
+    assert oracle.audit_verdict(np.array([0, 0]), np.array([1, 1]), 0.0)["fallback"] is False
+
+
+def test_rule_score_by_hand():
+    f = np.zeros((3, 16), dtype=np.float32)
+    f[0, 8], f[0, 9] = -3.0, -5.0
+    f[1, 8], f[1, 9] = -7.0, -2.5
+    f[2, 8], f[2, 9] = np.nan, -1.0
+    s = oracle.rule_score(f)
+    assert s[0] == 3.0 and s[1] == 2.5 and np.isnan(s[2])
