@@ -574,6 +574,11 @@ def main():
     ap.add_argument("--autotune", action="store_true",
                     help="run the launch-plan autotuner before the warmup and track with its "
                          "pick (reported in config)")
+    ap.add_argument("--tune-probe", type=int, default=10,
+                    help="--autotune: turns of each probe")
+    ap.add_argument("--tune-warm", type=int, default=200,
+                    help="--autotune: turns the probe copy is tracked before the probes "
+                         "(past the scan's early losses)")
     ap.add_argument("--separate", action="store_true",
                     help="cfg3: track the variants one after another, each with its own "
                          "lattice and particle set, instead of one batched launch per chunk")
@@ -651,14 +656,17 @@ def main():
 
     plan = None
     if args.autotune:
-        # the autotuner times the candidate forms on a copy of the set for a
-        # few turns and keeps the fastest as the lattice's (or batch's) plan,
+        # the autotuner times the candidate plans (form, chunk length,
+        # compaction period) on a copy of the set, advanced past its first
+        # turns, and keeps the fastest as the lattice's (or batch's) plan,
         # which tracking then uses when no variant is forced
         probe = P.Particles(n, ref).init(coords_dev)
         if batched:
-            plan = P.autotune(probe, batch=batch, first_slot=first)
+            plan = P.autotune(probe, batch=batch, first_slot=first, probe_turns=args.tune_probe,
+                              warm_turns=args.tune_warm)
         else:
-            plan = P.autotune(probe, lattice=lat)
+            plan = P.autotune(probe, lattice=lat, probe_turns=args.tune_probe,
+                              warm_turns=args.tune_warm)
         torch.cuda.synchronize()
         del probe
     if args.warmup > 0:
@@ -700,6 +708,9 @@ def main():
     flops_per_pass = float(flops.sum() / n_tracked)
     key = (args.workload, n, tps, variant_ran, kernel_source_hash())
     traffic, traffic_src = MEASURED_TRAFFIC.get(key, (None, None))
+    if args.chunk or args.autotune or args.block:
+        # the counters were taken with the default launch shape
+        traffic, traffic_src = None, None
 
     out = {
         "metric": "particle-element passes/s (FP64); DA wall-clock learned vs plain at 0.1 sigma",
@@ -716,6 +727,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": desc, "n_particles": n, "n_elements": n_el,
                    **({"autotune_pick": {"variant": plan.variant, "block": plan.block,
+                                         "turns_per_chunk": plan.turns_per_chunk,
+                                         "compact_every": plan.compact_every,
                                          "probe_passes_per_s": plan.passes_per_s}}
                       if plan is not None else {}),
                    "turns": steps * tps, "alive_at_end": int(alive),

@@ -220,6 +220,9 @@ typedef struct xtm_track_opts {
                               entries untouched (caller-owned, caller-cleared).
                               Forward tracking with the default, 4 or per-line
                               kernels only */
+  int32_t compact_every;   /* compact the alive list after every this many chunks (and
+                              after the last); 0 = the plan's, else 1 */
+  int32_t pad;
 } xtm_track_opts;
 
 typedef struct xtm_track_stats {
@@ -435,23 +438,37 @@ xtm_status xtm_track_batched(xtm_batch b, xtm_particles p, const int64_t* first_
                              int32_t n_turns, const xtm_track_opts* opts, void* stream,
                              xtm_track_stats* stats);
 
-/* Launch-plan autotuner.  Times every candidate (each form of the per-line
-   kernel, variants 5..xtm_max_variant(), when the line has one, each with its
-   own workgroup size; variant 4 with blocks of 64, 128 and 256 lanes) for probe_turns turns on
-   a scratch copy of the set (the set itself is not advanced), keeps the
-   fastest as the plan of the lattice (or batch), and reports it.  Later
-   xtm_track / xtm_track_batched calls whose options leave both `variant`
-   and `block` at 0 use the plan.  Give exactly one of `lat` and `batch`
+/* Launch-plan autotuner.  Times candidate plans on a scratch copy of the
+   set (the set itself is not advanced), each for probe_turns turns through
+   the ordinary tracking path, and keeps the fastest as the plan of the
+   lattice (or batch).  The search runs in three stages: (1) every kernel
+   form (the per-line kernel's forms 5..xtm_max_variant() when the line has
+   one, each with its own workgroup size; the interpreter 4 with blocks of 64,
+   128 and 256 lanes) with automatic chunks compacted after each chunk;
+   (2) for that form, the turns per chunk K in {1, 4, 16, 64, 256, 1024} up to
+   probe_turns, besides the automatic length; (3) for that form and K, the
+   compaction period 2, 4 or 8 chunks besides 1.  With warm_turns > 0 the
+   copy is first tracked warm_turns turns (with the plan then in force, not
+   timed) and every probe starts from there: a dynamic-aperture scan loses
+   most of its lost particles in its first turns, and the probe should see
+   the alive count and loss rate of the long stretch the plan is for.  Later
+   xtm_track / xtm_track_batched calls use the plan's form and block when
+   their options leave both `variant` and `block` at 0, its K when
+   turns_per_chunk is 0 (reached by a ramp from one turn) and its period
+   when compact_every is 0.  Give exactly one of `lat` and `batch`
    (`first_slot` as for xtm_track_batched with a batch, else ignored).
-   Synchronises; allocates a scratch set of the same size. */
+   Synchronises; allocates one scratch set of the same size (two with
+   warm_turns). */
 typedef struct xtm_plan {
-  int32_t variant;      /* kernel variant chosen (4 or a per-line form) */
-  int32_t block;        /* lanes per workgroup chosen */
-  double passes_per_s;  /* its measured rate, chunk epilogues included */
+  int32_t variant;          /* kernel variant chosen (4 or a per-line form) */
+  int32_t block;            /* lanes per workgroup chosen */
+  double passes_per_s;      /* its measured rate, chunk epilogues included */
+  int32_t turns_per_chunk;  /* turns per chunk chosen, 0 = automatic */
+  int32_t compact_every;    /* compaction period chosen, in chunks */
 } xtm_plan;
 xtm_status xtm_autotune(xtm_lattice lat, xtm_batch batch, xtm_particles p,
-                        const int64_t* first_slot, int32_t probe_turns, void* stream,
-                        xtm_plan* out);
+                        const int64_t* first_slot, int32_t probe_turns, int32_t warm_turns,
+                        void* stream, xtm_plan* out);
 
 /* ---------------------------------------------------------------------------
    Learned early stop.  The paper cites machine-learned dynamic-aperture

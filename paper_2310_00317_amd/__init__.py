@@ -58,7 +58,8 @@ class TrackOpts(ctypes.Structure):
                 ("no_compact", ctypes.c_int32), ("use_graph", ctypes.c_int32),
                 ("time_kernels", ctypes.c_int32), ("variant", ctypes.c_int32),
                 ("radiation", ctypes.c_int32), ("record_turns", ctypes.c_int32),
-                ("rng_seed", ctypes.c_uint64), ("record_buf", ctypes.c_void_p)]
+                ("rng_seed", ctypes.c_uint64), ("record_buf", ctypes.c_void_p),
+                ("compact_every", ctypes.c_int32), ("pad", ctypes.c_int32)]
 
 
 class TrackStats(ctypes.Structure):
@@ -69,7 +70,8 @@ class TrackStats(ctypes.Structure):
 
 class Plan(ctypes.Structure):
     _fields_ = [("variant", ctypes.c_int32), ("block", ctypes.c_int32),
-                ("passes_per_s", ctypes.c_double)]
+                ("passes_per_s", ctypes.c_double), ("turns_per_chunk", ctypes.c_int32),
+                ("compact_every", ctypes.c_int32)]
 
 
 _lib = None
@@ -116,7 +118,7 @@ def lib() -> ctypes.CDLL:
             "xtm_batch_create": ([vp, i32, vp], i32),
             "xtm_batch_destroy": ([vp], i32),
             "xtm_track_batched": ([vp, vp, vp, i32, vp, vp, vp], i32),
-            "xtm_autotune": ([vp, vp, vp, vp, i32, vp, vp], i32),
+            "xtm_autotune": ([vp, vp, vp, vp, i32, i32, vp, vp], i32),
             "xtm_features": ([vp, i64, vp, ctypes.c_double, ctypes.c_double, vp, vp], i32),
             "xtm_feature_stats": ([vp, vp, i64, vp, vp], i32),
             "xtm_mlp_init": ([vp, ctypes.c_uint64, vp], i32),
@@ -306,19 +308,13 @@ def line_variants() -> list:
 def track(lattice: Lattice, particles: Particles, n_turns: int, turns_per_chunk: int = 0,
           block: int = 0, compact: bool = True, graph: bool = False, stats: bool = True,
           time_kernels: bool = False, variant: int = 0, radiation: int = 0, seed: int = 0,
-          stream=None, full_stats: bool = False, record=None):
+          stream=None, full_stats: bool = False, record=None, compact_every: int = 0):
     """Track ``n_turns`` forward.  With ``stats`` (synchronising) returns
     (passes, alive), or the whole TrackStats if ``full_stats``.  ``record``:
     a float32 cuda tensor [T, 4, n] that receives (x, px, y, py) at the start
     of absolute turns < T."""
-    rec_turns, rec_ptr = 0, None
-    if record is not None:
-        if tuple(record.shape[1:]) != (4, particles.n) or not record.is_contiguous():
-            raise ValueError("record must be a contiguous [T, 4, n] tensor")
-        rec_turns, rec_ptr = int(record.shape[0]), record.data_ptr()
-    o = TrackOpts(int(turns_per_chunk), int(block), 0 if compact else 1, 1 if graph else 0,
-                  1 if time_kernels else 0, int(variant), int(radiation), rec_turns, int(seed),
-                  rec_ptr)
+    o = _opts(turns_per_chunk, block, compact, graph, time_kernels, variant, radiation, seed,
+              record, particles.n, compact_every)
     s = TrackStats()
     check(lib().xtm_track(lattice.handle, particles.handle, int(n_turns), ctypes.byref(o),
                           _stream(stream), ctypes.byref(s) if (stats or full_stats) else None),
@@ -355,7 +351,7 @@ class Batch:
 
 
 def _opts(turns_per_chunk=0, block=0, compact=True, graph=False, time_kernels=False, variant=0,
-          radiation=0, seed=0, record=None, n=0):
+          radiation=0, seed=0, record=None, n=0, compact_every=0):
     rec_turns, rec_ptr = 0, None
     if record is not None:
         if tuple(record.shape[1:]) != (4, n) or not record.is_contiguous():
@@ -363,7 +359,7 @@ def _opts(turns_per_chunk=0, block=0, compact=True, graph=False, time_kernels=Fa
         rec_turns, rec_ptr = int(record.shape[0]), record.data_ptr()
     return TrackOpts(int(turns_per_chunk), int(block), 0 if compact else 1, 1 if graph else 0,
                      1 if time_kernels else 0, int(variant), int(radiation), rec_turns, int(seed),
-                     rec_ptr)
+                     rec_ptr, int(compact_every), 0)
 
 
 def track_batched(batch: Batch, particles: Particles, first_slot, n_turns: int,
@@ -380,13 +376,14 @@ def track_batched(batch: Batch, particles: Particles, first_slot, n_turns: int,
 
 
 def autotune(particles: Particles, lattice: Lattice = None, batch: Batch = None, first_slot=None,
-             probe_turns: int = 2, stream=None) -> Plan:
+             probe_turns: int = 2, warm_turns: int = 0, stream=None) -> Plan:
     fs = None if first_slot is None else np.ascontiguousarray(first_slot, dtype=np.int64)
     plan = Plan()
     check(lib().xtm_autotune(None if lattice is None else lattice.handle,
                              None if batch is None else batch.handle, particles.handle,
                              None if fs is None else fs.ctypes.data_as(ctypes.c_void_p),
-                             int(probe_turns), _stream(stream), ctypes.byref(plan)),
+                             int(probe_turns), int(warm_turns), _stream(stream),
+                             ctypes.byref(plan)),
           "xtm_autotune")
     return plan
 

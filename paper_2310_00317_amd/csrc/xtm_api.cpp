@@ -79,9 +79,10 @@ struct xtm_lattice_s {
   int32_t* bwd_seg_d = nullptr;
   // per-line kernels, compiled on first use
   xtm::LineKernel fwd_line[xtm::kLineStyles], bwd_line[xtm::kLineStyles];
-  // launch plan chosen by xtm_autotune (0 = none): used when the caller's
-  // options leave the kernel variant and block size at 0
-  int32_t plan_variant = 0, plan_block = 0;
+  // launch plan chosen by xtm_autotune (0 = none): kernel form and block
+  // used when the caller's options leave both at 0, turns per chunk and
+  // compaction period when the caller leaves those at 0
+  int32_t plan_variant = 0, plan_block = 0, plan_chunk = 0, plan_compact_every = 0;
   // the element descriptions of the sliced line (thick elements replaced by
   // their slices) and the user element of each
   std::vector<xtm_element_desc> desc_h;
@@ -102,6 +103,8 @@ struct xtm_batch_s {
   std::vector<int64_t> first_h;      // the partition last uploaded
   int32_t plan_block = 0;
   int32_t plan_variant = 0;
+  int32_t plan_chunk = 0;
+  int32_t plan_compact_every = 0;
   // batched per-line kernels (one-wave forms), built on first use when every
   // variant has the same element structure
   xtm::LineKernel line[xtm::kLineStyles];
@@ -109,7 +112,7 @@ struct xtm_batch_s {
 
 struct GraphKey {
   uint64_t owner;  // lattice or batch id
-  int32_t n_turns, chunk, block, variant, backward, compact, cur, rad_mode;
+  int32_t n_turns, chunk, block, variant, backward, compact, compact_every, cur, rad_mode;
   int64_t alive_upper;
   uint64_t seed;
   const float* rec;
@@ -118,7 +121,7 @@ struct GraphKey {
   bool operator==(const GraphKey& o) const {
     return owner == o.owner && n_turns == o.n_turns && chunk == o.chunk && block == o.block &&
            variant == o.variant && backward == o.backward && compact == o.compact &&
-           cur == o.cur && rad_mode == o.rad_mode && alive_upper == o.alive_upper &&
+           compact_every == o.compact_every && cur == o.cur && rad_mode == o.rad_mode && alive_upper == o.alive_upper &&
            seed == o.seed && rec == o.rec && rec_turns == o.rec_turns && ramp == o.ramp;
   }
 };
@@ -351,6 +354,7 @@ struct ChunkPlan {
   const LineKernel* line;  // variant 5
   const uint64_t* tab;
   int32_t n_turns, chunk, block, variant;
+  int32_t compact_every;  // compact the alive list after every this many chunks (and the last)
   bool backward, compact;
   bool ramp;  // chunk lengths 1, 2, 4, ... up to `chunk` (automatic chunking)
 };
@@ -372,6 +376,14 @@ std::vector<int32_t> chunk_sizes(const ChunkPlan& c) {
   return v;
 }
 
+// Whether the alive list is compacted after chunk j of n: every
+// compact_every chunks and after the last one.
+bool compacts_after(const ChunkPlan& c, size_t j, size_t n) {
+  if (!c.compact) return false;
+  const size_t every = c.compact_every > 1 ? (size_t)c.compact_every : 1;
+  return (j + 1) % every == 0 || j + 1 == n;
+}
+
 // Enqueue the whole chunk sequence on stream s: per chunk the tracking launch,
 // the epilogue (passes + compaction) and the device-side turn advance.  The
 // alive-list buffer alternates per compaction starting from `cur`.  Optional
@@ -385,9 +397,12 @@ hipError_t enqueue_chunks(xtm_lattice_s* L, xtm_particles_s* P, const ChunkPlan&
   kr.rec_n = (int32_t)P->n;
   *launches = 0;
   if (P->alive_upper <= 0) return c.n_turns > 0 ? launch_advance(P->ctrl, c.backward ? -c.n_turns : c.n_turns, s) : hipSuccess;
-  for (const int32_t k : chunk_sizes(c)) {
+  const std::vector<int32_t> sizes = chunk_sizes(c);
+  for (size_t j = 0; j < sizes.size(); ++j) {
+    const int32_t k = sizes[j];
+    const bool compact_now = compacts_after(c, j, sizes.size());
     int32_t* in = P->idx[cur];
-    int32_t* out = c.compact ? P->idx[1 - cur] : nullptr;
+    int32_t* out = compact_now ? P->idx[1 - cur] : nullptr;
     hipError_t e;
     if (ev) {
       hipEvent_t a, b;
@@ -431,20 +446,23 @@ hipError_t enqueue_chunks(xtm_lattice_s* L, xtm_particles_s* P, const ChunkPlan&
     }
     e = launch_advance(P->ctrl, c.backward ? -k : k, s);
     if (e != hipSuccess) return e;
-    if (c.compact) cur = 1 - cur;
+    if (compact_now) cur = 1 - cur;
   }
   return hipSuccess;
 }
 
 int32_t flips(const ChunkPlan& c) {
   if (!c.compact || c.n_turns <= 0) return 0;
-  return (int32_t)chunk_sizes(c).size();
+  const size_t n = chunk_sizes(c).size();
+  int32_t f = 0;
+  for (size_t j = 0; j < n; ++j) f += compacts_after(c, j, n) ? 1 : 0;
+  return f;
 }
 
 xtm_status run_graph(xtm_lattice_s* L, xtm_particles_s* P, const ChunkPlan& c, hipStream_t s,
                      int32_t* launches) {
   GraphKey key{c.batch ? c.batch->id : L->id, c.n_turns, c.chunk, c.block, c.variant, c.backward ? 1 : 0, c.compact ? 1 : 0,
-               P->cur, c.rad_mode, P->alive_upper, c.seed, c.rec, c.rec_turns, c.ramp ? 1 : 0};
+               c.compact_every, P->cur, c.rad_mode, P->alive_upper, c.seed, c.rec, c.rec_turns, c.ramp ? 1 : 0};
   for (const GraphEntry& g : P->graphs) {
     if (g.key == key) {
       HIP_TRY(hipGraphLaunch(g.exec, s), "graph launch");
@@ -543,9 +561,18 @@ xtm_status run_turns(xtm_lattice_s* L, xtm_particles_s* P, int32_t n_turns,
       c.variant = 4;
     }
   }
+  // turns per chunk: the caller's (a fixed length), else the plan's or the
+  // automatic target, reached by a ramp from one turn
+  const int32_t plan_chunk = B ? B->plan_chunk : L->plan_chunk;
   c.ramp = !(o && o->turns_per_chunk > 0);
-  c.chunk = (o && o->turns_per_chunk > 0) ? o->turns_per_chunk
-                                           : auto_chunk(P->alive_upper, L->n_el, n_turns);
+  c.chunk = (o && o->turns_per_chunk > 0)
+                ? o->turns_per_chunk
+                : (plan_chunk > 0 ? std::min(plan_chunk, std::max(n_turns, 1))
+                                  : auto_chunk(P->alive_upper, L->n_el, n_turns));
+  if (o && o->compact_every < 0) return fail(XTM_E_ARG, "compact_every must be >= 0");
+  const int32_t plan_every = B ? B->plan_compact_every : L->plan_compact_every;
+  c.compact_every = (o && o->compact_every > 0) ? o->compact_every
+                                                 : (plan_every > 0 ? plan_every : 1);
   if (c.chunk < 1) c.chunk = 1;
   if (L->n_el > 0 && (int64_t)c.chunk * L->n_el > INT32_MAX - 1)
     c.chunk = (int32_t)((INT32_MAX - 1) / L->n_el);
@@ -1070,10 +1097,11 @@ xtm_status copy_set(const xtm_particles_s* src, xtm_particles_s* dst, hipStream_
 }  // namespace
 
 xtm_status xtm_autotune(xtm_lattice L, xtm_batch B, xtm_particles P, const int64_t* first_slot,
-                        int32_t probe_turns, void* stream, xtm_plan* out) {
+                        int32_t probe_turns, int32_t warm_turns, void* stream, xtm_plan* out) {
   return guarded([&]() -> xtm_status {
     if ((!L && !B) || (L && B) || !P) return fail(XTM_E_ARG, "give one of lattice or batch, and a set");
     if (probe_turns < 1) return fail(XTM_E_ARG, "probe_turns must be >= 1");
+    if (warm_turns < 0) return fail(XTM_E_ARG, "warm_turns must be >= 0");
     if (!P->initialised) return fail(XTM_E_STATE, "particle set not initialised");
     hipStream_t s = (hipStream_t)stream;
     xtm_lattice_s* lat = B ? B->lats[0] : L;
@@ -1082,9 +1110,28 @@ xtm_status xtm_autotune(xtm_lattice L, xtm_batch B, xtm_particles P, const int64
       xtm_status st = set_partition(B, P, first_slot, s);
       if (st != XTM_OK) return st;
     }
-    Scratch sc;
+    int32_t& pv = B ? B->plan_variant : L->plan_variant;
+    int32_t& pb = B ? B->plan_block : L->plan_block;
+    int32_t& pk = B ? B->plan_chunk : L->plan_chunk;
+    int32_t& pc = B ? B->plan_compact_every : L->plan_compact_every;
+    // the probes start from `base`: the set itself, or a copy of it tracked
+    // warm_turns turns further (past the losses of its first turns, so the
+    // probe sees the alive count and loss rate of the stretch it plans for)
+    Scratch base_sc, sc;
     xtm_status st = make_scratch(P, &sc);
     if (st != XTM_OK) return st;
+    const xtm_particles_s* base = P;
+    if (warm_turns > 0) {
+      st = make_scratch(P, &base_sc);
+      if (st == XTM_OK) st = copy_set(P, base_sc.P, s);
+      if (st == XTM_OK) st = run_turns(lat, base_sc.P, warm_turns, nullptr, s, nullptr, false, B);
+      if (st == XTM_OK) {
+        int64_t alive = 0;
+        st = read_alive(base_sc.P, s, &alive, nullptr);
+      }
+      if (st != XTM_OK) return st;
+      base = base_sc.P;
+    }
     std::vector<int32_t> variants;
     if (lat->n_el > 0) {
       std::vector<const std::vector<uint64_t>*> tabs;
@@ -1104,57 +1151,78 @@ xtm_status xtm_autotune(xtm_lattice L, xtm_batch B, xtm_particles P, const int64
       }
     }
     variants.push_back(4);
-    const int32_t blocks[3] = {64, 128, 256};
-    xtm_plan best{};
-    double best_rate = -1.0;
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0), "event");
     HIP_TRY(hipEventCreate(&e1), "event");
+    // one candidate plan: set it on the lattice (or batch), run the probe
+    // through the plain tracking path (as later calls will), untimed then timed
+    auto probe = [&](int32_t v, int32_t blk, int32_t k, int32_t every, double* rate) -> xtm_status {
+      pv = v;
+      pb = blk;
+      pk = k;
+      pc = every;
+      for (int rep = 0; rep < 2; ++rep) {
+        xtm_status r = copy_set(base, sc.P, s);
+        if (r != XTM_OK) return r;
+        if (hipEventRecord(e0, s) != hipSuccess) return fail(XTM_E_HIP, "event");
+        r = run_turns(lat, sc.P, probe_turns, nullptr, s, nullptr, false, B);
+        if (r != XTM_OK) return r;
+        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess)
+          return fail(XTM_E_HIP, "event");
+        int64_t alive = 0, passes = 0;
+        r = read_alive(sc.P, s, &alive, &passes);
+        if (r != XTM_OK) return r;
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, e0, e1);
+        *rate = ms > 0 ? (double)passes / (ms * 1e-3) : 0.0;
+      }
+      return XTM_OK;
+    };
+    xtm_plan best{};
+    double best_rate = -1.0;
+    auto consider = [&](int32_t v, int32_t blk, int32_t k, int32_t every) -> xtm_status {
+      double rate = 0.0;
+      xtm_status r = probe(v, blk, k, every, &rate);
+      if (r == XTM_OK && rate > best_rate) {
+        best_rate = rate;
+        best = xtm_plan{v, blk, rate, k, every};
+      }
+      return r;
+    };
+    // 1. kernel form and block, automatic chunks compacted after each
+    const int32_t blocks[3] = {64, 128, 256};
     for (int32_t v : variants) {
       for (int32_t blk : blocks) {
         if (v >= 5 && blk != line_block(v - 5)) continue;  // the per-line kernels' fixed shape
-        xtm_track_opts o{};
-        o.variant = v;
-        o.block = blk;
-        // one untimed run (first use), then the timed one
-        for (int rep = 0; rep < 2 && st == XTM_OK; ++rep) {
-          st = copy_set(P, sc.P, s);
-          if (st != XTM_OK) break;
-          if (hipEventRecord(e0, s) != hipSuccess) { st = fail(XTM_E_HIP, "event"); break; }
-          st = run_turns(lat, sc.P, probe_turns, &o, s, nullptr, false, B);
-          if (st != XTM_OK) break;
-          if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
-            st = fail(XTM_E_HIP, "event");
-            break;
-          }
-          int64_t alive = 0, passes = 0;
-          st = read_alive(sc.P, s, &alive, &passes);
-          float ms = 0.f;
-          hipEventElapsedTime(&ms, e0, e1);
-          if (rep == 1 && st == XTM_OK) {
-            const double rate = ms > 0 ? (double)passes / (ms * 1e-3) : 0.0;
-            if (rate > best_rate) {
-              best_rate = rate;
-              best.variant = v;
-              best.block = blk;
-              best.passes_per_s = rate;
-            }
-          }
-        }
-        if (st != XTM_OK) break;
+        if ((st = consider(v, blk, 0, 1)) != XTM_OK) break;
       }
       if (st != XTM_OK) break;
     }
+    // 2. turns per chunk for that form (0 = automatic), up to the probe length
+    if (st == XTM_OK) {
+      const xtm_plan f = best;
+      for (int32_t k : {1, 4, 16, 64, 256, 1024}) {
+        if (k > probe_turns) break;
+        if ((st = consider(f.variant, f.block, k, 1)) != XTM_OK) break;
+      }
+    }
+    // 3. compaction period for that form and chunk length
+    if (st == XTM_OK) {
+      const xtm_plan f = best;
+      for (int32_t every : {2, 4, 8}) {
+        if ((st = consider(f.variant, f.block, f.turns_per_chunk, every)) != XTM_OK) break;
+      }
+    }
     hipEventDestroy(e0);
     hipEventDestroy(e1);
-    if (st != XTM_OK) return st;
-    if (B) {
-      B->plan_variant = best.variant;
-      B->plan_block = best.block;
-    } else {
-      L->plan_variant = best.variant;
-      L->plan_block = best.block;
+    if (st != XTM_OK) {
+      pv = pb = pk = pc = 0;
+      return st;
     }
+    pv = best.variant;
+    pb = best.block;
+    pk = best.turns_per_chunk;
+    pc = best.compact_every;
     if (out) *out = best;
     return XTM_OK;
   });

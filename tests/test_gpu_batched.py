@@ -126,6 +126,51 @@ def test_autotune_leaves_set_and_results_unchanged(P):
         assert np.array_equal(ga[f], gb[f]), f
 
 
+def test_autotune_searches_chunk_length_and_compaction_period(P):
+    """With a warm-up the probes start past the first turns' losses; the plan
+    carries a chunk length and a compaction period, and tracking under it
+    equals tracking with the defaults bit for bit."""
+    el = I.cfg1_lattice()
+    c = I.gaussian_particles(6000, 78)
+    c[:2000, [0, 2]] *= 16.0            # a third lost within a few dozen turns
+    lat = P.Lattice(el, REF)
+    a = P.Particles(len(c), REF).init(c)
+    plan = P.autotune(a, lattice=lat, probe_turns=20, warm_turns=10)
+    assert plan.turns_per_chunk in (0, 1, 4, 16) and plan.compact_every in (1, 2, 4, 8)
+    assert plan.passes_per_s > 0 and a.turn == 0
+    b = P.Particles(len(c), REF).init(c)
+    pa = P.track(lat, a, 150)                              # the plan
+    pb = P.track(lat, b, 150, variant=10, turns_per_chunk=0, compact_every=1)
+    ga, gb = a.to_numpy(), b.to_numpy()
+    assert pa == pb
+    for f in FIELDS:
+        assert np.array_equal(ga[f], gb[f]), f
+
+
+@pytest.mark.parametrize("variant", [4, 10, 13])
+def test_compaction_period_gives_the_same_results(P, variant):
+    """Compacting the alive list only every few chunks (lost particles stay in
+    the list in between) changes no result, eager or replayed as a graph."""
+    el = I.cfg1_lattice()
+    c = I.gaussian_particles(3000, 79)
+    c[::3, [0, 2]] *= 16.0
+    lat = P.Lattice(el, REF)
+    ref_set = P.Particles(len(c), REF).init(c)
+    pr = P.track(lat, ref_set, 60, variant=variant, turns_per_chunk=3)
+    for every, graph in ((3, False), (7, False), (3, True)):
+        x = P.Particles(len(c), REF).init(c)
+        px = P.track(lat, x, 60, variant=variant, turns_per_chunk=3, compact_every=every,
+                     graph=graph)
+        assert px == pr, (every, graph)
+        gx, gr = x.to_numpy(), ref_set.to_numpy()
+        for f in FIELDS:
+            assert np.array_equal(gx[f], gr[f]), (every, graph, f)
+        # the set goes on as one after the period's last compaction
+        alive_after = P.track(lat, x, 5, variant=variant)[1]
+        fresh = P.Particles(len(c), REF).init(c)
+        assert alive_after == P.track(lat, fresh, 65, variant=variant)[1]
+
+
 def test_autotune_batch(P):
     counts = [200, 0, 500]
     els, coords = _variants(counts)
