@@ -119,7 +119,7 @@ def element_bytes(el) -> np.ndarray:
     return b
 
 
-def workload(name: str, n_override: int | None):
+def workload(name: str, n_override: int | None, radiation: int = 2):
     from paper_2310_00317_amd import inputs as I
     if name == "cfg2":
         el = I.cfg2_lattice()
@@ -144,7 +144,10 @@ def workload(name: str, n_override: int | None):
         el = I.cfg5_lattice()
         c = I.cfg5_particles(n_override or 1_000_000)
         desc = (f"electron ring, 20,000 thin elements (bends with radiation length, 8 RF), "
-                f"{len(c)} electrons at 45.6 GeV, mean + quantum radiation (Philox deviates)")
+                f"{len(c)} electrons at 45.6 GeV, " +
+                ("photon-by-photon radiation (Poisson photon counts, universal spectrum, "
+                 "Philox deviates)" if radiation == 3 else
+                 "mean + quantum radiation (Philox deviates)"))
         return el, c, I.ELECTRON_45GEV6, desc, 10, 2
     if name == "cfg3":
         counts = I.cfg3_counts()
@@ -583,11 +586,15 @@ def main():
                     help="cfg3: track the variants one after another, each with its own "
                          "lattice and particle set, instead of one batched launch per chunk")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--radiation", type=int, default=2, choices=[1, 2, 3],
+                    help="cfg5: 1 mean loss, 2 mean + Gaussian quantum excitation, "
+                         "3 photon by photon")
     ap.add_argument("--sat-turns", type=int, default=1000,
                     help="default workload: turns of the 2^20-particle FODO leg (0 = skip)")
     ap.add_argument("--cpu-sample-every", type=int, default=100)
     ap.add_argument("--cpu-turns", type=int, default=None,
-                    help="turns of the CPU oracle sample (default 1500; 150 with radiation)")
+                    help="turns of the CPU oracle sample (default 1500; 150 with radiation, "
+                         "50 photon by photon)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -616,7 +623,7 @@ def main():
         return twiss_bench(args)
     if args.workload == "cfg3" and args.separate:
         return cfg3_separate(args)
-    el, coords, ref, desc, tps_default, steps_default = workload(args.workload, args.particles)
+    el, coords, ref, desc, tps_default, steps_default = workload(args.workload, args.particles, args.radiation)
     tps = args.turns_per_step or tps_default
     steps = args.steps if args.steps is not None else steps_default
     batched = args.workload == "cfg3"
@@ -639,7 +646,7 @@ def main():
         lat = P.Lattice(el, ref)
     n_el_tracked = 0 if batched else lat.n_elements
     coords_dev = torch.from_numpy(np.ascontiguousarray(coords)).to("cuda")
-    extra = dict(radiation=2, seed=20231002) if args.workload == "cfg5" else {}
+    extra = dict(radiation=args.radiation, seed=20231002) if args.workload == "cfg5" else {}
 
     if args.per_element and (batched or extra):
         raise SystemExit("--per-element: single-lattice workloads without radiation only")
@@ -741,7 +748,7 @@ def main():
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a sample", file=sys.stderr, flush=True)
         if args.cpu_turns is None:
-            args.cpu_turns = 150 if extra else 1500
+            args.cpu_turns = (50 if args.radiation == 3 else 150) if extra else 1500
         if batched:
             out["cpu_baseline"] = cpu_baseline(el[0], coords[: counts[0]], ref,
                                                args.cpu_sample_every, args.cpu_turns)

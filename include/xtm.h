@@ -208,7 +208,8 @@ typedef struct xtm_track_opts {
                               XTM_E_UNSUPPORTED if it cannot be built */
   int32_t radiation;       /* synchrotron radiation in multipoles with length > 0:
                               0 off, 1 mean energy loss, 2 mean + quantum excitation
-                              (Gaussian, see below); forward tracking with the
+                              (Gaussian, see below), 3 photon by photon (see
+                              xtm_photon_table); forward tracking with the
                               default, 4 or per-line kernels only */
   int32_t record_turns;    /* with record_buf: record the start of turns 0 .. record_turns-1 */
   uint64_t rng_seed;       /* key of the quantum-excitation deviates */
@@ -411,6 +412,27 @@ xtm_status xtm_get_losses(xtm_particles p, int32_t* h_state, int32_t* h_at_turn,
    Stream-ordered. */
 xtm_status xtm_philox4x32_10(uint64_t seed, const uint32_t ctr0[4], int64_t n_blocks,
                              uint32_t* d_out, void* stream);
+
+/* Photon-by-photon radiation (radiation = 3; paper section "Synchrotron
+   radiation models and compensation": the quantum model emits individual
+   photons).  After the kick of a multipole of radiation length Lr > 0, with
+   h = |k| rpp / Lr and gamma = gamma0 (1 + beta0 ptau): photons arrive as a
+   Poisson process of mean count nbar = (5/(2 sqrt 3)) (r m / hbar_c) gamma h Lr;
+   photon j (j = 0, 1, ...; at most 255) uses Philox4x32-10 block (key seed,
+   counter (pid_lo, pid_hi, turn, element * 256 + j)): its uniforms u1, u2
+   (words 0,1 and 2,3, as for the Gaussian model) give the arrival
+   t_j = t_{j-1} - ln u1 (t_{-1} = 0; emission stops at the first t_j > nbar)
+   and the energy x_j u_c, u_c = (3/2) hbar_c gamma^3 h, x_j = g^3 where g
+   interpolates this table linearly at s = -ln u2: h_out[i] = g(i / 64), the
+   cube root of the photon energy (in units of u_c) exceeded with probability
+   exp(-i/64) under the universal synchrotron photon-number spectrum
+   3/(5 pi) int_x^inf K_{5/3}(t) dt, each value rounded to single precision.
+   The loss sum_j x_j u_c is taken from ptau at once (delta, rpp, rvv follow;
+   px, py keep their angles); its mean and variance are those of the mean and
+   Gaussian models.  Host only; n must be XTM_PHOTON_TABLE_NODES; the table is
+   computed once per process (a fraction of a second). */
+#define XTM_PHOTON_TABLE_NODES 2433
+xtm_status xtm_photon_table(double* h_out, int32_t n);
 
 /* ---------------------------------------------------------------------------
    Batched tracking of lattice variants (e.g. the same machine under different

@@ -195,9 +195,12 @@ def track(elements, ref, parts: Particles, n_turns: int, nthreads: int = 0,
           radiation: int = 0, seed: int = 0) -> int:
     """Forward tracking in place from turn ``parts.turn``; returns passes.
     radiation: 0 off, 1 mean energy loss, 2 mean + Gaussian quantum excitation
-    (Philox stream keyed by ``seed``, counter (particle id, turn, element))."""
+    (Philox stream keyed by ``seed``, counter (particle id, turn, element)),
+    3 photon by photon (the spectrum table of ``oracle.photons``)."""
     el = _els(elements)
     r = _ref3(ref)
+    if radiation == 3:
+        _set_photon_table()
     s = parts._struct()
     passes = lib().oracle_track_rad(el.ctypes.data_as(ctypes.c_void_p), ctypes.c_int32(len(el)),
                                     r.ctypes.data_as(ctypes.c_void_p), ctypes.byref(s),
@@ -208,6 +211,20 @@ def track(elements, ref, parts: Particles, n_turns: int, nthreads: int = 0,
         raise ValueError("oracle_track rejected its input (code %d)" % passes)
     parts.turn += n_turns
     return int(passes)
+
+
+_PHOTON_TABLE_SET = False
+
+
+def _set_photon_table():
+    global _PHOTON_TABLE_SET
+    if not _PHOTON_TABLE_SET:
+        from . import photons
+        g = np.ascontiguousarray(photons.table())
+        if lib().oracle_set_photon_table(g.ctypes.data_as(ctypes.c_void_p),
+                                         ctypes.c_int32(len(g))) != 0:
+            raise RuntimeError("oracle_set_photon_table failed")
+        _PHOTON_TABLE_SET = True
 
 
 def track_backward(elements, ref, parts: Particles, n_turns: int, nthreads: int = 0) -> int:

@@ -326,6 +326,9 @@ static int inside(const orc_pt* q, const orc_elem* e) {
 #define O_M_ELECTRON_EV 0.51099895000e6
 #define O_HBAR_C_EVM 197.3269804e-9
 
+static void radiate_photons(orc_pt* q, double fkx, double fky, double Lr, const orc_ref* r,
+                            uint64_t seed, int64_t pid, int32_t turn, int32_t element);
+
 static void radiate(orc_pt* q, double fkx, double fky, double Lr, const orc_ref* r, int mode,
                     double g) {
   double rclass = O_R_ELECTRON * (O_M_ELECTRON_EV / r->mass0) * r->charge0 * r->charge0;
@@ -456,7 +459,7 @@ int64_t oracle_track(const orc_elem* el, int32_t n_el, const double ref3[3], orc
 int64_t oracle_track_rad(const orc_elem* el, int32_t n_el, const double ref3[3], orc_parts* P,
                          int32_t t0, int32_t n_turns, int32_t nthreads, int32_t radiation,
                          uint64_t seed) {
-  if (n_turns < 0 || n_el < 0 || radiation < 0 || radiation > 2) return -1;
+  if (n_turns < 0 || n_el < 0 || radiation < 0 || radiation > 3) return -1;
   if (validate(el, n_el)) return -2;
   orc_ref r = make_ref(ref3);
   orc_coef* c = build_coefs(el, n_el);
@@ -475,7 +478,9 @@ int64_t oracle_track_rad(const orc_elem* el, int32_t n_el, const double ref3[3],
         ++passes;
         double fkx, fky;
         st = apply(&q, &el[e], &c[e], &r, 1.0, &fkx, &fky);
-        if (st == 1 && radiation && el[e].type == O_MULT && el[e].length > 0.0) {
+        if (st == 1 && radiation == 3 && el[e].type == O_MULT && el[e].length > 0.0) {
+          radiate_photons(&q, fkx, fky, el[e].length, &r, seed, P->pid[i], t, e);
+        } else if (st == 1 && radiation && el[e].type == O_MULT && el[e].length > 0.0) {
           double g = radiation == 2 ? oracle_gauss_at(seed, P->pid[i], t, e, 0) : 0.0;
           radiate(&q, fkx, fky, el[e].length, &r, radiation, g);
         }
@@ -649,6 +654,76 @@ double oracle_gauss_at(uint64_t seed, int64_t pid, int32_t turn, int32_t element
   uint32_t w[4];
   oracle_philox4x32_10(ctr, key, w);
   return oracle_gauss(w);
+}
+
+/* ------------------------------------------------ photon-by-photon emission */
+
+/* The quantum model as individual photons (paper section "Synchrotron
+   radiation models and compensation").  Along a radiating multipole of
+   length Lr a particle with gamma = gamma0 (1 + beta0 ptau) and curvature
+   h = |field kick| rpp / Lr emits photons as a Poisson process: the mean
+   count is alpha q^2 times 5/(2 sqrt 3) gamma per radian of bending, i.e.
+   nbar = 5/(2 sqrt 3) (r m / hbar_c) gamma h Lr (r m / hbar_c = alpha q^2).
+   Photon j uses the Philox block of counter (pid_lo, pid_hi, turn,
+   element * 256 + j): the uniform of words 0,1 extends the arrival time by an
+   exponential spacing, t_j = t_{j-1} - ln u, and the photon exists while
+   t_j <= nbar (at most 255 photons); the uniform of words 2,3 gives its
+   energy x u_c, u_c = (3/2) hbar_c gamma^3 h, through the sampling table of
+   the spectrum's inverse (oracle/photons.py): x = g^3, g interpolated
+   linearly at s = -ln u between the tabulated g(i/64).  The photons' total
+   energy leaves ptau at once; delta, rpp, rvv follow and px, py keep their
+   angles, as in the mean model. */
+static double* o_photon_g = NULL;
+static int32_t o_photon_n = 0;
+
+int oracle_set_photon_table(const double* g, int32_t n) {
+  if (n < 2) return -1;
+  double* t = (double*)malloc((size_t)n * sizeof(double));
+  if (!t) return -1;
+  memcpy(t, g, (size_t)n * sizeof(double));
+  free(o_photon_g);
+  o_photon_g = t;
+  o_photon_n = n;
+  return 0;
+}
+
+static double photon_energy(double s) {
+  double v = s * 64.0;
+  int32_t i = (int32_t)v;
+  if (i > o_photon_n - 2) i = o_photon_n - 2;
+  if (i < 0) i = 0;
+  double f = v - (double)i;
+  double a = o_photon_g[i], b = o_photon_g[i + 1];
+  double g = fma(f, b - a, a);
+  return g * g * g;
+}
+
+static void radiate_photons(orc_pt* q, double fkx, double fky, double Lr, const orc_ref* r,
+                            uint64_t seed, int64_t pid, int32_t turn, int32_t element) {
+  double rclass = O_R_ELECTRON * (O_M_ELECTRON_EV / r->mass0) * r->charge0 * r->charge0;
+  double h = sqrt(fkx * fkx + fky * fky) * q->rpp / Lr;
+  double gam = r->gamma0 * (1.0 + r->beta0 * q->ptau);
+  double nbar = 5.0 / (2.0 * sqrt(3.0)) * rclass * r->mass0 / O_HBAR_C_EVM * gam * h * Lr;
+  uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+  double t = 0.0, sum = 0.0;
+  for (uint32_t j = 0; j < 256u; ++j) {
+    uint32_t ctr[4] = {(uint32_t)(uint64_t)pid, (uint32_t)((uint64_t)pid >> 32), (uint32_t)turn,
+                       (uint32_t)element * 256u + j};
+    uint32_t w[4];
+    oracle_philox4x32_10(ctr, key, w);
+    t = t - oracle_log(oracle_uniform(w[0], w[1]));
+    if (!(t <= nbar)) break;
+    sum = sum + photon_energy(-oracle_log(oracle_uniform(w[2], w[3])));
+  }
+  if (sum == 0.0) return;
+  double g3 = gam * gam * gam;
+  double dE = 1.5 * O_HBAR_C_EVM * g3 * h * sum;
+  double opd_old = 1.0 + q->delta;
+  q->ptau = q->ptau - dE / r->p0c;
+  set_from_ptau(q, r->beta0);
+  double f = (1.0 + q->delta) / opd_old;
+  q->px = q->px * f;
+  q->py = q->py * f;
 }
 
 /* the four Philox constants as used above: multipliers M0, M1 and the Weyl

@@ -134,6 +134,7 @@ def lib() -> ctypes.CDLL:
             "xtm_retire": ([vp, vp, ctypes.c_float, ctypes.c_uint64, ctypes.c_double, vp, vp, vp,
                             vp], i32),
             "xtm_rule_score": ([vp, i64, vp, vp], i32),
+            "xtm_photon_table": ([vp, i32], i32),
             "xtm_audit_upper_bound": ([i64, i64, vp], i32),
             "xtm_audit_verdict": ([vp, vp, ctypes.c_double, vp, vp, vp, vp, vp], i32),
             "xtm_resume_retired": ([vp, vp, vp, vp, vp], i32),
@@ -620,6 +621,17 @@ def rule_score(feat, stream=None):
     out = torch.empty(max(n, 1), dtype=torch.float32, device=feat.device)
     check(lib().xtm_rule_score(_p(feat), n, _p(out), _stream(stream)), "xtm_rule_score")
     return out[:n]
+
+
+PHOTON_TABLE_NODES = 2433
+
+
+def photon_table() -> np.ndarray:
+    """The library's inverse photon spectrum (xtm_photon_table), host copy."""
+    out = np.zeros(PHOTON_TABLE_NODES, dtype=np.float64)
+    check(lib().xtm_photon_table(out.ctypes.data_as(ctypes.c_void_p), PHOTON_TABLE_NODES),
+          "xtm_photon_table")
+    return out
 
 
 def audit_upper_bound(n_lost: int, n_audited: int) -> float:

@@ -310,6 +310,9 @@ KernelRef kref(const RefQ& r, int32_t rad_mode = 0, uint64_t seed = 0) {
   const double rclass = kRElectron * (kMElectronEV / r.mass0) * r.charge0 * r.charge0;
   k.c_mean = 2.0 / 3.0 * rclass * r.mass0;
   k.c_quant = 55.0 / (24.0 * std::sqrt(3.0)) * rclass * r.mass0 * kHbarCEVM;
+  k.c_nphot = 5.0 / (2.0 * std::sqrt(3.0)) * rclass * r.mass0 / kHbarCEVM;
+  k.c_ucrit = 1.5 * kHbarCEVM;
+  k.photon_table = nullptr;
   k.p0c = r.p0c;
   k.seed = seed;
   k.rad_mode = rad_mode;
@@ -349,6 +352,7 @@ struct ChunkPlan {
   const xtm_batch_s* batch;  // batched tracking, or null
   int32_t rad_mode;
   uint64_t seed;
+  const double* photon_table;  // device inverse photon spectrum (radiation 3)
   float* rec;
   int32_t rec_turns;
   const LineKernel* line;  // variant 5
@@ -392,6 +396,7 @@ hipError_t enqueue_chunks(xtm_lattice_s* L, xtm_particles_s* P, const ChunkPlan&
                           hipStream_t s, std::vector<hipEvent_t>* ev, int32_t* launches) {
   const SoA soa = soa_of(P);
   KernelRef kr = kref(L->ref, c.rad_mode, c.seed);
+  kr.photon_table = c.photon_table;
   kr.rec = c.rec;
   kr.rec_turns = c.rec_turns;
   kr.rec_n = (int32_t)P->n;
@@ -516,7 +521,9 @@ xtm_status run_turns(xtm_lattice_s* L, xtm_particles_s* P, int32_t n_turns,
   c.rec_turns = (o && o->record_buf) ? o->record_turns : 0;
   if (c.rec && (c.rec_turns < 0 || backward))
     return fail(XTM_E_ARG, "the recorder needs record_turns >= 0 and forward tracking");
-  if (c.rad_mode < 0 || c.rad_mode > 2) return fail(XTM_E_ARG, "radiation must be 0, 1 or 2");
+  if (c.rad_mode < 0 || c.rad_mode > 3) return fail(XTM_E_ARG, "radiation must be 0, 1, 2 or 3");
+  c.photon_table = nullptr;
+  if (c.rad_mode == 3) HIP_TRY(photon_table_device(&c.photon_table), "photon spectrum table");
   if (c.rad_mode && backward) return fail(XTM_E_ARG, "backward tracking with radiation is undefined");
   const bool use_plan = !(o && (o->block || o->variant));
   const int32_t plan_block = B ? B->plan_block : L->plan_block;
@@ -1521,6 +1528,16 @@ xtm_status xtm_retire(xtm_particles P, const float* d_logit, float logit_thresho
     if (h_audited) *h_audited = hc[1];
     int64_t alive = 0;
     return read_alive(P, s, &alive, nullptr);
+  });
+}
+
+xtm_status xtm_photon_table(double* h_out, int32_t n) {
+  return guarded([&]() -> xtm_status {
+    if (!h_out || n != kPhotonTableNodes)
+      return fail(XTM_E_ARG, "need an output of XTM_PHOTON_TABLE_NODES values");
+    const std::vector<double>& t = photon_table_host();
+    std::copy(t.begin(), t.end(), h_out);
+    return XTM_OK;
   });
 }
 

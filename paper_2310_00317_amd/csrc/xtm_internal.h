@@ -54,12 +54,24 @@ struct KernelRef {
   double c_quant;  // 55/(24 sqrt 3) r m hbar_c      [eV^2 m^2]
   double p0c;
   unsigned long long seed;
-  int32_t rad_mode;  // 0 off, 1 mean, 2 mean + quantum
+  int32_t rad_mode;  // 0 off, 1 mean, 2 mean + quantum (Gaussian), 3 photon by photon
   int32_t pad;
   float* rec;          // early-turn recorder [rec_turns][4][rec_n] (x, px, y, py) or null
   int32_t rec_turns;   // record the start of absolute turns 0 .. rec_turns-1
   int32_t rec_n;       // particles in the set (record stride)
+  const double* photon_table;  // inverse photon spectrum on the device (mode 3), or null
+  double c_nphot;      // 5/(2 sqrt 3) r m / hbar_c: mean photon count per gamma h Lr
+  double c_ucrit;      // (3/2) hbar_c [eV m]: critical energy per gamma^3 h
 };
+
+// Inverse of the synchrotron photon-number spectrum for the photon-by-photon
+// model: g(s) = x^(1/3) where the probability of a photon energy of at least
+// x u_c is exp(-s), at s = i / 64, i = 0 .. kPhotonTableNodes - 1, each value
+// rounded to single precision (host table, computed once per process).
+constexpr int32_t kPhotonTableNodes = 2433;
+const std::vector<double>& photon_table_host();
+// The same table on the current device (uploaded once per device).
+hipError_t photon_table_device(const double** out);
 
 // launch helpers implemented in xtm_kernels.hip; all are stream-ordered
 hipError_t launch_init(const double* coords6, int64_t n, int64_t first_id, SoA P, KernelRef r,

@@ -273,9 +273,11 @@ std::string generate(const Decomp& d, int32_t style, bool batched) {
        "             int *state, *at_element, *at_turn; long long* pid; };\n"
        "struct KRef { double beta0, two_over_beta0, gamma0, c_mean, c_quant, p0c;\n"
        "              unsigned long long seed; int rad_mode; int pad;\n"
-       "              float* rec; int rec_turns; int rec_n; };\n"
+       "              float* rec; int rec_turns; int rec_n;\n"
+       "              const double* photon_table; double c_nphot, c_ucrit; };\n"
        "#define RAD(kx, ky, lr, j) xtmm::radiate_at<true>(q, kx, ky, lr, r.rad_mode, r.seed, pid, \\\n"
-       "    t0 + t, ec + (j), r.gamma0, r.c_mean, r.c_quant, r.p0c, beta0, two_over_beta0)\n"
+       "    t0 + t, ec + (j), r.gamma0, r.c_mean, r.c_quant, r.p0c, beta0, two_over_beta0, \\\n"
+       "    r.photon_table, r.c_nphot, r.c_ucrit)\n"
        "// a lane that fails a loss test stores the coordinates it entered the\n"
        "// element with (a rare, divergent store); the loss record follows at the end\n"
        "// (its slot index passes through a register move, so the nine store\n"

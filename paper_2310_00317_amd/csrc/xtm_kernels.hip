@@ -24,6 +24,8 @@
 //   RF             ptau += amp sin(phase - k zeta); delta = v/(1+sqrt(1+v)),
 //                  v = ptau (ptau + 2/beta0); rpp = 1/(1+delta); rvv = (1+delta)/(1+beta0 ptau)
 //   apertures      lost iff !(inside), so NaN is lost and the boundary survives
+#include <mutex>
+
 #include "xtm_internal.h"
 #include "xtm_maps.h"
 
@@ -106,7 +108,8 @@ __device__ __forceinline__ void maybe_radiate(xtmm::Pt& q, double kx, double ky,
                                               const KernelRef& r, long long pid, int turn,
                                               int element) {
   xtmm::radiate_at<true>(q, kx, ky, lr, r.rad_mode, r.seed, pid, turn, element, r.gamma0, r.c_mean,
-                   r.c_quant, r.p0c, r.beta0, r.two_over_beta0);
+                   r.c_quant, r.p0c, r.beta0, r.two_over_beta0, r.photon_table, r.c_nphot,
+                   r.c_ucrit);
 }
 
 __device__ __forceinline__ void apply_elem(xtmm::Pt& q, uint32_t ktype, uint32_t order,
@@ -528,6 +531,38 @@ __global__ void __launch_bounds__(256) k_philox(unsigned long long seed, uint32_
   out[4 * j + 1] = w.b;
   out[4 * j + 2] = w.c;
   out[4 * j + 3] = w.d;
+}
+
+// ------------------------------------------------ photon spectrum table
+// The inverse photon spectrum of the photon-by-photon radiation model,
+// uploaded from the host table at the first use on each device.  In host code
+// `photon_table_dev` names a host-side stand-in: kernels receive the device
+// address looked up with hipGetSymbolAddress.
+static __device__ __align__(256) double photon_table_dev[kPhotonTableNodes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_photon_mu;
+const double* g_photon_addr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t photon_table_device(const double** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  const std::vector<double>& host = photon_table_host();
+  std::lock_guard<std::mutex> lock(g_photon_mu);
+  if (!g_photon_addr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(photon_table_dev));
+    if (e != hipSuccess) return e;
+    e = hipMemcpy(p, host.data(), host.size() * sizeof(double), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return e;
+    g_photon_addr[dev] = static_cast<const double*>(p);
+  }
+  *out = g_photon_addr[dev];
+  return hipSuccess;
 }
 
 // ------------------------------------------------------------- launchers

@@ -407,16 +407,96 @@ __device__ __forceinline__ void radiate(Pt& q, double kx, double ky, double lr, 
   q.py = q.py * f;
 }
 
+// ------------------------------------------------- photon-by-photon emission
+// The quantum model emitted photon by photon: along a radiating multipole
+// the photons arrive as a Poisson process of mean count
+// nbar = (5 / (2 sqrt 3)) (r m / hbar_c) gamma h Lr (that is alpha q^2 times
+// the number of photons per radian of bending, 5/(2 sqrt 3) gamma), each
+// with energy x u_c, u_c = (3/2) hbar_c gamma^3 h the critical energy, and x
+// distributed as the universal synchrotron photon-number spectrum: the
+// probability of x or more is
+//   Q(x) = 3/(5 pi) int_0^inf exp(-x cosh t) cosh(5t/3) / cosh^2 t dt.
+// Photon j of a kick uses Philox block (pid_lo, pid_hi, turn,
+// element * 256 + j): its first uniform is the arrival's exponential
+// spacing -ln u (in units of the mean count), its second the energy through
+// the inverse of Q.  The inverse is tabulated (host-computed) as
+// g(s) = x^(1/3) with Q(x) = exp(-s) at s = i / 64, i = 0 .. 2432, in single
+// precision, and interpolated linearly in s; x = g^3.  At most 255 photons
+// per kick.
+constexpr int kPhotonNodes = 2433;
+
+__device__ __forceinline__ double photon_x(const double* __restrict__ tab, double s) {
+  const double v = s * 64.0;
+  int i = (int)v;
+  i = i < kPhotonNodes - 2 ? i : kPhotonNodes - 2;
+  i = i > 0 ? i : 0;
+  const double f = v - (double)i;
+  const double a = tab[i], b = tab[i + 1];
+  const double g = fma(f, b - a, a);
+  return g * g * g;
+}
+
+__device__ __forceinline__ void radiate_photons(Pt& q, double kx, double ky, double lr,
+                                                const double* __restrict__ tab, double c_nphot,
+                                                double c_ucrit, double gamma0, double p0c,
+                                                unsigned long long seed, long long pid, int turn,
+                                                int element, double beta0,
+                                                double two_over_beta0) {
+  const double h = sqrt(kx * kx + ky * ky) * q.rpp / lr;
+  const double gam = gamma0 * (1.0 + q.bpt);
+  const double nbar = c_nphot * gam * h * lr;
+  U4 c;
+  c.a = (unsigned int)(unsigned long long)pid;
+  c.b = (unsigned int)((unsigned long long)pid >> 32);
+  c.c = (unsigned int)turn;
+  double t = 0.0, sum = 0.0;
+  for (int j = 0; j < 256; ++j) {
+    c.d = (unsigned int)element * 256u + (unsigned int)j;
+    const U4 w = philox4x32_10(c, (unsigned int)seed, (unsigned int)(seed >> 32));
+    t = t - xlog(uniform52(w.a, w.b));
+    if (!(t <= nbar)) break;
+    sum = sum + photon_x(tab, -xlog(uniform52(w.c, w.d)));
+  }
+  if (sum == 0.0) return;
+  const double g3 = gam * gam * gam;
+  const double de = c_ucrit * g3 * h * sum;
+  const double opd_old = 1.0 + q.delta;
+  q.ptau = q.ptau - de / p0c;
+  from_ptau(q, beta0, two_over_beta0);
+  const double f = (1.0 + q.delta) / opd_old;
+  q.px = q.px * f;
+  q.py = q.py * f;
+}
+
+__device__ __attribute__((noinline)) void radiate_photons_far(
+    Pt& q, double kx, double ky, double lr, const double* __restrict__ tab, double c_nphot,
+    double c_ucrit, double gamma0, double p0c, unsigned long long seed, long long pid, int turn,
+    int element, double beta0, double two_over_beta0) {
+  radiate_photons(q, kx, ky, lr, tab, c_nphot, c_ucrit, gamma0, p0c, seed, pid, turn, element,
+                  beta0, two_over_beta0);
+}
+
 // Radiation step of a multipole with radiation length lr (none if lr <= 0 or
-// mode 0); the Gaussian deviate is keyed by (seed, particle id, absolute
-// turn, element index of the line as tracked, thick elements sliced).
+// mode 0): mean (1), mean + Gaussian quantum excitation (2), photon by photon
+// (3); the deviates are keyed by (seed, particle id, absolute turn, element
+// index of the line as tracked, thick elements sliced).
 template <bool kFar = false>
 __device__ __forceinline__ void radiate_at(Pt& q, double kx, double ky, double lr, int mode,
                                            unsigned long long seed, long long pid, int turn,
                                            int element, double gamma0, double c_mean,
                                            double c_quant, double p0c, double beta0,
-                                           double two_over_beta0) {
+                                           double two_over_beta0, const double* ptab,
+                                           double c_nphot, double c_ucrit) {
   if (mode == 0 || !(lr > 0.0)) return;
+  if (mode == 3) {
+    if (kFar)
+      radiate_photons_far(q, kx, ky, lr, ptab, c_nphot, c_ucrit, gamma0, p0c, seed, pid, turn,
+                          element, beta0, two_over_beta0);
+    else
+      radiate_photons(q, kx, ky, lr, ptab, c_nphot, c_ucrit, gamma0, p0c, seed, pid, turn,
+                      element, beta0, two_over_beta0);
+    return;
+  }
   const double g = (mode == 2) ? (kFar ? gauss_at_far(seed, pid, turn, element, 0)
                                         : gauss_at(seed, pid, turn, element, 0))
                                : 0.0;

@@ -136,3 +136,18 @@ def test_audit_upper_bound_host_function_matches_oracle(oracle_mod):
     for k, n in ((-1, 5), (6, 5), (0, -1)):
         with pytest.raises(P.XtmError):
             P.audit_upper_bound(k, n)
+
+
+def test_photon_table_equals_the_oracle_table():
+    """The library computes the photon-spectrum table on the host with its own
+    quadrature and root finding; rounded to single precision it must equal
+    the oracle's independently computed table value for value."""
+    import paper_2310_00317_amd as P
+    from oracle import photons
+    lib_t = P.photon_table()
+    orc_t = photons.table()
+    assert lib_t.shape == orc_t.shape == (P.PHOTON_TABLE_NODES,)
+    bad = np.nonzero(lib_t != orc_t)[0]
+    assert bad.size == 0, (bad[:5], lib_t[bad[:5]], orc_t[bad[:5]])
+    with pytest.raises(P.XtmError):
+        P.check(P.lib().xtm_photon_table(None, P.PHOTON_TABLE_NODES), "xtm_photon_table")

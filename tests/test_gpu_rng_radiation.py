@@ -56,7 +56,7 @@ def _ring():
     return I.cfg5_lattice(100, n_rf=4, sextupoles=False)
 
 
-@pytest.mark.parametrize("mode", [1, 2])
+@pytest.mark.parametrize("mode", [1, 2, 3])
 def test_radiation_parity_small_ring(P, oracle_mod, mode):
     el = _ring()
     c = I.gaussian_particles(600, 99, [3e-4, 3e-6, 3e-5, 3e-7, 3e-3, 1.5e-3])
@@ -83,16 +83,31 @@ def test_radiation_full_electron_ring_short(P, oracle_mod, variant):
     assert_bitwise(g, o)
 
 
-def test_radiation_graph_and_chunks_invariant(P):
+@pytest.mark.parametrize("variant", [0, 4, 10, 13])
+def test_photon_radiation_full_electron_ring_short(P, oracle_mod, variant):
+    """Photon-by-photon emission on the full 20,000-element electron ring
+    (about two photons per bend): bitwise parity with the oracle."""
+    el = I.cfg5_lattice()
+    c = I.cfg5_particles(256, seed=4)
+    g, gp, _, _, _ = gpu_run(P, el, EREF, c, 3, radiation=3, seed=9, variant=variant)
+    o = oracle_mod.init(c, EREF)
+    op = oracle_mod.track(el, EREF, o, 3, radiation=3, seed=9)
+    assert gp == op
+    assert_parity(g, o, rtol=1e-12)
+    assert_bitwise(g, o)
+
+
+@pytest.mark.parametrize("mode", [2, 3])
+def test_radiation_graph_and_chunks_invariant(P, mode):
     el = _ring()
     c = I.gaussian_particles(512, 5, [3e-4, 3e-6, 3e-5, 3e-7, 3e-3, 1.5e-3])
-    a, pa, _, _, _ = gpu_run(P, el, EREF, c, 40, radiation=2, seed=1)
+    a, pa, _, _, _ = gpu_run(P, el, EREF, c, 40, radiation=mode, seed=1)
     for kw in (dict(turns_per_chunk=7, variant=4), dict(variant=5, turns_per_chunk=9),
                dict(variant=6, turns_per_chunk=5), dict(variant=7), dict(variant=8),
                dict(variant=9, turns_per_chunk=3), dict(variant=10, turns_per_chunk=11),
                dict(variant=11, turns_per_chunk=6), dict(variant=12),
                dict(variant=13, turns_per_chunk=7)):
-        b, pb, _, _, _ = gpu_run(P, el, EREF, c, 40, radiation=2, seed=1, **kw)
+        b, pb, _, _, _ = gpu_run(P, el, EREF, c, 40, radiation=mode, seed=1, **kw)
         assert pa == pb, kw
         for f in a:
             assert np.array_equal(a[f], b[f], equal_nan=True), (kw, f)
@@ -101,14 +116,15 @@ def test_radiation_graph_and_chunks_invariant(P):
 def test_radiation_argument_checks(P):
     lat = P.Lattice(_ring(), EREF)
     parts = P.Particles(4, EREF).init(np.zeros((4, 6)))
-    for kw, code in [(dict(radiation=3), -1), (dict(radiation=1, variant=2), -1)]:
+    for kw, code in [(dict(radiation=4), -1), (dict(radiation=-1), -1),
+                     (dict(radiation=1, variant=2), -1)]:
         with pytest.raises(P.XtmError) as ei:
             P.track(lat, parts, 1, **kw)
         assert ei.value.code == code
 
 
-@pytest.mark.parametrize("variant", [0, 4, 13])
-def test_batched_radiation_and_recorder_equal_separate(P, variant):
+@pytest.mark.parametrize("variant,mode", [(0, 2), (4, 2), (13, 2), (0, 3), (4, 3)])
+def test_batched_radiation_and_recorder_equal_separate(P, variant, mode):
     """Two variants of the small electron ring (the second with its bending
     multipoles 1e-3 stronger: same structure, other values) tracked as one
     batch with quantum excitation and the early-turn recorder on: states,
@@ -124,14 +140,14 @@ def test_batched_radiation_and_recorder_equal_separate(P, variant):
     first = np.array([0, 130, 300], dtype=np.int64)
     big = P.Particles(300, EREF).init(c, first_id=500)
     rec = torch.full((16, 4, 300), float("nan"), dtype=torch.float32, device="cuda")
-    P.track_batched(P.Batch(lats), big, first, 25, radiation=2, seed=77, record=rec,
+    P.track_batched(P.Batch(lats), big, first, 25, radiation=mode, seed=77, record=rec,
                     variant=variant)
     g, gr = big.to_numpy(), rec.cpu().numpy()
     for v in range(2):
         a, b = int(first[v]), int(first[v + 1])
         one = P.Particles(b - a, EREF).init(c[a:b], first_id=500 + a)
         r1 = torch.full((16, 4, b - a), float("nan"), dtype=torch.float32, device="cuda")
-        P.track(lats[v], one, 25, radiation=2, seed=77, record=r1, variant=4)
+        P.track(lats[v], one, 25, radiation=mode, seed=77, record=r1, variant=4)
         o = one.to_numpy()
         for f in o:
             assert np.array_equal(g[f][a:b], o[f], equal_nan=True), (v, f)
