@@ -141,10 +141,15 @@ def workload(name: str, n_override: int | None, radiation: int = 2):
         desc = f"thin FODO ring, 801 elements, {len(c)} Gaussian protons at 450 GeV"
         return el, c, I.PROTON_450GEV, desc, 100, 1
     if name == "cfg5":
+        import paper_2310_00317_amd as P
         el = I.cfg5_lattice()
-        c = I.cfg5_particles(n_override or 1_000_000)
+        n = n_override or 1_000_000
+        # electrons matched to the ring's 6D normal form (closed orbit and
+        # eigenvectors with the mean energy loss) at the given emittances
+        nf = P.twiss6d(P.Lattice(el, I.ELECTRON_45GEV6), radiation=1)
+        c = P.matched_gaussian(nf, I.ELECTRON_45GEV6, I.CFG5_EMITTANCES, I.standard_normals(n))
         desc = (f"electron ring, 20,000 thin elements (bends with radiation length, 8 RF), "
-                f"{len(c)} electrons at 45.6 GeV, " +
+                f"{len(c)} electrons at 45.6 GeV matched to the 6D normal form, " +
                 ("photon-by-photon radiation (Poisson photon counts, universal spectrum, "
                  "Philox deviates)" if radiation == 3 else
                  "mean + quantum radiation (Philox deviates)"))

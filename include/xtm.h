@@ -385,6 +385,63 @@ xtm_status xtm_twiss_coupled(xtm_lattice lat, double delta0, double h, double hd
 xtm_status xtm_twiss_open(xtm_lattice lat, double delta0, double h, double hd, const double* init,
                           double* h_table, void* stream);
 
+/* 6D linear normal form by tracking (paper section "Twiss module": the
+   closed orbit from a root finder on the one-turn map, the Jacobian by
+   central differences, the linear normal form from its eigenvalues and
+   eigenvectors; with radiation the eigenvalues' moduli are the damping per
+   turn, section "Synchrotron radiation models and compensation").  In
+   canonical coordinates u = (x, px, y, py, zeta, pzeta), pzeta = ptau/beta0,
+   with every element of the line (RF included, apertures checked) and, with
+   radiation = 1, the mean energy loss of radiating multipoles:
+     1. closed orbit u* = T(u*) by Newton's method u <- u + (I - J)^-1 (T(u) - u)
+        from 0, J by central differences at u (13 particles tracked one turn),
+        until the largest component of T(u) - u is at most tol, stops
+        decreasing, or max_iter steps were made;
+     2. J at u* by central differences with steps h (h_steps: host, 6 values,
+        or NULL for 1e-7, 1e-9, 1e-7, 1e-9, 1e-6, 1e-8) and h/2, Richardson-
+        combined (4 J(h/2) - J(h)) / 3;
+     3. its eigenvalues (Hessenberg reduction, shifted QR steps); of each
+        complex-conjugate pair the eigenvector with Im(v^H S v) > 0, scaled to
+        v^H S v = 2i (S the 6x6 symplectic form); mode k is assigned to the
+        plane p = k (x, y, longitudinal) by the assignment maximising the
+        summed shares Im(conj(v_2p) v_2p+1), and its phase is set so that
+        v_2k is real and positive.
+   For an uncoupled plane, |v_2k|^2 is the beta function at the line start,
+   and a Gaussian beam with covariance sum_k eps_k (Re v_k Re v_k^T +
+   Im v_k Im v_k^T) is matched (xtm_matched_gaussian).
+   XTM_E_UNSUPPORTED for a real eigenvalue (an unstable plane), a singular
+   I - J or a probe particle lost.  Synchronising; allocates its scratch. */
+typedef struct xtm_normal_form6 {
+  double co[6];          /* closed orbit at the line start (canonical)        */
+  double J[36];          /* one-turn Jacobian at the closed orbit, row-major  */
+  double lam_re[3], lam_im[3];  /* eigenvalue of mode k                       */
+  double q[3];           /* tune of mode k: arg(lambda_k) / 2 pi, in [0, 1)   */
+  double damping[3];     /* -ln |lambda_k| per turn (0 without radiation)     */
+  double v_re[18], v_im[18];    /* eigenvector of mode k: components 6k..6k+5 */
+  int32_t iterations;    /* Newton steps made                                 */
+  int32_t pad;
+  double residual;       /* largest component of T(u) - u at the last step    */
+} xtm_normal_form6;
+xtm_status xtm_twiss6d(xtm_lattice lat, int32_t radiation, const double* h_steps, int32_t max_iter,
+                       double tol, xtm_normal_form6* out, void* stream);
+
+/* Step 3 of xtm_twiss6d alone, for a given one-turn Jacobian J (host,
+   row-major 6x6, canonical coordinates): fills everything of `out` but the
+   closed orbit (zero), iterations and residual.  Host only. */
+xtm_status xtm_normal_form_of_map(const double* J, xtm_normal_form6* out);
+
+/* Gaussian ensemble matched to a 6D normal form (paper section "Twiss
+   module": matched particle distributions from the linear normal form):
+   particle i from six standard normal deviates g = h_gauss[6i .. 6i+5]
+   (host, supplied by the caller): u = co + sum_k Re(v_k z_k) with
+   z_k = sqrt(eps_k) (g_2k + i g_2k+1), eps = host[3] emittances of the three
+   modes [m] (0 allowed); written to h_out[6i ..] as (x, px, y, py, zeta,
+   delta), delta = w / (1 + sqrt(1 + w)) from ptau = beta0 pzeta,
+   w = ptau (ptau + 2/beta0), ready for xtm_particles_init.  Host only. */
+xtm_status xtm_matched_gaussian(const xtm_normal_form6* nf, const xtm_reference* ref,
+                                const double eps[3], const double* h_gauss, int64_t n,
+                                double* h_out);
+
 /* Chromaticity by tracking (paper section "Twiss module": tunes and
    chromaticities measured on the tracking model): out_dq[0..1] (host) =
    (Q(delta0 + eps) - Q(delta0 - eps)) / (2 eps) for the horizontal and

@@ -502,14 +502,16 @@ def reference(ref) -> tuple[float, float]:
     return float(out[0]), float(out[1])
 
 
-def one_turn(elements, ref, u6, n_turns: int = 1) -> np.ndarray:
-    """Canonical map u = (x, px, y, py, zeta, pzeta) -> T^n(u)."""
+def one_turn(elements, ref, u6, n_turns: int = 1, radiation: int = 0) -> np.ndarray:
+    """Canonical map u = (x, px, y, py, zeta, pzeta) -> T^n(u); radiation 1
+    adds the mean energy loss of radiating multipoles (no deviates)."""
     el = _els(elements)
     r = _ref3(ref)
     u = np.array(u6, dtype=np.float64)
     st = lib().oracle_track_canonical(el.ctypes.data_as(ctypes.c_void_p), ctypes.c_int32(len(el)),
                                       r.ctypes.data_as(ctypes.c_void_p),
-                                      u.ctypes.data_as(ctypes.c_void_p), ctypes.c_int32(n_turns))
+                                      u.ctypes.data_as(ctypes.c_void_p), ctypes.c_int32(n_turns),
+                                      ctypes.c_int32(radiation))
     if st != 1:
         raise RuntimeError("reference trajectory lost (state %d)" % st)
     return u
@@ -519,7 +521,7 @@ DEFAULT_FD_STEPS = np.array([1e-7, 1e-9, 1e-7, 1e-9, 1e-6, 1e-8])
 
 
 def jacobian(elements, ref, u0=None, h=DEFAULT_FD_STEPS, n_turns: int = 1,
-             richardson: bool = True) -> np.ndarray:
+             richardson: bool = True, radiation: int = 0) -> np.ndarray:
     """Central-difference Jacobian of the canonical one-turn map (Twiss step 2):
     J[:, j] = (T(u0 + h_j e_j) - T(u0 - h_j e_j)) / (2 h_j), optionally
     Richardson-extrapolated from steps h and h/2."""
@@ -530,8 +532,8 @@ def jacobian(elements, ref, u0=None, h=DEFAULT_FD_STEPS, n_turns: int = 1,
         for j in range(6):
             e = np.zeros(6)
             e[j] = hh[j]
-            J[:, j] = (one_turn(elements, ref, u0 + e, n_turns)
-                       - one_turn(elements, ref, u0 - e, n_turns)) / (2.0 * hh[j])
+            J[:, j] = (one_turn(elements, ref, u0 + e, n_turns, radiation)
+                       - one_turn(elements, ref, u0 - e, n_turns, radiation)) / (2.0 * hh[j])
         return J
 
     h = np.asarray(h, dtype=np.float64)
@@ -560,6 +562,94 @@ def normal_form_2x2(M: np.ndarray) -> dict:
     mu = math.atan2(smu, cmu) % (2.0 * math.pi)
     return {"cos_mu": cmu, "sin_mu": smu, "beta": beta, "alpha": alpha,
             "q": mu / (2.0 * math.pi)}
+
+
+def closed_orbit_6d(elements, ref, radiation: int = 0, guess=None, h=DEFAULT_FD_STEPS,
+                    tol: float = 1e-15, max_iter: int = 20) -> np.ndarray:
+    """Fixed point u* = T(u*) of the canonical 6D one-turn map (RF included;
+    with radiation 1 the mean energy loss shifts it) by Newton's method,
+    u <- u + (I - J)^-1 (T(u) - u), J by central differences at u, until the
+    largest component of T(u) - u is below tol or stops decreasing."""
+    u = np.zeros(6) if guess is None else np.array(guess, dtype=np.float64)
+    best = np.inf
+    for _ in range(max_iter):
+        r = one_turn(elements, ref, u, 1, radiation) - u
+        res = float(np.max(np.abs(r)))
+        if res <= tol or res >= best:
+            break
+        best = res
+        J = jacobian(elements, ref, u, h, richardson=False, radiation=radiation)
+        u = u + np.linalg.solve(np.eye(6) - J, r)
+    return u
+
+
+def _mode_shares(v) -> np.ndarray:
+    """Im(conj(v_2p) v_2p+1) per plane p: the plane's part of v^H S v / 2i."""
+    return np.array([np.imag(np.conj(v[2 * p]) * v[2 * p + 1]) for p in range(3)])
+
+
+def normal_form_6d(elements, ref, radiation: int = 0, h=DEFAULT_FD_STEPS) -> dict:
+    """6D linear normal form by tracking (paper section "Twiss module": the
+    closed orbit by a root finder, the one-turn Jacobian by central
+    differences, the eigenvalues and eigenvectors of the Jacobian; with
+    radiation their moduli give the damping per turn).  In canonical
+    coordinates (x, px, y, py, zeta, pzeta): the eigen-decomposition is
+    LAPACK's (numpy.linalg.eig); of each complex-conjugate pair the
+    eigenvector with Im(v^H S v) > 0 is kept and scaled to v^H S v = 2i;
+    mode k is the one whose share Im(conj(v_2p) v_2p+1) is largest in plane
+    p = k (the assignment of modes to planes that maximises the summed
+    shares), its phase set so that v_2k is real and positive.  Returns the
+    closed orbit co, J, per mode the eigenvalue lam, tune q = arg(lam)/2 pi
+    mod 1, damping -ln|lam| per turn and eigenvector v (6 complex)."""
+    import itertools
+    co = closed_orbit_6d(elements, ref, radiation, h=h)
+    J = jacobian(elements, ref, co, h, radiation=radiation)
+    w, V = np.linalg.eig(J)
+    modes = []
+    used = np.zeros(6, dtype=bool)
+    for i in np.argsort(-np.abs(w.imag)):
+        if used[i]:
+            continue
+        j = int(np.argmin(np.abs(w - np.conj(w[i])) + used * 1e300 + (np.arange(6) == i) * 1e300))
+        used[i] = used[j] = True
+        v = V[:, i]
+        lam = w[i]
+        n = float(np.sum(_mode_shares(v)))
+        if n < 0:
+            v, lam, n = np.conj(v), np.conj(lam), -n
+        modes.append((lam, v / math.sqrt(n)))
+    if len(modes) != 3:
+        raise RuntimeError("the one-turn map has real eigenvalues (unstable or at a resonance)")
+    shares = np.array([_mode_shares(v) for _, v in modes])
+    perm = max(itertools.permutations(range(3)), key=lambda pm: sum(shares[pm[k], k] for k in range(3)))
+    lam = np.zeros(3, dtype=complex)
+    vec = np.zeros((3, 6), dtype=complex)
+    for k in range(3):
+        l, v = modes[perm[k]]
+        ph = v[2 * k] / abs(v[2 * k])
+        lam[k] = l
+        vec[k] = v / ph
+    q = (np.angle(lam) / (2.0 * math.pi)) % 1.0
+    return {"co": co, "J": J, "lam": lam, "q": q, "damping": -np.log(np.abs(lam)), "v": vec}
+
+
+def matched_gaussian(nf: dict, ref, eps, gauss) -> np.ndarray:
+    """Gaussian ensemble matched to the 6D normal form: for mode k with
+    emittance eps_k, z_k = sqrt(eps_k) (g_2k + i g_2k+1) from the given
+    standard normals g (n, 6); u = co + sum_k Re(v_k z_k) in canonical
+    coordinates; returned as (x, px, y, py, zeta, delta) rows with
+    ptau = beta0 pzeta and delta = w / (1 + sqrt(1 + w)), w = ptau (ptau + 2/beta0)."""
+    b0, _ = reference(ref)
+    g = np.asarray(gauss, dtype=np.float64)
+    u = np.tile(nf["co"], (len(g), 1))
+    for k in range(3):
+        z = math.sqrt(eps[k]) * (g[:, 2 * k] + 1j * g[:, 2 * k + 1])
+        u = u + np.real(np.outer(z, nf["v"][k]))
+    ptau = b0 * u[:, 5]
+    w = ptau * (ptau + 2.0 / b0)
+    out = u.copy()
+    out[:, 5] = w / (1.0 + np.sqrt(1.0 + w))
+    return out
 
 
 def regular_mask(elements, ref, coords6, n_turns: int = 100, rtol: float = 1e-13,

@@ -554,8 +554,8 @@ int64_t oracle_track_backward(const orc_elem* el, int32_t n_el, const double ref
    for the central-difference one-turn Jacobian, where the canonical partner of
    zeta is pzeta = ptau/beta0 (delta, rpp, rvv recomputed from ptau). */
 int oracle_track_canonical(const orc_elem* el, int32_t n_el, const double ref3[3],
-                           double* u6, int32_t n_turns) {
-  if (validate(el, n_el)) return -2;
+                           double* u6, int32_t n_turns, int32_t radiation) {
+  if (validate(el, n_el) || radiation < 0 || radiation > 1) return -2;
   orc_ref r = make_ref(ref3);
   orc_coef* c = build_coefs(el, n_el);
   orc_pt q;
@@ -567,6 +567,8 @@ int oracle_track_canonical(const orc_elem* el, int32_t n_el, const double ref3[3
     for (int32_t e = 0; e < n_el && st == 1; ++e) {
       double fkx, fky;
       st = apply(&q, &el[e], &c[e], &r, 1.0, &fkx, &fky);
+      if (st == 1 && radiation && el[e].type == O_MULT && el[e].length > 0.0)
+        radiate(&q, fkx, fky, el[e].length, &r, 1, 0.0);
     }
   u6[0] = q.x; u6[1] = q.px; u6[2] = q.y; u6[3] = q.py; u6[4] = q.zeta;
   u6[5] = q.ptau / r.beta0;

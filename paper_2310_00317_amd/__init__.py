@@ -68,6 +68,23 @@ class TrackStats(ctypes.Structure):
                 ("kernel_ms", ctypes.c_double)]
 
 
+class NormalForm6(ctypes.Structure):
+    _fields_ = [("co", ctypes.c_double * 6), ("J", ctypes.c_double * 36),
+                ("lam_re", ctypes.c_double * 3), ("lam_im", ctypes.c_double * 3),
+                ("q", ctypes.c_double * 3), ("damping", ctypes.c_double * 3),
+                ("v_re", ctypes.c_double * 18), ("v_im", ctypes.c_double * 18),
+                ("iterations", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("residual", ctypes.c_double)]
+
+    def as_dict(self) -> dict:
+        v = np.array(self.v_re[:]) + 1j * np.array(self.v_im[:])
+        return {"co": np.array(self.co[:]), "J": np.array(self.J[:]).reshape(6, 6),
+                "lam": np.array(self.lam_re[:]) + 1j * np.array(self.lam_im[:]),
+                "q": np.array(self.q[:]), "damping": np.array(self.damping[:]),
+                "v": v.reshape(3, 6), "iterations": int(self.iterations),
+                "residual": float(self.residual)}
+
+
 class Plan(ctypes.Structure):
     _fields_ = [("variant", ctypes.c_int32), ("block", ctypes.c_int32),
                 ("passes_per_s", ctypes.c_double), ("turns_per_chunk", ctypes.c_int32),
@@ -135,6 +152,9 @@ def lib() -> ctypes.CDLL:
                             vp], i32),
             "xtm_rule_score": ([vp, i64, vp, vp], i32),
             "xtm_photon_table": ([vp, i32], i32),
+            "xtm_twiss6d": ([vp, i32, vp, i32, ctypes.c_double, vp, vp], i32),
+            "xtm_normal_form_of_map": ([vp, vp], i32),
+            "xtm_matched_gaussian": ([vp, vp, vp, vp, i64, vp], i32),
             "xtm_audit_upper_bound": ([i64, i64, vp], i32),
             "xtm_audit_verdict": ([vp, vp, ctypes.c_double, vp, vp, vp, vp, vp], i32),
             "xtm_resume_retired": ([vp, vp, vp, vp, vp], i32),
@@ -621,6 +641,41 @@ def rule_score(feat, stream=None):
     out = torch.empty(max(n, 1), dtype=torch.float32, device=feat.device)
     check(lib().xtm_rule_score(_p(feat), n, _p(out), _stream(stream)), "xtm_rule_score")
     return out[:n]
+
+
+def twiss6d(lattice: Lattice, radiation: int = 0, h=None, max_iter: int = 20,
+            tol: float = 1e-15, stream=None) -> NormalForm6:
+    """6D linear normal form by tracking (xtm_twiss6d)."""
+    out = NormalForm6()
+    hh = None if h is None else np.ascontiguousarray(h, dtype=np.float64)
+    check(lib().xtm_twiss6d(lattice.handle, int(radiation),
+                            None if hh is None else hh.ctypes.data_as(ctypes.c_void_p),
+                            int(max_iter), float(tol), ctypes.byref(out), _stream(stream)),
+          "xtm_twiss6d")
+    return out
+
+
+def normal_form_of_map(J) -> NormalForm6:
+    out = NormalForm6()
+    Jc = np.ascontiguousarray(J, dtype=np.float64).reshape(36)
+    check(lib().xtm_normal_form_of_map(Jc.ctypes.data_as(ctypes.c_void_p), ctypes.byref(out)),
+          "xtm_normal_form_of_map")
+    return out
+
+
+def matched_gaussian(nf: NormalForm6, ref, eps, gauss) -> np.ndarray:
+    """(n, 6) coordinates (x, px, y, py, zeta, delta) matched to the normal
+    form with mode emittances eps[3], from standard normals gauss (n, 6)."""
+    g = np.ascontiguousarray(gauss, dtype=np.float64).reshape(-1, 6)
+    e = np.ascontiguousarray(eps, dtype=np.float64)
+    out = np.zeros_like(g)
+    r = _ref_struct(ref)
+    check(lib().xtm_matched_gaussian(ctypes.byref(nf), ctypes.byref(r),
+                                     e.ctypes.data_as(ctypes.c_void_p),
+                                     g.ctypes.data_as(ctypes.c_void_p), len(g),
+                                     out.ctypes.data_as(ctypes.c_void_p)),
+          "xtm_matched_gaussian")
+    return out
 
 
 PHOTON_TABLE_NODES = 2433

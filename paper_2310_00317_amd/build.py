@@ -25,7 +25,7 @@ DEVICE = ["-x", "hip", f"--offload-arch={ARCH}",
           "-munsafe-fp-atomics"]
 
 KERNEL_SOURCES = ["xtm_kernels.hip", "xtm_learn.hip"]
-HOST_SOURCES = ["xtm_api.cpp", "xtm_jit.cpp", "xtm_photon.cpp"]
+HOST_SOURCES = ["xtm_api.cpp", "xtm_jit.cpp", "xtm_photon.cpp", "xtm_normal6.cpp"]
 
 
 def _embed_maps() -> None:

@@ -1071,8 +1071,8 @@ struct Scratch {
   }
 };
 
-xtm_status make_scratch(const xtm_particles_s* src, Scratch* sc) {
-  const int64_t m = src->n > 0 ? src->n : 1;
+xtm_status make_scratch_n(int64_t n, const RefQ& ref, Scratch* sc) {
+  const int64_t m = n > 0 ? n : 1;
   const size_t bytes = (size_t)m * (9 * sizeof(double) + 3 * sizeof(int32_t) + sizeof(int64_t));
   HIP_TRY(hipMalloc(&sc->mem, bytes), "scratch particles");
   char* b = static_cast<char*>(sc->mem);
@@ -1082,9 +1082,13 @@ xtm_status make_scratch(const xtm_particles_s* src, Scratch* sc) {
   a.particle_id = reinterpret_cast<int64_t*>(b); b += m * sizeof(int64_t);
   int32_t** g[3] = {&a.state, &a.at_element, &a.at_turn};
   for (int k = 0; k < 3; ++k) { *g[k] = reinterpret_cast<int32_t*>(b); b += m * sizeof(int32_t); }
-  a.n = src->n;
-  xtm_reference r{src->ref.mass0, src->ref.charge0, src->ref.p0c};
+  a.n = n;
+  xtm_reference r{ref.mass0, ref.charge0, ref.p0c};
   return xtm_particles_bind(&a, &r, &sc->P);
+}
+
+xtm_status make_scratch(const xtm_particles_s* src, Scratch* sc) {
+  return make_scratch_n(src->n, src->ref, sc);
 }
 
 xtm_status copy_set(const xtm_particles_s* src, xtm_particles_s* dst, hipStream_t s) {
@@ -2294,6 +2298,201 @@ xtm_status xtm_twiss_open(xtm_lattice L, double delta0, double h, double hd, con
         row[11 + i] = acc + md[i];
       }
     }
+    return XTM_OK;
+  });
+}
+
+namespace {
+// One turn of m particles given in canonical coordinates (x, px, y, py, zeta,
+// pzeta = ptau / beta0) through the tracker (RF included; the mean energy
+// loss of radiating multipoles when rad = 1); returns the same coordinates
+// after the turn and each particle's state.
+xtm_status track_turn_canonical(xtm_lattice_s* L, int32_t rad, const std::vector<double>& u,
+                                std::vector<double>* out, std::vector<int32_t>* state,
+                                hipStream_t s) {
+  const int64_t m = (int64_t)(u.size() / 6);
+  Scratch sc;
+  xtm_status st = make_scratch_n(m, L->ref, &sc);
+  if (st != XTM_OK) return st;
+  const double b0 = L->ref.beta0;
+  std::vector<double> c(u);
+  for (int64_t i = 0; i < m; ++i) {
+    const double ptau = b0 * u[6 * i + 5];
+    const double w = ptau * (ptau + 2.0 / b0);
+    c[6 * i + 5] = w / (1.0 + std::sqrt(1.0 + w));
+  }
+  st = xtm_particles_init(sc.P, c.data(), 0, 0, s);
+  if (st != XTM_OK) return st;
+  xtm_track_opts o{};
+  o.radiation = rad;
+  o.variant = 4;
+  st = run_turns(L, sc.P, 1, &o, s, nullptr, false);
+  if (st != XTM_OK) return st;
+  const xtm_arrays& a = sc.P->a;
+  std::vector<double> f[6];
+  double* src[6] = {a.x, a.px, a.y, a.py, a.zeta, a.ptau};
+  for (int k = 0; k < 6; ++k) {
+    f[k].resize(m);
+    HIP_TRY(hipMemcpyAsync(f[k].data(), src[k], m * sizeof(double), hipMemcpyDeviceToHost, s),
+            "read coordinates");
+  }
+  state->resize(m);
+  HIP_TRY(hipMemcpyAsync(state->data(), a.state, m * sizeof(int32_t), hipMemcpyDeviceToHost, s),
+          "read states");
+  HIP_TRY(hipStreamSynchronize(s), "synchronise");
+  out->resize(6 * m);
+  for (int64_t i = 0; i < m; ++i) {
+    for (int k = 0; k < 5; ++k) (*out)[6 * i + k] = f[k][i];
+    (*out)[6 * i + 5] = f[5][i] / b0;
+  }
+  return XTM_OK;
+}
+
+// T(u) and the central-difference Jacobian at u: 13 particles (u, u +- h_j
+// e_j) in one turn; with Richardson, also the steps h/2 (25 particles) and
+// J = (4 J(h/2) - J(h)) / 3.
+xtm_status map_and_jacobian(xtm_lattice_s* L, int32_t rad, const double u[6], const double h[6],
+                            bool richardson, double Tu[6], double J[36], hipStream_t s) {
+  const int n_steps = richardson ? 2 : 1;
+  std::vector<double> in;
+  for (int k = 0; k < 6; ++k) in.push_back(u[k]);
+  for (int r = 0; r < n_steps; ++r)
+    for (int j = 0; j < 6; ++j)
+      for (int sg = 0; sg < 2; ++sg) {
+        for (int k = 0; k < 6; ++k) in.push_back(u[k]);
+        in[in.size() - 6 + j] += (sg == 0 ? 1.0 : -1.0) * h[j] / (r == 0 ? 1.0 : 2.0);
+      }
+  std::vector<double> out;
+  std::vector<int32_t> st;
+  xtm_status e = track_turn_canonical(L, rad, in, &out, &st, s);
+  if (e != XTM_OK) return e;
+  for (int32_t v : st)
+    if (v != 1) return fail(XTM_E_UNSUPPORTED, "a probe particle was lost in one turn");
+  for (int k = 0; k < 6; ++k) Tu[k] = out[k];
+  double Jr[2][36];
+  for (int r = 0; r < n_steps; ++r)
+    for (int j = 0; j < 6; ++j) {
+      const double hh = h[j] / (r == 0 ? 1.0 : 2.0);
+      const size_t p = 6 * (1 + 12 * r + 2 * j), m = p + 6;
+      for (int i = 0; i < 6; ++i) Jr[r][6 * i + j] = (out[p + i] - out[m + i]) / (2.0 * hh);
+    }
+  for (int i = 0; i < 36; ++i) J[i] = richardson ? (4.0 * Jr[1][i] - Jr[0][i]) / 3.0 : Jr[0][i];
+  return XTM_OK;
+}
+
+bool solve6(const double A[36], const double b[6], double x[6]) {
+  double a[6][7];
+  for (int i = 0; i < 6; ++i) {
+    for (int j = 0; j < 6; ++j) a[i][j] = A[6 * i + j];
+    a[i][6] = b[i];
+  }
+  for (int k = 0; k < 6; ++k) {
+    int p = k;
+    for (int i = k + 1; i < 6; ++i)
+      if (std::fabs(a[i][k]) > std::fabs(a[p][k])) p = i;
+    if (a[p][k] == 0.0) return false;
+    for (int j = 0; j < 7; ++j) std::swap(a[k][j], a[p][j]);
+    for (int i = k + 1; i < 6; ++i) {
+      const double f = a[i][k] / a[k][k];
+      for (int j = k; j < 7; ++j) a[i][j] -= f * a[k][j];
+    }
+  }
+  for (int k = 5; k >= 0; --k) {
+    double sum = a[k][6];
+    for (int j = k + 1; j < 6; ++j) sum -= a[k][j] * x[j];
+    x[k] = sum / a[k][k];
+  }
+  return true;
+}
+}  // namespace
+
+xtm_status xtm_twiss6d(xtm_lattice L, int32_t radiation, const double* h_steps, int32_t max_iter,
+                       double tol, xtm_normal_form6* out, void* stream) {
+  return guarded([&]() -> xtm_status {
+    if (!L || !out) return fail(XTM_E_ARG, "null argument");
+    if (radiation < 0 || radiation > 1) return fail(XTM_E_ARG, "radiation must be 0 or 1");
+    if (max_iter < 0 || !(tol >= 0.0)) return fail(XTM_E_ARG, "need max_iter >= 0, tol >= 0");
+    double h[6] = {1e-7, 1e-9, 1e-7, 1e-9, 1e-6, 1e-8};
+    if (h_steps)
+      for (int k = 0; k < 6; ++k) {
+        if (!(h_steps[k] > 0.0)) return fail(XTM_E_ARG, "steps must be positive");
+        h[k] = h_steps[k];
+      }
+    hipStream_t s = (hipStream_t)stream;
+    double u[6] = {0, 0, 0, 0, 0, 0}, Tu[6], J[36];
+    double best = INFINITY, res = INFINITY;
+    int32_t it = 0;
+    for (;;) {
+      xtm_status st = map_and_jacobian(L, radiation, u, h, false, Tu, J, s);
+      if (st != XTM_OK) return st;
+      double r[6];
+      res = 0.0;
+      for (int k = 0; k < 6; ++k) {
+        r[k] = Tu[k] - u[k];
+        res = std::max(res, std::fabs(r[k]));
+      }
+      if (res <= tol || res >= best || it >= max_iter) break;
+      best = res;
+      double A[36], du[6];
+      for (int i = 0; i < 36; ++i) A[i] = (i % 7 == 0 ? 1.0 : 0.0) - J[i];
+      if (!solve6(A, r, du)) return fail(XTM_E_UNSUPPORTED, "I - J is singular (integer tune)");
+      for (int k = 0; k < 6; ++k) u[k] += du[k];
+      ++it;
+    }
+    xtm_status st = map_and_jacobian(L, radiation, u, h, true, Tu, J, s);
+    if (st != XTM_OK) return st;
+    NormalForm6 nf{};
+    for (int k = 0; k < 6; ++k) nf.co[k] = u[k];
+    if (!normal_form6(J, &nf))
+      return fail(XTM_E_UNSUPPORTED, "the one-turn map has a real eigenvalue (unstable plane)");
+    std::memcpy(out->co, nf.co, sizeof out->co);
+    std::memcpy(out->J, J, sizeof out->J);
+    std::memcpy(out->lam_re, nf.lam_re, sizeof out->lam_re);
+    std::memcpy(out->lam_im, nf.lam_im, sizeof out->lam_im);
+    std::memcpy(out->q, nf.q, sizeof out->q);
+    std::memcpy(out->damping, nf.damping, sizeof out->damping);
+    std::memcpy(out->v_re, nf.v_re, sizeof out->v_re);
+    std::memcpy(out->v_im, nf.v_im, sizeof out->v_im);
+    out->iterations = it;
+    out->pad = 0;
+    out->residual = res;
+    return XTM_OK;
+  });
+}
+
+xtm_status xtm_normal_form_of_map(const double* J, xtm_normal_form6* out) {
+  return guarded([&]() -> xtm_status {
+    if (!J || !out) return fail(XTM_E_ARG, "null argument");
+    NormalForm6 nf{};
+    if (!normal_form6(J, &nf))
+      return fail(XTM_E_UNSUPPORTED, "the map has a real eigenvalue (unstable plane)");
+    std::memset(out, 0, sizeof *out);
+    std::memcpy(out->J, J, sizeof out->J);
+    std::memcpy(out->lam_re, nf.lam_re, sizeof out->lam_re);
+    std::memcpy(out->lam_im, nf.lam_im, sizeof out->lam_im);
+    std::memcpy(out->q, nf.q, sizeof out->q);
+    std::memcpy(out->damping, nf.damping, sizeof out->damping);
+    std::memcpy(out->v_re, nf.v_re, sizeof out->v_re);
+    std::memcpy(out->v_im, nf.v_im, sizeof out->v_im);
+    return XTM_OK;
+  });
+}
+
+xtm_status xtm_matched_gaussian(const xtm_normal_form6* nf, const xtm_reference* ref,
+                                const double eps[3], const double* h_gauss, int64_t n,
+                                double* h_out) {
+  return guarded([&]() -> xtm_status {
+    if (!nf || !ref || !eps || n < 0 || (n > 0 && (!h_gauss || !h_out)))
+      return fail(XTM_E_ARG, "null argument or negative count");
+    for (int k = 0; k < 3; ++k)
+      if (!(eps[k] >= 0.0)) return fail(XTM_E_ARG, "emittances must be >= 0");
+    RefQ r;
+    if (!make_ref(ref, &r)) return fail(XTM_E_REFERENCE, "mass and p0c must be positive");
+    NormalForm6 f{};
+    std::memcpy(f.co, nf->co, sizeof f.co);
+    std::memcpy(f.v_re, nf->v_re, sizeof f.v_re);
+    std::memcpy(f.v_im, nf->v_im, sizeof f.v_im);
+    matched_gaussian(f, r.beta0, eps, h_gauss, n, h_out);
     return XTM_OK;
   });
 }

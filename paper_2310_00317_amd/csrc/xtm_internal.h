@@ -73,6 +73,21 @@ const std::vector<double>& photon_table_host();
 // The same table on the current device (uploaded once per device).
 hipError_t photon_table_device(const double** out);
 
+// 6D linear normal form of a one-turn Jacobian J (row-major 6x6, canonical
+// x, px, y, py, zeta, pzeta): per mode k (the plane it dominates) the
+// eigenvalue, the eigenvector normalised to v^H S v = 2i with v_2k real and
+// positive, the tune arg(lambda)/2pi mod 1 and the damping -ln|lambda|.
+// False for real eigenvalues (an unstable plane) or a failed iteration.
+struct NormalForm6 {
+  double co[6];
+  double lam_re[3], lam_im[3], q[3], damping[3];
+  double v_re[18], v_im[18];
+};
+bool normal_form6(const double J[36], NormalForm6* out);
+// u = co + sum_k Re(v_k sqrt(eps_k) (g_2k + i g_2k+1)), delta from pzeta.
+void matched_gaussian(const NormalForm6& nf, double beta0, const double eps[3],
+                      const double* gauss, int64_t n, double* out);
+
 // launch helpers implemented in xtm_kernels.hip; all are stream-ordered
 hipError_t launch_init(const double* coords6, int64_t n, int64_t first_id, SoA P, KernelRef r,
                        hipStream_t s);

@@ -514,3 +514,16 @@ CFG5_SIGMAS = np.array([1e-4, 1e-6, 1e-5, 1e-7, 3e-3, 4e-4])
 def cfg5_particles(n: int = 1_000_000, seed: int = 50505) -> np.ndarray:
     """6D Gaussian electrons with roughly equilibrium-sized sigmas."""
     return gaussian_particles(n, seed, CFG5_SIGMAS)
+
+
+# Mode emittances [m] of the matched cfg5 ensemble (horizontal, vertical,
+# longitudinal in canonical zeta-pzeta): the horizontal and vertical ones
+# give sigma_x ~ 1e-4 m and sigma_y ~ 1e-5 m at the line start, the
+# longitudinal one an energy spread near the ring's equilibrium 4.3e-4.
+CFG5_EMITTANCES = (6.0e-11, 3.4e-12, 1.2e-6)
+
+
+def standard_normals(n: int, seed: int = 50506) -> np.ndarray:
+    """(n, 6) independent standard normal deviates (seeded), the random input
+    of a matched ensemble."""
+    return np.random.default_rng(seed).standard_normal((n, 6))

@@ -151,3 +151,30 @@ def test_photon_table_equals_the_oracle_table():
     assert bad.size == 0, (bad[:5], lib_t[bad[:5]], orc_t[bad[:5]])
     with pytest.raises(P.XtmError):
         P.check(P.lib().xtm_photon_table(None, P.PHOTON_TABLE_NODES), "xtm_photon_table")
+
+
+def test_normal_form_and_matched_gaussian_host_functions_match_oracle(oracle_mod):
+    """The library's eigen-analysis (Hessenberg + shifted QR, null vectors by
+    full pivoting) against LAPACK's on the oracle's one-turn maps, and its
+    matched-ensemble arithmetic against the oracle's."""
+    import paper_2310_00317_amd as P
+    eref = I.ELECTRON_45GEV6
+    cases = ((I.cfg1_lattice(), I.PROTON_450GEV, 0),
+             (I.cfg5_lattice(100, n_rf=4, apertures=False, sextupoles=False), eref, 1),
+             (I.cfg5_lattice(), eref, 1))
+    for el, ref, rad in cases:
+        nf = oracle_mod.normal_form_6d(el, ref, radiation=rad)
+        got = P.normal_form_of_map(nf["J"])
+        d = got.as_dict()
+        assert np.max(np.abs(d["q"] - nf["q"])) < 1e-13
+        assert np.max(np.abs(d["damping"] - nf["damping"])) < 1e-13
+        assert np.max(np.abs(d["lam"] - nf["lam"])) < 1e-13
+        assert np.max(np.abs(d["v"] - nf["v"])) < 1e-11 * np.max(np.abs(nf["v"]))
+        for k in range(6):
+            got.co[k] = nf["co"][k]
+        g = np.random.default_rng(7).normal(size=(500, 6))
+        a = P.matched_gaussian(got, ref, [2e-9, 5e-10, 1e-6], g)
+        b = oracle_mod.matched_gaussian(nf, ref, [2e-9, 5e-10, 1e-6], g)
+        assert np.max(np.abs(a - b) / np.std(b, axis=0)) < 1e-10
+    with pytest.raises(P.XtmError):
+        P.normal_form_of_map(np.diag([2.0, 0.5, 1.0, 1.0, 1.0, 1.0]))   # real eigenvalues

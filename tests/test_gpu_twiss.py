@@ -166,3 +166,56 @@ def test_record_several_workgroups(P, oracle_mod):
     o = oracle_mod.track_record(el, REF, c)
     same = (g.view(np.int64) == o.view(np.int64)) | (np.isnan(g) & np.isnan(o))
     assert same.all(), f"{(~same).sum()} values differ"
+
+
+@pytest.mark.parametrize("case", ["fodo", "electron100", "electron_cfg5", "da_ring"])
+def test_normal_form_6d_matches_oracle(P, oracle_mod, case):
+    """6D closed orbit, one-turn Jacobian and normal form by tracking on the
+    GPU against the oracle's (the same steps with LAPACK's eigen-solver):
+    the FODO ring with its cavity, the two electron rings with the mean
+    energy loss (damping from the eigenvalue moduli), the errored
+    20,000-element DA ring."""
+    eref = I.ELECTRON_45GEV6
+    # The electron rings' thin bends (0.03 and 0.002 rad, each cancelled by
+    # its reference curvature) leave about 1e-14 m of rounding noise in a
+    # one-turn x: the steps are a hundred times the proton defaults there,
+    # and the noise divided by the steps sets the tolerances (tune 5e-9,
+    # damping 2e-8 per turn, Jacobian 2e-6 of its largest entry).
+    big = np.array([1e-5, 1e-7, 1e-5, 1e-7, 1e-4, 1e-6])
+    el, ref, rad, h, tq, tj = {
+        "fodo": (I.cfg1_lattice(), I.PROTON_450GEV, 0, None, 1e-9, 1e-7),
+        "electron100": (I.cfg5_lattice(100, n_rf=4, apertures=False, sextupoles=False), eref, 1,
+                        big, 5e-9, 2e-6),
+        "electron_cfg5": (I.cfg5_lattice(), eref, 1, big, 5e-9, 2e-6),
+        "da_ring": (I.cfg2_lattice(), I.PROTON_450GEV, 0, None, 1e-9, 1e-7),
+    }[case]
+    lat = P.Lattice(el, ref)
+    g = P.twiss6d(lat, radiation=rad, h=h).as_dict()
+    o = oracle_mod.normal_form_6d(el, ref, radiation=rad,
+                                  h=oracle_mod.DEFAULT_FD_STEPS if h is None else h)
+    print(f"[gpu-twiss6d] {case}: q {g['q']} damping {g['damping']} iterations "
+          f"{g['iterations']} residual {g['residual']:.1e}; |dq| {np.max(np.abs(g['q'] - o['q'])):.1e}",
+          flush=True)
+    assert np.max(np.abs(g["co"] - o["co"])) < 1e-12
+    assert np.max(np.abs(g["q"] - o["q"])) < tq
+    assert np.max(np.abs(g["damping"] - o["damping"])) < 4 * tq
+    assert np.max(np.abs(np.abs(g["v"]) - np.abs(o["v"]))) < 10 * tj * np.max(np.abs(o["v"]))
+    assert np.max(np.abs(g["J"] - o["J"])) < tj * np.max(np.abs(o["J"]))
+
+
+def test_matched_electrons_stay_matched(P, oracle_mod):
+    """An ensemble matched to the electron ring's 6D normal form (mean
+    radiation off) keeps its second moments turn after turn."""
+    import torch
+    eref = I.ELECTRON_45GEV6
+    el = I.cfg5_lattice(100, n_rf=4, apertures=False, sextupoles=False)
+    lat = P.Lattice(el, eref)
+    nf = P.twiss6d(lat)
+    g = np.random.default_rng(11).normal(size=(20000, 6))
+    c = P.matched_gaussian(nf, eref, [1e-10, 1e-12, 1e-7], g)
+    parts = P.Particles(len(c), eref).init(c)
+    s0 = parts.to_numpy()
+    P.track(lat, parts, 7)
+    s1 = parts.to_numpy()
+    for f in ("x", "px", "y", "py", "zeta", "delta"):
+        assert abs(np.std(s1[f]) / np.std(s0[f]) - 1) < 0.03, f

@@ -10,6 +10,8 @@ import pytest
 
 from paper_2310_00317_amd import inputs as I
 
+EREF = I.ELECTRON_45GEV6
+
 REF = I.PROTON_450GEV
 
 
@@ -163,3 +165,83 @@ def test_open_line_from_periodic_conditions_reproduces_the_ring(oracle_mod):
     o = oracle_mod.twiss_open(el, REF, init, h=1e-6, hd=1e-6)
     for c in ("betx", "alfx", "mux", "bety", "alfy", "muy", "dx", "dpx"):
         assert np.max(np.abs(o[c] - t[c])) < 1e-9 * max(1.0, np.max(np.abs(t[c]))), c
+
+
+# ------------------------------------------------------------ 6D normal form
+def _symp_norm(v):
+    # v^H S v / 2i summed over the three planes
+    return sum(float(np.imag(np.conj(v[2 * p]) * v[2 * p + 1])) for p in range(3))
+
+
+def test_6d_normal_form_reproduces_the_fodo_closed_forms(oracle_mod):
+    """FODO ring with its RF cavity, no radiation: the transverse tunes and
+    the synchrotron tune of the thin-lens closed forms, no damping, the
+    closed orbit on the axis, and |v_x|^2 = beta_x of the transverse optics."""
+    el = I.cfg1_lattice()
+    nf = oracle_mod.normal_form_6d(el, I.PROTON_450GEV)
+    assert np.all(np.abs(nf["co"]) < 1e-15)
+    assert abs(nf["q"][0] - 0.99580450867910) < 1e-10     # Q = 24.9958045086791
+    assert abs(nf["q"][1] - 0.99580450867910) < 1e-10
+    assert abs(nf["q"][2] - 3.5084512757054226e-4) < 1e-10
+    assert np.all(np.abs(nf["damping"]) < 1e-12)
+    # the line starts at the RF cavity, next to the QF: the thin-lens closed
+    # forms L_c (1 +- sin(mu/2)) / sin mu, 170.70136... m and 29.29864... m
+    assert abs(abs(nf["v"][0][0]) ** 2 / 170.70136339712423 - 1) < 1e-9
+    assert abs(abs(nf["v"][1][2]) ** 2 / 29.298643551925238 - 1) < 1e-9
+    for k in range(3):
+        assert abs(_symp_norm(nf["v"][k]) - 1) < 1e-12
+        assert abs(nf["v"][k][2 * k].imag) == 0.0 and nf["v"][k][2 * k].real > 0
+    # symplectic orthogonality of different modes: v_j^T S v_k = 0
+    S = oracle_mod.S6
+    for j in range(3):
+        for k in range(3):
+            if j != k:
+                assert abs(nf["v"][j] @ S @ nf["v"][k]) < 1e-9
+
+
+def test_6d_damping_partition_numbers_and_robinson_sum(oracle_mod):
+    """Electron ring with the mean energy loss: the damping decrement of mode
+    k per turn is J_k U0 / (2 E0); flat ring J_y = 1, separated-function
+    thin bends J_x = 1 and J_z = 2, their sum 4 (Robinson); the decrements
+    and the determinant of the one-turn map agree exactly
+    (det J = prod |lambda|^2)."""
+    el = I.cfg5_lattice(100, n_rf=4, apertures=False, sextupoles=False)
+    nf = oracle_mod.normal_form_6d(el, EREF, radiation=1)
+    u0 = I.CFG5_U0_OVER_E0[100]
+    jk = nf["damping"] / (u0 / 2.0)
+    assert abs(jk[1] - 1.0) < 2e-3
+    assert abs(jk[0] - 1.0) < 2e-3 and abs(jk[2] - 2.0) < 2e-3
+    assert abs(jk.sum() - 4.0) < 2e-3
+    assert abs(2.0 * nf["damping"].sum() + math.log(np.linalg.det(nf["J"]))) < 1e-10
+    # the closed orbit is a fixed point of the damped map
+    u = oracle_mod.one_turn(el, EREF, nf["co"], 1, radiation=1)
+    assert np.max(np.abs(u - nf["co"])) < 1e-14
+    nf0 = oracle_mod.normal_form_6d(el, EREF, radiation=0)
+    # without radiation the map is symplectic: no damping beyond the
+    # central differences' truncation
+    assert np.all(np.abs(nf0["damping"]) < 1e-7)
+
+
+def test_matched_gaussian_is_invariant_under_the_map(oracle_mod):
+    """The covariance sum_k eps_k (Re v_k Re v_k^T + Im v_k Im v_k^T) of the
+    matched ensemble is carried into itself by the one-turn map, and the
+    sample covariance of a generated ensemble agrees with it."""
+    el = I.cfg1_lattice()
+    nf = oracle_mod.normal_form_6d(el, I.PROTON_450GEV)
+    eps = [3e-9, 1e-9, 2e-5]
+    sig = np.zeros((6, 6))
+    for k in range(3):
+        a, b = nf["v"][k].real, nf["v"][k].imag
+        sig += eps[k] * (np.outer(a, a) + np.outer(b, b))
+    J = nf["J"]
+    assert np.max(np.abs(J @ sig @ J.T - sig)) < 1e-8 * np.max(np.abs(sig))
+    g = np.random.default_rng(3).normal(size=(200000, 6))
+    c = oracle_mod.matched_gaussian(nf, I.PROTON_450GEV, eps, g)
+    b0, _ = oracle_mod.reference(I.PROTON_450GEV)
+    u = c.copy()
+    # back to pzeta = ptau / beta0 for the comparison
+    d = c[:, 5]
+    u[:, 5] = (d * (2.0 + d)) / (1.0 / b0 + np.sqrt(1.0 / b0 ** 2 + d * (2.0 + d))) / b0
+    cov = np.cov(u.T)
+    for i in range(6):
+        assert abs(cov[i, i] / sig[i, i] - 1) < 0.02, i
