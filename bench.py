@@ -433,7 +433,7 @@ def learned_da(args):
     plain = L.scan(lat, ref, gc, H, tune_turns=tt)
     log(f"plain scan {plain['wall_s']:.1f} s")
     learned = L.scan(lat, ref, gc, H, tw, emit, rap, predictor=pred, tune_turns=tt,
-                     stages=args.stages)
+                     stages=args.stages, keep_decisions=True)
     log(f"learned scan {learned['wall_s']:.1f} s, retired {learned['retired']}")
     if args.no_rule_scan:
         ruled = None
@@ -442,6 +442,36 @@ def learned_da(args):
         log(f"rule scan {ruled['wall_s']:.1f} s, retired {ruled['retired']}")
     nr, nt = args.da_radii, args.da_rays
     e_l = L.da_error(learned["state"], plain["state"], gr, nr, nt)
+    per_ray = L.da_error_per_ray(learned["state"], plain["state"], gr, nr, nt)
+    sub = per_ray[::10]   # the 50-ray sub-grid (every 10th angle)
+    worst = int(np.argmax(per_ray))
+    da_p = P.dynamic_aperture(plain["state"], gr, nr, nt)
+    da_l = P.dynamic_aperture(learned["state"], gr, nr, nt)
+    # the particles whose retirement moved the worst ray's aperture: lost in
+    # plain tracking, retired by the network, inside the learned aperture
+    on_ray = np.arange(worst * nr, (worst + 1) * nr)
+    culprits = [int(i) for i in on_ray
+                if plain["state"][i] in (0, -1) and learned["state"][i] == 2
+                and gr[i] < (da_l[worst] if np.isfinite(da_l[worst]) else np.inf)]
+    dec = learned["decisions"][0]
+    worst_ray = {"ray": worst, "error_sigma": float(per_ray[worst]),
+                 "da_plain": float(da_p[worst]), "da_learned": float(da_l[worst]),
+                 "falsely_retired": [{"particle": i, "radius_sigma": float(gr[i]),
+                                      "lost_at_turn_plain": int(plain["at_turn"][i]),
+                                      "logit": float(dec["score"][i]), "tau": float(dec["tau"]),
+                                      "features": [float(v) for v in dec["features"][i]]}
+                                     for i in culprits[:3]]}
+    false_ret = (learned["state"] == 2) & np.isin(plain["state"], (0, -1))
+    ray_stats = {"grid_500": {"mean": float(per_ray.mean()), "max": float(per_ray.max()),
+                              "q50": float(np.quantile(per_ray, 0.5)),
+                              "q90": float(np.quantile(per_ray, 0.9)),
+                              "q99": float(np.quantile(per_ray, 0.99)),
+                              "rays_above_0.1": int((per_ray > 0.1).sum()),
+                              "rays_above_1": int((per_ray > 1.0).sum())},
+                 "grid_50": {"mean": float(sub.mean()), "max": float(sub.max()),
+                             "rays_above_0.1": int((sub > 0.1).sum())},
+                 "falsely_retired_total": int(false_ret.sum()),
+                 "worst_ray": worst_ray}
     e_r = L.da_error(ruled["state"], plain["state"], gr, nr, nt) if ruled else (None, None)
     da = P.dynamic_aperture(plain["state"], gr, nr, nt)
     keys = ("retired", "audited", "audit_lost", "audit_upper", "fallback", "wall_s")
@@ -460,6 +490,7 @@ def learned_da(args):
                    "stages": args.stages, "windows": max(args.windows, args.stages)},
         "da_error_sigma": {"network_mean": e_l[0], "network_max": e_l[1],
                            "rule_mean": e_r[0], "rule_max": e_r[1]},
+        "da_error_rays": ray_stats,
         "plain": {"wall_s": plain["wall_s"], "da_mean_sigma": float(np.mean(np.where(
             np.isfinite(da), da, args.da_rmax))), "da_min_sigma": float(np.min(da))},
         "network": {k: learned[k] for k in keys if k in learned},

@@ -153,7 +153,8 @@ def rule_scores(feat):
 def scan(lat, ref, coords, horizon: int, twiss4=None, emit=None, r_aperture=None,
          predictor: Predictor | None = None, rule_tau: float | None = None,
          audit_fraction: float = 0.05, audit_seed: int = 0x5EED, fallback_rate: float = 5e-3,
-         first_id: int = 0, tune_turns: int = 0, variant: int = 0, stages: int = 1) -> dict:
+         first_id: int = 0, tune_turns: int = 0, variant: int = 0, stages: int = 1,
+         keep_decisions: bool = False) -> dict:
     """One DA scan.  Plain when neither a predictor nor a rule threshold is
     given; otherwise learned (network) or rule-based early stop, decided at
     the end of each of the first `stages` 1024-turn windows.  Returns the
@@ -165,7 +166,9 @@ def scan(lat, ref, coords, horizon: int, twiss4=None, emit=None, r_aperture=None
     still tracked, for that many turns, and the stretch runs with the
     fastest (inside the timed wall time; results are the same bit for bit).
     The plan stays set on the lattice afterwards.  variant != 0 runs that
-    tracking kernel throughout instead (see xtm_track_opts.variant)."""
+    tracking kernel throughout instead (see xtm_track_opts.variant).
+    keep_decisions: also return each decision's scores and features (host
+    arrays, indexed by particle) for analysis."""
     import torch
     n = len(coords)
     coords_dev = torch.as_tensor(np.ascontiguousarray(coords), device="cuda")
@@ -192,6 +195,9 @@ def scan(lat, ref, coords, horizon: int, twiss4=None, emit=None, r_aperture=None
                 score, tau = P.rule_score(feat), rule_tau
             retired, audited = P.retire(parts, score, tau, audit_seed, audit_fraction,
                                         audit_flags=audit_flags)
+            if keep_decisions:
+                out.setdefault("decisions", []).append(
+                    {"score": score.cpu().numpy(), "features": feat.cpu().numpy(), "tau": tau})
             out["retired"] += retired
             out["stages"].append({"turn": (k + 1) * RECORD_TURNS, "tau": float(tau),
                                   "retired": retired, "audited": audited,
@@ -214,13 +220,18 @@ def scan(lat, ref, coords, horizon: int, twiss4=None, emit=None, r_aperture=None
     return out
 
 
-def da_error(state_a, state_b, radius, n_r: int, n_theta: int) -> tuple[float, float]:
-    """Mean and max over rays of |DA_a - DA_b| in sigma (rays with no loss on
-    either side are censored at the scan edge)."""
+def da_error_per_ray(state_a, state_b, radius, n_r: int, n_theta: int) -> np.ndarray:
+    """|DA_a - DA_b| in sigma for every ray (rays with no loss on either side
+    censored at the scan edge)."""
     da_a = P.dynamic_aperture(state_a, radius, n_r, n_theta)
     da_b = P.dynamic_aperture(state_b, radius, n_r, n_theta)
     edge = float(np.max(radius))
     a = np.where(np.isfinite(da_a), da_a, edge)
     b = np.where(np.isfinite(da_b), da_b, edge)
-    d = np.abs(a - b)
+    return np.abs(a - b)
+
+
+def da_error(state_a, state_b, radius, n_r: int, n_theta: int) -> tuple[float, float]:
+    """Mean and max over rays of |DA_a - DA_b| in sigma."""
+    d = da_error_per_ray(state_a, state_b, radius, n_r, n_theta)
     return float(d.mean()), float(d.max())
