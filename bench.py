@@ -506,6 +506,58 @@ def learned_da(args):
           flush=True)
 
 
+def mlp_bench(args):
+    """The loss predictor's kernels alone: inference on 2^20 feature rows and
+    training steps (gradient + Adam) on batches of 4,096, timed with events;
+    BF16 MFMA work per sample 37,120 FLOP forward (2 (16 x 128 + 128 x 128 +
+    128)), about three times that for a training sample."""
+    import torch
+    import paper_2310_00317_amd as P
+    rng = np.random.default_rng(5)
+    n = args.particles or (1 << 20)
+    X = torch.tensor(rng.normal(size=(n, 16)).astype(np.float32), device="cuda")
+    Y = torch.tensor((rng.random(4096) < 0.6).astype(np.float32), device="cuda")
+    theta = P.mlp_init(3)
+    norm = P.feature_stats(X)
+    m, v = torch.zeros_like(theta), torch.zeros_like(theta)
+    work = torch.empty(P.mlp_workspace(4096), dtype=torch.float32, device="cuda")
+    Xb = X[:4096].contiguous()
+    for _ in range(3):
+        P.mlp_forward(theta, norm, X)
+        g, _ = P.mlp_grad(theta, norm, Xb, Y, 1.5, work=work)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 20
+    a.record()
+    for _ in range(reps):
+        P.mlp_forward(theta, norm, X)
+    b.record()
+    torch.cuda.synchronize()
+    fwd_ms = a.elapsed_time(b) / reps
+    steps = 200
+    a.record()
+    for k in range(steps):
+        g, _ = P.mlp_grad(theta, norm, Xb, Y, 1.5, work=work)
+        P.mlp_adam(theta, m, v, g, k + 1, 1e-3)
+    b.record()
+    torch.cuda.synchronize()
+    step_ms = a.elapsed_time(b) / steps
+    fwd_flop = 2.0 * (16 * 128 + 128 * 128 + 128)
+    peak = 2500.0
+    out = {"metric": "loss-predictor inference rows/s (BF16 MFMA, FP32 accumulate)",
+           "value": n / (fwd_ms / 1e3), "unit": "rows/s", "n_gpus": 1, "higher_is_better": True,
+           "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
+           "config": {"workload": f"MLP 16-128-128-1, {n} rows forward; training batches of "
+                                  "4096 (gradient + Adam)"},
+           "forward_ms": fwd_ms, "train_step_ms": step_ms,
+           "roofline": {"bound": "mfma", "achieved": n * fwd_flop / (fwd_ms / 1e3) / 1e12,
+                        "peak": peak, "unit": "TFLOP/s",
+                        "frac": n * fwd_flop / (fwd_ms / 1e3) / 1e12 / peak,
+                        "traffic": None, "kernel": "k_mlp_forward"},
+           "train_tflops": 3 * 4096 * fwd_flop / (step_ms / 1e3) / 1e12}
+    print(json.dumps(out), flush=True)
+
+
 def timed_steps(parts, run, steps: int, tps: int, log: bool = False) -> dict:
     """Time `steps` calls of run(parts, tps) between two events on the current
     stream (inputs resident in HBM); the library times each tracking launch
@@ -577,7 +629,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--turns-per-step", type=int, default=None)
     ap.add_argument("--workload", default="cfg2",
-                    choices=["cfg2", "cfg1", "cfg1sat", "cfg3", "cfg4", "cfg5", "refine",
+                    choices=["cfg2", "cfg1", "cfg1sat", "cfg3", "cfg4", "cfg5", "mlp", "refine",
                              "twiss", "thick"])
     ap.add_argument("--refine-vertices", type=int, default=64,
                     help="refine: polygon vertices per aperture")
@@ -653,6 +705,8 @@ def main():
         return
     if args.workload == "cfg4":
         return learned_da(args)
+    if args.workload == "mlp":
+        return mlp_bench(args)
     if args.workload == "refine":
         return refine_bench(args)
     if args.workload == "twiss":

@@ -41,16 +41,18 @@ __device__ __forceinline__ f32x4 mfma16(bf16x4 a, bf16x4 b, f32x4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
 }
 
-// W1 and the vectors live in LDS; W2 (64 KB in FP32) is read from global
-// memory (L2-resident) and rounded to BF16 as it is loaded into operands.
+// The network lives in LDS for the whole block: W1 and W2 rounded to BF16
+// once (36 KB), the bias vectors and w3 in FP32.
 struct NetLds {
   unsigned short w1[kIn * kH];   // bf16 W1[k][n]
+  unsigned short w2[kH * kH];    // bf16 W2[k][n]
   float b1[kH], b2[kH], w3[kH];  // w3 already rounded to bf16 values
   float b3;
 };
 
 __device__ void load_net(NetLds& s, const float* __restrict__ th) {
   for (int i = threadIdx.x; i < kIn * kH; i += blockDim.x) s.w1[i] = to_bf16(th[oW1 + i]);
+  for (int i = threadIdx.x; i < kH * kH; i += blockDim.x) s.w2[i] = to_bf16(th[oW2 + i]);
   for (int i = threadIdx.x; i < kH; i += blockDim.x) {
     s.b1[i] = th[oB1 + i];
     s.b2[i] = th[oB2 + i];
@@ -64,8 +66,8 @@ __device__ void load_net(NetLds& s, const float* __restrict__ th) {
 // block-local arrays, and returns z3 for lane l < 16 (sample s0 + l).
 // The ReLU masks are read back from the activations: bf16(relu(z)) != 0 iff
 // z > 0 (only z below half the smallest bf16 subnormal would differ).
-__device__ float wave_forward(const NetLds& net, const float* __restrict__ th,
-                              const float* __restrict__ X, const float* __restrict__ norm,
+__device__ float wave_forward(const NetLds& net, const float* __restrict__ X,
+                              const float* __restrict__ norm,
                               int64_t B, int64_t s0, int r0, unsigned short (*sx)[kIn],
                               unsigned short (*h1)[kH], unsigned short (*h2)[kH]) {
   const int l = threadIdx.x & 63;
@@ -98,7 +100,7 @@ __device__ float wave_forward(const NetLds& net, const float* __restrict__ th,
       bf16x4 aa, b;
       for (int j = 0; j < 4; ++j) {
         aa[j] = (short)h1[r0 + row][kt * 16 + 4 * quad + j];
-        b[j] = (short)to_bf16(th[oW2 + (kt * 16 + 4 * quad + j) * kH + nt * 16 + row]);
+        b[j] = (short)net.w2[(kt * 16 + 4 * quad + j) * kH + nt * 16 + row];
       }
       c = mfma16(aa, b, c);
     }
@@ -125,6 +127,9 @@ struct FwdLds {
   unsigned short h2[kSamplesPerBlock][kH];
 };
 
+// Each block loads the network once and then runs 64-sample tiles
+// blockIdx.x, blockIdx.x + gridDim.x, ... (the loop bound is uniform over
+// the block, so every wave meets the same barriers).
 __global__ void __launch_bounds__(256) k_mlp_forward(const float* __restrict__ theta,
                                                      const float* __restrict__ norm,
                                                      const float* __restrict__ X, int64_t B,
@@ -133,9 +138,13 @@ __global__ void __launch_bounds__(256) k_mlp_forward(const float* __restrict__ t
   load_net(s.net, theta);
   __syncthreads();
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-  const int64_t s0 = (int64_t)blockIdx.x * kSamplesPerBlock + 16 * w;
-  const float z = wave_forward(s.net, theta, X, norm, B, s0, 16 * w, s.x, s.h1, s.h2);
-  if (l < 16 && s0 + l < B) logit[s0 + l] = z;
+  const int64_t n_tiles = (B + kSamplesPerBlock - 1) / kSamplesPerBlock;
+  for (int64_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
+    const int64_t s0 = t * kSamplesPerBlock + 16 * w;
+    const float z = wave_forward(s.net, X, norm, B, s0, 16 * w, s.x, s.h1, s.h2);
+    if (l < 16 && s0 + l < B) logit[s0 + l] = z;
+    __syncthreads();
+  }
 }
 
 struct GradLds {
@@ -164,7 +173,7 @@ __global__ void __launch_bounds__(256) k_mlp_grad(const float* __restrict__ thet
   const int row = l & 15, quad = l >> 4;
   const int64_t base = (int64_t)blockIdx.x * kSamplesPerBlock;
   const int64_t s0 = base + 16 * w;
-  const float z = wave_forward(s.net, theta, X, norm, B, s0, 16 * w, s.x, s.h1, s.h2);
+  const float z = wave_forward(s.net, X, norm, B, s0, 16 * w, s.x, s.h1, s.h2);
   if (l < 16) {
     const int64_t si = s0 + l;
     float d = 0.f, lv = 0.f;
@@ -212,7 +221,7 @@ __global__ void __launch_bounds__(256) k_mlp_grad(const float* __restrict__ thet
       bf16x4 a, b;
       for (int j = 0; j < 4; ++j) {
         a[j] = (short)s.dz2[16 * w + row][kt * 16 + 4 * quad + j];
-        b[j] = (short)to_bf16(theta[oW2 + (nt * 16 + row) * kH + kt * 16 + 4 * quad + j]);
+        b[j] = (short)s.net.w2[(nt * 16 + row) * kH + kt * 16 + 4 * quad + j];
       }
       c = mfma16(a, b, c);
     }
@@ -491,37 +500,45 @@ __global__ void __launch_bounds__(256) k_features(const float* __restrict__ rec,
   }
 }
 
-// Column mean and 1/std of features over rows with mask != 0 (single
-// workgroup, fixed reduction order); norm = [mean[16], inv_std[16]].
+// Column mean and 1/std of features over rows with mask != 0 (one
+// workgroup, fixed reduction order): thread t accumulates rows t, t + 256,
+// ... (each row's 16 values from one 64-byte stretch), then the
+// 33 sums are reduced pairwise across the workgroup; norm = [mean[16],
+// inv_std[16]].
 __global__ void __launch_bounds__(256) k_feature_stats(const float* __restrict__ f,
                                                        const int32_t* __restrict__ mask,
                                                        int64_t n, float* __restrict__ norm) {
-  __shared__ double acc[3][256];
+  __shared__ double acc[33][256];
+  double s1[16], s2[16], cnt = 0.0;
+  for (int c = 0; c < 16; ++c) s1[c] = s2[c] = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+    if (mask && !mask[i]) continue;
+    const float* row = f + i * 16;
+    for (int c = 0; c < 16; ++c) {
+      const double v = row[c];
+      s1[c] += v;
+      s2[c] += v * v;
+    }
+    cnt += 1.0;
+  }
   for (int c = 0; c < 16; ++c) {
-    double s1 = 0.0, s2 = 0.0, cnt = 0.0;
-    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
-      if (mask && !mask[i]) continue;
-      const double v = f[i * 16 + c];
-      s1 += v;
-      s2 += v * v;
-      cnt += 1.0;
-    }
-    acc[0][threadIdx.x] = s1;
-    acc[1][threadIdx.x] = s2;
-    acc[2][threadIdx.x] = cnt;
+    acc[c][threadIdx.x] = s1[c];
+    acc[16 + c][threadIdx.x] = s2[c];
+  }
+  acc[32][threadIdx.x] = cnt;
+  __syncthreads();
+  for (int st = blockDim.x / 2; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st)
+      for (int k = 0; k < 33; ++k) acc[k][threadIdx.x] += acc[k][threadIdx.x + st];
     __syncthreads();
-    for (int st = blockDim.x / 2; st > 0; st >>= 1) {
-      if ((int)threadIdx.x < st)
-        for (int k = 0; k < 3; ++k) acc[k][threadIdx.x] += acc[k][threadIdx.x + st];
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-      const double m = acc[2][0] > 0 ? acc[0][0] / acc[2][0] : 0.0;
-      const double var = acc[2][0] > 0 ? acc[1][0] / acc[2][0] - m * m : 1.0;
-      norm[c] = (float)m;
-      norm[16 + c] = (float)(1.0 / sqrt(var > 1e-30 ? var : 1.0));
-    }
-    __syncthreads();
+  }
+  if (threadIdx.x < 16) {
+    const int c = threadIdx.x;
+    const double nn = acc[32][0];
+    const double m = nn > 0 ? acc[c][0] / nn : 0.0;
+    const double var = nn > 0 ? acc[16 + c][0] / nn - m * m : 1.0;
+    norm[c] = (float)m;
+    norm[16 + c] = (float)(1.0 / sqrt(var > 1e-30 ? var : 1.0));
   }
 }
 
@@ -592,7 +609,9 @@ hipError_t launch_gather_rows(const float* X, const float* Y, const int32_t* per
 hipError_t launch_mlp_forward(const float* theta, const float* norm, const float* X, int64_t B,
                               float* logit, hipStream_t s) {
   if (B <= 0) return hipSuccess;
-  const unsigned nb = (unsigned)((B + kSamplesPerBlock - 1) / kSamplesPerBlock);
+  // at most two blocks per compute unit: each loads the network once
+  const int64_t tiles = (B + kSamplesPerBlock - 1) / kSamplesPerBlock;
+  const unsigned nb = (unsigned)(tiles < 512 ? tiles : 512);
   hipLaunchKernelGGL(k_mlp_forward, dim3(nb), dim3(256), 0, s, theta, norm, X, B, logit);
   return hipGetLastError();
 }
