@@ -43,17 +43,40 @@ __device__ __forceinline__ void refresh(Pt& q, double beta0) {
 //   in one family: a divisor whose significand is all ones (b = 2^k (2 -
 //   2^-52)) and a power-of-two numerator, where the exact q + r (a - b q) is
 //   a tie.  Callers keep that family out (the drift's window below).
-__device__ __forceinline__ double sqrt_in(double x) {
+//   div_by_root: a / sqrt_in(x) with the reciprocal taken from the square
+//   root's own iteration: after Goldschmidt's step h approximates
+//   1/(2 sqrt x) about as closely as one Newton step from the hardware
+//   reciprocal would (both estimates are within 2^-24 of their values, so
+//   either is within about 2^-47 after it), and one Newton step on 2h, the
+//   product and Markstein's step follow as in div_in (the same exclusions).
+//   This takes the reciprocal estimate and one dependent Newton step off the
+//   chain from the square root to the quotient.
+__device__ __forceinline__ double sqrt_in(double x, double& h_out) {
   const double y = __builtin_amdgcn_rsq(x);
   double g = x * y;
   double h = y * 0.5;
   const double r = fma(-h, g, 0.5);
   g = fma(g, r, g);
   h = fma(h, r, h);
+  h_out = h;
   double d = fma(-g, g, x);
   g = fma(d, h, g);
   d = fma(-g, g, x);
   return fma(d, h, g);
+}
+
+__device__ __forceinline__ double sqrt_in(double x) {
+  double h;
+  return sqrt_in(x, h);
+}
+
+__device__ __forceinline__ double div_by_root(double a, double root, double h) {
+  double r = 2.0 * h;
+  const double e = fma(-root, r, 1.0);
+  r = fma(r, e, r);
+  const double q = a * r;
+  const double rho = fma(-root, q, a);
+  return fma(rho, r, q);
 }
 
 __device__ __forceinline__ double div_in(double a, double b) {
@@ -109,9 +132,10 @@ __device__ __forceinline__ void drift_apply(Pt& q, double lp, double dq) {
 // particle the results are NaN and unused).
 __device__ __forceinline__ void drift_quotients(double L, const DriftIn& d, bool any_length,
                                                 double& lp, double& dq, bool& fast) {
-  const double pz = sqrt_in(d.pz2);
+  double h;
+  const double pz = sqrt_in(d.pz2, h);
   const double b1 = 1.0 + pz;
-  lp = div_in(L, pz);
+  lp = div_by_root(L, pz, h);
   dq = div_in(d.a, b1);
   fast = !any_length & drift_window(d) & (b1 != 0x1.fffffffffffffp+0);
 }
