@@ -14,6 +14,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -45,10 +46,10 @@ TRAFFIC_SOURCES = ("xtm_jit.cpp", "xtm_maps.h")
 MEASURED_TRAFFIC = {
     # (workload, particles, turns per step, kernel variant, source hash):
     #     (bytes per launch, profile)
-    ("cfg2", 100000, 1000, 10, "e607783bd40dbf2c"):
-        (21453937.0, "profiles/xtm_line_cfg2_hbm_counters.txt"),
-    ("cfg1sat", 1048576, 1000, 10, "e607783bd40dbf2c"):
-        (189112442.0, "profiles/xtm_line_cfg2_hbm_counters.txt"),
+    ("cfg2", 100000, 1000, 10, "61415f6179fc1dda"):
+        (21458222.0, "profiles/xtm_line_cfg2_hbm_counters.txt"),
+    ("cfg1sat", 1048576, 1000, 10, "61415f6179fc1dda"):
+        (189123160.0, "profiles/xtm_line_cfg2_hbm_counters.txt"),
 }
 
 
@@ -506,6 +507,74 @@ def learned_da(args):
           flush=True)
 
 
+def radiation_equilibrium(args):
+    """The electron ring's radiation equilibrium at scale: an ensemble matched
+    to the 6D normal form, tracked `--eq-turns` turns (five longitudinal
+    damping times by default) with quantum excitation (Gaussian or photon by
+    photon); the energy spread of the last tenth of the run, the energy loss
+    per turn of a particle on the design orbit through the ring without its
+    cavities, and the longitudinal damping time of the normal form, each
+    beside its closed form: U0 = (2/3) r m gamma^4 sum h^2 L_r, sigma_delta^2 =
+    C_q gamma^2 h / J_z (identical bends, C_q = 55 hbar_c / (32 sqrt 3 m c^2)),
+    tau_z = 2 E0 / (J_z U0) turns with J_z = 2."""
+    import torch
+    import paper_2310_00317_amd as P
+    from paper_2310_00317_amd import inputs as I
+    ref = I.ELECTRON_45GEV6
+    el = I.cfg5_lattice()
+    lat = P.Lattice(el, ref)
+    n = args.particles or 100_000
+    nf = P.twiss6d(lat, radiation=1)
+    c = P.matched_gaussian(nf, ref, I.CFG5_EMITTANCES, I.standard_normals(n))
+    parts = P.Particles(n, ref).init(c)
+    seed = 20231003
+    turns = args.eq_turns
+    chunk = 100
+    samples = []
+    t0 = time.perf_counter()
+    for k in range(turns // chunk):
+        P.track(lat, parts, chunk, radiation=args.radiation, seed=seed)
+        if (k + 1) * chunk > 0.9 * turns:
+            samples.append(float(parts.delta[:n].std().cpu()))
+        if k % 10 == 9:
+            print(f"[eq] {(k + 1) * chunk} turns, sigma_delta {float(parts.delta[:n].std().cpu()):.4e}",
+                  file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    alive = int((parts.state[:n] == 1).sum().cpu())
+    # energy loss per turn on the design orbit, cavities removed (mean model)
+    no_rf = el[el["type"] != I.RF]
+    lat0 = P.Lattice(no_rf, ref)
+    one = P.Particles(1, ref).init(np.zeros((1, 6)))
+    P.track(lat0, one, 1, radiation=1)
+    e0 = math.sqrt(ref.p0c_eV ** 2 + ref.mass0_eV ** 2)
+    b0 = ref.p0c_eV / e0
+    g0 = e0 / ref.mass0_eV
+    u0_meas = -float(one.ptau[0].cpu()) * ref.p0c_eV
+    bends = el[(el["type"] == I.MULTIPOLE) & (el["length"] > 0)]
+    h = np.abs(bends["knl"][:, 0]) / bends["length"]
+    u0_cf = 2.0 / 3.0 * I.R_ELECTRON * I.ELECTRON_MASS_EV * g0 ** 4 * float(np.sum(h * h * bends["length"]))
+    cq = 55.0 / (32.0 * math.sqrt(3.0)) * I.HBAR_C_EVM / I.ELECTRON_MASS_EV
+    jz = 2.0
+    sd_cf = math.sqrt(cq * g0 ** 2 * float(h[0]) / jz)
+    tau_nf = 1.0 / nf.damping[2]
+    tau_cf = 2.0 * e0 / (jz * u0_cf)
+    out = {"metric": "radiation equilibrium of the electron ring against closed forms",
+           "value": float(np.mean(samples)) / sd_cf, "unit": "sigma_delta / closed form",
+           "n_gpus": 1, "higher_is_better": None, "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic",
+           "config": {"workload": f"electron ring, 20,000 thin elements, {n} electrons at 45.6 GeV "
+                                  f"matched to the 6D normal form, {turns} turns, radiation "
+                                  f"{'photon by photon' if args.radiation == 3 else 'mean + Gaussian quantum'}"},
+           "sigma_delta": {"tracked": float(np.mean(samples)), "closed_form": sd_cf},
+           "u0_eV": {"tracked": u0_meas, "closed_form": u0_cf},
+           "tau_z_turns": {"normal_form": tau_nf, "closed_form": tau_cf},
+           "partition_numbers": [float(d / (u0_cf / (2 * e0))) for d in nf.damping[:]],
+           "alive_at_end": alive, "wall_s": wall,
+           "passes_per_s": n * len(el) * turns / wall}
+    print(json.dumps(out), flush=True)
+
+
 def mlp_bench(args):
     """The loss predictor's kernels alone: inference on 2^20 feature rows and
     training steps (gradient + Adam) on batches of 4,096, timed with events;
@@ -674,6 +743,10 @@ def main():
                     help="cfg3: track the variants one after another, each with its own "
                          "lattice and particle set, instead of one batched launch per chunk")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--equilibrium", action="store_true",
+                    help="cfg5: track a matched ensemble to equilibrium and compare the energy "
+                         "spread, energy loss and damping time with their closed forms")
+    ap.add_argument("--eq-turns", type=int, default=5000)
     ap.add_argument("--radiation", type=int, default=2, choices=[1, 2, 3],
                     help="cfg5: 1 mean loss, 2 mean + Gaussian quantum excitation, "
                          "3 photon by photon")
@@ -707,6 +780,8 @@ def main():
         return learned_da(args)
     if args.workload == "mlp":
         return mlp_bench(args)
+    if args.workload == "cfg5" and args.equilibrium:
+        return radiation_equilibrium(args)
     if args.workload == "refine":
         return refine_bench(args)
     if args.workload == "twiss":
