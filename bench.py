@@ -46,9 +46,9 @@ TRAFFIC_SOURCES = ("xtm_jit.cpp", "xtm_maps.h")
 MEASURED_TRAFFIC = {
     # (workload, particles, turns per step, kernel variant, source hash):
     #     (bytes per launch, profile)
-    ("cfg2", 100000, 1000, 10, "61415f6179fc1dda"):
+    ("cfg2", 100000, 1000, 10, "2c474f0b7de7e195"):
         (21458222.0, "profiles/xtm_line_cfg2_hbm_counters.txt"),
-    ("cfg1sat", 1048576, 1000, 10, "61415f6179fc1dda"):
+    ("cfg1sat", 1048576, 1000, 10, "2c474f0b7de7e195"):
         (189123160.0, "profiles/xtm_line_cfg2_hbm_counters.txt"),
 }
 
@@ -257,7 +257,7 @@ def refine_bench(args):
                                f"100,000-particle grid tracked {turns} turns)",
                    "n_particles": n, "n_lost": n_lost, "n_vertices": M, "ds": ds,
                    "n_bisect": nb, "polygon_tests": total_tests, "wall_s": wall},
-        "roofline": {"bound": "alu", "kernel": "k_refine (one thread per particle)",
+        "roofline": {"bound": "alu", "kernel": "k_refine (one wave per lost particle)",
                      "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": None,
                      "flops_per_test": flops_per_test, "avg_launch_ms": avg_ms,
@@ -328,8 +328,9 @@ def twiss_bench(args):
                                "errors), 4D uncoupled, delta0 = 0",
                    "n_elements": len(el), "newton_steps": tw["iterations"],
                    "particle_turns": turns, "qx": tw["qx"], "qy": tw["qy"], "wall_s": wall},
-        "roofline": {"bound": "alu", "kernel": "k_record (one thread per particle, 9 or 11 "
-                                               "particles: one wave, latency-bound)",
+        "roofline": {"bound": "alu", "kernel": "xtm_record (generated recording kernel, one "
+                                               "thread per particle, 9 or 11 particles: one "
+                                               "wave, latency-bound)",
                      "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": None,
                      "flops_per_call": flops},

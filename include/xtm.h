@@ -305,11 +305,15 @@ xtm_status xtm_refine_losses(xtm_lattice lat, xtm_particles p, int32_t n_vertice
    "Twiss module": the lattice is probed by tracking).  d_in: device (n, 6)
    rows (x, px, y, py, zeta, delta), set up as by xtm_particles_init;
    d_out: device (n_el + 1) x n x 6, element-major: d_out[(e n + i) 6 + c]
-   holds particle i entering element e (e = n_el: after the turn).
+   holds particle i entering element e (e = n_el: after the turn); 16-byte
+   aligned (XTM_E_ARG otherwise).
    Apertures are not checked (optics of the bare lattice); a particle whose
    longitudinal momentum becomes imaginary in a drift keeps the coordinates
-   it entered that drift with; no radiation.  One thread per particle;
-   stream-ordered. */
+   it entered that drift with; no radiation.  One thread per particle, in
+   a kernel generated from the lattice's cell structure and compiled at the
+   lattice's first call (as the per-line tracking kernels; a line without a
+   cell decomposition runs the element interpreter, with the same maps and
+   records); stream-ordered. */
 xtm_status xtm_track_record(xtm_lattice lat, const double* d_in, int64_t n, double* d_out,
                             void* stream);
 

@@ -77,8 +77,12 @@ struct xtm_lattice_s {
   std::vector<int32_t> fwd_seg_h, bwd_seg_h;
   int32_t* fwd_seg_d = nullptr;
   int32_t* bwd_seg_d = nullptr;
-  // per-line kernels, compiled on first use
-  xtm::LineKernel fwd_line[xtm::kLineStyles], bwd_line[xtm::kLineStyles];
+  // per-line kernels, compiled on first use: forward ones for each radiation
+  // form, backward ones (never radiating)
+  bool radiates = false;  // the line holds radiating multipoles
+  xtm::LineKernel fwd_line[xtm::kRadForms][xtm::kLineStyles], bwd_line[xtm::kLineStyles];
+  // generated recording kernel of optics by tracking, compiled on first use
+  xtm::LineKernel rec_line;
   // launch plan chosen by xtm_autotune (0 = none): kernel form and block
   // used when the caller's options leave both at 0, turns per chunk and
   // compaction period when the caller leaves those at 0
@@ -105,9 +109,9 @@ struct xtm_batch_s {
   int32_t plan_variant = 0;
   int32_t plan_chunk = 0;
   int32_t plan_compact_every = 0;
-  // batched per-line kernels (one-wave forms), built on first use when every
-  // variant has the same element structure
-  xtm::LineKernel line[xtm::kLineStyles];
+  // batched per-line kernels (one-wave forms) for each radiation form, built
+  // on first use when every variant has the same element structure
+  xtm::LineKernel line[xtm::kRadForms][xtm::kLineStyles];
 };
 
 struct GraphKey {
@@ -172,14 +176,15 @@ xtm_status pack(const xtm_element_desc& e, int32_t index, const RefQ& r, double 
     case XTM_DRIFT_EXPANDED:
       if (!std::isfinite(e.length)) return fail(XTM_E_ELEMENT, where + "non-finite drift length");
       if (e.type == XTM_DRIFT) {
-        // order 0: a length the device's short quotient sequence serves for
-        // every momentum (|L| in [2^-600, 2^600] and not a power of two);
-        // order 1: any other length, zero included (generic division)
+        // the length's class for the device's short quotient sequence:
+        // 0, |L| in [2^-600, 2^600] and not a power of two (served for every
+        // momentum); 1, a power of two in that range (served unless pz has
+        // an all-ones significand); 2, any other length, zero included
+        // (generic division)
         int ex = 0;
         const double m = std::frexp(std::fabs(e.length), &ex);
-        const bool short_ok = std::fabs(e.length) >= 0x1p-600 && std::fabs(e.length) <= 0x1p600 &&
-                              m != 0.5;
-        hdr(K_DRIFT, short_ok ? 0 : 1, 1);
+        const bool in_range = std::fabs(e.length) >= 0x1p-600 && std::fabs(e.length) <= 0x1p600;
+        hdr(K_DRIFT, in_range ? (m != 0.5 ? 0 : 1) : 2, 1);
       } else {
         hdr(K_DRIFT_EXP, 0, 1);
       }
@@ -547,15 +552,17 @@ xtm_status run_turns(xtm_lattice_s* L, xtm_particles_s* P, int32_t n_turns,
     // the register-loss interpreter if the line has no compact cell structure
     // (a batch: if its variants differ in element structure)
     const int32_t want = c.variant ? c.variant : default_line_variant(P->alive_upper);
-    LineKernel& lk = B ? B->line[want - 5] : (backward ? L->bwd_line : L->fwd_line)[want - 5];
+    const int32_t form = rad_form(L->radiates, c.rad_mode);
+    LineKernel& lk = B ? B->line[form][want - 5]
+                       : (backward ? L->bwd_line[want - 5] : L->fwd_line[form][want - 5]);
     if (!lk.tried && L->n_el > 0) {
       lk.tried = true;
       if (B) {
         std::vector<const std::vector<uint64_t>*> tabs;
         for (const xtm_lattice_s* l : B->lats) tabs.push_back(&l->fwd_h);
-        build_line_kernel_multi(tabs, L->n_el, want - 5, true, &lk);
+        build_line_kernel_multi(tabs, L->n_el, want - 5, true, form, &lk);
       } else {
-        build_line_kernel(backward ? L->bwd_h : L->fwd_h, L->n_el, want - 5, &lk);
+        build_line_kernel(backward ? L->bwd_h : L->fwd_h, L->n_el, want - 5, form, &lk);
       }
     }
     if (lk.ok) {
@@ -729,6 +736,7 @@ xtm_status xtm_lattice_create(const xtm_element_desc* el, int32_t n, const xtm_r
       xtm_status st = pack(L->desc_h[i], L->user_h[i], r, -1.0, L->bwd_h);
       if (st != XTM_OK) { delete L; return st; }
     }
+    L->radiates = table_radiates(L->fwd_h, n);
     L->fwd_seg_h = segment(L->fwd_h, n);
     L->bwd_seg_h = segment(L->bwd_h, n);
     const size_t sbytes = L->fwd_seg_h.size() * sizeof(int32_t);
@@ -770,9 +778,10 @@ xtm_status xtm_lattice_destroy(xtm_lattice L) {
   hipFree(L->bwd_seg_d);
   hipFree(L->refine_buf);
   for (int32_t k = 0; k < kLineStyles; ++k) {
-    free_line_kernel(&L->fwd_line[k]);
+    for (int32_t f = 0; f < kRadForms; ++f) free_line_kernel(&L->fwd_line[f][k]);
     free_line_kernel(&L->bwd_line[k]);
   }
+  free_line_kernel(&L->rec_line);
   delete L;
   return XTM_OK;
 }
@@ -1020,7 +1029,8 @@ xtm_status xtm_batch_create(const xtm_lattice* lattices, int32_t n_variants, xtm
 
 xtm_status xtm_batch_destroy(xtm_batch B) {
   if (!B) return XTM_OK;
-  for (int32_t k = 0; k < kLineStyles; ++k) free_line_kernel(&B->line[k]);
+  for (int32_t f = 0; f < kRadForms; ++f)
+    for (int32_t k = 0; k < kLineStyles; ++k) free_line_kernel(&B->line[f][k]);
   hipFree(B->tabs_d);
   hipFree(B->first_d);
   delete B;
@@ -1150,13 +1160,14 @@ xtm_status xtm_autotune(xtm_lattice L, xtm_batch B, xtm_particles P, const int64
         for (const xtm_lattice_s* l : B->lats) tabs.push_back(&l->fwd_h);
       for (int32_t k = 0; k < kLineStyles; ++k) {
         if (B && line_block(k) != 64) continue;  // batches: the one-wave forms
-        LineKernel& lk = B ? B->line[k] : lat->fwd_line[k];
+        // the probes track without radiation
+        LineKernel& lk = B ? B->line[0][k] : lat->fwd_line[0][k];
         if (!lk.tried) {
           lk.tried = true;
           if (B)
-            build_line_kernel_multi(tabs, lat->n_el, k, true, &lk);
+            build_line_kernel_multi(tabs, lat->n_el, k, true, 0, &lk);
           else
-            build_line_kernel(lat->fwd_h, lat->n_el, k, &lk);
+            build_line_kernel(lat->fwd_h, lat->n_el, k, 0, &lk);
         }
         if (lk.ok) variants.push_back(5 + k);
       }
@@ -1880,6 +1891,24 @@ bool solve_i_minus(const double A[4][4], const double b[4], double x[4]) {
   }
   return true;
 }
+// One recorded turn (the coordinates at every element's entry and after the
+// last): the generated recording kernel, compiled on the lattice's first
+// call, or the element interpreter (k_record) for a line without a cell
+// decomposition.  Both apply the same maps, so the records are the same.
+// all_rows = false: only the row after the turn is needed (the generated
+// kernel then stores only that row; the interpreter stores every row).
+hipError_t record_turn(xtm_lattice_s* L, const double* d_in, int64_t n, double* d_out,
+                       hipStream_t s, bool all_rows = true) {
+  if (!L->rec_line.tried && L->n_el > 0) {
+    L->rec_line.tried = true;
+    build_record_kernel(L->fwd_h, L->n_el, &L->rec_line);
+  }
+  if (L->rec_line.ok)
+    return launch_line_record(L->rec_line, L->n_el, d_in, n, d_out, all_rows,
+                              kref(L->ref, 0, 0), s);
+  return launch_record(L->fwd_d, L->fwd_seg_d, (int32_t)(L->fwd_seg_h.size() / 3), L->n_el, d_in,
+                       n, d_out, kref(L->ref, 0, 0), s);
+}
 }  // namespace
 
 xtm_status xtm_track_record(xtm_lattice L, const double* d_in, int64_t n, double* d_out,
@@ -1888,8 +1917,8 @@ xtm_status xtm_track_record(xtm_lattice L, const double* d_in, int64_t n, double
     if (!L) return fail(XTM_E_ARG, "null lattice");
     if (n < 0 || n > 65536) return fail(XTM_E_ARG, "n must be in 0..65536");
     if (n > 0 && (!d_in || !d_out)) return fail(XTM_E_ARG, "null array");
-    HIP_TRY(launch_record(L->fwd_d, L->fwd_seg_d, (int32_t)(L->fwd_seg_h.size() / 3), L->n_el,
-                          d_in, n, d_out, kref(L->ref, 0, 0), (hipStream_t)stream),
+    if (((uintptr_t)d_out & 15u) != 0) return fail(XTM_E_ARG, "d_out must be 16-byte aligned");
+    HIP_TRY(record_turn(L, d_in, n, d_out, (hipStream_t)stream),
             "record launch");
     return XTM_OK;
   });
@@ -1934,8 +1963,7 @@ xtm_status xtm_twiss(xtm_lattice L, double delta0, double h, double hd, int32_t 
       }
       if (hipMemcpyAsync(d_in, c, m * 6 * sizeof(double), hipMemcpyHostToDevice, s) != hipSuccess)
         return fail(XTM_E_HIP, "twiss upload");
-      if (launch_record(L->fwd_d, L->fwd_seg_d, (int32_t)(L->fwd_seg_h.size() / 3), n_el, d_in, m,
-                        d_out, kref(L->ref, 0, 0), s) != hipSuccess)
+      if (record_turn(L, d_in, m, d_out, s, all_rows) != hipSuccess)
         return fail(XTM_E_HIP, "twiss record launch");
       const size_t first = all_rows ? 0 : (size_t)n_el * m * 6;
       const size_t cnt = (all_rows ? (size_t)(n_el + 1) : 1) * m * 6;
@@ -2130,8 +2158,7 @@ xtm_status xtm_twiss_coupled(xtm_lattice L, double delta0, double h, double hd, 
     }
     std::vector<double> out(out_n);
     if (hipMemcpyAsync(d_in, c, sizeof c, hipMemcpyHostToDevice, s) != hipSuccess ||
-        launch_record(L->fwd_d, L->fwd_seg_d, (int32_t)(L->fwd_seg_h.size() / 3), n_el, d_in, 9,
-                      d_out, kref(L->ref, 0, 0), s) != hipSuccess ||
+        record_turn(L, d_in, 9, d_out, s) != hipSuccess ||
         hipMemcpyAsync(out.data(), d_out, out_n * sizeof(double), hipMemcpyDeviceToHost, s) !=
             hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)
@@ -2252,8 +2279,7 @@ xtm_status xtm_twiss_open(xtm_lattice L, double delta0, double h, double hd, con
     std::vector<double> out(out_n);
     xtm_status st = XTM_OK;
     if (hipMemcpyAsync(d_in, c, sizeof c, hipMemcpyHostToDevice, s) != hipSuccess ||
-        launch_record(L->fwd_d, L->fwd_seg_d, (int32_t)(L->fwd_seg_h.size() / 3), n_el, d_in, 11,
-                      d_out, kref(L->ref, 0, 0), s) != hipSuccess ||
+        record_turn(L, d_in, 11, d_out, s) != hipSuccess ||
         hipMemcpyAsync(out.data(), d_out, out_n * sizeof(double), hipMemcpyDeviceToHost, s) !=
             hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)

@@ -200,13 +200,35 @@ inline int32_t line_block(int32_t style) { return kLineStyle[style].lanes; }
 inline int32_t line_fetch(int32_t style) { return kLineStyle[style].fetch; }
 inline bool line_deferred(int32_t style) { return kLineStyle[style].deferred; }
 inline int32_t line_ppt(int32_t style) { return kLineStyle[style].ppt; }
+// Radiation forms of a per-line kernel: which radiation steps its radiating
+// multipoles carry, so that a kernel holds only the code its calls can take
+// (the photon emitter is an out-of-line call whose register and stack cost a
+// kernel pays across its whole element loop whether it runs or not).
+//   0: none (radiation off, or a line without radiating multipoles);
+//   1: the mean loss and Gaussian quantum excitation (modes 1 and 2, the
+//      mode read at run time);
+//   2: photon by photon (mode 3).
+constexpr int32_t kRadForms = 3;
+inline int32_t rad_form(bool line_radiates, int32_t mode) {
+  return (!line_radiates || mode == 0) ? 0 : (mode == 3 ? 2 : 1);
+}
+// Whether an element table holds radiating multipoles (a curvature term or
+// a radiation length).
+bool table_radiates(const std::vector<uint64_t>& tab, int32_t n_el);
 bool build_line_kernel(const std::vector<uint64_t>& tab, int32_t n_el, int32_t style,
-                       LineKernel* k);
+                       int32_t rad_form, LineKernel* k);
 // The same for a batch of lattice variants (batched = true: the kernel takes
 // the slot partition and reads each variant's parameters); fails if the
 // variants' element structures differ.
 bool build_line_kernel_multi(const std::vector<const std::vector<uint64_t>*>& tabs, int32_t n_el,
-                             int32_t style, bool batched, LineKernel* k);
+                             int32_t style, bool batched, int32_t rad_form, LineKernel* k);
+// The generated recording kernel of optics by tracking (the coordinates of
+// one turn at every element's entry, as launch_record, or with all_rows =
+// false only after the turn, row n_el); fails if the line has no cell
+// decomposition.
+bool build_record_kernel(const std::vector<uint64_t>& tab, int32_t n_el, LineKernel* k);
+hipError_t launch_line_record(const LineKernel& k, int32_t n_el, const double* c6, int64_t n,
+                              double* out, bool all_rows, KernelRef r, hipStream_t s);
 void free_line_kernel(LineKernel* k);
 hipError_t launch_line(const LineKernel& k, int32_t n_el, SoA P, const int32_t* idx,
                        const int32_t* ctrl, int64_t grid_upper, int32_t block, int32_t n_turns,

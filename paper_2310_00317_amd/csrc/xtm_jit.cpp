@@ -52,18 +52,21 @@ struct Decomp {
 // Cover the line with cells: a repeating unit U of P elements wherever it
 // matches, and the stretches in between ("gaps", e.g. a lone RF cavity or a
 // cell whose sextupole slot holds a cavity) as further kinds, split into
-// pieces of at most kMaxUnit elements.  Among all units (P <= kMaxUnit,
+// pieces of at most max_unit elements.  Among all units (P <= max_unit,
 // every phase) keep the cover with the fewest cells whose distinct kinds
 // need at most kMaxCode elements of generated code.
 constexpr int kMaxUnit = 24;
 constexpr int kMaxCode = 48;
+// the recording kernel buffers a cell's rows in LDS: at most 16 elements a
+// cell (16 x 64 lanes x 48 bytes)
+constexpr int kMaxRecordUnit = 16;
 
-bool decompose(const std::vector<uint32_t>& sig, Decomp* out) {
+bool decompose(const std::vector<uint32_t>& sig, Decomp* out, int32_t max_unit = kMaxUnit) {
   const int32_t E = (int32_t)sig.size();
   if (E == 0) return false;
   size_t best_cells = 0;
   int32_t best_code = 0;
-  for (int32_t P = 1; P <= kMaxUnit && P <= E; ++P) {
+  for (int32_t P = 1; P <= max_unit && P <= E; ++P) {
     for (int32_t o = 0; o < P && o + P <= E; ++o) {
       const uint32_t* U = &sig[o];
       std::map<std::vector<uint32_t>, int32_t> kinds;
@@ -84,7 +87,7 @@ bool decompose(const std::vector<uint32_t>& sig, Decomp* out) {
         d.cell_start.push_back(start);
       };
       auto flush = [&](int32_t g0, int32_t g1) {  // gap [g0, g1)
-        for (int32_t s = g0; s < g1; s += kMaxUnit) add(s, std::min(kMaxUnit, g1 - s));
+        for (int32_t s = g0; s < g1; s += max_unit) add(s, std::min(max_unit, g1 - s));
       };
       int32_t i = 0, gap = -1;
       while (i < E && ok) {
@@ -133,7 +136,10 @@ int32_t n_words(uint32_t s) {
 // coordinates at the element; kMarkOnly only records the loss code (the cell
 // is replayed for lanes lost in it, see generate); kReplay applies the map
 // alone (the replay itself).
-enum EmitMode { kSaveAtLoss = 0, kMarkOnly = 1, kReplay = 2 };
+// kRecord: the maps for optics by tracking (apertures not applied; a lane
+// whose drift finds no real longitudinal momentum keeps its entry
+// coordinates and applies no further maps).
+enum EmitMode { kSaveAtLoss = 0, kMarkOnly = 1, kReplay = 2, kRecord = 3 };
 
 std::string emit(uint32_t s, const std::string& arr, const std::string& j, bool far_rf,
                  EmitMode mode) {
@@ -142,10 +148,13 @@ std::string emit(uint32_t s, const std::string& arr, const std::string& j, bool 
   std::ostringstream c;
   switch (kt) {
     case K_DRIFT: {
-      // order 1: a drift length outside the short sequences' window
-      const char* any = order ? "true" : "false";
+      // the drift record's order: the length's class for the short sequences
+      const std::string any = std::to_string(order);
       if (mode == kReplay)
         c << "(void)xtmm::drift_exact(q, " << P(0) << ", " << any << ");";
+      else if (mode == kRecord)
+        c << "{ const xtmm::Pt q0_ = q; if (!xtmm::drift_exact(q, " << P(0) << ", " << any
+          << ")) { q = q0_; alive = false; } }";
       else if (mode == kMarkOnly)
         c << "xtmm::mark(xtmm::drift_exact(q, " << P(0) << ", " << any << "), code, st, e0 + "
           << j << ", -1);";
@@ -191,7 +200,7 @@ std::string emit(uint32_t s, const std::string& arr, const std::string& j, bool 
     case K_AP_CIRC:
     case K_AP_ELL:
     case K_AP_RECT: {
-      if (mode == kReplay) break;  // a test, no change of coordinates
+      if (mode == kReplay || mode == kRecord) break;  // a test, no change of coordinates
       std::string test;
       if (kt == K_AP_CIRC) test = "xtmm::in_circle(q, " + P(0) + ")";
       else if (kt == K_AP_ELL) test = "xtmm::in_ellipse(q, " + P(0) + ", " + P(1) + ")";
@@ -221,7 +230,7 @@ int32_t kind_words(const std::vector<uint32_t>& k) {
 // memory and writes it to the other slot before the cell barrier.  Element
 // code then reads its parameters as broadcast LDS reads at compile-time
 // offsets.
-std::string generate(const Decomp& d, int32_t style, bool batched) {
+std::string generate(const Decomp& d, int32_t style, bool batched, int32_t rad_form) {
   int32_t maxw = 1;
   for (const auto& k : d.kinds) maxw = std::max(maxw, kind_words(k));
   // the lanes of a workgroup share one LDS slot pair, filled by all of them
@@ -262,10 +271,23 @@ std::string generate(const Decomp& d, int32_t style, bool batched) {
                     "__constant__ int elem_sig[] = {" + es.str() + "};\n"
                     "__constant__ int elem_off[] = {" + eo.str() + "};\n";
   }
-  // a line with radiating multipoles calls its RF sine out of line
+  // a kernel with radiation steps calls its RF sine out of line
   bool far_rf = false;
-  for (const auto& k : d.kinds)
-    for (uint32_t e : k) far_rf |= ((e & 0xffu) == K_MULT_CURV || (e & 0xffu) == K_MULT_LR);
+  if (rad_form != 0)
+    for (const auto& k : d.kinds)
+      for (uint32_t e : k) far_rf |= ((e & 0xffu) == K_MULT_CURV || (e & 0xffu) == K_MULT_LR);
+  // the radiation step after a radiating multipole (rad_form): none; the
+  // mean and Gaussian models with the mode read at run time; photon by photon
+  std::string rad_macro;
+  if (rad_form == 0)
+    rad_macro = "#define RAD(kx, ky, lr, j) ((void)0)\n";
+  else
+    rad_macro = std::string("#define RAD(kx, ky, lr, j) xtmm::radiate_at<true, ") +
+                (rad_form == 2 ? "true>(q, kx, ky, lr, 3, " : "false>(q, kx, ky, lr, r.rad_mode, ") +
+                "r.seed, pid, \\\n"
+                "    t0 + t, ec + (j), r.gamma0, r.c_mean, r.c_quant, r.p0c, beta0, two_over_beta0, "
+                "\\\n"
+                "    r.photon_table, r.c_nphot, r.c_ucrit)\n";
   const int32_t per_thread = (maxw + lanes - 1) / lanes;
   std::ostringstream s;
   s << "#include \"xtm_maps.h\"\n"
@@ -275,9 +297,7 @@ std::string generate(const Decomp& d, int32_t style, bool batched) {
        "              unsigned long long seed; int rad_mode; int pad;\n"
        "              float* rec; int rec_turns; int rec_n;\n"
        "              const double* photon_table; double c_nphot, c_ucrit; };\n"
-       "#define RAD(kx, ky, lr, j) xtmm::radiate_at<true>(q, kx, ky, lr, r.rad_mode, r.seed, pid, \\\n"
-       "    t0 + t, ec + (j), r.gamma0, r.c_mean, r.c_quant, r.p0c, beta0, two_over_beta0, \\\n"
-       "    r.photon_table, r.c_nphot, r.c_ucrit)\n"
+    << rad_macro <<
        "// a lane that fails a loss test stores the coordinates it entered the\n"
        "// element with (a rare, divergent store); the loss record follows at the end\n"
        "// (its slot index passes through a register move, so the nine store\n"
@@ -560,7 +580,185 @@ std::string generate(const Decomp& d, int32_t style, bool batched) {
   return s.str();
 }
 
-Compiled compile(const std::string& src) {
+// Generated recording kernel for optics by tracking: one turn of a few
+// particles from their (x, px, y, py, zeta, delta), the coordinates stored at
+// the entry of every element and after the last.  The cell structure,
+// parameter staging (two LDS slots, the next cell's words loaded during the
+// current cell) and element code are those of the tracking kernel's
+// one-wave form with the next element's parameters read ahead; apertures are
+// not applied, and a lane whose drift finds no real longitudinal momentum
+// keeps its entry coordinates and applies no further maps.  The rows of a
+// cell go to an LDS buffer and leave for global memory together at the
+// cell's end, as contiguous runs written by all lanes.
+std::string generate_record(const Decomp& d) {
+  int32_t maxw = 1, maxk = 1;
+  for (const auto& k : d.kinds) {
+    maxw = std::max(maxw, kind_words(k));
+    maxk = std::max(maxk, (int32_t)k.size());
+  }
+  constexpr int32_t lanes = 64;
+  const int32_t per_thread = (maxw + lanes - 1) / lanes;
+  std::ostringstream s;
+  s << "#include \"xtm_maps.h\"\n"
+       "struct KRef { double beta0, two_over_beta0, gamma0, c_mean, c_quant, p0c;\n"
+       "              unsigned long long seed; int rad_mode; int pad;\n"
+       "              float* rec; int rec_turns; int rec_n;\n"
+       "              const double* photon_table; double c_nphot, c_ucrit; };\n"
+       "#define RAD(kx, ky, lr, j) ((void)0)\n"
+       "#define MAXW " << maxw << "\n"
+       "#define MAXK " << maxk << "\n"
+       "#define PER_THREAD " << per_thread << "\n"
+       "#define LANES " << lanes << "\n"
+       "// row j of the cell in the LDS buffer (every lane writes its own)\n"
+       "#define REC(j) do { if (ALL) { double2* r_ = rows + ((j) * LANES + lane) * 3; \\\n"
+       "    r_[0] = make_double2(q.x, q.px); r_[1] = make_double2(q.y, q.py); \\\n"
+       "    r_[2] = make_double2(q.zeta, q.delta); } } while (0)\n"
+       "// ALL: every row, else only the row after the turn (one kernel for both,\n"
+       "// each body specialised)\n"
+       "template <bool ALL>\n"
+       "__device__ __forceinline__ void record_body(const double* __restrict__ prm,\n"
+       "    const int* __restrict__ cells, int n_cells, int n_el, const double* __restrict__ c6,\n"
+       "    long long n, double* __restrict__ out, const KRef& r, double* slot, double2* rows) {\n"
+       "  const int lane = threadIdx.x;\n"
+       "  const long long i0 = (long long)blockIdx.x * LANES;\n"
+       "  const long long i = i0 + lane;\n"
+       "  const bool act = i < n;\n"
+       "  // the block's particles: its rows of one element are nb_ consecutive 48-byte rows\n"
+       "  const int nb_ = (int)(n - i0 < LANES ? n - i0 : LANES);\n"
+       "  double2* __restrict__ out2 = reinterpret_cast<double2*>(out);\n"
+       "  const double beta0 = r.beta0, two_over_beta0 = r.two_over_beta0;\n"
+       "  (void)two_over_beta0;\n"
+       "  xtmm::Pt q{};\n"
+       "  if (act) {\n"
+       "    const double* c = c6 + 6 * i;\n"
+       "    const double dl = c[5];\n"
+       "    const double u = dl * (2.0 + dl);\n"
+       "    q.x = c[0]; q.px = c[1]; q.y = c[2]; q.py = c[3]; q.zeta = c[4]; q.delta = dl;\n"
+       "    q.ptau = beta0 * u / (1.0 + sqrt(1.0 + beta0 * beta0 * u));\n"
+       "    q.rpp = 1.0 / (1.0 + dl);\n"
+       "    q.rvv = (1.0 + dl) / (1.0 + beta0 * q.ptau);\n"
+       "    xtmm::refresh(q, beta0);\n"
+       "  }\n"
+       "  bool alive = act;\n"
+       "  // the coordinates have arrived before the cell loop: otherwise the\n"
+       "  // loop's first uses of them would carry a wait for every load in\n"
+       "  // flight, the next cell's parameters included, on every cell\n"
+       "  __builtin_amdgcn_s_waitcnt(0);\n"
+       "  {\n"
+       "    const int off0 = cells[1], nw0 = cells[3];\n"
+       "    for (int w = lane; w < nw0; w += LANES) slot[w] = prm[off0 + w];\n"
+       "  }\n"
+       "  // parameters two cells ahead: the words of cell c + 1 arrived during\n"
+       "  // cell c - 1 (a lone wave reads each cell's words once, from beyond the\n"
+       "  // L2, and one cell of work does not cover that latency).  Two register\n"
+       "  // sets take turns, the loop body holding two cells, so no set is copied\n"
+       "  // (a copy would wait for the loads in flight).\n"
+       "  double preA[PER_THREAD], preB[PER_THREAD];\n"
+       "  {\n"
+       "    const int c1 = n_cells > 1 ? 1 : 0;\n"
+       "    const int off1 = cells[4 * c1 + 1], nw1 = cells[4 * c1 + 3];\n"
+       "#pragma unroll\n"
+       "    for (int k = 0; k < PER_THREAD; ++k) {\n"
+       "      const int w = lane + k * LANES;\n"
+       "      preA[k] = (w < nw1) ? prm[off1 + w] : 0.0;\n"
+       "    }\n"
+       "  }\n"
+       "  __syncthreads();\n"
+       "  int b = 0;\n"
+       "  for (int c = 0; c < n_cells; c += 2) {\n";
+  // one cell cc = c + half: its words in slot b, the next cell's in `cur`,
+  // the cell after that loaded into `nxt`
+  auto cell = [&](int half, const char* cur, const char* nxt) {
+    s << "  {\n"
+         "    const int cc = c + " << half << ";\n"
+         "    const int cn = (cc + 1 == n_cells) ? cc : cc + 1;\n"
+         "    const int nwn = cells[4 * cn + 3];\n"
+         "    const int c2 = (cc + 2 < n_cells) ? cc + 2 : n_cells - 1;\n"
+         "    const int off2 = cells[4 * c2 + 1], nw2 = cells[4 * c2 + 3];\n"
+         "    // every lane loads (a lane past the cell's words reads its first\n"
+         "    // word, the parameter array ends in a pad word), so the loads are\n"
+         "    // not under a branch and the waits for them can count\n"
+         "#pragma unroll\n"
+         "    for (int k = 0; k < PER_THREAD; ++k) {\n"
+         "      const int w = lane + k * LANES;\n"
+         "      const double v_ = prm[off2 + (w < nw2 ? w : 0)];\n"
+         "      " << nxt << "[k] = (w < nw2) ? v_ : 0.0;\n"
+         "    }\n"
+         "    const int kind = cells[4 * cc];\n"
+         "    const int ec = cells[4 * cc + 2];\n"
+         "    const int len = (cc + 1 == n_cells ? n_el : cells[4 * (cc + 1) + 2]) - ec;\n"
+         "    int base;\n"
+         "    asm volatile(\"v_mov_b32 %0, %1\" : \"=v\"(base) : \"s\"(b * MAXW));\n"
+         "    const double* p = &slot[base & 0x3fff];\n";
+    for (size_t k = 0; k < d.kinds.size(); ++k) {
+      s << "    " << (k ? "else if" : "if") << " (kind == " << k << ") {\n";
+      const auto& kd = d.kinds[k];
+      std::vector<int32_t> off(kd.size() + 1, 0);
+      for (size_t j = 0; j < kd.size(); ++j) off[j + 1] = off[j] + n_words(kd[j]);
+      auto load = [&](size_t j) {
+        const int32_t nw = n_words(kd[j]);
+        if (nw == 0) return;
+        s << "      double w" << j << "[" << nw << "];\n"
+          << "#pragma unroll\n"
+          << "      for (int m = 0; m < " << nw << "; ++m) w" << j << "[m] = p[" << off[j]
+          << " + m];\n";
+      };
+      if (!kd.empty()) load(0);
+      for (size_t j = 0; j < kd.size(); ++j) {
+        if (j + 1 < kd.size()) load(j + 1);
+        s << "      __builtin_amdgcn_sched_barrier(0);\n";
+        const std::string arr =
+            n_words(kd[j]) > 0 ? "w" + std::to_string(j) : "p + " + std::to_string(off[j]);
+        s << "      REC(" << j << ");\n";
+        const std::string stmt = emit(kd[j], arr, std::to_string(j), false, kRecord);
+        if (!stmt.empty()) s << "      if (alive) { " << stmt << " }\n";
+      }
+      s << "    }\n";
+    }
+    s << "#pragma unroll\n"
+         "    for (int k = 0; k < PER_THREAD; ++k) {\n"
+         "      const int w = lane + k * LANES;\n"
+         "      if (w < nwn) slot[(b ^ 1) * MAXW + w] = " << cur << "[k];\n"
+         "    }\n"
+         "    b ^= 1;\n"
+         "    __syncthreads();\n"
+         "    if (ALL) {\n"
+         "      // the cell's rows, element-major: len runs of nb_ rows of three\n"
+         "      // 16-byte words, each run contiguous in the output\n"
+         "      const int per = nb_ * 3;\n"
+         "      for (int t = lane; t < len * per; t += LANES) {\n"
+         "        const int er = t / per, rem = t - er * per;\n"
+         "        const int pp = rem / 3, kk = rem - pp * 3;\n"
+         "        out2[((unsigned long long)(ec + er) * n + i0 + pp) * 3 + kk] =\n"
+         "            rows[(er * LANES + pp) * 3 + kk];\n"
+         "      }\n"
+         "      __syncthreads();\n"
+         "    }\n"
+         "  }\n";
+  };
+  cell(0, "preA", "preB");
+  s << "  if (c + 1 < n_cells)\n";
+  cell(1, "preB", "preA");
+  s << "  }\n"
+       "  if (act) {\n"
+       "    double2* o_ = out2 + ((unsigned long long)n_el * n + i) * 3;\n"
+       "    o_[0] = make_double2(q.x, q.px); o_[1] = make_double2(q.y, q.py);\n"
+       "    o_[2] = make_double2(q.zeta, q.delta);\n"
+       "  }\n"
+       "}\n"
+       "extern \"C\" __global__ void __launch_bounds__(64)\n"
+       "xtm_record(const double* __restrict__ prm, const int* __restrict__ cells, int n_cells,\n"
+       "           int n_el, const double* __restrict__ c6, long long n,\n"
+       "           double* __restrict__ out, int all_rows, KRef r) {\n"
+       "  __shared__ double slot[2 * MAXW];\n"
+       "  __shared__ double2 rows[MAXK * LANES * 3];\n"
+       "  if (all_rows) record_body<true>(prm, cells, n_cells, n_el, c6, n, out, r, slot, rows);\n"
+       "  else record_body<false>(prm, cells, n_cells, n_el, c6, n, out, r, slot, rows);\n"
+       "}\n";
+  return s.str();
+}
+
+Compiled compile(const std::string& src, const char* name) {
   Compiled out;
   hiprtcProgram prog;
   const char* hdr = kMapsSource;
@@ -591,7 +789,7 @@ Compiled compile(const std::string& src) {
     out.error = "hipModuleLoadData failed";
     return out;
   }
-  if (hipModuleGetFunction(&out.fn, out.module, "xtm_line") != hipSuccess) {
+  if (hipModuleGetFunction(&out.fn, out.module, name) != hipSuccess) {
     out.error = "hipModuleGetFunction failed";
     out.fn = nullptr;
   }
@@ -621,13 +819,65 @@ void split_table(const std::vector<uint64_t>& tab, int32_t n_el, std::vector<uin
 }
 }  // namespace
 
-bool build_line_kernel(const std::vector<uint64_t>& tab, int32_t n_el, int32_t style,
-                       LineKernel* k) {
-  return build_line_kernel_multi({&tab}, n_el, style, false, k);
+bool table_radiates(const std::vector<uint64_t>& tab, int32_t n_el) {
+  size_t off = 0;
+  for (int32_t e = 0; e < n_el && off < tab.size(); ++e) {
+    const uint32_t kt = (uint32_t)(tab[off] & 0xffu);
+    if (kt == K_MULT_CURV || kt == K_MULT_LR) return true;
+    off += 1 + (size_t)((tab[off] >> 16) & 0xffffu);
+  }
+  return false;
 }
 
+bool build_line_kernel(const std::vector<uint64_t>& tab, int32_t n_el, int32_t style,
+                       int32_t rad_form, LineKernel* k) {
+  return build_line_kernel_multi({&tab}, n_el, style, false, rad_form, k);
+}
+
+namespace {
+// Compile (or take from the cache) a generated kernel and upload its
+// parameter array and cell table.
+bool finish_kernel(const Decomp& d, const std::string& source, const char* name,
+                   const std::vector<int32_t>& word_of, const std::vector<double>& prm,
+                   LineKernel* k) {
+  k->source = source;
+  {
+    std::lock_guard<std::mutex> lock(g_mu);
+    auto it = g_cache.find(k->source);
+    if (it == g_cache.end()) it = g_cache.emplace(k->source, compile(k->source, name)).first;
+    if (!it->second.fn) {
+      k->error = it->second.error;
+      return false;
+    }
+    k->fn = it->second.fn;
+  }
+  std::vector<int32_t> cells;  // per cell: kind, first parameter word, first element, words
+  for (size_t c = 0; c < d.cell_kind.size(); ++c) {
+    cells.push_back(d.cell_kind[c]);
+    cells.push_back(word_of[d.cell_start[c]]);
+    cells.push_back(d.cell_start[c]);
+    cells.push_back(kind_words(d.kinds[d.cell_kind[c]]));
+  }
+  k->period = (int32_t)d.kinds[0].size();
+  k->n_cells = (int32_t)d.cell_kind.size();
+  k->n_kinds = (int32_t)d.kinds.size();
+  if (hipMalloc(&k->prm_d, prm.size() * sizeof(double)) != hipSuccess ||
+      hipMalloc(&k->cells_d, cells.size() * sizeof(int32_t)) != hipSuccess ||
+      hipMemcpy(k->prm_d, prm.data(), prm.size() * sizeof(double), hipMemcpyHostToDevice) !=
+          hipSuccess ||
+      hipMemcpy(k->cells_d, cells.data(), cells.size() * sizeof(int32_t),
+                hipMemcpyHostToDevice) != hipSuccess) {
+    k->error = "device allocation for the line kernel failed";
+    free_line_kernel(k);
+    return false;
+  }
+  k->ok = true;
+  return true;
+}
+}  // namespace
+
 bool build_line_kernel_multi(const std::vector<const std::vector<uint64_t>*>& tabs, int32_t n_el,
-                             int32_t style, bool batched, LineKernel* k) {
+                             int32_t style, bool batched, int32_t rad_form, LineKernel* k) {
   std::vector<uint32_t> sig;
   std::vector<int32_t> word_of;  // parameter-array offset of each element
   std::vector<double> prm;
@@ -660,39 +910,23 @@ bool build_line_kernel_multi(const std::vector<const std::vector<uint64_t>*>& ta
   k->batched = batched;
   k->nv = (int32_t)tabs.size();
   k->stride = (int64_t)stride;
-  k->source = generate(d, style, batched);
-  {
-    std::lock_guard<std::mutex> lock(g_mu);
-    auto it = g_cache.find(k->source);
-    if (it == g_cache.end()) it = g_cache.emplace(k->source, compile(k->source)).first;
-    if (!it->second.fn) {
-      k->error = it->second.error;
-      return false;
-    }
-    k->fn = it->second.fn;
-  }
-  std::vector<int32_t> cells;  // per cell: kind, first parameter word, first element, words
-  for (size_t c = 0; c < d.cell_kind.size(); ++c) {
-    cells.push_back(d.cell_kind[c]);
-    cells.push_back(word_of[d.cell_start[c]]);
-    cells.push_back(d.cell_start[c]);
-    cells.push_back(kind_words(d.kinds[d.cell_kind[c]]));
-  }
-  k->period = (int32_t)d.kinds[0].size();
-  k->n_cells = (int32_t)d.cell_kind.size();
-  k->n_kinds = (int32_t)d.kinds.size();
-  if (hipMalloc(&k->prm_d, prm.size() * sizeof(double)) != hipSuccess ||
-      hipMalloc(&k->cells_d, cells.size() * sizeof(int32_t)) != hipSuccess ||
-      hipMemcpy(k->prm_d, prm.data(), prm.size() * sizeof(double), hipMemcpyHostToDevice) !=
-          hipSuccess ||
-      hipMemcpy(k->cells_d, cells.data(), cells.size() * sizeof(int32_t),
-                hipMemcpyHostToDevice) != hipSuccess) {
-    k->error = "device allocation for the line kernel failed";
-    free_line_kernel(k);
+  return finish_kernel(d, generate(d, style, batched, rad_form), "xtm_line", word_of, prm, k);
+}
+
+bool build_record_kernel(const std::vector<uint64_t>& tab, int32_t n_el, LineKernel* k) {
+  std::vector<uint32_t> sig;
+  std::vector<int32_t> word_of;
+  std::vector<double> prm;
+  split_table(tab, n_el, &sig, &word_of, &prm);
+  prm.push_back(0.0);  // pad word: the first word of a cell without words
+  Decomp d;
+  if (!decompose(sig, &d, kMaxRecordUnit)) {
+    k->error = "no cell decomposition within the code budget";
     return false;
   }
-  k->ok = true;
-  return true;
+  k->style = 5;  // one-wave workgroups, the next element's parameters read ahead
+  k->stride = (int64_t)prm.size();
+  return finish_kernel(d, generate_record(d), "xtm_record", word_of, prm, k);
 }
 
 void free_line_kernel(LineKernel* k) {
@@ -719,6 +953,20 @@ hipError_t launch_line(const LineKernel& k, int32_t n_el, SoA P, const int32_t* 
   const int64_t per_wg = (int64_t)wg * line_ppt(k.style);  // particles per workgroup
   const unsigned grid = (unsigned)((grid_upper + per_wg - 1) / per_wg);
   return hipModuleLaunchKernel(k.fn, grid, 1, 1, (unsigned)wg, 1, 1, 0, s, args, nullptr);
+}
+
+hipError_t launch_line_record(const LineKernel& k, int32_t n_el, const double* c6, int64_t n,
+                              double* out, bool all_rows, KernelRef r, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const double* prm = k.prm_d;
+  const int32_t* cells = k.cells_d;
+  int32_t n_cells = k.n_cells;
+  long long nn = (long long)n;
+  int32_t all = all_rows ? 1 : 0;
+  void* args[] = {(void*)&prm, (void*)&cells, (void*)&n_cells, (void*)&n_el, (void*)&c6,
+                  (void*)&nn,  (void*)&out,   (void*)&all,     (void*)&r};
+  const unsigned grid = (unsigned)((n + 63) / 64);
+  return hipModuleLaunchKernel(k.fn, grid, 1, 1, 64, 1, 1, 0, s, args, nullptr);
 }
 
 hipError_t launch_line_batched(const LineKernel& k, int32_t n_el, SoA P, const int32_t* idx,

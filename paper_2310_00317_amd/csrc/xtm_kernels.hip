@@ -112,6 +112,11 @@ __device__ __forceinline__ void maybe_radiate(xtmm::Pt& q, double kx, double ky,
                    r.c_ucrit);
 }
 
+// kRad = false compiles the radiation step out, for kernels that always run
+// with radiation off (optics by tracking, loss refinement): the photon
+// emitter is an out-of-line call whose register and stack cost would
+// otherwise be paid across their whole element loop.
+template <bool kRad = true>
 __device__ __forceinline__ void apply_elem(xtmm::Pt& q, uint32_t ktype, uint32_t order,
                                            const double* __restrict__ prm, const KernelRef& r,
                                            bool& ok, int& lost_state, long long pid, int turn,
@@ -121,7 +126,7 @@ __device__ __forceinline__ void apply_elem(xtmm::Pt& q, uint32_t ktype, uint32_t
   lost_state = 0;
   if (ktype == K_MULT_LR) {
     multipole_n(q, prm, order, kx, ky);
-    maybe_radiate(q, kx, ky, prm[2 * (order + 1)], r, pid, turn, element);
+    if (kRad) maybe_radiate(q, kx, ky, prm[2 * (order + 1)], r, pid, turn, element);
     return;
   }
   if (ktype == K_MULT) {
@@ -142,7 +147,7 @@ __device__ __forceinline__ void apply_elem(xtmm::Pt& q, uint32_t ktype, uint32_t
   }
   switch (ktype) {
     case K_DRIFT:
-      ok = xtmm::drift_exact(q, prm[0], order != 0);
+      ok = xtmm::drift_exact(q, prm[0], (int)order);
       lost_state = -1;
       break;
     case K_AP_CIRC:
@@ -155,7 +160,7 @@ __device__ __forceinline__ void apply_elem(xtmm::Pt& q, uint32_t ktype, uint32_t
       multipole_n(q, prm, order, kx, ky);
       const double* cv = prm + 2 * (order + 1);
       xtmm::curvature(q, cv[0], cv[1], cv[2]);
-      maybe_radiate(q, kx, ky, cv[2], r, pid, turn, element);
+      if (kRad) maybe_radiate(q, kx, ky, cv[2], r, pid, turn, element);
       break;
     }
     case K_RF:
@@ -633,7 +638,7 @@ __global__ void __launch_bounds__(256) k_elem(const uint64_t* __restrict__ tab, 
     q.x = P.x[p]; q.px = P.px[p]; q.y = P.y[p]; q.py = P.py[p]; q.zeta = P.zeta[p];
     q.delta = P.delta[p]; q.ptau = P.ptau[p];
     xtmm::refresh(q, r.beta0);
-    if (!xtmm::drift_exact(q, prm[0], order != 0)) return elem_lost(P, p, -1, e, turn);
+    if (!xtmm::drift_exact(q, prm[0], (int)order)) return elem_lost(P, p, -1, e, turn);
     P.x[p] = q.x; P.y[p] = q.y; P.zeta[p] = q.zeta;
   } else if constexpr (KT == K_MULT) {
     q.x = P.x[p]; q.y = P.y[p]; q.px = P.px[p]; q.py = P.py[p];
@@ -824,7 +829,7 @@ k_record(const uint64_t* __restrict__ fwd, const int32_t* __restrict__ seg, int3
       const xtmm::Pt q0 = q;
       bool ok;
       int lost_state;
-      apply_elem(q, kt, (uint32_t)((h >> 8) & 0xffu), prm, r, ok, lost_state, 0, 0, e);
+      apply_elem<false>(q, kt, (uint32_t)((h >> 8) & 0xffu), prm, r, ok, lost_state, 0, 0, e);
       if (!ok) {
         q = q0;
         alive = false;
@@ -976,8 +981,8 @@ k_refine(const uint64_t* __restrict__ fwd, const uint64_t* __restrict__ bwd, Ref
         const double* prm = reinterpret_cast<const double*>(bwd + g.off_b[j] + 1);
         bool okj;
         int lost_state;
-        apply_elem(q, (uint32_t)(h & 0xffu), (uint32_t)((h >> 8) & 0xffu), prm, r, okj, lost_state,
-                   pid, 0, j);
+        apply_elem<false>(q, (uint32_t)(h & 0xffu), (uint32_t)((h >> 8) & 0xffu), prm, r, okj,
+                          lost_state, pid, 0, j);
         if (!okj) { ok = false; break; }
       }
       if (ok) {
@@ -1009,13 +1014,15 @@ k_refine(const uint64_t* __restrict__ fwd, const uint64_t* __restrict__ bwd, Ref
           bool okj;
           int lost_state;
           if (!is_drift_k(kt)) {
-            apply_elem(q, kt, (uint32_t)((h >> 8) & 0xffu), prm, r, okj, lost_state, pid, 0, j);
+            apply_elem<false>(q, kt, (uint32_t)((h >> 8) & 0xffu), prm, r, okj, lost_state, pid,
+                              0, j);
             continue;
           }
           const double L = prm[0];
           double v0x, v0y, v1x, v1y;
           to_line(g.G + 6 * j, q.x, q.y, v0x, v0y);
-          apply_elem(q, kt, (uint32_t)((h >> 8) & 0xffu), prm, r, okj, lost_state, pid, 0, j);
+          apply_elem<false>(q, kt, (uint32_t)((h >> 8) & 0xffu), prm, r, okj, lost_state, pid, 0,
+                            j);
           if (!okj) break;
           to_line(g.G + 6 * j, q.x, q.y, v1x, v1y);
           bool found = false;

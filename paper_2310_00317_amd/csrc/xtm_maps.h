@@ -99,9 +99,11 @@ __device__ __forceinline__ double div_in(double a, double b) {
 //   a = d(2+d) - px^2 - py^2 with |a| >= 2^-600 (|a| < 2^1000 whenever pz^2
 //   is finite);
 //   1 + pz != 2 - 2^-52, the one all-ones divisor in (1, 3);
-//   a drift length the lattice packer marked as a non-power of two inside
-//   [2^-600, 2^600] (order-0 record; order 1 marks any other length, zero
-//   included), so L / pz never meets the all-ones family either.
+//   the drift length as the lattice packer classed it (the drift record's
+//   order): 0, |L| in [2^-600, 2^600] and not a power of two, served for
+//   every pz; 1, a power of two in that range, served unless pz's
+//   significand is all ones (the one case of L / pz in the excluded family);
+//   2, any other length, zero included, never served.
 // Other operands take the generic operations on a rare branch.
 struct DriftIn {
   double px2, py2, pz2, a;
@@ -127,17 +129,24 @@ __device__ __forceinline__ void drift_apply(Pt& q, double lp, double dq) {
   q.zeta = fma(lp, dq - q.bpt, q.zeta);
 }
 
+__device__ __forceinline__ bool all_ones_significand(double v) {
+  const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+  return (b & 0xfffffffffffffull) == 0xfffffffffffffull;
+}
+
 // Quotients of the drift: the short sequences where the window holds
 // (`fast` returns whether it did), else the generic operations (for a lost
-// particle the results are NaN and unused).
-__device__ __forceinline__ void drift_quotients(double L, const DriftIn& d, bool any_length,
+// particle the results are NaN and unused).  len_class: the drift record's
+// order (see the window above).
+__device__ __forceinline__ void drift_quotients(double L, const DriftIn& d, int len_class,
                                                 double& lp, double& dq, bool& fast) {
   double h;
   const double pz = sqrt_in(d.pz2, h);
   const double b1 = 1.0 + pz;
   lp = div_by_root(L, pz, h);
   dq = div_in(d.a, b1);
-  fast = !any_length & drift_window(d) & (b1 != 0x1.fffffffffffffp+0);
+  const bool len_ok = (len_class == 0) | ((len_class == 1) & !all_ones_significand(pz));
+  fast = len_ok & drift_window(d) & (b1 != 0x1.fffffffffffffp+0);
 }
 
 __device__ __forceinline__ void drift_generic(double L, const DriftIn& d, double& lp, double& dq) {
@@ -147,13 +156,13 @@ __device__ __forceinline__ void drift_generic(double L, const DriftIn& d, double
 }
 
 // The whole drift; returns false if the particle is lost (its coordinates
-// are then NaN and must not be used).  any_length: the drift length is
-// outside the window (order-1 drift record).
-__device__ __forceinline__ bool drift_exact(Pt& q, double L, bool any_length = false) {
+// are then NaN and must not be used).  len_class: the drift record's order
+// (0 for a length known to be served for every pz).
+__device__ __forceinline__ bool drift_exact(Pt& q, double L, int len_class = 0) {
   const DriftIn d = drift_in(q);
   double lp, dq;
   bool fast;
-  drift_quotients(L, d, any_length, lp, dq, fast);
+  drift_quotients(L, d, len_class, lp, dq, fast);
   if (!fast) drift_generic(L, d, lp, dq);
   drift_apply(q, lp, dq);
   return d.pz2 > 0.0;
@@ -503,8 +512,10 @@ __device__ __attribute__((noinline)) void radiate_photons_far(
 // Radiation step of a multipole with radiation length lr (none if lr <= 0 or
 // mode 0): mean (1), mean + Gaussian quantum excitation (2), photon by photon
 // (3); the deviates are keyed by (seed, particle id, absolute turn, element
-// index of the line as tracked, thick elements sliced).
-template <bool kFar = false>
+// index of the line as tracked, thick elements sliced).  kFar: the deviates'
+// and photons' code out of line; kPhotons = false leaves mode 3 out (the
+// caller never passes it).
+template <bool kFar = false, bool kPhotons = true>
 __device__ __forceinline__ void radiate_at(Pt& q, double kx, double ky, double lr, int mode,
                                            unsigned long long seed, long long pid, int turn,
                                            int element, double gamma0, double c_mean,
@@ -512,7 +523,7 @@ __device__ __forceinline__ void radiate_at(Pt& q, double kx, double ky, double l
                                            double two_over_beta0, const double* ptab,
                                            double c_nphot, double c_ucrit) {
   if (mode == 0 || !(lr > 0.0)) return;
-  if (mode == 3) {
+  if (kPhotons && mode == 3) {
     if (kFar)
       radiate_photons_far(q, kx, ky, lr, ptab, c_nphot, c_ucrit, gamma0, p0c, seed, pid, turn,
                           element, beta0, two_over_beta0);

@@ -3,7 +3,9 @@ drift's window: a CPU emulation of its square-root and quotient sequences,
 with the hardware estimates modelled at their measured error bounds, agrees
 with the IEEE operations on several million adversarial inputs, apart from
 the one family the window excludes (all-ones divisor, power-of-two
-numerator)."""
+numerator).  A power-of-two drift length is therefore served by the short
+sequences for every pz whose significand is not all ones, and only those
+lengths need the device's significand test."""
 import os
 import re
 import subprocess

@@ -71,6 +71,23 @@ def test_radiation_parity_small_ring(P, oracle_mod, mode):
     assert_bitwise(g, o)
 
 
+def test_one_lattice_every_radiation_mode(P, oracle_mod):
+    """One lattice handle tracked with the radiation modes in turn (photons,
+    off, Gaussian, mean): the per-line kernel is generated once per radiation
+    form (none; mean and Gaussian; photons) and each run is bitwise equal to
+    the oracle."""
+    el = _ring()
+    c = I.gaussian_particles(400, 23, [3e-4, 3e-6, 3e-5, 3e-7, 3e-3, 1.5e-3])
+    lat = P.Lattice(el, EREF)
+    for mode in (3, 0, 2, 1, 3):
+        parts = P.Particles(len(c), EREF).init(c, first_id=7)
+        gp, _ = P.track(lat, parts, 20, radiation=mode, seed=31, variant=10)
+        o = oracle_mod.init(c, EREF, first_id=7)
+        op = oracle_mod.track(el, EREF, o, 20, radiation=mode, seed=31)
+        assert gp == op, mode
+        assert_bitwise(parts.to_numpy(), o)
+
+
 @pytest.mark.parametrize("variant", [0, 7, 9, 10, 11, 12, 13])
 def test_radiation_full_electron_ring_short(P, oracle_mod, variant):
     el = I.cfg5_lattice()

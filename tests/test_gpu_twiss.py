@@ -168,6 +168,72 @@ def test_record_several_workgroups(P, oracle_mod):
     assert same.all(), f"{(~same).sum()} values differ"
 
 
+def _record_same(g, o):
+    same = (g.view(np.int64) == o.view(np.int64)) | (np.isnan(g) & np.isnan(o))
+    assert same.all(), f"{(~same).sum()} values differ"
+
+
+def test_record_lost_in_drift_and_line_without_cells(P, oracle_mod):
+    """The recorder's two kernels: the generated one (the cfg1 ring, with
+    particles whose longitudinal momentum turns imaginary in a drift: they
+    keep their entry coordinates and apply no further maps) and the element
+    interpreter, taken for a line whose element sequence has no repeating
+    cell structure (a random sequence of every element type)."""
+    el = I.cfg1_lattice()
+    c = I.cfg1_particles(70, seed=11)
+    c[3, 1] = 1.2                   # |px| > 1 + delta from the first drift on
+    c[10, 3] = -0.999               # py^2 ~ (1 + delta)^2: pz^2 small, then the kicks push it over
+    c[20, 5] = -1.0                 # 1 + delta = 0: pz^2 = -(px^2 + py^2) <= 0
+    c[30, 1], c[30, 3] = 0.7, 0.72  # px^2 + py^2 > 1
+    g = P.track_record(P.Lattice(el, REF), c).cpu().numpy()
+    o = oracle_mod.track_record(el, REF, c)
+    _record_same(g, o)
+    frozen = [3, 20, 30]
+    # frozen from the first drift (element 4) on: its entry equals every later record
+    assert all(np.array_equal(g[-1, i], g[4, i], equal_nan=True) for i in frozen)
+    rng = np.random.default_rng(4)
+    els = []
+    for k in rng.integers(0, 6, 150):
+        if k == 0:
+            els.append(I.drift(rng.uniform(0.05, 0.5)))
+        elif k == 1:
+            N = int(rng.integers(0, 11))
+            els.append(I.multipole(knl=rng.normal(0, 1e-4, N + 1), ksl=rng.normal(0, 1e-4, N + 1)))
+        elif k == 2:
+            els.append(I.rf(rng.uniform(1e5, 1e6), 4e8, rng.uniform(0, 360)))
+        elif k == 3:
+            els.append(I.xyshift(*rng.normal(0, 1e-4, 2)))
+        elif k == 4:
+            els.append(I.srotation(rng.normal(0, 0.3)))
+        else:
+            els.append(I.ap_circle(0.0085))
+    el = I.line(els)
+    c = rng.normal(0, [3e-3, 2e-5, 3e-3, 2e-5, 0.05, 1e-3], (90, 6))
+    g = P.track_record(P.Lattice(el, REF), c).cpu().numpy()
+    _record_same(g, oracle_mod.track_record(el, REF, c))
+
+
+def test_record_output_alignment_checked(P):
+    """The recorder stores 16-byte pairs: an output array that is not
+    16-byte aligned is refused before any launch."""
+    import ctypes
+    import torch
+    lat = P.Lattice(I.cfg1_lattice(), REF)
+    c = torch.as_tensor(I.cfg1_particles(4, seed=2), dtype=torch.float64, device="cuda")
+    size = (lat.n_elements + 1) * 4 * 6
+    out = torch.zeros((size + 2,), dtype=torch.float64, device="cuda")
+    st = P.lib().xtm_track_record(lat.handle, ctypes.c_void_p(c.data_ptr()), 4,
+                                  ctypes.c_void_p(out.data_ptr() + 8), None)
+    assert st == -1
+    assert torch.count_nonzero(out).item() == 0
+    st = P.lib().xtm_track_record(lat.handle, ctypes.c_void_p(c.data_ptr()), 4,
+                                  ctypes.c_void_p(out.data_ptr() + 16), None)
+    assert st == 0
+    ref = P.track_record(lat, c).reshape(-1)
+    assert torch.count_nonzero(out[:2]).item() == 0
+    assert torch.equal(out[2:], ref)
+
+
 @pytest.mark.parametrize("case", ["fodo", "electron100", "electron_cfg5", "da_ring"])
 def test_normal_form_6d_matches_oracle(P, oracle_mod, case):
     """6D closed orbit, one-turn Jacobian and normal form by tracking on the
