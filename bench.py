@@ -46,10 +46,10 @@ TRAFFIC_SOURCES = ("xtm_jit.cpp", "xtm_maps.h")
 MEASURED_TRAFFIC = {
     # (workload, particles, turns per step, kernel variant, source hash):
     #     (bytes per launch, profile)
-    ("cfg2", 100000, 1000, 10, "6621191edaf999b0"):
-        (21458696.0, "profiles/xtm_line_cfg2_hbm_counters.txt"),
-    ("cfg1sat", 1048576, 1000, 10, "6621191edaf999b0"):
-        (189125943.0, "profiles/xtm_line_cfg2_hbm_counters.txt"),
+    ("cfg2", 100000, 1000, 10, "7da6f7364290dfbb"):
+        (21453289.0, "profiles/xtm_line_cfg2_hbm_counters.txt"),
+    ("cfg1sat", 1048576, 1000, 10, "7da6f7364290dfbb"):
+        (189125540.0, "profiles/xtm_line_cfg2_hbm_counters.txt"),
 }
 
 

@@ -427,7 +427,13 @@ std::string generate(const Decomp& d, int32_t style, bool batched, int32_t rad_f
        "    for (int w = lane; w < nw0; w += LANES) slot[w] = prm[off0 + w];\n"
        "  }\n";
   s << "  __syncthreads();\n";
+  // the cell table read one record (kind, first word, first element, words)
+  // at a time, one cell ahead: the current cell's record came with the
+  // previous cell's, so a cell starts with one scalar load, not three in
+  // sequence
   s << "  int b = 0;\n"
+       "  const int4* __restrict__ cells4 = reinterpret_cast<const int4*>(cells);\n"
+       "  int4 rc = cells4[0];\n"
        "  for (int t = 0; t < n_turns; ++t) {\n"
        "    const int enc_t = t * n_el + 1;\n";
   const std::string rec_body =
@@ -449,15 +455,19 @@ std::string generate(const Decomp& d, int32_t style, bool batched, int32_t rad_f
   s <<
        "    for (int c = 0; c < n_cells; ++c) {\n"
        "      const int cn = (c + 1 == n_cells) ? 0 : c + 1;\n"
-       "      const int offn = cells[4 * cn + 1], nwn = cells[4 * cn + 3];\n"
+       "      const int4 rn = cells4[cn];\n"
+       "      const int offn = rn.y, nwn = rn.w;\n"
+       "      // every lane loads (past the cell's words, its first word; the\n"
+       "      // parameter array ends in a pad word): no branch around the loads\n"
        "      double pre[PER_THREAD];\n"
        "#pragma unroll\n"
        "      for (int k = 0; k < PER_THREAD; ++k) {\n"
        "        const int w = lane + k * LANES;\n"
-       "        pre[k] = (w < nwn) ? prm[offn + w] : 0.0;\n"
+       "        const double v_ = prm[offn + (w < nwn ? w : 0)];\n"
+       "        pre[k] = (w < nwn) ? v_ : 0.0;\n"
        "      }\n"
-       "      const int kind = cells[4 * c];\n"
-       "      const int ec = cells[4 * c + 2];\n"
+       "      const int kind = rc.x;\n"
+       "      const int ec = rc.z;\n"
        "      // slot base hidden behind a register move: element reads become\n"
        "      // base + immediate-offset LDS loads instead of hoisted constant selects\n"
        "      int base;\n"
@@ -486,6 +496,19 @@ std::string generate(const Decomp& d, int32_t style, bool batched, int32_t rad_f
         << "        for (int m = 0; m < " << nw << "; ++m) w" << j << "[m] = p[" << off[j]
         << " + m];\n";
     };
+    // fetch 2: element m's words are read before element m - 1's arithmetic,
+    // or, for an element of many words (a high-order multipole) after a
+    // short test or frame change, before element m - 2's: the aperture's few
+    // operations would not cover the multipole's reads.  (Reading a drift's
+    // one word that early costs the saturated rings more registers than it
+    // saves.)
+    std::vector<size_t> read_before(kd.size(), 0);
+    for (size_t m = 1; m < kd.size(); ++m) {
+      const uint32_t kp = kd[m - 1] & 0xffu;
+      const bool short_prev = kp == K_AP_CIRC || kp == K_AP_ELL || kp == K_AP_RECT ||
+                              kp == K_SHIFT || kp == K_SROT || kp == K_MARKER;
+      read_before[m] = (short_prev && m >= 2 && n_words(kd[m]) >= 8) ? m - 2 : m - 1;
+    }
     if (fetch == 2 && !kd.empty()) load(0);
     for (size_t j = 0; j < kd.size(); ++j) {
       std::string arr = "p + " + std::to_string(off[j]);
@@ -493,7 +516,8 @@ std::string generate(const Decomp& d, int32_t style, bool batched, int32_t rad_f
         load(j);
         s << "        __builtin_amdgcn_sched_barrier(0);\n";
       } else if (fetch == 2) {
-        if (j + 1 < kd.size()) load(j + 1);
+        for (size_t m = j + 1; m < kd.size() && m <= j + 2; ++m)
+          if (read_before[m] == j) load(m);
         s << "        __builtin_amdgcn_sched_barrier(0);\n";
       }
       if (fetch != 0 && n_words(kd[j]) > 0) arr = "w" + std::to_string(j);
@@ -544,7 +568,8 @@ std::string generate(const Decomp& d, int32_t style, bool batched, int32_t rad_f
        "        const int w = lane + k * LANES;\n"
        "        if (w < nwn) slot[(b ^ 1) * MAXW + w] = pre[k];\n"
        "      }\n"
-       "      b ^= 1;\n";
+       "      b ^= 1;\n"
+       "      rc = rn;\n";
   s << "      __syncthreads();\n";
   s << "    }\n";
   if (ppt == 1)
@@ -897,6 +922,7 @@ bool build_line_kernel_multi(const std::vector<const std::vector<uint64_t>*>& ta
     }
     prm.insert(prm.end(), pv.begin(), pv.end());
   }
+  prm.push_back(0.0);  // pad word: the first word of a cell without words
   if (batched && line_block(style) != 64) {
     k->error = "batched per-line kernels use one-wave workgroups";
     return false;
