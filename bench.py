@@ -33,6 +33,8 @@ for _s in range(8):
          "fetched one element ahead, one loss test per cell")[_s >> 1])
 KERNEL_NAMES[13] = ("xtm_line (per-line generated kernel, one-wave workgroups, parameters "
                     "fetched one element ahead, two particles per lane)")
+KERNEL_NAMES[14] = ("xtm_line (per-line generated kernel, one-wave workgroups, parameters "
+                    "fetched one element ahead, long cells)")
 
 # HBM bytes per tracking-kernel launch, averaged over the timed region of one
 # FETCH_SIZE and one WRITE_SIZE counter pass of this benchmark, each scaled by
@@ -46,10 +48,10 @@ TRAFFIC_SOURCES = ("xtm_jit.cpp", "xtm_maps.h")
 MEASURED_TRAFFIC = {
     # (workload, particles, turns per step, kernel variant, source hash):
     #     (bytes per launch, profile)
-    ("cfg2", 100000, 1000, 10, "7da6f7364290dfbb"):
-        (21453289.0, "profiles/xtm_line_cfg2_hbm_counters.txt"),
-    ("cfg1sat", 1048576, 1000, 10, "7da6f7364290dfbb"):
-        (189125540.0, "profiles/xtm_line_cfg2_hbm_counters.txt"),
+    ("cfg2", 100000, 1000, 14, "27497ba4e42ffa7b"):
+        (21436331.0, "profiles/xtm_line_cfg2_hbm_counters.txt"),
+    ("cfg1sat", 1048576, 1000, 10, "27497ba4e42ffa7b"):
+        (189124664.0, "profiles/xtm_line_cfg2_hbm_counters.txt"),
 }
 
 

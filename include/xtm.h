@@ -184,8 +184,9 @@ typedef struct xtm_track_opts {
   int32_t use_graph;       /* 1 = replay the chunk sequence as a captured hipGraph    */
   int32_t time_kernels;    /* 1 = time each tracking launch with HIP events (stats)   */
   int32_t variant;         /* tracking kernel (all give bitwise the same results):
-                              0 = default (10 when the line has a compact periodic
-                              cell structure, else 4); 1..3 are not used
+                              0 = default (when the line has a compact periodic
+                              cell structure 14 for sets of at most 131,072
+                              particles, else 10; without one 4); 1..3 are not used
                               (XTM_E_ARG); 4 = interpreter, losses
                               kept in registers and replayed after the chunk;
                               5..xtm_max_variant() = per-line kernel generated from
@@ -204,7 +205,10 @@ typedef struct xtm_track_opts {
                               cell's maps from its entry to find the coordinates
                               to store).  Variant 13: as 10 with two particles
                               per lane (slots i and i + 64 of a workgroup's
-                              range), their maps interleaved.
+                              range), their maps interleaved.  Variant 14: as 10
+                              with long cells (repeating units of up to 40
+                              elements instead of 24: fewer cell boundaries per
+                              turn, more code and prefetch registers).
                               XTM_E_UNSUPPORTED if it cannot be built */
   int32_t radiation;       /* synchrotron radiation in multipoles with length > 0:
                               0 off, 1 mean energy loss, 2 mean + quantum excitation

@@ -341,7 +341,11 @@ xtm_status read_alive(xtm_particles_s* p, hipStream_t s, int64_t* alive, int64_t
 // workgroups with each element's parameters fetched one element ahead
 // (variant 10), the fastest form on the dynamic-aperture scans measured,
 // whose surviving particles are too few to give every SIMD two waves.
-int32_t default_line_variant(int64_t) { return 10; }
+// the default per-line form: one-wave workgroups with the next element's
+// parameters read ahead (10); for a set of at most two waves per SIMD
+// (131,072 particles), whose time is the latency of each wave's element
+// chain, the same form with long cells (14: fewer cell boundaries)
+int32_t default_line_variant(int64_t alive) { return alive <= 131072 ? 14 : 10; }
 
 int32_t auto_chunk(int64_t n, int32_t n_el, int32_t n_turns) {
   // aim at ~2e10 passes per launch so launch and epilogue costs vanish, while

@@ -181,25 +181,31 @@ struct LineKernel {
 // Generated-kernel forms ("styles"), all computing the same maps in the same
 // order: the workgroup (256 lanes or one wave), the way element code reads
 // its parameters from the LDS slot (line_fetch), where a lost particle's
-// coordinates are stored (line_deferred) and how many particles each lane
-// carries (line_ppt).  Kernel variant 5 + style.
+// coordinates are stored (line_deferred), how many particles each lane
+// carries (line_ppt) and whether the cells are long (line_long: units of up
+// to 40 elements within 64 elements of code, instead of 24 within 48; fewer
+// cell boundaries for a latency-bound set, more code and prefetch registers
+// for a saturated one).  Kernel variant 5 + style.
 struct LineStyle {
   int32_t lanes, fetch;
   bool deferred;
   int32_t ppt;
+  bool long_cells;
 };
 constexpr LineStyle kLineStyle[] = {
-    {256, 0, false, 1}, {64, 0, false, 1},  // 5, 6: parameters read at each use
-    {256, 1, false, 1}, {64, 1, false, 1},  // 7, 8: an element's words in one group
-    {256, 2, false, 1}, {64, 2, false, 1},  // 9, 10: the next element's group ahead
-    {256, 2, true, 1},  {64, 2, true, 1},   // 11, 12: as 9, 10, one loss test per cell
-    {64, 2, false, 2},                      // 13: as 10, two particles per lane
+    {256, 0, false, 1, false}, {64, 0, false, 1, false},  // 5, 6: parameters read at each use
+    {256, 1, false, 1, false}, {64, 1, false, 1, false},  // 7, 8: an element's words in one group
+    {256, 2, false, 1, false}, {64, 2, false, 1, false},  // 9, 10: the next element's group ahead
+    {256, 2, true, 1, false},  {64, 2, true, 1, false},   // 11, 12: as 9, 10, one loss test per cell
+    {64, 2, false, 2, false},                             // 13: as 10, two particles per lane
+    {64, 2, false, 1, true},                              // 14: as 10, long cells
 };
 constexpr int32_t kLineStyles = (int32_t)(sizeof(kLineStyle) / sizeof(kLineStyle[0]));
 inline int32_t line_block(int32_t style) { return kLineStyle[style].lanes; }
 inline int32_t line_fetch(int32_t style) { return kLineStyle[style].fetch; }
 inline bool line_deferred(int32_t style) { return kLineStyle[style].deferred; }
 inline int32_t line_ppt(int32_t style) { return kLineStyle[style].ppt; }
+inline bool line_long(int32_t style) { return kLineStyle[style].long_cells; }
 // Radiation forms of a per-line kernel: which radiation steps its radiating
 // multipoles carry, so that a kernel holds only the code its calls can take
 // (the photon emitter is an out-of-line call whose register and stack cost a

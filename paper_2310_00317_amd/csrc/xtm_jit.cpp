@@ -54,14 +54,18 @@ struct Decomp {
 // cell whose sextupole slot holds a cavity) as further kinds, split into
 // pieces of at most max_unit elements.  Among all units (P <= max_unit,
 // every phase) keep the cover with the fewest cells whose distinct kinds
-// need at most kMaxCode elements of generated code.
+// need at most max_code elements of generated code.
 constexpr int kMaxUnit = 24;
 constexpr int kMaxCode = 48;
+// the long-cell forms
+constexpr int kLongUnit = 40;
+constexpr int kLongCode = 64;
 // the recording kernel buffers a cell's rows in LDS: at most 16 elements a
 // cell (16 x 64 lanes x 48 bytes)
 constexpr int kMaxRecordUnit = 16;
 
-bool decompose(const std::vector<uint32_t>& sig, Decomp* out, int32_t max_unit = kMaxUnit) {
+bool decompose(const std::vector<uint32_t>& sig, Decomp* out, int32_t max_unit = kMaxUnit,
+               int32_t max_code = kMaxCode) {
   const int32_t E = (int32_t)sig.size();
   if (E == 0) return false;
   size_t best_cells = 0;
@@ -100,10 +104,10 @@ bool decompose(const std::vector<uint32_t>& sig, Decomp* out, int32_t max_unit =
           if (gap < 0) gap = i;
           ++i;
         }
-        if (code > kMaxCode) ok = false;
+        if (code > max_code) ok = false;
       }
       if (ok && gap >= 0) flush(gap, E);
-      if (!ok || code > kMaxCode) continue;
+      if (!ok || code > max_code) continue;
       if (best_cells == 0 || d.cell_kind.size() < best_cells ||
           (d.cell_kind.size() == best_cells && code < best_code)) {
         best_cells = d.cell_kind.size();
@@ -928,7 +932,8 @@ bool build_line_kernel_multi(const std::vector<const std::vector<uint64_t>*>& ta
     return false;
   }
   Decomp d;
-  if (!decompose(sig, &d)) {
+  if (!decompose(sig, &d, line_long(style) ? kLongUnit : kMaxUnit,
+                 line_long(style) ? kLongCode : kMaxCode)) {
     k->error = "no cell decomposition within the code budget";
     return false;
   }

@@ -31,7 +31,7 @@ def _twiss():
 # ------------------------------------------------------------------ recorder
 @pytest.mark.parametrize("variant,chunk", [(0, 100), (4, 0), (0, 0), (5, 50), (6, 30), (7, 0),
                                            (8, 100), (9, 0), (10, 64), (11, 0), (12, 40),
-                                           (13, 0), (13, 50)])
+                                           (13, 0), (13, 50), (14, 0), (14, 30)])
 def test_recorder_matches_oracle(P, oracle_mod, variant, chunk):
     """cfg1 without RF (bitwise tracking) on a polar grid reaching 32 sigma:
     survivors and particles lost at turns 0..95.  Entries up to the loss turn

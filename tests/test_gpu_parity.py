@@ -156,7 +156,9 @@ def test_resume_bitwise(P):
                                   dict(variant=12), dict(variant=12, turns_per_chunk=3,
                                                          compact=False),
                                   dict(variant=13), dict(variant=13, turns_per_chunk=5,
-                                                         compact=False)])
+                                                         compact=False),
+                                  dict(variant=10), dict(variant=14, turns_per_chunk=7),
+                                  dict(variant=14, turns_per_chunk=3, compact=False)])
 def test_launch_shape_invariance(P, opts):
     banner(f"launch shape {opts}")
     el = I.cfg1_lattice()
@@ -290,7 +292,7 @@ def test_cfg2_loss_parity_at_da_scale(P, oracle_mod):
     assert np.array_equal(g["state"][both_lost], o.state[both_lost])
 
 
-@pytest.mark.parametrize("variant", [4, 5, 6, 7, 8, 9, 10, 11, 12, 13])
+@pytest.mark.parametrize("variant", [4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14])
 def test_kernel_variants_on_multisegment_lattice(P, variant):
     """The 20,000-element lattice spans many LDS segments: every kernel variant
     must give bitwise the same result as the default one."""
@@ -365,11 +367,11 @@ def test_empty_lattice_counts_turns(P, oracle_mod):
 
 def test_variant_numbers(P):
     """Every per-line form is a kernel number; one past the last is refused."""
-    assert P.line_variants() == list(range(5, 14))
+    assert P.line_variants() == list(range(5, 15))
     lat = P.Lattice(I.cfg1_lattice(), REF)
     parts = P.Particles(8, REF).init(np.zeros((8, 6)))
     with pytest.raises(P.XtmError) as ei:
-        P.track(lat, parts, 1, variant=14)
+        P.track(lat, parts, 1, variant=15)
     assert ei.value.code == -1
 
 
@@ -410,7 +412,7 @@ def large_cell_lattice(seed=3, units=30):
     return I.line(els)
 
 
-@pytest.mark.parametrize("variant", [0, 4, 6, 7, 8, 9, 10, 11, 12, 13])
+@pytest.mark.parametrize("variant", [0, 4, 6, 7, 8, 9, 10, 11, 12, 13, 14])
 def test_line_kernel_with_multi_pass_staging(P, oracle_mod, variant):
     banner(f"large-cell lattice, variant {variant}")
     el = large_cell_lattice()
@@ -488,7 +490,7 @@ def test_drift_domain_edges(P, oracle_mod):
     assert gp == op
     assert (o.state != 1).any() and (o.state == 1).sum() > len(c) // 2
     assert_bitwise(g, o)
-    for v in (0, 5, 12, 13):
+    for v in (0, 5, 10, 12, 13, 14):
         gv, _, _, _, _ = gpu_run(P, el, REF, c, 1, variant=v)
         for f in g:
             assert np.array_equal(np.asarray(gv[f]).view(np.uint8),

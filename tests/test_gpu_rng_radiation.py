@@ -88,7 +88,7 @@ def test_one_lattice_every_radiation_mode(P, oracle_mod):
         assert_bitwise(parts.to_numpy(), o)
 
 
-@pytest.mark.parametrize("variant", [0, 7, 9, 10, 11, 12, 13])
+@pytest.mark.parametrize("variant", [0, 7, 9, 10, 11, 12, 13, 14])
 def test_radiation_full_electron_ring_short(P, oracle_mod, variant):
     el = I.cfg5_lattice()
     c = I.cfg5_particles(256, seed=3)
@@ -100,7 +100,7 @@ def test_radiation_full_electron_ring_short(P, oracle_mod, variant):
     assert_bitwise(g, o)
 
 
-@pytest.mark.parametrize("variant", [0, 4, 10, 13])
+@pytest.mark.parametrize("variant", [0, 4, 10, 13, 14])
 def test_photon_radiation_full_electron_ring_short(P, oracle_mod, variant):
     """Photon-by-photon emission on the full 20,000-element electron ring
     (about two photons per bend): bitwise parity with the oracle."""
@@ -123,7 +123,7 @@ def test_radiation_graph_and_chunks_invariant(P, mode):
                dict(variant=6, turns_per_chunk=5), dict(variant=7), dict(variant=8),
                dict(variant=9, turns_per_chunk=3), dict(variant=10, turns_per_chunk=11),
                dict(variant=11, turns_per_chunk=6), dict(variant=12),
-               dict(variant=13, turns_per_chunk=7)):
+               dict(variant=13, turns_per_chunk=7), dict(variant=14, turns_per_chunk=4)):
         b, pb, _, _, _ = gpu_run(P, el, EREF, c, 40, radiation=mode, seed=1, **kw)
         assert pa == pb, kw
         for f in a:
