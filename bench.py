@@ -49,9 +49,9 @@ MEASURED_TRAFFIC = {
     # (workload, particles, turns per step, kernel variant, source hash):
     #     (bytes per launch, profile)
     ("cfg2", 100000, 1000, 14, "27497ba4e42ffa7b"):
-        (21436331.0, "profiles/xtm_line_cfg2_hbm_counters.txt"),
-    ("cfg1sat", 1048576, 1000, 10, "27497ba4e42ffa7b"):
-        (189124664.0, "profiles/xtm_line_cfg2_hbm_counters.txt"),
+        (21436151.0, "profiles/xtm_line_cfg2_hbm_counters.txt"),
+    ("cfg1sat", 1048576, 1000, 14, "27497ba4e42ffa7b"):
+        (189171626.0, "profiles/xtm_line_cfg2_hbm_counters.txt"),
 }
 
 

@@ -184,9 +184,8 @@ typedef struct xtm_track_opts {
   int32_t use_graph;       /* 1 = replay the chunk sequence as a captured hipGraph    */
   int32_t time_kernels;    /* 1 = time each tracking launch with HIP events (stats)   */
   int32_t variant;         /* tracking kernel (all give bitwise the same results):
-                              0 = default (when the line has a compact periodic
-                              cell structure 14 for sets of at most 131,072
-                              particles, else 10; without one 4); 1..3 are not used
+                              0 = default (14 when the line has a compact
+                              periodic cell structure, else 4); 1..3 are not used
                               (XTM_E_ARG); 4 = interpreter, losses
                               kept in registers and replayed after the chunk;
                               5..xtm_max_variant() = per-line kernel generated from

@@ -342,10 +342,10 @@ xtm_status read_alive(xtm_particles_s* p, hipStream_t s, int64_t* alive, int64_t
 // (variant 10), the fastest form on the dynamic-aperture scans measured,
 // whose surviving particles are too few to give every SIMD two waves.
 // the default per-line form: one-wave workgroups with the next element's
-// parameters read ahead (10); for a set of at most two waves per SIMD
-// (131,072 particles), whose time is the latency of each wave's element
-// chain, the same form with long cells (14: fewer cell boundaries)
-int32_t default_line_variant(int64_t alive) { return alive <= 131072 ? 14 : 10; }
+// parameters read ahead, long cells (14); measured on one GPU against the
+// same form with short cells (10), as fast or faster from 10^3 to 2^22
+// particles
+int32_t default_line_variant(int64_t) { return 14; }
 
 int32_t auto_chunk(int64_t n, int32_t n_el, int32_t n_turns) {
   // aim at ~2e10 passes per launch so launch and epilogue costs vanish, while

@@ -57,8 +57,7 @@ def test_batched_equals_separate(P, chunk, graph, variant):
     st = P.track_batched(batch, big, first, 300, turns_per_chunk=chunk, graph=graph,
                          variant=variant, full_stats=not graph)
     if not graph:
-        # the default for a set this small (at most 131,072 particles) is
-        # the long-cell one-wave form
+        # the default is the long-cell one-wave form
         assert st.variant == (14 if variant == 0 else variant)
     g = big.to_numpy()
     n_lost = 0
