@@ -788,7 +788,7 @@ def select_threshold(logit, label, max_false_rate: float):
 
 # ---------------------------------------------------- elementary functions
 def xsin(x: float) -> float:
-    """The tracker's sine (series evaluation shared by both implementations)."""
+    """The tracker's sine (the series evaluation both implementations follow)."""
     return float(lib().oracle_sin(x))
 
 

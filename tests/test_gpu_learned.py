@@ -216,6 +216,44 @@ def test_mlp_gradient_matches_oracle(P, B):
         assert rel <= 1e-2 and cos >= 0.999, (name, rel, cos)
 
 
+@pytest.mark.parametrize("B", [4096, 1000])
+def test_mlp_gradient_elementwise_bound(P, B):
+    """Every gradient element within 2^-7 of its magnitude scale: the same
+    backward sums taken over absolute values (|A|^T |D| for a weight, sum |D|
+    for a bias, no ReLU masks, so a unit whose sign differs between FP32 and
+    FP64 is covered).  Both sides round the GEMM operands to BF16 at the same
+    points; what is left is FP32 against FP64 accumulation (about 2^-24 of
+    the scale per term) and a BF16 rounding that may fall one ulp (2^-8)
+    apart where the value before it differs: together below 2^-8 of the
+    scale at each of the two chained products, hence 2^-7.  (Removing every
+    BF16 rounding on one side moves the elements by up to 2e-2 of the scale,
+    which this bound does not admit.)"""
+    import torch
+    from oracle import mlp
+    theta, x, norm, y = _net_inputs(B, seed=7)
+    w = float((y == 0).sum() / max((y == 1).sum(), 1))
+    t = lambda a: torch.tensor(a, device="cuda")
+    g, _ = P.mlp_grad(t(theta), t(norm), t(x), t(y), w)
+    gp = mlp.unpack(g.cpu().numpy().astype(np.float64))
+    th = theta.astype(np.float64)
+    _, go = mlp.backward(th, mlp.standardise(x, norm), y, w)
+    op = mlp.unpack(go)
+    f = mlp.forward(th, mlp.standardise(x, norm))
+    p = mlp.unpack(th)
+    yy = y.astype(np.float64)
+    s = 1.0 / (1.0 + np.exp(-f["z3"]))
+    m3 = np.abs(s * (w * yy + (1 - yy)) - w * yy) / B
+    m2 = np.outer(m3, np.abs(p["w3"]))
+    m1 = m2 @ np.abs(p["W2"]).T
+    scale = {"b3": np.array([m3.sum()]), "w3": np.abs(f["H2"]).T @ m3,
+             "b2": m2.sum(axis=0), "W2": np.abs(f["H1"]).T @ m2,
+             "b1": m1.sum(axis=0), "W1": np.abs(f["X"]).T @ m1}
+    for name, _ in mlp.SIZES:
+        err = np.abs(gp[name] - op[name])
+        bound = 2.0 ** -7 * scale[name] + 1e-12
+        assert np.all(err <= bound), (name, float((err / bound).max()))
+
+
 def test_adam_steps_match_oracle(P):
     import torch
     from oracle import mlp
