@@ -48,10 +48,10 @@ TRAFFIC_SOURCES = ("xtm_jit.cpp", "xtm_maps.h")
 MEASURED_TRAFFIC = {
     # (workload, particles, turns per step, kernel variant, source hash):
     #     (bytes per launch, profile)
-    ("cfg2", 100000, 1000, 14, "13436aeff526fee0"):
-        (21432335.0, "profiles/xtm_line_cfg2_hbm_counters.txt"),
-    ("cfg1sat", 1048576, 1000, 14, "13436aeff526fee0"):
-        (189155979.0, "profiles/xtm_line_cfg2_hbm_counters.txt"),
+    ("cfg2", 100000, 1000, 14, "8fc270e379fe13d4"):
+        (21432430.0, "profiles/xtm_line_cfg2_hbm_counters.txt"),
+    ("cfg1sat", 1048576, 1000, 14, "8fc270e379fe13d4"):
+        (189155935.0, "profiles/xtm_line_cfg2_hbm_counters.txt"),
 }
 
 

@@ -953,10 +953,12 @@ bool build_line_kernel_multi(const std::vector<const std::vector<uint64_t>*>& ta
   k->nv = (int32_t)tabs.size();
   k->stride = (int64_t)stride;
   // single-lattice kernels take the ILP schedule (measured 2-4 % faster on
-  // the DA, radiation and recording rings, level on saturated rings); the
-  // batched ones keep the default (0.7 % slower with it on 64 variants)
-  return finish_kernel(d, generate(d, style, batched, rad_form), "xtm_line", !batched, word_of,
-                       prm, k);
+  // the DA ring and with the mean and Gaussian radiation, 1 % slower on a
+  // saturated FODO ring); the batched ones (0.7 % slower with it on 64
+  // variants) and the photon form (4 % slower) keep the default
+  const bool ilp = !batched && rad_form != 2;
+  return finish_kernel(d, generate(d, style, batched, rad_form), "xtm_line", ilp, word_of, prm,
+                       k);
 }
 
 bool build_record_kernel(const std::vector<uint64_t>& tab, int32_t n_el, LineKernel* k) {
